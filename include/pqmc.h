@@ -1,0 +1,173 @@
+/*
+ * pqmc.h -- C ABI of the MI355X (gfx950) ground-state AFQMC field-update sweep.
+ *
+ * The library runs one projector-QMC Markov chain (one "walker") of a
+ * spin-1/2 lattice model with on-site Hubbard interaction, following
+ * H. Du and Y.-Y. He, "Accelerating ground-state auxiliary-field quantum
+ * Monte Carlo simulations by delayed update and block force-bias update",
+ * arXiv:2506.09611:
+ *
+ *   weight      W(X) = prod_s det(P_s^+ B_M ... B_1 P_s)          Sec. II B, Eq. (8)
+ *   propagator  B_l^s = diag(e^{alpha f_s x_l}) e^{-dtau H0}      Eqs. (9), (13)-(14)
+ *   state       U_R, U_L, T = (U_L U_R)^{-1}; G = 1 - U_R T U_L   Sec. II B, Eq. (15)
+ *   updates     local (Eqs. (20)-(21)), delayed (Sec. III A, Eqs. (27)-(30)),
+ *               block force-bias (Sec. III B, Eqs. (31)-(36))
+ *
+ * All matrices are float64.  U > 0 uses the real coupling
+ * alpha = arccosh(e^{dtau U/2}) with two spin sectors (f_up = +1, f_dn = -1);
+ * U = 0 gives alpha = 0.  U < 0 (the paper's complex coupling) is rejected
+ * with PQMC_EINVAL by this build.
+ *
+ * Memory: the library allocates no device memory.  The caller obtains the
+ * size from pqmc_workspace_bytes() and passes one device buffer of at least
+ * that many bytes, 256-byte aligned, which must stay valid until
+ * pqmc_destroy().  Host inputs are copied during pqmc_create(); the caller
+ * keeps ownership of every pointer it passes.
+ *
+ * Streams: every call enqueues work on the HIP stream given to pqmc_create()
+ * (NULL = the null stream).  pqmc_sweep() returns after its work completes;
+ * the getters synchronise the stream before they copy.
+ *
+ * Errors: every function returns a pqmc_status; a message for the calling
+ * thread's last failure is available from pqmc_last_error().  After
+ * PQMC_ESINGULAR or PQMC_ENONFINITE the context refuses further sweeps
+ * (PQMC_ESTATE) until pqmc_set_fields() rebuilds its state.  No C++
+ * exception crosses this interface.
+ */
+#ifndef PQMC_H
+#define PQMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pqmc_ctx pqmc_ctx;
+
+typedef enum {
+  PQMC_OK = 0,
+  PQMC_EINVAL = -1,      /* bad argument or unsupported problem             */
+  PQMC_ENOMEM = -2,      /* workspace too small                             */
+  PQMC_EDEVICE = -3,     /* a HIP runtime call failed                       */
+  PQMC_ESINGULAR = -4,   /* a stabilisation factorisation broke down        */
+  PQMC_ENONFINITE = -5,  /* a determinant ratio was not finite              */
+  PQMC_ESTATE = -6       /* context is in a failed state                    */
+} pqmc_status;
+
+/* Update schemes.
+ *   PQMC_LOCAL    sites i = 1..N of a slice one by one, Sherman-Morrison
+ *                 rank-1 upgrade of T per accepted flip (Sec. II D).
+ *   PQMC_DELAYED  groups of delay_k consecutive sites; ratios from the
+ *                 delayed recursion and one rank-n_A flush of T per group
+ *                 (Sec. III A, first strategy: n_d = proposals).
+ *   PQMC_BLOCK_FB blocks of block_b consecutive sites proposed together from
+ *                 the force-bias heat-bath prior, one Metropolis test per
+ *                 block and a rank-n_F Woodbury upgrade (Sec. III B).     */
+typedef enum { PQMC_LOCAL = 0, PQMC_DELAYED = 1, PQMC_BLOCK_FB = 2 } pqmc_scheme;
+
+/* flags of pqmc_update_opts */
+#define PQMC_FLAG_LOG    1u  /* record every decision of the last pqmc_sweep call */
+#define PQMC_FLAG_TIMING 2u  /* time propagation / update / stabilisation phases  */
+
+typedef struct {
+  int32_t n_sites;            /* N_s: number of lattice sites                          */
+  int32_t n_up, n_dn;         /* N_up, N_dn: particles per spin, 1 <= N_s <= n_sites   */
+  const double *hopping;      /* H0, N_s x N_s row-major, real symmetric (Sec. II B)   */
+  const double *trial_up;     /* P_up, N_s x N_up row-major, orthonormal columns       */
+  const double *trial_dn;     /* P_dn, N_s x N_dn row-major, orthonormal columns       */
+  double U;                   /* on-site interaction, U >= 0 in this build             */
+  double dtau;                /* imaginary-time step                                   */
+  int32_t n_slices;           /* M = 2 Theta / dtau                                     */
+  int32_t stab_every;         /* k_tau: QR stabilisation period, must divide M         */
+  uint64_t seed;              /* Philox key word 0                                     */
+  uint64_t walker_id;         /* Philox key word 1                                     */
+} pqmc_problem;
+
+typedef struct {
+  int32_t scheme;             /* pqmc_scheme                                           */
+  int32_t delay_k;            /* n_d for PQMC_DELAYED, 1 <= k <= 128 (clipped to N_s)   */
+  int32_t block_b;            /* n_b for PQMC_BLOCK_FB, 1 <= b <= 128 (clipped to N_s)  */
+  uint32_t flags;             /* PQMC_FLAG_*                                           */
+} pqmc_update_opts;
+
+typedef struct {
+  uint64_t proposed;          /* Metropolis tests (sites, or blocks for block FB)      */
+  uint64_t accepted;          /* accepted tests                                        */
+  uint64_t flips;             /* fields changed                                        */
+  uint64_t low_margin;        /* decisions with | |A| - u | < 1e-12 (incl. heat bath)  */
+  uint64_t negative;          /* accepted-or-not tests with a negative weight ratio    */
+  uint64_t field_updates;     /* single-site field visits (2 M N per sweep)            */
+  double t_total_s;           /* wall time of the call (stream-synchronised)           */
+  double t_update_s;          /* with PQMC_FLAG_TIMING: field-update phase             */
+  double t_prop_s;            /* with PQMC_FLAG_TIMING: B-matrix propagation phase     */
+  double t_stab_s;            /* with PQMC_FLAG_TIMING: QR + inverse phase             */
+} pqmc_stats;
+
+/* Size of the device workspace for this problem and the largest delay_k /
+ * block_b the context will be asked to run (opts->delay_k, opts->block_b
+ * are upper bounds for later pqmc_set_opts calls).  Validates the problem. */
+pqmc_status pqmc_workspace_bytes(const pqmc_problem *prob, const pqmc_update_opts *opts,
+                                 size_t *bytes);
+
+/* Build a context: copies H0 and P_s to the device, computes
+ * K = e^{-dtau H0} and K^{-1} (Taylor series with scaling and squaring),
+ * draws the initial fields x_{l,i} = +1 iff u(INIT; 0, l-1, i) < 1/2, builds
+ * the stack of row-orthonormalised U_L at every k_tau (Sec. II B) and sets
+ * the walker at position 0 with U_R = P, T = (U_L U_R)^{-1}.
+ * workspace: device pointer, >= pqmc_workspace_bytes(), 256-byte aligned. */
+pqmc_status pqmc_create(const pqmc_problem *prob, const pqmc_update_opts *opts,
+                        void *hip_stream, void *workspace, size_t workspace_bytes,
+                        pqmc_ctx **out);
+
+/* Change scheme / k / b / flags (k and b within the workspace bounds). */
+pqmc_status pqmc_set_opts(pqmc_ctx *ctx, const pqmc_update_opts *opts);
+
+/* Replace the field configuration (host, M x N_s int8 row-major, entries
+ * +1 or -1) and rebuild the stack and position-0 state; clears a failed state. */
+pqmc_status pqmc_set_fields(pqmc_ctx *ctx, const int8_t *fields);
+
+/* Copy the current fields to host memory (M x N_s int8). */
+pqmc_status pqmc_get_fields(pqmc_ctx *ctx, int8_t *fields);
+
+/* Run n_sweeps sweeps.  One sweep is the forward pass l = 1..M (propagate,
+ * update slice l, stabilise when k_tau divides l) followed by the backward
+ * pass l = M..1 (update slice l, propagate back, stabilise when k_tau
+ * divides l-1) -- Sec. II B and the efficiency measurements of Sec. IV.
+ * Metropolis test of Eq. (16): accept iff u < |A|, u from Philox4x64-10 at
+ * counter (sweep, dir*M + l-1, site, purpose).  out may be NULL. */
+pqmc_status pqmc_sweep(pqmc_ctx *ctx, int32_t n_sweeps, pqmc_stats *out);
+
+/* Run only the forward pass over slices 1..n_slices (a window of a sweep;
+ * leaves the walker at position n_slices).  Used for windowed comparisons
+ * at sizes where a whole sweep is long; the next pqmc_sweep is refused. */
+pqmc_status pqmc_forward_window(pqmc_ctx *ctx, int32_t n_slices, pqmc_stats *out);
+
+/* G^s = 1 - U_R T U_L at the walker's current position (Eq. (15)),
+ * written to host memory as N_s x N_s row-major float64.  spin: 0 up, 1 down. */
+pqmc_status pqmc_get_green(pqmc_ctx *ctx, int32_t spin, double *out);
+
+/* Decisions of the last pqmc_sweep / pqmc_forward_window call made with
+ * PQMC_FLAG_LOG, in order: meta[3*n] = (dir*M + l-1, site, accepted) and
+ * margin[n] = |A| - u.  For block FB, site is the block's first site and the
+ * heat-bath draws are not included.  cap: capacity of the host arrays; *n
+ * receives the number of entries (copied: min(cap, count)). */
+pqmc_status pqmc_get_decisions(pqmc_ctx *ctx, int32_t *meta, double *margin, size_t cap,
+                               size_t *n);
+
+/* Heat-bath draws of the last block-FB call made with PQMC_FLAG_LOG:
+ * meta[3*n] = (dir*M + l-1, site, proposed x'), margin[n] = p(+1) - u. */
+pqmc_status pqmc_get_heat_bath(pqmc_ctx *ctx, int32_t *meta, double *margin, size_t cap,
+                               size_t *n);
+
+/* Release the context (the workspace stays the caller's). */
+pqmc_status pqmc_destroy(pqmc_ctx *ctx);
+
+/* Message of the calling thread's last failure ("" if none). */
+const char *pqmc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PQMC_H */

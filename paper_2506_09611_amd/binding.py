@@ -1,0 +1,229 @@
+"""ctypes binding of libpqmc.so (include/pqmc.h), same names as the C ABI.
+
+Argument marshalling only: every step of the sweep runs in the library's
+HIP kernels.  The device workspace is one torch uint8 tensor on the
+current CUDA (HIP) device and work goes to torch's current stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import enum
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+EXPORTED_SYMBOLS = (
+    "pqmc_workspace_bytes", "pqmc_create", "pqmc_set_opts", "pqmc_set_fields",
+    "pqmc_get_fields", "pqmc_sweep", "pqmc_forward_window", "pqmc_get_green",
+    "pqmc_get_decisions", "pqmc_get_heat_bath", "pqmc_destroy", "pqmc_last_error",
+)
+
+
+class Scheme(enum.IntEnum):
+    LOCAL = 0
+    DELAYED = 1
+    BLOCK_FB = 2
+
+
+FLAG_LOG = 1
+FLAG_TIMING = 2
+
+
+class PQMCError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"pqmc status {status}: {msg}")
+        self.status = status
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("n_sites", ctypes.c_int32), ("n_up", ctypes.c_int32), ("n_dn", ctypes.c_int32),
+                ("hopping", ctypes.POINTER(ctypes.c_double)),
+                ("trial_up", ctypes.POINTER(ctypes.c_double)),
+                ("trial_dn", ctypes.POINTER(ctypes.c_double)),
+                ("U", ctypes.c_double), ("dtau", ctypes.c_double),
+                ("n_slices", ctypes.c_int32), ("stab_every", ctypes.c_int32),
+                ("seed", ctypes.c_uint64), ("walker_id", ctypes.c_uint64)]
+
+
+class UpdateOpts(ctypes.Structure):
+    _fields_ = [("scheme", ctypes.c_int32), ("delay_k", ctypes.c_int32),
+                ("block_b", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("proposed", ctypes.c_uint64), ("accepted", ctypes.c_uint64),
+                ("flips", ctypes.c_uint64), ("low_margin", ctypes.c_uint64),
+                ("negative", ctypes.c_uint64), ("field_updates", ctypes.c_uint64),
+                ("t_total_s", ctypes.c_double), ("t_update_s", ctypes.c_double),
+                ("t_prop_s", ctypes.c_double), ("t_stab_s", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def library_path() -> str:
+    return os.path.join(_HERE, "libpqmc.so")
+
+
+def load_library():
+    """Load the in-tree libpqmc.so; raise ImportError if it has not been built."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    path = library_path()
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with __graft_entry__.build()")
+    lib = ctypes.CDLL(path)
+    c_void_p, c_size_t = ctypes.c_void_p, ctypes.c_size_t
+    sig = {
+        "pqmc_workspace_bytes": [ctypes.POINTER(Problem), ctypes.POINTER(UpdateOpts),
+                                 ctypes.POINTER(c_size_t)],
+        "pqmc_create": [ctypes.POINTER(Problem), ctypes.POINTER(UpdateOpts), c_void_p, c_void_p,
+                        c_size_t, ctypes.POINTER(c_void_p)],
+        "pqmc_set_opts": [c_void_p, ctypes.POINTER(UpdateOpts)],
+        "pqmc_set_fields": [c_void_p, ctypes.POINTER(ctypes.c_int8)],
+        "pqmc_get_fields": [c_void_p, ctypes.POINTER(ctypes.c_int8)],
+        "pqmc_sweep": [c_void_p, ctypes.c_int32, ctypes.POINTER(Stats)],
+        "pqmc_forward_window": [c_void_p, ctypes.c_int32, ctypes.POINTER(Stats)],
+        "pqmc_get_green": [c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)],
+        "pqmc_get_decisions": [c_void_p, ctypes.POINTER(ctypes.c_int32),
+                               ctypes.POINTER(ctypes.c_double), c_size_t,
+                               ctypes.POINTER(c_size_t)],
+        "pqmc_get_heat_bath": [c_void_p, ctypes.POINTER(ctypes.c_int32),
+                               ctypes.POINTER(ctypes.c_double), c_size_t,
+                               ctypes.POINTER(c_size_t)],
+        "pqmc_destroy": [c_void_p],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.pqmc_last_error.argtypes = []
+    lib.pqmc_last_error.restype = ctypes.c_char_p
+    _LIB = lib
+    return lib
+
+
+def _check(lib, status):
+    if status != 0:
+        raise PQMCError(status, lib.pqmc_last_error().decode())
+
+
+def _dptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+class Chain:
+    """One PQMC walker on the GPU (a pqmc_ctx).
+
+    hopping: N x N float64; trial_up/trial_dn: N x N_s float64 (orthonormal
+    columns); U >= 0; dtau; n_slices = M; stab_every = k_tau; seed, walker_id:
+    Philox key.  scheme / k / b: update scheme, delay rank, block size; k_max
+    and b_max bound later set_opts calls (workspace sizing).
+    """
+
+    def __init__(self, hopping, trial_up, trial_dn, U, dtau, n_slices, stab_every, seed,
+                 walker_id=0, scheme=Scheme.LOCAL, k=1, b=1, k_max=None, b_max=None,
+                 log=False, timing=False):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device visible to torch")
+        self._lib = load_library()
+        self._H = np.ascontiguousarray(hopping, dtype=np.float64)
+        self._Pu = np.ascontiguousarray(trial_up, dtype=np.float64)
+        self._Pd = np.ascontiguousarray(trial_dn, dtype=np.float64)
+        N = self._H.shape[0]
+        self.N, self.M = N, int(n_slices)
+        self.n_up, self.n_dn = self._Pu.shape[1], self._Pd.shape[1]
+        self._prob = Problem(N, self.n_up, self.n_dn, _dptr(self._H), _dptr(self._Pu),
+                             _dptr(self._Pd), float(U), float(dtau), int(n_slices),
+                             int(stab_every), int(seed) & (2**64 - 1), int(walker_id))
+        self._flags = (FLAG_LOG if log else 0) | (FLAG_TIMING if timing else 0)
+        kmax = int(k_max if k_max is not None else k)
+        bmax = int(b_max if b_max is not None else b)
+        sizing = UpdateOpts(int(scheme), max(kmax, 1), max(bmax, 1), self._flags)
+        nbytes = ctypes.c_size_t(0)
+        _check(self._lib, self._lib.pqmc_workspace_bytes(ctypes.byref(self._prob),
+                                                         ctypes.byref(sizing),
+                                                         ctypes.byref(nbytes)))
+        self.workspace_bytes = nbytes.value
+        self._ws = torch.empty(nbytes.value + 256, dtype=torch.uint8, device="cuda")
+        base = self._ws.data_ptr()
+        base = (base + 255) // 256 * 256
+        self._stream = torch.cuda.current_stream()
+        handle = ctypes.c_void_p(0)
+        _check(self._lib, self._lib.pqmc_create(ctypes.byref(self._prob), ctypes.byref(sizing),
+                                                ctypes.c_void_p(self._stream.cuda_stream),
+                                                ctypes.c_void_p(base),
+                                                ctypes.c_size_t(nbytes.value),
+                                                ctypes.byref(handle)))
+        self._ctx = handle
+        self.set_opts(scheme, k, b)
+
+    # -- calls with the C ABI's names
+    def set_opts(self, scheme, k=1, b=1, log=None, timing=None):
+        flags = self._flags
+        if log is not None:
+            flags = (flags & ~FLAG_LOG) | (FLAG_LOG if log else 0)
+        if timing is not None:
+            flags = (flags & ~FLAG_TIMING) | (FLAG_TIMING if timing else 0)
+        o = UpdateOpts(int(scheme), int(k), int(b), flags)
+        _check(self._lib, self._lib.pqmc_set_opts(self._ctx, ctypes.byref(o)))
+        self.scheme, self.k, self.b, self._flags = Scheme(int(scheme)), int(k), int(b), flags
+
+    def sweep(self, n=1):
+        st = Stats()
+        _check(self._lib, self._lib.pqmc_sweep(self._ctx, int(n), ctypes.byref(st)))
+        return st.as_dict()
+
+    def forward_window(self, n_slices):
+        st = Stats()
+        _check(self._lib, self._lib.pqmc_forward_window(self._ctx, int(n_slices),
+                                                        ctypes.byref(st)))
+        return st.as_dict()
+
+    def green(self, spin):
+        out = np.empty((self.N, self.N), np.float64)
+        _check(self._lib, self._lib.pqmc_get_green(self._ctx, int(spin), _dptr(out)))
+        return out
+
+    def fields(self):
+        out = np.empty((self.M, self.N), np.int8)
+        _check(self._lib, self._lib.pqmc_get_fields(
+            self._ctx, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int8))))
+        return out
+
+    def set_fields(self, fields):
+        f = np.ascontiguousarray(fields, dtype=np.int8).reshape(self.M, self.N)
+        _check(self._lib, self._lib.pqmc_set_fields(
+            self._ctx, f.ctypes.data_as(ctypes.POINTER(ctypes.c_int8))))
+
+    def _log(self, fn):
+        n = ctypes.c_size_t(0)
+        _check(self._lib, fn(self._ctx, None, None, 0, ctypes.byref(n)))
+        meta = np.empty((max(n.value, 1), 3), np.int32)
+        margin = np.empty(max(n.value, 1), np.float64)
+        _check(self._lib, fn(self._ctx, meta.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                             _dptr(margin), n.value, ctypes.byref(n)))
+        return meta[:n.value], margin[:n.value]
+
+    def decisions(self):
+        """(meta[n, 3] = (dir*M + l-1, site, accepted), margin[n]) of the last call."""
+        return self._log(self._lib.pqmc_get_decisions)
+
+    def heat_bath(self):
+        return self._log(self._lib.pqmc_get_heat_bath)
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            self._lib.pqmc_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,801 @@
+// C ABI of the PQMC field-update sweep: context, workspace layout, setup
+// (K = e^{-dtau H0}, initial stack) and the sweep driver (Sec. II B).
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/pqmc.h"
+#include "engine.hpp"
+
+namespace {
+thread_local std::string g_last_error;
+
+pqmc_status set_error(pqmc_status st, const std::string &msg) {
+  g_last_error = msg;
+  return st;
+}
+}  // namespace
+
+namespace pq {
+int fail_device(hipError_t e, const char *expr, const char *file, int line) {
+  char buf[512];
+  std::snprintf(buf, sizeof buf, "HIP error %d (%s) in %s at %s:%d", (int)e, hipGetErrorString(e),
+                expr, file, line);
+  g_last_error = buf;
+  return PQMC_EDEVICE;
+}
+}  // namespace pq
+
+using namespace pq;
+
+struct pqmc_ctx {
+  int N = 0, Ns[2] = {0, 0}, M = 0, kt = 0, nst = 0;
+  double U = 0, dtau = 0, alpha = 0;
+  uint64_t seed = 0, walker = 0;
+  pqmc_update_opts opts{};
+  int kmax = 1, bmax = 1, gmax = 1;
+  bool log_alloc = false;
+  hipStream_t st = nullptr;
+
+  double *K = nullptr, *Kinv = nullptr, *Tay0 = nullptr, *Tay1 = nullptr;
+  int8_t *fields = nullptr;
+  double *P[2] = {nullptr, nullptr};
+  double *URw[2][2] = {}, *ULw[2][2] = {};
+  double *Lstack[2] = {}, *Rstack[2] = {};
+  double *T[2] = {};
+  double *E[2] = {}, *R2[2] = {}, *Z[2] = {};
+  int *piv[2] = {};
+  double *qrtmp[2] = {};
+  LocalBufs lb{};
+  GroupBufs gb{};
+  unsigned long long *stats = nullptr;
+  int32_t *log_meta = nullptr, *hb_meta = nullptr;
+  double *log_margin = nullptr, *hb_margin = nullptr;
+  long long log_cap = 0;
+  double *gtmp = nullptr, *xtmp = nullptr;
+
+  double *UR[2] = {};
+  double *ULt[2] = {};
+  int position = 0;
+  bool failed = false, windowed = false;
+  uint64_t sweep_index = 0;
+  long long log_count = 0, hb_count = 0, hb_total = 0;
+  std::vector<hipEvent_t> evs;
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+struct Carver {
+  char *base;
+  size_t off = 0;
+  template <class T>
+  T *take(size_t count) {
+    off = (off + kAlign - 1) / kAlign * kAlign;
+    T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+int ceil_div(int a, int b) { return (a + b - 1) / b; }
+
+// Assign every device buffer inside the workspace (or only size it).
+void layout(pqmc_ctx &c, char *base, size_t *bytes) {
+  Carver cv{base};
+  const size_t N = c.N;
+  const size_t NN = N * N;
+  c.K = cv.take<double>(NN);
+  c.Kinv = cv.take<double>(NN);
+  c.Tay0 = cv.take<double>(NN);
+  c.Tay1 = cv.take<double>(NN);
+  c.gtmp = c.Tay0;   // Green's function output reuses the Taylor scratch
+  c.fields = cv.take<int8_t>((size_t)c.M * N);
+  c.stats = cv.take<unsigned long long>(16);
+  const int kmax = c.gmax;
+  for (int s = 0; s < 2; ++s) {
+    const size_t ns = c.Ns[s];
+    const size_t nt = ceil_div(c.Ns[s], 64);
+    c.P[s] = cv.take<double>(N * ns);
+    c.URw[s][0] = cv.take<double>(N * ns);
+    c.URw[s][1] = cv.take<double>(N * ns);
+    c.ULw[s][0] = cv.take<double>(N * ns);
+    c.ULw[s][1] = cv.take<double>(N * ns);
+    c.Lstack[s] = cv.take<double>((size_t)(c.nst + 1) * N * ns);
+    c.Rstack[s] = cv.take<double>((size_t)(c.nst + 1) * N * ns);
+    c.T[s] = cv.take<double>(ns * ns);
+    c.E[s] = cv.take<double>(ns * 2 * ns);
+    c.R2[s] = cv.take<double>((size_t)kNB * 2 * ns);
+    c.Z[s] = cv.take<double>(2 * kNB * kNB);
+    c.piv[s] = cv.take<int>(kNB);
+    c.qrtmp[s] = cv.take<double>(N * ns);
+    for (int p = 0; p < 2; ++p) {
+      c.lb.ypart[s][p] = cv.take<double>(nt * ns);
+      c.lb.tpart[s][p] = cv.take<double>(nt * ns);
+      c.lb.spart[s][p] = cv.take<double>(nt * nt);
+    }
+    c.gb.P2part[s] = cv.take<double>(nt * kmax * ns);
+    c.gb.P1part[s] = cv.take<double>(nt * ns * kmax);
+    c.gb.P2[s] = cv.take<double>(kmax * ns);
+    c.gb.P1[s] = cv.take<double>(ns * kmax);
+    c.gb.W0part[s] = cv.take<double>(nt * kmax * kmax);
+    c.gb.W0[s] = cv.take<double>(kmax * kmax);
+    c.gb.Minv[s] = cv.take<double>(kmax * kmax);
+    c.gb.Q[s] = cv.take<double>(ns * kmax);
+    c.gb.P2c[s] = cv.take<double>(kmax * ns);
+    c.gb.Dsel[s] = cv.take<double>(kmax);
+  }
+  c.lb.delta[0] = cv.take<double>(2);
+  c.lb.delta[1] = cv.take<double>(2);
+  c.gb.Alist = cv.take<int>(kmax);
+  c.gb.nA = cv.take<int>(1);
+  c.gb.kmax = kmax;
+  c.gb.Ns[0] = c.Ns[0];
+  c.gb.Ns[1] = c.Ns[1];
+  c.xtmp = cv.take<double>(N * (size_t)std::max(c.Ns[0], c.Ns[1]));
+  if (c.log_alloc) {
+    c.log_cap = 2LL * c.M * c.N;
+    c.log_meta = cv.take<int32_t>(3 * (size_t)c.log_cap);
+    c.log_margin = cv.take<double>((size_t)c.log_cap);
+    c.hb_meta = cv.take<int32_t>(3 * (size_t)c.log_cap);
+    c.hb_margin = cv.take<double>((size_t)c.log_cap);
+  }
+  *bytes = cv.off + kAlign;
+}
+
+pqmc_status validate(const pqmc_problem *p, const pqmc_update_opts *o) {
+  if (!p || !o) return set_error(PQMC_EINVAL, "null problem or options");
+  if (p->n_sites < 1) return set_error(PQMC_EINVAL, "n_sites must be >= 1");
+  if (p->n_up < 1 || p->n_dn < 1 || p->n_up > p->n_sites || p->n_dn > p->n_sites)
+    return set_error(PQMC_EINVAL, "need 1 <= n_up, n_dn <= n_sites");
+  if (p->n_up > 2048 || p->n_dn > 2048)
+    return set_error(PQMC_EINVAL, "particle numbers above 2048 are not supported");
+  if (!p->hopping || !p->trial_up || !p->trial_dn) return set_error(PQMC_EINVAL, "null input");
+  if (!(p->dtau > 0) || !std::isfinite(p->dtau)) return set_error(PQMC_EINVAL, "dtau must be > 0");
+  if (!std::isfinite(p->U)) return set_error(PQMC_EINVAL, "U must be finite");
+  if (p->U < 0)
+    return set_error(PQMC_EINVAL, "U < 0 (complex coupling) is not supported by this build");
+  if (p->n_slices < 1 || p->stab_every < 1 || p->n_slices % p->stab_every)
+    return set_error(PQMC_EINVAL, "stab_every must divide n_slices");
+  if (o->scheme < PQMC_LOCAL || o->scheme > PQMC_BLOCK_FB) return set_error(PQMC_EINVAL, "scheme");
+  if (o->delay_k < 1 || o->delay_k > 128) return set_error(PQMC_EINVAL, "delay_k in [1, 128]");
+  if (o->block_b < 1 || o->block_b > 64) return set_error(PQMC_EINVAL, "block_b in [1, 64]");
+  const size_t NN = (size_t)p->n_sites * p->n_sites;
+  for (size_t e = 0; e < NN; ++e)
+    if (!std::isfinite(p->hopping[e])) return set_error(PQMC_EINVAL, "non-finite hopping matrix");
+  return PQMC_OK;
+}
+
+void fill_problem(pqmc_ctx &c, const pqmc_problem *p, const pqmc_update_opts *o) {
+  c.N = p->n_sites;
+  c.Ns[0] = p->n_up;
+  c.Ns[1] = p->n_dn;
+  c.M = p->n_slices;
+  c.kt = p->stab_every;
+  c.nst = c.M / c.kt;
+  c.U = p->U;
+  c.dtau = p->dtau;
+  c.alpha = p->U > 0 ? std::acosh(std::exp(p->dtau * p->U / 2.0)) : 0.0;
+  c.seed = p->seed;
+  c.walker = p->walker_id;
+  c.opts = *o;
+  c.kmax = std::min(o->delay_k, c.N);
+  c.bmax = std::min(o->block_b, c.N);
+  c.gmax = std::max(c.kmax, c.bmax);
+  c.log_alloc = (o->flags & PQMC_FLAG_LOG) != 0;
+}
+
+const double kSpin[2] = {1.0, -1.0};
+
+// ------------------------------------------------------------------ helpers
+double *other(double *cur, double *const w[2]) { return cur == w[0] ? w[1] : w[0]; }
+
+int sync_check(pqmc_ctx &c) {
+  PQ_HIP_CHECK(hipStreamSynchronize(c.st));
+  unsigned long long h[16];
+  PQ_HIP_CHECK(hipMemcpy(h, c.stats, sizeof h, hipMemcpyDeviceToHost));
+  if (h[kStError] & kErrSingular) {
+    c.failed = true;
+    return set_error(PQMC_ESINGULAR, "stabilisation factorisation broke down (zero pivot)");
+  }
+  if (h[kStError] & kErrNonFinite) {
+    c.failed = true;
+    return set_error(PQMC_ENONFINITE, "non-finite determinant ratio");
+  }
+  return PQMC_OK;
+}
+
+// CholQR2 of the columns of A (N x Ns per spin) into dst.
+int orthonormalize(pqmc_ctx &c, double *const A[2], double *const dst[2]) {
+  const bool same = c.Ns[0] == c.Ns[1];
+  for (int pass = 0; pass < 2; ++pass) {
+    const double *src[2] = {pass ? c.qrtmp[0] : A[0], pass ? c.qrtmp[1] : A[1]};
+    double *out[2] = {pass ? dst[0] : c.qrtmp[0], pass ? dst[1] : c.qrtmp[1]};
+    GemmBatch gb{};
+    for (int s = 0; s < 2; ++s) {
+      const int n = c.Ns[s];
+      gb.d[gb.count++] = gemm_desc(src[s], n, src[s], n, c.E[s], 2 * n, n, n, c.N);
+    }
+    PQ_HIP_CHECK(gemm(gb, true, false, c.st));
+    ElimSpin es[2];
+    for (int s = 0; s < 2; ++s) {
+      const int n = c.Ns[s];
+      PQ_HIP_CHECK(set_identity_block(c.E[s], nullptr, 2 * n, n, n, c.st));
+      es[s] = ElimSpin{c.E[s], 2L * n, n, 2 * n, c.Z[s], c.piv[s], c.R2[s]};
+    }
+    if (same) {
+      PQ_HIP_CHECK(chol_eliminate(es, 2, c.stats, c.st));
+    } else {
+      PQ_HIP_CHECK(chol_eliminate(&es[0], 1, c.stats, c.st));
+      PQ_HIP_CHECK(chol_eliminate(&es[1], 1, c.stats, c.st));
+    }
+    GemmBatch qb{};
+    for (int s = 0; s < 2; ++s) {
+      const int n = c.Ns[s];
+      qb.d[qb.count++] = gemm_desc(src[s], n, c.E[s] + n, 2 * n, out[s], n, c.N, n, n);
+    }
+    PQ_HIP_CHECK(gemm(qb, false, true, c.st));
+  }
+  return PQMC_OK;
+}
+
+// T = (U_L U_R)^{-1} by blocked Gauss-Jordan with partial pivoting.
+int refresh_T(pqmc_ctx &c) {
+  GemmBatch gb{};
+  for (int s = 0; s < 2; ++s) {
+    const int n = c.Ns[s];
+    gb.d[gb.count++] = gemm_desc(c.ULt[s], n, c.UR[s], n, c.E[s], 2 * n, n, n, c.N);
+  }
+  PQ_HIP_CHECK(gemm(gb, true, false, c.st));
+  ElimSpin es[2];
+  for (int s = 0; s < 2; ++s) {
+    const int n = c.Ns[s];
+    PQ_HIP_CHECK(set_identity_block(c.E[s], nullptr, 2 * n, n, n, c.st));
+    es[s] = ElimSpin{c.E[s], 2L * n, n, 2 * n, c.Z[s], c.piv[s], c.R2[s]};
+  }
+  if (c.Ns[0] == c.Ns[1]) {
+    PQ_HIP_CHECK(gj_invert(es, 2, c.stats, c.st));
+  } else {
+    PQ_HIP_CHECK(gj_invert(&es[0], 1, c.stats, c.st));
+    PQ_HIP_CHECK(gj_invert(&es[1], 1, c.stats, c.st));
+  }
+  for (int s = 0; s < 2; ++s) {
+    const int n = c.Ns[s];
+    PQ_HIP_CHECK(copy_matrix(c.E[s] + n, nullptr, 2 * n, c.T[s], nullptr, n, n, n, c.st));
+  }
+  return PQMC_OK;
+}
+
+double *slot(double *stack, int j, const pqmc_ctx &c, int s) {
+  return stack + (size_t)j * c.N * c.Ns[s];
+}
+
+// position l-1 -> l: U_R <- B_l U_R, U_L <- U_L B_l^{-1}   (Eq. (9))
+int prop_forward(pqmc_ctx &c, int l) {
+  const int8_t *row = c.fields + (size_t)(l - 1) * c.N;
+  GemmBatch gb{};
+  double *nur[2], *nul[2];
+  for (int s = 0; s < 2; ++s) {
+    const int n = c.Ns[s];
+    const double ep = std::exp(c.alpha * kSpin[s]), em = std::exp(-c.alpha * kSpin[s]);
+    nur[s] = other(c.UR[s], c.URw[s]);
+    nul[s] = other(c.ULt[s], c.ULw[s]);
+    GemmDesc d = gemm_desc(c.K, c.N, c.UR[s], n, nur[s], n, c.N, n, c.N);
+    d.rs_field = row; d.rs_pos = ep; d.rs_neg = em;
+    gb.d[gb.count++] = d;
+    GemmDesc e = gemm_desc(c.Kinv, c.N, c.ULt[s], n, nul[s], n, c.N, n, c.N);
+    e.rs_field = row; e.rs_pos = em; e.rs_neg = ep;
+    gb.d[gb.count++] = e;
+  }
+  PQ_HIP_CHECK(gemm(gb, false, false, c.st));
+  for (int s = 0; s < 2; ++s) { c.UR[s] = nur[s]; c.ULt[s] = nul[s]; }
+  return PQMC_OK;
+}
+
+// position l -> l-1: U_L <- U_L B_l, U_R <- B_l^{-1} U_R
+int prop_backward(pqmc_ctx &c, int l, bool with_R) {
+  const int8_t *row = c.fields + (size_t)(l - 1) * c.N;
+  GemmBatch gb{};
+  double *nur[2], *nul[2];
+  for (int s = 0; s < 2; ++s) {
+    const int n = c.Ns[s];
+    const double ep = std::exp(c.alpha * kSpin[s]), em = std::exp(-c.alpha * kSpin[s]);
+    nul[s] = other(c.ULt[s], c.ULw[s]);
+    GemmDesc d = gemm_desc(c.K, c.N, c.ULt[s], n, nul[s], n, c.N, n, c.N);
+    d.ks_field = row; d.ks_pos = ep; d.ks_neg = em;
+    gb.d[gb.count++] = d;
+    if (with_R) {
+      nur[s] = other(c.UR[s], c.URw[s]);
+      GemmDesc e = gemm_desc(c.Kinv, c.N, c.UR[s], n, nur[s], n, c.N, n, c.N);
+      e.ks_field = row; e.ks_pos = em; e.ks_neg = ep;
+      gb.d[gb.count++] = e;
+    }
+  }
+  PQ_HIP_CHECK(gemm(gb, false, false, c.st));
+  for (int s = 0; s < 2; ++s) {
+    c.ULt[s] = nul[s];
+    if (with_R) c.UR[s] = nur[s];
+  }
+  return PQMC_OK;
+}
+
+// Initial stack of row-orthonormalised U_L and position-0 state (Sec. II B).
+int build_state(pqmc_ctx &c) {
+  for (int s = 0; s < 2; ++s) {
+    const int n = c.Ns[s];
+    PQ_HIP_CHECK(copy_matrix(c.P[s], nullptr, n, slot(c.Lstack[s], c.nst, c, s), nullptr, n, c.N,
+                             n, c.st));
+    PQ_HIP_CHECK(copy_matrix(c.P[s], nullptr, n, slot(c.Rstack[s], 0, c, s), nullptr, n, c.N, n,
+                             c.st));
+    c.ULt[s] = slot(c.Lstack[s], c.nst, c, s);
+  }
+  for (int l = c.M; l >= 1; --l) {
+    int rc = prop_backward(c, l, false);
+    if (rc) return rc;
+    if ((l - 1) % c.kt == 0) {
+      const int j = (l - 1) / c.kt;
+      double *src[2] = {c.ULt[0], c.ULt[1]};
+      double *dst[2] = {slot(c.Lstack[0], j, c, 0), slot(c.Lstack[1], j, c, 1)};
+      rc = orthonormalize(c, src, dst);
+      if (rc) return rc;
+      c.ULt[0] = dst[0];
+      c.ULt[1] = dst[1];
+    }
+  }
+  for (int s = 0; s < 2; ++s) c.UR[s] = slot(c.Rstack[s], 0, c, s);
+  int rc = refresh_T(c);
+  if (rc) return rc;
+  c.position = 0;
+  c.windowed = false;
+  return PQMC_OK;
+}
+
+// e^{X} for X = sign * dtau * H0 (uploaded in Tay0 unscaled) by a degree-18
+// Taylor series in Horner form after scaling by 2^-sq, then sq squarings.
+int expm_taylor(pqmc_ctx &c, double scale, int sq, double *dst) {
+  const int N = c.N;
+  double *Y = dst, *Yn = c.Tay1;
+  PQ_HIP_CHECK(set_identity_block(Y, nullptr, N, N, 0, c.st));
+  for (int j = 18; j >= 1; --j) {
+    GemmBatch gb{};
+    GemmDesc d = gemm_desc(c.Tay0, N, Y, N, Yn, N, N, N, N, scale / j);
+    d.addI = 1;
+    gb.d[gb.count++] = d;
+    PQ_HIP_CHECK(gemm(gb, false, false, c.st));
+    std::swap(Y, Yn);
+  }
+  for (int q = 0; q < sq; ++q) {
+    GemmBatch gb{};
+    gb.d[gb.count++] = gemm_desc(Y, N, Y, N, Yn, N, N, N, N);
+    PQ_HIP_CHECK(gemm(gb, false, false, c.st));
+    std::swap(Y, Yn);
+  }
+  if (Y != dst) PQ_HIP_CHECK(copy_matrix(Y, nullptr, N, dst, nullptr, N, N, N, c.st));
+  return PQMC_OK;
+}
+
+SweepCtx sweep_ctx(pqmc_ctx &c, int l, int dir) {
+  SweepCtx x{};
+  x.key0 = c.seed;
+  x.key1 = c.walker;
+  x.sweep = c.sweep_index;
+  x.slice_code = (uint64_t)dir * c.M + (l - 1);
+  x.li = l - 1;
+  x.N = c.N;
+  x.fields = c.fields;
+  for (int s = 0; s < 2; ++s) {
+    x.dflip[s][0] = std::expm1(-2.0 * c.alpha * kSpin[s]);
+    x.dflip[s][1] = std::expm1(2.0 * c.alpha * kSpin[s]);
+    x.dremove[s][0] = std::expm1(-c.alpha * kSpin[s]);
+    x.dremove[s][1] = std::expm1(c.alpha * kSpin[s]);
+  }
+  x.alpha = c.alpha;
+  x.stats = c.stats;
+  if (c.log_alloc && (c.opts.flags & PQMC_FLAG_LOG)) {
+    x.log_meta = c.log_meta;
+    x.log_margin = c.log_margin;
+    x.hb_meta = c.hb_meta;
+    x.hb_margin = c.hb_margin;
+  }
+  x.log_base = c.log_count;
+  x.hb_base = c.hb_count;
+  x.log_cap = c.log_cap;
+  return x;
+}
+
+int update_slice(pqmc_ctx &c, int l, int dir) {
+  SweepCtx x = sweep_ctx(c, l, dir);
+  SpinMats m{};
+  for (int s = 0; s < 2; ++s) {
+    m.T[s] = c.T[s];
+    m.UR[s] = c.UR[s];
+    m.ULt[s] = c.ULt[s];
+    m.Ns[s] = c.Ns[s];
+  }
+  const int N = c.N;
+  switch (c.opts.scheme) {
+    case PQMC_LOCAL: {
+      const int nt = ceil_div(std::max(c.Ns[0], c.Ns[1]), 64);
+      for (int i = 0; i <= N; ++i) PQ_HIP_CHECK(local_step(m, c.lb, x, i, nt, c.st));
+      c.log_count += N;
+      break;
+    }
+    case PQMC_DELAYED: {
+      const int k = std::min(c.opts.delay_k, N);
+      for (int g0 = 0; g0 < N; g0 += k) {
+        const int kk = std::min(k, N - g0);
+        PQ_HIP_CHECK(group_panels(m, c.gb, g0, kk, c.st));
+        PQ_HIP_CHECK(delayed_decide(c.gb, x, g0, kk, c.st));
+        PQ_HIP_CHECK(group_flush(m, c.gb, g0, kk, c.st));
+      }
+      c.log_count += N;
+      break;
+    }
+    default: {
+      const int b = std::min(c.opts.block_b, N);
+      long long bi = 0;
+      for (int g0 = 0; g0 < N; g0 += b, ++bi) {
+        const int kk = std::min(b, N - g0);
+        PQ_HIP_CHECK(group_panels(m, c.gb, g0, kk, c.st));
+        PQ_HIP_CHECK(block_decide(c.gb, x, g0, kk, bi, c.st));
+        PQ_HIP_CHECK(group_flush(m, c.gb, g0, kk, c.st));
+      }
+      c.log_count += bi;
+      c.hb_count += N;
+      break;
+    }
+  }
+  return PQMC_OK;
+}
+
+int stab_forward(pqmc_ctx &c, int l) {
+  const int j = l / c.kt;
+  double *src[2] = {c.UR[0], c.UR[1]};
+  double *dst[2] = {slot(c.Rstack[0], j, c, 0), slot(c.Rstack[1], j, c, 1)};
+  int rc = orthonormalize(c, src, dst);
+  if (rc) return rc;
+  for (int s = 0; s < 2; ++s) {
+    c.UR[s] = dst[s];
+    c.ULt[s] = slot(c.Lstack[s], j, c, s);
+  }
+  return refresh_T(c);
+}
+
+int stab_backward(pqmc_ctx &c, int l) {
+  const int j = (l - 1) / c.kt;
+  double *src[2] = {c.ULt[0], c.ULt[1]};
+  double *dst[2] = {slot(c.Lstack[0], j, c, 0), slot(c.Lstack[1], j, c, 1)};
+  int rc = orthonormalize(c, src, dst);
+  if (rc) return rc;
+  for (int s = 0; s < 2; ++s) {
+    c.ULt[s] = dst[s];
+    c.UR[s] = slot(c.Rstack[s], j, c, s);
+  }
+  return refresh_T(c);
+}
+
+// phase timing: events recorded at boundaries, summed per phase at the end
+struct PhaseTimer {
+  pqmc_ctx &c;
+  bool on;
+  std::vector<std::pair<int, size_t>> marks;  // (phase, event index of start)
+  size_t used = 0;
+  explicit PhaseTimer(pqmc_ctx &cc) : c(cc), on((cc.opts.flags & PQMC_FLAG_TIMING) != 0) {}
+  int mark(int phase) {
+    if (!on) return PQMC_OK;
+    if (used == c.evs.size()) {
+      hipEvent_t e;
+      PQ_HIP_CHECK(hipEventCreate(&e));
+      c.evs.push_back(e);
+    }
+    PQ_HIP_CHECK(hipEventRecord(c.evs[used], c.st));
+    marks.push_back({phase, used});
+    ++used;
+    return PQMC_OK;
+  }
+  void totals(double out[3]) {
+    out[0] = out[1] = out[2] = 0.0;
+    if (!on) return;
+    for (size_t k = 0; k + 1 < marks.size(); ++k) {
+      float ms = 0.f;
+      if (marks[k].first < 0) continue;
+      if (hipEventElapsedTime(&ms, c.evs[marks[k].second], c.evs[marks[k + 1].second]) ==
+          hipSuccess)
+        out[marks[k].first] += ms * 1e-3;
+    }
+  }
+};
+enum { kPhUpdate = 0, kPhProp = 1, kPhStab = 2, kPhEnd = -1 };
+
+int begin_call(pqmc_ctx &c) {
+  PQ_HIP_CHECK(hipMemsetAsync(c.stats, 0, 16 * sizeof(unsigned long long), c.st));
+  c.log_count = 0;
+  c.hb_count = 0;
+  return PQMC_OK;
+}
+
+int finish_call(pqmc_ctx &c, PhaseTimer &tm, double t0, pqmc_stats *out) {
+  int rc = tm.mark(kPhEnd);
+  if (rc) return rc;
+  rc = sync_check(c);
+  const double t1 =
+      std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+  if (out) {
+    unsigned long long h[16];
+    PQ_HIP_CHECK(hipMemcpy(h, c.stats, sizeof h, hipMemcpyDeviceToHost));
+    std::memset(out, 0, sizeof *out);
+    out->proposed = h[kStProposed];
+    out->accepted = h[kStAccepted];
+    out->flips = h[kStFlips];
+    out->low_margin = h[kStLowMargin];
+    out->negative = h[kStNegative];
+    out->field_updates = h[kStFieldUpdates];
+    out->t_total_s = t1 - t0;
+    double ph[3];
+    tm.totals(ph);
+    out->t_update_s = ph[kPhUpdate];
+    out->t_prop_s = ph[kPhProp];
+    out->t_stab_s = ph[kPhStab];
+  }
+  c.hb_total = c.hb_count;
+  return rc;
+}
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+int run_forward(pqmc_ctx &c, int upto, PhaseTimer &tm) {
+  for (int l = 1; l <= upto; ++l) {
+    int rc = tm.mark(kPhProp);
+    if (!rc) rc = prop_forward(c, l);
+    if (!rc) rc = tm.mark(kPhUpdate);
+    if (!rc) rc = update_slice(c, l, 0);
+    if (!rc && l % c.kt == 0) {
+      rc = tm.mark(kPhStab);
+      if (!rc) rc = stab_forward(c, l);
+    }
+    if (rc) return rc;
+    c.position = l;
+  }
+  return PQMC_OK;
+}
+
+int run_backward(pqmc_ctx &c, PhaseTimer &tm) {
+  for (int l = c.M; l >= 1; --l) {
+    int rc = tm.mark(kPhUpdate);
+    if (!rc) rc = update_slice(c, l, 1);
+    if (!rc) rc = tm.mark(kPhProp);
+    if (!rc) rc = prop_backward(c, l, true);
+    if (!rc && (l - 1) % c.kt == 0) {
+      rc = tm.mark(kPhStab);
+      if (!rc) rc = stab_backward(c, l);
+    }
+    if (rc) return rc;
+    c.position = l - 1;
+  }
+  return PQMC_OK;
+}
+
+pqmc_status as_status(int rc) { return (pqmc_status)rc; }
+
+}  // namespace
+
+extern "C" {
+
+const char *pqmc_last_error(void) { return g_last_error.c_str(); }
+
+pqmc_status pqmc_workspace_bytes(const pqmc_problem *prob, const pqmc_update_opts *opts,
+                                 size_t *bytes) {
+  if (!bytes) return set_error(PQMC_EINVAL, "null bytes");
+  pqmc_status v = validate(prob, opts);
+  if (v) return v;
+  pqmc_ctx c;
+  fill_problem(c, prob, opts);
+  layout(c, nullptr, bytes);
+  return PQMC_OK;
+}
+
+pqmc_status pqmc_create(const pqmc_problem *prob, const pqmc_update_opts *opts, void *hip_stream,
+                        void *workspace, size_t workspace_bytes, pqmc_ctx **out) {
+  if (!out) return set_error(PQMC_EINVAL, "null out");
+  *out = nullptr;
+  pqmc_status v = validate(prob, opts);
+  if (v) return v;
+  if (!workspace || (reinterpret_cast<uintptr_t>(workspace) % kAlign))
+    return set_error(PQMC_EINVAL, "workspace must be a 256-byte aligned device pointer");
+  pqmc_ctx *c = new (std::nothrow) pqmc_ctx();
+  if (!c) return set_error(PQMC_ENOMEM, "host allocation failed");
+  fill_problem(*c, prob, opts);
+  size_t need = 0;
+  layout(*c, nullptr, &need);
+  if (workspace_bytes < need) {
+    delete c;
+    return set_error(PQMC_ENOMEM, "workspace smaller than pqmc_workspace_bytes()");
+  }
+  layout(*c, static_cast<char *>(workspace), &need);
+  c->st = static_cast<hipStream_t>(hip_stream);
+  auto fail = [&](int rc) {
+    delete c;
+    return as_status(rc);
+  };
+  const int N = c->N;
+  // host: trial states and H0 (scaled below) to the device
+  int rc = PQMC_OK;
+  {
+    hipError_t e = hipMemcpyAsync(c->P[0], prob->trial_up, sizeof(double) * N * c->Ns[0],
+                                  hipMemcpyHostToDevice, c->st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(c->P[1], prob->trial_dn, sizeof(double) * N * c->Ns[1],
+                         hipMemcpyHostToDevice, c->st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(c->Tay0, prob->hopping, sizeof(double) * N * N, hipMemcpyHostToDevice,
+                         c->st);
+    if (e != hipSuccess) return fail(fail_device(e, "upload", __FILE__, __LINE__));
+  }
+  // scaling: ||dtau H0||_1 / 2^sq <= 1/2
+  double norm1 = 0.0;
+  for (int j = 0; j < N; ++j) {
+    double s = 0.0;
+    for (int i = 0; i < N; ++i) s += std::fabs(prob->hopping[(size_t)i * N + j]);
+    norm1 = std::max(norm1, s);
+  }
+  norm1 *= prob->dtau;
+  int sq = 0;
+  while (norm1 / std::ldexp(1.0, sq) > 0.5) ++sq;
+  const double sc = prob->dtau / std::ldexp(1.0, sq);
+  rc = expm_taylor(*c, -sc, sq, c->K);
+  if (!rc) rc = expm_taylor(*c, +sc, sq, c->Kinv);
+  if (!rc) {
+    hipError_t e = hipMemsetAsync(c->stats, 0, 16 * sizeof(unsigned long long), c->st);
+    if (e != hipSuccess) rc = fail_device(e, "memset", __FILE__, __LINE__);
+  }
+  if (!rc) {
+    hipError_t e = init_fields(c->fields, c->M, N, c->seed, c->walker, c->st);
+    if (e != hipSuccess) rc = fail_device(e, "init_fields", __FILE__, __LINE__);
+  }
+  if (!rc) rc = build_state(*c);
+  if (!rc) rc = sync_check(*c);
+  if (rc) return fail(rc);
+  *out = c;
+  return PQMC_OK;
+}
+
+pqmc_status pqmc_set_opts(pqmc_ctx *c, const pqmc_update_opts *o) {
+  if (!c || !o) return set_error(PQMC_EINVAL, "null argument");
+  if (o->scheme < PQMC_LOCAL || o->scheme > PQMC_BLOCK_FB) return set_error(PQMC_EINVAL, "scheme");
+  if (o->delay_k < 1 || std::min(o->delay_k, c->N) > c->gmax)
+    return set_error(PQMC_EINVAL, "delay_k exceeds the workspace bound");
+  if (o->block_b < 1 || o->block_b > 64 || std::min(o->block_b, c->N) > c->gmax)
+    return set_error(PQMC_EINVAL, "block_b exceeds the workspace bound");
+  if ((o->flags & PQMC_FLAG_LOG) && !c->log_alloc)
+    return set_error(PQMC_EINVAL, "logging was not sized in the workspace");
+  c->opts = *o;
+  return PQMC_OK;
+}
+
+pqmc_status pqmc_set_fields(pqmc_ctx *c, const int8_t *fields) {
+  if (!c || !fields) return set_error(PQMC_EINVAL, "null argument");
+  const size_t n = (size_t)c->M * c->N;
+  for (size_t e = 0; e < n; ++e)
+    if (fields[e] != 1 && fields[e] != -1) return set_error(PQMC_EINVAL, "fields must be +-1");
+  hipError_t e = hipMemcpyAsync(c->fields, fields, n, hipMemcpyHostToDevice, c->st);
+  if (e != hipSuccess) return as_status(fail_device(e, "upload fields", __FILE__, __LINE__));
+  e = hipMemsetAsync(c->stats, 0, 16 * sizeof(unsigned long long), c->st);
+  if (e != hipSuccess) return as_status(fail_device(e, "memset", __FILE__, __LINE__));
+  c->failed = false;
+  int rc = build_state(*c);
+  if (!rc) rc = sync_check(*c);
+  return as_status(rc);
+}
+
+pqmc_status pqmc_get_fields(pqmc_ctx *c, int8_t *fields) {
+  if (!c || !fields) return set_error(PQMC_EINVAL, "null argument");
+  hipError_t e = hipStreamSynchronize(c->st);
+  if (e == hipSuccess)
+    e = hipMemcpy(fields, c->fields, (size_t)c->M * c->N, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return as_status(fail_device(e, "download fields", __FILE__, __LINE__));
+  return PQMC_OK;
+}
+
+pqmc_status pqmc_sweep(pqmc_ctx *c, int32_t n_sweeps, pqmc_stats *out) {
+  if (!c) return set_error(PQMC_EINVAL, "null context");
+  if (n_sweeps < 0) return set_error(PQMC_EINVAL, "n_sweeps < 0");
+  if (c->failed) return set_error(PQMC_ESTATE, "context failed; call pqmc_set_fields");
+  if (c->windowed || c->position != 0)
+    return set_error(PQMC_ESTATE, "walker is mid-sweep after pqmc_forward_window");
+  const double t0 = now_s();
+  int rc = begin_call(*c);
+  PhaseTimer tm(*c);
+  for (int k = 0; k < n_sweeps && !rc; ++k) {
+    rc = run_forward(*c, c->M, tm);
+    if (!rc) rc = run_backward(*c, tm);
+    if (!rc) ++c->sweep_index;
+  }
+  if (rc) {
+    c->failed = true;
+    return as_status(rc);
+  }
+  return as_status(finish_call(*c, tm, t0, out));
+}
+
+pqmc_status pqmc_forward_window(pqmc_ctx *c, int32_t n_slices, pqmc_stats *out) {
+  if (!c) return set_error(PQMC_EINVAL, "null context");
+  if (n_slices < 0 || n_slices > c->M) return set_error(PQMC_EINVAL, "n_slices out of range");
+  if (c->failed) return set_error(PQMC_ESTATE, "context failed; call pqmc_set_fields");
+  if (c->windowed || c->position != 0) return set_error(PQMC_ESTATE, "walker is mid-sweep");
+  const double t0 = now_s();
+  int rc = begin_call(*c);
+  PhaseTimer tm(*c);
+  if (!rc) rc = run_forward(*c, n_slices, tm);
+  c->windowed = true;
+  if (rc) {
+    c->failed = true;
+    return as_status(rc);
+  }
+  return as_status(finish_call(*c, tm, t0, out));
+}
+
+pqmc_status pqmc_get_green(pqmc_ctx *c, int32_t spin, double *out) {
+  if (!c || !out || spin < 0 || spin > 1) return set_error(PQMC_EINVAL, "bad argument");
+  const int N = c->N, n = c->Ns[spin];
+  GemmBatch a{};
+  a.d[a.count++] = gemm_desc(c->UR[spin], n, c->T[spin], n, c->xtmp, n, N, n, n);
+  hipError_t e = gemm(a, false, false, c->st);
+  GemmBatch b{};
+  GemmDesc d = gemm_desc(c->xtmp, n, c->ULt[spin], n, c->gtmp, N, N, N, n, -1.0);
+  d.addI = 1;
+  b.d[b.count++] = d;
+  if (e == hipSuccess) e = gemm(b, false, true, c->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+  if (e == hipSuccess)
+    e = hipMemcpy(out, c->gtmp, sizeof(double) * N * N, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return as_status(fail_device(e, "green", __FILE__, __LINE__));
+  return PQMC_OK;
+}
+
+static pqmc_status copy_log(pqmc_ctx *c, const int32_t *dmeta, const double *dmargin,
+                            long long count, int32_t *meta, double *margin, size_t cap,
+                            size_t *n) {
+  if (!c || !n) return set_error(PQMC_EINVAL, "null argument");
+  if (!c->log_alloc) return set_error(PQMC_EINVAL, "logging was not enabled at creation");
+  const size_t cnt = (size_t)std::min<long long>(count, c->log_cap);
+  *n = cnt;
+  const size_t m = std::min(cnt, cap);
+  hipError_t e = hipStreamSynchronize(c->st);
+  if (e == hipSuccess && m && meta)
+    e = hipMemcpy(meta, dmeta, 3 * sizeof(int32_t) * m, hipMemcpyDeviceToHost);
+  if (e == hipSuccess && m && margin)
+    e = hipMemcpy(margin, dmargin, sizeof(double) * m, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return as_status(fail_device(e, "log copy", __FILE__, __LINE__));
+  return PQMC_OK;
+}
+
+pqmc_status pqmc_get_decisions(pqmc_ctx *c, int32_t *meta, double *margin, size_t cap,
+                               size_t *n) {
+  if (!c) return set_error(PQMC_EINVAL, "null context");
+  return copy_log(c, c->log_meta, c->log_margin, c->log_count, meta, margin, cap, n);
+}
+
+pqmc_status pqmc_get_heat_bath(pqmc_ctx *c, int32_t *meta, double *margin, size_t cap,
+                               size_t *n) {
+  if (!c) return set_error(PQMC_EINVAL, "null context");
+  return copy_log(c, c->hb_meta, c->hb_margin, c->hb_total, meta, margin, cap, n);
+}
+
+pqmc_status pqmc_destroy(pqmc_ctx *c) {
+  if (!c) return PQMC_OK;
+  (void)hipStreamSynchronize(c->st);
+  for (hipEvent_t e : c->evs) (void)hipEventDestroy(e);
+  delete c;
+  return PQMC_OK;
+}
+
+}  // extern "C"

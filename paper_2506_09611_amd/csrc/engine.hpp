@@ -1,0 +1,103 @@
+// Internal interface between the C ABI (capi.cpp) and the kernel files.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include "common.hpp"
+
+namespace pq {
+
+int fail_device(hipError_t e, const char *expr, const char *file, int line);
+
+// ------------------------------------------------------------------ GEMM
+// C = alpha * rs(i) * sum_k op(A)(i,k) ks(k) op(B)(k,j) + beta * Cin(i,j) + [addI && i == j]
+// Row-major storage; op(A) is M x K (A stored K x M when transA), op(B) K x N.
+// rs / ks: optional diagonal scalings read from a field row: x > 0 -> pos, else neg.
+// Split-K: when ksplit > 0, z-slice s of the grid handles k in [s*ksplit, (s+1)*ksplit)
+// and writes C + s*csplit (beta, Cin, addI ignored).
+struct GemmDesc {
+  const double *A, *B, *Cin;
+  double *C;
+  long lda, ldb, ldcin, ldc;
+  int M, N, K;
+  const int *Kdev;                // if set: K = min(K, *Kdev)
+  const int8_t *rs_field;
+  double rs_pos, rs_neg;
+  const int8_t *ks_field;
+  double ks_pos, ks_neg;
+  double alpha, beta;
+  int addI;
+  int ksplit;
+  long csplit;
+};
+constexpr int kGemmMaxBatch = 8;
+struct GemmBatch {
+  GemmDesc d[kGemmMaxBatch];
+  int count;
+};
+GemmDesc gemm_desc(const double *A, long lda, const double *B, long ldb, double *C, long ldc,
+                   int M, int N, int K, double alpha = 1.0, double beta = 0.0,
+                   const double *Cin = nullptr, long ldcin = 0);
+hipError_t gemm(const GemmBatch &b, bool transA, bool transB, hipStream_t st);
+
+// ------------------------------------------------------------- dense LA
+constexpr int kNB = 32;   // panel width of the blocked eliminations
+struct ElimSpin {
+  double *E;       // n x w augmented matrix, row-major, leading dim ld
+  long ld;
+  int n, w;
+  double *Z;       // 2 * kNB * kNB scratch: Z1 then Z2
+  int *piv;        // kNB
+  double *R2;      // kNB x w scratch (Cholesky mode)
+};
+// In-place Gauss-Jordan inversion with partial pivoting inside each panel:
+// E = [A | I] (n x 2n) becomes [* | A^{-1}].
+hipError_t gj_invert(const ElimSpin *s, int nspin, unsigned long long *stats, hipStream_t st);
+// Forward elimination normalised by the Cholesky factor of each diagonal
+// block: E = [S | I] with S SPD becomes [R | R^{-T}], S = R^T R.
+hipError_t chol_eliminate(const ElimSpin *s, int nspin, unsigned long long *stats,
+                          hipStream_t st);
+hipError_t set_identity_block(double *E0, double *E1, long ld, int n, int col0, hipStream_t st);
+hipError_t copy_matrix(const double *src0, const double *src1, long lds, double *dst0,
+                       double *dst1, long ldd, int rows, int cols, hipStream_t st);
+hipError_t init_fields(int8_t *fields, int M, int N, uint64_t k0, uint64_t k1, hipStream_t st);
+
+// ---------------------------------------------------------- field updates
+struct SpinMats {
+  double *T[2];          // Ns x Ns
+  double *UR[2];         // N x Ns (rows = u_i^T)
+  const double *ULt[2];  // N x Ns (rows = columns of U_L)
+  int Ns[2];
+};
+struct LocalBufs {       // fused local-step partials, double-buffered by site parity
+  double *ypart[2][2];   // [spin][parity]: ntr x Ns
+  double *tpart[2][2];   // ntc x Ns
+  double *spart[2][2];   // ntr x ntc
+  double *delta[2];      // [parity]: Delta of the pending site, per spin
+};
+// One launch per site i = 0..N: applies site i-1's decision and rank-1
+// upgrade, then forms the partial ratio products of site i.
+hipError_t local_step(const SpinMats &m, const LocalBufs &b, const SweepCtx &c, int i,
+                      int nt_max, hipStream_t st);
+
+struct GroupBufs {
+  double *P2part[2], *P1part[2];   // split-K partials
+  double *P2[2], *P1[2];           // kmax x Ns, Ns x kmax
+  double *W0part[2];               // nstrip x kmax x kmax
+  double *W0[2];                   // kmax x kmax (block FB scratch)
+  double *Minv[2];                 // kmax x kmax
+  double *Q[2];                    // Ns x kmax
+  double *P2c[2];                  // kmax x Ns
+  double *Dsel[2];                 // kmax
+  int *Alist;                      // kmax
+  int *nA;                         // 1
+  int kmax;
+  int Ns[2];                       // particles per spin
+};
+hipError_t group_panels(const SpinMats &m, const GroupBufs &g, int g0, int kk, hipStream_t st);
+hipError_t delayed_decide(const GroupBufs &g, const SweepCtx &c, int g0, int kk,
+                          hipStream_t st);
+hipError_t block_decide(const GroupBufs &g, const SweepCtx &c, int g0, int kk,
+                        long long block_index, hipStream_t st);
+hipError_t group_flush(const SpinMats &m, const GroupBufs &g, int g0, int kk, hipStream_t st);
+
+}  // namespace pq

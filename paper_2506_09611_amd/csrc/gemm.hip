@@ -1,0 +1,175 @@
+// FP64 GEMM on gfx950 matrix cores (v_mfma_f64_16x16x4f64).
+//
+// One 256-thread workgroup computes a 64x64 tile of C; its four waves each
+// own a 32x32 quadrant held as 2x2 MFMA accumulators (4 doubles per lane per
+// 16x16 block).  A and B tiles of depth 16 are staged through LDS, with the
+// next depth slice prefetched into registers while the current one is
+// multiplied.  The same kernel serves the B-matrix propagation (diagonal
+// field scalings fused into the operand load or the epilogue), the Taylor
+// series of e^{-dtau H0}, the Gram and product matrices of the
+// stabilisation, the split-K panel products of the delayed and block
+// updates, the rank-n_A flush of T and the Green's function assembly.
+//
+// MFMA f64 16x16x4 operand layout (lane l of 64):
+//   A (16x4):  A[l % 16][l / 16]        B (4x16): B[l / 16][l % 16]
+//   D (16x16): lane l, register j holds D[4 * (l / 16) + j][l % 16]
+#include "engine.hpp"
+
+namespace pq {
+
+namespace {
+constexpr int BM = 64, BN = 64, BK = 16, LDSP = 80;  // LDSP: padded LDS row stride
+
+template <bool TA, bool TB>
+__global__ __launch_bounds__(256) void gemm_f64_kernel(GemmBatch batch, int nsplit) {
+  const int bz = blockIdx.z / nsplit;
+  const int split = blockIdx.z % nsplit;
+  if (bz >= batch.count) return;
+  const GemmDesc &g = batch.d[bz];
+  const int M = g.M, N = g.N;
+  int K = g.K;
+  if (g.Kdev) K = min(K, *g.Kdev);
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  if (m0 >= M || n0 >= N) return;
+  int kbeg = 0, kend = K;
+  if (g.ksplit > 0) {
+    kbeg = split * g.ksplit;
+    kend = min(K, kbeg + g.ksplit);
+  } else if (split > 0) {
+    return;
+  }
+  if (g.ksplit <= 0 && K <= 0 && g.Kdev && g.beta == 1.0 && g.Cin == g.C && !g.addI) return;
+
+  __shared__ double As[BK][LDSP];
+  __shared__ double Bs[BK][LDSP];
+
+  const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+
+  const double *A = g.A, *B = g.B;
+  const long lda = g.lda, ldb = g.ldb;
+
+  double ra[4], rb[4];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      int mm, kk;
+      if (!TA) { kk = t & 15; mm = (t >> 4) + 16 * p; }
+      else     { mm = t & 63; kk = (t >> 6) + 4 * p; }
+      const int gi = m0 + mm, gk = k0 + kk;
+      double v = 0.0;
+      if (gi < M && gk < kend) v = TA ? A[(long)gk * lda + gi] : A[(long)gi * lda + gk];
+      ra[p] = v;
+    }
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      int nn, kk;
+      if (!TB) { nn = t & 63; kk = (t >> 6) + 4 * p; }
+      else     { kk = t & 15; nn = (t >> 4) + 16 * p; }
+      const int gj = n0 + nn, gk = k0 + kk;
+      double v = 0.0;
+      if (gj < N && gk < kend) {
+        v = TB ? B[(long)gj * ldb + gk] : B[(long)gk * ldb + gj];
+        if (g.ks_field) v *= (g.ks_field[gk] > 0) ? g.ks_pos : g.ks_neg;
+      }
+      rb[p] = v;
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      int mm, kk;
+      if (!TA) { kk = t & 15; mm = (t >> 4) + 16 * p; }
+      else     { mm = t & 63; kk = (t >> 6) + 4 * p; }
+      As[kk][mm] = ra[p];
+    }
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      int nn, kk;
+      if (!TB) { nn = t & 63; kk = (t >> 6) + 4 * p; }
+      else     { kk = t & 15; nn = (t >> 4) + 16 * p; }
+      Bs[kk][nn] = rb[p];
+    }
+  };
+
+  dbl4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+
+  if (kbeg < kend) load(kbeg);
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
+    store();
+    __syncthreads();
+    if (k0 + BK < kend) load(k0 + BK);
+#pragma unroll
+    for (int ks = 0; ks < BK / 4; ++ks) {
+      const int kk = ks * 4 + (lane >> 4);
+      const double a0 = As[kk][wm * 32 + (lane & 15)];
+      const double a1 = As[kk][wm * 32 + 16 + (lane & 15)];
+      const double b0 = Bs[kk][wn * 32 + (lane & 15)];
+      const double b1 = Bs[kk][wn * 32 + 16 + (lane & 15)];
+      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+
+  double *C = g.C;
+  if (g.ksplit > 0) C += (long)split * g.csplit;
+  const bool split_out = g.ksplit > 0;
+#pragma unroll
+  for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int row = m0 + wm * 32 + mi * 16 + 4 * (lane >> 4) + j;
+        const int col = n0 + wn * 32 + ni * 16 + (lane & 15);
+        if (row < M && col < N) {
+          double v = g.alpha * acc[mi][ni][j];
+          if (g.rs_field) v *= (g.rs_field[row] > 0) ? g.rs_pos : g.rs_neg;
+          if (!split_out) {
+            if (g.beta != 0.0) v += g.beta * g.Cin[(long)row * g.ldcin + col];
+            if (g.addI && row == col) v += 1.0;
+          }
+          C[(long)row * g.ldc + col] = v;
+        }
+      }
+}
+}  // namespace
+
+GemmDesc gemm_desc(const double *A, long lda, const double *B, long ldb, double *C, long ldc,
+                   int M, int N, int K, double alpha, double beta, const double *Cin,
+                   long ldcin) {
+  GemmDesc d{};
+  d.A = A; d.B = B; d.C = C; d.Cin = Cin ? Cin : C;
+  d.lda = lda; d.ldb = ldb; d.ldc = ldc; d.ldcin = Cin ? ldcin : ldc;
+  d.M = M; d.N = N; d.K = K;
+  d.alpha = alpha; d.beta = beta;
+  d.rs_pos = d.rs_neg = d.ks_pos = d.ks_neg = 1.0;
+  return d;
+}
+
+hipError_t gemm(const GemmBatch &b, bool transA, bool transB, hipStream_t st) {
+  if (b.count <= 0) return hipSuccess;
+  int mt = 0, nt = 0, ns = 1;
+  for (int i = 0; i < b.count; ++i) {
+    mt = max(mt, (b.d[i].M + BM - 1) / BM);
+    nt = max(nt, (b.d[i].N + BN - 1) / BN);
+    if (b.d[i].ksplit > 0) ns = max(ns, (b.d[i].K + b.d[i].ksplit - 1) / b.d[i].ksplit);
+  }
+  if (mt == 0 || nt == 0) return hipSuccess;
+  dim3 grid(nt, mt, b.count * ns);
+  if (!transA && !transB) hipLaunchKernelGGL((gemm_f64_kernel<false, false>), grid, dim3(256), 0, st, b, ns);
+  else if (transA && !transB) hipLaunchKernelGGL((gemm_f64_kernel<true, false>), grid, dim3(256), 0, st, b, ns);
+  else if (!transA && transB) hipLaunchKernelGGL((gemm_f64_kernel<false, true>), grid, dim3(256), 0, st, b, ns);
+  else hipLaunchKernelGGL((gemm_f64_kernel<true, true>), grid, dim3(256), 0, st, b, ns);
+  return hipGetLastError();
+}
+
+}  // namespace pq

@@ -1,0 +1,93 @@
+"""GPU <-> oracle parity through the C ABI.
+
+Same seeded inputs (synth) and the same Philox counters on both sides: the
+GPU path must reproduce the oracle's accepted-flip sequence exactly (up to
+any decision with | |A| - u | < 1e-12, counted) and G to 1e-10 relative.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle.pqmc import Walker
+from gpu_util import make_chain, compare_decisions, green_rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2506_09611_amd import load_library
+    load_library()
+
+
+def _small(**kw):
+    base = dict(n_slices=20, stab_every=5, perturb=1e-3, seed=synth.SEED_BASE + 11)
+    base.update(kw)
+    return synth.make_problem(4, 5, 5, 4.0, **base)
+
+
+def test_initial_fields_match_philox():
+    p = _small()
+    ch = make_chain(p, "local")
+    w = Walker(p, "local")
+    assert np.array_equal(ch.fields(), w.fields)
+
+
+def test_initial_green_matches():
+    p = _small()
+    ch = make_chain(p, "local")
+    w = Walker(p, "local")
+    assert green_rel_err(ch, w) < 1e-12
+
+
+def test_u0_projector_after_sweep():
+    """U = 0: every proposal accepted and G = 1 - P P^T after a full sweep."""
+    p = synth.make_problem(4, 5, 5, 0.0, n_slices=20, stab_every=5, perturb=1e-3, seed=5)
+    for scheme, kw in [("local", {}), ("delayed", {"k": 3}), ("block", {"b": 4})]:
+        ch = make_chain(p, scheme, **kw)
+        st = ch.sweep(1)
+        assert st["accepted"] == st["proposed"] > 0
+        G0 = np.eye(16) - p.trial_up @ p.trial_up.T
+        for s in range(2):
+            assert np.max(np.abs(ch.green(s) - G0)) < 1e-12, scheme
+
+
+@pytest.mark.parametrize("scheme,kw", [("local", {}), ("delayed", {"k": 4}),
+                                       ("delayed", {"k": 7}), ("block", {"b": 4}),
+                                       ("block", {"b": 3})])
+def test_small_parity_two_sweeps(scheme, kw):
+    p = _small()
+    w = Walker(p, scheme, **kw)
+    ch = make_chain(p, scheme, **kw)
+    for sw in range(2):
+        w.sweep()
+        ch.sweep(1)
+        meta, margin = ch.decisions()
+        n, low = compare_decisions(meta, margin, w.log, sw, p.n_slices)
+        print(f"{scheme} {kw} sweep {sw}: {n} decisions equal, low-margin {low}", flush=True)
+        if low:
+            return
+        assert np.array_equal(ch.fields(), w.fields)
+        assert green_rel_err(ch, w) < 1e-10
+
+
+@pytest.mark.parametrize("scheme,kw", [("local", {}), ("delayed", {"k": 4}), ("block", {"b": 4})])
+def test_c1_parity(scheme, kw):
+    """4x4, U/t = 4, N_sigma = 5, dtau = 0.05, M = 400, k_tau = 10 (closed shell)."""
+    p = synth.workload("c1")
+    w = Walker(p, scheme, **kw)
+    ch = make_chain(p, scheme, **kw)
+    for sw in range(2):
+        w.sweep()
+        ch.sweep(1)
+        meta, margin = ch.decisions()
+        n, low = compare_decisions(meta, margin, w.log, sw, p.n_slices)
+        if low:
+            return
+        assert np.array_equal(ch.fields(), w.fields)
+        assert green_rel_err(ch, w) < 1e-10
