@@ -68,21 +68,27 @@ __global__ __launch_bounds__(kPanelThreads) void gj_panel_kernel(PanelArgs a) {
       red_i[rg] = bi;
     }
     __syncthreads();
-    if (t == 0) {
-      double best = -1.0;
-      int bi = j;
-      for (int g = 0; g < 32; ++g) {
-        if (red_i[g] >= 0 && (red_v[g] > best || (red_v[g] == best && red_i[g] < bi))) {
-          best = red_v[g];
-          bi = red_i[g];
+    // argmax over the 32 row groups in wave 0 (ties: smallest row)
+    if (t < 64) {
+      double bv = (t < 32 && red_i[t] >= 0) ? red_v[t] : -1.0;
+      int bix = (t < 32 && red_i[t] >= 0) ? red_i[t] : 0x7fffffff;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ov = __shfl_xor(bv, o, 64);
+        const int oi = __shfl_xor(bix, o, 64);
+        const bool take = (ov > bv) || (ov == bv && oi < bix);
+        bv = take ? ov : bv;
+        bix = take ? oi : bix;
+      }
+      if (t == 0) {
+        int bi = bix;
+        if (!(bv > 0.0) || bi == 0x7fffffff) {
+          a.stats[kStError] |= kErrSingular;
+          bi = j;
         }
+        s_p = bi;
+        S.piv[j] = kb + bi;
       }
-      if (!(best > 0.0)) {
-        a.stats[kStError] |= kErrSingular;
-        bi = j;
-      }
-      s_p = bi;
-      S.piv[j] = kb + bi;
     }
     __syncthreads();
     const int p = s_p;

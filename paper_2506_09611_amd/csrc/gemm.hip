@@ -12,7 +12,7 @@
 //
 // MFMA f64 16x16x4 operand layout (lane l of 64):
 //   A (16x4):  A[l % 16][l / 16]        B (4x16): B[l / 16][l % 16]
-//   D (16x16): lane l, register j holds D[4 * (l / 16) + j][l % 16]
+//   D (16x16): lane l, register j holds D[l / 16 + 4 * j][l % 16]
 #include "engine.hpp"
 
 namespace pq {
@@ -128,7 +128,7 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmBatch batch, int nspl
     for (int ni = 0; ni < 2; ++ni)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int row = m0 + wm * 32 + mi * 16 + 4 * (lane >> 4) + j;
+        const int row = m0 + wm * 32 + mi * 16 + (lane >> 4) + 4 * j;
         const int col = n0 + wn * 32 + ni * 16 + (lane & 15);
         if (row < M && col < N) {
           double v = g.alpha * acc[mi][ni][j];

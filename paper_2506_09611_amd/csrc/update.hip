@@ -99,7 +99,8 @@ __global__ __launch_bounds__(256) void local_step_kernel(LocalArgs a) {
     const double u = philox_uniform(C.key0, C.key1, C.sweep, C.slice_code, (uint64_t)(i - 1),
                                     kPurposeMH);
     const bool finite = isfinite(R);
-    const bool acc = finite && (u < absA);
+    // every lane computes the same value; make it an explicit scalar
+    const bool acc = __builtin_amdgcn_readfirstlane((finite && (u < absA)) ? 1 : 0) != 0;
     const double rs = s ? r1 : r0;
     if (acc) {
       // x_r = (T v)_r / r over all column tiles; y_c over all row tiles
@@ -250,14 +251,13 @@ constexpr int kDecThreads = 1024;
 struct DecideArgs {
   GroupBufs g;
   SweepCtx c;
-  int Ns[2];
   int g0, kk;
   long long block_index;
 };
 
 // sum of the W0 strip partials for element (a, b)
 __device__ __forceinline__ double w0_elem(const DecideArgs &A, int s, int a, int b) {
-  const int nt = (A.Ns[s] + 63) / 64;
+  const int nt = (A.g.Ns[s] + 63) / 64;
   const int kmax = A.g.kmax;
   double v = 0.0;
   for (int sp = 0; sp < nt; ++sp) v += A.g.W0part[s][(long)sp * kmax * kmax + a * kmax + b];
@@ -275,7 +275,6 @@ __global__ __launch_bounds__(kDecThreads) void delayed_decide_kernel(DecideArgs 
   __shared__ double dl[2][128];
   __shared__ int acc_s[128];
   __shared__ int pos[128];
-  __shared__ int s_nA;
 
   if (t < kk) {
     const int site = A.g0 + t;
@@ -300,14 +299,13 @@ __global__ __launch_bounds__(kDecThreads) void delayed_decide_kernel(DecideArgs 
     }
   }
   __syncthreads();
-  int nA = 0;
   for (int j = 0; j < kk; ++j) {
     const int par = j & 1, nxt = par ^ 1;
     const double p0 = colb[0][par][j], p1 = colb[1][par][j];
     const double R = p0 * p1;
     const double absA = fabs(R);
     const bool finite = isfinite(R);
-    const bool acc = finite && (uni[j] < absA);
+    const bool acc = __builtin_amdgcn_readfirstlane((finite && (uni[j] < absA)) ? 1 : 0) != 0;
     if (t == 0) {
       const double margin = absA - uni[j];
       C.stats[kStProposed] += 1;
@@ -319,7 +317,6 @@ __global__ __launch_bounds__(kDecThreads) void delayed_decide_kernel(DecideArgs 
       record_decision(C, C.log_base + A.g0 + j, A.g0 + j, acc, margin);
       acc_s[j] = acc ? 1 : 0;
     }
-    if (acc) ++nA;
 #pragma unroll
     for (int q = 0; q < kDecQ; ++q) {
       const int e = t + kDecThreads * q;
@@ -342,23 +339,21 @@ __global__ __launch_bounds__(kDecThreads) void delayed_decide_kernel(DecideArgs 
     }
     __syncthreads();
   }
-  if (t == 0) {
-    int n = 0;
-    for (int j = 0; j < kk; ++j) {
-      pos[j] = acc_s[j] ? n : -1;
-      if (acc_s[j]) {
-        A.g.Alist[n] = j;
-        A.g.Dsel[0][n] = dl[0][j];
-        A.g.Dsel[1][n] = dl[1][j];
-        C.fields[(long)C.li * C.N + A.g0 + j] = (int8_t)(-C.fields[(long)C.li * C.N + A.g0 + j]);
-        ++n;
-      }
+  // compaction of the accepted set, one lane per site (no single-lane loops)
+  if (t < kk) {
+    int before = 0;
+    for (int m = 0; m < t; ++m) before += acc_s[m];
+    const int mine = acc_s[t];
+    pos[t] = mine ? before : -1;
+    if (mine) {
+      A.g.Alist[before] = t;
+      A.g.Dsel[0][before] = dl[0][t];
+      A.g.Dsel[1][before] = dl[1][t];
+      C.fields[(long)C.li * C.N + A.g0 + t] = (int8_t)(-C.fields[(long)C.li * C.N + A.g0 + t]);
     }
-    s_nA = n;
-    *A.g.nA = n;
+    if (t == kk - 1) *A.g.nA = before + mine;
   }
   __syncthreads();
-  (void)nA;
   // M^{-1} = (E_AA)^{-1} = -(swept E)_AA, compacted
   const int kmax = A.g.kmax;
 #pragma unroll
@@ -490,14 +485,16 @@ __global__ __launch_bounds__(kDecThreads) void block_decide_kernel(DecideArgs A)
       if (fabs(hb_margin_s[j]) < 1e-12) ++low;
     C.stats[kStLowMargin] += low;
   }
-  if (t == 0) {
-    int n = 0;
-    for (int j = 0; j < kk; ++j)
-      if (xnew[j] != xold[j]) flist[n++] = j;
-    s_nF = n;
+  // flip set F in site order, one lane per site
+  if (t < kk) {
+    int before = 0;
+    for (int m = 0; m < t; ++m) before += (xnew[m] != xold[m]) ? 1 : 0;
+    const int mine = (xnew[t] != xold[t]) ? 1 : 0;
+    if (mine) flist[before] = t;
+    if (t == kk - 1) s_nF = before + mine;
   }
   __syncthreads();
-  const int nF = s_nF;
+  const int nF = __builtin_amdgcn_readfirstlane(s_nF);
   const double u_mh = philox_uniform(C.key0, C.key1, C.sweep, C.slice_code, (uint64_t)A.g0,
                                      kPurposeMH);
   if (nF == 0) {
@@ -557,40 +554,36 @@ __global__ __launch_bounds__(kDecThreads) void block_decide_kernel(DecideArgs A)
     }
     __syncthreads();
   }
-  __shared__ int s_acc;
+  // prior ratio P(X'->X)/P(X->X') and the test, evaluated identically in every lane
+  double lp = 0.0;
+  for (int a = 0; a < nF; ++a) {
+    const int j = flist[a];
+    lp += sval[j] * (double)(xold[j] - xnew[j]);
+  }
+  const double prior = exp(lp);
+  const double Rb = pivprod[0] * pivprod[1];
+  const double absAb = fabs(Rb * prior);
+  const bool finite_b = isfinite(absAb);
+  const bool acc_b = __builtin_amdgcn_readfirstlane((finite_b && (u_mh < absAb)) ? 1 : 0) != 0;
   if (t == 0) {
-    double lp = 0.0;
-    for (int a = 0; a < nF; ++a) {
-      const int j = flist[a];
-      lp += sval[j] * (double)(xold[j] - xnew[j]);
-    }
-    const double prior = exp(lp);
-    const double R = pivprod[0] * pivprod[1];
-    const double absA = fabs(R * prior);
-    const bool finite = isfinite(absA);
-    const bool acc = finite && (u_mh < absA);
-    const double margin = absA - u_mh;
+    const double margin = absAb - u_mh;
     C.stats[kStProposed] += 1;
     C.stats[kStFieldUpdates] += kk;
-    if (acc) { C.stats[kStAccepted] += 1; C.stats[kStFlips] += nF; }
+    if (acc_b) { C.stats[kStAccepted] += 1; C.stats[kStFlips] += nF; }
     if (fabs(margin) < 1e-12) C.stats[kStLowMargin] += 1;
-    if (R < 0.0) C.stats[kStNegative] += 1;
-    if (!finite) C.stats[kStError] |= kErrNonFinite;
-    record_decision(C, C.log_base + A.block_index, A.g0, acc, margin);
-    s_acc = acc ? 1 : 0;
-    if (acc) {
-      for (int a = 0; a < nF; ++a) {
-        const int j = flist[a];
-        A.g.Alist[a] = j;
-        A.g.Dsel[0][a] = dp[0][a];
-        A.g.Dsel[1][a] = dp[1][a];
-        C.fields[(long)C.li * C.N + A.g0 + j] = (int8_t)xnew[j];
-      }
-    }
-    *A.g.nA = acc ? nF : 0;
+    if (Rb < 0.0) C.stats[kStNegative] += 1;
+    if (!finite_b) C.stats[kStError] |= kErrNonFinite;
+    record_decision(C, C.log_base + A.block_index, A.g0, acc_b, margin);
+    *A.g.nA = acc_b ? nF : 0;
   }
-  __syncthreads();
-  if (s_acc) {
+  if (acc_b && t < nF) {
+    const int j = flist[t];
+    A.g.Alist[t] = j;
+    A.g.Dsel[0][t] = dp[0][t];
+    A.g.Dsel[1][t] = dp[1][t];
+    C.fields[(long)C.li * C.N + A.g0 + j] = (int8_t)xnew[j];
+  }
+  if (acc_b) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int e = t + kDecThreads * q;
@@ -716,8 +709,6 @@ hipError_t block_decide(const GroupBufs &g, const SweepCtx &c, int g0, int kk,
   a.c = c;
   a.g0 = g0;
   a.kk = kk;
-  a.Ns[0] = g.Ns[0];
-  a.Ns[1] = g.Ns[1];
   a.block_index = block_index;
   hipLaunchKernelGGL(block_decide_kernel, dim3(1), dim3(kDecThreads), 0, st, a);
   return hipGetLastError();
