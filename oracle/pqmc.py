@@ -205,8 +205,11 @@ class Walker:
 
     def metropolis(self, d, li, site, R, extra=1.0):
         """Eq. (16) with a symmetric proposal: accept iff u < |R * extra|."""
-        A = R * extra
-        absA = abs(A)
+        with np.errstate(over="ignore", invalid="ignore"):
+            A = R * extra
+            absA = abs(A)
+        if np.isnan(absA):
+            raise FloatingPointError("acceptance ratio is NaN")
         if self.trace is not None:
             self.trace.append((d, li, site, R, extra, self.fields.copy()))
         u = self.mh_uniform(d, li, site)
@@ -308,8 +311,13 @@ class Walker:
 
     @staticmethod
     def heat_bath_prob(svec):
-        """P(x' = +1) = e^{s} / (e^{s} + e^{-s}) per site (Sec. II D, second step)."""
-        return np.array([1.0 / (1.0 + math.exp(-2.0 * s)) for s in svec])
+        """P(x' = +1) = e^{s} / (e^{s} + e^{-s}) per site (Sec. II D, second step).
+
+        For U > 0 the mixed-estimate force bias is unbounded when the overlap
+        with the block's fields removed nearly vanishes, so e^{-2s} may
+        overflow: it is evaluated in IEEE arithmetic (inf gives P = 0)."""
+        with np.errstate(over="ignore"):
+            return np.array([1.0 / (1.0 + np.exp(-2.0 * float(s))) for s in svec])
 
     def block_ratio(self, li, sites, xnew, svec):
         """det ratios r_s = det[1 + (U' T) V'] over the flip set (Sec. III B) and
@@ -325,7 +333,8 @@ class Walker:
             Up = self.UR[s][idx, :]
             Wp = np.eye(len(F)) + (Up @ self.T[s]) @ Vp
             out.append((np.linalg.det(Wp), Vp, Up, Wp, Dp))
-        prior = math.exp(float(np.sum(svec[F] * (xold[F] - xnew[F]))))
+        with np.errstate(over="ignore"):
+            prior = float(np.exp(float(np.sum(svec[F] * (xold[F] - xnew[F])))))
         return F, idx, out, prior
 
     def block_slice(self, l, d):
