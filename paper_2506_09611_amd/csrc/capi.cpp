@@ -427,28 +427,33 @@ int update_slice(pqmc_ctx &c, int l, int dir) {
       c.log_count += N;
       break;
     }
-    case PQMC_DELAYED: {
-      const int k = std::min(c.opts.delay_k, N);
-      for (int g0 = 0; g0 < N; g0 += k) {
-        const int kk = std::min(k, N - g0);
-        PQ_HIP_CHECK(group_panels(m, c.gb, g0, kk, c.st));
-        PQ_HIP_CHECK(delayed_decide(c.gb, x, g0, kk, c.st));
-        PQ_HIP_CHECK(group_flush(m, c.gb, g0, kk, c.st));
-      }
-      c.log_count += N;
-      break;
-    }
+    case PQMC_DELAYED:
     default: {
-      const int b = std::min(c.opts.block_b, N);
+      const bool delayed = c.opts.scheme == PQMC_DELAYED;
+      const int k = std::min(delayed ? c.opts.delay_k : c.opts.block_b, N);
+      const bool fused = c.gmax <= 64;
       long long bi = 0;
-      for (int g0 = 0; g0 < N; g0 += b, ++bi) {
-        const int kk = std::min(b, N - g0);
-        PQ_HIP_CHECK(group_panels(m, c.gb, g0, kk, c.st));
-        PQ_HIP_CHECK(block_decide(c.gb, x, g0, kk, bi, c.st));
-        PQ_HIP_CHECK(group_flush(m, c.gb, g0, kk, c.st));
+      int g_prev = -1;
+      for (int g0 = 0; g0 < N; g0 += k, ++bi) {
+        const int kk = std::min(k, N - g0);
+        if (fused) {
+          PQ_HIP_CHECK(group_tile(m, c.gb, g_prev >= 0, g_prev, g0, kk, c.st));
+          PQ_HIP_CHECK(group_reduce(m, c.gb, g0, kk, c.st));
+        } else {
+          PQ_HIP_CHECK(group_panels(m, c.gb, g0, kk, c.st));
+        }
+        if (delayed) PQ_HIP_CHECK(delayed_decide(c.gb, x, g0, kk, c.st));
+        else PQ_HIP_CHECK(block_decide(c.gb, x, g0, kk, bi, c.st));
+        if (fused) g_prev = g0;
+        else PQ_HIP_CHECK(group_flush(m, c.gb, g0, kk, c.st));
       }
-      c.log_count += bi;
-      c.hb_count += N;
+      if (fused && g_prev >= 0) PQ_HIP_CHECK(group_tile(m, c.gb, true, g_prev, 0, 0, c.st));
+      if (delayed) {
+        c.log_count += N;
+      } else {
+        c.log_count += bi;
+        c.hb_count += N;
+      }
       break;
     }
   }

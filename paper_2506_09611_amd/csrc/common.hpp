@@ -70,6 +70,20 @@ enum { kStProposed = 0, kStAccepted = 1, kStFlips = 2, kStLowMargin = 3, kStNega
        kStFieldUpdates = 5, kStError = 8 };
 enum { kErrNonFinite = 1, kErrSingular = 2 };
 
+// sum_{i < n} p[i * stride] in index order; loads issued eight at a time so
+// the partial-sum chains are not serialised on memory latency.
+__device__ __forceinline__ double sum_strided(const double *p, long stride, int n) {
+  double s = 0.0;
+  for (int b = 0; b < n; b += 8) {
+    double v[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = (b + i < n) ? p[(long)(b + i) * stride] : 0.0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) s += v[i];
+  }
+  return s;
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);

@@ -99,5 +99,11 @@ hipError_t delayed_decide(const GroupBufs &g, const SweepCtx &c, int g0, int kk,
 hipError_t block_decide(const GroupBufs &g, const SweepCtx &c, int g0, int kk,
                         long long block_index, hipStream_t st);
 hipError_t group_flush(const SpinMats &m, const GroupBufs &g, int g0, int kk, hipStream_t st);
+// Fused path (kmax <= 64): one tile kernel per group applies the previous
+// group's flush and forms this group's split-K panel partials; group_reduce
+// then sums them (and the W0 strip partials).
+hipError_t group_tile(const SpinMats &m, const GroupBufs &g, bool flush, int g0_prev, int g0,
+                      int kk, hipStream_t st);
+hipError_t group_reduce(const SpinMats &m, const GroupBufs &g, int g0, int kk, hipStream_t st);
 
 }  // namespace pq

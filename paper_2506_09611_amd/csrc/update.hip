@@ -71,6 +71,7 @@ __global__ __launch_bounds__(256) void local_step_kernel(LocalArgs a) {
   __shared__ double red[4][64];
   __shared__ double sred[4];
   __shared__ double s_r[2];
+  __shared__ double xs[64], ys[64];
 
   double tv[16];
 #pragma unroll
@@ -98,24 +99,24 @@ __global__ __launch_bounds__(256) void local_step_kernel(LocalArgs a) {
     const double absA = fabs(R);
     const double u = philox_uniform(C.key0, C.key1, C.sweep, C.slice_code, (uint64_t)(i - 1),
                                     kPurposeMH);
-    const bool finite = isfinite(R);
+    const bool finite = !isnan(absA);
     // every lane computes the same value; make it an explicit scalar
     const bool acc = __builtin_amdgcn_readfirstlane((finite && (u < absA)) ? 1 : 0) != 0;
     const double rs = s ? r1 : r0;
     if (acc) {
-      // x_r = (T v)_r / r over all column tiles; y_c over all row tiles
-      double yc = 0.0;
-      if (colok)
-        for (int b2 = 0; b2 < nt; ++b2) yc += a.b.ypart[s][par][(long)b2 * Ns + col];
-#pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        const int r = row0 + rq + 4 * q;
-        if (r < Ns) {
-          double xr = 0.0;
-          for (int b2 = 0; b2 < nt; ++b2) xr += a.b.tpart[s][par][(long)b2 * Ns + r];
-          tv[q] -= (xr / rs) * yc;
-        }
+      // x_r = (T v)_r / r over all column tiles (threads 0..63), y_c over all
+      // row tiles (threads 64..127), then the rank-1 upgrade of this tile
+      if (t < 64) {
+        const int r = row0 + t;
+        xs[t] = (r < Ns) ? sum_strided(a.b.tpart[s][par] + r, Ns, nt) / rs : 0.0;
+      } else if (t < 128) {
+        const int cc = col0 + (t - 64);
+        ys[t - 64] = (cc < Ns) ? sum_strided(a.b.ypart[s][par] + cc, Ns, nt) : 0.0;
       }
+      __syncthreads();
+      const double yc = ys[c];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) tv[q] -= xs[rq + 4 * q] * yc;
       dirty = true;
     }
     if (designated) {
@@ -216,7 +217,7 @@ __global__ __launch_bounds__(256) void group_reduce_kernel(ReduceArgs a) {
     double v = 0.0, l = 0.0;
     if (cc < w) {
       const long off = (long)mrow * Ns + c0 + cc;
-      for (int sp = 0; sp < nt; ++sp) v += a.g.P2part[s][(long)sp * kmax * Ns + off];
+      v = sum_strided(a.g.P2part[s] + off, (long)kmax * Ns, nt);
       a.g.P2[s][off] = v;
       l = a.m.ULt[s][(long)(a.g0 + mrow) * Ns + c0 + cc];
     }
@@ -228,9 +229,7 @@ __global__ __launch_bounds__(256) void group_reduce_kernel(ReduceArgs a) {
     const int rr = e / kk, mcol = e % kk;
     if (rr < w) {
       const long off = (long)(c0 + rr) * kmax + mcol;
-      double v = 0.0;
-      for (int sp = 0; sp < nt; ++sp) v += a.g.P1part[s][(long)sp * Ns * kmax + off];
-      a.g.P1[s][off] = v;
+      a.g.P1[s][off] = sum_strided(a.g.P1part[s] + off, (long)Ns * kmax, nt);
     }
   }
   __syncthreads();
@@ -246,7 +245,6 @@ __global__ __launch_bounds__(256) void group_reduce_kernel(ReduceArgs a) {
 // ------------------------------------------------------------------------
 // decision kernels (one workgroup of 1024 threads)
 // ------------------------------------------------------------------------
-constexpr int kDecThreads = 1024;
 
 struct DecideArgs {
   GroupBufs g;
@@ -259,13 +257,12 @@ struct DecideArgs {
 __device__ __forceinline__ double w0_elem(const DecideArgs &A, int s, int a, int b) {
   const int nt = (A.g.Ns[s] + 63) / 64;
   const int kmax = A.g.kmax;
-  double v = 0.0;
-  for (int sp = 0; sp < nt; ++sp) v += A.g.W0part[s][(long)sp * kmax * kmax + a * kmax + b];
-  return v;
+  return sum_strided(A.g.W0part[s] + a * kmax + b, (long)kmax * kmax, nt);
 }
 
-// kDecQ = ceil(kk * kk / 1024) elements of each spin's E per thread.
-template <int kDecQ>
+// kDecThreads lanes, kDecQ = ceil(kk * kk / kDecThreads) elements of each
+// spin's E per lane (kk <= kDecThreads).
+template <int kDecThreads, int kDecQ>
 __global__ __launch_bounds__(kDecThreads) void delayed_decide_kernel(DecideArgs A) {
   const int kk = A.kk;
   const int t = threadIdx.x;
@@ -304,8 +301,9 @@ __global__ __launch_bounds__(kDecThreads) void delayed_decide_kernel(DecideArgs 
     const double p0 = colb[0][par][j], p1 = colb[1][par][j];
     const double R = p0 * p1;
     const double absA = fabs(R);
-    const bool finite = isfinite(R);
+    const bool finite = !isnan(absA);
     const bool acc = __builtin_amdgcn_readfirstlane((finite && (uni[j] < absA)) ? 1 : 0) != 0;
+    const double ip0 = 1.0 / p0, ip1 = 1.0 / p1;
     if (t == 0) {
       const double margin = absA - uni[j];
       C.stats[kStProposed] += 1;
@@ -324,12 +322,12 @@ __global__ __launch_bounds__(kDecThreads) void delayed_decide_kernel(DecideArgs 
         const int ia = e / kk, ib = e % kk;
         if (acc) {
           // principal pivot transform on pivot j, both spins
-          const double ca0 = colb[0][par][ia], rb0 = rowb[0][par][ib];
-          const double ca1 = colb[1][par][ia], rb1 = rowb[1][par][ib];
-          if (ia == j && ib == j) { e0[q] = -1.0 / p0; e1[q] = -1.0 / p1; }
-          else if (ib == j) { e0[q] = ca0 / p0; e1[q] = ca1 / p1; }
-          else if (ia == j) { e0[q] = rb0 / p0; e1[q] = rb1 / p1; }
-          else { e0[q] -= ca0 * rb0 / p0; e1[q] -= ca1 * rb1 / p1; }
+          const double ca0 = colb[0][par][ia] * ip0, rb0 = rowb[0][par][ib];
+          const double ca1 = colb[1][par][ia] * ip1, rb1 = rowb[1][par][ib];
+          if (ia == j && ib == j) { e0[q] = -ip0; e1[q] = -ip1; }
+          else if (ib == j) { e0[q] = ca0; e1[q] = ca1; }
+          else if (ia == j) { e0[q] = rb0 * ip0; e1[q] = rb1 * ip1; }
+          else { e0[q] -= ca0 * rb0; e1[q] -= ca1 * rb1; }
         }
         if (j + 1 < kk) {
           if (ib == j + 1) { colb[0][nxt][ia] = e0[q]; colb[1][nxt][ia] = e1[q]; }
@@ -370,22 +368,90 @@ __global__ __launch_bounds__(kDecThreads) void delayed_decide_kernel(DecideArgs 
   }
 }
 
-__global__ __launch_bounds__(kDecThreads) void block_decide_kernel(DecideArgs A) {
+// In-place inverse of the n x n matrix A (LDS, row-major, stride ld, n <= 64)
+// by Gauss-Jordan elimination with partial pivoting; returns det(A).  Every
+// lane of the workgroup takes part and gets the same result.
+template <int NT>
+__device__ double lds_gj_inverse(double *A, int ld, int n, double *colk, double *rowk, int *ipiv,
+                                 int *s_piv) {
+  const int t = threadIdx.x;
+  double det = 1.0;
+  for (int k = 0; k < n; ++k) {
+    if (t < 64) {
+      double bv = (t >= k && t < n) ? fabs(A[t * ld + k]) : -1.0;
+      int bi = (t >= k && t < n) ? t : 0x7fffffff;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ov = __shfl_xor(bv, o, 64);
+        const int oi = __shfl_xor(bi, o, 64);
+        const bool take = (ov > bv) || (ov == bv && oi < bi);
+        bv = take ? ov : bv;
+        bi = take ? oi : bi;
+      }
+      if (t == 0) {
+        *s_piv = (bi < n) ? bi : k;
+        ipiv[k] = (bi < n) ? bi : k;
+      }
+    }
+    __syncthreads();
+    const int p = __builtin_amdgcn_readfirstlane(*s_piv);
+    if (p != k)
+      for (int j = t; j < n; j += NT) {
+        const double x = A[k * ld + j];
+        A[k * ld + j] = A[p * ld + j];
+        A[p * ld + j] = x;
+      }
+    __syncthreads();
+    const double piv = A[k * ld + k];
+    det *= (p != k) ? -piv : piv;
+    const double ip = 1.0 / piv;
+    for (int i = t; i < n; i += NT) {
+      colk[i] = A[i * ld + k];
+      rowk[i] = A[k * ld + i] * ip;
+    }
+    __syncthreads();
+    for (int e = t; e < n * n; e += NT) {
+      const int i = e / n, j = e % n;
+      double v;
+      if (i == k) v = (j == k) ? ip : rowk[j];
+      else v = (j == k) ? -colk[i] * ip : A[i * ld + j] - colk[i] * rowk[j];
+      A[i * ld + j] = v;
+    }
+    __syncthreads();
+  }
+  for (int k = n - 1; k >= 0; --k) {
+    const int p = __builtin_amdgcn_readfirstlane(ipiv[k]);
+    if (p != k)
+      for (int i = t; i < n; i += NT) {
+        const double x = A[i * ld + k];
+        A[i * ld + k] = A[i * ld + p];
+        A[i * ld + p] = x;
+      }
+    __syncthreads();
+  }
+  return det;
+}
+
+// Block force-bias decision for kk <= 64 sites (one workgroup of NT lanes):
+// force bias from B = 1 + diag(Delta_b) W0 (Eq. (35)), heat-bath proposal,
+// det[1 + W0_FF diag(Delta'_F)] per spin and the Metropolis test with the
+// prior ratio (Sec. III B).  Both small inversions use partial pivoting.
+template <int NT>
+__global__ __launch_bounds__(NT) void block_decide_kernel(DecideArgs A) {
   const int kk = A.kk;
   const int t = threadIdx.x;
   const SweepCtx &C = A.c;
   const int kmax = A.g.kmax;
-  __shared__ double colb[2][2][64], rowb[2][2][64];
-  __shared__ double db[2][64];
-  __shared__ double prod[64][65];
-  __shared__ double nbar[2][64];
-  __shared__ double sval[64];
-  __shared__ int xold[64], xnew[64];
-  __shared__ int flist[64];
+  constexpr int LD = 65;
+  extern __shared__ double blds[];
+  double *M0 = blds;              // 64 x 65
+  double *M1 = blds + 64 * LD;    // 64 x 65
+  __shared__ double colk[64], rowk[64];
+  __shared__ int ipiv[64];
+  __shared__ int s_piv;
+  __shared__ double db[2][64], nbar[2][64], sval[64], dp[2][64], hbm[64];
+  __shared__ int xold[64], xnew[64], flist[64];
   __shared__ int s_nF;
-  __shared__ double dp[2][64];
-  __shared__ double pivprod[2];
-  __shared__ double hb_margin_s[64];
 
   if (t < kk) {
     const int8_t x = C.fields[(long)C.li * C.N + A.g0 + t];
@@ -394,66 +460,21 @@ __global__ __launch_bounds__(kDecThreads) void block_decide_kernel(DecideArgs A)
     db[1][t] = C.dremove[1][x > 0 ? 0 : 1];
   }
   __syncthreads();
-  // W0 (reduced, kept in global scratch for the flipped submatrix later);
-  // owned element e <-> (ia, ib) holds E_ab = delta_ab + Db_a W0_ab and the
-  // transposed W0_ba for the force-bias product.
-  double e0[4], e1[4], wt0[4], wt1[4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int e = t + kDecThreads * q;
-    e0[q] = e1[q] = wt0[q] = wt1[q] = 0.0;
-    if (e < kk * kk) {
-      const int ia = e / kk, ib = e % kk;
-      const double w0 = w0_elem(A, 0, ia, ib), w1 = w0_elem(A, 1, ia, ib);
-      A.g.W0[0][ia * kmax + ib] = w0;
-      A.g.W0[1][ia * kmax + ib] = w1;
-      wt0[q] = w0_elem(A, 0, ib, ia);
-      wt1[q] = w0_elem(A, 1, ib, ia);
-      e0[q] = (ia == ib ? 1.0 : 0.0) + db[0][ia] * w0;
-      e1[q] = (ia == ib ? 1.0 : 0.0) + db[1][ia] * w1;
-      if (ib == 0) { colb[0][0][ia] = e0[q]; colb[1][0][ia] = e1[q]; }
-      if (ia == 0) { rowb[0][0][ib] = e0[q]; rowb[1][0][ib] = e1[q]; }
-    }
-  }
-  __syncthreads();
-  // invert E by sweeping every pivot: afterwards e = -(E^{-1})_ab
-  for (int j = 0; j < kk; ++j) {
-    const int par = j & 1, nxt = par ^ 1;
-    const double p0 = colb[0][par][j], p1 = colb[1][par][j];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int e = t + kDecThreads * q;
-      if (e < kk * kk) {
-        const int ia = e / kk, ib = e % kk;
-        const double ca0 = colb[0][par][ia], rb0 = rowb[0][par][ib];
-        const double ca1 = colb[1][par][ia], rb1 = rowb[1][par][ib];
-        if (ia == j && ib == j) { e0[q] = -1.0 / p0; e1[q] = -1.0 / p1; }
-        else if (ib == j) { e0[q] = ca0 / p0; e1[q] = ca1 / p1; }
-        else if (ia == j) { e0[q] = rb0 / p0; e1[q] = rb1 / p1; }
-        else { e0[q] -= ca0 * rb0 / p0; e1[q] -= ca1 * rb1 / p1; }
-        if (j + 1 < kk) {
-          if (ib == j + 1) { colb[0][nxt][ia] = e0[q]; colb[1][nxt][ia] = e1[q]; }
-          if (ia == j + 1) { rowb[0][nxt][ib] = e0[q]; rowb[1][nxt][ib] = e1[q]; }
-        }
-      }
-    }
-    __syncthreads();
-  }
-  // nbar_b = (1 + Db_b) sum_a W0_ba (E^{-1})_ab, per spin (column sums of the products)
   for (int s = 0; s < 2; ++s) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int e = t + kDecThreads * q;
-      if (e < kk * kk) {
-        const int ia = e / kk, ib = e % kk;
-        prod[ia][ib] = s ? (-e1[q] * wt1[q]) : (-e0[q] * wt0[q]);
-      }
+    // M1 = W0 (kept for the force-bias product), M0 = 1 + diag(Delta_b) W0
+    for (int e = t; e < kk * kk; e += NT) {
+      const int ia = e / kk, ib = e % kk;
+      const double w = w0_elem(A, s, ia, ib);
+      A.g.W0[s][ia * kmax + ib] = w;
+      M1[ia * LD + ib] = w;
+      M0[ia * LD + ib] = (ia == ib ? 1.0 : 0.0) + db[s][ia] * w;
     }
     __syncthreads();
+    lds_gj_inverse<NT>(M0, LD, kk, colk, rowk, ipiv, &s_piv);
     if (t < kk) {
       double v = 0.0;
-      for (int ia = 0; ia < kk; ++ia) v += prod[ia][t];
-      nbar[s][t] = (1.0 + db[s][t]) * v;
+      for (int m = 0; m < kk; ++m) v += M1[t * LD + m] * M0[m * LD + t];
+      nbar[s][t] = (1.0 + db[s][t]) * v;     // [UU_R (U_L UU_R)^{-1} U_L]_ii
     }
     __syncthreads();
   }
@@ -467,7 +488,7 @@ __global__ __launch_bounds__(kDecThreads) void block_decide_kernel(DecideArgs A)
                                     kPurposeHB);
     xnew[t] = (u < pp) ? 1 : -1;
     const double margin = pp - u;
-    hb_margin_s[t] = margin;
+    hbm[t] = margin;
     if (C.hb_meta) {
       const long long idx = C.hb_base + site;
       if (idx < C.log_cap) {
@@ -481,8 +502,7 @@ __global__ __launch_bounds__(kDecThreads) void block_decide_kernel(DecideArgs A)
   __syncthreads();
   if (t == 0) {
     unsigned long long low = 0;
-    for (int j = 0; j < kk; ++j)
-      if (fabs(hb_margin_s[j]) < 1e-12) ++low;
+    for (int j = 0; j < kk; ++j) low += (fabs(hbm[j]) < 1e-12) ? 1ull : 0ull;
     C.stats[kStLowMargin] += low;
   }
   // flip set F in site order, one lane per site
@@ -509,51 +529,22 @@ __global__ __launch_bounds__(kDecThreads) void block_decide_kernel(DecideArgs A)
     }
     return;
   }
-  // E' = 1 + W0_FF diag(Delta'_F), Delta'_i = e^{-2 alpha f_s x_i} - 1; det by pivot sweep
+  // E'_s = 1 + W0_FF diag(Delta'_F), Delta'_i = e^{-2 alpha f_s x_i} - 1
   if (t < nF) {
     const int j = flist[t];
     dp[0][t] = C.dflip[0][xold[j] > 0 ? 0 : 1];
     dp[1][t] = C.dflip[1][xold[j] > 0 ? 0 : 1];
   }
-  if (t == 0) { pivprod[0] = 1.0; pivprod[1] = 1.0; }
   __syncthreads();
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int e = t + kDecThreads * q;
-    e0[q] = e1[q] = 0.0;
-    if (e < nF * nF) {
-      const int ia = e / nF, ib = e % nF;
-      const int fa = flist[ia], fb = flist[ib];
-      e0[q] = (ia == ib ? 1.0 : 0.0) + A.g.W0[0][fa * kmax + fb] * dp[0][ib];
-      e1[q] = (ia == ib ? 1.0 : 0.0) + A.g.W0[1][fa * kmax + fb] * dp[1][ib];
-      if (ib == 0) { colb[0][0][ia] = e0[q]; colb[1][0][ia] = e1[q]; }
-      if (ia == 0) { rowb[0][0][ib] = e0[q]; rowb[1][0][ib] = e1[q]; }
-    }
+  for (int e = t; e < nF * nF; e += NT) {
+    const int ia = e / nF, ib = e % nF;
+    const int fa = flist[ia], fb = flist[ib];
+    M0[ia * LD + ib] = (ia == ib ? 1.0 : 0.0) + A.g.W0[0][fa * kmax + fb] * dp[0][ib];
+    M1[ia * LD + ib] = (ia == ib ? 1.0 : 0.0) + A.g.W0[1][fa * kmax + fb] * dp[1][ib];
   }
   __syncthreads();
-  for (int j = 0; j < nF; ++j) {
-    const int par = j & 1, nxt = par ^ 1;
-    const double p0 = colb[0][par][j], p1 = colb[1][par][j];
-    if (t == 0) { pivprod[0] *= p0; pivprod[1] *= p1; }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int e = t + kDecThreads * q;
-      if (e < nF * nF) {
-        const int ia = e / nF, ib = e % nF;
-        const double ca0 = colb[0][par][ia], rb0 = rowb[0][par][ib];
-        const double ca1 = colb[1][par][ia], rb1 = rowb[1][par][ib];
-        if (ia == j && ib == j) { e0[q] = -1.0 / p0; e1[q] = -1.0 / p1; }
-        else if (ib == j) { e0[q] = ca0 / p0; e1[q] = ca1 / p1; }
-        else if (ia == j) { e0[q] = rb0 / p0; e1[q] = rb1 / p1; }
-        else { e0[q] -= ca0 * rb0 / p0; e1[q] -= ca1 * rb1 / p1; }
-        if (j + 1 < nF) {
-          if (ib == j + 1) { colb[0][nxt][ia] = e0[q]; colb[1][nxt][ia] = e1[q]; }
-          if (ia == j + 1) { rowb[0][nxt][ib] = e0[q]; rowb[1][nxt][ib] = e1[q]; }
-        }
-      }
-    }
-    __syncthreads();
-  }
+  const double r0 = lds_gj_inverse<NT>(M0, LD, nF, colk, rowk, ipiv, &s_piv);
+  const double r1 = lds_gj_inverse<NT>(M1, LD, nF, colk, rowk, ipiv, &s_piv);
   // prior ratio P(X'->X)/P(X->X') and the test, evaluated identically in every lane
   double lp = 0.0;
   for (int a = 0; a < nF; ++a) {
@@ -561,10 +552,10 @@ __global__ __launch_bounds__(kDecThreads) void block_decide_kernel(DecideArgs A)
     lp += sval[j] * (double)(xold[j] - xnew[j]);
   }
   const double prior = exp(lp);
-  const double Rb = pivprod[0] * pivprod[1];
+  const double Rb = r0 * r1;
   const double absAb = fabs(Rb * prior);
-  const bool finite_b = isfinite(absAb);
-  const bool acc_b = __builtin_amdgcn_readfirstlane((finite_b && (u_mh < absAb)) ? 1 : 0) != 0;
+  const bool nan_b = isnan(absAb);
+  const bool acc_b = __builtin_amdgcn_readfirstlane((!nan_b && (u_mh < absAb)) ? 1 : 0) != 0;
   if (t == 0) {
     const double margin = absAb - u_mh;
     C.stats[kStProposed] += 1;
@@ -572,26 +563,22 @@ __global__ __launch_bounds__(kDecThreads) void block_decide_kernel(DecideArgs A)
     if (acc_b) { C.stats[kStAccepted] += 1; C.stats[kStFlips] += nF; }
     if (fabs(margin) < 1e-12) C.stats[kStLowMargin] += 1;
     if (Rb < 0.0) C.stats[kStNegative] += 1;
-    if (!finite_b) C.stats[kStError] |= kErrNonFinite;
+    if (nan_b) C.stats[kStError] |= kErrNonFinite;
     record_decision(C, C.log_base + A.block_index, A.g0, acc_b, margin);
     *A.g.nA = acc_b ? nF : 0;
   }
-  if (acc_b && t < nF) {
-    const int j = flist[t];
-    A.g.Alist[t] = j;
-    A.g.Dsel[0][t] = dp[0][t];
-    A.g.Dsel[1][t] = dp[1][t];
-    C.fields[(long)C.li * C.N + A.g0 + j] = (int8_t)xnew[j];
-  }
   if (acc_b) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int e = t + kDecThreads * q;
-      if (e < nF * nF) {
-        const int ia = e / nF, ib = e % nF;
-        A.g.Minv[0][ia * kmax + ib] = -e0[q];
-        A.g.Minv[1][ia * kmax + ib] = -e1[q];
-      }
+    if (t < nF) {
+      const int j = flist[t];
+      A.g.Alist[t] = j;
+      A.g.Dsel[0][t] = dp[0][t];
+      A.g.Dsel[1][t] = dp[1][t];
+      C.fields[(long)C.li * C.N + A.g0 + j] = (int8_t)xnew[j];
+    }
+    for (int e = t; e < nF * nF; e += NT) {
+      const int ia = e / nF, ib = e % nF;
+      A.g.Minv[0][ia * kmax + ib] = M0[ia * LD + ib];
+      A.g.Minv[1][ia * kmax + ib] = M1[ia * LD + ib];
     }
   }
 }
@@ -639,6 +626,195 @@ __global__ __launch_bounds__(256) void group_q_kernel(QArgs a) {
       const int j = a.g.Alist[m];
       a.g.P2c[s][(long)m * Ns + r0 + cc] = a.g.P2[s][(long)j * Ns + r0 + cc];
       a.m.UR[s][(long)(a.g0 + j) * Ns + r0 + cc] *= (1.0 + a.g.Dsel[s][m]);
+    }
+  }
+}
+
+// ------------------------------------------------------------------------
+// fused group tile kernel: one 64x64 tile of T per workgroup, read once per
+// group.  (1) applies the pending flush of the previous group,
+//     T_tile -= (P1_A diag(Delta_A) M) P2_A,   M = (E_AA)^{-1}   (Eqs. (30)/(36)),
+// and scales that group's accepted rows of U_R; (2) forms this tile's
+// split-K contributions to the next group's panels P2 = U_g T and
+// P1 = T L_g from the updated tile.  All products run on MFMA from LDS.
+// ------------------------------------------------------------------------
+struct TileArgs {
+  SpinMats m;
+  GroupBufs g;
+  int flush;     // apply the pending flush (its size is read from g.nA)
+  int g0_prev;   // first site of the pending group
+  int g0, kk;    // next group (kk == 0: flush only)
+  int kpad;      // kmax rounded up to a multiple of 32
+};
+
+constexpr int kLdt = 65;   // padded LDS row stride
+
+// acc (this wave's 32x32 quadrant of a 64x64 result) += A (64 x K) B (K x 64)
+// with A, B in LDS; TB: B(k, j) = Bm[j * ldb + k].  Quadrants whose rows
+// are >= mrows or columns >= ncols are skipped.
+template <bool TB>
+__device__ __forceinline__ void lds_mma(dbl4 (&acc)[2][2], const double *A, int lda,
+                                        const double *B, int ldb, int K, int mrows, int ncols,
+                                        int wm, int wn, int lane) {
+  if (wm * 32 >= mrows || wn * 32 >= ncols) return;
+  const int i0 = wm * 32 + (lane & 15);
+  const int j0 = wn * 32 + (lane & 15);
+  for (int k0 = 0; k0 < K; k0 += 4) {
+    const int kk = k0 + (lane >> 4);
+    const bool kv = kk < K;
+    const double a0 = kv ? A[i0 * lda + kk] : 0.0;
+    const double a1 = kv ? A[(i0 + 16) * lda + kk] : 0.0;
+    double b0, b1;
+    if (!TB) {
+      b0 = kv ? B[kk * ldb + j0] : 0.0;
+      b1 = kv ? B[kk * ldb + j0 + 16] : 0.0;
+    } else {
+      b0 = kv ? B[j0 * ldb + kk] : 0.0;
+      b1 = kv ? B[(j0 + 16) * ldb + kk] : 0.0;
+    }
+    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+  }
+}
+
+// (row, col) of accumulator element [mi][ni][j] in the 64x64 tile
+__device__ __forceinline__ int acc_row(int wm, int mi, int lane, int j) {
+  return wm * 32 + mi * 16 + (lane >> 4) + 4 * j;
+}
+__device__ __forceinline__ int acc_col(int wn, int ni, int lane) {
+  return wn * 32 + ni * 16 + (lane & 15);
+}
+
+__global__ __launch_bounds__(256) void group_tile_kernel(TileArgs a) {
+  const int s = blockIdx.y;
+  const int Ns = a.m.Ns[s];
+  const int nt = (Ns + 63) / 64;
+  const int rb = blockIdx.x / nt, cb = blockIdx.x % nt;
+  if (rb >= nt) return;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int row0 = rb * 64, col0 = cb * 64;
+  const int kmax = a.g.kmax, kpad = a.kpad;
+  double *T = a.m.T[s];
+  extern __shared__ double lds[];
+  double *X = lds;                       // 64 x kLdt
+  double *Y = lds + 64 * kLdt;           // kpad x kLdt
+  double *Z = Y + kpad * kLdt;           // kpad x kLdt
+
+  dbl4 acc[2][2];
+#pragma unroll
+  for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int r = row0 + acc_row(wm, mi, lane, j), c = col0 + acc_col(wn, ni, lane);
+        acc[mi][ni][j] = (r < Ns && c < Ns) ? T[(long)r * Ns + c] : 0.0;
+      }
+
+  const int nA = a.flush ? *a.g.nA : 0;
+  if (nA > 0) {
+    const double *P1 = a.g.P1[s], *P2 = a.g.P2[s], *Mi = a.g.Minv[s], *D = a.g.Dsel[s];
+    const int *Al = a.g.Alist;
+    for (int e = t; e < 64 * kpad; e += 256) {
+      const int r = e / kpad, m = e % kpad;
+      X[r * kLdt + m] = (m < nA && row0 + r < Ns) ? -P1[(long)(row0 + r) * kmax + Al[m]] * D[m] : 0.0;
+    }
+    for (int e = t; e < kpad * 64; e += 256) {
+      const int m = e >> 6, c = e & 63;
+      Y[m * kLdt + c] = (m < nA && c < nA) ? Mi[m * kmax + c] : 0.0;
+      Z[m * kLdt + c] = (m < nA && col0 + c < Ns) ? P2[(long)Al[m] * Ns + col0 + c] : 0.0;
+    }
+    __syncthreads();
+    dbl4 q[2][2];
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+      for (int ni = 0; ni < 2; ++ni) q[mi][ni] = dbl4{0.0, 0.0, 0.0, 0.0};
+    lds_mma<false>(q, X, kLdt, Y, kLdt, nA, 64, nA, wm, wn, lane);   // Q = -P1_A D M
+    __syncthreads();
+    if (wn * 32 < nA) {
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            X[acc_row(wm, mi, lane, j) * kLdt + acc_col(wn, ni, lane)] = q[mi][ni][j];
+    }
+    __syncthreads();
+    lds_mma<false>(acc, X, kLdt, Z, kLdt, nA, 64, 64, wm, wn, lane);  // T += Q P2_A
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+      for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int r = row0 + acc_row(wm, mi, lane, j), c = col0 + acc_col(wn, ni, lane);
+          if (r < Ns && c < Ns) T[(long)r * Ns + c] = acc[mi][ni][j];
+        }
+    if (rb == 0) {
+      // accepted rows of U_R over this tile's columns
+      for (int e = t; e < nA * 64; e += 256) {
+        const int m = e >> 6, c = col0 + (e & 63);
+        if (c < Ns) a.m.UR[s][(long)(a.g0_prev + Al[m]) * Ns + c] *= (1.0 + D[m]);
+      }
+    }
+    __syncthreads();
+  }
+
+  const int kk = a.kk;
+  if (kk > 0) {
+    const double *UR = a.m.UR[s], *ULt = a.m.ULt[s];
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+      for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          X[acc_row(wm, mi, lane, j) * kLdt + acc_col(wn, ni, lane)] = acc[mi][ni][j];
+    for (int e = t; e < kpad * 64; e += 256) {
+      const int m = e >> 6, c = e & 63;
+      Y[m * kLdt + c] = (m < kk && row0 + c < Ns) ? UR[(long)(a.g0 + m) * Ns + row0 + c] : 0.0;
+      Z[m * kLdt + c] = (m < kk && col0 + c < Ns) ? ULt[(long)(a.g0 + m) * Ns + col0 + c] : 0.0;
+    }
+    __syncthreads();
+    dbl4 p[2][2];
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+      for (int ni = 0; ni < 2; ++ni) p[mi][ni] = dbl4{0.0, 0.0, 0.0, 0.0};
+    lds_mma<false>(p, Y, kLdt, X, kLdt, 64, kk, 64, wm, wn, lane);   // U_g[:, R] T_tile
+    if (wm * 32 < kk) {
+      double *out = a.g.P2part[s] + (long)rb * kmax * Ns;
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int m = acc_row(wm, mi, lane, j), c = col0 + acc_col(wn, ni, lane);
+            if (m < kk && c < Ns) out[(long)m * Ns + c] = p[mi][ni][j];
+          }
+    }
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+      for (int ni = 0; ni < 2; ++ni) p[mi][ni] = dbl4{0.0, 0.0, 0.0, 0.0};
+    lds_mma<true>(p, X, kLdt, Z, kLdt, 64, 64, kk, wm, wn, lane);    // T_tile L_g[C, :]
+    if (wn * 32 < kk) {
+      double *out = a.g.P1part[s] + (long)cb * Ns * kmax;
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int r = row0 + acc_row(wm, mi, lane, j), m = acc_col(wn, ni, lane);
+            if (r < Ns && m < kk) out[(long)r * kmax + m] = p[mi][ni][j];
+          }
     }
   }
 }
@@ -693,12 +869,11 @@ hipError_t delayed_decide(const GroupBufs &g, const SweepCtx &c, int g0, int kk,
   a.c = c;
   a.g0 = g0;
   a.kk = kk;
-  const int q = (kk * kk + kDecThreads - 1) / kDecThreads;
-  if (q <= 1) hipLaunchKernelGGL(delayed_decide_kernel<1>, dim3(1), dim3(kDecThreads), 0, st, a);
-  else if (q <= 2) hipLaunchKernelGGL(delayed_decide_kernel<2>, dim3(1), dim3(kDecThreads), 0, st, a);
-  else if (q <= 4) hipLaunchKernelGGL(delayed_decide_kernel<4>, dim3(1), dim3(kDecThreads), 0, st, a);
-  else if (q <= 8) hipLaunchKernelGGL(delayed_decide_kernel<8>, dim3(1), dim3(kDecThreads), 0, st, a);
-  else hipLaunchKernelGGL(delayed_decide_kernel<16>, dim3(1), dim3(kDecThreads), 0, st, a);
+  if (kk <= 8) hipLaunchKernelGGL((delayed_decide_kernel<64, 1>), dim3(1), dim3(64), 0, st, a);
+  else if (kk <= 16) hipLaunchKernelGGL((delayed_decide_kernel<64, 4>), dim3(1), dim3(64), 0, st, a);
+  else if (kk <= 32) hipLaunchKernelGGL((delayed_decide_kernel<64, 16>), dim3(1), dim3(64), 0, st, a);
+  else if (kk <= 64) hipLaunchKernelGGL((delayed_decide_kernel<256, 16>), dim3(1), dim3(256), 0, st, a);
+  else hipLaunchKernelGGL((delayed_decide_kernel<512, 32>), dim3(1), dim3(512), 0, st, a);
   return hipGetLastError();
 }
 
@@ -710,7 +885,59 @@ hipError_t block_decide(const GroupBufs &g, const SweepCtx &c, int g0, int kk,
   a.g0 = g0;
   a.kk = kk;
   a.block_index = block_index;
-  hipLaunchKernelGGL(block_decide_kernel, dim3(1), dim3(kDecThreads), 0, st, a);
+  const size_t lds = sizeof(double) * 2 * 64 * 65;
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void *)block_decide_kernel<256>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute((const void *)block_decide_kernel<64>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  if (kk <= 16) hipLaunchKernelGGL((block_decide_kernel<64>), dim3(1), dim3(64), lds, st, a);
+  else hipLaunchKernelGGL((block_decide_kernel<256>), dim3(1), dim3(256), lds, st, a);
+  return hipGetLastError();
+}
+
+hipError_t group_tile(const SpinMats &m, const GroupBufs &g, bool flush, int g0_prev, int g0,
+                      int kk, hipStream_t st) {
+  TileArgs a{};
+  a.m = m;
+  a.g = g;
+  a.flush = flush ? 1 : 0;
+  a.g0_prev = g0_prev;
+  a.g0 = g0;
+  a.kk = kk;
+  a.kpad = (g.kmax + 31) / 32 * 32;
+  const size_t lds = sizeof(double) * kLdt * (64 + 2 * (size_t)a.kpad);
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void *)group_tile_kernel,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)(sizeof(double) * kLdt * (64 + 2 * 64)));
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  const int nt = (max(m.Ns[0], m.Ns[1]) + 63) / 64;
+  hipLaunchKernelGGL(group_tile_kernel, dim3(nt * nt, 2), dim3(256), lds, st, a);
+  return hipGetLastError();
+}
+
+hipError_t group_reduce(const SpinMats &m, const GroupBufs &g, int g0, int kk, hipStream_t st) {
+  const int nt = (max(m.Ns[0], m.Ns[1]) + 63) / 64;
+  ReduceArgs ra{m, g, g0, kk};
+  const size_t lds = sizeof(double) * 2 * 65 * (size_t)kk;
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void *)group_reduce_kernel,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)(sizeof(double) * 2 * 65 * 128));
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(group_reduce_kernel, dim3(nt, 2), dim3(256), lds, st, ra);
   return hipGetLastError();
 }
 

@@ -26,7 +26,10 @@ def compare_decisions(meta, margin, ref_log, sweep, M):
         if abs(mg) < LOW or abs(e[5]) < LOW:
             return n, 1
         assert bool(acc) == e[4], f"decision {n} differs: gpu {acc} margin {mg:.3e}, oracle {e}"
-        assert abs(mg - e[5]) < 1e-9 * max(1.0, abs(e[5])), (n, mg, e[5])
+        if np.isinf(mg) or np.isinf(e[5]):
+            assert mg == e[5], (n, mg, e[5])
+        else:
+            assert abs(mg - e[5]) < 1e-9 * max(1.0, abs(e[5])), (n, mg, e[5])
         n += 1
     return n, 0
 

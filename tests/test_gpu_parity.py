@@ -91,3 +91,58 @@ def test_c1_parity(scheme, kw):
             return
         assert np.array_equal(ch.fields(), w.fields)
         assert green_rel_err(ch, w) < 1e-10
+
+
+@pytest.mark.parametrize("scheme,kw", [("delayed", {"k": 64}), ("delayed", {"k": 72}),
+                                       ("delayed", {"k": 128}), ("block", {"b": 40}),
+                                       ("block", {"b": 64})])
+def test_wide_groups_10x10(scheme, kw):
+    """10x10, N_sigma = 37: groups wider than 64 take the unfused panel/flush path;
+    k = 64 and b up to 64 take the fused tile path; ragged last groups."""
+    p = synth.make_problem(10, 37, 37, 4.0, n_slices=10, stab_every=5, perturb=1e-3,
+                           seed=synth.SEED_BASE + 21)
+    w = Walker(p, scheme, **kw)
+    ch = make_chain(p, scheme, **kw)
+    w.sweep()
+    ch.sweep(1)
+    meta, margin = ch.decisions()
+    n, low = compare_decisions(meta, margin, w.log, 0, p.n_slices)
+    if not low:
+        assert np.array_equal(ch.fields(), w.fields)
+        assert green_rel_err(ch, w) < 1e-10
+
+
+@pytest.mark.parametrize("scheme,kw", [("local", {}), ("delayed", {"k": 16}), ("block", {"b": 8})])
+def test_c2_parity_one_sweep(scheme, kw):
+    """16x16, N_sigma = 121, U/t = 4, dtau = 0.05, M = 400, k_tau = 10, bond perturbation."""
+    p = synth.workload("c2")
+    w = Walker(p, scheme, **kw)
+    ch = make_chain(p, scheme, **kw)
+    w.sweep()
+    ch.sweep(1)
+    meta, margin = ch.decisions()
+    n, low = compare_decisions(meta, margin, w.log, 0, p.n_slices)
+    print(f"c2 {scheme} {kw}: {n} decisions equal, low-margin {low}", flush=True)
+    if not low:
+        assert np.array_equal(ch.fields(), w.fields)
+        assert green_rel_err(ch, w) < 1e-10
+
+
+@pytest.mark.parametrize("scheme,kw,window", [("local", {}, 1), ("delayed", {"k": 32}, 10),
+                                              ("block", {"b": 16}, 2)])
+def test_c3_window_parity(scheme, kw, window):
+    """40x40, N_sigma = 800 (the benchmark's lattice, fillings and launch
+    configuration), projection shortened to M = 20 so the oracle's setup takes
+    seconds: decisions and G over a forward window (10 slices cross one
+    stabilisation)."""
+    p = synth.workload("c3", n_slices=20, stab_every=10)
+    w = Walker(p, scheme, **kw)
+    ch = make_chain(p, scheme, **kw)
+    w.forward_window(window)
+    ch.forward_window(window)
+    meta, margin = ch.decisions()
+    n, low = compare_decisions(meta, margin, w.log, 0, p.n_slices)
+    print(f"c3 {scheme} {kw} window {window}: {n} decisions equal, low-margin {low}", flush=True)
+    if not low:
+        assert np.array_equal(ch.fields(), w.fields)
+        assert green_rel_err(ch, w) < 1e-10
