@@ -136,6 +136,7 @@ void layout(pqmc_ctx &c, char *base, size_t *bytes) {
   c.lb.delta[1] = cv.take<double>(2);
   c.gb.Alist = cv.take<int>(kmax);
   c.gb.nA = cv.take<int>(1);
+  c.gb.ticket = cv.take<int>(2);
   c.gb.kmax = kmax;
   c.gb.Ns[0] = c.Ns[0];
   c.gb.Ns[1] = c.Ns[1];
@@ -660,6 +661,7 @@ pqmc_status pqmc_create(const pqmc_problem *prob, const pqmc_update_opts *opts, 
   if (!rc) rc = expm_taylor(*c, +sc, sq, c->Kinv);
   if (!rc) {
     hipError_t e = hipMemsetAsync(c->stats, 0, 16 * sizeof(unsigned long long), c->st);
+    if (e == hipSuccess) e = hipMemsetAsync(c->gb.ticket, 0, 2 * sizeof(int), c->st);
     if (e != hipSuccess) rc = fail_device(e, "memset", __FILE__, __LINE__);
   }
   if (!rc) {

@@ -83,7 +83,8 @@ struct GroupBufs {
   double *P2part[2], *P1part[2];   // split-K partials
   double *P2[2], *P1[2];           // kmax x Ns, Ns x kmax
   double *W0part[2];               // nstrip x kmax x kmax
-  double *W0[2];                   // kmax x kmax (block FB scratch)
+  double *W0[2];                   // kmax x kmax: W0 = U_g T L_g
+  int *ticket;                     // per spin: strips of W0 summed so far (reduce kernel)
   double *Minv[2];                 // kmax x kmax
   double *Q[2];                    // Ns x kmax
   double *P2c[2];                  // kmax x Ns
@@ -101,7 +102,7 @@ hipError_t block_decide(const GroupBufs &g, const SweepCtx &c, int g0, int kk,
 hipError_t group_flush(const SpinMats &m, const GroupBufs &g, int g0, int kk, hipStream_t st);
 // Fused path (kmax <= 64): one tile kernel per group applies the previous
 // group's flush and forms this group's split-K panel partials; group_reduce
-// then sums them (and the W0 strip partials).
+// sums them into P1, P2 and W0.
 hipError_t group_tile(const SpinMats &m, const GroupBufs &g, bool flush, int g0_prev, int g0,
                       int kk, hipStream_t st);
 hipError_t group_reduce(const SpinMats &m, const GroupBufs &g, int g0, int kk, hipStream_t st);

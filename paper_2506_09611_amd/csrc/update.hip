@@ -198,7 +198,9 @@ struct ReduceArgs {
   int g0, kk;
 };
 
-__global__ __launch_bounds__(256) void group_reduce_kernel(ReduceArgs a) {
+constexpr int kRedThreads = 1024;
+
+__global__ __launch_bounds__(kRedThreads) void group_reduce_kernel(ReduceArgs a) {
   const int s = blockIdx.y;
   const int Ns = a.m.Ns[s];
   const int nt = (Ns + 63) / 64;
@@ -212,7 +214,7 @@ __global__ __launch_bounds__(256) void group_reduce_kernel(ReduceArgs a) {
   double (*p2s)[65] = reinterpret_cast<double (*)[65]>(dyn_lds);
   double (*lgs)[65] = reinterpret_cast<double (*)[65]>(dyn_lds + (size_t)kk * 65);
   // P2[:, strip] and the group's rows of U_L^T over the strip
-  for (int e = t; e < kk * 64; e += 256) {
+  for (int e = t; e < kk * 64; e += kRedThreads) {
     const int mrow = e >> 6, cc = e & 63;
     double v = 0.0, l = 0.0;
     if (cc < w) {
@@ -225,7 +227,7 @@ __global__ __launch_bounds__(256) void group_reduce_kernel(ReduceArgs a) {
     lgs[mrow][cc] = l;
   }
   // P1[strip rows, :]
-  for (int e = t; e < 64 * kk; e += 256) {
+  for (int e = t; e < 64 * kk; e += kRedThreads) {
     const int rr = e / kk, mcol = e % kk;
     if (rr < w) {
       const long off = (long)(c0 + rr) * kmax + mcol;
@@ -234,11 +236,28 @@ __global__ __launch_bounds__(256) void group_reduce_kernel(ReduceArgs a) {
   }
   __syncthreads();
   // W0 partial over this strip: sum_c P2[m1][c] L_g[m2][c]
-  for (int e = t; e < kk * kk; e += 256) {
+  for (int e = t; e < kk * kk; e += kRedThreads) {
     const int m1 = e / kk, m2 = e % kk;
     double v = 0.0;
+#pragma unroll 8
     for (int cc = 0; cc < 64; ++cc) v += p2s[m1][cc] * lgs[m2][cc];
     a.g.W0part[s][(long)strip * kmax * kmax + m1 * kmax + m2] = v;
+  }
+  // the last strip to finish sums the partials in strip order into W0
+  // (deterministic; the ticket counter is reset for the next launch)
+  __shared__ int s_last;
+  __threadfence();
+  __syncthreads();
+  if (t == 0) s_last = (atomicAdd(&a.g.ticket[s], 1) == nt - 1) ? 1 : 0;
+  __syncthreads();
+  if (s_last) {
+    __threadfence();
+    for (int e = t; e < kk * kk; e += kRedThreads) {
+      const int m1 = e / kk, m2 = e % kk;
+      a.g.W0[s][m1 * kmax + m2] =
+          sum_strided(a.g.W0part[s] + m1 * kmax + m2, (long)kmax * kmax, nt);
+    }
+    if (t == 0) a.g.ticket[s] = 0;
   }
 }
 
@@ -253,11 +272,9 @@ struct DecideArgs {
   long long block_index;
 };
 
-// sum of the W0 strip partials for element (a, b)
+// W0 = U_g T L_g for element (a, b), as summed by the reduce kernel
 __device__ __forceinline__ double w0_elem(const DecideArgs &A, int s, int a, int b) {
-  const int nt = (A.g.Ns[s] + 63) / 64;
-  const int kmax = A.g.kmax;
-  return sum_strided(A.g.W0part[s] + a * kmax + b, (long)kmax * kmax, nt);
+  return A.g.W0[s][a * A.g.kmax + b];
 }
 
 // kDecThreads lanes, kDecQ = ceil(kk * kk / kDecThreads) elements of each
@@ -281,14 +298,17 @@ __global__ __launch_bounds__(kDecThreads) void delayed_decide_kernel(DecideArgs 
     uni[t] = philox_uniform(C.key0, C.key1, C.sweep, C.slice_code, (uint64_t)site, kPurposeMH);
   }
   __syncthreads();
-  // owned elements of E_s = 1 + W0_s diag(Delta_s)
+  // owned elements of E_s = 1 + W0_s diag(Delta_s); (row, column) per element
   double e0[kDecQ], e1[kDecQ];
+  int ra[kDecQ], cb_[kDecQ];
 #pragma unroll
   for (int q = 0; q < kDecQ; ++q) {
     const int e = t + kDecThreads * q;
     e0[q] = e1[q] = 0.0;
+    ra[q] = (e < kk * kk) ? e / kk : 1 << 20;
+    cb_[q] = (e < kk * kk) ? e % kk : 1 << 20;
     if (e < kk * kk) {
-      const int ia = e / kk, ib = e % kk;
+      const int ia = ra[q], ib = cb_[q];
       e0[q] = (ia == ib ? 1.0 : 0.0) + w0_elem(A, 0, ia, ib) * dl[0][ib];
       e1[q] = (ia == ib ? 1.0 : 0.0) + w0_elem(A, 1, ia, ib) * dl[1][ib];
       if (ib == 0) { colb[0][0][ia] = e0[q]; colb[1][0][ia] = e1[q]; }
@@ -296,38 +316,45 @@ __global__ __launch_bounds__(kDecThreads) void delayed_decide_kernel(DecideArgs 
     }
   }
   __syncthreads();
+  // lane 0 keeps the statistics in registers and writes them once
+  unsigned long long n_acc = 0, n_low = 0, n_neg = 0;
+  bool any_nan = false;
   for (int j = 0; j < kk; ++j) {
     const int par = j & 1, nxt = par ^ 1;
     const double p0 = colb[0][par][j], p1 = colb[1][par][j];
     const double R = p0 * p1;
     const double absA = fabs(R);
     const bool finite = !isnan(absA);
+    // every lane computes the same value; make it an explicit scalar
     const bool acc = __builtin_amdgcn_readfirstlane((finite && (uni[j] < absA)) ? 1 : 0) != 0;
-    const double ip0 = 1.0 / p0, ip1 = 1.0 / p1;
     if (t == 0) {
       const double margin = absA - uni[j];
-      C.stats[kStProposed] += 1;
-      C.stats[kStFieldUpdates] += 1;
-      if (acc) { C.stats[kStAccepted] += 1; C.stats[kStFlips] += 1; }
-      if (fabs(margin) < 1e-12) C.stats[kStLowMargin] += 1;
-      if (R < 0.0) C.stats[kStNegative] += 1;
-      if (!finite) C.stats[kStError] |= kErrNonFinite;
+      n_acc += acc ? 1 : 0;
+      n_low += (fabs(margin) < 1e-12) ? 1 : 0;
+      n_neg += (R < 0.0) ? 1 : 0;
+      any_nan = any_nan || !finite;
       record_decision(C, C.log_base + A.g0 + j, A.g0 + j, acc, margin);
       acc_s[j] = acc ? 1 : 0;
     }
+    const double ip0 = 1.0 / p0, ip1 = 1.0 / p1;
 #pragma unroll
     for (int q = 0; q < kDecQ; ++q) {
-      const int e = t + kDecThreads * q;
-      if (e < kk * kk) {
-        const int ia = e / kk, ib = e % kk;
+      const int ia = ra[q], ib = cb_[q];
+      if (ia < kk) {
         if (acc) {
-          // principal pivot transform on pivot j, both spins
+          // principal pivot transform on pivot j, both spins (branch-free)
+          const bool rj = ia == j, cj = ib == j;
           const double ca0 = colb[0][par][ia] * ip0, rb0 = rowb[0][par][ib];
           const double ca1 = colb[1][par][ia] * ip1, rb1 = rowb[1][par][ib];
-          if (ia == j && ib == j) { e0[q] = -ip0; e1[q] = -ip1; }
-          else if (ib == j) { e0[q] = ca0; e1[q] = ca1; }
-          else if (ia == j) { e0[q] = rb0 * ip0; e1[q] = rb1 * ip1; }
-          else { e0[q] -= ca0 * rb0; e1[q] -= ca1 * rb1; }
+          double v0 = e0[q] - ca0 * rb0, v1 = e1[q] - ca1 * rb1;
+          v0 = rj ? rb0 * ip0 : v0;
+          v1 = rj ? rb1 * ip1 : v1;
+          v0 = cj ? ca0 : v0;
+          v1 = cj ? ca1 : v1;
+          v0 = (rj && cj) ? -ip0 : v0;
+          v1 = (rj && cj) ? -ip1 : v1;
+          e0[q] = v0;
+          e1[q] = v1;
         }
         if (j + 1 < kk) {
           if (ib == j + 1) { colb[0][nxt][ia] = e0[q]; colb[1][nxt][ia] = e1[q]; }
@@ -336,6 +363,15 @@ __global__ __launch_bounds__(kDecThreads) void delayed_decide_kernel(DecideArgs 
       }
     }
     __syncthreads();
+  }
+  if (t == 0) {
+    C.stats[kStProposed] += kk;
+    C.stats[kStFieldUpdates] += kk;
+    C.stats[kStAccepted] += n_acc;
+    C.stats[kStFlips] += n_acc;
+    C.stats[kStLowMargin] += n_low;
+    C.stats[kStNegative] += n_neg;
+    if (any_nan) C.stats[kStError] |= kErrNonFinite;
   }
   // compaction of the accepted set, one lane per site (no single-lane loops)
   if (t < kk) {
@@ -356,9 +392,8 @@ __global__ __launch_bounds__(kDecThreads) void delayed_decide_kernel(DecideArgs 
   const int kmax = A.g.kmax;
 #pragma unroll
   for (int q = 0; q < kDecQ; ++q) {
-    const int e = t + kDecThreads * q;
-    if (e < kk * kk) {
-      const int ia = e / kk, ib = e % kk;
+    const int ia = ra[q], ib = cb_[q];
+    if (ia < kk) {
       const int pa = pos[ia], pb = pos[ib];
       if (pa >= 0 && pb >= 0) {
         A.g.Minv[0][pa * kmax + pb] = -e0[q];
@@ -465,7 +500,6 @@ __global__ __launch_bounds__(NT) void block_decide_kernel(DecideArgs A) {
     for (int e = t; e < kk * kk; e += NT) {
       const int ia = e / kk, ib = e % kk;
       const double w = w0_elem(A, s, ia, ib);
-      A.g.W0[s][ia * kmax + ib] = w;
       M1[ia * LD + ib] = w;
       M0[ia * LD + ib] = (ia == ib ? 1.0 : 0.0) + db[s][ia] * w;
     }
@@ -640,7 +674,7 @@ __global__ __launch_bounds__(256) void group_q_kernel(QArgs a) {
 // ------------------------------------------------------------------------
 struct TileArgs {
   SpinMats m;
-  GroupBufs g;
+  GroupBufs g;   // g.P1 / g.P2: panels of the pending (flushed) group
   int flush;     // apply the pending flush (its size is read from g.nA)
   int g0_prev;   // first site of the pending group
   int g0, kk;    // next group (kk == 0: flush only)
@@ -687,6 +721,15 @@ __device__ __forceinline__ int acc_col(int wn, int ni, int lane) {
   return wn * 32 + ni * 16 + (lane & 15);
 }
 
+__device__ __forceinline__ void zero_acc(dbl4 (&a)[2][2]) {
+#pragma unroll
+  for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < 2; ++ni) a[mi][ni] = dbl4{0.0, 0.0, 0.0, 0.0};
+}
+
+constexpr int kPanMax = 16;   // panel elements per lane staged in registers (kpad <= 64)
+
 __global__ __launch_bounds__(256) void group_tile_kernel(TileArgs a) {
   const int s = blockIdx.y;
   const int Ns = a.m.Ns[s];
@@ -697,12 +740,16 @@ __global__ __launch_bounds__(256) void group_tile_kernel(TileArgs a) {
   const int wm = wave >> 1, wn = wave & 1;
   const int row0 = rb * 64, col0 = cb * 64;
   const int kmax = a.g.kmax, kpad = a.kpad;
+  const int kk = a.kk;
   double *T = a.m.T[s];
   extern __shared__ double lds[];
   double *X = lds;                       // 64 x kLdt
   double *Y = lds + 64 * kLdt;           // kpad x kLdt
   double *Z = Y + kpad * kLdt;           // kpad x kLdt
+  __shared__ int al_s[64];
+  __shared__ double dsel_s[64];
 
+  // issue every independent load first: T tile, next group's panel rows, flush size
   dbl4 acc[2][2];
 #pragma unroll
   for (int mi = 0; mi < 2; ++mi)
@@ -713,26 +760,39 @@ __global__ __launch_bounds__(256) void group_tile_kernel(TileArgs a) {
         const int r = row0 + acc_row(wm, mi, lane, j), c = col0 + acc_col(wn, ni, lane);
         acc[mi][ni][j] = (r < Ns && c < Ns) ? T[(long)r * Ns + c] : 0.0;
       }
+  double ug[kPanMax], lg[kPanMax];
+  if (kk > 0) {
+    const double *UR = a.m.UR[s], *ULt = a.m.ULt[s];
+#pragma unroll
+    for (int i = 0; i < kPanMax; ++i) {
+      const int e = t + 256 * i;
+      const int m = e >> 6, c = e & 63;
+      const bool ok = e < kpad * 64 && m < kk;
+      ug[i] = (ok && row0 + c < Ns) ? UR[(long)(a.g0 + m) * Ns + row0 + c] : 0.0;
+      lg[i] = (ok && col0 + c < Ns) ? ULt[(long)(a.g0 + m) * Ns + col0 + c] : 0.0;
+    }
+  }
+  const int nA = a.flush ? __builtin_amdgcn_readfirstlane(*a.g.nA) : 0;
 
-  const int nA = a.flush ? *a.g.nA : 0;
   if (nA > 0) {
-    const double *P1 = a.g.P1[s], *P2 = a.g.P2[s], *Mi = a.g.Minv[s], *D = a.g.Dsel[s];
-    const int *Al = a.g.Alist;
+    const double *P1 = a.g.P1[s], *P2 = a.g.P2[s], *Mi = a.g.Minv[s];
+    if (t < nA) {
+      al_s[t] = a.g.Alist[t];
+      dsel_s[t] = a.g.Dsel[s][t];
+    }
+    __syncthreads();
     for (int e = t; e < 64 * kpad; e += 256) {
       const int r = e / kpad, m = e % kpad;
-      X[r * kLdt + m] = (m < nA && row0 + r < Ns) ? -P1[(long)(row0 + r) * kmax + Al[m]] * D[m] : 0.0;
+      X[r * kLdt + m] = (m < nA && row0 + r < Ns) ? -P1[(long)(row0 + r) * kmax + al_s[m]] * dsel_s[m] : 0.0;
     }
     for (int e = t; e < kpad * 64; e += 256) {
       const int m = e >> 6, c = e & 63;
       Y[m * kLdt + c] = (m < nA && c < nA) ? Mi[m * kmax + c] : 0.0;
-      Z[m * kLdt + c] = (m < nA && col0 + c < Ns) ? P2[(long)Al[m] * Ns + col0 + c] : 0.0;
+      Z[m * kLdt + c] = (m < nA && col0 + c < Ns) ? P2[(long)al_s[m] * Ns + col0 + c] : 0.0;
     }
     __syncthreads();
     dbl4 q[2][2];
-#pragma unroll
-    for (int mi = 0; mi < 2; ++mi)
-#pragma unroll
-      for (int ni = 0; ni < 2; ++ni) q[mi][ni] = dbl4{0.0, 0.0, 0.0, 0.0};
+    zero_acc(q);
     lds_mma<false>(q, X, kLdt, Y, kLdt, nA, 64, nA, wm, wn, lane);   // Q = -P1_A D M
     __syncthreads();
     if (wn * 32 < nA) {
@@ -759,64 +819,59 @@ __global__ __launch_bounds__(256) void group_tile_kernel(TileArgs a) {
       // accepted rows of U_R over this tile's columns
       for (int e = t; e < nA * 64; e += 256) {
         const int m = e >> 6, c = col0 + (e & 63);
-        if (c < Ns) a.m.UR[s][(long)(a.g0_prev + Al[m]) * Ns + c] *= (1.0 + D[m]);
+        if (c < Ns) a.m.UR[s][(long)(a.g0_prev + al_s[m]) * Ns + c] *= (1.0 + dsel_s[m]);
       }
     }
     __syncthreads();
   }
 
-  const int kk = a.kk;
-  if (kk > 0) {
-    const double *UR = a.m.UR[s], *ULt = a.m.ULt[s];
+  if (kk <= 0) return;
+#pragma unroll
+  for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        X[acc_row(wm, mi, lane, j) * kLdt + acc_col(wn, ni, lane)] = acc[mi][ni][j];
+#pragma unroll
+  for (int i = 0; i < kPanMax; ++i) {
+    const int e = t + 256 * i;
+    if (e < kpad * 64) {
+      Y[(e >> 6) * kLdt + (e & 63)] = ug[i];
+      Z[(e >> 6) * kLdt + (e & 63)] = lg[i];
+    }
+  }
+  __syncthreads();
+  dbl4 p[2][2];
+  zero_acc(p);
+  lds_mma<false>(p, Y, kLdt, X, kLdt, 64, kk, 64, wm, wn, lane);   // U_g[:, R] T_tile
+  if (wm * 32 < kk) {
+    double *out = a.g.P2part[s] + (long)rb * kmax * Ns;
 #pragma unroll
     for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
       for (int ni = 0; ni < 2; ++ni)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-          X[acc_row(wm, mi, lane, j) * kLdt + acc_col(wn, ni, lane)] = acc[mi][ni][j];
-    for (int e = t; e < kpad * 64; e += 256) {
-      const int m = e >> 6, c = e & 63;
-      Y[m * kLdt + c] = (m < kk && row0 + c < Ns) ? UR[(long)(a.g0 + m) * Ns + row0 + c] : 0.0;
-      Z[m * kLdt + c] = (m < kk && col0 + c < Ns) ? ULt[(long)(a.g0 + m) * Ns + col0 + c] : 0.0;
-    }
-    __syncthreads();
-    dbl4 p[2][2];
-#pragma unroll
-    for (int mi = 0; mi < 2; ++mi)
-#pragma unroll
-      for (int ni = 0; ni < 2; ++ni) p[mi][ni] = dbl4{0.0, 0.0, 0.0, 0.0};
-    lds_mma<false>(p, Y, kLdt, X, kLdt, 64, kk, 64, wm, wn, lane);   // U_g[:, R] T_tile
-    if (wm * 32 < kk) {
-      double *out = a.g.P2part[s] + (long)rb * kmax * Ns;
-#pragma unroll
-      for (int mi = 0; mi < 2; ++mi)
-#pragma unroll
-        for (int ni = 0; ni < 2; ++ni)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            const int m = acc_row(wm, mi, lane, j), c = col0 + acc_col(wn, ni, lane);
-            if (m < kk && c < Ns) out[(long)m * Ns + c] = p[mi][ni][j];
-          }
-    }
-#pragma unroll
-    for (int mi = 0; mi < 2; ++mi)
-#pragma unroll
-      for (int ni = 0; ni < 2; ++ni) p[mi][ni] = dbl4{0.0, 0.0, 0.0, 0.0};
-    lds_mma<true>(p, X, kLdt, Z, kLdt, 64, 64, kk, wm, wn, lane);    // T_tile L_g[C, :]
-    if (wn * 32 < kk) {
-      double *out = a.g.P1part[s] + (long)cb * Ns * kmax;
-#pragma unroll
-      for (int mi = 0; mi < 2; ++mi)
-#pragma unroll
-        for (int ni = 0; ni < 2; ++ni)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            const int r = row0 + acc_row(wm, mi, lane, j), m = acc_col(wn, ni, lane);
-            if (r < Ns && m < kk) out[(long)r * kmax + m] = p[mi][ni][j];
-          }
-    }
+        for (int j = 0; j < 4; ++j) {
+          const int m = acc_row(wm, mi, lane, j), c = col0 + acc_col(wn, ni, lane);
+          if (m < kk && c < Ns) out[(long)m * Ns + c] = p[mi][ni][j];
+        }
   }
+  zero_acc(p);
+  lds_mma<true>(p, X, kLdt, Z, kLdt, 64, 64, kk, wm, wn, lane);    // T_tile L_g[C, :]
+  if (wn * 32 < kk) {
+    double *out = a.g.P1part[s] + (long)cb * Ns * kmax;
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+      for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int r = row0 + acc_row(wm, mi, lane, j), m = acc_col(wn, ni, lane);
+          if (r < Ns && m < kk) out[(long)r * kmax + m] = p[mi][ni][j];
+        }
+  }
+
 }
 
 }  // namespace
@@ -858,7 +913,7 @@ hipError_t group_panels(const SpinMats &m, const GroupBufs &g, int g0, int kk, h
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL(group_reduce_kernel, dim3(nt, 2), dim3(256), lds, st, ra);
+  hipLaunchKernelGGL(group_reduce_kernel, dim3(nt, 2), dim3(kRedThreads), lds, st, ra);
   return hipGetLastError();
 }
 
@@ -871,9 +926,9 @@ hipError_t delayed_decide(const GroupBufs &g, const SweepCtx &c, int g0, int kk,
   a.kk = kk;
   if (kk <= 8) hipLaunchKernelGGL((delayed_decide_kernel<64, 1>), dim3(1), dim3(64), 0, st, a);
   else if (kk <= 16) hipLaunchKernelGGL((delayed_decide_kernel<64, 4>), dim3(1), dim3(64), 0, st, a);
-  else if (kk <= 32) hipLaunchKernelGGL((delayed_decide_kernel<64, 16>), dim3(1), dim3(64), 0, st, a);
-  else if (kk <= 64) hipLaunchKernelGGL((delayed_decide_kernel<256, 16>), dim3(1), dim3(256), 0, st, a);
-  else hipLaunchKernelGGL((delayed_decide_kernel<512, 32>), dim3(1), dim3(512), 0, st, a);
+  else if (kk <= 32) hipLaunchKernelGGL((delayed_decide_kernel<256, 4>), dim3(1), dim3(256), 0, st, a);
+  else if (kk <= 64) hipLaunchKernelGGL((delayed_decide_kernel<512, 8>), dim3(1), dim3(512), 0, st, a);
+  else hipLaunchKernelGGL((delayed_decide_kernel<1024, 16>), dim3(1), dim3(1024), 0, st, a);
   return hipGetLastError();
 }
 
@@ -911,6 +966,7 @@ hipError_t group_tile(const SpinMats &m, const GroupBufs &g, bool flush, int g0_
   a.g0 = g0;
   a.kk = kk;
   a.kpad = (g.kmax + 31) / 32 * 32;
+  if (a.kpad > 64) return hipErrorInvalidValue;
   const size_t lds = sizeof(double) * kLdt * (64 + 2 * (size_t)a.kpad);
   static bool attr_set = false;
   if (!attr_set) {
@@ -937,7 +993,7 @@ hipError_t group_reduce(const SpinMats &m, const GroupBufs &g, int g0, int kk, h
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL(group_reduce_kernel, dim3(nt, 2), dim3(256), lds, st, ra);
+  hipLaunchKernelGGL(group_reduce_kernel, dim3(nt, 2), dim3(kRedThreads), lds, st, ra);
   return hipGetLastError();
 }
 
