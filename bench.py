@@ -38,6 +38,44 @@ def make_chain(p, scheme, k=1, b=1, timing=True):
                  p.seed, p.walker_id, scheme=sc, k=k, b=b, timing=timing)
 
 
+def kernel_work(p, cls, scheme, k, b, acc):
+    """Algorithmic work of one launch of a kernel class: (flops, bytes, bound).
+    Two spin sectors; Ns = N_sigma; T is Ns x Ns; U_R, U_L^T are N x Ns."""
+    N, Ns = p.n_sites, p.n_up
+    kk = k if scheme == "delayed" else b
+    n_a = acc * kk
+    if cls == "propagate":     # U_R and U_L^T: 2 spins x 2 products of N x N by N x Ns
+        return 8.0 * N * N * Ns, 2 * 2 * (N * N + 2 * N * Ns) * 8.0, "mfma"
+    if cls == "tile":          # flush T -= Q P2_A (rank n_A) + panels U_g T, T L_g
+        return 2 * (2.0 * Ns * Ns * n_a + 4.0 * Ns * Ns * kk), 2 * 2 * Ns * Ns * 8.0, "mfma"
+    if cls == "reduce":        # read split-K partials of P1, P2 (ceil(Ns/64) each)
+        nt = -(-Ns // 64)
+        return 2 * 2.0 * nt * kk * Ns, 2 * (2 * nt * kk * Ns + 2 * kk * Ns) * 8.0, "hbm"
+    if cls == "decide":        # kk x kk pivot sweeps, two spins
+        return 2 * 2.0 * n_a * kk * kk, 2 * kk * kk * 8.0, "alu"
+    if cls == "local":         # read T (partials of y, Tv), rank-1 write when accepted
+        return 2 * (2.0 + 4.0 * acc) * Ns * Ns, 2 * (1.0 + acc) * Ns * Ns * 8.0, "hbm"
+    raise KeyError(cls)
+
+
+def roofline(p, scheme, k, b, acc, ktimes):
+    """Roofline of the kernel class with the largest device time."""
+    cls, (tot, cnt) = max(((c, v) for c, v in ktimes.items() if v[1] > 0),
+                          key=lambda cv: cv[1][0])
+    avg = tot / cnt
+    flops, nbytes, bound = kernel_work(p, cls, scheme, k, b, acc)
+    if bound == "hbm":
+        achieved, peak, unit = nbytes / avg / 1e9, MI355X_HBM_TBPS * 1e3, "GB/s"
+    else:
+        achieved, peak, unit = flops / avg / 1e12, MI355X_FP64_PEAK_TFLOPS, "TFLOP/s"
+    shares = {c: v[0] for c, v in ktimes.items() if v[1] > 0}
+    total = sum(shares.values())
+    return {"kernel": cls, "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
+            "frac": achieved / peak, "traffic": None, "avg_launch_us": avg * 1e6,
+            "launches": cnt, "flops_per_launch": flops, "bytes_per_launch": nbytes,
+            "device_time_share": {c: v / total for c, v in shares.items()}}
+
+
 def time_sweeps(ch, steps, warmup):
     import torch
     for _ in range(warmup):
@@ -51,17 +89,10 @@ def time_sweeps(ch, steps, warmup):
     return t1 - t0, agg
 
 
-def prop_flops(p):
-    """Algorithmic FLOPs of one propagation launch: 2 spins x (U_R and U_L)
-    x one N x N_sigma x N dense product."""
-    N = p.hopping.shape[0]
-    return 2.0 * (2 * N * p.n_up * N + 2 * N * p.n_dn * N)
-
-
 def cpu_baseline(p, scheme, k, b, budget_s=20.0):
     """The oracle on the host cores: a window of forward slice visits
     (propagation + update of each slice) on the same 40x40 lattice, with the
-    projection shortened to M = 10 slices so its setup stays small."""
+    projection shortened to M = 40 slices so its setup stays small."""
     import numpy as np
     import synth
     from oracle.pqmc import Walker
@@ -70,7 +101,7 @@ def cpu_baseline(p, scheme, k, b, budget_s=20.0):
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     except Exception:  # pragma: no cover
         threads = os.cpu_count()
-    q = synth.workload("c3", n_slices=10, stab_every=10)
+    q = synth.workload("c3", n_slices=40, stab_every=10)
     w = Walker(q, scheme, k=k, b=b)
     t0 = time.perf_counter()
     n = 0
@@ -84,7 +115,8 @@ def cpu_baseline(p, scheme, k, b, budget_s=20.0):
     return {"value": n * q.n_sites / dt, "unit": "field-updates/s", "cores": int(threads),
             "kind": "oracle",
             "sample": f"{scheme} k={k} b={b}: {n} forward slice visits (propagation + update) of "
-                      f"the 40x40 lattice, N_sigma=800, M shortened to 10, {dt:.1f} s"}
+                      f"the 40x40 lattice, N_sigma=800, projection shortened to M=40, "
+                      f"{dt:.1f} s of host time"}
 
 
 def main():
@@ -101,6 +133,8 @@ def main():
     ap.add_argument("--local-window", type=int, default=20,
                     help="slice visits timed for the local comparison (0 = full sweeps)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--ktime-window", type=int, default=10,
+                    help="forward slice visits instrumented per kernel after the timed sweeps")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs one Markov chain on one GPU; --gpus must be 1"}))
@@ -119,10 +153,15 @@ def main():
     dt, agg = time_sweeps(ch, args.steps, args.warmup)
     value = args.steps * per_sweep / dt
     upd = args.steps * per_sweep / agg["t_update_s"] if agg["t_update_s"] > 0 else None
-    n_prop = 2 * M * args.steps
-    prop_avg = agg["t_prop_s"] / n_prop
-    achieved = prop_flops(p) / prop_avg / 1e12
+    acc = agg["accepted"] / max(1, agg["proposed"])
+    # per-kernel device time, live on the library's stream: an instrumented
+    # forward window after the timed sweeps
+    ch.set_opts(ch.scheme, ch.k, ch.b, ktime=True)
+    ch.forward_window(args.ktime_window)
+    ktimes = ch.kernel_times()
+    roof = roofline(p, args.scheme, args.k, args.b, acc, ktimes)
     log(f"{args.scheme}: {dt / args.steps:.3f} s/sweep, {value:.4g} fu/s, update-only {upd:.4g}")
+    log("kernel times", {c: (round(v[0] * 1e3, 3), v[1]) for c, v in ktimes.items()})
     result = {
         "metric": METRIC,
         "value": value,
@@ -143,15 +182,13 @@ def main():
             "scheme": args.scheme, "delay_k": args.k, "block_b": args.b,
         },
         "update_only_field_updates_per_s": upd,
-        "acceptance": agg["accepted"] / max(1, agg["proposed"]),
+        "acceptance": acc,
         "low_margin": agg["low_margin"],
         "phase_s_per_sweep": {"update": agg["t_update_s"] / args.steps,
                               "propagation": agg["t_prop_s"] / args.steps,
                               "stabilization": agg["t_stab_s"] / args.steps},
-        "roofline": {"kernel": "B-matrix propagation GEMM (one batched launch per slice visit)",
-                     "bound": "mfma", "achieved": achieved, "peak": MI355X_FP64_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / MI355X_FP64_PEAK_TFLOPS,
-                     "traffic": None},
+        "roofline": roof,
+        "kernel_avg_us": {c: 1e6 * v[0] / v[1] for c, v in ktimes.items() if v[1] > 0},
     }
     ch.close()
     del ch

@@ -70,6 +70,17 @@ typedef enum { PQMC_LOCAL = 0, PQMC_DELAYED = 1, PQMC_BLOCK_FB = 2 } pqmc_scheme
 /* flags of pqmc_update_opts */
 #define PQMC_FLAG_LOG    1u  /* record every decision of the last pqmc_sweep call */
 #define PQMC_FLAG_TIMING 2u  /* time propagation / update / stabilisation phases  */
+#define PQMC_FLAG_KTIME  4u  /* time every launch of the kernel classes below      */
+
+/* kernel classes of pqmc_get_kernel_times() */
+enum {
+  PQMC_K_PROPAGATE = 0,  /* batched B-matrix propagation GEMM (one per slice visit)  */
+  PQMC_K_LOCAL = 1,      /* local-update site step                                  */
+  PQMC_K_TILE = 2,       /* group flush + next group's panel products (MFMA)        */
+  PQMC_K_REDUCE = 3,     /* panel partial sums and W0                                */
+  PQMC_K_DECIDE = 4,     /* delayed / block force-bias decision kernel              */
+  PQMC_K_COUNT = 5
+};
 
 typedef struct {
   int32_t n_sites;            /* N_s: number of lattice sites                          */
@@ -88,7 +99,7 @@ typedef struct {
 typedef struct {
   int32_t scheme;             /* pqmc_scheme                                           */
   int32_t delay_k;            /* n_d for PQMC_DELAYED, 1 <= k <= 128 (clipped to N_s)   */
-  int32_t block_b;            /* n_b for PQMC_BLOCK_FB, 1 <= b <= 128 (clipped to N_s)  */
+  int32_t block_b;            /* n_b for PQMC_BLOCK_FB, 1 <= b <= 64 (clipped to N_s)   */
   uint32_t flags;             /* PQMC_FLAG_*                                           */
 } pqmc_update_opts;
 
@@ -160,6 +171,12 @@ pqmc_status pqmc_get_decisions(pqmc_ctx *ctx, int32_t *meta, double *margin, siz
  * meta[3*n] = (dir*M + l-1, site, proposed x'), margin[n] = p(+1) - u. */
 pqmc_status pqmc_get_heat_bath(pqmc_ctx *ctx, int32_t *meta, double *margin, size_t cap,
                                size_t *n);
+
+/* With PQMC_FLAG_KTIME set for the last pqmc_sweep / pqmc_forward_window
+ * call: total device time (seconds, from HIP events bracketing each launch
+ * on the context's stream) and launch count per kernel class PQMC_K_*.
+ * totals and counts: host arrays of PQMC_K_COUNT entries. */
+pqmc_status pqmc_get_kernel_times(pqmc_ctx *ctx, double *totals, uint64_t *counts);
 
 /* Release the context (the workspace stays the caller's). */
 pqmc_status pqmc_destroy(pqmc_ctx *ctx);

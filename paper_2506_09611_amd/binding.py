@@ -18,8 +18,10 @@ _LIB = None
 EXPORTED_SYMBOLS = (
     "pqmc_workspace_bytes", "pqmc_create", "pqmc_set_opts", "pqmc_set_fields",
     "pqmc_get_fields", "pqmc_sweep", "pqmc_forward_window", "pqmc_get_green",
-    "pqmc_get_decisions", "pqmc_get_heat_bath", "pqmc_destroy", "pqmc_last_error",
+    "pqmc_get_decisions", "pqmc_get_heat_bath", "pqmc_get_kernel_times", "pqmc_destroy",
+    "pqmc_last_error",
 )
+KERNEL_CLASSES = ("propagate", "local", "tile", "reduce", "decide")
 
 
 class Scheme(enum.IntEnum):
@@ -30,6 +32,7 @@ class Scheme(enum.IntEnum):
 
 FLAG_LOG = 1
 FLAG_TIMING = 2
+FLAG_KTIME = 4
 
 
 class PQMCError(RuntimeError):
@@ -95,6 +98,8 @@ def load_library():
         "pqmc_get_heat_bath": [c_void_p, ctypes.POINTER(ctypes.c_int32),
                                ctypes.POINTER(ctypes.c_double), c_size_t,
                                ctypes.POINTER(c_size_t)],
+        "pqmc_get_kernel_times": [c_void_p, ctypes.POINTER(ctypes.c_double),
+                                  ctypes.POINTER(ctypes.c_uint64)],
         "pqmc_destroy": [c_void_p],
     }
     for name, args in sig.items():
@@ -164,8 +169,10 @@ class Chain:
         self.set_opts(scheme, k, b)
 
     # -- calls with the C ABI's names
-    def set_opts(self, scheme, k=1, b=1, log=None, timing=None):
+    def set_opts(self, scheme, k=1, b=1, log=None, timing=None, ktime=None):
         flags = self._flags
+        if ktime is not None:
+            flags = (flags & ~FLAG_KTIME) | (FLAG_KTIME if ktime else 0)
         if log is not None:
             flags = (flags & ~FLAG_LOG) | (FLAG_LOG if log else 0)
         if timing is not None:
@@ -216,6 +223,13 @@ class Chain:
 
     def heat_bath(self):
         return self._log(self._lib.pqmc_get_heat_bath)
+
+    def kernel_times(self):
+        """{class: (total_seconds, launches)} of the last call made with ktime on."""
+        tot = (ctypes.c_double * len(KERNEL_CLASSES))()
+        cnt = (ctypes.c_uint64 * len(KERNEL_CLASSES))()
+        _check(self._lib, self._lib.pqmc_get_kernel_times(self._ctx, tot, cnt))
+        return {k: (tot[i], int(cnt[i])) for i, k in enumerate(KERNEL_CLASSES)}
 
     def close(self):
         if getattr(self, "_ctx", None):

@@ -67,6 +67,12 @@ struct pqmc_ctx {
   uint64_t sweep_index = 0;
   long long log_count = 0, hb_count = 0, hb_total = 0;
   std::vector<hipEvent_t> evs;
+  // per-launch kernel timing (PQMC_FLAG_KTIME)
+  std::vector<hipEvent_t> kevs;
+  std::vector<int> kclass;
+  size_t kused = 0;
+  double kt_total[PQMC_K_COUNT] = {};
+  uint64_t kt_count[PQMC_K_COUNT] = {};
 };
 
 namespace {
@@ -195,6 +201,29 @@ void fill_problem(pqmc_ctx &c, const pqmc_problem *p, const pqmc_update_opts *o)
 
 const double kSpin[2] = {1.0, -1.0};
 
+// PQMC_FLAG_KTIME: an event pair around one launch, resolved after the call
+struct KTimer {
+  pqmc_ctx &c;
+  int cls;
+  size_t i0 = 0;
+  bool on;
+  KTimer(pqmc_ctx &cc, int k) : c(cc), cls(k), on((cc.opts.flags & PQMC_FLAG_KTIME) != 0) {
+    if (!on) return;
+    while (c.kevs.size() < c.kused + 2) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) { on = false; return; }
+      c.kevs.push_back(e);
+    }
+    i0 = c.kused;
+    c.kused += 2;
+    c.kclass.push_back(cls);
+    (void)hipEventRecord(c.kevs[i0], c.st);
+  }
+  ~KTimer() {
+    if (on) (void)hipEventRecord(c.kevs[i0 + 1], c.st);
+  }
+};
+
 // ------------------------------------------------------------------ helpers
 double *other(double *cur, double *const w[2]) { return cur == w[0] ? w[1] : w[0]; }
 
@@ -295,7 +324,10 @@ int prop_forward(pqmc_ctx &c, int l) {
     e.rs_field = row; e.rs_pos = em; e.rs_neg = ep;
     gb.d[gb.count++] = e;
   }
-  PQ_HIP_CHECK(gemm(gb, false, false, c.st));
+  {
+    KTimer kt(c, PQMC_K_PROPAGATE);
+    PQ_HIP_CHECK(gemm(gb, false, false, c.st));
+  }
   for (int s = 0; s < 2; ++s) { c.UR[s] = nur[s]; c.ULt[s] = nul[s]; }
   return PQMC_OK;
 }
@@ -319,7 +351,10 @@ int prop_backward(pqmc_ctx &c, int l, bool with_R) {
       gb.d[gb.count++] = e;
     }
   }
-  PQ_HIP_CHECK(gemm(gb, false, false, c.st));
+  {
+    KTimer kt(c, with_R ? PQMC_K_PROPAGATE : -1);
+    PQ_HIP_CHECK(gemm(gb, false, false, c.st));
+  }
   for (int s = 0; s < 2; ++s) {
     c.ULt[s] = nul[s];
     if (with_R) c.UR[s] = nur[s];
@@ -424,7 +459,10 @@ int update_slice(pqmc_ctx &c, int l, int dir) {
   switch (c.opts.scheme) {
     case PQMC_LOCAL: {
       const int nt = ceil_div(std::max(c.Ns[0], c.Ns[1]), 64);
-      for (int i = 0; i <= N; ++i) PQ_HIP_CHECK(local_step(m, c.lb, x, i, nt, c.st));
+      for (int i = 0; i <= N; ++i) {
+        KTimer kt(c, PQMC_K_LOCAL);
+        PQ_HIP_CHECK(local_step(m, c.lb, x, i, nt, c.st));
+      }
       c.log_count += N;
       break;
     }
@@ -438,17 +476,27 @@ int update_slice(pqmc_ctx &c, int l, int dir) {
       for (int g0 = 0; g0 < N; g0 += k, ++bi) {
         const int kk = std::min(k, N - g0);
         if (fused) {
-          PQ_HIP_CHECK(group_tile(m, c.gb, g_prev >= 0, g_prev, g0, kk, c.st));
+          {
+            KTimer kt(c, PQMC_K_TILE);
+            PQ_HIP_CHECK(group_tile(m, c.gb, g_prev >= 0, g_prev, g0, kk, c.st));
+          }
+          KTimer kt(c, PQMC_K_REDUCE);
           PQ_HIP_CHECK(group_reduce(m, c.gb, g0, kk, c.st));
         } else {
           PQ_HIP_CHECK(group_panels(m, c.gb, g0, kk, c.st));
         }
-        if (delayed) PQ_HIP_CHECK(delayed_decide(c.gb, x, g0, kk, c.st));
-        else PQ_HIP_CHECK(block_decide(c.gb, x, g0, kk, bi, c.st));
+        {
+          KTimer kt(c, PQMC_K_DECIDE);
+          if (delayed) PQ_HIP_CHECK(delayed_decide(c.gb, x, g0, kk, c.st));
+          else PQ_HIP_CHECK(block_decide(c.gb, x, g0, kk, bi, c.st));
+        }
         if (fused) g_prev = g0;
         else PQ_HIP_CHECK(group_flush(m, c.gb, g0, kk, c.st));
       }
-      if (fused && g_prev >= 0) PQ_HIP_CHECK(group_tile(m, c.gb, true, g_prev, 0, 0, c.st));
+      if (fused && g_prev >= 0) {
+        KTimer kt(c, PQMC_K_TILE);
+        PQ_HIP_CHECK(group_tile(m, c.gb, true, g_prev, 0, 0, c.st));
+      }
       if (delayed) {
         c.log_count += N;
       } else {
@@ -524,13 +572,32 @@ int begin_call(pqmc_ctx &c) {
   PQ_HIP_CHECK(hipMemsetAsync(c.stats, 0, 16 * sizeof(unsigned long long), c.st));
   c.log_count = 0;
   c.hb_count = 0;
+  c.kused = 0;
+  c.kclass.clear();
+  for (int k = 0; k < PQMC_K_COUNT; ++k) {
+    c.kt_total[k] = 0.0;
+    c.kt_count[k] = 0;
+  }
   return PQMC_OK;
+}
+
+void resolve_kernel_times(pqmc_ctx &c) {
+  for (size_t p = 0; p < c.kclass.size(); ++p) {
+    const int k = c.kclass[p];
+    if (k < 0 || k >= PQMC_K_COUNT) continue;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, c.kevs[2 * p], c.kevs[2 * p + 1]) == hipSuccess) {
+      c.kt_total[k] += ms * 1e-3;
+      c.kt_count[k] += 1;
+    }
+  }
 }
 
 int finish_call(pqmc_ctx &c, PhaseTimer &tm, double t0, pqmc_stats *out) {
   int rc = tm.mark(kPhEnd);
   if (rc) return rc;
   rc = sync_check(c);
+  resolve_kernel_times(c);
   const double t1 =
       std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
   if (out) {
@@ -797,10 +864,20 @@ pqmc_status pqmc_get_heat_bath(pqmc_ctx *c, int32_t *meta, double *margin, size_
   return copy_log(c, c->hb_meta, c->hb_margin, c->hb_total, meta, margin, cap, n);
 }
 
+pqmc_status pqmc_get_kernel_times(pqmc_ctx *c, double *totals, uint64_t *counts) {
+  if (!c || !totals || !counts) return set_error(PQMC_EINVAL, "null argument");
+  for (int k = 0; k < PQMC_K_COUNT; ++k) {
+    totals[k] = c->kt_total[k];
+    counts[k] = c->kt_count[k];
+  }
+  return PQMC_OK;
+}
+
 pqmc_status pqmc_destroy(pqmc_ctx *c) {
   if (!c) return PQMC_OK;
   (void)hipStreamSynchronize(c->st);
   for (hipEvent_t e : c->evs) (void)hipEventDestroy(e);
+  for (hipEvent_t e : c->kevs) (void)hipEventDestroy(e);
   delete c;
   return PQMC_OK;
 }
