@@ -131,18 +131,16 @@ void layout(pqmc_ctx &c, char *base, size_t *bytes) {
     c.gb.P1part[s] = cv.take<double>(nt * ns * kmax);
     c.gb.P2[s] = cv.take<double>(kmax * ns);
     c.gb.P1[s] = cv.take<double>(ns * kmax);
-    c.gb.W0part[s] = cv.take<double>(nt * kmax * kmax);
+    c.gb.W0part[s] = cv.take<double>(nt * nt * kmax * kmax);
     c.gb.W0[s] = cv.take<double>(kmax * kmax);
-    c.gb.Minv[s] = cv.take<double>(kmax * kmax);
+    c.gb.Mc[s] = cv.take<double>(kmax * kmax);
+    c.gb.sc[s] = cv.take<double>(kmax);
     c.gb.Q[s] = cv.take<double>(ns * kmax);
-    c.gb.P2c[s] = cv.take<double>(kmax * ns);
-    c.gb.Dsel[s] = cv.take<double>(kmax);
   }
   c.lb.delta[0] = cv.take<double>(2);
   c.lb.delta[1] = cv.take<double>(2);
-  c.gb.Alist = cv.take<int>(kmax);
-  c.gb.nA = cv.take<int>(1);
-  c.gb.ticket = cv.take<int>(2);
+  c.gb.nA = cv.take<int>(2);
+  c.gb.uni = cv.take<double>(kmax + 1);
   c.gb.kmax = kmax;
   c.gb.Ns[0] = c.Ns[0];
   c.gb.Ns[1] = c.Ns[1];
@@ -471,31 +469,36 @@ int update_slice(pqmc_ctx &c, int l, int dir) {
       const bool delayed = c.opts.scheme == PQMC_DELAYED;
       const int k = std::min(delayed ? c.opts.delay_k : c.opts.block_b, N);
       const bool fused = c.gmax <= 64;
+      const int mode = delayed ? kUniDelayed : kUniBlock;
       long long bi = 0;
-      int g_prev = -1;
+      int g_prev = -1, kk_prev = 0;
       for (int g0 = 0; g0 < N; g0 += k, ++bi) {
         const int kk = std::min(k, N - g0);
         if (fused) {
           {
             KTimer kt(c, PQMC_K_TILE);
-            PQ_HIP_CHECK(group_tile(m, c.gb, g_prev >= 0, g_prev, g0, kk, c.st));
+            PQ_HIP_CHECK(group_tile(m, c.gb, g_prev >= 0, g_prev, kk_prev, g0, kk, c.st));
           }
           KTimer kt(c, PQMC_K_REDUCE);
-          PQ_HIP_CHECK(group_reduce(m, c.gb, g0, kk, c.st));
+          PQ_HIP_CHECK(group_reduce(m, c.gb, x, mode, g0, kk, c.st));
         } else {
-          PQ_HIP_CHECK(group_panels(m, c.gb, g0, kk, c.st));
+          PQ_HIP_CHECK(group_panels(m, c.gb, x, mode, g0, kk, c.st));
         }
         {
           KTimer kt(c, PQMC_K_DECIDE);
           if (delayed) PQ_HIP_CHECK(delayed_decide(c.gb, x, g0, kk, c.st));
           else PQ_HIP_CHECK(block_decide(c.gb, x, g0, kk, bi, c.st));
         }
-        if (fused) g_prev = g0;
-        else PQ_HIP_CHECK(group_flush(m, c.gb, g0, kk, c.st));
+        if (fused) {
+          g_prev = g0;
+          kk_prev = kk;
+        } else {
+          PQ_HIP_CHECK(group_flush(m, c.gb, g0, kk, c.st));
+        }
       }
       if (fused && g_prev >= 0) {
         KTimer kt(c, PQMC_K_TILE);
-        PQ_HIP_CHECK(group_tile(m, c.gb, true, g_prev, 0, 0, c.st));
+        PQ_HIP_CHECK(group_tile(m, c.gb, true, g_prev, kk_prev, 0, 0, c.st));
       }
       if (delayed) {
         c.log_count += N;
@@ -728,7 +731,6 @@ pqmc_status pqmc_create(const pqmc_problem *prob, const pqmc_update_opts *opts, 
   if (!rc) rc = expm_taylor(*c, +sc, sq, c->Kinv);
   if (!rc) {
     hipError_t e = hipMemsetAsync(c->stats, 0, 16 * sizeof(unsigned long long), c->st);
-    if (e == hipSuccess) e = hipMemsetAsync(c->gb.ticket, 0, 2 * sizeof(int), c->st);
     if (e != hipSuccess) rc = fail_device(e, "memset", __FILE__, __LINE__);
   }
   if (!rc) {

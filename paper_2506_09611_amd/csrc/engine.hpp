@@ -82,19 +82,25 @@ hipError_t local_step(const SpinMats &m, const LocalBufs &b, const SweepCtx &c, 
 struct GroupBufs {
   double *P2part[2], *P1part[2];   // split-K partials
   double *P2[2], *P1[2];           // kmax x Ns, Ns x kmax
-  double *W0part[2];               // nstrip x kmax x kmax
-  double *W0[2];                   // kmax x kmax: W0 = U_g T L_g
-  int *ticket;                     // per spin: strips of W0 summed so far (reduce kernel)
-  double *Minv[2];                 // kmax x kmax
-  double *Q[2];                    // Ns x kmax
-  double *P2c[2];                  // kmax x Ns
-  double *Dsel[2];                 // kmax
-  int *Alist;                      // kmax
-  int *nA;                         // 1
+  double *W0part[2];               // nt^2 x kmax x kmax: per-tile partials of W0
+  double *W0[2];                   // kmax x kmax: W0 = U_g T L_g (partials in fixed order)
+  double *uni;                     // kmax + 1: the group's Metropolis / heat-bath uniforms
+  // Result of a decision over the group's kk sites, with A the accepted
+  // (delayed) or flipped (block force bias) set:
+  //   Mc = diag(Delta_A) (E_AA)^{-1} spread to kk x kk (zero outside A x A),
+  //   sc = 1 + Delta on A and 1 elsewhere (the U_R row scale),
+  // so that the flush is T <- T - P1 Mc P2 (Eqs. (30), (36)).
+  double *Mc[2];                   // kmax x kmax
+  double *sc[2];                   // kmax
+  double *Q[2];                    // Ns x kmax: P1 Mc (flush without the tile kernel)
+  int *nA;                         // 2: |A|, and the flush rank (kk, or 0 when A is empty)
   int kmax;
   int Ns[2];                       // particles per spin
 };
-hipError_t group_panels(const SpinMats &m, const GroupBufs &g, int g0, int kk, hipStream_t st);
+// Uniforms drawn by the reduce kernel for the decision that follows it.
+enum UniMode { kUniNone = 0, kUniDelayed = 1, kUniBlock = 2 };
+hipError_t group_panels(const SpinMats &m, const GroupBufs &g, const SweepCtx &c, int mode,
+                        int g0, int kk, hipStream_t st);
 hipError_t delayed_decide(const GroupBufs &g, const SweepCtx &c, int g0, int kk,
                           hipStream_t st);
 hipError_t block_decide(const GroupBufs &g, const SweepCtx &c, int g0, int kk,
@@ -103,8 +109,9 @@ hipError_t group_flush(const SpinMats &m, const GroupBufs &g, int g0, int kk, hi
 // Fused path (kmax <= 64): one tile kernel per group applies the previous
 // group's flush and forms this group's split-K panel partials; group_reduce
 // sums them into P1, P2 and W0.
-hipError_t group_tile(const SpinMats &m, const GroupBufs &g, bool flush, int g0_prev, int g0,
-                      int kk, hipStream_t st);
-hipError_t group_reduce(const SpinMats &m, const GroupBufs &g, int g0, int kk, hipStream_t st);
+hipError_t group_tile(const SpinMats &m, const GroupBufs &g, bool flush, int g0_prev,
+                      int kk_prev, int g0, int kk, hipStream_t st);
+hipError_t group_reduce(const SpinMats &m, const GroupBufs &g, const SweepCtx &c, int mode,
+                        int g0, int kk, hipStream_t st);
 
 }  // namespace pq

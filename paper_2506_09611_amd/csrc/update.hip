@@ -27,6 +27,8 @@
 // Eq. (36) (block), done as a rank-n_A MFMA GEMM.
 #include "engine.hpp"
 
+#include <algorithm>
+
 namespace pq {
 
 namespace {
@@ -190,74 +192,140 @@ __global__ __launch_bounds__(256) void local_step_kernel(LocalArgs a) {
 }
 
 // ------------------------------------------------------------------------
-// group panels: reduce split-K partials, form W0 partials per column strip
+// group panels: sums of the split-K partials of P1, P2 and W0
 // ------------------------------------------------------------------------
 struct ReduceArgs {
   SpinMats m;
   GroupBufs g;
   int g0, kk;
+  int do_panels;             // sum the split-K partials of P1 and P2
+  int w0_mode;               // W0 partials to add: 0 none, 1 one per tile (nt^2), 2 per strip (nt)
+  int mode;                  // UniMode: uniforms drawn for the following decision
+  uint64_t key0, key1, sweep, slice_code;
 };
 
-constexpr int kRedThreads = 1024;
+constexpr int kRedThreads = 256;
+constexpr int kRedParts = 4;       // panel workgroups per (column strip, spin)
+constexpr int kRedChunk = 16;      // partials loaded together per element
 
+// p[0] + p[stride] + ... + p[(n-1) stride], added in index order, for two
+// independent elements at once so that all their loads are in flight together.
+__device__ __forceinline__ void sum_pair(const double *p, const double *q, bool pv, bool qv,
+                                         long stride, int n, double &sp, double &sq) {
+  sp = 0.0;
+  sq = 0.0;
+  for (int b = 0; b < n; b += kRedChunk) {
+    double vp[kRedChunk], vq[kRedChunk];
+#pragma unroll
+    for (int i = 0; i < kRedChunk; ++i) {
+      const bool in = b + i < n;
+      vp[i] = (pv && in) ? p[(long)(b + i) * stride] : 0.0;
+      vq[i] = (qv && in) ? q[(long)(b + i) * stride] : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < kRedChunk; ++i) {
+      if (b + i < n) {
+        sp += vp[i];
+        sq += vq[i];
+      }
+    }
+  }
+}
+
+// Grid (nP + nW + 1, 2 spins) with nP = nt * kRedParts panel workgroups and
+// nW = kk W0 workgroups per spin.  Panel workgroup (strip, part) sums its
+// share of the split-K partials of P2[:, strip] (rows of P2) and of
+// P1[strip rows, :]; W0 workgroup m adds the partials of row m of W0 in a
+// fixed order; the last workgroup (spin 0) draws the group's uniforms.  No
+// workgroup depends on another.
 __global__ __launch_bounds__(kRedThreads) void group_reduce_kernel(ReduceArgs a) {
   const int s = blockIdx.y;
+  const int t = threadIdx.x;
+  const int kk = a.kk, kmax = a.g.kmax;
   const int Ns = a.m.Ns[s];
   const int nt = (Ns + 63) / 64;
-  const int strip = blockIdx.x;
+  const int ntm = (max(a.m.Ns[0], a.m.Ns[1]) + 63) / 64;
+  const int nP = a.do_panels ? ntm * kRedParts : 0;
+  const int nW = a.w0_mode ? kk : 0;
+  const int x = blockIdx.x;
+  if (x == (int)gridDim.x - 1) {
+    if (s == 0 && a.mode != kUniNone) {
+      const uint64_t purpose = a.mode == kUniDelayed ? kPurposeMH : kPurposeHB;
+      if (t < kk)
+        a.g.uni[t] = philox_uniform(a.key0, a.key1, a.sweep, a.slice_code, (uint64_t)(a.g0 + t),
+                                    purpose);
+      if (a.mode == kUniBlock && t == kk)
+        a.g.uni[kk] = philox_uniform(a.key0, a.key1, a.sweep, a.slice_code, (uint64_t)a.g0,
+                                     kPurposeMH);
+    }
+    return;
+  }
+  if (x >= nP) {
+    // ---- row m of W0: partials added with lane group q taking partials
+    // q, q + 4, ... in order, then the four groups in order
+    const int mrow = x - nP;
+    if (mrow >= nW) return;
+    __shared__ double red[4][64];
+    const long stride = (long)kmax * kmax;
+    const int np = a.w0_mode == 1 ? nt * nt : nt;
+    const int q = t >> 6, ln = t & 63;
+    for (int n0 = 0; n0 < kk; n0 += 64) {
+      const int n = n0 + ln;
+      const double *p = a.g.W0part[s] + mrow * kmax + n;
+      double sum = 0.0;
+      for (int b = q; b < np; b += 4 * kRedChunk) {
+        double v[kRedChunk];
+#pragma unroll
+        for (int i = 0; i < kRedChunk; ++i) {
+          const int pi = b + 4 * i;
+          v[i] = (n < kk && pi < np) ? p[(long)pi * stride] : 0.0;
+        }
+#pragma unroll
+        for (int i = 0; i < kRedChunk; ++i)
+          if (b + 4 * i < np) sum += v[i];
+      }
+      red[q][ln] = sum;
+      __syncthreads();
+      if (q == 0 && n < kk)
+        a.g.W0[s][mrow * kmax + n] = ((red[0][ln] + red[1][ln]) + red[2][ln]) + red[3][ln];
+      __syncthreads();
+    }
+    return;
+  }
+  // ---- panel workgroup
+  const int strip = x / kRedParts, part = x % kRedParts;
   if (strip >= nt) return;
-  const int kk = a.kk, kmax = a.g.kmax;
-  const int t = threadIdx.x;
   const int c0 = strip * 64;
   const int w = min(64, Ns - c0);
-  extern __shared__ double dyn_lds[];
-  double (*p2s)[65] = reinterpret_cast<double (*)[65]>(dyn_lds);
-  double (*lgs)[65] = reinterpret_cast<double (*)[65]>(dyn_lds + (size_t)kk * 65);
-  // P2[:, strip] and the group's rows of U_L^T over the strip
-  for (int e = t; e < kk * 64; e += kRedThreads) {
-    const int mrow = e >> 6, cc = e & 63;
-    double v = 0.0, l = 0.0;
-    if (cc < w) {
-      const long off = (long)mrow * Ns + c0 + cc;
-      v = sum_strided(a.g.P2part[s] + off, (long)kmax * Ns, nt);
-      a.g.P2[s][off] = v;
-      l = a.m.ULt[s][(long)(a.g0 + mrow) * Ns + c0 + cc];
-    }
-    p2s[mrow][cc] = v;
-    lgs[mrow][cc] = l;
+  const int mper = (kk + kRedParts - 1) / kRedParts;
+  const int m0 = part * mper, m1 = min(kk, m0 + mper);
+  const int r0 = part * (64 / kRedParts), r1 = min(w, r0 + 64 / kRedParts);
+  // P2 rows [m0, m1) over the strip
+  const int n2 = max(0, m1 - m0) * 64;
+  for (int e = t; e < n2; e += 2 * kRedThreads) {
+    const int e2 = e + kRedThreads;
+    const int ma = m0 + (e >> 6), ca = e & 63;
+    const int mb = m0 + (e2 >> 6), cb = e2 & 63;
+    const bool va = ca < w, vb = e2 < n2 && cb < w;
+    const long oa = (long)ma * Ns + c0 + ca, ob = (long)mb * Ns + c0 + cb;
+    double sa, sb;
+    sum_pair(a.g.P2part[s] + oa, a.g.P2part[s] + (vb ? ob : oa), va, vb, (long)kmax * Ns, nt, sa,
+             sb);
+    if (va) a.g.P2[s][oa] = sa;
+    if (vb) a.g.P2[s][ob] = sb;
   }
-  // P1[strip rows, :]
-  for (int e = t; e < 64 * kk; e += kRedThreads) {
-    const int rr = e / kk, mcol = e % kk;
-    if (rr < w) {
-      const long off = (long)(c0 + rr) * kmax + mcol;
-      a.g.P1[s][off] = sum_strided(a.g.P1part[s] + off, (long)Ns * kmax, nt);
-    }
-  }
-  __syncthreads();
-  // W0 partial over this strip: sum_c P2[m1][c] L_g[m2][c]
-  for (int e = t; e < kk * kk; e += kRedThreads) {
-    const int m1 = e / kk, m2 = e % kk;
-    double v = 0.0;
-#pragma unroll 8
-    for (int cc = 0; cc < 64; ++cc) v += p2s[m1][cc] * lgs[m2][cc];
-    a.g.W0part[s][(long)strip * kmax * kmax + m1 * kmax + m2] = v;
-  }
-  // the last strip to finish sums the partials in strip order into W0
-  // (deterministic; the ticket counter is reset for the next launch)
-  __shared__ int s_last;
-  __threadfence();
-  __syncthreads();
-  if (t == 0) s_last = (atomicAdd(&a.g.ticket[s], 1) == nt - 1) ? 1 : 0;
-  __syncthreads();
-  if (s_last) {
-    __threadfence();
-    for (int e = t; e < kk * kk; e += kRedThreads) {
-      const int m1 = e / kk, m2 = e % kk;
-      a.g.W0[s][m1 * kmax + m2] =
-          sum_strided(a.g.W0part[s] + m1 * kmax + m2, (long)kmax * kmax, nt);
-    }
-    if (t == 0) a.g.ticket[s] = 0;
+  // P1 rows [c0 + r0, c0 + r1)
+  const int n1 = max(0, r1 - r0) * kk;
+  for (int e = t; e < n1; e += 2 * kRedThreads) {
+    const int e2 = e + kRedThreads;
+    const long oa = (long)(c0 + r0 + e / kk) * kmax + e % kk;
+    const long ob = (long)(c0 + r0 + e2 / kk) * kmax + e2 % kk;
+    const bool vb = e2 < n1;
+    double sa, sb;
+    sum_pair(a.g.P1part[s] + oa, a.g.P1part[s] + (vb ? ob : oa), true, vb, (long)Ns * kmax, nt,
+             sa, sb);
+    a.g.P1[s][oa] = sa;
+    if (vb) a.g.P1[s][ob] = sb;
   }
 }
 
@@ -272,10 +340,6 @@ struct DecideArgs {
   long long block_index;
 };
 
-// W0 = U_g T L_g for element (a, b), as summed by the reduce kernel
-__device__ __forceinline__ double w0_elem(const DecideArgs &A, int s, int a, int b) {
-  return A.g.W0[s][a * A.g.kmax + b];
-}
 
 // kDecThreads lanes, kDecQ = ceil(kk * kk / kDecThreads) elements of each
 // spin's E per lane (kk <= kDecThreads).
@@ -288,14 +352,13 @@ __global__ __launch_bounds__(kDecThreads) void delayed_decide_kernel(DecideArgs 
   __shared__ double uni[128];
   __shared__ double dl[2][128];
   __shared__ int acc_s[128];
-  __shared__ int pos[128];
 
   if (t < kk) {
     const int site = A.g0 + t;
     const int8_t x = C.fields[(long)C.li * C.N + site];
     dl[0][t] = C.dflip[0][x > 0 ? 0 : 1];
     dl[1][t] = C.dflip[1][x > 0 ? 0 : 1];
-    uni[t] = philox_uniform(C.key0, C.key1, C.sweep, C.slice_code, (uint64_t)site, kPurposeMH);
+    uni[t] = A.g.uni[t];
   }
   __syncthreads();
   // owned elements of E_s = 1 + W0_s diag(Delta_s); (row, column) per element
@@ -309,8 +372,8 @@ __global__ __launch_bounds__(kDecThreads) void delayed_decide_kernel(DecideArgs 
     cb_[q] = (e < kk * kk) ? e % kk : 1 << 20;
     if (e < kk * kk) {
       const int ia = ra[q], ib = cb_[q];
-      e0[q] = (ia == ib ? 1.0 : 0.0) + w0_elem(A, 0, ia, ib) * dl[0][ib];
-      e1[q] = (ia == ib ? 1.0 : 0.0) + w0_elem(A, 1, ia, ib) * dl[1][ib];
+      e0[q] = (ia == ib ? 1.0 : 0.0) + A.g.W0[0][ia * A.g.kmax + ib] * dl[0][ib];
+      e1[q] = (ia == ib ? 1.0 : 0.0) + A.g.W0[1][ia * A.g.kmax + ib] * dl[1][ib];
       if (ib == 0) { colb[0][0][ia] = e0[q]; colb[1][0][ia] = e1[q]; }
       if (ia == 0) { rowb[0][0][ib] = e0[q]; rowb[1][0][ib] = e1[q]; }
     }
@@ -373,32 +436,413 @@ __global__ __launch_bounds__(kDecThreads) void delayed_decide_kernel(DecideArgs 
     C.stats[kStNegative] += n_neg;
     if (any_nan) C.stats[kStError] |= kErrNonFinite;
   }
-  // compaction of the accepted set, one lane per site (no single-lane loops)
+  // row scales and flipped fields, one lane per site
   if (t < kk) {
-    int before = 0;
-    for (int m = 0; m < t; ++m) before += acc_s[m];
     const int mine = acc_s[t];
-    pos[t] = mine ? before : -1;
-    if (mine) {
-      A.g.Alist[before] = t;
-      A.g.Dsel[0][before] = dl[0][t];
-      A.g.Dsel[1][before] = dl[1][t];
-      C.fields[(long)C.li * C.N + A.g0 + t] = (int8_t)(-C.fields[(long)C.li * C.N + A.g0 + t]);
-    }
-    if (t == kk - 1) *A.g.nA = before + mine;
+    A.g.sc[0][t] = mine ? 1.0 + dl[0][t] : 1.0;
+    A.g.sc[1][t] = mine ? 1.0 + dl[1][t] : 1.0;
+    if (mine) C.fields[(long)C.li * C.N + A.g0 + t] = (int8_t)(-C.fields[(long)C.li * C.N + A.g0 + t]);
   }
-  __syncthreads();
-  // M^{-1} = (E_AA)^{-1} = -(swept E)_AA, compacted
+  if (t == 0) {
+    A.g.nA[0] = (int)n_acc;
+    A.g.nA[1] = n_acc ? kk : 0;
+  }
+  // Mc = diag(Delta_A) (E_AA)^{-1} = -diag(Delta_A) (swept E)_AA, zero elsewhere
   const int kmax = A.g.kmax;
 #pragma unroll
   for (int q = 0; q < kDecQ; ++q) {
     const int ia = ra[q], ib = cb_[q];
     if (ia < kk) {
-      const int pa = pos[ia], pb = pos[ib];
-      if (pa >= 0 && pb >= 0) {
-        A.g.Minv[0][pa * kmax + pb] = -e0[q];
-        A.g.Minv[1][pa * kmax + pb] = -e1[q];
+      const bool in = acc_s[ia] && acc_s[ib];
+      A.g.Mc[0][ia * kmax + ib] = in ? -dl[0][ia] * e0[q] : 0.0;
+      A.g.Mc[1][ia * kmax + ib] = in ? -dl[1][ia] * e1[q] : 0.0;
+    }
+  }
+}
+
+// Value of v in lane src (uniform src): the result is a wave-uniform scalar.
+__device__ __forceinline__ double readlane_f64(double v, int src) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, src);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), src);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Blocked delayed decision for kk <= KK sites (one workgroup of NT lanes).
+// E_s = 1 + W0_s diag(Delta_s) lives in LDS.  Sites are taken in sub-blocks
+// of kSub: wave 0 holds the sub-block's kSub x kSub diagonal block of both
+// spins in registers (lane = 8 a + b) and takes its decisions one after the
+// other, sweeping accepted pivots with cross-lane reads and no barrier.  The
+// sub-block's accepted set S is then swept out of the rest of E at once:
+// with C = (E_SS)^{-1} (minus the swept diagonal block),
+//   E_RR -= E_RS C E_SR,  E_SR <- C E_SR,  E_RS <- E_RS C,
+// which equals sweeping the pivots of S one by one.  Rows and columns of
+// rejected sites are never read again and are left stale.
+constexpr int kSub = 8;
+constexpr int kDLd = 65;
+
+// 1/p to full double precision for the pivots of the decision kernels:
+// hardware reciprocal estimate refined by two Newton steps (p is a finite,
+// nonzero pivot of an accepted proposal).
+__device__ __forceinline__ double recip(double p) {
+  double r = __builtin_amdgcn_rcp(p);
+  r = fma(r, fma(-p, r, 1.0), r);
+  return fma(r, fma(-p, r, 1.0), r);
+}
+
+template <int NT, int KK>
+__global__ __launch_bounds__(NT) void delayed_decide_blocked_kernel(DecideArgs A) {
+  static_assert(KK * KK % NT == 0 && KK <= 64, "tile shape");
+  constexpr int EPT = KK * KK / NT;           // elements of each spin's E per lane
+  const int kk = A.kk;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const SweepCtx &C = A.c;
+  const int kmax = A.g.kmax;
+  __shared__ double Es[2][KK * kDLd];
+  __shared__ double Xs[2][KK][kSub];     // E_{a,S} C for rows a outside the sub-block
+  __shared__ double Rn[2][kSub][KK];     // new rows S outside the sub-block: C E_{S,b}
+  __shared__ double Ro[2][kSub][KK];     // old rows S outside the sub-block
+  __shared__ double Cs[2][kSub][kSub];   // C, compacted to S x S
+  __shared__ double uni[KK], dl[2][KK];
+  __shared__ int accf[KK];
+  __shared__ int s_mask;
+
+  const int8_t *xrow = C.fields + (long)C.li * C.N + A.g0;
+  if (t < kk) {
+    const int8_t x = xrow[t];
+    dl[0][t] = C.dflip[0][x > 0 ? 0 : 1];
+    dl[1][t] = C.dflip[1][x > 0 ? 0 : 1];
+    uni[t] = A.g.uni[t];
+  }
+  // E_s = 1 + W0_s diag(Delta_s)
+  {
+    double w[2][EPT], dv[2][EPT];
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int e = t + NT * i, a = e / KK, b = e % KK;
+      const bool ok = a < kk && b < kk;
+      const int8_t x = ok ? xrow[b] : 1;
+#pragma unroll
+      for (int sp = 0; sp < 2; ++sp) {
+        w[sp][i] = ok ? A.g.W0[sp][a * kmax + b] : 0.0;
+        dv[sp][i] = C.dflip[sp][x > 0 ? 0 : 1];
       }
+    }
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int e = t + NT * i, a = e / KK, b = e % KK;
+      if (a < kk && b < kk) {
+#pragma unroll
+        for (int sp = 0; sp < 2; ++sp)
+          Es[sp][a * kDLd + b] = (a == b ? 1.0 : 0.0) + w[sp][i] * dv[sp][i];
+      }
+    }
+  }
+  __syncthreads();
+
+  unsigned long long n_acc = 0, n_low = 0, n_neg = 0;
+  bool any_nan = false;
+  for (int j0 = 0; j0 < kk; j0 += kSub) {
+    const int nb = min(kSub, kk - j0);
+    const int jend = j0 + nb;
+    if (wave == 0) {
+      const int ra = lane >> 3, cb = lane & 7;
+      const bool own = ra < nb && cb < nb;
+      double e0 = own ? Es[0][(j0 + ra) * kDLd + j0 + cb] : 0.0;
+      double e1 = own ? Es[1][(j0 + ra) * kDLd + j0 + cb] : 0.0;
+      const double ul = lane < nb ? uni[j0 + lane] : 0.0;
+      int mask = 0;
+      for (int jj = 0; jj < nb; ++jj) {
+        // pivot row and column values, fetched before the decision is known
+        const double ca0 = __shfl(e0, ra * 8 + jj, 64), rb0 = __shfl(e0, jj * 8 + cb, 64);
+        const double ca1 = __shfl(e1, ra * 8 + jj, 64), rb1 = __shfl(e1, jj * 8 + cb, 64);
+        const double p0 = readlane_f64(e0, jj * 9), p1 = readlane_f64(e1, jj * 9);
+        const double u = readlane_f64(ul, jj);
+        const double R = p0 * p1;
+        const double absA = fabs(R);
+        const bool finite = !isnan(absA);
+        const bool acc = __builtin_amdgcn_readfirstlane((finite && (u < absA)) ? 1 : 0) != 0;
+        const double margin = absA - u;
+        n_acc += acc ? 1 : 0;
+        n_low += (fabs(margin) < 1e-12) ? 1 : 0;
+        n_neg += (R < 0.0) ? 1 : 0;
+        any_nan = any_nan || !finite;
+        if (lane == 0) record_decision(C, C.log_base + A.g0 + j0 + jj, A.g0 + j0 + jj, acc, margin);
+        // principal pivot transform on pivot jj, both spins, kept only if accepted
+        const double ip0 = recip(p0), ip1 = recip(p1);
+        const bool rj = ra == jj, cj = cb == jj;
+        const double c0 = ca0 * ip0, c1 = ca1 * ip1;
+        double v0 = e0 - c0 * rb0, v1 = e1 - c1 * rb1;
+        v0 = rj ? rb0 * ip0 : v0;
+        v1 = rj ? rb1 * ip1 : v1;
+        v0 = cj ? c0 : v0;
+        v1 = cj ? c1 : v1;
+        v0 = (rj && cj) ? -ip0 : v0;
+        v1 = (rj && cj) ? -ip1 : v1;
+        e0 = acc ? v0 : e0;
+        e1 = acc ? v1 : e1;
+        mask |= acc ? (1 << jj) : 0;
+      }
+      if (own) {
+        Es[0][(j0 + ra) * kDLd + j0 + cb] = e0;
+        Es[1][(j0 + ra) * kDLd + j0 + cb] = e1;
+        // C = minus the swept S x S block, compacted
+        if (((mask >> ra) & 1) && ((mask >> cb) & 1)) {
+          const int pa = __popc(mask & ((1 << ra) - 1)), pb = __popc(mask & ((1 << cb) - 1));
+          Cs[0][pa][pb] = -e0;
+          Cs[1][pa][pb] = -e1;
+        }
+      }
+      if (lane < nb) accf[j0 + lane] = (mask >> lane) & 1;
+      if (lane == 0) s_mask = mask;
+    }
+    __syncthreads();
+    const int mask = __builtin_amdgcn_readfirstlane(s_mask);
+    if (mask == 0) continue;
+    const int ns = __popc(mask);
+    // positions of the accepted sites in the sub-block (uniform)
+    int sl[kSub];
+    {
+      int mm = mask;
+#pragma unroll
+      for (int q = 0; q < kSub; ++q) {
+        sl[q] = mm ? __ffs(mm) - 1 : 0;
+        mm &= mm - 1;
+      }
+    }
+    // rows outside the sub-block: X = E_{a,S} C
+    for (int e = t; e < KK * kSub; e += NT) {
+      const int a = e / kSub, p = e % kSub;
+      if (a >= kk || (a >= j0 && a < jend) || p >= ns) continue;
+      double v0 = 0.0, v1 = 0.0;
+#pragma unroll
+      for (int q = 0; q < kSub; ++q) {
+        if (q < ns) {
+          v0 += Es[0][a * kDLd + j0 + sl[q]] * Cs[0][q][p];
+          v1 += Es[1][a * kDLd + j0 + sl[q]] * Cs[1][q][p];
+        }
+      }
+      Xs[0][a][p] = v0;
+      Xs[1][a][p] = v1;
+    }
+    // rows S outside the sub-block: old values and C E_{S,b}
+    for (int e = t; e < kSub * KK; e += NT) {
+      const int p = e / KK, b = e % KK;
+      if (p >= ns || b >= kk || (b >= j0 && b < jend)) continue;
+      double v0 = 0.0, v1 = 0.0;
+#pragma unroll
+      for (int q = 0; q < kSub; ++q) {
+        if (q < ns) {
+          v0 += Cs[0][p][q] * Es[0][(j0 + sl[q]) * kDLd + b];
+          v1 += Cs[1][p][q] * Es[1][(j0 + sl[q]) * kDLd + b];
+        }
+      }
+      Rn[0][p][b] = v0;
+      Rn[1][p][b] = v1;
+      int sp_row = j0;
+#pragma unroll
+      for (int q = 0; q < kSub; ++q) sp_row = (q == p) ? j0 + sl[q] : sp_row;
+      Ro[0][p][b] = Es[0][sp_row * kDLd + b];
+      Ro[1][p][b] = Es[1][sp_row * kDLd + b];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int e = t + NT * i, a = e / KK, b = e % KK;
+      if (a >= kk || b >= kk) continue;
+      const bool ain = a >= j0 && a < jend, bin = b >= j0 && b < jend;
+      if (ain && bin) continue;
+      if (!ain && !bin) {
+        double v0 = Es[0][a * kDLd + b], v1 = Es[1][a * kDLd + b];
+#pragma unroll
+        for (int p = 0; p < kSub; ++p) {
+          if (p < ns) {
+            v0 -= Xs[0][a][p] * Ro[0][p][b];
+            v1 -= Xs[1][a][p] * Ro[1][p][b];
+          }
+        }
+        Es[0][a * kDLd + b] = v0;
+        Es[1][a * kDLd + b] = v1;
+      } else if (ain) {
+        if ((mask >> (a - j0)) & 1) {
+          const int p = __popc(mask & ((1 << (a - j0)) - 1));
+          Es[0][a * kDLd + b] = Rn[0][p][b];
+          Es[1][a * kDLd + b] = Rn[1][p][b];
+        }
+      } else if ((mask >> (b - j0)) & 1) {
+        const int p = __popc(mask & ((1 << (b - j0)) - 1));
+        Es[0][a * kDLd + b] = Xs[0][a][p];
+        Es[1][a * kDLd + b] = Xs[1][a][p];
+      }
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    C.stats[kStProposed] += kk;
+    C.stats[kStFieldUpdates] += kk;
+    C.stats[kStAccepted] += n_acc;
+    C.stats[kStFlips] += n_acc;
+    C.stats[kStLowMargin] += n_low;
+    C.stats[kStNegative] += n_neg;
+    if (any_nan) C.stats[kStError] |= kErrNonFinite;
+  }
+  // row scales and flipped fields, one lane per site
+  if (t < kk) {
+    const int mine = accf[t];
+    A.g.sc[0][t] = mine ? 1.0 + dl[0][t] : 1.0;
+    A.g.sc[1][t] = mine ? 1.0 + dl[1][t] : 1.0;
+    if (mine) C.fields[(long)C.li * C.N + A.g0 + t] = (int8_t)(-xrow[t]);
+  }
+  if (t == 0) {
+    A.g.nA[0] = (int)n_acc;
+    A.g.nA[1] = n_acc ? kk : 0;
+  }
+  // Mc = diag(Delta_A) (E_AA)^{-1} = -diag(Delta_A) (swept E)_AA, zero elsewhere
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = t + NT * i, a = e / KK, b = e % KK;
+    if (a >= kk || b >= kk) continue;
+    const bool in = accf[a] && accf[b];
+    A.g.Mc[0][a * kmax + b] = in ? -dl[0][a] * Es[0][a * kDLd + b] : 0.0;
+    A.g.Mc[1][a * kmax + b] = in ? -dl[1][a] * Es[1][a * kDLd + b] : 0.0;
+  }
+}
+
+// Delayed decision for kk <= KK <= 32 sites in a single wave.  The whole of
+// E_s = 1 + W0_s diag(Delta_s), both spins, stays in registers: lane
+// (ra, cb) = (lane / 8, lane % 8) holds rows ra + 8 i and columns cb + 8 j,
+// i, j < KK / 8.  Each decision reads its pivot's row and column with
+// cross-lane permutes and, when accepted, sweeps the pivot out of every
+// element (principal pivot transform), so decisions follow one another
+// without barriers or shared-memory round trips.
+template <int KK>
+__global__ __launch_bounds__(64) void delayed_decide_wave_kernel(DecideArgs A) {
+  constexpr int R = KK / 8;
+  static_assert(KK % 8 == 0 && R >= 1 && R <= 4, "tile shape");
+  const int kk = A.kk;
+  const int lane = threadIdx.x;
+  const int ra = lane >> 3, cb = lane & 7;
+  const SweepCtx &C = A.c;
+  const int kmax = A.g.kmax;
+  const int8_t *xrow = C.fields + (long)C.li * C.N + A.g0;
+
+  // the group's uniforms and field values, one lane per site
+  const double ul = lane < kk ? A.g.uni[lane] : 0.0;
+  const int8_t xl = lane < kk ? xrow[lane] : 1;
+  double e0[R][R], e1[R][R];
+  double da0[R], da1[R];   // Delta of this lane's rows, from the fields before any flip
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const int a = ra + 8 * i;
+    const int8_t xa = a < kk ? xrow[a] : 1;
+    da0[i] = C.dflip[0][xa > 0 ? 0 : 1];
+    da1[i] = C.dflip[1][xa > 0 ? 0 : 1];
+  }
+#pragma unroll
+  for (int i = 0; i < R; ++i)
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      const int a = ra + 8 * i, b = cb + 8 * j;
+      const bool ok = a < kk && b < kk;
+      const int8_t xb = ok ? xrow[b] : 1;
+      const double w0 = ok ? A.g.W0[0][a * kmax + b] : 0.0;
+      const double w1 = ok ? A.g.W0[1][a * kmax + b] : 0.0;
+      e0[i][j] = (a == b ? 1.0 : 0.0) + w0 * C.dflip[0][xb > 0 ? 0 : 1];
+      e1[i][j] = (a == b ? 1.0 : 0.0) + w1 * C.dflip[1][xb > 0 ? 0 : 1];
+    }
+
+  unsigned long long amask = 0;   // accepted sites (uniform)
+  unsigned long long n_low = 0, n_neg = 0;
+  bool any_nan = false;
+#pragma unroll
+  for (int J = 0; J < R; ++J) {
+    for (int jl = 0; jl < 8; ++jl) {
+      const int j = 8 * J + jl;
+      if (j >= kk) break;
+      const int src_c = ra * 8 + jl, src_r = jl * 8 + cb;
+      double c0[R], c1[R], r0[R], r1[R];
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        c0[i] = __shfl(e0[i][J], src_c, 64);
+        c1[i] = __shfl(e1[i][J], src_c, 64);
+        r0[i] = __shfl(e0[J][i], src_r, 64);
+        r1[i] = __shfl(e1[J][i], src_r, 64);
+      }
+      const double p0 = readlane_f64(e0[J][J], jl * 9), p1 = readlane_f64(e1[J][J], jl * 9);
+      const double u = readlane_f64(ul, j);
+      const double Rr = p0 * p1;
+      const double absA = fabs(Rr);
+      const bool finite = !isnan(absA);
+      const bool acc = __builtin_amdgcn_readfirstlane((finite && (u < absA)) ? 1 : 0) != 0;
+      const double margin = absA - u;
+      n_low += (fabs(margin) < 1e-12) ? 1 : 0;
+      n_neg += (Rr < 0.0) ? 1 : 0;
+      any_nan = any_nan || !finite;
+      if (lane == 0) record_decision(C, C.log_base + A.g0 + j, A.g0 + j, acc, margin);
+      if (acc) {
+        amask |= 1ull << j;
+        const double ip0 = recip(p0), ip1 = recip(p1);
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+          const double ci0 = c0[i] * ip0, ci1 = c1[i] * ip1;
+#pragma unroll
+          for (int jp = 0; jp < R; ++jp) {
+            e0[i][jp] -= ci0 * r0[jp];
+            e1[i][jp] -= ci1 * r1[jp];
+          }
+        }
+        if (ra == jl) {   // pivot row: E_jb / p
+#pragma unroll
+          for (int jp = 0; jp < R; ++jp) {
+            e0[J][jp] = r0[jp] * ip0;
+            e1[J][jp] = r1[jp] * ip1;
+          }
+        }
+        if (cb == jl) {   // pivot column: E_aj / p
+#pragma unroll
+          for (int i = 0; i < R; ++i) {
+            e0[i][J] = c0[i] * ip0;
+            e1[i][J] = c1[i] * ip1;
+          }
+        }
+        if (lane == jl * 9) {
+          e0[J][J] = -ip0;
+          e1[J][J] = -ip1;
+        }
+      }
+    }
+  }
+  const int n_acc = __popcll(amask);
+  if (lane == 0) {
+    C.stats[kStProposed] += kk;
+    C.stats[kStFieldUpdates] += kk;
+    C.stats[kStAccepted] += n_acc;
+    C.stats[kStFlips] += n_acc;
+    C.stats[kStLowMargin] += n_low;
+    C.stats[kStNegative] += n_neg;
+    if (any_nan) C.stats[kStError] |= kErrNonFinite;
+    A.g.nA[0] = n_acc;
+    A.g.nA[1] = n_acc ? kk : 0;
+  }
+  // row scales and flipped fields, one lane per site
+  if (lane < kk) {
+    const bool mine = (amask >> lane) & 1;
+    A.g.sc[0][lane] = mine ? 1.0 + C.dflip[0][xl > 0 ? 0 : 1] : 1.0;
+    A.g.sc[1][lane] = mine ? 1.0 + C.dflip[1][xl > 0 ? 0 : 1] : 1.0;
+    if (mine) C.fields[(long)C.li * C.N + A.g0 + lane] = (int8_t)(-xl);
+  }
+  // Mc = diag(Delta_A) (E_AA)^{-1} = -diag(Delta_A) (swept E)_AA, zero elsewhere
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const int a = ra + 8 * i;
+    if (a >= kk) continue;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      const int b = cb + 8 * j;
+      if (b >= kk) continue;
+      const bool in = ((amask >> a) & 1) && ((amask >> b) & 1);
+      A.g.Mc[0][a * kmax + b] = in ? -da0[i] * e0[i][j] : 0.0;
+      A.g.Mc[1][a * kmax + b] = in ? -da1[i] * e1[i][j] : 0.0;
     }
   }
 }
@@ -485,8 +929,9 @@ __global__ __launch_bounds__(NT) void block_decide_kernel(DecideArgs A) {
   __shared__ int ipiv[64];
   __shared__ int s_piv;
   __shared__ double db[2][64], nbar[2][64], sval[64], dp[2][64], hbm[64];
-  __shared__ int xold[64], xnew[64], flist[64];
+  __shared__ int xold[64], xnew[64], flist[64], posF[64];
   __shared__ int s_nF;
+  __shared__ double W0s[2][64 * LD];
 
   if (t < kk) {
     const int8_t x = C.fields[(long)C.li * C.N + A.g0 + t];
@@ -494,12 +939,16 @@ __global__ __launch_bounds__(NT) void block_decide_kernel(DecideArgs A) {
     db[0][t] = C.dremove[0][x > 0 ? 0 : 1];
     db[1][t] = C.dremove[1][x > 0 ? 0 : 1];
   }
+  for (int e = t; e < kk * kk; e += NT) {
+    W0s[0][(e / kk) * LD + e % kk] = A.g.W0[0][(e / kk) * kmax + e % kk];
+    W0s[1][(e / kk) * LD + e % kk] = A.g.W0[1][(e / kk) * kmax + e % kk];
+  }
   __syncthreads();
   for (int s = 0; s < 2; ++s) {
     // M1 = W0 (kept for the force-bias product), M0 = 1 + diag(Delta_b) W0
     for (int e = t; e < kk * kk; e += NT) {
       const int ia = e / kk, ib = e % kk;
-      const double w = w0_elem(A, s, ia, ib);
+      const double w = W0s[s][ia * LD + ib];
       M1[ia * LD + ib] = w;
       M0[ia * LD + ib] = (ia == ib ? 1.0 : 0.0) + db[s][ia] * w;
     }
@@ -518,8 +967,7 @@ __global__ __launch_bounds__(NT) void block_decide_kernel(DecideArgs A) {
     const double sv = C.alpha * (nbar[0][t] - nbar[1][t]);
     sval[t] = sv;
     const double pp = 1.0 / (1.0 + exp(-2.0 * sv));
-    const double u = philox_uniform(C.key0, C.key1, C.sweep, C.slice_code, (uint64_t)site,
-                                    kPurposeHB);
+    const double u = A.g.uni[t];
     xnew[t] = (u < pp) ? 1 : -1;
     const double margin = pp - u;
     hbm[t] = margin;
@@ -545,12 +993,12 @@ __global__ __launch_bounds__(NT) void block_decide_kernel(DecideArgs A) {
     for (int m = 0; m < t; ++m) before += (xnew[m] != xold[m]) ? 1 : 0;
     const int mine = (xnew[t] != xold[t]) ? 1 : 0;
     if (mine) flist[before] = t;
+    posF[t] = mine ? before : -1;
     if (t == kk - 1) s_nF = before + mine;
   }
   __syncthreads();
   const int nF = __builtin_amdgcn_readfirstlane(s_nF);
-  const double u_mh = philox_uniform(C.key0, C.key1, C.sweep, C.slice_code, (uint64_t)A.g0,
-                                     kPurposeMH);
+  const double u_mh = A.g.uni[kk];
   if (nF == 0) {
     if (t == 0) {
       C.stats[kStProposed] += 1;
@@ -559,7 +1007,8 @@ __global__ __launch_bounds__(NT) void block_decide_kernel(DecideArgs A) {
       const double margin = 1.0 - u_mh;
       if (fabs(margin) < 1e-12) C.stats[kStLowMargin] += 1;
       record_decision(C, C.log_base + A.block_index, A.g0, true, margin);
-      *A.g.nA = 0;
+      A.g.nA[0] = 0;
+      A.g.nA[1] = 0;
     }
     return;
   }
@@ -573,8 +1022,8 @@ __global__ __launch_bounds__(NT) void block_decide_kernel(DecideArgs A) {
   for (int e = t; e < nF * nF; e += NT) {
     const int ia = e / nF, ib = e % nF;
     const int fa = flist[ia], fb = flist[ib];
-    M0[ia * LD + ib] = (ia == ib ? 1.0 : 0.0) + A.g.W0[0][fa * kmax + fb] * dp[0][ib];
-    M1[ia * LD + ib] = (ia == ib ? 1.0 : 0.0) + A.g.W0[1][fa * kmax + fb] * dp[1][ib];
+    M0[ia * LD + ib] = (ia == ib ? 1.0 : 0.0) + W0s[0][fa * LD + fb] * dp[0][ib];
+    M1[ia * LD + ib] = (ia == ib ? 1.0 : 0.0) + W0s[1][fa * LD + fb] * dp[1][ib];
   }
   __syncthreads();
   const double r0 = lds_gj_inverse<NT>(M0, LD, nF, colk, rowk, ipiv, &s_piv);
@@ -599,31 +1048,36 @@ __global__ __launch_bounds__(NT) void block_decide_kernel(DecideArgs A) {
     if (Rb < 0.0) C.stats[kStNegative] += 1;
     if (nan_b) C.stats[kStError] |= kErrNonFinite;
     record_decision(C, C.log_base + A.block_index, A.g0, acc_b, margin);
-    *A.g.nA = acc_b ? nF : 0;
+    A.g.nA[0] = acc_b ? nF : 0;
+    A.g.nA[1] = acc_b ? kk : 0;
   }
   if (acc_b) {
-    if (t < nF) {
-      const int j = flist[t];
-      A.g.Alist[t] = j;
-      A.g.Dsel[0][t] = dp[0][t];
-      A.g.Dsel[1][t] = dp[1][t];
-      C.fields[(long)C.li * C.N + A.g0 + j] = (int8_t)xnew[j];
+    // Mc = diag(Delta'_F) (E'_FF)^{-1} spread to kk x kk, row scales, new fields
+    if (t < kk) {
+      const int pf = posF[t];
+      A.g.sc[0][t] = pf >= 0 ? 1.0 + dp[0][pf] : 1.0;
+      A.g.sc[1][t] = pf >= 0 ? 1.0 + dp[1][pf] : 1.0;
+      if (pf >= 0) C.fields[(long)C.li * C.N + A.g0 + t] = (int8_t)xnew[t];
     }
-    for (int e = t; e < nF * nF; e += NT) {
-      const int ia = e / nF, ib = e % nF;
-      A.g.Minv[0][ia * kmax + ib] = M0[ia * LD + ib];
-      A.g.Minv[1][ia * kmax + ib] = M1[ia * LD + ib];
+    for (int e = t; e < kk * kk; e += NT) {
+      const int a = e / kk, b = e % kk;
+      const int pa = posF[a], pb = posF[b];
+      const bool in = pa >= 0 && pb >= 0;
+      A.g.Mc[0][a * kmax + b] = in ? dp[0][pa] * M0[pa * LD + pb] : 0.0;
+      A.g.Mc[1][a * kmax + b] = in ? dp[1][pa] * M1[pa * LD + pb] : 0.0;
     }
   }
 }
 
 // ------------------------------------------------------------------------
-// flush: Q = P1_A diag(Delta_A) Minv, P2c = P2_A, U_R rows of accepted sites
+// flush without the tile kernel (kmax > 64): Q = P1 Mc per row strip, and
+// the accepted rows of U_R scaled; T -= Q P2 follows as a GEMM of rank kk
+// (skipped on the device when nothing was accepted)
 // ------------------------------------------------------------------------
 struct QArgs {
   SpinMats m;
   GroupBufs g;
-  int g0;
+  int g0, kk;
 };
 
 __global__ __launch_bounds__(256) void group_q_kernel(QArgs a) {
@@ -632,53 +1086,48 @@ __global__ __launch_bounds__(256) void group_q_kernel(QArgs a) {
   const int nt = (Ns + 63) / 64;
   const int strip = blockIdx.x;
   if (strip >= nt) return;
-  const int nA = *a.g.nA;
-  if (nA == 0) return;
-  const int kmax = a.g.kmax;
+  if (a.g.nA[0] == 0) return;
+  const int kmax = a.g.kmax, kk = a.kk;
   const int t = threadIdx.x;
   const int r0 = strip * 64;
   const int w = min(64, Ns - r0);
   extern __shared__ double dyn_lds[];
-  const int ldp = a.g.kmax + 1;
-  for (int e = t; e < 64 * nA; e += 256) {
-    const int rr = e / nA, m = e % nA;
-    dyn_lds[rr * ldp + m] = (rr < w) ? a.g.P1[s][(long)(r0 + rr) * kmax + a.g.Alist[m]] * a.g.Dsel[s][m] : 0.0;
+  const int ldp = kmax + 1;
+  for (int e = t; e < 64 * kk; e += 256) {
+    const int rr = e / kk, m = e % kk;
+    dyn_lds[rr * ldp + m] = (rr < w) ? a.g.P1[s][(long)(r0 + rr) * kmax + m] : 0.0;
   }
   __syncthreads();
-  for (int e = t; e < 64 * nA; e += 256) {
-    const int rr = e / nA, cc = e % nA;
+  const double *Mc = a.g.Mc[s];
+  for (int e = t; e < 64 * kk; e += 256) {
+    const int rr = e / kk, cc = e % kk;
     if (rr < w) {
       double v = 0.0;
-      for (int m = 0; m < nA; ++m) v += dyn_lds[rr * ldp + m] * a.g.Minv[s][m * kmax + cc];
+      for (int m = 0; m < kk; ++m) v += dyn_lds[rr * ldp + m] * Mc[m * kmax + cc];
       a.g.Q[s][(long)(r0 + rr) * kmax + cc] = v;
     }
   }
-  // compact P2 rows and scale the accepted rows of U_R over this column strip
-  for (int e = t; e < nA * 64; e += 256) {
-    const int m = e >> 6, cc = e & 63;
-    if (cc < w) {
-      const int j = a.g.Alist[m];
-      a.g.P2c[s][(long)m * Ns + r0 + cc] = a.g.P2[s][(long)j * Ns + r0 + cc];
-      a.m.UR[s][(long)(a.g0 + j) * Ns + r0 + cc] *= (1.0 + a.g.Dsel[s][m]);
-    }
+  for (int e = t; e < kk * 64; e += 256) {
+    const int j = e >> 6, cc = e & 63;
+    if (cc < w) a.m.UR[s][(long)(a.g0 + j) * Ns + r0 + cc] *= a.g.sc[s][j];
   }
 }
 
 // ------------------------------------------------------------------------
 // fused group tile kernel: one 64x64 tile of T per workgroup, read once per
 // group.  (1) applies the pending flush of the previous group,
-//     T_tile -= (P1_A diag(Delta_A) M) P2_A,   M = (E_AA)^{-1}   (Eqs. (30)/(36)),
+//     T_tile -= (P1 Mc) P2,   Mc = diag(Delta_A) (E_AA)^{-1}   (Eqs. (30)/(36)),
 // and scales that group's accepted rows of U_R; (2) forms this tile's
 // split-K contributions to the next group's panels P2 = U_g T and
-// P1 = T L_g from the updated tile.  All products run on MFMA from LDS.
+// P1 = T L_g from the updated tile.  Every operand is loaded at the start,
+// and all products run on MFMA from LDS.
 // ------------------------------------------------------------------------
 struct TileArgs {
   SpinMats m;
-  GroupBufs g;   // g.P1 / g.P2: panels of the pending (flushed) group
-  int flush;     // apply the pending flush (its size is read from g.nA)
-  int g0_prev;   // first site of the pending group
+  GroupBufs g;   // pending group: panels P1, P2, its Mc, sc and nA
+  int flush;     // a group is pending (its flush is skipped on the device if nA == 0)
+  int g0_prev, kk_prev;
   int g0, kk;    // next group (kk == 0: flush only)
-  int kpad;      // kmax rounded up to a multiple of 32
 };
 
 constexpr int kLdt = 65;   // padded LDS row stride
@@ -713,6 +1162,22 @@ __device__ __forceinline__ void lds_mma(dbl4 (&acc)[2][2], const double *A, int 
   }
 }
 
+// One 16x16 tile: returns A (16 x K) B (K x 16), K a multiple of 4, with
+// A(i, k) = Am[i * lda + k] and B(k, j) = Bm[k * ldb + j] (TB: Bm[j * ldb + k]).
+template <bool TB>
+__device__ __forceinline__ dbl4 mma16(const double *Am, int lda, const double *Bm, int ldb,
+                                      int K, int lane) {
+  dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+  const int i = lane & 15, kq = lane >> 4;
+  for (int k0 = 0; k0 < K; k0 += 4) {
+    const int k = k0 + kq;
+    const double a = Am[i * lda + k];
+    const double b = TB ? Bm[i * ldb + k] : Bm[k * ldb + i];
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+  }
+  return acc;
+}
+
 // (row, col) of accumulator element [mi][ni][j] in the 64x64 tile
 __device__ __forceinline__ int acc_row(int wm, int mi, int lane, int j) {
   return wm * 32 + mi * 16 + (lane >> 4) + 4 * j;
@@ -721,16 +1186,12 @@ __device__ __forceinline__ int acc_col(int wn, int ni, int lane) {
   return wn * 32 + ni * 16 + (lane & 15);
 }
 
-__device__ __forceinline__ void zero_acc(dbl4 (&a)[2][2]) {
-#pragma unroll
-  for (int mi = 0; mi < 2; ++mi)
-#pragma unroll
-    for (int ni = 0; ni < 2; ++ni) a[mi][ni] = dbl4{0.0, 0.0, 0.0, 0.0};
-}
-
-constexpr int kPanMax = 16;   // panel elements per lane staged in registers (kpad <= 64)
-
+// KP: kmax rounded up to a multiple of 16 (16, 32 or 64).
+template <int KP>
 __global__ __launch_bounds__(256) void group_tile_kernel(TileArgs a) {
+  constexpr int kPre = KP / 4;                       // per lane: a 64 x KP operand
+  constexpr int kPreM = KP * KP >= 256 ? KP * KP / 256 : 1;   // per lane: KP x KP
+  constexpr int kpad = KP;
   const int s = blockIdx.y;
   const int Ns = a.m.Ns[s];
   const int nt = (Ns + 63) / 64;
@@ -739,17 +1200,13 @@ __global__ __launch_bounds__(256) void group_tile_kernel(TileArgs a) {
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int row0 = rb * 64, col0 = cb * 64;
-  const int kmax = a.g.kmax, kpad = a.kpad;
-  const int kk = a.kk;
+  const int kmax = a.g.kmax;
+  const int kk = a.kk, kkp = a.kk_prev;
+  const int kp = (kkp + 3) & ~3;            // flush rank rounded to the MFMA depth
   double *T = a.m.T[s];
   extern __shared__ double lds[];
-  double *X = lds;                       // 64 x kLdt
-  double *Y = lds + 64 * kLdt;           // kpad x kLdt
-  double *Z = Y + kpad * kLdt;           // kpad x kLdt
-  __shared__ int al_s[64];
-  __shared__ double dsel_s[64];
 
-  // issue every independent load first: T tile, next group's panel rows, flush size
+  // ---- every load first: T tile, the pending flush's operands, next panels
   dbl4 acc[2][2];
 #pragma unroll
   for (int mi = 0; mi < 2; ++mi)
@@ -760,52 +1217,71 @@ __global__ __launch_bounds__(256) void group_tile_kernel(TileArgs a) {
         const int r = row0 + acc_row(wm, mi, lane, j), c = col0 + acc_col(wn, ni, lane);
         acc[mi][ni][j] = (r < Ns && c < Ns) ? T[(long)r * Ns + c] : 0.0;
       }
-  double ug[kPanMax], lg[kPanMax];
+  const bool fl = a.flush && a.g.nA[0] > 0;
+  double p1v[kPre], p2v[kPre], mcv[kPreM], urv[kPre];
+  if (fl) {
+    const double *P1 = a.g.P1[s], *P2 = a.g.P2[s], *Mc = a.g.Mc[s];
+    const double *UR = a.m.UR[s];
+#pragma unroll
+    for (int i = 0; i < kPre; ++i) {
+      const int e = t + 256 * i;
+      // P1 rows of the tile (64 x kpad), P2 columns of the tile (kpad x 64)
+      const int r = e / kpad, m = e % kpad;
+      p1v[i] = (e < 64 * kpad && m < kkp && row0 + r < Ns) ? P1[(long)(row0 + r) * kmax + m] : 0.0;
+      const int m2 = e >> 6, c2 = e & 63;
+      p2v[i] = (m2 < kkp && col0 + c2 < Ns) ? P2[(long)m2 * Ns + col0 + c2] : 0.0;
+      // accepted rows of U_R over this tile's columns (row-block 0 only)
+      urv[i] = (rb == 0 && m2 < kkp && col0 + c2 < Ns)
+                   ? UR[(long)(a.g0_prev + m2) * Ns + col0 + c2] : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < kPreM; ++i) {
+      const int e = t + 256 * i;
+      const int ma = e / kpad, mb = e % kpad;
+      mcv[i] = (e < kpad * kpad && ma < kkp && mb < kkp) ? Mc[ma * kmax + mb] : 0.0;
+    }
+  }
+  double ug[kPre], lg[kPre];
   if (kk > 0) {
     const double *UR = a.m.UR[s], *ULt = a.m.ULt[s];
 #pragma unroll
-    for (int i = 0; i < kPanMax; ++i) {
+    for (int i = 0; i < kPre; ++i) {
       const int e = t + 256 * i;
       const int m = e >> 6, c = e & 63;
-      const bool ok = e < kpad * 64 && m < kk;
+      const bool ok = m < kk;
       ug[i] = (ok && row0 + c < Ns) ? UR[(long)(a.g0 + m) * Ns + row0 + c] : 0.0;
       lg[i] = (ok && col0 + c < Ns) ? ULt[(long)(a.g0 + m) * Ns + col0 + c] : 0.0;
     }
   }
-  const int nA = a.flush ? __builtin_amdgcn_readfirstlane(*a.g.nA) : 0;
 
-  if (nA > 0) {
-    const double *P1 = a.g.P1[s], *P2 = a.g.P2[s], *Mi = a.g.Minv[s];
-    if (t < nA) {
-      al_s[t] = a.g.Alist[t];
-      dsel_s[t] = a.g.Dsel[s][t];
-    }
-    __syncthreads();
-    for (int e = t; e < 64 * kpad; e += 256) {
-      const int r = e / kpad, m = e % kpad;
-      X[r * kLdt + m] = (m < nA && row0 + r < Ns) ? -P1[(long)(row0 + r) * kmax + al_s[m]] * dsel_s[m] : 0.0;
-    }
-    for (int e = t; e < kpad * 64; e += 256) {
-      const int m = e >> 6, c = e & 63;
-      Y[m * kLdt + c] = (m < nA && c < nA) ? Mi[m * kmax + c] : 0.0;
-      Z[m * kLdt + c] = (m < nA && col0 + c < Ns) ? P2[(long)al_s[m] * Ns + col0 + c] : 0.0;
-    }
-    __syncthreads();
-    dbl4 q[2][2];
-    zero_acc(q);
-    lds_mma<false>(q, X, kLdt, Y, kLdt, nA, 64, nA, wm, wn, lane);   // Q = -P1_A D M
-    __syncthreads();
-    if (wn * 32 < nA) {
+  // ---- (1) pending flush: T_tile -= (P1 Mc) P2
+  if (fl) {
+    const int ld1 = kpad + 1;
+    double *A1 = lds;                       // 64 x ld1: P1 rows
+    double *M1 = A1 + 64 * ld1;             // kpad x ld1: Mc
+    double *B1 = M1 + kpad * ld1;           // kpad x kLdt: P2 columns
+    double *QS = B1 + kpad * kLdt;          // 64 x kLdt: -(P1 Mc)
 #pragma unroll
-      for (int mi = 0; mi < 2; ++mi)
+    for (int i = 0; i < kPre; ++i) {
+      const int e = t + 256 * i;
+      A1[(e / kpad) * ld1 + e % kpad] = p1v[i];
+      B1[(e >> 6) * kLdt + (e & 63)] = p2v[i];
+    }
 #pragma unroll
-        for (int ni = 0; ni < 2; ++ni)
-#pragma unroll
-          for (int j = 0; j < 4; ++j)
-            X[acc_row(wm, mi, lane, j) * kLdt + acc_col(wn, ni, lane)] = q[mi][ni][j];
+    for (int i = 0; i < kPreM; ++i) {
+      const int e = t + 256 * i;
+      if (e < kpad * kpad) M1[(e / kpad) * ld1 + e % kpad] = mcv[i];
     }
     __syncthreads();
-    lds_mma<false>(acc, X, kLdt, Z, kLdt, nA, 64, 64, wm, wn, lane);  // T += Q P2_A
+    // -(P1 Mc): wave w forms rows [16 w, 16 w + 16)
+    for (int n0 = 0; n0 < kp; n0 += 16) {
+      const dbl4 q = mma16<false>(A1 + 16 * wave * ld1, ld1, M1 + n0, ld1, kp, lane);
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        QS[(16 * wave + (lane >> 4) + 4 * j) * kLdt + n0 + (lane & 15)] = -q[j];
+    }
+    __syncthreads();
+    lds_mma<false>(acc, QS, kLdt, B1, kLdt, kp, 64, 64, wm, wn, lane);
 #pragma unroll
     for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
@@ -816,16 +1292,23 @@ __global__ __launch_bounds__(256) void group_tile_kernel(TileArgs a) {
           if (r < Ns && c < Ns) T[(long)r * Ns + c] = acc[mi][ni][j];
         }
     if (rb == 0) {
-      // accepted rows of U_R over this tile's columns
-      for (int e = t; e < nA * 64; e += 256) {
+      const double *sc = a.g.sc[s];
+      double *UR = a.m.UR[s];
+#pragma unroll
+      for (int i = 0; i < kPre; ++i) {
+        const int e = t + 256 * i;
         const int m = e >> 6, c = col0 + (e & 63);
-        if (c < Ns) a.m.UR[s][(long)(a.g0_prev + al_s[m]) * Ns + c] *= (1.0 + dsel_s[m]);
+        if (m < kkp && c < Ns) UR[(long)(a.g0_prev + m) * Ns + c] = urv[i] * sc[m];
       }
     }
     __syncthreads();
   }
 
   if (kk <= 0) return;
+  // ---- (2) next group's split-K panel partials from the updated tile
+  double *X = lds;                 // 64 x kLdt: T tile
+  double *Y = X + 64 * kLdt;       // kpad x kLdt: U_g over the tile's rows
+  double *Z = Y + kpad * kLdt;     // kpad x kLdt: L_g over the tile's columns
 #pragma unroll
   for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
@@ -834,44 +1317,65 @@ __global__ __launch_bounds__(256) void group_tile_kernel(TileArgs a) {
       for (int j = 0; j < 4; ++j)
         X[acc_row(wm, mi, lane, j) * kLdt + acc_col(wn, ni, lane)] = acc[mi][ni][j];
 #pragma unroll
-  for (int i = 0; i < kPanMax; ++i) {
+  for (int i = 0; i < kPre; ++i) {
     const int e = t + 256 * i;
-    if (e < kpad * 64) {
-      Y[(e >> 6) * kLdt + (e & 63)] = ug[i];
-      Z[(e >> 6) * kLdt + (e & 63)] = lg[i];
+    Y[(e >> 6) * kLdt + (e & 63)] = ug[i];
+    Z[(e >> 6) * kLdt + (e & 63)] = lg[i];
+  }
+  __syncthreads();
+  // 16x16 output tiles, round robin over the waves:
+  //   P2 part (kk x 64) = U_g[:, rows] T_tile,  P1 part (64 x kk) = T_tile L_g[cols, :],
+  //   W0 part (kk x kk) = (P2 part) L_g[cols, :]
+  const int mtk = (kk + 15) >> 4;
+  const int n2 = mtk * 4;
+  double *o2 = a.g.P2part[s] + (long)rb * kmax * Ns;
+  double *o1 = a.g.P1part[s] + (long)cb * Ns * kmax;
+  double *ow = a.g.W0part[s] + (long)(rb * nt + cb) * kmax * kmax;
+  dbl4 p2t[(KP / 16) * 4 / 4];   // this wave's P2 tiles (at most KP / 16 of them)
+#pragma unroll
+  for (int u = 0; u < KP / 16; ++u) {
+    const int tt = wave + 4 * u;
+    p2t[u] = dbl4{0.0, 0.0, 0.0, 0.0};
+    if (tt < n2) {
+      const int mt = tt >> 2, ct = tt & 3;
+      p2t[u] = mma16<false>(Y + mt * 16 * kLdt, kLdt, X + ct * 16, kLdt, 64, lane);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int m = mt * 16 + (lane >> 4) + 4 * j, c = col0 + ct * 16 + (lane & 15);
+        if (m < kk && c < Ns) o2[(long)m * Ns + c] = p2t[u][j];
+      }
+    }
+  }
+  for (int tt = wave; tt < n2; tt += 4) {
+    const int rt = tt / mtk, mt = tt % mtk;   // P1 tiles: 4 x mtk, as many as P2 tiles
+    const dbl4 p = mma16<true>(X + rt * 16 * kLdt, kLdt, Z + mt * 16 * kLdt, kLdt, 64, lane);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int r = row0 + rt * 16 + (lane >> 4) + 4 * j, m = mt * 16 + (lane & 15);
+      if (r < Ns && m < kk) o1[(long)r * kmax + m] = p[j];
+    }
+  }
+  __syncthreads();   // every wave is done with Y (U_g): it now takes the P2 part
+#pragma unroll
+  for (int u = 0; u < KP / 16; ++u) {
+    const int tt = wave + 4 * u;
+    if (tt < n2) {
+      const int mt = tt >> 2, ct = tt & 3;
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        Y[(mt * 16 + (lane >> 4) + 4 * j) * kLdt + ct * 16 + (lane & 15)] = p2t[u][j];
     }
   }
   __syncthreads();
-  dbl4 p[2][2];
-  zero_acc(p);
-  lds_mma<false>(p, Y, kLdt, X, kLdt, 64, kk, 64, wm, wn, lane);   // U_g[:, R] T_tile
-  if (wm * 32 < kk) {
-    double *out = a.g.P2part[s] + (long)rb * kmax * Ns;
+  for (int tt = wave; tt < mtk * mtk; tt += 4) {
+    const int mt = tt / mtk, nt2 = tt % mtk;
+    const dbl4 p = mma16<true>(Y + mt * 16 * kLdt, kLdt, Z + nt2 * 16 * kLdt, kLdt, 64, lane);
 #pragma unroll
-    for (int mi = 0; mi < 2; ++mi)
-#pragma unroll
-      for (int ni = 0; ni < 2; ++ni)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int m = acc_row(wm, mi, lane, j), c = col0 + acc_col(wn, ni, lane);
-          if (m < kk && c < Ns) out[(long)m * Ns + c] = p[mi][ni][j];
-        }
+    for (int j = 0; j < 4; ++j) {
+      const int m = mt * 16 + (lane >> 4) + 4 * j, n = nt2 * 16 + (lane & 15);
+      if (m < kk && n < kk) ow[m * kmax + n] = p[j];
+    }
   }
-  zero_acc(p);
-  lds_mma<true>(p, X, kLdt, Z, kLdt, 64, 64, kk, wm, wn, lane);    // T_tile L_g[C, :]
-  if (wn * 32 < kk) {
-    double *out = a.g.P1part[s] + (long)cb * Ns * kmax;
-#pragma unroll
-    for (int mi = 0; mi < 2; ++mi)
-#pragma unroll
-      for (int ni = 0; ni < 2; ++ni)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int r = row0 + acc_row(wm, mi, lane, j), m = acc_col(wn, ni, lane);
-          if (r < Ns && m < kk) out[(long)r * kmax + m] = p[mi][ni][j];
-        }
-  }
-
 }
 
 }  // namespace
@@ -883,7 +1387,19 @@ hipError_t local_step(const SpinMats &m, const LocalBufs &b, const SweepCtx &c, 
   return hipGetLastError();
 }
 
-hipError_t group_panels(const SpinMats &m, const GroupBufs &g, int g0, int kk, hipStream_t st) {
+namespace {
+hipError_t launch_reduce(const SpinMats &m, const GroupBufs &g, const SweepCtx &c, int mode,
+                         int g0, int kk, int do_panels, int w0_mode, hipStream_t st) {
+  const int ntm = (max(m.Ns[0], m.Ns[1]) + 63) / 64;
+  ReduceArgs ra{m, g, g0, kk, do_panels, w0_mode, mode, c.key0, c.key1, c.sweep, c.slice_code};
+  const int nP = do_panels ? ntm * kRedParts : 0, nW = w0_mode ? kk : 0;
+  hipLaunchKernelGGL(group_reduce_kernel, dim3(nP + nW + 1, 2), dim3(kRedThreads), 0, st, ra);
+  return hipGetLastError();
+}
+}  // namespace
+
+hipError_t group_panels(const SpinMats &m, const GroupBufs &g, const SweepCtx &c, int mode,
+                        int g0, int kk, hipStream_t st) {
   GemmBatch b2{}, b1{};
   for (int s = 0; s < 2; ++s) {
     const int Ns = m.Ns[s];
@@ -901,20 +1417,21 @@ hipError_t group_panels(const SpinMats &m, const GroupBufs &g, int g0, int kk, h
   if (err != hipSuccess) return err;
   err = gemm(b1, false, true, st);
   if (err != hipSuccess) return err;
-  const int nt = (max(m.Ns[0], m.Ns[1]) + 63) / 64;
-  ReduceArgs ra{m, g, g0, kk};
-  const size_t lds = sizeof(double) * 2 * 65 * (size_t)kk;
-  static bool attr_set = false;
-  if (!attr_set) {
-    // up to 133 KB of LDS for kk = 128 (gfx950 has 160 KB per CU)
-    hipError_t e = hipFuncSetAttribute((const void *)group_reduce_kernel,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)(sizeof(double) * 2 * 65 * 128));
-    if (e != hipSuccess) return e;
-    attr_set = true;
+  err = launch_reduce(m, g, c, mode, g0, kk, 1, 0, st);
+  if (err != hipSuccess) return err;
+  // W0 = P2 L_g^T, split over column strips, then its partials added
+  GemmBatch bw{};
+  for (int s = 0; s < 2; ++s) {
+    const int Ns = m.Ns[s];
+    GemmDesc d = gemm_desc(g.P2[s], Ns, m.ULt[s] + (long)g0 * Ns, Ns, g.W0part[s], g.kmax, kk,
+                           kk, Ns);
+    d.ksplit = 64;
+    d.csplit = (long)g.kmax * g.kmax;
+    bw.d[bw.count++] = d;
   }
-  hipLaunchKernelGGL(group_reduce_kernel, dim3(nt, 2), dim3(kRedThreads), lds, st, ra);
-  return hipGetLastError();
+  err = gemm(bw, false, true, st);
+  if (err != hipSuccess) return err;
+  return launch_reduce(m, g, c, kUniNone, g0, kk, 0, 2, st);
 }
 
 hipError_t delayed_decide(const GroupBufs &g, const SweepCtx &c, int g0, int kk,
@@ -924,10 +1441,16 @@ hipError_t delayed_decide(const GroupBufs &g, const SweepCtx &c, int g0, int kk,
   a.c = c;
   a.g0 = g0;
   a.kk = kk;
-  if (kk <= 8) hipLaunchKernelGGL((delayed_decide_kernel<64, 1>), dim3(1), dim3(64), 0, st, a);
-  else if (kk <= 16) hipLaunchKernelGGL((delayed_decide_kernel<64, 4>), dim3(1), dim3(64), 0, st, a);
-  else if (kk <= 32) hipLaunchKernelGGL((delayed_decide_kernel<256, 4>), dim3(1), dim3(256), 0, st, a);
-  else if (kk <= 64) hipLaunchKernelGGL((delayed_decide_kernel<512, 8>), dim3(1), dim3(512), 0, st, a);
+  if (kk <= 8)
+    hipLaunchKernelGGL((delayed_decide_wave_kernel<8>), dim3(1), dim3(64), 0, st, a);
+  else if (kk <= 16)
+    hipLaunchKernelGGL((delayed_decide_wave_kernel<16>), dim3(1), dim3(64), 0, st, a);
+  else if (kk <= 24)
+    hipLaunchKernelGGL((delayed_decide_wave_kernel<24>), dim3(1), dim3(64), 0, st, a);
+  else if (kk <= 32)
+    hipLaunchKernelGGL((delayed_decide_wave_kernel<32>), dim3(1), dim3(64), 0, st, a);
+  else if (kk <= 64)
+    hipLaunchKernelGGL((delayed_decide_blocked_kernel<512, 64>), dim3(1), dim3(512), 0, st, a);
   else hipLaunchKernelGGL((delayed_decide_kernel<1024, 16>), dim3(1), dim3(1024), 0, st, a);
   return hipGetLastError();
 }
@@ -956,62 +1479,68 @@ hipError_t block_decide(const GroupBufs &g, const SweepCtx &c, int g0, int kk,
   return hipGetLastError();
 }
 
-hipError_t group_tile(const SpinMats &m, const GroupBufs &g, bool flush, int g0_prev, int g0,
-                      int kk, hipStream_t st) {
+template <int KP>
+hipError_t launch_tile(const TileArgs &a, int nt, hipStream_t st) {
+  const size_t flush_lds = (size_t)64 * (KP + 1) + (size_t)KP * (KP + 1) + (size_t)KP * kLdt +
+                           (size_t)64 * kLdt;
+  const size_t panel_lds = (size_t)64 * kLdt + 2 * (size_t)KP * kLdt;
+  const size_t lds = sizeof(double) * std::max(flush_lds, panel_lds);
+  static bool attr_set = false;
+  if (!attr_set) {
+    // at most 133 KB (KP = 64) of the 160 KB per CU
+    hipError_t e = hipFuncSetAttribute((const void *)group_tile_kernel<KP>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(group_tile_kernel<KP>, dim3(nt * nt, 2), dim3(256), lds, st, a);
+  return hipGetLastError();
+}
+
+hipError_t group_tile(const SpinMats &m, const GroupBufs &g, bool flush, int g0_prev,
+                      int kk_prev, int g0, int kk, hipStream_t st) {
   TileArgs a{};
   a.m = m;
   a.g = g;
   a.flush = flush ? 1 : 0;
   a.g0_prev = g0_prev;
+  a.kk_prev = flush ? kk_prev : 0;
   a.g0 = g0;
   a.kk = kk;
-  a.kpad = (g.kmax + 31) / 32 * 32;
-  if (a.kpad > 64) return hipErrorInvalidValue;
-  const size_t lds = sizeof(double) * kLdt * (64 + 2 * (size_t)a.kpad);
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void *)group_tile_kernel,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)(sizeof(double) * kLdt * (64 + 2 * 64)));
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
   const int nt = (max(m.Ns[0], m.Ns[1]) + 63) / 64;
-  hipLaunchKernelGGL(group_tile_kernel, dim3(nt * nt, 2), dim3(256), lds, st, a);
-  return hipGetLastError();
+  if (g.kmax <= 16) return launch_tile<16>(a, nt, st);
+  if (g.kmax <= 32) return launch_tile<32>(a, nt, st);
+  if (g.kmax <= 64) return launch_tile<64>(a, nt, st);
+  return hipErrorInvalidValue;
 }
 
-hipError_t group_reduce(const SpinMats &m, const GroupBufs &g, int g0, int kk, hipStream_t st) {
-  const int nt = (max(m.Ns[0], m.Ns[1]) + 63) / 64;
-  ReduceArgs ra{m, g, g0, kk};
-  const size_t lds = sizeof(double) * 2 * 65 * (size_t)kk;
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void *)group_reduce_kernel,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)(sizeof(double) * 2 * 65 * 128));
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
-  hipLaunchKernelGGL(group_reduce_kernel, dim3(nt, 2), dim3(kRedThreads), lds, st, ra);
-  return hipGetLastError();
+hipError_t group_reduce(const SpinMats &m, const GroupBufs &g, const SweepCtx &c, int mode,
+                        int g0, int kk, hipStream_t st) {
+  return launch_reduce(m, g, c, mode, g0, kk, 1, 1, st);
 }
 
 hipError_t group_flush(const SpinMats &m, const GroupBufs &g, int g0, int kk, hipStream_t st) {
   const int nt = (max(m.Ns[0], m.Ns[1]) + 63) / 64;
-  QArgs qa{m, g, g0};
+  QArgs qa{m, g, g0, kk};
   const size_t lds = sizeof(double) * 64 * (size_t)(g.kmax + 1);
+  static bool attr_set = false;
+  if (!attr_set) {
+    // 66 KB for kmax = 128
+    hipError_t e = hipFuncSetAttribute((const void *)group_q_kernel,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)(sizeof(double) * 64 * 129));
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
   hipLaunchKernelGGL(group_q_kernel, dim3(nt, 2), dim3(256), lds, st, qa);
   GemmBatch b{};
   for (int s = 0; s < 2; ++s) {
     const int Ns = m.Ns[s];
-    GemmDesc d = gemm_desc(g.Q[s], g.kmax, g.P2c[s], Ns, m.T[s], Ns, Ns, Ns, kk, -1.0, 1.0,
+    GemmDesc d = gemm_desc(g.Q[s], g.kmax, g.P2[s], Ns, m.T[s], Ns, Ns, Ns, kk, -1.0, 1.0,
                            m.T[s], Ns);
-    d.Kdev = g.nA;
+    d.Kdev = g.nA + 1;   // rank kk, or 0 when nothing was accepted
     b.d[b.count++] = d;
   }
-  (void)kk;
   return gemm(b, false, false, st);
 }
-
 }  // namespace pq
