@@ -49,8 +49,8 @@ struct pqmc_ctx {
   double *URw[2][2] = {}, *ULw[2][2] = {};
   double *Lstack[2] = {}, *Rstack[2] = {};
   double *T[2] = {};
-  double *E[2] = {}, *R2[2] = {}, *Z[2] = {};
-  int *piv[2] = {};
+  double *E[2] = {}, *F[2] = {}, *BR[2] = {}, *Z[2] = {};
+  int *prow[2] = {}, *slot[2] = {};
   double *qrtmp[2] = {};
   LocalBufs lb{};
   GroupBufs gb{};
@@ -118,9 +118,11 @@ void layout(pqmc_ctx &c, char *base, size_t *bytes) {
     c.Rstack[s] = cv.take<double>((size_t)(c.nst + 1) * N * ns);
     c.T[s] = cv.take<double>(ns * ns);
     c.E[s] = cv.take<double>(ns * 2 * ns);
-    c.R2[s] = cv.take<double>((size_t)kNB * 2 * ns);
-    c.Z[s] = cv.take<double>(2 * kNB * kNB);
-    c.piv[s] = cv.take<int>(kNB);
+    c.F[s] = cv.take<double>(ns * ns);
+    c.BR[s] = cv.take<double>((size_t)2 * kNB * 2 * ns);
+    c.Z[s] = cv.take<double>(kNB * kNB);
+    c.prow[s] = cv.take<int>(ns);
+    c.slot[s] = cv.take<int>(ns);
     c.qrtmp[s] = cv.take<double>(N * ns);
     for (int p = 0; p < 2; ++p) {
       c.lb.ypart[s][p] = cv.take<double>(nt * ns);
@@ -160,8 +162,8 @@ pqmc_status validate(const pqmc_problem *p, const pqmc_update_opts *o) {
   if (p->n_sites < 1) return set_error(PQMC_EINVAL, "n_sites must be >= 1");
   if (p->n_up < 1 || p->n_dn < 1 || p->n_up > p->n_sites || p->n_dn > p->n_sites)
     return set_error(PQMC_EINVAL, "need 1 <= n_up, n_dn <= n_sites");
-  if (p->n_up > 2048 || p->n_dn > 2048)
-    return set_error(PQMC_EINVAL, "particle numbers above 2048 are not supported");
+  if (p->n_up > 1024 || p->n_dn > 1024)
+    return set_error(PQMC_EINVAL, "particle numbers above 1024 are not supported");
   if (!p->hopping || !p->trial_up || !p->trial_dn) return set_error(PQMC_EINVAL, "null input");
   if (!(p->dtau > 0) || !std::isfinite(p->dtau)) return set_error(PQMC_EINVAL, "dtau must be > 0");
   if (!std::isfinite(p->U)) return set_error(PQMC_EINVAL, "U must be finite");
@@ -256,7 +258,7 @@ int orthonormalize(pqmc_ctx &c, double *const A[2], double *const dst[2]) {
     for (int s = 0; s < 2; ++s) {
       const int n = c.Ns[s];
       PQ_HIP_CHECK(set_identity_block(c.E[s], nullptr, 2 * n, n, n, c.st));
-      es[s] = ElimSpin{c.E[s], 2L * n, n, 2 * n, c.Z[s], c.piv[s], c.R2[s]};
+      es[s] = ElimSpin{c.E[s], 2L * n, n, 2 * n, c.Z[s], c.prow[s], c.slot[s], c.BR[s], c.F[s]};
     }
     if (same) {
       PQ_HIP_CHECK(chol_eliminate(es, 2, c.stats, c.st));
@@ -267,7 +269,7 @@ int orthonormalize(pqmc_ctx &c, double *const A[2], double *const dst[2]) {
     GemmBatch qb{};
     for (int s = 0; s < 2; ++s) {
       const int n = c.Ns[s];
-      qb.d[qb.count++] = gemm_desc(src[s], n, c.E[s] + n, 2 * n, out[s], n, c.N, n, n);
+      qb.d[qb.count++] = gemm_desc(src[s], n, c.F[s], n, out[s], n, c.N, n, n);
     }
     PQ_HIP_CHECK(gemm(qb, false, true, c.st));
   }
@@ -286,17 +288,15 @@ int refresh_T(pqmc_ctx &c) {
   for (int s = 0; s < 2; ++s) {
     const int n = c.Ns[s];
     PQ_HIP_CHECK(set_identity_block(c.E[s], nullptr, 2 * n, n, n, c.st));
-    es[s] = ElimSpin{c.E[s], 2L * n, n, 2 * n, c.Z[s], c.piv[s], c.R2[s]};
+    es[s] = ElimSpin{c.E[s], 2L * n, n, 2 * n, c.Z[s], c.prow[s], c.slot[s], c.BR[s], c.F[s]};
   }
   if (c.Ns[0] == c.Ns[1]) {
-    PQ_HIP_CHECK(gj_invert(es, 2, c.stats, c.st));
+    PQ_HIP_CHECK(gj_invert(es, 2, c.stats, c.T, c.Ns[0], c.st));
   } else {
-    PQ_HIP_CHECK(gj_invert(&es[0], 1, c.stats, c.st));
-    PQ_HIP_CHECK(gj_invert(&es[1], 1, c.stats, c.st));
-  }
-  for (int s = 0; s < 2; ++s) {
-    const int n = c.Ns[s];
-    PQ_HIP_CHECK(copy_matrix(c.E[s] + n, nullptr, 2 * n, c.T[s], nullptr, n, n, n, c.st));
+    for (int s = 0; s < 2; ++s) {
+      double *const out[2] = {c.T[s], c.T[s]};
+      PQ_HIP_CHECK(gj_invert(&es[s], 1, c.stats, out, c.Ns[s], c.st));
+    }
   }
   return PQMC_OK;
 }

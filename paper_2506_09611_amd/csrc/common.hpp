@@ -3,7 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-typedef double dbl4 __attribute__((ext_vector_type(4)));
+#include "mfma.hpp"
 
 namespace pq {
 

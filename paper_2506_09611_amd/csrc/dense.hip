@@ -1,276 +1,385 @@
 // Dense FP64 linear algebra for the stabilisation step (Sec. II B): the
 // inverse T = (U_L U_R)^{-1} and the re-orthonormalisation of U_R / U_L.
 //
-// Both run one blocked elimination engine over an augmented row-major
-// matrix E = [M | I] (n x 2n), panel width kNB = 32:
-//   * Gauss-Jordan with partial pivoting (T): a single workgroup factors the
-//     panel E[kb:n, kb:kb+nb] with row pivoting on a private register copy,
-//     returning the pivots and Z = inverse of the pivoted diagonal block;
-//     the pivots are applied to whole rows, the block row is replaced by
-//     Z * (block row), and every other row gets a rank-nb GEMM update.
-//     The right half ends as M^{-1}.
-//   * Cholesky-normalised forward elimination (QR): the diagonal block's
-//     Cholesky factor C gives Z1 = C^{-1} for the block row and
-//     Z2 = Z1^T Z1 for the rank-nb update of the rows below.  E = [S | I]
-//     with S = A^T A ends as [R | R^{-T}], so Q = A R^{-1} (CholQR).
+// Both run one blocked elimination over an augmented row-major matrix
+// E = [M | I] (n x 2n, n <= 1024), panel width kNB = 32, with two launches
+// per panel:
+//   * a panel kernel factors the panel's pivot block and returns
+//     Z = (pivot block)^{-1} (Gauss-Jordan) or the inverse Cholesky factor;
+//   * an update kernel tiles the live columns: it forms the new block rows
+//     Z E[block rows, :] on MFMA and subtracts their rank-kNB product from
+//     every other row, reading each tile of E once.
+// Gauss-Jordan (T = M^{-1}) pivots implicitly: the panel kernel picks, for
+// each column, the largest remaining entry among rows not yet used as pivots
+// (partial pivoting on the Schur complement), and records the chosen rows;
+// no rows are moved.  The new block rows of a pass go to a side buffer
+// (the rows are still being read by other workgroups of that pass) and are
+// taken from there by the next pass, so each pass updates E in place.  At
+// the end the right half holds P M^{-1} for the recorded pivot order P, and
+// T is gathered row by row.
+// Cholesky-normalised forward elimination (CholQR) on E = [S | I], S SPD:
+// the diagonal block's Cholesky factor C gives the block row C^{-1} E_b and
+// the update of the rows below with multipliers E[i, panel] C^{-T}.  The
+// right half ends as R^{-T} with S = R^T R, collected block row by block
+// row in F, so that Q = A R^{-1} = A F^T.
 #include "engine.hpp"
 
 namespace pq {
 
 namespace {
 
-constexpr int kPanelThreads = 1024;
-// rows per row group (template): panels up to 32 * MAXQ rows
-
-struct PanelArgs {
+struct ElimArgs {
   ElimSpin s[2];
-  int nspin;
-  int kb;
+  int kb, nb, pass;
   unsigned long long *stats;
 };
 
-// LU with partial pivoting of the panel E[kb:n, kb:kb+nb] (register copy),
-// then Z = U11^{-1} L11^{-1}.  Thread (rg, c): column c, rows rg + 32 q.
-template <int kPanelMaxQ>
-__global__ __launch_bounds__(kPanelThreads) void gj_panel_kernel(PanelArgs a) {
-  const ElimSpin &S = a.s[blockIdx.x];
-  const int kb = a.kb;
-  const int nb = min(kNB, S.n - kb);
-  const int R = S.n - kb;
-  const int t = threadIdx.x, c = t & 31, rg = t >> 5;
-  const int lane = t & 63;
-  double v[kPanelMaxQ];
-#pragma unroll
-  for (int q = 0; q < kPanelMaxQ; ++q) {
-    const int r = rg + 32 * q;
-    v[q] = (r < R && c < nb) ? S.E[(long)(kb + r) * S.ld + kb + c] : 0.0;
-  }
-  __shared__ double red_v[32];
-  __shared__ int red_i[32];
-  __shared__ double rowj[32], rowp[32];
-  __shared__ int s_p;
-  __shared__ double LU[32][33];
-  __shared__ double Li[32][33], Ui[32][33];
+// Value of v in lane src (src uniform).
+__device__ __forceinline__ double lane_value(double v, int src) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, src);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), src);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
 
-  for (int j = 0; j < nb; ++j) {
-    if (c == j) {
-      double best = -1.0;
-      int bi = -1;
-#pragma unroll
-      for (int q = 0; q < kPanelMaxQ; ++q) {
-        const int r = rg + 32 * q;
-        if (r >= j && r < R) {
-          const double av = fabs(v[q]);
-          if (av > best) { best = av; bi = r; }
-        }
-      }
-      red_v[rg] = best;
-      red_i[rg] = bi;
+// Inverse of the kNB x kNB matrix LU = L U (unit lower L, upper U, both in
+// LU; rows and columns >= nb padded with the identity) into Z (nb x nb
+// written, row-major, leading dimension kNB).  Threads 0..31 invert L by
+// forward substitution and threads 64..95 invert U by back substitution,
+// one column each (the partial results stay in LDS), then all threads form
+// U^{-1} L^{-1}.
+__device__ void lu_inverse_to(const double (*LU)[kNB + 1], double (*Li)[kNB + 1],
+                              double (*Ui)[kNB + 1], int nb, double *Z) {
+  const int t = threadIdx.x;
+  if (t < kNB) {
+    const int col = t;
+    for (int i = 0; i < kNB; ++i) {
+      double s = (i == col) ? 1.0 : 0.0;
+#pragma unroll 4
+      for (int m = 0; m < i; ++m) s -= LU[i][m] * Li[m][col];
+      Li[i][col] = s;
     }
-    __syncthreads();
-    // argmax over the 32 row groups in wave 0 (ties: smallest row)
-    if (t < 64) {
-      double bv = (t < 32 && red_i[t] >= 0) ? red_v[t] : -1.0;
-      int bix = (t < 32 && red_i[t] >= 0) ? red_i[t] : 0x7fffffff;
+  } else if (t >= 64 && t < 64 + kNB) {
+    const int col = t - 64;
+    for (int i = kNB - 1; i >= 0; --i) {
+      double s = (i == col) ? 1.0 : 0.0;
+#pragma unroll 4
+      for (int m = i + 1; m < kNB; ++m) s -= LU[i][m] * Ui[m][col];
+      const double dd = LU[i][i];
+      Ui[i][col] = (dd != 0.0) ? s / dd : 0.0;
+    }
+  }
+  __syncthreads();
+  for (int e = t; e < kNB * kNB; e += blockDim.x) {
+    const int i = e / kNB, cc = e % kNB;
+    double s = 0.0;
+#pragma unroll 8
+    for (int m = 0; m < kNB; ++m) s += Ui[i][m] * Li[m][cc];
+    if (i < nb && cc < nb) Z[i * kNB + cc] = s;
+  }
+}
+
+// Gauss-Jordan panel E[:, kb:kb+nb) with implicit partial pivoting.  Thread
+// r holds row r's panel entries; per column the largest |entry| among the
+// rows not yet used as pivots wins (ties: the smaller row index).  Each
+// wave's candidate writes its whole row to LDS with its key, so one barrier
+// per column suffices.  Outputs: prow[kb + j] = pivot row of column kb + j,
+// slot[row] = kb + j, Z = (E[prow, kb:kb+nb))^{-1}.
+constexpr int kLuThreads = 1024;
+constexpr int kLuWaves = kLuThreads / 64;
+
+__global__ __launch_bounds__(kLuThreads) void lu_panel_kernel(ElimArgs a) {
+  const ElimSpin &S = a.s[blockIdx.x];
+  const int kb = a.kb, nb = a.nb, n = S.n;
+  const int r = threadIdx.x, lane = r & 63, wave = r >> 6;
+  __shared__ double rowbuf[2][kLuWaves][kNB];
+  __shared__ double cval[2][kLuWaves];
+  __shared__ int crow[2][kLuWaves];
+  __shared__ double LU[kNB][kNB + 1], Li[kNB][kNB + 1], Ui[kNB][kNB + 1];
+  __shared__ int bad;
+  if (r == 0) bad = 0;
+  bool cand = r < n && S.slot[r] < 0;
+  double v[kNB];
+#pragma unroll
+  for (int c = 0; c < kNB; ++c) v[c] = (cand && c < nb) ? S.E[(long)r * S.ld + kb + c] : 0.0;
+  int mypos = -1;
+#pragma clang loop unroll(full)
+  for (int j = 0; j < kNB; ++j) {
+    if (j < nb) {   // uniform
+      const int par = j & 1;
+      double key = -1.0;
+      if (cand) key = isnan(v[j]) ? 0.0 : fabs(v[j]);
+      int kr = cand ? r : 0x7fffffff;
 #pragma unroll
       for (int o = 32; o > 0; o >>= 1) {
-        const double ov = __shfl_xor(bv, o, 64);
-        const int oi = __shfl_xor(bix, o, 64);
-        const bool take = (ov > bv) || (ov == bv && oi < bix);
-        bv = take ? ov : bv;
-        bix = take ? oi : bix;
+        const double ok = __shfl_xor(key, o, 64);
+        const int orr = __shfl_xor(kr, o, 64);
+        const bool take = (ok > key) || (ok == key && orr < kr);
+        key = take ? ok : key;
+        kr = take ? orr : kr;
       }
-      if (t == 0) {
-        int bi = bix;
-        if (!(bv > 0.0) || bi == 0x7fffffff) {
-          a.stats[kStError] |= kErrSingular;
-          bi = j;
-        }
-        s_p = bi;
-        S.piv[j] = kb + bi;
-      }
-    }
-    __syncthreads();
-    const int p = s_p;
-    // swap local rows j (row group j, q = 0) and p (row group p % 32, q = p / 32)
-    if (rg == j) rowj[c] = v[0];
-    if (rg == (p & 31)) {
+      if (r == kr) {
 #pragma unroll
-      for (int q = 0; q < kPanelMaxQ; ++q)
-        if (q == (p >> 5)) rowp[c] = v[q];
-    }
-    __syncthreads();
-    if (p != j) {
-      if (rg == (p & 31)) {
-#pragma unroll
-        for (int q = 0; q < kPanelMaxQ; ++q)
-          if (q == (p >> 5)) v[q] = rowj[c];
+        for (int c = 0; c < kNB; ++c) rowbuf[par][wave][c] = v[c];
       }
-      if (rg == j) v[0] = rowp[c];
-    }
-    // pivot row is now rowp (old row p)
-    const double d = rowp[j];
-    const double pr = rowp[c];
+      if (lane == 0) {
+        cval[par][wave] = key;
+        crow[par][wave] = kr;
+      }
+      __syncthreads();
+      double best = -1.0;
+      int brow = 0x7fffffff, bw = 0;
 #pragma unroll
-    for (int q = 0; q < kPanelMaxQ; ++q) {
-      const int r = rg + 32 * q;
-      const double arj = __shfl(v[q], (lane & 32) | j, 64);
-      if (r > j && r < R) {
-        const double l = (d != 0.0) ? arj / d : 0.0;
-        if (c > j) v[q] -= l * pr;
-        else if (c == j) v[q] = l;
+      for (int w = 0; w < kLuWaves; ++w) {
+        const double kv = cval[par][w];
+        const int kr2 = crow[par][w];
+        const bool take = (kv > best) || (kv == best && kr2 < brow);
+        best = take ? kv : best;
+        brow = take ? kr2 : brow;
+        bw = take ? w : bw;
+      }
+      bw = __builtin_amdgcn_readfirstlane(bw);
+      const double d = rowbuf[par][bw][j];
+      if (r == 0 && !(best > 0.0)) bad = 1;
+      const double invd = (best > 0.0) ? 1.0 / d : 0.0;
+      if (r == brow) {
+        cand = false;
+        mypos = j;
+      }
+      if (cand) {
+        const double l = v[j] * invd;
+#pragma unroll
+        for (int c = j + 1; c < kNB; ++c) v[c] -= l * rowbuf[par][bw][c];
+        v[j] = l;
       }
     }
-    __syncthreads();
   }
-  // L11 (unit lower) and U11 sit in rows 0..nb-1 = row groups 0..nb-1, q = 0.
-  if (rg < 32) LU[rg][c] = (rg < nb && c < nb) ? v[0] : (rg == c ? 1.0 : 0.0);
-  __syncthreads();
-  if (t < 32) {
-    const int col = t;
-    // column col of L^{-1} (unit lower) by forward substitution
-    double x[32];
+  if (mypos >= 0) {
 #pragma unroll
-    for (int i = 0; i < 32; ++i) {
-      double s = (i == col) ? 1.0 : 0.0;
-#pragma unroll
-      for (int m = 0; m < 32; ++m)
-        if (m < i) s -= LU[i][m] * x[m];
-      x[i] = s;
-    }
-#pragma unroll
-    for (int i = 0; i < 32; ++i) Li[i][col] = x[i];
-  } else if (t >= 64 && t < 96) {
-    const int col = t - 64;
-    // column col of U^{-1} by back substitution
-    double x[32];
-#pragma unroll
-    for (int ii = 0; ii < 32; ++ii) {
-      const int i = 31 - ii;
-      double s = (i == col) ? 1.0 : 0.0;
-#pragma unroll
-      for (int m = 0; m < 32; ++m)
-        if (m > i) s -= LU[i][m] * x[m];
-      const double dd = LU[i][i];
-      x[i] = (dd != 0.0) ? s / dd : 0.0;
-    }
-#pragma unroll
-    for (int i = 0; i < 32; ++i) Ui[i][col] = x[i];
+    for (int c = 0; c < kNB; ++c) LU[mypos][c] = v[c];
+    S.slot[r] = kb + mypos;
+    S.prow[kb + mypos] = r;
   }
   __syncthreads();
-  {
-    const int i = t >> 5, cc = t & 31;
-    double s = 0.0;
+  if (r >= nb && r < kNB) {
 #pragma unroll
-    for (int m = 0; m < 32; ++m) s += Ui[i][m] * Li[m][cc];
-    if (i < nb && cc < nb) {
-      S.Z[i * kNB + cc] = s;
-      S.Z[kNB * kNB + i * kNB + cc] = s;
-    }
+    for (int c = 0; c < kNB; ++c) LU[r][c] = (r == c) ? 1.0 : 0.0;
   }
+  if (r < nb) {
+#pragma unroll
+    for (int c = 0; c < kNB; ++c)
+      if (c >= nb) LU[r][c] = 0.0;
+  }
+  __syncthreads();
+  if (r == 0 && bad) atomicOr(&a.stats[kStError], (unsigned long long)kErrSingular);
+  lu_inverse_to(LU, Li, Ui, nb, S.Z);
 }
 
-// Cholesky of the nb x nb diagonal block (current Schur complement), then
-// Z1 = C^{-1} (lower) and Z2 = Z1^T Z1.
-__global__ __launch_bounds__(kPanelThreads) void chol_panel_kernel(PanelArgs a) {
+// Cholesky panel: C C^T = E[kb:kb+nb, kb:kb+nb) (the current Schur
+// complement), Z = C^{-1} (lower).  One wave, lane i holds row i.
+__global__ __launch_bounds__(64) void chol_panel_kernel(ElimArgs a) {
   const ElimSpin &S = a.s[blockIdx.x];
-  const int kb = a.kb;
-  const int nb = min(kNB, S.n - kb);
-  const int t = threadIdx.x, i = t >> 5, j = t & 31;
-  __shared__ double A[32][33];
-  __shared__ double Ci[32][33];
-  __shared__ int bad;
-  if (t == 0) bad = 0;
-  A[i][j] = (i < nb && j < nb) ? S.E[(long)(kb + i) * S.ld + kb + j] : (i == j ? 1.0 : 0.0);
-  __syncthreads();
-  for (int k = 0; k < 32; ++k) {
-    if (t == 0) {
-      const double d = A[k][k];
-      if (!(d > 0.0)) { bad = 1; A[k][k] = 1.0; }
-      else A[k][k] = sqrt(d);
-    }
+  const int kb = a.kb, nb = a.nb;
+  const int i = threadIdx.x;
+  __shared__ double lcol[64];
+  __shared__ double C[kNB][kNB + 1], X[kNB][kNB + 1];
+  double v[kNB];
+#pragma unroll
+  for (int c = 0; c < kNB; ++c)
+    v[c] = (i < nb && c < nb) ? S.E[(long)(kb + i) * S.ld + kb + c] : (i == c ? 1.0 : 0.0);
+  bool bad = false;
+#pragma unroll
+  for (int k = 0; k < kNB; ++k) {
+    const double dk = lane_value(v[k], k);
+    const bool ok = dk > 0.0;
+    bad = bad || !ok;
+    const double ck = ok ? sqrt(dk) : 1.0;
+    const double l = (i > k) ? v[k] / ck : 0.0;
+    if (i == k) v[k] = ck;
+    if (i > k) v[k] = l;
+    lcol[i] = l;
     __syncthreads();
-    if (j == k && i > k) A[i][k] /= A[k][k];
-    __syncthreads();
-    if (i > k && j > k && j <= i) A[i][j] -= A[i][k] * A[j][k];
+#pragma unroll
+    for (int j = k + 1; j < kNB; ++j)
+      if (i >= j) v[j] -= l * lcol[j];
     __syncthreads();
   }
-  if (t == 0 && bad) a.stats[kStError] |= kErrSingular;
-  if (t < 32) {
-    const int col = t;
-    double x[32];
+  if (i < kNB) {
 #pragma unroll
-    for (int r = 0; r < 32; ++r) {
-      double s = (r == col) ? 1.0 : 0.0;
-#pragma unroll
-      for (int m = 0; m < 32; ++m)
-        if (m < r) s -= A[r][m] * x[m];
-      x[r] = s / A[r][r];
-    }
-#pragma unroll
-    for (int r = 0; r < 32; ++r) Ci[r][col] = x[r];
+    for (int c = 0; c < kNB; ++c) C[i][c] = (c <= i) ? v[c] : 0.0;
   }
   __syncthreads();
-  double z2 = 0.0;
-#pragma unroll
-  for (int m = 0; m < 32; ++m) z2 += Ci[m][i] * Ci[m][j];
-  if (i < nb && j < nb) {
-    S.Z[i * kNB + j] = (j <= i) ? Ci[i][j] : 0.0;
-    S.Z[kNB * kNB + i * kNB + j] = z2;
+  if (i == 0 && bad) atomicOr(&a.stats[kStError], (unsigned long long)kErrSingular);
+  // Z = C^{-1} by forward substitution, lane col forming column col
+  if (i < kNB) {
+    const int col = i;
+    for (int rr = 0; rr < kNB; ++rr) {
+      double s = (rr == col) ? 1.0 : 0.0;
+#pragma unroll 4
+      for (int m = 0; m < rr; ++m) s -= C[rr][m] * X[m][col];
+      X[rr][col] = s / C[rr][rr];
+    }
+  }
+  __syncthreads();
+  for (int e = i; e < kNB * kNB; e += 64) {
+    const int rr = e / kNB, cc = e % kNB;
+    if (rr < nb && cc < nb) S.Z[rr * kNB + cc] = X[rr][cc];
   }
 }
 
-struct ColArgs {
+// One 64 x 64 tile (rows r0.., live columns c0..) of a pass.
+//   block rows:  B = Z E[b, :]  (Gauss-Jordan: to the side buffer BR;
+//                Cholesky: their right-half entries to F)
+//   other rows:  E[i, :] -= L_i B with L_i = E[i, panel] (Gauss-Jordan) or
+//                E[i, panel] Z^T (Cholesky).
+// Gauss-Jordan rows that were block rows of the previous pass are read from
+// BR.  Rows < kb are final in the Cholesky mode and are not visited.
+template <bool GJ>
+__global__ __launch_bounds__(256) void elim_update_kernel(ElimArgs a) {
+  const ElimSpin &S = a.s[blockIdx.z];
+  const int n = S.n, w = S.w, kb = a.kb, nb = a.nb;
+  const long ld = S.ld;
+  const int r0 = (GJ ? 0 : kb) + blockIdx.x * 64;
+  const int c0 = kb + nb + blockIdx.y * 64;
+  const int c1 = GJ ? w : min(w, n + kb + nb);
+  if (r0 >= n || c0 >= c1) return;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6, wm = wave >> 1, wn = wave & 1;
+  constexpr int LZ = kNB + 1, LB = 65;
+  __shared__ double Zs[kNB * LZ];
+  __shared__ double EB[kNB * LB];
+  __shared__ double NBs[kNB * LB];
+  __shared__ double Lp[64 * LZ];
+  __shared__ const double *rsrc[64];
+  __shared__ int rcur[64];
+
+  if (t < 64) {
+    const int r = r0 + t;
+    const double *p = nullptr;
+    int cur = -1;
+    if (r < n) {
+      p = S.E + (long)r * ld;
+      if (GJ) {
+        const int sl = S.slot[r];
+        if (sl >= kb && sl < kb + nb) {
+          cur = sl - kb;
+        } else if (kb > 0 && sl >= kb - kNB && sl < kb) {
+          p = S.BR + (long)((a.pass - 1) & 1) * kNB * w + (long)(sl - (kb - kNB)) * w;
+        }
+      } else if (r < kb + nb) {
+        cur = r - kb;
+      }
+    }
+    rsrc[t] = p;
+    rcur[t] = cur;
+  }
+  for (int e = t; e < kNB * kNB; e += 256) {
+    const int i = e / kNB, j = e % kNB;
+    Zs[i * LZ + j] = (i < nb && j < nb) ? S.Z[i * kNB + j] : 0.0;
+  }
+  for (int e = t; e < kNB * 64; e += 256) {
+    const int b = e >> 6, cc = e & 63, c = c0 + cc;
+    double v = 0.0;
+    if (b < nb && c < c1) {
+      const int pr = GJ ? S.prow[kb + b] : kb + b;
+      v = S.E[(long)pr * ld + c];
+    }
+    EB[b * LB + cc] = v;
+  }
+  __syncthreads();
+  for (int e = t; e < 64 * kNB; e += 256) {
+    const int rr = e / kNB, b = e % kNB;
+    const double *p = rsrc[rr];
+    const double v = (p && b < nb) ? p[kb + b] : 0.0;
+    Lp[rr * LZ + b] = GJ ? -v : v;
+  }
+  dbl4 acc[2][2];
+#pragma unroll
+  for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int rr = acc_row(wm, mi, lane, j), c = c0 + acc_col(wn, ni, lane);
+        const double *p = rsrc[rr];
+        acc[mi][ni][j] = (p && c < c1) ? p[c] : 0.0;
+      }
+  __syncthreads();
+  // block rows B = Z EB: 2 x 4 tiles of 16 x 16, two per wave
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int tt = wave + 4 * u, mt = tt >> 2, ct = tt & 3;
+    const dbl4 q = mma16<false>(Zs + mt * 16 * LZ, LZ, EB + ct * 16, LB, kNB, lane);
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      NBs[(mt * 16 + (lane >> 4) + 4 * j) * LB + ct * 16 + (lane & 15)] = q[j];
+  }
+  if (!GJ) {
+    // multipliers -(E[i, panel] Z^T): wave w owns rows [16 w, 16 w + 16) and
+    // overwrites them after both of its tiles are formed
+    const dbl4 q0 = mma16<true>(Lp + wave * 16 * LZ, LZ, Zs, LZ, kNB, lane);
+    const dbl4 q1 = mma16<true>(Lp + wave * 16 * LZ, LZ, Zs + 16 * LZ, LZ, kNB, lane);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int rr = wave * 16 + (lane >> 4) + 4 * j;
+      Lp[rr * LZ + (lane & 15)] = -q0[j];
+      Lp[rr * LZ + 16 + (lane & 15)] = -q1[j];
+    }
+  }
+  __syncthreads();
+  lds_mma<false>(acc, Lp, LZ, NBs, LB, kNB, 64, 64, wm, wn, lane);
+#pragma unroll
+  for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int rr = acc_row(wm, mi, lane, j), cc = acc_col(wn, ni, lane);
+        const int r = r0 + rr, c = c0 + cc;
+        if (r >= n || c >= c1) continue;
+        const int cur = rcur[rr];
+        if (cur >= 0) {
+          const double v = NBs[cur * LB + cc];
+          if (GJ) S.BR[(long)(a.pass & 1) * kNB * w + (long)cur * w + c] = v;
+          else if (c >= n) S.F[(long)r * n + (c - n)] = v;
+        } else {
+          S.E[(long)r * ld + c] = acc[mi][ni][j];
+        }
+      }
+}
+
+// T[c, :] = (right half of row prow[c]) after the last Gauss-Jordan pass
+struct GatherArgs {
   ElimSpin s[2];
-  int kb;
-  int c0[2], c1[2];   // column range per spin
+  double *out[2];
+  long ldo;
+  int kb_last, pass_last;
 };
 
-// Apply the panel's row interchanges to columns [c0, c1).
-__global__ void swap_rows_kernel(ColArgs a) {
-  const ElimSpin &S = a.s[blockIdx.y];
-  const int col = a.c0[blockIdx.y] + blockIdx.x * blockDim.x + threadIdx.x;
-  if (col >= a.c1[blockIdx.y]) return;
-  const int nb = min(kNB, S.n - a.kb);
-  for (int j = 0; j < nb; ++j) {
-    const int p = S.piv[j];
-    const int r = a.kb + j;
-    if (p != r) {
-      const double x = S.E[(long)r * S.ld + col];
-      S.E[(long)r * S.ld + col] = S.E[(long)p * S.ld + col];
-      S.E[(long)p * S.ld + col] = x;
-    }
-  }
+__global__ void gj_gather_kernel(GatherArgs a) {
+  const ElimSpin &S = a.s[blockIdx.z];
+  const int n = S.n, c = blockIdx.y;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n || j >= n) return;
+  const int r = S.prow[c];
+  const int sl = S.slot[r];
+  const double *src = (sl >= a.kb_last)
+                          ? S.BR + (long)(a.pass_last & 1) * kNB * S.w + (long)(sl - a.kb_last) * S.w
+                          : S.E + (long)r * S.ld;
+  a.out[blockIdx.z][(long)c * a.ldo + j] = src[n + j];
 }
 
-// Block row: E[b, c] <- Z1 E[b, c]; optionally R2[:, c] <- Z2 E_old[b, c].
-__global__ void block_row_kernel(ColArgs a, int with_r2) {
-  const ElimSpin &S = a.s[blockIdx.y];
-  const int nb = min(kNB, S.n - a.kb);
-  __shared__ double z1[kNB * kNB], z2[kNB * kNB];
-  for (int e = threadIdx.x; e < kNB * kNB; e += blockDim.x) {
-    z1[e] = S.Z[e];
-    z2[e] = S.Z[kNB * kNB + e];
-  }
-  __syncthreads();
-  const int col = a.c0[blockIdx.y] + blockIdx.x * blockDim.x + threadIdx.x;
-  if (col >= a.c1[blockIdx.y]) return;
-  double x[kNB];
-#pragma unroll
-  for (int m = 0; m < kNB; ++m) x[m] = (m < nb) ? S.E[(long)(a.kb + m) * S.ld + col] : 0.0;
-#pragma unroll
-  for (int i = 0; i < kNB; ++i) {
-    if (i < nb) {
-      double s1 = 0.0, s2 = 0.0;
-#pragma unroll
-      for (int m = 0; m < kNB; ++m) {
-        s1 += z1[i * kNB + m] * x[m];
-        s2 += z2[i * kNB + m] * x[m];
-      }
-      S.E[(long)(a.kb + i) * S.ld + col] = s1;
-      if (with_r2) S.R2[(long)i * S.w + col] = s2;
-    }
-  }
+__global__ void fill_int_kernel(int *p0, int *p1, long count, int value) {
+  int *p = blockIdx.y ? p1 : p0;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+       e += (long)gridDim.x * blockDim.x)
+    p[e] = value;
+}
+
+__global__ void zero_kernel(double *p0, double *p1, long count) {
+  double *p = blockIdx.y ? p1 : p0;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+       e += (long)gridDim.x * blockDim.x)
+    p[e] = 0.0;
 }
 
 __global__ void set_identity_kernel(double *E0, double *E1, long ld, int n, int col0) {
@@ -297,88 +406,64 @@ __global__ void init_fields_kernel(int8_t *f, int M, int N, uint64_t k0, uint64_
   f[e] = (u < 0.5) ? (int8_t)1 : (int8_t)-1;
 }
 
-hipError_t run_elimination(const ElimSpin *s, int nspin, unsigned long long *stats,
-                           hipStream_t st, bool pivoted) {
-  const int n = s[0].n;
-  for (int i = 1; i < nspin; ++i)
-    if (s[i].n != n) return hipErrorInvalidValue;
-  for (int kb = 0; kb < n; kb += kNB) {
-    const int nb = min(kNB, n - kb);
-    PanelArgs pa{};
-    for (int i = 0; i < nspin; ++i) pa.s[i] = s[i];
-    pa.nspin = nspin;
-    pa.kb = kb;
-    pa.stats = stats;
-    ColArgs ca{};
-    for (int i = 0; i < nspin; ++i) ca.s[i] = s[i];
-    ca.kb = kb;
-    if (pivoted) {
-      const int rows = n - kb;
-      if (rows <= 32 * 8)
-        hipLaunchKernelGGL(gj_panel_kernel<8>, dim3(nspin), dim3(kPanelThreads), 0, st, pa);
-      else if (rows <= 32 * 16)
-        hipLaunchKernelGGL(gj_panel_kernel<16>, dim3(nspin), dim3(kPanelThreads), 0, st, pa);
-      else if (rows <= 32 * 32)
-        hipLaunchKernelGGL(gj_panel_kernel<32>, dim3(nspin), dim3(kPanelThreads), 0, st, pa);
-      else
-        hipLaunchKernelGGL(gj_panel_kernel<64>, dim3(nspin), dim3(kPanelThreads), 0, st, pa);
-      // interchange whole rows: panel and everything right of it
-      int maxc = 0;
-      for (int i = 0; i < nspin; ++i) {
-        ca.c0[i] = kb;
-        ca.c1[i] = s[i].w;
-        maxc = max(maxc, ca.c1[i] - ca.c0[i]);
-      }
-      hipLaunchKernelGGL(swap_rows_kernel, dim3((maxc + 255) / 256, nspin), dim3(256), 0, st, ca);
-    } else {
-      hipLaunchKernelGGL(chol_panel_kernel, dim3(nspin), dim3(kPanelThreads), 0, st, pa);
-    }
-    // columns carrying nonzeros of the block row: without pivoting, the
-    // right half is lower triangular so far; with pivoting, everything.
-    int maxc = 0;
-    for (int i = 0; i < nspin; ++i) {
-      ca.c0[i] = kb + nb;
-      ca.c1[i] = pivoted ? s[i].w : min(s[i].w, n + kb + nb);
-      maxc = max(maxc, ca.c1[i] - ca.c0[i]);
-    }
-    if (maxc > 0)
-      hipLaunchKernelGGL(block_row_kernel, dim3((maxc + 127) / 128, nspin), dim3(128), 0, st, ca,
-                         pivoted ? 0 : 1);
-    GemmBatch gb{};
-    gb.count = 0;
-    for (int i = 0; i < nspin; ++i) {
-      const ElimSpin &S = s[i];
-      const int c0 = kb + nb, c1 = ca.c1[i];
-      if (c1 <= c0) continue;
-      const double *R2 = pivoted ? S.E + (long)kb * S.ld : S.R2;
-      const long ldr = pivoted ? S.ld : S.w;
-      // rows below the block
-      if (kb + nb < n) {
-        gb.d[gb.count++] = gemm_desc(S.E + (long)(kb + nb) * S.ld + kb, S.ld, R2 + c0, ldr,
-                                     S.E + (long)(kb + nb) * S.ld + c0, S.ld, n - kb - nb,
-                                     c1 - c0, nb, -1.0, 1.0);
-      }
-      // rows above the block (Gauss-Jordan only)
-      if (pivoted && kb > 0) {
-        gb.d[gb.count++] = gemm_desc(S.E + kb, S.ld, R2 + c0, ldr, S.E + c0, S.ld, kb, c1 - c0,
-                                     nb, -1.0, 1.0);
-      }
-    }
-    hipError_t e = gemm(gb, false, false, st);
-    if (e != hipSuccess) return e;
-  }
-  return hipGetLastError();
-}
-
 }  // namespace
 
-hipError_t gj_invert(const ElimSpin *s, int nspin, unsigned long long *stats, hipStream_t st) {
-  return run_elimination(s, nspin, stats, st, true);
+hipError_t gj_invert(const ElimSpin *s, int nspin, unsigned long long *stats,
+                     double *const out[2], long ldo, hipStream_t st) {
+  const int n = s[0].n;
+  for (int i = 1; i < nspin; ++i)
+    if (s[i].n != n || s[i].w != s[0].w) return hipErrorInvalidValue;
+  if (n < 1 || n > kLuThreads || nspin < 1 || nspin > 2) return hipErrorInvalidValue;
+  const int w = s[0].w;
+  hipLaunchKernelGGL(fill_int_kernel, dim3((n + 255) / 256, nspin), dim3(256), 0, st, s[0].slot,
+                     nspin > 1 ? s[1].slot : s[0].slot, (long)n, -1);
+  ElimArgs ea{};
+  for (int i = 0; i < nspin; ++i) ea.s[i] = s[i];
+  ea.stats = stats;
+  int pass = 0, kb = 0;
+  for (; kb < n; kb += kNB, ++pass) {
+    ea.kb = kb;
+    ea.nb = min(kNB, n - kb);
+    ea.pass = pass;
+    hipLaunchKernelGGL(lu_panel_kernel, dim3(nspin), dim3(kLuThreads), 0, st, ea);
+    const int cols = w - kb - ea.nb;
+    hipLaunchKernelGGL(elim_update_kernel<true>, dim3((n + 63) / 64, (cols + 63) / 64, nspin),
+                       dim3(256), 0, st, ea);
+  }
+  GatherArgs ga{};
+  for (int i = 0; i < nspin; ++i) {
+    ga.s[i] = s[i];
+    ga.out[i] = out[i];
+  }
+  ga.ldo = ldo;
+  ga.kb_last = kb - kNB;
+  ga.pass_last = pass - 1;
+  hipLaunchKernelGGL(gj_gather_kernel, dim3((n + 255) / 256, n, nspin), dim3(256), 0, st, ga);
+  return hipGetLastError();
 }
 
 hipError_t chol_eliminate(const ElimSpin *s, int nspin, unsigned long long *stats,
                           hipStream_t st) {
-  return run_elimination(s, nspin, stats, st, false);
+  const int n = s[0].n;
+  for (int i = 1; i < nspin; ++i)
+    if (s[i].n != n || s[i].w != s[0].w) return hipErrorInvalidValue;
+  if (n < 1 || nspin < 1 || nspin > 2 || s[0].w < 2 * n) return hipErrorInvalidValue;
+  const int w = s[0].w;
+  hipLaunchKernelGGL(zero_kernel, dim3(256, nspin), dim3(256), 0, st, s[0].F,
+                     nspin > 1 ? s[1].F : s[0].F, (long)n * n);
+  ElimArgs ea{};
+  for (int i = 0; i < nspin; ++i) ea.s[i] = s[i];
+  ea.stats = stats;
+  for (int kb = 0, pass = 0; kb < n; kb += kNB, ++pass) {
+    ea.kb = kb;
+    ea.nb = min(kNB, n - kb);
+    ea.pass = pass;
+    hipLaunchKernelGGL(chol_panel_kernel, dim3(nspin), dim3(64), 0, st, ea);
+    const int cols = min(w, n + kb + ea.nb) - kb - ea.nb;
+    hipLaunchKernelGGL(elim_update_kernel<false>,
+                       dim3((n - kb + 63) / 64, (cols + 63) / 64, nspin), dim3(256), 0, st, ea);
+  }
+  return hipGetLastError();
 }
 
 hipError_t set_identity_block(double *E0, double *E1, long ld, int n, int col0, hipStream_t st) {

@@ -42,18 +42,21 @@ hipError_t gemm(const GemmBatch &b, bool transA, bool transB, hipStream_t st);
 // ------------------------------------------------------------- dense LA
 constexpr int kNB = 32;   // panel width of the blocked eliminations
 struct ElimSpin {
-  double *E;       // n x w augmented matrix, row-major, leading dim ld
+  double *E;       // n x w augmented matrix [M | I], row-major, leading dim ld, w = 2 n
   long ld;
   int n, w;
-  double *Z;       // 2 * kNB * kNB scratch: Z1 then Z2
-  int *piv;        // kNB
-  double *R2;      // kNB x w scratch (Cholesky mode)
+  double *Z;       // kNB x kNB: inverse of the current panel's pivot block
+  int *prow;       // n: pivot row chosen for column c (Gauss-Jordan)
+  int *slot;       // n: pivot column of row r, -1 while unused (Gauss-Jordan)
+  double *BR;      // 2 x kNB x w: new block rows of the last two passes (Gauss-Jordan)
+  double *F;       // n x n: rows of R^{-T} (Cholesky)
 };
-// In-place Gauss-Jordan inversion with partial pivoting inside each panel:
-// E = [A | I] (n x 2n) becomes [* | A^{-1}].
-hipError_t gj_invert(const ElimSpin *s, int nspin, unsigned long long *stats, hipStream_t st);
+// out = M^{-1} (n x n, leading dim ldo) for E = [M | I], n <= 1024, by
+// Gauss-Jordan elimination with partial pivoting.  E is overwritten.
+hipError_t gj_invert(const ElimSpin *s, int nspin, unsigned long long *stats,
+                     double *const out[2], long ldo, hipStream_t st);
 // Forward elimination normalised by the Cholesky factor of each diagonal
-// block: E = [S | I] with S SPD becomes [R | R^{-T}], S = R^T R.
+// block on E = [S | I], S SPD: F receives R^{-T}, S = R^T R.
 hipError_t chol_eliminate(const ElimSpin *s, int nspin, unsigned long long *stats,
                           hipStream_t st);
 hipError_t set_identity_block(double *E0, double *E1, long ld, int n, int col0, hipStream_t st);

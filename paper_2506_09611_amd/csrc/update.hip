@@ -1132,60 +1132,6 @@ struct TileArgs {
 
 constexpr int kLdt = 65;   // padded LDS row stride
 
-// acc (this wave's 32x32 quadrant of a 64x64 result) += A (64 x K) B (K x 64)
-// with A, B in LDS; TB: B(k, j) = Bm[j * ldb + k].  Quadrants whose rows
-// are >= mrows or columns >= ncols are skipped.
-template <bool TB>
-__device__ __forceinline__ void lds_mma(dbl4 (&acc)[2][2], const double *A, int lda,
-                                        const double *B, int ldb, int K, int mrows, int ncols,
-                                        int wm, int wn, int lane) {
-  if (wm * 32 >= mrows || wn * 32 >= ncols) return;
-  const int i0 = wm * 32 + (lane & 15);
-  const int j0 = wn * 32 + (lane & 15);
-  for (int k0 = 0; k0 < K; k0 += 4) {
-    const int kk = k0 + (lane >> 4);
-    const bool kv = kk < K;
-    const double a0 = kv ? A[i0 * lda + kk] : 0.0;
-    const double a1 = kv ? A[(i0 + 16) * lda + kk] : 0.0;
-    double b0, b1;
-    if (!TB) {
-      b0 = kv ? B[kk * ldb + j0] : 0.0;
-      b1 = kv ? B[kk * ldb + j0 + 16] : 0.0;
-    } else {
-      b0 = kv ? B[j0 * ldb + kk] : 0.0;
-      b1 = kv ? B[(j0 + 16) * ldb + kk] : 0.0;
-    }
-    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
-  }
-}
-
-// One 16x16 tile: returns A (16 x K) B (K x 16), K a multiple of 4, with
-// A(i, k) = Am[i * lda + k] and B(k, j) = Bm[k * ldb + j] (TB: Bm[j * ldb + k]).
-template <bool TB>
-__device__ __forceinline__ dbl4 mma16(const double *Am, int lda, const double *Bm, int ldb,
-                                      int K, int lane) {
-  dbl4 acc = {0.0, 0.0, 0.0, 0.0};
-  const int i = lane & 15, kq = lane >> 4;
-  for (int k0 = 0; k0 < K; k0 += 4) {
-    const int k = k0 + kq;
-    const double a = Am[i * lda + k];
-    const double b = TB ? Bm[i * ldb + k] : Bm[k * ldb + i];
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
-  }
-  return acc;
-}
-
-// (row, col) of accumulator element [mi][ni][j] in the 64x64 tile
-__device__ __forceinline__ int acc_row(int wm, int mi, int lane, int j) {
-  return wm * 32 + mi * 16 + (lane >> 4) + 4 * j;
-}
-__device__ __forceinline__ int acc_col(int wn, int ni, int lane) {
-  return wn * 32 + ni * 16 + (lane & 15);
-}
-
 // KP: kmax rounded up to a multiple of 16 (16, 32 or 64).
 template <int KP>
 __global__ __launch_bounds__(256) void group_tile_kernel(TileArgs a) {
