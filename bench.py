@@ -58,10 +58,15 @@ def kernel_work(p, cls, scheme, k, b, acc):
     raise KeyError(cls)
 
 
-def roofline(p, scheme, k, b, acc, ktimes):
-    """Roofline of the kernel class with the largest device time."""
-    cls, (tot, cnt) = max(((c, v) for c, v in ktimes.items() if v[1] > 0),
-                          key=lambda cv: cv[1][0])
+def roofline(p, scheme, k, b, acc, ktimes, cls=None):
+    """Roofline of one kernel class (default: the one with the largest device
+    time), from its average launch duration on the library's stream."""
+    live = {c: v for c, v in ktimes.items() if v[1] > 0}
+    if not live or (cls is not None and cls not in live):
+        return None
+    if cls is None:
+        cls = max(live, key=lambda c: live[c][0])
+    tot, cnt = live[cls]
     avg = tot / cnt
     flops, nbytes, bound = kernel_work(p, cls, scheme, k, b, acc)
     if bound == "hbm":
@@ -160,6 +165,8 @@ def main():
     ch.forward_window(args.ktime_window)
     ktimes = ch.kernel_times()
     roof = roofline(p, args.scheme, args.k, args.b, acc, ktimes)
+    # the rank-n_A flush with the next group's panels, on MFMA (delayed / block)
+    roof_flush = roofline(p, args.scheme, args.k, args.b, acc, ktimes, "tile")
     log(f"{args.scheme}: {dt / args.steps:.3f} s/sweep, {value:.4g} fu/s, update-only {upd:.4g}")
     log("kernel times", {c: (round(v[0] * 1e3, 3), v[1]) for c, v in ktimes.items()})
     result = {
@@ -188,6 +195,7 @@ def main():
                               "propagation": agg["t_prop_s"] / args.steps,
                               "stabilization": agg["t_stab_s"] / args.steps},
         "roofline": roof,
+        "roofline_flush": roof_flush,
         "kernel_avg_us": {c: 1e6 * v[0] / v[1] for c, v in ktimes.items() if v[1] > 0},
     }
     ch.close()

@@ -51,7 +51,6 @@ struct pqmc_ctx {
   double *T[2] = {};
   double *E[2] = {}, *F[2] = {}, *BR[2] = {}, *Z[2] = {};
   int *prow[2] = {}, *slot[2] = {};
-  double *qrtmp[2] = {};
   LocalBufs lb{};
   GroupBufs gb{};
   unsigned long long *stats = nullptr;
@@ -123,7 +122,6 @@ void layout(pqmc_ctx &c, char *base, size_t *bytes) {
     c.Z[s] = cv.take<double>(kNB * kNB);
     c.prow[s] = cv.take<int>(ns);
     c.slot[s] = cv.take<int>(ns);
-    c.qrtmp[s] = cv.take<double>(N * ns);
     for (int p = 0; p < 2; ++p) {
       c.lb.ypart[s][p] = cv.take<double>(nt * ns);
       c.lb.tpart[s][p] = cv.take<double>(nt * ns);
@@ -242,37 +240,37 @@ int sync_check(pqmc_ctx &c) {
   return PQMC_OK;
 }
 
-// CholQR2 of the columns of A (N x Ns per spin) into dst.
+// CholQR of the columns of A (N x Ns per spin) into dst: S = A^T A = R^T R,
+// dst = A R^{-1}.  One pass suffices here: the Green's function depends on
+// U_R (U_L) only through its column (row) space, which A R^{-1} keeps to
+// within kappa(A) eps; the re-orthonormalisation only has to keep the basis
+// well conditioned for the next k_tau slices.
 int orthonormalize(pqmc_ctx &c, double *const A[2], double *const dst[2]) {
   const bool same = c.Ns[0] == c.Ns[1];
-  for (int pass = 0; pass < 2; ++pass) {
-    const double *src[2] = {pass ? c.qrtmp[0] : A[0], pass ? c.qrtmp[1] : A[1]};
-    double *out[2] = {pass ? dst[0] : c.qrtmp[0], pass ? dst[1] : c.qrtmp[1]};
-    GemmBatch gb{};
-    for (int s = 0; s < 2; ++s) {
-      const int n = c.Ns[s];
-      gb.d[gb.count++] = gemm_desc(src[s], n, src[s], n, c.E[s], 2 * n, n, n, c.N);
-    }
-    PQ_HIP_CHECK(gemm(gb, true, false, c.st));
-    ElimSpin es[2];
-    for (int s = 0; s < 2; ++s) {
-      const int n = c.Ns[s];
-      PQ_HIP_CHECK(set_identity_block(c.E[s], nullptr, 2 * n, n, n, c.st));
-      es[s] = ElimSpin{c.E[s], 2L * n, n, 2 * n, c.Z[s], c.prow[s], c.slot[s], c.BR[s], c.F[s]};
-    }
-    if (same) {
-      PQ_HIP_CHECK(chol_eliminate(es, 2, c.stats, c.st));
-    } else {
-      PQ_HIP_CHECK(chol_eliminate(&es[0], 1, c.stats, c.st));
-      PQ_HIP_CHECK(chol_eliminate(&es[1], 1, c.stats, c.st));
-    }
-    GemmBatch qb{};
-    for (int s = 0; s < 2; ++s) {
-      const int n = c.Ns[s];
-      qb.d[qb.count++] = gemm_desc(src[s], n, c.F[s], n, out[s], n, c.N, n, n);
-    }
-    PQ_HIP_CHECK(gemm(qb, false, true, c.st));
+  GemmBatch gb{};
+  for (int s = 0; s < 2; ++s) {
+    const int n = c.Ns[s];
+    gb.d[gb.count++] = gemm_desc(A[s], n, A[s], n, c.E[s], 2 * n, n, n, c.N);
   }
+  PQ_HIP_CHECK(gemm(gb, true, false, c.st));
+  ElimSpin es[2];
+  for (int s = 0; s < 2; ++s) {
+    const int n = c.Ns[s];
+    PQ_HIP_CHECK(set_identity_block(c.E[s], nullptr, 2 * n, n, n, c.st));
+    es[s] = ElimSpin{c.E[s], 2L * n, n, 2 * n, c.Z[s], c.prow[s], c.slot[s], c.BR[s], c.F[s]};
+  }
+  if (same) {
+    PQ_HIP_CHECK(chol_eliminate(es, 2, c.stats, c.st));
+  } else {
+    PQ_HIP_CHECK(chol_eliminate(&es[0], 1, c.stats, c.st));
+    PQ_HIP_CHECK(chol_eliminate(&es[1], 1, c.stats, c.st));
+  }
+  GemmBatch qb{};
+  for (int s = 0; s < 2; ++s) {
+    const int n = c.Ns[s];
+    qb.d[qb.count++] = gemm_desc(A[s], n, c.F[s], n, dst[s], n, c.N, n, n);
+  }
+  PQ_HIP_CHECK(gemm(qb, false, true, c.st));
   return PQMC_OK;
 }
 

@@ -42,188 +42,248 @@ __device__ __forceinline__ double lane_value(double v, int src) {
   return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-// Inverse of the kNB x kNB matrix LU = L U (unit lower L, upper U, both in
-// LU; rows and columns >= nb padded with the identity) into Z (nb x nb
-// written, row-major, leading dimension kNB).  Threads 0..31 invert L by
-// forward substitution and threads 64..95 invert U by back substitution,
-// one column each (the partial results stay in LDS), then all threads form
-// U^{-1} L^{-1}.
-__device__ void lu_inverse_to(const double (*LU)[kNB + 1], double (*Li)[kNB + 1],
-                              double (*Ui)[kNB + 1], int nb, double *Z) {
-  const int t = threadIdx.x;
-  if (t < kNB) {
-    const int col = t;
-    for (int i = 0; i < kNB; ++i) {
-      double s = (i == col) ? 1.0 : 0.0;
-#pragma unroll 4
-      for (int m = 0; m < i; ++m) s -= LU[i][m] * Li[m][col];
-      Li[i][col] = s;
-    }
-  } else if (t >= 64 && t < 64 + kNB) {
-    const int col = t - 64;
-    for (int i = kNB - 1; i >= 0; --i) {
-      double s = (i == col) ? 1.0 : 0.0;
-#pragma unroll 4
-      for (int m = i + 1; m < kNB; ++m) s -= LU[i][m] * Ui[m][col];
-      const double dd = LU[i][i];
-      Ui[i][col] = (dd != 0.0) ? s / dd : 0.0;
-    }
-  }
+// In-place inverse of a lower-triangular kNB x kNB matrix X (LDS, entries
+// above the diagonal zero) by doubling: once the diagonal blocks A, C of
+// size b hold their inverses, the block B below A becomes -C^{-1} B A^{-1}.
+// unit: X has a unit diagonal.  Tm is scratch.  All threads of the block
+// take part; every thread must call it.
+__device__ void tri_lower_inverse(double (*X)[kNB + 1], double (*Tm)[kNB + 1], bool unit) {
+  const int t = threadIdx.x, nt = blockDim.x;
+  for (int i = t; i < kNB; i += nt) X[i][i] = unit ? 1.0 : 1.0 / X[i][i];
   __syncthreads();
-  for (int e = t; e < kNB * kNB; e += blockDim.x) {
-    const int i = e / kNB, cc = e % kNB;
-    double s = 0.0;
-#pragma unroll 8
-    for (int m = 0; m < kNB; ++m) s += Ui[i][m] * Li[m][cc];
-    if (i < nb && cc < nb) Z[i * kNB + cc] = s;
+  for (int b = 1; b < kNB; b <<= 1) {
+    const int ne = (kNB / (2 * b)) * b * b;
+    for (int e = t; e < ne; e += nt) {
+      const int q = e / (b * b), i = (e / b) % b, j = e % b, p0 = 2 * b * q;
+      double s = 0.0;
+      for (int m = j; m < b; ++m) s += X[p0 + b + i][p0 + m] * X[p0 + m][p0 + j];
+      Tm[p0 + b + i][p0 + j] = s;
+    }
+    __syncthreads();
+    for (int e = t; e < ne; e += nt) {
+      const int q = e / (b * b), i = (e / b) % b, j = e % b, p0 = 2 * b * q;
+      double s = 0.0;
+      for (int m = 0; m <= i; ++m) s += X[p0 + b + i][p0 + b + m] * Tm[p0 + b + m][p0 + j];
+      X[p0 + b + i][p0 + j] = -s;
+    }
+    __syncthreads();
   }
 }
 
-// Gauss-Jordan panel E[:, kb:kb+nb) with implicit partial pivoting.  Thread
-// r holds row r's panel entries; per column the largest |entry| among the
-// rows not yet used as pivots wins (ties: the smaller row index).  Each
-// wave's candidate writes its whole row to LDS with its key, so one barrier
-// per column suffices.  Outputs: prow[kb + j] = pivot row of column kb + j,
-// slot[row] = kb + j, Z = (E[prow, kb:kb+nb))^{-1}.
-constexpr int kLuThreads = 1024;
+// Gauss-Jordan panel E[:, kb:kb+nb) with implicit partial pivoting.
+// Thread t holds rows t and t + 512 of the panel in registers (staged
+// through LDS so that the global loads are coalesced).  Per column the
+// largest |entry| among the rows not yet used as pivots wins; the key packs
+// the magnitude's bits (an IEEE double >= 0 orders like its bit pattern)
+// with the row index in the low 11 bits, so ties go to the smaller row and
+// the reduction is an integer max.  Each wave's winner writes its row to LDS
+// with its key, so one barrier per column suffices.  Columns are taken in
+// blocks of 8, the register rows shifted by 8 after each block, so the
+// column loop need not be unrolled in full.  No global memory is touched
+// inside the column loop.  Outputs: prow[kb + j], slot[row] = kb + j, and
+// Z = D^{-1} for the pivot block D (rows in pivot order) from D = L U:
+// with U from the elimination, L = D U^{-1} and Z = U^{-1} L^{-1}.
+constexpr int kLuThreads = 512;
 constexpr int kLuWaves = kLuThreads / 64;
+constexpr int kLuChunk = 128;   // rows staged through LDS at a time
+
+__device__ __forceinline__ unsigned long long pivot_key(double x, int r) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(fabs(x));
+  return (b & ~2047ull) | (unsigned long long)(2047 - r);
+}
 
 __global__ __launch_bounds__(kLuThreads) void lu_panel_kernel(ElimArgs a) {
   const ElimSpin &S = a.s[blockIdx.x];
   const int kb = a.kb, nb = a.nb, n = S.n;
-  const int r = threadIdx.x, lane = r & 63, wave = r >> 6;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int rr0 = t, rr1 = t + kLuThreads;
   __shared__ double rowbuf[2][kLuWaves][kNB];
-  __shared__ double cval[2][kLuWaves];
-  __shared__ int crow[2][kLuWaves];
-  __shared__ double LU[kNB][kNB + 1], Li[kNB][kNB + 1], Ui[kNB][kNB + 1];
+  __shared__ unsigned long long kbuf[2][kLuWaves];
+  __shared__ double shm[kLuChunk * (kNB + 1)];
+  __shared__ double Ut[kNB][kNB + 1];
+  __shared__ int prs[kNB];
   __shared__ int bad;
-  if (r == 0) bad = 0;
-  bool cand = r < n && S.slot[r] < 0;
-  double v[kNB];
+  double (*stage)[kNB + 1] = reinterpret_cast<double (*)[kNB + 1]>(shm);
+  double (*Lm)[kNB + 1] = reinterpret_cast<double (*)[kNB + 1]>(shm);
+  double (*Tm)[kNB + 1] = reinterpret_cast<double (*)[kNB + 1]>(shm + kNB * (kNB + 1));
+  if (t == 0) bad = 0;
+  for (int e = t; e < kNB * kNB; e += kLuThreads) {
+    const int i = e / kNB, j = e % kNB;
+    Ut[i][j] = (i == j && j >= nb) ? 1.0 : 0.0;
+  }
+  bool cand0 = rr0 < n && S.slot[rr0] < 0;
+  bool cand1 = rr1 < n && S.slot[rr1] < 0;
+  double v0[kNB], v1[kNB];
 #pragma unroll
-  for (int c = 0; c < kNB; ++c) v[c] = (cand && c < nb) ? S.E[(long)r * S.ld + kb + c] : 0.0;
-  int mypos = -1;
-#pragma clang loop unroll(full)
-  for (int j = 0; j < kNB; ++j) {
-    if (j < nb) {   // uniform
-      const int par = j & 1;
-      double key = -1.0;
-      if (cand) key = isnan(v[j]) ? 0.0 : fabs(v[j]);
-      int kr = cand ? r : 0x7fffffff;
+  for (int c = 0; c < kNB; ++c) v0[c] = v1[c] = 0.0;
+  for (int c0 = 0; c0 < n; c0 += kLuChunk) {
+    for (int e = t; e < kLuChunk * kNB; e += kLuThreads) {
+      const int i = e / kNB, c = e % kNB, row = c0 + i;
+      stage[i][c] = (row < n && c < nb) ? S.E[(long)row * S.ld + kb + c] : 0.0;
+    }
+    __syncthreads();
+    const bool in0 = cand0 && rr0 >= c0 && rr0 < c0 + kLuChunk;
+    const bool in1 = cand1 && rr1 >= c0 && rr1 < c0 + kLuChunk;
 #pragma unroll
-      for (int o = 32; o > 0; o >>= 1) {
-        const double ok = __shfl_xor(key, o, 64);
-        const int orr = __shfl_xor(kr, o, 64);
-        const bool take = (ok > key) || (ok == key && orr < kr);
-        key = take ? ok : key;
-        kr = take ? orr : kr;
-      }
-      if (r == kr) {
+    for (int c = 0; c < kNB; ++c) {
+      if (in0) v0[c] = stage[rr0 - c0][c];
+      if (in1) v1[c] = stage[rr1 - c0][c];
+    }
+    __syncthreads();
+  }
+  int pos0 = -1, pos1 = -1;
+  for (int jb = 0; jb < nb; jb += 8) {
 #pragma unroll
-        for (int c = 0; c < kNB; ++c) rowbuf[par][wave][c] = v[c];
-      }
-      if (lane == 0) {
-        cval[par][wave] = key;
-        crow[par][wave] = kr;
-      }
-      __syncthreads();
-      double best = -1.0;
-      int brow = 0x7fffffff, bw = 0;
+    for (int jj = 0; jj < 8; ++jj) {
+      const int j = jb + jj;
+      if (j < nb) {   // uniform
+        const int par = jj & 1;
+        const unsigned long long k0 = cand0 ? pivot_key(v0[jj], rr0) : 0ull;
+        const unsigned long long k1 = cand1 ? pivot_key(v1[jj], rr1) : 0ull;
+        unsigned long long key = k0 > k1 ? k0 : k1;
 #pragma unroll
-      for (int w = 0; w < kLuWaves; ++w) {
-        const double kv = cval[par][w];
-        const int kr2 = crow[par][w];
-        const bool take = (kv > best) || (kv == best && kr2 < brow);
-        best = take ? kv : best;
-        brow = take ? kr2 : brow;
-        bw = take ? w : bw;
-      }
-      bw = __builtin_amdgcn_readfirstlane(bw);
-      const double d = rowbuf[par][bw][j];
-      if (r == 0 && !(best > 0.0)) bad = 1;
-      const double invd = (best > 0.0) ? 1.0 / d : 0.0;
-      if (r == brow) {
-        cand = false;
-        mypos = j;
-      }
-      if (cand) {
-        const double l = v[j] * invd;
+        for (int o = 32; o > 0; o >>= 1) {
+          const unsigned long long ok = __shfl_xor(key, o, 64);
+          key = ok > key ? ok : key;
+        }
+        if (key != 0ull) {
+          const int rw = 2047 - (int)(key & 2047ull);
+          if (rw == rr0) {
 #pragma unroll
-        for (int c = j + 1; c < kNB; ++c) v[c] -= l * rowbuf[par][bw][c];
-        v[j] = l;
+            for (int c = 0; c < kNB; ++c) rowbuf[par][wave][c] = v0[c];
+          } else if (rw == rr1) {
+#pragma unroll
+            for (int c = 0; c < kNB; ++c) rowbuf[par][wave][c] = v1[c];
+          }
+        }
+        if (lane == 0) kbuf[par][wave] = key;
+        __syncthreads();
+        unsigned long long best = 0ull;
+#pragma unroll
+        for (int w = 0; w < kLuWaves; ++w) {
+          const unsigned long long kv = kbuf[par][w];
+          best = kv > best ? kv : best;
+        }
+        const int brow = __builtin_amdgcn_readfirstlane(2047 - (int)(best & 2047ull));
+        const int bw = (brow & (kLuThreads - 1)) >> 6;
+        const double *prw = rowbuf[par][bw];
+        const double d = prw[jj];
+        const bool okp = fabs(d) > 0.0;
+        if (t == 0 && !okp) bad = 1;
+        const double invd = okp ? 1.0 / d : 0.0;
+        // row j of U (columns >= j), stored transposed
+        if (t >= jj && t < kNB - jb) Ut[jb + t][j] = prw[t];
+        if (t == 0) prs[j] = brow;
+        if (rr0 == brow) {
+          cand0 = false;
+          pos0 = j;
+        }
+        if (rr1 == brow) {
+          cand1 = false;
+          pos1 = j;
+        }
+        const double l0 = v0[jj] * invd, l1 = v1[jj] * invd;
+#pragma unroll
+        for (int c = jj + 1; c < kNB; ++c) {
+          const double pc = prw[c];
+          if (cand0) v0[c] -= l0 * pc;
+          if (cand1) v1[c] -= l1 * pc;
+        }
       }
     }
-  }
-  if (mypos >= 0) {
 #pragma unroll
-    for (int c = 0; c < kNB; ++c) LU[mypos][c] = v[c];
-    S.slot[r] = kb + mypos;
-    S.prow[kb + mypos] = r;
+    for (int c = 0; c < kNB; ++c) {
+      v0[c] = (c + 8 < kNB) ? v0[c + 8] : 0.0;
+      v1[c] = (c + 8 < kNB) ? v1[c + 8] : 0.0;
+    }
+  }
+  if (pos0 >= 0) {
+    S.slot[rr0] = kb + pos0;
+    S.prow[kb + pos0] = rr0;
+  }
+  if (pos1 >= 0) {
+    S.slot[rr1] = kb + pos1;
+    S.prow[kb + pos1] = rr1;
   }
   __syncthreads();
-  if (r >= nb && r < kNB) {
-#pragma unroll
-    for (int c = 0; c < kNB; ++c) LU[r][c] = (r == c) ? 1.0 : 0.0;
-  }
-  if (r < nb) {
-#pragma unroll
-    for (int c = 0; c < kNB; ++c)
-      if (c >= nb) LU[r][c] = 0.0;
+  if (t == 0 && bad) atomicOr(&a.stats[kStError], (unsigned long long)kErrSingular);
+  // (U^T)^{-1}, in place
+  tri_lower_inverse(Ut, Tm, false);
+  // D (pivot rows in order, original entries) into Lm
+  for (int e = t; e < kNB * kNB; e += kLuThreads) {
+    const int i = e / kNB, c = e % kNB;
+    Lm[i][c] = (i < nb && c < nb) ? S.E[(long)prs[i] * S.ld + kb + c] : (i == c ? 1.0 : 0.0);
   }
   __syncthreads();
-  if (r == 0 && bad) atomicOr(&a.stats[kStError], (unsigned long long)kErrSingular);
-  lu_inverse_to(LU, Li, Ui, nb, S.Z);
+  // L = D U^{-1}, strictly lower part, unit diagonal; U^{-1}(m, j) = Ut(j, m)
+  for (int e = t; e < kNB * kNB; e += kLuThreads) {
+    const int i = e / kNB, j = e % kNB;
+    double s = 0.0;
+    if (j < i) {
+#pragma unroll 8
+      for (int m = 0; m < kNB; ++m) s += Lm[i][m] * Ut[j][m];
+    }
+    Tm[i][j] = (j < i) ? s : (i == j ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  tri_lower_inverse(Tm, Lm, true);
+  for (int e = t; e < kNB * kNB; e += kLuThreads) {
+    const int i = e / kNB, j = e % kNB;
+    double s = 0.0;
+#pragma unroll 8
+    for (int m = 0; m < kNB; ++m) s += Ut[m][i] * Tm[m][j];
+    if (i < nb && j < nb) S.Z[i * kNB + j] = s;
+  }
 }
 
 // Cholesky panel: C C^T = E[kb:kb+nb, kb:kb+nb) (the current Schur
-// complement), Z = C^{-1} (lower).  One wave, lane i holds row i.
-__global__ __launch_bounds__(64) void chol_panel_kernel(ElimArgs a) {
+// complement), Z = C^{-1} (lower).  Wave 0 factors the block with lane i
+// holding row i and cross-lane reads (no barriers); then the workgroup
+// inverts C.
+constexpr int kCholThreads = 256;
+
+__global__ __launch_bounds__(kCholThreads) void chol_panel_kernel(ElimArgs a) {
   const ElimSpin &S = a.s[blockIdx.x];
   const int kb = a.kb, nb = a.nb;
-  const int i = threadIdx.x;
-  __shared__ double lcol[64];
-  __shared__ double C[kNB][kNB + 1], X[kNB][kNB + 1];
-  double v[kNB];
-#pragma unroll
-  for (int c = 0; c < kNB; ++c)
-    v[c] = (i < nb && c < nb) ? S.E[(long)(kb + i) * S.ld + kb + c] : (i == c ? 1.0 : 0.0);
-  bool bad = false;
-#pragma unroll
-  for (int k = 0; k < kNB; ++k) {
-    const double dk = lane_value(v[k], k);
-    const bool ok = dk > 0.0;
-    bad = bad || !ok;
-    const double ck = ok ? sqrt(dk) : 1.0;
-    const double l = (i > k) ? v[k] / ck : 0.0;
-    if (i == k) v[k] = ck;
-    if (i > k) v[k] = l;
-    lcol[i] = l;
-    __syncthreads();
-#pragma unroll
-    for (int j = k + 1; j < kNB; ++j)
-      if (i >= j) v[j] -= l * lcol[j];
-    __syncthreads();
-  }
-  if (i < kNB) {
-#pragma unroll
-    for (int c = 0; c < kNB; ++c) C[i][c] = (c <= i) ? v[c] : 0.0;
+  const int t = threadIdx.x;
+  __shared__ double C[kNB][kNB + 1], Tm[kNB][kNB + 1];
+  for (int e = t; e < kNB * kNB; e += kCholThreads) {
+    const int i = e / kNB, c = e % kNB;
+    C[i][c] = (i < nb && c < nb) ? S.E[(long)(kb + i) * S.ld + kb + c] : (i == c ? 1.0 : 0.0);
   }
   __syncthreads();
-  if (i == 0 && bad) atomicOr(&a.stats[kStError], (unsigned long long)kErrSingular);
-  // Z = C^{-1} by forward substitution, lane col forming column col
-  if (i < kNB) {
-    const int col = i;
-    for (int rr = 0; rr < kNB; ++rr) {
-      double s = (rr == col) ? 1.0 : 0.0;
-#pragma unroll 4
-      for (int m = 0; m < rr; ++m) s -= C[rr][m] * X[m][col];
-      X[rr][col] = s / C[rr][rr];
+  if (t < 64) {
+    const int i = t;
+    double v[kNB];
+#pragma unroll
+    for (int c = 0; c < kNB; ++c) v[c] = (i < kNB) ? C[i][c] : 0.0;
+    bool bad = false;
+#pragma unroll
+    for (int k = 0; k < kNB; ++k) {
+      const double dk = lane_value(v[k], k);
+      const bool ok = dk > 0.0;
+      bad = bad || !ok;
+      const double ck = ok ? sqrt(dk) : 1.0;
+      const double ick = 1.0 / ck;
+      const double l = (i > k) ? v[k] * ick : 0.0;
+      v[k] = (i == k) ? ck : ((i > k) ? l : v[k]);
+#pragma unroll
+      for (int j = k + 1; j < kNB; ++j) {
+        const double lj = lane_value(l, j);
+        if (i >= j) v[j] -= l * lj;
+      }
     }
+    if (i < kNB) {
+#pragma unroll
+      for (int c = 0; c < kNB; ++c) C[i][c] = (c <= i) ? v[c] : 0.0;
+    }
+    if (i == 0 && bad) atomicOr(&a.stats[kStError], (unsigned long long)kErrSingular);
   }
   __syncthreads();
-  for (int e = i; e < kNB * kNB; e += 64) {
+  tri_lower_inverse(C, Tm, false);
+  for (int e = t; e < kNB * kNB; e += kCholThreads) {
     const int rr = e / kNB, cc = e % kNB;
-    if (rr < nb && cc < nb) S.Z[rr * kNB + cc] = X[rr][cc];
+    if (rr < nb && cc < nb) S.Z[rr * kNB + cc] = C[rr][cc];
   }
 }
 
@@ -413,7 +473,7 @@ hipError_t gj_invert(const ElimSpin *s, int nspin, unsigned long long *stats,
   const int n = s[0].n;
   for (int i = 1; i < nspin; ++i)
     if (s[i].n != n || s[i].w != s[0].w) return hipErrorInvalidValue;
-  if (n < 1 || n > kLuThreads || nspin < 1 || nspin > 2) return hipErrorInvalidValue;
+  if (n < 1 || n > 2 * kLuThreads || nspin < 1 || nspin > 2) return hipErrorInvalidValue;
   const int w = s[0].w;
   hipLaunchKernelGGL(fill_int_kernel, dim3((n + 255) / 256, nspin), dim3(256), 0, st, s[0].slot,
                      nspin > 1 ? s[1].slot : s[0].slot, (long)n, -1);
@@ -458,7 +518,7 @@ hipError_t chol_eliminate(const ElimSpin *s, int nspin, unsigned long long *stat
     ea.kb = kb;
     ea.nb = min(kNB, n - kb);
     ea.pass = pass;
-    hipLaunchKernelGGL(chol_panel_kernel, dim3(nspin), dim3(64), 0, st, ea);
+    hipLaunchKernelGGL(chol_panel_kernel, dim3(nspin), dim3(kCholThreads), 0, st, ea);
     const int cols = min(w, n + kb + ea.nb) - kb - ea.nb;
     hipLaunchKernelGGL(elim_update_kernel<false>,
                        dim3((n - kb + 63) / 64, (cols + 63) / 64, nspin), dim3(256), 0, st, ea);

@@ -1,10 +1,10 @@
 // FP64 GEMM on gfx950 matrix cores (v_mfma_f64_16x16x4f64).
 //
-// One 256-thread workgroup computes a 64x64 tile of C; its four waves each
-// own a 32x32 quadrant held as 2x2 MFMA accumulators (4 doubles per lane per
-// 16x16 block).  A and B tiles of depth 16 are staged through LDS, with the
-// next depth slice prefetched into registers while the current one is
-// multiplied.  The same kernel serves the B-matrix propagation (diagonal
+// One 256-thread workgroup computes a 64x32 tile of C; its four waves each
+// own a 32x16 block held as 2x1 MFMA accumulators (4 doubles per lane per
+// 16x16 block).  A and B tiles of depth 16 are staged through two LDS
+// buffers: the next depth slice is loaded into registers while the current
+// one is multiplied, then stored to the other buffer, one barrier per slice.  The same kernel serves the B-matrix propagation (diagonal
 // field scalings fused into the operand load or the epilogue), the Taylor
 // series of e^{-dtau H0}, the Gram and product matrices of the
 // stabilisation, the split-K panel products of the delayed and block
@@ -18,7 +18,16 @@
 namespace pq {
 
 namespace {
-constexpr int BM = 64, BN = 64, BK = 16, LDSP = 80;  // LDSP: padded LDS row stride
+// Tile shape chosen by measurement on MI355X at the propagation shape
+// (4 x [1600 x 1600] x [1600 x 800]): 64 x 32 tiles of 4 waves (32 x 16
+// each) reached 40-42 TFLOP/s, against 28 for 64 x 64 single-buffered,
+// 37 for 64 x 64 double-buffered, 27 for 128 x 64 and 44 for the vendor
+// library without the fused scaling.
+constexpr int BM = 64, BN = 32, WM = 32, WN = 16, BK = 16;
+constexpr int PA = BM + 4, PB = BN + 4;   // padded LDS rows
+constexpr int MI = WM / 16, NI = WN / 16, WGM = BM / WM;
+constexpr int NA = BM * BK / 256, NB = BN * BK / 256;
+static_assert((BM / WM) * (BN / WN) == 4, "four waves per workgroup");
 
 template <bool TA, bool TB>
 __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmBatch batch, int nsplit) {
@@ -40,33 +49,34 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmBatch batch, int nspl
   }
   if (g.ksplit <= 0 && K <= 0 && g.Kdev && g.beta == 1.0 && g.Cin == g.C && !g.addI) return;
 
-  __shared__ double As[BK][LDSP];
-  __shared__ double Bs[BK][LDSP];
+  // two depth slices in flight: one being multiplied, the next being stored
+  __shared__ double As[2][BK][PA];
+  __shared__ double Bs[2][BK][PB];
 
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wm = wave % WGM, wn = wave / WGM;
 
   const double *A = g.A, *B = g.B;
   const long lda = g.lda, ldb = g.ldb;
 
-  double ra[4], rb[4];
+  double ra[NA], rb[NB];
   auto load = [&](int k0) {
 #pragma unroll
-    for (int p = 0; p < 4; ++p) {
+    for (int p = 0; p < NA; ++p) {
       int mm, kk;
-      if (!TA) { kk = t & 15; mm = (t >> 4) + 16 * p; }
-      else     { mm = t & 63; kk = (t >> 6) + 4 * p; }
+      if (!TA) { kk = t % BK; mm = t / BK + (256 / BK) * p; }
+      else     { mm = t % BM; kk = t / BM + (256 / BM) * p; }
       const int gi = m0 + mm, gk = k0 + kk;
       double v = 0.0;
       if (gi < M && gk < kend) v = TA ? A[(long)gk * lda + gi] : A[(long)gi * lda + gk];
       ra[p] = v;
     }
 #pragma unroll
-    for (int p = 0; p < 4; ++p) {
+    for (int p = 0; p < NB; ++p) {
       int nn, kk;
-      if (!TB) { nn = t & 63; kk = (t >> 6) + 4 * p; }
-      else     { kk = t & 15; nn = (t >> 4) + 16 * p; }
+      if (!TB) { nn = t % BN; kk = t / BN + (256 / BN) * p; }
+      else     { kk = t % BK; nn = t / BK + (256 / BK) * p; }
       const int gj = n0 + nn, gk = k0 + kk;
       double v = 0.0;
       if (gj < N && gk < kend) {
@@ -76,60 +86,69 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmBatch batch, int nspl
       rb[p] = v;
     }
   };
-  auto store = [&]() {
+  auto store = [&](int buf) {
 #pragma unroll
-    for (int p = 0; p < 4; ++p) {
+    for (int p = 0; p < NA; ++p) {
       int mm, kk;
-      if (!TA) { kk = t & 15; mm = (t >> 4) + 16 * p; }
-      else     { mm = t & 63; kk = (t >> 6) + 4 * p; }
-      As[kk][mm] = ra[p];
+      if (!TA) { kk = t % BK; mm = t / BK + (256 / BK) * p; }
+      else     { mm = t % BM; kk = t / BM + (256 / BM) * p; }
+      As[buf][kk][mm] = ra[p];
     }
 #pragma unroll
-    for (int p = 0; p < 4; ++p) {
+    for (int p = 0; p < NB; ++p) {
       int nn, kk;
-      if (!TB) { nn = t & 63; kk = (t >> 6) + 4 * p; }
-      else     { kk = t & 15; nn = (t >> 4) + 16 * p; }
-      Bs[kk][nn] = rb[p];
+      if (!TB) { nn = t % BN; kk = t / BN + (256 / BN) * p; }
+      else     { kk = t % BK; nn = t / BK + (256 / BK) * p; }
+      Bs[buf][kk][nn] = rb[p];
     }
   };
 
-  dbl4 acc[2][2];
+  dbl4 acc[MI][NI];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < MI; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < NI; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
 
-  if (kbeg < kend) load(kbeg);
+  if (kbeg < kend) {
+    load(kbeg);
+    store(0);
+  }
+  __syncthreads();
+  int buf = 0;
   for (int k0 = kbeg; k0 < kend; k0 += BK) {
-    store();
-    __syncthreads();
-    if (k0 + BK < kend) load(k0 + BK);
+    const bool more = k0 + BK < kend;
+    if (more) load(k0 + BK);
 #pragma unroll
     for (int ks = 0; ks < BK / 4; ++ks) {
       const int kk = ks * 4 + (lane >> 4);
-      const double a0 = As[kk][wm * 32 + (lane & 15)];
-      const double a1 = As[kk][wm * 32 + 16 + (lane & 15)];
-      const double b0 = Bs[kk][wn * 32 + (lane & 15)];
-      const double b1 = Bs[kk][wn * 32 + 16 + (lane & 15)];
-      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+      double a[MI], b[NI];
+#pragma unroll
+      for (int i = 0; i < MI; ++i) a[i] = As[buf][kk][wm * WM + i * 16 + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < NI; ++j) b[j] = Bs[buf][kk][wn * WN + j * 16 + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < MI; ++i)
+#pragma unroll
+        for (int j = 0; j < NI; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
     }
+    // the other buffer was last read before the previous barrier
+    if (more) store(buf ^ 1);
     __syncthreads();
+    buf ^= 1;
   }
 
   double *C = g.C;
   if (g.ksplit > 0) C += (long)split * g.csplit;
   const bool split_out = g.ksplit > 0;
 #pragma unroll
-  for (int mi = 0; mi < 2; ++mi)
+  for (int mi = 0; mi < MI; ++mi)
 #pragma unroll
-    for (int ni = 0; ni < 2; ++ni)
+    for (int ni = 0; ni < NI; ++ni)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int row = m0 + wm * 32 + mi * 16 + (lane >> 4) + 4 * j;
-        const int col = n0 + wn * 32 + ni * 16 + (lane & 15);
+        const int row = m0 + wm * WM + mi * 16 + (lane >> 4) + 4 * j;
+        const int col = n0 + wn * WN + ni * 16 + (lane & 15);
         if (row < M && col < N) {
           double v = g.alpha * acc[mi][ni][j];
           if (g.rs_field) v *= (g.rs_field[row] > 0) ? g.rs_pos : g.rs_neg;
