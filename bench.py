@@ -58,9 +58,10 @@ def kernel_work(p, cls, scheme, k, b, acc):
     raise KeyError(cls)
 
 
-def roofline(p, scheme, k, b, acc, ktimes, cls=None):
+def roofline(p, scheme, k, b, acc, ktimes, cls=None, walkers=1):
     """Roofline of one kernel class (default: the one with the largest device
-    time), from its average launch duration on the library's stream."""
+    time), from its average launch duration on the library's stream; one
+    launch covers `walkers` walkers."""
     live = {c: v for c, v in ktimes.items() if v[1] > 0}
     if not live or (cls is not None and cls not in live):
         return None
@@ -69,6 +70,7 @@ def roofline(p, scheme, k, b, acc, ktimes, cls=None):
     tot, cnt = live[cls]
     avg = tot / cnt
     flops, nbytes, bound = kernel_work(p, cls, scheme, k, b, acc)
+    flops, nbytes = flops * walkers, nbytes * walkers
     if bound == "hbm":
         achieved, peak, unit = nbytes / avg / 1e9, MI355X_HBM_TBPS * 1e3, "GB/s"
     else:
@@ -81,16 +83,21 @@ def roofline(p, scheme, k, b, acc, ktimes, cls=None):
             "device_time_share": {c: v / total for c, v in shares.items()}}
 
 
-def time_sweeps(ch, steps, warmup):
+def time_sweeps(chains, steps, warmup):
+    """Wall time of `steps` sweeps of all chains (one batch, lockstep) and the
+    statistics summed over chains and steps (phase times: the batch's)."""
     import torch
+    from paper_2506_09611_amd import batch_sweep
     for _ in range(warmup):
-        ch.sweep(1)
+        batch_sweep(chains, 1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    st = [ch.sweep(1) for _ in range(steps)]
+    st = [batch_sweep(chains, 1) for _ in range(steps)]
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    agg = {k: sum(s[k] for s in st) for k in st[0]}
+    agg = {k: sum(s[0][k] for s in st) for k in st[0][0]}
+    for k in ("proposed", "accepted", "flips", "low_margin", "negative", "field_updates"):
+        agg[k] = sum(w[k] for s in st for w in s)
     return t1 - t0, agg
 
 
@@ -133,6 +140,8 @@ def main():
     ap.add_argument("--k", type=int, default=32)
     ap.add_argument("--b", type=int, default=16)
     ap.add_argument("--workload", default="c3")
+    ap.add_argument("--walkers", type=int, default=1,
+                    help="independent walkers swept together in one batch (1..8)")
     ap.add_argument("--compare", default="local,block",
                     help="other schemes timed beside the headline one ('' for none)")
     ap.add_argument("--local-window", type=int, default=20,
@@ -154,19 +163,25 @@ def main():
     per_sweep = 2 * M * N
     log(f"workload {args.workload}: N={N} N_sigma={p.n_up} M={M}; creating {args.scheme}")
 
-    ch = make_chain(p, args.scheme, args.k, args.b)
-    dt, agg = time_sweeps(ch, args.steps, args.warmup)
-    value = args.steps * per_sweep / dt
-    upd = args.steps * per_sweep / agg["t_update_s"] if agg["t_update_s"] > 0 else None
+    import dataclasses
+    from paper_2506_09611_amd import batch_forward_window
+    W = args.walkers
+    chains = [make_chain(dataclasses.replace(p, walker_id=w), args.scheme, args.k, args.b)
+              for w in range(W)]
+    ch = chains[0]
+    dt, agg = time_sweeps(chains, args.steps, args.warmup)
+    value = W * args.steps * per_sweep / dt
+    upd = W * args.steps * per_sweep / agg["t_update_s"] if agg["t_update_s"] > 0 else None
     acc = agg["accepted"] / max(1, agg["proposed"])
     # per-kernel device time, live on the library's stream: an instrumented
     # forward window after the timed sweeps
     ch.set_opts(ch.scheme, ch.k, ch.b, ktime=True)
-    ch.forward_window(args.ktime_window)
+    if args.ktime_window > 0:
+        batch_forward_window(chains, args.ktime_window)
     ktimes = ch.kernel_times()
-    roof = roofline(p, args.scheme, args.k, args.b, acc, ktimes)
+    roof = roofline(p, args.scheme, args.k, args.b, acc, ktimes, walkers=W)
     # the rank-n_A flush with the next group's panels, on MFMA (delayed / block)
-    roof_flush = roofline(p, args.scheme, args.k, args.b, acc, ktimes, "tile")
+    roof_flush = roofline(p, args.scheme, args.k, args.b, acc, ktimes, "tile", walkers=W)
     log(f"{args.scheme}: {dt / args.steps:.3f} s/sweep, {value:.4g} fu/s, update-only {upd:.4g}")
     log("kernel times", {c: (round(v[0] * 1e3, 3), v[1]) for c, v in ktimes.items()})
     result = {
@@ -186,7 +201,7 @@ def main():
             "workload": "40x40 periodic Hubbard, N=1600, N_sigma=800 per spin, U/t=4, dtau=0.05, "
                         "M=400, k_tau=10, seeded 1e-3 bond perturbation"
                         if args.workload == "c3" else args.workload,
-            "scheme": args.scheme, "delay_k": args.k, "block_b": args.b,
+            "scheme": args.scheme, "delay_k": args.k, "block_b": args.b, "walkers": W,
         },
         "update_only_field_updates_per_s": upd,
         "acceptance": acc,
@@ -198,36 +213,40 @@ def main():
         "roofline_flush": roof_flush,
         "kernel_avg_us": {c: 1e6 * v[0] / v[1] for c, v in ktimes.items() if v[1] > 0},
     }
-    ch.close()
-    del ch
+    for c in chains:
+        c.close()
+    del ch, chains
     torch.cuda.empty_cache()
 
     schemes = {args.scheme: {"s_per_sweep": dt / args.steps, "field_updates_per_s": value,
-                             "update_only": upd}}
+                             "update_only": upd, "walkers": W}}
     for name in [s for s in args.compare.split(",") if s and s != args.scheme]:
-        c = make_chain(p, name, args.k, args.b)
+        cs = [make_chain(dataclasses.replace(p, walker_id=w), name, args.k, args.b)
+              for w in range(W)]
+        c = cs[0]
         if name == "local" and args.local_window > 0:
             # whole local sweeps take tens of seconds here: time a forward window
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            st = c.forward_window(args.local_window)
+            st = batch_forward_window(cs, args.local_window)[0]
             torch.cuda.synchronize()
             w = time.perf_counter() - t0
-            rate = args.local_window * N / w
+            rate = W * args.local_window * N / w
             schemes[name] = {"window_slice_visits": args.local_window, "s_window": w,
                              "field_updates_per_s": rate,
-                             "update_only": args.local_window * N / st["t_update_s"]
+                             "update_only": W * args.local_window * N / st["t_update_s"]
                              if st["t_update_s"] > 0 else None,
-                             "note": "forward window, not a whole sweep"}
+                             "walkers": W, "note": "forward window, not a whole sweep"}
         else:
-            d2, a2 = time_sweeps(c, 1, 0)
-            schemes[name] = {"s_per_sweep": d2, "field_updates_per_s": per_sweep / d2,
-                             "update_only": per_sweep / a2["t_update_s"]
+            d2, a2 = time_sweeps(cs, 1, 0)
+            schemes[name] = {"s_per_sweep": d2, "field_updates_per_s": W * per_sweep / d2,
+                             "update_only": W * per_sweep / a2["t_update_s"]
                              if a2["t_update_s"] > 0 else None,
-                             "acceptance": a2["accepted"] / max(1, a2["proposed"])}
+                             "acceptance": a2["accepted"] / max(1, a2["proposed"]), "walkers": W}
         log(name, schemes[name])
-        c.close()
-        del c
+        for x in cs:
+            x.close()
+        del c, cs
         torch.cuda.empty_cache()
     if "local" in schemes:
         base = schemes["local"]["field_updates_per_s"]

@@ -155,6 +155,22 @@ pqmc_status pqmc_sweep(pqmc_ctx *ctx, int32_t n_sweeps, pqmc_stats *out);
  * at sizes where a whole sweep is long; the next pqmc_sweep is refused. */
 pqmc_status pqmc_forward_window(pqmc_ctx *ctx, int32_t n_slices, pqmc_stats *out);
 
+/* Batched walkers: run the sweeps of n contexts (1 <= n <= 8) in lockstep,
+ * every kernel launch covering all of them (independent Markov chains, each
+ * with its own Philox key, fields, stack and statistics).  The contexts must
+ * have been created with the same n_sites, n_up, n_dn, n_slices, stab_every,
+ * scheme, delay_k, block_b and stream (PQMC_EINVAL otherwise); their
+ * hopping matrices, U and seeds may differ.  Each walker's decisions, fields
+ * and G are the ones pqmc_sweep would give it alone.  out: n entries or
+ * NULL; the timing fields of every entry are those of the whole batch.  The
+ * phase and kernel timers are those of ctxs[0]. */
+pqmc_status pqmc_batch_sweep(pqmc_ctx *const *ctxs, int32_t n, int32_t n_sweeps,
+                             pqmc_stats *out);
+
+/* pqmc_forward_window for a batch of walkers (same rules as pqmc_batch_sweep). */
+pqmc_status pqmc_batch_forward_window(pqmc_ctx *const *ctxs, int32_t n, int32_t n_slices,
+                                      pqmc_stats *out);
+
 /* G^s = 1 - U_R T U_L at the walker's current position (Eq. (15)),
  * written to host memory as N_s x N_s row-major float64.  spin: 0 up, 1 down. */
 pqmc_status pqmc_get_green(pqmc_ctx *ctx, int32_t spin, double *out);

@@ -6,6 +6,7 @@ supplies the device workspace and the stream.  There is no CPU fallback:
 importing `Chain` without the built library raises ImportError.
 """
 from .binding import (Chain, Scheme, PQMCError, load_library, library_path,  # noqa: F401
-                      EXPORTED_SYMBOLS)
+                      EXPORTED_SYMBOLS, MAX_BATCH, batch_sweep, batch_forward_window)
 
-__all__ = ["Chain", "Scheme", "PQMCError", "load_library", "library_path", "EXPORTED_SYMBOLS"]
+__all__ = ["Chain", "Scheme", "PQMCError", "load_library", "library_path", "EXPORTED_SYMBOLS",
+           "MAX_BATCH", "batch_sweep", "batch_forward_window"]

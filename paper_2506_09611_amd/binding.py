@@ -17,7 +17,8 @@ _LIB = None
 
 EXPORTED_SYMBOLS = (
     "pqmc_workspace_bytes", "pqmc_create", "pqmc_set_opts", "pqmc_set_fields",
-    "pqmc_get_fields", "pqmc_sweep", "pqmc_forward_window", "pqmc_get_green",
+    "pqmc_get_fields", "pqmc_sweep", "pqmc_forward_window", "pqmc_batch_sweep",
+    "pqmc_batch_forward_window", "pqmc_get_green",
     "pqmc_get_decisions", "pqmc_get_heat_bath", "pqmc_get_kernel_times", "pqmc_destroy",
     "pqmc_last_error",
 )
@@ -91,6 +92,10 @@ def load_library():
         "pqmc_get_fields": [c_void_p, ctypes.POINTER(ctypes.c_int8)],
         "pqmc_sweep": [c_void_p, ctypes.c_int32, ctypes.POINTER(Stats)],
         "pqmc_forward_window": [c_void_p, ctypes.c_int32, ctypes.POINTER(Stats)],
+        "pqmc_batch_sweep": [ctypes.POINTER(c_void_p), ctypes.c_int32, ctypes.c_int32,
+                             ctypes.POINTER(Stats)],
+        "pqmc_batch_forward_window": [ctypes.POINTER(c_void_p), ctypes.c_int32, ctypes.c_int32,
+                                      ctypes.POINTER(Stats)],
         "pqmc_get_green": [c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)],
         "pqmc_get_decisions": [c_void_p, ctypes.POINTER(ctypes.c_int32),
                                ctypes.POINTER(ctypes.c_double), c_size_t,
@@ -241,3 +246,27 @@ class Chain:
             self.close()
         except Exception:
             pass
+
+
+MAX_BATCH = 8
+
+
+def _batch_call(chains, fn, n):
+    if not 1 <= len(chains) <= MAX_BATCH:
+        raise ValueError(f"a batch holds 1..{MAX_BATCH} chains")
+    lib = chains[0]._lib
+    ctxs = (ctypes.c_void_p * len(chains))(*[c._ctx.value for c in chains])
+    st = (Stats * len(chains))()
+    _check(lib, fn(lib)(ctxs, len(chains), int(n), st))
+    return [s.as_dict() for s in st]
+
+
+def batch_sweep(chains, n=1):
+    """pqmc_batch_sweep: n sweeps of up to 8 chains of one shape in lockstep,
+    one launch per kernel for all of them.  Returns one stats dict per chain."""
+    return _batch_call(chains, lambda lib: lib.pqmc_batch_sweep, n)
+
+
+def batch_forward_window(chains, n_slices):
+    """pqmc_batch_forward_window for up to 8 chains of one shape."""
+    return _batch_call(chains, lambda lib: lib.pqmc_batch_forward_window, n_slices)

@@ -240,61 +240,109 @@ int sync_check(pqmc_ctx &c) {
   return PQMC_OK;
 }
 
-// CholQR of the columns of A (N x Ns per spin) into dst: S = A^T A = R^T R,
-// dst = A R^{-1}.  One pass suffices here: the Green's function depends on
-// U_R (U_L) only through its column (row) space, which A R^{-1} keeps to
-// within kappa(A) eps; the re-orthonormalisation only has to keep the basis
-// well conditioned for the next k_tau slices.
-int orthonormalize(pqmc_ctx &c, double *const A[2], double *const dst[2]) {
-  const bool same = c.Ns[0] == c.Ns[1];
-  GemmBatch gb{};
-  for (int s = 0; s < 2; ++s) {
-    const int n = c.Ns[s];
-    gb.d[gb.count++] = gemm_desc(A[s], n, A[s], n, c.E[s], 2 * n, n, n, c.N);
+// A set of walkers of one shape (N, N_sigma, M, k_tau, scheme, k, b) run in
+// lockstep on the lead walker's stream: every launch covers all of them.
+struct Walkers {
+  pqmc_ctx *const *w;
+  int n;
+  pqmc_ctx &lead() const { return *w[0]; }
+  pqmc_ctx &operator[](int i) const { return *w[i]; }
+};
+
+// GEMM descriptors queued and launched kGemmMaxBatch at a time.
+struct GemmQueue {
+  hipStream_t st;
+  bool ta, tb;
+  GemmBatch cur{};
+  int add(const GemmDesc &d) {
+    cur.d[cur.count++] = d;
+    return cur.count == kGemmMaxBatch ? flush() : PQMC_OK;
   }
-  PQ_HIP_CHECK(gemm(gb, true, false, c.st));
-  ElimSpin es[2];
-  for (int s = 0; s < 2; ++s) {
-    const int n = c.Ns[s];
-    PQ_HIP_CHECK(set_identity_block(c.E[s], nullptr, 2 * n, n, n, c.st));
-    es[s] = ElimSpin{c.E[s], 2L * n, n, 2 * n, c.Z[s], c.prow[s], c.slot[s], c.BR[s], c.F[s]};
+  int flush() {
+    if (cur.count == 0) return PQMC_OK;
+    hipError_t e = gemm(cur, ta, tb, st);
+    cur.count = 0;
+    if (e != hipSuccess) return fail_device(e, "gemm", __FILE__, __LINE__);
+    return PQMC_OK;
   }
-  if (same) {
-    PQ_HIP_CHECK(chol_eliminate(es, 2, c.stats, c.st));
-  } else {
-    PQ_HIP_CHECK(chol_eliminate(&es[0], 1, c.stats, c.st));
-    PQ_HIP_CHECK(chol_eliminate(&es[1], 1, c.stats, c.st));
+};
+
+ElimSpin elim_spin(pqmc_ctx &c, int s) {
+  const int n = c.Ns[s];
+  return ElimSpin{c.E[s], 2L * n, n, 2 * n, c.Z[s], c.prow[s], c.slot[s], c.BR[s], c.F[s], c.stats};
+}
+
+// CholQR of the columns of A (N x Ns per walker and spin, index 2 w + s)
+// into dst: S = A^T A = R^T R, dst = A R^{-1}.  One pass suffices here: the
+// Green's function depends on U_R (U_L) only through its column (row) space,
+// which A R^{-1} keeps to within kappa(A) eps; the re-orthonormalisation only
+// has to keep the basis well conditioned for the next k_tau slices.
+int orthonormalize(const Walkers &b, double *const *A, double *const *dst) {
+  pqmc_ctx &L = b.lead();
+  GemmQueue gram{L.st, true, false};
+  for (int i = 0; i < b.n; ++i)
+    for (int s = 0; s < 2; ++s) {
+      const int n = b[i].Ns[s];
+      int rc = gram.add(gemm_desc(A[2 * i + s], n, A[2 * i + s], n, b[i].E[s], 2 * n, n, n, b[i].N));
+      if (rc) return rc;
+    }
+  int rc = gram.flush();
+  if (rc) return rc;
+  // spin sectors of equal size go in one elimination call
+  const int nsec = L.Ns[0] == L.Ns[1] ? 1 : 2;
+  for (int sec = 0; sec < nsec; ++sec) {
+    ElimSpin es[kMaxMats];
+    double *E[kMaxMats];
+    int m = 0;
+    for (int i = 0; i < b.n; ++i)
+      for (int s = 0; s < 2; ++s) {
+        if (nsec == 2 && s != sec) continue;
+        es[m] = elim_spin(b[i], s);
+        E[m] = b[i].E[s];
+        ++m;
+      }
+    const int n = es[0].n;
+    PQ_HIP_CHECK(set_identity_block(E, m, 2 * n, n, n, L.st));
+    PQ_HIP_CHECK(chol_eliminate(es, m, L.st));
   }
-  GemmBatch qb{};
-  for (int s = 0; s < 2; ++s) {
-    const int n = c.Ns[s];
-    qb.d[qb.count++] = gemm_desc(A[s], n, c.F[s], n, dst[s], n, c.N, n, n);
-  }
-  PQ_HIP_CHECK(gemm(qb, false, true, c.st));
-  return PQMC_OK;
+  GemmQueue q{L.st, false, true};
+  for (int i = 0; i < b.n; ++i)
+    for (int s = 0; s < 2; ++s) {
+      const int n = b[i].Ns[s];
+      rc = q.add(gemm_desc(A[2 * i + s], n, b[i].F[s], n, dst[2 * i + s], n, b[i].N, n, n));
+      if (rc) return rc;
+    }
+  return q.flush();
 }
 
 // T = (U_L U_R)^{-1} by blocked Gauss-Jordan with partial pivoting.
-int refresh_T(pqmc_ctx &c) {
-  GemmBatch gb{};
-  for (int s = 0; s < 2; ++s) {
-    const int n = c.Ns[s];
-    gb.d[gb.count++] = gemm_desc(c.ULt[s], n, c.UR[s], n, c.E[s], 2 * n, n, n, c.N);
-  }
-  PQ_HIP_CHECK(gemm(gb, true, false, c.st));
-  ElimSpin es[2];
-  for (int s = 0; s < 2; ++s) {
-    const int n = c.Ns[s];
-    PQ_HIP_CHECK(set_identity_block(c.E[s], nullptr, 2 * n, n, n, c.st));
-    es[s] = ElimSpin{c.E[s], 2L * n, n, 2 * n, c.Z[s], c.prow[s], c.slot[s], c.BR[s], c.F[s]};
-  }
-  if (c.Ns[0] == c.Ns[1]) {
-    PQ_HIP_CHECK(gj_invert(es, 2, c.stats, c.T, c.Ns[0], c.st));
-  } else {
+int refresh_T(const Walkers &b) {
+  pqmc_ctx &L = b.lead();
+  GemmQueue q{L.st, true, false};
+  for (int i = 0; i < b.n; ++i)
     for (int s = 0; s < 2; ++s) {
-      double *const out[2] = {c.T[s], c.T[s]};
-      PQ_HIP_CHECK(gj_invert(&es[s], 1, c.stats, out, c.Ns[s], c.st));
+      const int n = b[i].Ns[s];
+      int rc = q.add(gemm_desc(b[i].ULt[s], n, b[i].UR[s], n, b[i].E[s], 2 * n, n, n, b[i].N));
+      if (rc) return rc;
     }
+  int rc = q.flush();
+  if (rc) return rc;
+  const int nsec = L.Ns[0] == L.Ns[1] ? 1 : 2;
+  for (int sec = 0; sec < nsec; ++sec) {
+    ElimSpin es[kMaxMats];
+    double *E[kMaxMats], *out[kMaxMats];
+    int m = 0;
+    for (int i = 0; i < b.n; ++i)
+      for (int s = 0; s < 2; ++s) {
+        if (nsec == 2 && s != sec) continue;
+        es[m] = elim_spin(b[i], s);
+        E[m] = b[i].E[s];
+        out[m] = b[i].T[s];
+        ++m;
+      }
+    const int n = es[0].n;
+    PQ_HIP_CHECK(set_identity_block(E, m, 2 * n, n, n, L.st));
+    PQ_HIP_CHECK(gj_invert(es, m, out, n, L.st));
   }
   return PQMC_OK;
 }
@@ -304,88 +352,101 @@ double *slot(double *stack, int j, const pqmc_ctx &c, int s) {
 }
 
 // position l-1 -> l: U_R <- B_l U_R, U_L <- U_L B_l^{-1}   (Eq. (9))
-int prop_forward(pqmc_ctx &c, int l) {
-  const int8_t *row = c.fields + (size_t)(l - 1) * c.N;
-  GemmBatch gb{};
-  double *nur[2], *nul[2];
-  for (int s = 0; s < 2; ++s) {
-    const int n = c.Ns[s];
-    const double ep = std::exp(c.alpha * kSpin[s]), em = std::exp(-c.alpha * kSpin[s]);
-    nur[s] = other(c.UR[s], c.URw[s]);
-    nul[s] = other(c.ULt[s], c.ULw[s]);
-    GemmDesc d = gemm_desc(c.K, c.N, c.UR[s], n, nur[s], n, c.N, n, c.N);
-    d.rs_field = row; d.rs_pos = ep; d.rs_neg = em;
-    gb.d[gb.count++] = d;
-    GemmDesc e = gemm_desc(c.Kinv, c.N, c.ULt[s], n, nul[s], n, c.N, n, c.N);
-    e.rs_field = row; e.rs_pos = em; e.rs_neg = ep;
-    gb.d[gb.count++] = e;
+int prop_forward(const Walkers &b, int l) {
+  pqmc_ctx &L = b.lead();
+  GemmQueue q{L.st, false, false};
+  KTimer kt(L, PQMC_K_PROPAGATE);
+  for (int i = 0; i < b.n; ++i) {
+    pqmc_ctx &c = b[i];
+    const int8_t *row = c.fields + (size_t)(l - 1) * c.N;
+    for (int s = 0; s < 2; ++s) {
+      const int n = c.Ns[s];
+      const double ep = std::exp(c.alpha * kSpin[s]), em = std::exp(-c.alpha * kSpin[s]);
+      double *nur = other(c.UR[s], c.URw[s]);
+      double *nul = other(c.ULt[s], c.ULw[s]);
+      GemmDesc d = gemm_desc(c.K, c.N, c.UR[s], n, nur, n, c.N, n, c.N);
+      d.rs_field = row; d.rs_pos = ep; d.rs_neg = em;
+      int rc = q.add(d);
+      GemmDesc e = gemm_desc(c.Kinv, c.N, c.ULt[s], n, nul, n, c.N, n, c.N);
+      e.rs_field = row; e.rs_pos = em; e.rs_neg = ep;
+      if (!rc) rc = q.add(e);
+      if (rc) return rc;
+      c.UR[s] = nur;
+      c.ULt[s] = nul;
+    }
   }
-  {
-    KTimer kt(c, PQMC_K_PROPAGATE);
-    PQ_HIP_CHECK(gemm(gb, false, false, c.st));
-  }
-  for (int s = 0; s < 2; ++s) { c.UR[s] = nur[s]; c.ULt[s] = nul[s]; }
-  return PQMC_OK;
+  return q.flush();
 }
 
 // position l -> l-1: U_L <- U_L B_l, U_R <- B_l^{-1} U_R
-int prop_backward(pqmc_ctx &c, int l, bool with_R) {
-  const int8_t *row = c.fields + (size_t)(l - 1) * c.N;
-  GemmBatch gb{};
-  double *nur[2], *nul[2];
-  for (int s = 0; s < 2; ++s) {
-    const int n = c.Ns[s];
-    const double ep = std::exp(c.alpha * kSpin[s]), em = std::exp(-c.alpha * kSpin[s]);
-    nul[s] = other(c.ULt[s], c.ULw[s]);
-    GemmDesc d = gemm_desc(c.K, c.N, c.ULt[s], n, nul[s], n, c.N, n, c.N);
-    d.ks_field = row; d.ks_pos = ep; d.ks_neg = em;
-    gb.d[gb.count++] = d;
-    if (with_R) {
-      nur[s] = other(c.UR[s], c.URw[s]);
-      GemmDesc e = gemm_desc(c.Kinv, c.N, c.UR[s], n, nur[s], n, c.N, n, c.N);
-      e.ks_field = row; e.ks_pos = em; e.ks_neg = ep;
-      gb.d[gb.count++] = e;
+int prop_backward(const Walkers &b, int l, bool with_R) {
+  pqmc_ctx &L = b.lead();
+  GemmQueue q{L.st, false, false};
+  KTimer kt(L, with_R ? PQMC_K_PROPAGATE : -1);
+  for (int i = 0; i < b.n; ++i) {
+    pqmc_ctx &c = b[i];
+    const int8_t *row = c.fields + (size_t)(l - 1) * c.N;
+    for (int s = 0; s < 2; ++s) {
+      const int n = c.Ns[s];
+      const double ep = std::exp(c.alpha * kSpin[s]), em = std::exp(-c.alpha * kSpin[s]);
+      double *nul = other(c.ULt[s], c.ULw[s]);
+      GemmDesc d = gemm_desc(c.K, c.N, c.ULt[s], n, nul, n, c.N, n, c.N);
+      d.ks_field = row; d.ks_pos = ep; d.ks_neg = em;
+      int rc = q.add(d);
+      if (rc) return rc;
+      c.ULt[s] = nul;
+      if (with_R) {
+        double *nur = other(c.UR[s], c.URw[s]);
+        GemmDesc e = gemm_desc(c.Kinv, c.N, c.UR[s], n, nur, n, c.N, n, c.N);
+        e.ks_field = row; e.ks_pos = em; e.ks_neg = ep;
+        rc = q.add(e);
+        if (rc) return rc;
+        c.UR[s] = nur;
+      }
     }
   }
-  {
-    KTimer kt(c, with_R ? PQMC_K_PROPAGATE : -1);
-    PQ_HIP_CHECK(gemm(gb, false, false, c.st));
-  }
-  for (int s = 0; s < 2; ++s) {
-    c.ULt[s] = nul[s];
-    if (with_R) c.UR[s] = nur[s];
-  }
-  return PQMC_OK;
+  return q.flush();
 }
 
 // Initial stack of row-orthonormalised U_L and position-0 state (Sec. II B).
-int build_state(pqmc_ctx &c) {
-  for (int s = 0; s < 2; ++s) {
-    const int n = c.Ns[s];
-    PQ_HIP_CHECK(copy_matrix(c.P[s], nullptr, n, slot(c.Lstack[s], c.nst, c, s), nullptr, n, c.N,
-                             n, c.st));
-    PQ_HIP_CHECK(copy_matrix(c.P[s], nullptr, n, slot(c.Rstack[s], 0, c, s), nullptr, n, c.N, n,
-                             c.st));
-    c.ULt[s] = slot(c.Lstack[s], c.nst, c, s);
-  }
-  for (int l = c.M; l >= 1; --l) {
-    int rc = prop_backward(c, l, false);
-    if (rc) return rc;
-    if ((l - 1) % c.kt == 0) {
-      const int j = (l - 1) / c.kt;
-      double *src[2] = {c.ULt[0], c.ULt[1]};
-      double *dst[2] = {slot(c.Lstack[0], j, c, 0), slot(c.Lstack[1], j, c, 1)};
-      rc = orthonormalize(c, src, dst);
-      if (rc) return rc;
-      c.ULt[0] = dst[0];
-      c.ULt[1] = dst[1];
+int build_state(const Walkers &b) {
+  for (int i = 0; i < b.n; ++i) {
+    pqmc_ctx &c = b[i];
+    for (int s = 0; s < 2; ++s) {
+      const int n = c.Ns[s];
+      PQ_HIP_CHECK(copy_matrix(c.P[s], nullptr, n, slot(c.Lstack[s], c.nst, c, s), nullptr, n,
+                               c.N, n, c.st));
+      PQ_HIP_CHECK(copy_matrix(c.P[s], nullptr, n, slot(c.Rstack[s], 0, c, s), nullptr, n, c.N,
+                               n, c.st));
+      c.ULt[s] = slot(c.Lstack[s], c.nst, c, s);
     }
   }
-  for (int s = 0; s < 2; ++s) c.UR[s] = slot(c.Rstack[s], 0, c, s);
-  int rc = refresh_T(c);
+  const pqmc_ctx &L = b.lead();
+  for (int l = L.M; l >= 1; --l) {
+    int rc = prop_backward(b, l, false);
+    if (rc) return rc;
+    if ((l - 1) % L.kt == 0) {
+      const int j = (l - 1) / L.kt;
+      double *src[kMaxMats], *dst[kMaxMats];
+      for (int i = 0; i < b.n; ++i)
+        for (int s = 0; s < 2; ++s) {
+          src[2 * i + s] = b[i].ULt[s];
+          dst[2 * i + s] = slot(b[i].Lstack[s], j, b[i], s);
+        }
+      rc = orthonormalize(b, src, dst);
+      if (rc) return rc;
+      for (int i = 0; i < b.n; ++i)
+        for (int s = 0; s < 2; ++s) b[i].ULt[s] = dst[2 * i + s];
+    }
+  }
+  for (int i = 0; i < b.n; ++i)
+    for (int s = 0; s < 2; ++s) b[i].UR[s] = slot(b[i].Rstack[s], 0, b[i], s);
+  int rc = refresh_T(b);
   if (rc) return rc;
-  c.position = 0;
-  c.windowed = false;
+  for (int i = 0; i < b.n; ++i) {
+    b[i].position = 0;
+    b[i].windowed = false;
+  }
   return PQMC_OK;
 }
 
@@ -394,7 +455,7 @@ int build_state(pqmc_ctx &c) {
 int expm_taylor(pqmc_ctx &c, double scale, int sq, double *dst) {
   const int N = c.N;
   double *Y = dst, *Yn = c.Tay1;
-  PQ_HIP_CHECK(set_identity_block(Y, nullptr, N, N, 0, c.st));
+  PQ_HIP_CHECK(set_identity_block(&Y, 1, N, N, 0, c.st));
   for (int j = 18; j >= 1; --j) {
     GemmBatch gb{};
     GemmDesc d = gemm_desc(c.Tay0, N, Y, N, Yn, N, N, N, N, scale / j);
@@ -442,31 +503,40 @@ SweepCtx sweep_ctx(pqmc_ctx &c, int l, int dir) {
   return x;
 }
 
-int update_slice(pqmc_ctx &c, int l, int dir) {
-  SweepCtx x = sweep_ctx(c, l, dir);
-  SpinMats m{};
-  for (int s = 0; s < 2; ++s) {
-    m.T[s] = c.T[s];
-    m.UR[s] = c.UR[s];
-    m.ULt[s] = c.ULt[s];
-    m.Ns[s] = c.Ns[s];
+int update_slice(const Walkers &b, int l, int dir) {
+  pqmc_ctx &L = b.lead();
+  SweepCtx x[kMaxBatch];
+  SpinMats m[kMaxBatch];
+  LocalBufs lb[kMaxBatch];
+  GroupBufs gb[kMaxBatch];
+  for (int i = 0; i < b.n; ++i) {
+    pqmc_ctx &c = b[i];
+    x[i] = sweep_ctx(c, l, dir);
+    for (int s = 0; s < 2; ++s) {
+      m[i].T[s] = c.T[s];
+      m[i].UR[s] = c.UR[s];
+      m[i].ULt[s] = c.ULt[s];
+      m[i].Ns[s] = c.Ns[s];
+    }
+    lb[i] = c.lb;
+    gb[i] = c.gb;
   }
-  const int N = c.N;
-  switch (c.opts.scheme) {
+  const int N = L.N, nw = b.n;
+  switch (L.opts.scheme) {
     case PQMC_LOCAL: {
-      const int nt = ceil_div(std::max(c.Ns[0], c.Ns[1]), 64);
+      const int nt = ceil_div(std::max(L.Ns[0], L.Ns[1]), 64);
       for (int i = 0; i <= N; ++i) {
-        KTimer kt(c, PQMC_K_LOCAL);
-        PQ_HIP_CHECK(local_step(m, c.lb, x, i, nt, c.st));
+        KTimer kt(L, PQMC_K_LOCAL);
+        PQ_HIP_CHECK(local_step(m, lb, x, nw, i, nt, L.st));
       }
-      c.log_count += N;
+      for (int i = 0; i < nw; ++i) b[i].log_count += N;
       break;
     }
     case PQMC_DELAYED:
     default: {
-      const bool delayed = c.opts.scheme == PQMC_DELAYED;
-      const int k = std::min(delayed ? c.opts.delay_k : c.opts.block_b, N);
-      const bool fused = c.gmax <= 64;
+      const bool delayed = L.opts.scheme == PQMC_DELAYED;
+      const int k = std::min(delayed ? L.opts.delay_k : L.opts.block_b, N);
+      const bool fused = L.gmax <= 64;
       const int mode = delayed ? kUniDelayed : kUniBlock;
       long long bi = 0;
       int g_prev = -1, kk_prev = 0;
@@ -474,35 +544,37 @@ int update_slice(pqmc_ctx &c, int l, int dir) {
         const int kk = std::min(k, N - g0);
         if (fused) {
           {
-            KTimer kt(c, PQMC_K_TILE);
-            PQ_HIP_CHECK(group_tile(m, c.gb, g_prev >= 0, g_prev, kk_prev, g0, kk, c.st));
+            KTimer kt(L, PQMC_K_TILE);
+            PQ_HIP_CHECK(group_tile(m, gb, nw, g_prev >= 0, g_prev, kk_prev, g0, kk, L.st));
           }
-          KTimer kt(c, PQMC_K_REDUCE);
-          PQ_HIP_CHECK(group_reduce(m, c.gb, x, mode, g0, kk, c.st));
+          KTimer kt(L, PQMC_K_REDUCE);
+          PQ_HIP_CHECK(group_reduce(m, gb, x, nw, mode, g0, kk, L.st));
         } else {
-          PQ_HIP_CHECK(group_panels(m, c.gb, x, mode, g0, kk, c.st));
+          PQ_HIP_CHECK(group_panels(m, gb, x, nw, mode, g0, kk, L.st));
         }
         {
-          KTimer kt(c, PQMC_K_DECIDE);
-          if (delayed) PQ_HIP_CHECK(delayed_decide(c.gb, x, g0, kk, c.st));
-          else PQ_HIP_CHECK(block_decide(c.gb, x, g0, kk, bi, c.st));
+          KTimer kt(L, PQMC_K_DECIDE);
+          if (delayed) PQ_HIP_CHECK(delayed_decide(gb, x, nw, g0, kk, L.st));
+          else PQ_HIP_CHECK(block_decide(gb, x, nw, g0, kk, bi, L.st));
         }
         if (fused) {
           g_prev = g0;
           kk_prev = kk;
         } else {
-          PQ_HIP_CHECK(group_flush(m, c.gb, g0, kk, c.st));
+          PQ_HIP_CHECK(group_flush(m, gb, nw, g0, kk, L.st));
         }
       }
       if (fused && g_prev >= 0) {
-        KTimer kt(c, PQMC_K_TILE);
-        PQ_HIP_CHECK(group_tile(m, c.gb, true, g_prev, kk_prev, 0, 0, c.st));
+        KTimer kt(L, PQMC_K_TILE);
+        PQ_HIP_CHECK(group_tile(m, gb, nw, true, g_prev, kk_prev, 0, 0, L.st));
       }
-      if (delayed) {
-        c.log_count += N;
-      } else {
-        c.log_count += bi;
-        c.hb_count += N;
+      for (int i = 0; i < nw; ++i) {
+        if (delayed) {
+          b[i].log_count += N;
+        } else {
+          b[i].log_count += bi;
+          b[i].hb_count += N;
+        }
       }
       break;
     }
@@ -510,30 +582,40 @@ int update_slice(pqmc_ctx &c, int l, int dir) {
   return PQMC_OK;
 }
 
-int stab_forward(pqmc_ctx &c, int l) {
-  const int j = l / c.kt;
-  double *src[2] = {c.UR[0], c.UR[1]};
-  double *dst[2] = {slot(c.Rstack[0], j, c, 0), slot(c.Rstack[1], j, c, 1)};
-  int rc = orthonormalize(c, src, dst);
+int stab_forward(const Walkers &b, int l) {
+  const int j = l / b.lead().kt;
+  double *src[kMaxMats], *dst[kMaxMats];
+  for (int i = 0; i < b.n; ++i)
+    for (int s = 0; s < 2; ++s) {
+      src[2 * i + s] = b[i].UR[s];
+      dst[2 * i + s] = slot(b[i].Rstack[s], j, b[i], s);
+    }
+  int rc = orthonormalize(b, src, dst);
   if (rc) return rc;
-  for (int s = 0; s < 2; ++s) {
-    c.UR[s] = dst[s];
-    c.ULt[s] = slot(c.Lstack[s], j, c, s);
-  }
-  return refresh_T(c);
+  for (int i = 0; i < b.n; ++i)
+    for (int s = 0; s < 2; ++s) {
+      b[i].UR[s] = dst[2 * i + s];
+      b[i].ULt[s] = slot(b[i].Lstack[s], j, b[i], s);
+    }
+  return refresh_T(b);
 }
 
-int stab_backward(pqmc_ctx &c, int l) {
-  const int j = (l - 1) / c.kt;
-  double *src[2] = {c.ULt[0], c.ULt[1]};
-  double *dst[2] = {slot(c.Lstack[0], j, c, 0), slot(c.Lstack[1], j, c, 1)};
-  int rc = orthonormalize(c, src, dst);
+int stab_backward(const Walkers &b, int l) {
+  const int j = (l - 1) / b.lead().kt;
+  double *src[kMaxMats], *dst[kMaxMats];
+  for (int i = 0; i < b.n; ++i)
+    for (int s = 0; s < 2; ++s) {
+      src[2 * i + s] = b[i].ULt[s];
+      dst[2 * i + s] = slot(b[i].Lstack[s], j, b[i], s);
+    }
+  int rc = orthonormalize(b, src, dst);
   if (rc) return rc;
-  for (int s = 0; s < 2; ++s) {
-    c.ULt[s] = dst[s];
-    c.UR[s] = slot(c.Rstack[s], j, c, s);
-  }
-  return refresh_T(c);
+  for (int i = 0; i < b.n; ++i)
+    for (int s = 0; s < 2; ++s) {
+      b[i].ULt[s] = dst[2 * i + s];
+      b[i].UR[s] = slot(b[i].Rstack[s], j, b[i], s);
+    }
+  return refresh_T(b);
 }
 
 // phase timing: events recorded at boundaries, summed per phase at the end
@@ -594,13 +676,13 @@ void resolve_kernel_times(pqmc_ctx &c) {
   }
 }
 
-int finish_call(pqmc_ctx &c, PhaseTimer &tm, double t0, pqmc_stats *out) {
-  int rc = tm.mark(kPhEnd);
-  if (rc) return rc;
-  rc = sync_check(c);
-  resolve_kernel_times(c);
-  const double t1 =
-      std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// Statistics of one walker after the batch's work has completed.
+int finish_walker(pqmc_ctx &c, const double ph[3], double t_total, pqmc_stats *out) {
+  int rc = sync_check(c);
   if (out) {
     unsigned long long h[16];
     PQ_HIP_CHECK(hipMemcpy(h, c.stats, sizeof h, hipMemcpyDeviceToHost));
@@ -611,9 +693,7 @@ int finish_call(pqmc_ctx &c, PhaseTimer &tm, double t0, pqmc_stats *out) {
     out->low_margin = h[kStLowMargin];
     out->negative = h[kStNegative];
     out->field_updates = h[kStFieldUpdates];
-    out->t_total_s = t1 - t0;
-    double ph[3];
-    tm.totals(ph);
+    out->t_total_s = t_total;
     out->t_update_s = ph[kPhUpdate];
     out->t_prop_s = ph[kPhProp];
     out->t_stab_s = ph[kPhStab];
@@ -622,38 +702,70 @@ int finish_call(pqmc_ctx &c, PhaseTimer &tm, double t0, pqmc_stats *out) {
   return rc;
 }
 
-double now_s() {
-  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+int finish_call(const Walkers &b, PhaseTimer &tm, double t0, pqmc_stats *out) {
+  pqmc_ctx &L = b.lead();
+  int rc = tm.mark(kPhEnd);
+  if (rc) return rc;
+  PQ_HIP_CHECK(hipStreamSynchronize(L.st));
+  resolve_kernel_times(L);
+  const double t1 = now_s();
+  double ph[3];
+  tm.totals(ph);
+  for (int i = 0; i < b.n; ++i) {
+    const int r = finish_walker(b[i], ph, t1 - t0, out ? out + i : nullptr);
+    if (r && !rc) rc = r;
+  }
+  return rc;
 }
 
-int run_forward(pqmc_ctx &c, int upto, PhaseTimer &tm) {
+int run_forward(const Walkers &b, int upto, PhaseTimer &tm) {
+  const int kt = b.lead().kt;
   for (int l = 1; l <= upto; ++l) {
     int rc = tm.mark(kPhProp);
-    if (!rc) rc = prop_forward(c, l);
+    if (!rc) rc = prop_forward(b, l);
     if (!rc) rc = tm.mark(kPhUpdate);
-    if (!rc) rc = update_slice(c, l, 0);
-    if (!rc && l % c.kt == 0) {
+    if (!rc) rc = update_slice(b, l, 0);
+    if (!rc && l % kt == 0) {
       rc = tm.mark(kPhStab);
-      if (!rc) rc = stab_forward(c, l);
+      if (!rc) rc = stab_forward(b, l);
     }
     if (rc) return rc;
-    c.position = l;
+    for (int i = 0; i < b.n; ++i) b[i].position = l;
   }
   return PQMC_OK;
 }
 
-int run_backward(pqmc_ctx &c, PhaseTimer &tm) {
-  for (int l = c.M; l >= 1; --l) {
+int run_backward(const Walkers &b, PhaseTimer &tm) {
+  const int M = b.lead().M, kt = b.lead().kt;
+  for (int l = M; l >= 1; --l) {
     int rc = tm.mark(kPhUpdate);
-    if (!rc) rc = update_slice(c, l, 1);
+    if (!rc) rc = update_slice(b, l, 1);
     if (!rc) rc = tm.mark(kPhProp);
-    if (!rc) rc = prop_backward(c, l, true);
-    if (!rc && (l - 1) % c.kt == 0) {
+    if (!rc) rc = prop_backward(b, l, true);
+    if (!rc && (l - 1) % kt == 0) {
       rc = tm.mark(kPhStab);
-      if (!rc) rc = stab_backward(c, l);
+      if (!rc) rc = stab_backward(b, l);
     }
     if (rc) return rc;
-    c.position = l - 1;
+    for (int i = 0; i < b.n; ++i) b[i].position = l - 1;
+  }
+  return PQMC_OK;
+}
+
+// Walkers run together must agree on everything that shapes the launches.
+pqmc_status check_batch(pqmc_ctx *const *w, int n) {
+  if (!w || n < 1 || n > kMaxBatch) return set_error(PQMC_EINVAL, "batch size must be 1..8");
+  for (int i = 0; i < n; ++i) {
+    if (!w[i]) return set_error(PQMC_EINVAL, "null context in batch");
+    const pqmc_ctx &a = *w[0], &c = *w[i];
+    if (c.N != a.N || c.Ns[0] != a.Ns[0] || c.Ns[1] != a.Ns[1] || c.M != a.M || c.kt != a.kt ||
+        c.gmax != a.gmax || c.opts.scheme != a.opts.scheme || c.opts.delay_k != a.opts.delay_k ||
+        c.opts.block_b != a.opts.block_b || c.st != a.st)
+      return set_error(PQMC_EINVAL,
+                       "batched walkers need the same N, N_sigma, M, k_tau, scheme, k, b, stream");
+    for (int j = 0; j < i; ++j)
+      if (w[j] == w[i]) return set_error(PQMC_EINVAL, "a context appears twice in the batch");
+    if (c.failed) return set_error(PQMC_ESTATE, "context failed; call pqmc_set_fields");
   }
   return PQMC_OK;
 }
@@ -735,7 +847,10 @@ pqmc_status pqmc_create(const pqmc_problem *prob, const pqmc_update_opts *opts, 
     hipError_t e = init_fields(c->fields, c->M, N, c->seed, c->walker, c->st);
     if (e != hipSuccess) rc = fail_device(e, "init_fields", __FILE__, __LINE__);
   }
-  if (!rc) rc = build_state(*c);
+  if (!rc) {
+    pqmc_ctx *one[1] = {c};
+    rc = build_state(Walkers{one, 1});
+  }
   if (!rc) rc = sync_check(*c);
   if (rc) return fail(rc);
   *out = c;
@@ -765,7 +880,8 @@ pqmc_status pqmc_set_fields(pqmc_ctx *c, const int8_t *fields) {
   e = hipMemsetAsync(c->stats, 0, 16 * sizeof(unsigned long long), c->st);
   if (e != hipSuccess) return as_status(fail_device(e, "memset", __FILE__, __LINE__));
   c->failed = false;
-  int rc = build_state(*c);
+  pqmc_ctx *one[1] = {c};
+  int rc = build_state(Walkers{one, 1});
   if (!rc) rc = sync_check(*c);
   return as_status(rc);
 }
@@ -779,42 +895,64 @@ pqmc_status pqmc_get_fields(pqmc_ctx *c, int8_t *fields) {
   return PQMC_OK;
 }
 
-pqmc_status pqmc_sweep(pqmc_ctx *c, int32_t n_sweeps, pqmc_stats *out) {
-  if (!c) return set_error(PQMC_EINVAL, "null context");
+pqmc_status pqmc_batch_sweep(pqmc_ctx *const *ctxs, int32_t n, int32_t n_sweeps,
+                             pqmc_stats *out) {
+  pqmc_status v = check_batch(ctxs, n);
+  if (v) return v;
   if (n_sweeps < 0) return set_error(PQMC_EINVAL, "n_sweeps < 0");
-  if (c->failed) return set_error(PQMC_ESTATE, "context failed; call pqmc_set_fields");
-  if (c->windowed || c->position != 0)
-    return set_error(PQMC_ESTATE, "walker is mid-sweep after pqmc_forward_window");
+  for (int i = 0; i < n; ++i)
+    if (ctxs[i]->windowed || ctxs[i]->position != 0)
+      return set_error(PQMC_ESTATE, "walker is mid-sweep after pqmc_forward_window");
+  const Walkers b{ctxs, n};
   const double t0 = now_s();
-  int rc = begin_call(*c);
-  PhaseTimer tm(*c);
+  int rc = PQMC_OK;
+  for (int i = 0; i < n && !rc; ++i) rc = begin_call(b[i]);
+  PhaseTimer tm(b.lead());
   for (int k = 0; k < n_sweeps && !rc; ++k) {
-    rc = run_forward(*c, c->M, tm);
-    if (!rc) rc = run_backward(*c, tm);
-    if (!rc) ++c->sweep_index;
+    rc = run_forward(b, b.lead().M, tm);
+    if (!rc) rc = run_backward(b, tm);
+    if (!rc)
+      for (int i = 0; i < n; ++i) ++b[i].sweep_index;
   }
   if (rc) {
-    c->failed = true;
+    for (int i = 0; i < n; ++i) b[i].failed = true;
     return as_status(rc);
   }
-  return as_status(finish_call(*c, tm, t0, out));
+  return as_status(finish_call(b, tm, t0, out));
+}
+
+pqmc_status pqmc_sweep(pqmc_ctx *c, int32_t n_sweeps, pqmc_stats *out) {
+  if (!c) return set_error(PQMC_EINVAL, "null context");
+  pqmc_ctx *one[1] = {c};
+  return pqmc_batch_sweep(one, 1, n_sweeps, out);
+}
+
+pqmc_status pqmc_batch_forward_window(pqmc_ctx *const *ctxs, int32_t n, int32_t n_slices,
+                                      pqmc_stats *out) {
+  pqmc_status v = check_batch(ctxs, n);
+  if (v) return v;
+  if (n_slices < 0 || n_slices > ctxs[0]->M) return set_error(PQMC_EINVAL, "n_slices out of range");
+  for (int i = 0; i < n; ++i)
+    if (ctxs[i]->windowed || ctxs[i]->position != 0)
+      return set_error(PQMC_ESTATE, "walker is mid-sweep");
+  const Walkers b{ctxs, n};
+  const double t0 = now_s();
+  int rc = PQMC_OK;
+  for (int i = 0; i < n && !rc; ++i) rc = begin_call(b[i]);
+  PhaseTimer tm(b.lead());
+  if (!rc) rc = run_forward(b, n_slices, tm);
+  for (int i = 0; i < n; ++i) b[i].windowed = true;
+  if (rc) {
+    for (int i = 0; i < n; ++i) b[i].failed = true;
+    return as_status(rc);
+  }
+  return as_status(finish_call(b, tm, t0, out));
 }
 
 pqmc_status pqmc_forward_window(pqmc_ctx *c, int32_t n_slices, pqmc_stats *out) {
   if (!c) return set_error(PQMC_EINVAL, "null context");
-  if (n_slices < 0 || n_slices > c->M) return set_error(PQMC_EINVAL, "n_slices out of range");
-  if (c->failed) return set_error(PQMC_ESTATE, "context failed; call pqmc_set_fields");
-  if (c->windowed || c->position != 0) return set_error(PQMC_ESTATE, "walker is mid-sweep");
-  const double t0 = now_s();
-  int rc = begin_call(*c);
-  PhaseTimer tm(*c);
-  if (!rc) rc = run_forward(*c, n_slices, tm);
-  c->windowed = true;
-  if (rc) {
-    c->failed = true;
-    return as_status(rc);
-  }
-  return as_status(finish_call(*c, tm, t0, out));
+  pqmc_ctx *one[1] = {c};
+  return pqmc_batch_forward_window(one, 1, n_slices, out);
 }
 
 pqmc_status pqmc_get_green(pqmc_ctx *c, int32_t spin, double *out) {

@@ -29,9 +29,8 @@ namespace pq {
 namespace {
 
 struct ElimArgs {
-  ElimSpin s[2];
+  ElimSpin s[kMaxMats];
   int kb, nb, pass;
-  unsigned long long *stats;
 };
 
 // Value of v in lane src (src uniform).
@@ -206,7 +205,7 @@ __global__ __launch_bounds__(kLuThreads) void lu_panel_kernel(ElimArgs a) {
     S.prow[kb + pos1] = rr1;
   }
   __syncthreads();
-  if (t == 0 && bad) atomicOr(&a.stats[kStError], (unsigned long long)kErrSingular);
+  if (t == 0 && bad) atomicOr(&S.stats[kStError], (unsigned long long)kErrSingular);
   // (U^T)^{-1}, in place
   tri_lower_inverse(Ut, Tm, false);
   // D (pivot rows in order, original entries) into Lm
@@ -277,7 +276,7 @@ __global__ __launch_bounds__(kCholThreads) void chol_panel_kernel(ElimArgs a) {
 #pragma unroll
       for (int c = 0; c < kNB; ++c) C[i][c] = (c <= i) ? v[c] : 0.0;
     }
-    if (i == 0 && bad) atomicOr(&a.stats[kStError], (unsigned long long)kErrSingular);
+    if (i == 0 && bad) atomicOr(&S.stats[kStError], (unsigned long long)kErrSingular);
   }
   __syncthreads();
   tri_lower_inverse(C, Tm, false);
@@ -409,8 +408,8 @@ __global__ __launch_bounds__(256) void elim_update_kernel(ElimArgs a) {
 
 // T[c, :] = (right half of row prow[c]) after the last Gauss-Jordan pass
 struct GatherArgs {
-  ElimSpin s[2];
-  double *out[2];
+  ElimSpin s[kMaxMats];
+  double *out[kMaxMats];
   long ldo;
   int kb_last, pass_last;
 };
@@ -428,22 +427,31 @@ __global__ void gj_gather_kernel(GatherArgs a) {
   a.out[blockIdx.z][(long)c * a.ldo + j] = src[n + j];
 }
 
-__global__ void fill_int_kernel(int *p0, int *p1, long count, int value) {
-  int *p = blockIdx.y ? p1 : p0;
+struct FillArgs {
+  int *ip[kMaxMats];
+  double *dp[kMaxMats];
+};
+
+__global__ void fill_int_kernel(FillArgs f, long count, int value) {
+  int *p = f.ip[blockIdx.y];
   for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < count;
        e += (long)gridDim.x * blockDim.x)
     p[e] = value;
 }
 
-__global__ void zero_kernel(double *p0, double *p1, long count) {
-  double *p = blockIdx.y ? p1 : p0;
+__global__ void zero_kernel(FillArgs f, long count) {
+  double *p = f.dp[blockIdx.y];
   for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < count;
        e += (long)gridDim.x * blockDim.x)
     p[e] = 0.0;
 }
 
-__global__ void set_identity_kernel(double *E0, double *E1, long ld, int n, int col0) {
-  double *E = blockIdx.z ? E1 : E0;
+struct IdentArgs {
+  double *E[kMaxMats];
+};
+
+__global__ void set_identity_kernel(IdentArgs a, long ld, int n, int col0) {
+  double *E = a.E[blockIdx.z];
   const int r = blockIdx.y;
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c < n) E[(long)r * ld + col0 + c] = (r == c) ? 1.0 : 0.0;
@@ -468,67 +476,72 @@ __global__ void init_fields_kernel(int8_t *f, int M, int N, uint64_t k0, uint64_
 
 }  // namespace
 
-hipError_t gj_invert(const ElimSpin *s, int nspin, unsigned long long *stats,
-                     double *const out[2], long ldo, hipStream_t st) {
+hipError_t gj_invert(const ElimSpin *s, int nmat, double *const *out, long ldo, hipStream_t st) {
+  if (nmat < 1 || nmat > kMaxMats) return hipErrorInvalidValue;
   const int n = s[0].n;
-  for (int i = 1; i < nspin; ++i)
+  for (int i = 1; i < nmat; ++i)
     if (s[i].n != n || s[i].w != s[0].w) return hipErrorInvalidValue;
-  if (n < 1 || n > 2 * kLuThreads || nspin < 1 || nspin > 2) return hipErrorInvalidValue;
+  if (n < 1 || n > 2 * kLuThreads) return hipErrorInvalidValue;
   const int w = s[0].w;
-  hipLaunchKernelGGL(fill_int_kernel, dim3((n + 255) / 256, nspin), dim3(256), 0, st, s[0].slot,
-                     nspin > 1 ? s[1].slot : s[0].slot, (long)n, -1);
+  FillArgs fa{};
+  for (int i = 0; i < nmat; ++i) fa.ip[i] = s[i].slot;
+  hipLaunchKernelGGL(fill_int_kernel, dim3((n + 255) / 256, nmat), dim3(256), 0, st, fa, (long)n,
+                     -1);
   ElimArgs ea{};
-  for (int i = 0; i < nspin; ++i) ea.s[i] = s[i];
-  ea.stats = stats;
+  for (int i = 0; i < nmat; ++i) ea.s[i] = s[i];
   int pass = 0, kb = 0;
   for (; kb < n; kb += kNB, ++pass) {
     ea.kb = kb;
     ea.nb = min(kNB, n - kb);
     ea.pass = pass;
-    hipLaunchKernelGGL(lu_panel_kernel, dim3(nspin), dim3(kLuThreads), 0, st, ea);
+    hipLaunchKernelGGL(lu_panel_kernel, dim3(nmat), dim3(kLuThreads), 0, st, ea);
     const int cols = w - kb - ea.nb;
-    hipLaunchKernelGGL(elim_update_kernel<true>, dim3((n + 63) / 64, (cols + 63) / 64, nspin),
+    hipLaunchKernelGGL(elim_update_kernel<true>, dim3((n + 63) / 64, (cols + 63) / 64, nmat),
                        dim3(256), 0, st, ea);
   }
   GatherArgs ga{};
-  for (int i = 0; i < nspin; ++i) {
+  for (int i = 0; i < nmat; ++i) {
     ga.s[i] = s[i];
     ga.out[i] = out[i];
   }
   ga.ldo = ldo;
   ga.kb_last = kb - kNB;
   ga.pass_last = pass - 1;
-  hipLaunchKernelGGL(gj_gather_kernel, dim3((n + 255) / 256, n, nspin), dim3(256), 0, st, ga);
+  hipLaunchKernelGGL(gj_gather_kernel, dim3((n + 255) / 256, n, nmat), dim3(256), 0, st, ga);
   return hipGetLastError();
 }
 
-hipError_t chol_eliminate(const ElimSpin *s, int nspin, unsigned long long *stats,
-                          hipStream_t st) {
+hipError_t chol_eliminate(const ElimSpin *s, int nmat, hipStream_t st) {
+  if (nmat < 1 || nmat > kMaxMats) return hipErrorInvalidValue;
   const int n = s[0].n;
-  for (int i = 1; i < nspin; ++i)
+  for (int i = 1; i < nmat; ++i)
     if (s[i].n != n || s[i].w != s[0].w) return hipErrorInvalidValue;
-  if (n < 1 || nspin < 1 || nspin > 2 || s[0].w < 2 * n) return hipErrorInvalidValue;
+  if (n < 1 || s[0].w < 2 * n) return hipErrorInvalidValue;
   const int w = s[0].w;
-  hipLaunchKernelGGL(zero_kernel, dim3(256, nspin), dim3(256), 0, st, s[0].F,
-                     nspin > 1 ? s[1].F : s[0].F, (long)n * n);
+  FillArgs fa{};
+  for (int i = 0; i < nmat; ++i) fa.dp[i] = s[i].F;
+  hipLaunchKernelGGL(zero_kernel, dim3(256, nmat), dim3(256), 0, st, fa, (long)n * n);
   ElimArgs ea{};
-  for (int i = 0; i < nspin; ++i) ea.s[i] = s[i];
-  ea.stats = stats;
+  for (int i = 0; i < nmat; ++i) ea.s[i] = s[i];
   for (int kb = 0, pass = 0; kb < n; kb += kNB, ++pass) {
     ea.kb = kb;
     ea.nb = min(kNB, n - kb);
     ea.pass = pass;
-    hipLaunchKernelGGL(chol_panel_kernel, dim3(nspin), dim3(kCholThreads), 0, st, ea);
+    hipLaunchKernelGGL(chol_panel_kernel, dim3(nmat), dim3(kCholThreads), 0, st, ea);
     const int cols = min(w, n + kb + ea.nb) - kb - ea.nb;
     hipLaunchKernelGGL(elim_update_kernel<false>,
-                       dim3((n - kb + 63) / 64, (cols + 63) / 64, nspin), dim3(256), 0, st, ea);
+                       dim3((n - kb + 63) / 64, (cols + 63) / 64, nmat), dim3(256), 0, st, ea);
   }
   return hipGetLastError();
 }
 
-hipError_t set_identity_block(double *E0, double *E1, long ld, int n, int col0, hipStream_t st) {
-  dim3 grid((n + 255) / 256, n, E1 ? 2 : 1);
-  hipLaunchKernelGGL(set_identity_kernel, grid, dim3(256), 0, st, E0, E1, ld, n, col0);
+hipError_t set_identity_block(double *const *E, int nmat, long ld, int n, int col0,
+                              hipStream_t st) {
+  if (nmat < 1 || nmat > kMaxMats) return hipErrorInvalidValue;
+  IdentArgs a{};
+  for (int i = 0; i < nmat; ++i) a.E[i] = E[i];
+  dim3 grid((n + 255) / 256, n, nmat);
+  hipLaunchKernelGGL(set_identity_kernel, grid, dim3(256), 0, st, a, ld, n, col0);
   return hipGetLastError();
 }
 

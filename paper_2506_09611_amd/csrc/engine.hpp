@@ -50,21 +50,34 @@ struct ElimSpin {
   int *slot;       // n: pivot column of row r, -1 while unused (Gauss-Jordan)
   double *BR;      // 2 x kNB x w: new block rows of the last two passes (Gauss-Jordan)
   double *F;       // n x n: rows of R^{-T} (Cholesky)
+  unsigned long long *stats;   // error flags of the owning walker
 };
-// out = M^{-1} (n x n, leading dim ldo) for E = [M | I], n <= 1024, by
-// Gauss-Jordan elimination with partial pivoting.  E is overwritten.
-hipError_t gj_invert(const ElimSpin *s, int nspin, unsigned long long *stats,
-                     double *const out[2], long ldo, hipStream_t st);
+// Up to kMaxMats matrices of the same size per call (two spin sectors of up
+// to kMaxBatch walkers).
+constexpr int kMaxMats = 16;
+// out[i] = M_i^{-1} (n x n, leading dim ldo) for E_i = [M_i | I], n <= 1024,
+// by Gauss-Jordan elimination with partial pivoting.  E_i is overwritten.
+hipError_t gj_invert(const ElimSpin *s, int nmat, double *const *out, long ldo, hipStream_t st);
 // Forward elimination normalised by the Cholesky factor of each diagonal
-// block on E = [S | I], S SPD: F receives R^{-T}, S = R^T R.
-hipError_t chol_eliminate(const ElimSpin *s, int nspin, unsigned long long *stats,
-                          hipStream_t st);
-hipError_t set_identity_block(double *E0, double *E1, long ld, int n, int col0, hipStream_t st);
+// block on E_i = [S_i | I], S_i SPD: F_i receives R_i^{-T}, S_i = R_i^T R_i.
+hipError_t chol_eliminate(const ElimSpin *s, int nmat, hipStream_t st);
+// E_i[r, col0 + c] = (r == c) for r, c < n, i < nmat.
+hipError_t set_identity_block(double *const *E, int nmat, long ld, int n, int col0,
+                              hipStream_t st);
 hipError_t copy_matrix(const double *src0, const double *src1, long lds, double *dst0,
                        double *dst1, long ldd, int rows, int cols, hipStream_t st);
 hipError_t init_fields(int8_t *fields, int M, int N, uint64_t k0, uint64_t k1, hipStream_t st);
 
 // ---------------------------------------------------------- field updates
+// Batched launches: every update kernel takes one argument record per walker
+// (blockIdx.z, or blockIdx.x for the single-workgroup decision kernels), so
+// kMaxBatch independent walkers of the same shape share each launch.
+constexpr int kMaxBatch = 8;
+template <class T>
+struct Batch {
+  T w[kMaxBatch];
+};
+
 struct SpinMats {
   double *T[2];          // Ns x Ns
   double *UR[2];         // N x Ns (rows = u_i^T)
@@ -79,7 +92,7 @@ struct LocalBufs {       // fused local-step partials, double-buffered by site p
 };
 // One launch per site i = 0..N: applies site i-1's decision and rank-1
 // upgrade, then forms the partial ratio products of site i.
-hipError_t local_step(const SpinMats &m, const LocalBufs &b, const SweepCtx &c, int i,
+hipError_t local_step(const SpinMats *m, const LocalBufs *b, const SweepCtx *c, int nw, int i,
                       int nt_max, hipStream_t st);
 
 struct GroupBufs {
@@ -102,19 +115,20 @@ struct GroupBufs {
 };
 // Uniforms drawn by the reduce kernel for the decision that follows it.
 enum UniMode { kUniNone = 0, kUniDelayed = 1, kUniBlock = 2 };
-hipError_t group_panels(const SpinMats &m, const GroupBufs &g, const SweepCtx &c, int mode,
-                        int g0, int kk, hipStream_t st);
-hipError_t delayed_decide(const GroupBufs &g, const SweepCtx &c, int g0, int kk,
+hipError_t group_panels(const SpinMats *m, const GroupBufs *g, const SweepCtx *c, int nw,
+                        int mode, int g0, int kk, hipStream_t st);
+hipError_t delayed_decide(const GroupBufs *g, const SweepCtx *c, int nw, int g0, int kk,
                           hipStream_t st);
-hipError_t block_decide(const GroupBufs &g, const SweepCtx &c, int g0, int kk,
+hipError_t block_decide(const GroupBufs *g, const SweepCtx *c, int nw, int g0, int kk,
                         long long block_index, hipStream_t st);
-hipError_t group_flush(const SpinMats &m, const GroupBufs &g, int g0, int kk, hipStream_t st);
+hipError_t group_flush(const SpinMats *m, const GroupBufs *g, int nw, int g0, int kk,
+                       hipStream_t st);
 // Fused path (kmax <= 64): one tile kernel per group applies the previous
 // group's flush and forms this group's split-K panel partials; group_reduce
 // sums them into P1, P2 and W0.
-hipError_t group_tile(const SpinMats &m, const GroupBufs &g, bool flush, int g0_prev,
+hipError_t group_tile(const SpinMats *m, const GroupBufs *g, int nw, bool flush, int g0_prev,
                       int kk_prev, int g0, int kk, hipStream_t st);
-hipError_t group_reduce(const SpinMats &m, const GroupBufs &g, const SweepCtx &c, int mode,
-                        int g0, int kk, hipStream_t st);
+hipError_t group_reduce(const SpinMats *m, const GroupBufs *g, const SweepCtx *c, int nw,
+                        int mode, int g0, int kk, hipStream_t st);
 
 }  // namespace pq

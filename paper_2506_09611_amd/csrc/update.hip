@@ -53,7 +53,8 @@ __device__ __forceinline__ void record_decision(const SweepCtx &c, long long idx
   }
 }
 
-__global__ __launch_bounds__(256) void local_step_kernel(LocalArgs a) {
+__global__ __launch_bounds__(256) void local_step_kernel(Batch<LocalArgs> B) {
+  const LocalArgs &a = B.w[blockIdx.z];
   const int s = blockIdx.y;
   const int Ns = a.m.Ns[s];
   const int nt = (Ns + 63) / 64;
@@ -238,7 +239,8 @@ __device__ __forceinline__ void sum_pair(const double *p, const double *q, bool 
 // P1[strip rows, :]; W0 workgroup m adds the partials of row m of W0 in a
 // fixed order; the last workgroup (spin 0) draws the group's uniforms.  No
 // workgroup depends on another.
-__global__ __launch_bounds__(kRedThreads) void group_reduce_kernel(ReduceArgs a) {
+__global__ __launch_bounds__(kRedThreads) void group_reduce_kernel(Batch<ReduceArgs> B) {
+  const ReduceArgs &a = B.w[blockIdx.z];
   const int s = blockIdx.y;
   const int t = threadIdx.x;
   const int kk = a.kk, kmax = a.g.kmax;
@@ -344,7 +346,8 @@ struct DecideArgs {
 // kDecThreads lanes, kDecQ = ceil(kk * kk / kDecThreads) elements of each
 // spin's E per lane (kk <= kDecThreads).
 template <int kDecThreads, int kDecQ>
-__global__ __launch_bounds__(kDecThreads) void delayed_decide_kernel(DecideArgs A) {
+__global__ __launch_bounds__(kDecThreads) void delayed_decide_kernel(Batch<DecideArgs> B) {
+  const DecideArgs &A = B.w[blockIdx.x];
   const int kk = A.kk;
   const int t = threadIdx.x;
   const SweepCtx &C = A.c;
@@ -491,7 +494,8 @@ __device__ __forceinline__ double recip(double p) {
 }
 
 template <int NT, int KK>
-__global__ __launch_bounds__(NT) void delayed_decide_blocked_kernel(DecideArgs A) {
+__global__ __launch_bounds__(NT) void delayed_decide_blocked_kernel(Batch<DecideArgs> B) {
+  const DecideArgs &A = B.w[blockIdx.x];
   static_assert(KK * KK % NT == 0 && KK <= 64, "tile shape");
   constexpr int EPT = KK * KK / NT;           // elements of each spin's E per lane
   const int kk = A.kk;
@@ -716,7 +720,8 @@ __global__ __launch_bounds__(NT) void delayed_decide_blocked_kernel(DecideArgs A
 // element (principal pivot transform), so decisions follow one another
 // without barriers or shared-memory round trips.
 template <int KK>
-__global__ __launch_bounds__(64) void delayed_decide_wave_kernel(DecideArgs A) {
+__global__ __launch_bounds__(64) void delayed_decide_wave_kernel(Batch<DecideArgs> B) {
+  const DecideArgs &A = B.w[blockIdx.x];
   constexpr int R = KK / 8;
   static_assert(KK % 8 == 0 && R >= 1 && R <= 4, "tile shape");
   const int kk = A.kk;
@@ -916,7 +921,8 @@ __device__ double lds_gj_inverse(double *A, int ld, int n, double *colk, double 
 // det[1 + W0_FF diag(Delta'_F)] per spin and the Metropolis test with the
 // prior ratio (Sec. III B).  Both small inversions use partial pivoting.
 template <int NT>
-__global__ __launch_bounds__(NT) void block_decide_kernel(DecideArgs A) {
+__global__ __launch_bounds__(NT) void block_decide_kernel(Batch<DecideArgs> B) {
+  const DecideArgs &A = B.w[blockIdx.x];
   const int kk = A.kk;
   const int t = threadIdx.x;
   const SweepCtx &C = A.c;
@@ -1080,7 +1086,8 @@ struct QArgs {
   int g0, kk;
 };
 
-__global__ __launch_bounds__(256) void group_q_kernel(QArgs a) {
+__global__ __launch_bounds__(256) void group_q_kernel(Batch<QArgs> B) {
+  const QArgs &a = B.w[blockIdx.z];
   const int s = blockIdx.y;
   const int Ns = a.m.Ns[s];
   const int nt = (Ns + 63) / 64;
@@ -1134,7 +1141,8 @@ constexpr int kLdt = 65;   // padded LDS row stride
 
 // KP: kmax rounded up to a multiple of 16 (16, 32 or 64).
 template <int KP>
-__global__ __launch_bounds__(256) void group_tile_kernel(TileArgs a) {
+__global__ __launch_bounds__(256) void group_tile_kernel(Batch<TileArgs> B) {
+  const TileArgs &a = B.w[blockIdx.z];
   constexpr int kPre = KP / 4;                       // per lane: a 64 x KP operand
   constexpr int kPreM = KP * KP >= 256 ? KP * KP / 256 : 1;   // per lane: KP x KP
   constexpr int kpad = KP;
@@ -1326,89 +1334,125 @@ __global__ __launch_bounds__(256) void group_tile_kernel(TileArgs a) {
 
 }  // namespace
 
-hipError_t local_step(const SpinMats &m, const LocalBufs &b, const SweepCtx &c, int i,
+// kernel arguments are passed by value: keep every batch within 4 KB
+static_assert(sizeof(Batch<LocalArgs>) <= 4096 && sizeof(Batch<ReduceArgs>) <= 4096 &&
+                  sizeof(Batch<DecideArgs>) <= 4096 && sizeof(Batch<QArgs>) <= 4096 &&
+                  sizeof(Batch<TileArgs>) <= 4096,
+              "kernel argument batch above 4 KB");
+
+hipError_t local_step(const SpinMats *m, const LocalBufs *b, const SweepCtx *c, int nw, int i,
                       int nt_max, hipStream_t st) {
-  LocalArgs a{m, b, c, i};
-  hipLaunchKernelGGL(local_step_kernel, dim3(nt_max * nt_max, 2), dim3(256), 0, st, a);
+  if (nw < 1 || nw > kMaxBatch) return hipErrorInvalidValue;
+  Batch<LocalArgs> B{};
+  for (int w = 0; w < nw; ++w) B.w[w] = LocalArgs{m[w], b[w], c[w], i};
+  hipLaunchKernelGGL(local_step_kernel, dim3(nt_max * nt_max, 2, nw), dim3(256), 0, st, B);
   return hipGetLastError();
 }
 
 namespace {
-hipError_t launch_reduce(const SpinMats &m, const GroupBufs &g, const SweepCtx &c, int mode,
-                         int g0, int kk, int do_panels, int w0_mode, hipStream_t st) {
-  const int ntm = (max(m.Ns[0], m.Ns[1]) + 63) / 64;
-  ReduceArgs ra{m, g, g0, kk, do_panels, w0_mode, mode, c.key0, c.key1, c.sweep, c.slice_code};
+int max_tiles(const SpinMats *m, int nw) {
+  int ns = 0;
+  for (int w = 0; w < nw; ++w) ns = max(ns, max(m[w].Ns[0], m[w].Ns[1]));
+  return (ns + 63) / 64;
+}
+
+hipError_t launch_reduce(const SpinMats *m, const GroupBufs *g, const SweepCtx *c, int nw,
+                         int mode, int g0, int kk, int do_panels, int w0_mode, hipStream_t st) {
+  if (nw < 1 || nw > kMaxBatch) return hipErrorInvalidValue;
+  const int ntm = max_tiles(m, nw);
+  Batch<ReduceArgs> B{};
+  for (int w = 0; w < nw; ++w)
+    B.w[w] = ReduceArgs{m[w], g[w], g0, kk, do_panels, w0_mode, mode,
+                        c[w].key0, c[w].key1, c[w].sweep, c[w].slice_code};
   const int nP = do_panels ? ntm * kRedParts : 0, nW = w0_mode ? kk : 0;
-  hipLaunchKernelGGL(group_reduce_kernel, dim3(nP + nW + 1, 2), dim3(kRedThreads), 0, st, ra);
+  hipLaunchKernelGGL(group_reduce_kernel, dim3(nP + nW + 1, 2, nw), dim3(kRedThreads), 0, st, B);
   return hipGetLastError();
 }
 }  // namespace
 
-hipError_t group_panels(const SpinMats &m, const GroupBufs &g, const SweepCtx &c, int mode,
-                        int g0, int kk, hipStream_t st) {
-  GemmBatch b2{}, b1{};
-  for (int s = 0; s < 2; ++s) {
-    const int Ns = m.Ns[s];
-    GemmDesc d = gemm_desc(m.UR[s] + (long)g0 * Ns, Ns, m.T[s], Ns, g.P2part[s], Ns, kk, Ns, Ns);
-    d.ksplit = 64;
-    d.csplit = (long)g.kmax * Ns;
-    b2.d[b2.count++] = d;
-    GemmDesc e = gemm_desc(m.T[s], Ns, m.ULt[s] + (long)g0 * Ns, Ns, g.P1part[s], g.kmax, Ns, kk,
-                           Ns);
-    e.ksplit = 64;
-    e.csplit = (long)Ns * g.kmax;
-    b1.d[b1.count++] = e;
+hipError_t group_panels(const SpinMats *m, const GroupBufs *g, const SweepCtx *c, int nw,
+                        int mode, int g0, int kk, hipStream_t st) {
+  if (nw < 1 || nw > kMaxBatch) return hipErrorInvalidValue;
+  // split-K partial panels, then their sums (and the group's uniforms)
+  for (int w0 = 0; w0 < nw; w0 += kGemmMaxBatch / 2) {
+    GemmBatch b2{}, b1{};
+    for (int w = w0; w < min(nw, w0 + kGemmMaxBatch / 2); ++w)
+      for (int s = 0; s < 2; ++s) {
+        const int Ns = m[w].Ns[s];
+        GemmDesc d = gemm_desc(m[w].UR[s] + (long)g0 * Ns, Ns, m[w].T[s], Ns, g[w].P2part[s], Ns,
+                               kk, Ns, Ns);
+        d.ksplit = 64;
+        d.csplit = (long)g[w].kmax * Ns;
+        b2.d[b2.count++] = d;
+        GemmDesc e = gemm_desc(m[w].T[s], Ns, m[w].ULt[s] + (long)g0 * Ns, Ns, g[w].P1part[s],
+                               g[w].kmax, Ns, kk, Ns);
+        e.ksplit = 64;
+        e.csplit = (long)Ns * g[w].kmax;
+        b1.d[b1.count++] = e;
+      }
+    hipError_t err = gemm(b2, false, false, st);
+    if (err != hipSuccess) return err;
+    err = gemm(b1, false, true, st);
+    if (err != hipSuccess) return err;
   }
-  hipError_t err = gemm(b2, false, false, st);
-  if (err != hipSuccess) return err;
-  err = gemm(b1, false, true, st);
-  if (err != hipSuccess) return err;
-  err = launch_reduce(m, g, c, mode, g0, kk, 1, 0, st);
+  hipError_t err = launch_reduce(m, g, c, nw, mode, g0, kk, 1, 0, st);
   if (err != hipSuccess) return err;
   // W0 = P2 L_g^T, split over column strips, then its partials added
-  GemmBatch bw{};
-  for (int s = 0; s < 2; ++s) {
-    const int Ns = m.Ns[s];
-    GemmDesc d = gemm_desc(g.P2[s], Ns, m.ULt[s] + (long)g0 * Ns, Ns, g.W0part[s], g.kmax, kk,
-                           kk, Ns);
-    d.ksplit = 64;
-    d.csplit = (long)g.kmax * g.kmax;
-    bw.d[bw.count++] = d;
+  for (int w0 = 0; w0 < nw; w0 += kGemmMaxBatch / 2) {
+    GemmBatch bw{};
+    for (int w = w0; w < min(nw, w0 + kGemmMaxBatch / 2); ++w)
+      for (int s = 0; s < 2; ++s) {
+        const int Ns = m[w].Ns[s];
+        GemmDesc d = gemm_desc(g[w].P2[s], Ns, m[w].ULt[s] + (long)g0 * Ns, Ns, g[w].W0part[s],
+                               g[w].kmax, kk, kk, Ns);
+        d.ksplit = 64;
+        d.csplit = (long)g[w].kmax * g[w].kmax;
+        bw.d[bw.count++] = d;
+      }
+    err = gemm(bw, false, true, st);
+    if (err != hipSuccess) return err;
   }
-  err = gemm(bw, false, true, st);
-  if (err != hipSuccess) return err;
-  return launch_reduce(m, g, c, kUniNone, g0, kk, 0, 2, st);
+  return launch_reduce(m, g, c, nw, kUniNone, g0, kk, 0, 2, st);
 }
 
-hipError_t delayed_decide(const GroupBufs &g, const SweepCtx &c, int g0, int kk,
+namespace {
+Batch<DecideArgs> decide_batch(const GroupBufs *g, const SweepCtx *c, int nw, int g0, int kk,
+                               long long block_index) {
+  Batch<DecideArgs> B{};
+  for (int w = 0; w < nw; ++w) {
+    B.w[w].g = g[w];
+    B.w[w].c = c[w];
+    B.w[w].g0 = g0;
+    B.w[w].kk = kk;
+    B.w[w].block_index = block_index;
+  }
+  return B;
+}
+}  // namespace
+
+hipError_t delayed_decide(const GroupBufs *g, const SweepCtx *c, int nw, int g0, int kk,
                           hipStream_t st) {
-  DecideArgs a{};
-  a.g = g;
-  a.c = c;
-  a.g0 = g0;
-  a.kk = kk;
+  if (nw < 1 || nw > kMaxBatch) return hipErrorInvalidValue;
+  const Batch<DecideArgs> B = decide_batch(g, c, nw, g0, kk, 0);
+  const dim3 grid(nw);
   if (kk <= 8)
-    hipLaunchKernelGGL((delayed_decide_wave_kernel<8>), dim3(1), dim3(64), 0, st, a);
+    hipLaunchKernelGGL((delayed_decide_wave_kernel<8>), grid, dim3(64), 0, st, B);
   else if (kk <= 16)
-    hipLaunchKernelGGL((delayed_decide_wave_kernel<16>), dim3(1), dim3(64), 0, st, a);
+    hipLaunchKernelGGL((delayed_decide_wave_kernel<16>), grid, dim3(64), 0, st, B);
   else if (kk <= 24)
-    hipLaunchKernelGGL((delayed_decide_wave_kernel<24>), dim3(1), dim3(64), 0, st, a);
+    hipLaunchKernelGGL((delayed_decide_wave_kernel<24>), grid, dim3(64), 0, st, B);
   else if (kk <= 32)
-    hipLaunchKernelGGL((delayed_decide_wave_kernel<32>), dim3(1), dim3(64), 0, st, a);
+    hipLaunchKernelGGL((delayed_decide_wave_kernel<32>), grid, dim3(64), 0, st, B);
   else if (kk <= 64)
-    hipLaunchKernelGGL((delayed_decide_blocked_kernel<512, 64>), dim3(1), dim3(512), 0, st, a);
-  else hipLaunchKernelGGL((delayed_decide_kernel<1024, 16>), dim3(1), dim3(1024), 0, st, a);
+    hipLaunchKernelGGL((delayed_decide_blocked_kernel<512, 64>), grid, dim3(512), 0, st, B);
+  else hipLaunchKernelGGL((delayed_decide_kernel<1024, 16>), grid, dim3(1024), 0, st, B);
   return hipGetLastError();
 }
 
-hipError_t block_decide(const GroupBufs &g, const SweepCtx &c, int g0, int kk,
+hipError_t block_decide(const GroupBufs *g, const SweepCtx *c, int nw, int g0, int kk,
                         long long block_index, hipStream_t st) {
-  DecideArgs a{};
-  a.g = g;
-  a.c = c;
-  a.g0 = g0;
-  a.kk = kk;
-  a.block_index = block_index;
+  if (nw < 1 || nw > kMaxBatch) return hipErrorInvalidValue;
+  const Batch<DecideArgs> B = decide_batch(g, c, nw, g0, kk, block_index);
   const size_t lds = sizeof(double) * 2 * 64 * 65;
   static bool attr_set = false;
   if (!attr_set) {
@@ -1420,13 +1464,13 @@ hipError_t block_decide(const GroupBufs &g, const SweepCtx &c, int g0, int kk,
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  if (kk <= 16) hipLaunchKernelGGL((block_decide_kernel<64>), dim3(1), dim3(64), lds, st, a);
-  else hipLaunchKernelGGL((block_decide_kernel<256>), dim3(1), dim3(256), lds, st, a);
+  if (kk <= 16) hipLaunchKernelGGL((block_decide_kernel<64>), dim3(nw), dim3(64), lds, st, B);
+  else hipLaunchKernelGGL((block_decide_kernel<256>), dim3(nw), dim3(256), lds, st, B);
   return hipGetLastError();
 }
 
 template <int KP>
-hipError_t launch_tile(const TileArgs &a, int nt, hipStream_t st) {
+hipError_t launch_tile(const Batch<TileArgs> &B, int nw, int nt, hipStream_t st) {
   const size_t flush_lds = (size_t)64 * (KP + 1) + (size_t)KP * (KP + 1) + (size_t)KP * kLdt +
                            (size_t)64 * kLdt;
   const size_t panel_lds = (size_t)64 * kLdt + 2 * (size_t)KP * kLdt;
@@ -1439,36 +1483,49 @@ hipError_t launch_tile(const TileArgs &a, int nt, hipStream_t st) {
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL(group_tile_kernel<KP>, dim3(nt * nt, 2), dim3(256), lds, st, a);
+  hipLaunchKernelGGL(group_tile_kernel<KP>, dim3(nt * nt, 2, nw), dim3(256), lds, st, B);
   return hipGetLastError();
 }
 
-hipError_t group_tile(const SpinMats &m, const GroupBufs &g, bool flush, int g0_prev,
+hipError_t group_tile(const SpinMats *m, const GroupBufs *g, int nw, bool flush, int g0_prev,
                       int kk_prev, int g0, int kk, hipStream_t st) {
-  TileArgs a{};
-  a.m = m;
-  a.g = g;
-  a.flush = flush ? 1 : 0;
-  a.g0_prev = g0_prev;
-  a.kk_prev = flush ? kk_prev : 0;
-  a.g0 = g0;
-  a.kk = kk;
-  const int nt = (max(m.Ns[0], m.Ns[1]) + 63) / 64;
-  if (g.kmax <= 16) return launch_tile<16>(a, nt, st);
-  if (g.kmax <= 32) return launch_tile<32>(a, nt, st);
-  if (g.kmax <= 64) return launch_tile<64>(a, nt, st);
+  if (nw < 1 || nw > kMaxBatch) return hipErrorInvalidValue;
+  Batch<TileArgs> B{};
+  int kmax = 0;
+  for (int w = 0; w < nw; ++w) {
+    TileArgs &a = B.w[w];
+    a.m = m[w];
+    a.g = g[w];
+    a.flush = flush ? 1 : 0;
+    a.g0_prev = g0_prev;
+    a.kk_prev = flush ? kk_prev : 0;
+    a.g0 = g0;
+    a.kk = kk;
+    kmax = max(kmax, g[w].kmax);
+  }
+  const int nt = max_tiles(m, nw);
+  if (kmax <= 16) return launch_tile<16>(B, nw, nt, st);
+  if (kmax <= 32) return launch_tile<32>(B, nw, nt, st);
+  if (kmax <= 64) return launch_tile<64>(B, nw, nt, st);
   return hipErrorInvalidValue;
 }
 
-hipError_t group_reduce(const SpinMats &m, const GroupBufs &g, const SweepCtx &c, int mode,
-                        int g0, int kk, hipStream_t st) {
-  return launch_reduce(m, g, c, mode, g0, kk, 1, 1, st);
+hipError_t group_reduce(const SpinMats *m, const GroupBufs *g, const SweepCtx *c, int nw,
+                        int mode, int g0, int kk, hipStream_t st) {
+  return launch_reduce(m, g, c, nw, mode, g0, kk, 1, 1, st);
 }
 
-hipError_t group_flush(const SpinMats &m, const GroupBufs &g, int g0, int kk, hipStream_t st) {
-  const int nt = (max(m.Ns[0], m.Ns[1]) + 63) / 64;
-  QArgs qa{m, g, g0, kk};
-  const size_t lds = sizeof(double) * 64 * (size_t)(g.kmax + 1);
+hipError_t group_flush(const SpinMats *m, const GroupBufs *g, int nw, int g0, int kk,
+                       hipStream_t st) {
+  if (nw < 1 || nw > kMaxBatch) return hipErrorInvalidValue;
+  const int nt = max_tiles(m, nw);
+  Batch<QArgs> B{};
+  int kmax = 0;
+  for (int w = 0; w < nw; ++w) {
+    B.w[w] = QArgs{m[w], g[w], g0, kk};
+    kmax = max(kmax, g[w].kmax);
+  }
+  const size_t lds = sizeof(double) * 64 * (size_t)(kmax + 1);
   static bool attr_set = false;
   if (!attr_set) {
     // 66 KB for kmax = 128
@@ -1478,15 +1535,20 @@ hipError_t group_flush(const SpinMats &m, const GroupBufs &g, int g0, int kk, hi
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL(group_q_kernel, dim3(nt, 2), dim3(256), lds, st, qa);
-  GemmBatch b{};
-  for (int s = 0; s < 2; ++s) {
-    const int Ns = m.Ns[s];
-    GemmDesc d = gemm_desc(g.Q[s], g.kmax, g.P2[s], Ns, m.T[s], Ns, Ns, Ns, kk, -1.0, 1.0,
-                           m.T[s], Ns);
-    d.Kdev = g.nA + 1;   // rank kk, or 0 when nothing was accepted
-    b.d[b.count++] = d;
+  hipLaunchKernelGGL(group_q_kernel, dim3(nt, 2, nw), dim3(256), lds, st, B);
+  for (int w0 = 0; w0 < nw; w0 += kGemmMaxBatch / 2) {
+    GemmBatch b{};
+    for (int w = w0; w < min(nw, w0 + kGemmMaxBatch / 2); ++w)
+      for (int s = 0; s < 2; ++s) {
+        const int Ns = m[w].Ns[s];
+        GemmDesc d = gemm_desc(g[w].Q[s], g[w].kmax, g[w].P2[s], Ns, m[w].T[s], Ns, Ns, Ns, kk,
+                               -1.0, 1.0, m[w].T[s], Ns);
+        d.Kdev = g[w].nA + 1;   // rank kk, or 0 when nothing was accepted
+        b.d[b.count++] = d;
+      }
+    hipError_t e = gemm(b, false, false, st);
+    if (e != hipSuccess) return e;
   }
-  return gemm(b, false, false, st);
+  return hipSuccess;
 }
 }  // namespace pq

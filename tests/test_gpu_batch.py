@@ -1,0 +1,114 @@
+"""Batched walkers (pqmc_batch_sweep / pqmc_batch_forward_window).
+
+Each walker of a batch is an independent Markov chain with its own Philox
+key (seed, walker_id): batched, it must take the oracle's decisions for that
+key and reach its G, and it must match the same walker run alone.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import synth
+from oracle.pqmc import Walker
+from gpu_util import make_chain, compare_decisions, green_rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2506_09611_amd import load_library
+    load_library()
+
+
+def _walkers(p, n):
+    return [dataclasses.replace(p, walker_id=w) for w in range(n)]
+
+
+@pytest.mark.parametrize("scheme,kw", [("local", {}), ("delayed", {"k": 4}), ("block", {"b": 4})])
+def test_batch_matches_oracle_per_walker(scheme, kw):
+    from paper_2506_09611_amd import batch_sweep
+    p = synth.make_problem(4, 5, 5, 4.0, n_slices=20, stab_every=5, perturb=1e-3,
+                           seed=synth.SEED_BASE + 31)
+    probs = _walkers(p, 3)
+    chains = [make_chain(q, scheme, **kw) for q in probs]
+    refs = [Walker(q, scheme, **kw) for q in probs]
+    for sw in range(2):
+        batch_sweep(chains, 1)
+        for ch, w in zip(chains, refs):
+            w.sweep()
+            meta, margin = ch.decisions()
+            n, low = compare_decisions(meta, margin, w.log, sw, p.n_slices)
+            print(f"{scheme} walker {w.key[1]} sweep {sw}: {n} decisions, low {low}", flush=True)
+            if low:
+                continue
+            assert np.array_equal(ch.fields(), w.fields)
+            assert green_rel_err(ch, w) < 1e-10
+    for ch in chains:
+        ch.close()
+
+
+def test_batch_of_eight_equals_single_runs():
+    """8 walkers batched (the largest batch) vs the same walkers one by one."""
+    from paper_2506_09611_amd import batch_sweep
+    p = synth.make_problem(4, 5, 5, 4.0, n_slices=20, stab_every=5, perturb=1e-3,
+                           seed=synth.SEED_BASE + 32)
+    probs = _walkers(p, 8)
+    batched = [make_chain(q, "delayed", k=4) for q in probs]
+    batch_sweep(batched, 1)
+    for q, bc in zip(probs, batched):
+        single = make_chain(q, "delayed", k=4)
+        single.sweep(1)
+        mb, gb = bc.decisions()
+        ms, gs = single.decisions()
+        assert np.array_equal(mb, ms)
+        assert np.array_equal(bc.fields(), single.fields())
+        for s in range(2):
+            assert np.array_equal(bc.green(s), single.green(s))
+        single.close()
+    for ch in batched:
+        ch.close()
+
+
+@pytest.mark.parametrize("scheme,kw,window", [("delayed", {"k": 32}, 10), ("block", {"b": 16}, 2)])
+def test_batch_c3_window(scheme, kw, window):
+    """40x40, N_sigma = 800: two walkers batched over a forward window that
+    crosses a stabilisation; walker 0 against the oracle, both against their
+    single runs."""
+    from paper_2506_09611_amd import batch_forward_window
+    p = synth.workload("c3", n_slices=20, stab_every=10)
+    probs = _walkers(p, 2)
+    chains = [make_chain(q, scheme, **kw) for q in probs]
+    batch_forward_window(chains, window)
+    w = Walker(probs[0], scheme, **kw)
+    w.forward_window(window)
+    meta, margin = chains[0].decisions()
+    n, low = compare_decisions(meta, margin, w.log, 0, p.n_slices)
+    print(f"c3 batch {scheme}: {n} decisions equal, low {low}", flush=True)
+    if not low:
+        assert np.array_equal(chains[0].fields(), w.fields)
+        assert green_rel_err(chains[0], w) < 1e-10
+    single = make_chain(probs[1], scheme, **kw)
+    single.forward_window(window)
+    assert np.array_equal(chains[1].decisions()[0], single.decisions()[0])
+    for s in range(2):
+        assert np.array_equal(chains[1].green(s), single.green(s))
+    for ch in chains + [single]:
+        ch.close()
+
+
+def test_batch_rejects_mismatched_shapes():
+    from paper_2506_09611_amd import batch_sweep, PQMCError
+    p = synth.make_problem(4, 5, 5, 4.0, n_slices=20, stab_every=5, perturb=1e-3, seed=3)
+    a = make_chain(p, "delayed", k=4)
+    b = make_chain(dataclasses.replace(p, walker_id=1), "delayed", k=3)
+    with pytest.raises(PQMCError):
+        batch_sweep([a, b], 1)
+    with pytest.raises(PQMCError):
+        batch_sweep([a, a], 1)
+    a.close()
+    b.close()
