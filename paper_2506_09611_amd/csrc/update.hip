@@ -1132,6 +1132,7 @@ __global__ __launch_bounds__(256) void group_q_kernel(Batch<QArgs> B) {
 struct TileArgs {
   SpinMats m;
   GroupBufs g;   // pending group: panels P1, P2, its Mc, sc and nA
+  int nmat, tpm; // matrices (2 spins x walkers) and tiles per matrix of the launch
   int flush;     // a group is pending (its flush is skipped on the device if nA == 0)
   int g0_prev, kk_prev;
   int g0, kk;    // next group (kk == 0: flush only)
@@ -1142,14 +1143,24 @@ constexpr int kLdt = 65;   // padded LDS row stride
 // KP: kmax rounded up to a multiple of 16 (16, 32 or 64).
 template <int KP>
 __global__ __launch_bounds__(256) void group_tile_kernel(Batch<TileArgs> B) {
-  const TileArgs &a = B.w[blockIdx.z];
+  // XCD-aware placement: consecutive workgroup ids go round-robin to the 8
+  // XCDs, so XCD x receives ids x, x + 8, ...; giving it the contiguous range
+  // [x per, (x + 1) per) of (matrix, tile) indices keeps the tiles that share
+  // panel operands (same matrix, neighbouring row strips) in one L2.
+  const int per = gridDim.x >> 3;   // the grid is a multiple of 8
+  const int flat = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  const int tpm = B.w[0].tpm;
+  const int mat = flat / tpm;
+  if (mat >= B.w[0].nmat) return;
+  const TileArgs &a = B.w[mat >> 1];
   constexpr int kPre = KP / 4;                       // per lane: a 64 x KP operand
   constexpr int kPreM = KP * KP >= 256 ? KP * KP / 256 : 1;   // per lane: KP x KP
   constexpr int kpad = KP;
-  const int s = blockIdx.y;
+  const int s = mat & 1;
   const int Ns = a.m.Ns[s];
   const int nt = (Ns + 63) / 64;
-  const int rb = blockIdx.x / nt, cb = blockIdx.x % nt;
+  const int tile = flat % tpm;
+  const int rb = tile / nt, cb = tile % nt;
   if (rb >= nt) return;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int wm = wave >> 1, wn = wave & 1;
@@ -1214,7 +1225,6 @@ __global__ __launch_bounds__(256) void group_tile_kernel(Batch<TileArgs> B) {
     double *A1 = lds;                       // 64 x ld1: P1 rows
     double *M1 = A1 + 64 * ld1;             // kpad x ld1: Mc
     double *B1 = M1 + kpad * ld1;           // kpad x kLdt: P2 columns
-    double *QS = B1 + kpad * kLdt;          // 64 x kLdt: -(P1 Mc)
 #pragma unroll
     for (int i = 0; i < kPre; ++i) {
       const int e = t + 256 * i;
@@ -1227,15 +1237,28 @@ __global__ __launch_bounds__(256) void group_tile_kernel(Batch<TileArgs> B) {
       if (e < kpad * kpad) M1[(e / kpad) * ld1 + e % kpad] = mcv[i];
     }
     __syncthreads();
-    // -(P1 Mc): wave w forms rows [16 w, 16 w + 16)
-    for (int n0 = 0; n0 < kp; n0 += 16) {
-      const dbl4 q = mma16<false>(A1 + 16 * wave * ld1, ld1, M1 + n0, ld1, kp, lane);
+    // -(P1 Mc): wave w forms rows [16 w, 16 w + 16), its KP / 16 column
+    // tiles as independent accumulators, and overwrites those rows of A1
+    {
+      dbl4 q[KP / 16];
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
-        QS[(16 * wave + (lane >> 4) + 4 * j) * kLdt + n0 + (lane & 15)] = -q[j];
+      for (int u = 0; u < KP / 16; ++u) q[u] = dbl4{0.0, 0.0, 0.0, 0.0};
+      const int li = lane & 15, lk = lane >> 4;
+      for (int k0 = 0; k0 < kp; k0 += 4) {
+        const double av = A1[(16 * wave + li) * ld1 + k0 + lk];
+#pragma unroll
+        for (int u = 0; u < KP / 16; ++u)
+          q[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, M1[(k0 + lk) * ld1 + u * 16 + li],
+                                                      q[u], 0, 0, 0);
+      }
+#pragma unroll
+      for (int u = 0; u < KP / 16; ++u)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          A1[(16 * wave + lk + 4 * j) * ld1 + u * 16 + li] = -q[u][j];
     }
     __syncthreads();
-    lds_mma<false>(acc, QS, kLdt, B1, kLdt, kp, 64, 64, wm, wn, lane);
+    lds_mma<false>(acc, A1, ld1, B1, kLdt, kp, 64, 64, wm, wn, lane);
 #pragma unroll
     for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
@@ -1280,54 +1303,89 @@ __global__ __launch_bounds__(256) void group_tile_kernel(Batch<TileArgs> B) {
   // 16x16 output tiles, round robin over the waves:
   //   P2 part (kk x 64) = U_g[:, rows] T_tile,  P1 part (64 x kk) = T_tile L_g[cols, :],
   //   W0 part (kk x kk) = (P2 part) L_g[cols, :]
+  // Each wave runs all of its tiles in one depth loop, as independent
+  // accumulators, so that consecutive MFMAs do not wait on each other.
+  constexpr int U = KP / 16;          // P2 tiles and P1 tiles per wave
+  constexpr int UW = (U * U + 3) / 4; // W0 tiles per wave
   const int mtk = (kk + 15) >> 4;
   const int n2 = mtk * 4;
+  const int li = lane & 15, lk = lane >> 4;
   double *o2 = a.g.P2part[s] + (long)rb * kmax * Ns;
   double *o1 = a.g.P1part[s] + (long)cb * Ns * kmax;
   double *ow = a.g.W0part[s] + (long)(rb * nt + cb) * kmax * kmax;
-  dbl4 p2t[(KP / 16) * 4 / 4];   // this wave's P2 tiles (at most KP / 16 of them)
+  dbl4 p2t[U], p1t[U];
+  int mt2[U], ct2[U], rt1[U], mt1[U];
 #pragma unroll
-  for (int u = 0; u < KP / 16; ++u) {
+  for (int u = 0; u < U; ++u) {
     const int tt = wave + 4 * u;
-    p2t[u] = dbl4{0.0, 0.0, 0.0, 0.0};
-    if (tt < n2) {
-      const int mt = tt >> 2, ct = tt & 3;
-      p2t[u] = mma16<false>(Y + mt * 16 * kLdt, kLdt, X + ct * 16, kLdt, 64, lane);
+    const bool v = tt < n2;
+    mt2[u] = v ? tt >> 2 : 0;
+    ct2[u] = v ? tt & 3 : 0;
+    rt1[u] = v ? tt / mtk : 0;    // P1 tiles: 4 x mtk, as many as P2 tiles
+    mt1[u] = v ? tt % mtk : 0;
+    p2t[u] = p1t[u] = dbl4{0.0, 0.0, 0.0, 0.0};
+  }
+  for (int k0 = 0; k0 < 64; k0 += 4) {
+    const int k = k0 + lk;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int m = mt * 16 + (lane >> 4) + 4 * j, c = col0 + ct * 16 + (lane & 15);
-        if (m < kk && c < Ns) o2[(long)m * Ns + c] = p2t[u][j];
-      }
+    for (int u = 0; u < U; ++u) {
+      p2t[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(Y[(mt2[u] * 16 + li) * kLdt + k],
+                                                    X[k * kLdt + ct2[u] * 16 + li], p2t[u], 0,
+                                                    0, 0);
+      p1t[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(X[(rt1[u] * 16 + li) * kLdt + k],
+                                                    Z[(mt1[u] * 16 + li) * kLdt + k], p1t[u], 0,
+                                                    0, 0);
     }
   }
-  for (int tt = wave; tt < n2; tt += 4) {
-    const int rt = tt / mtk, mt = tt % mtk;   // P1 tiles: 4 x mtk, as many as P2 tiles
-    const dbl4 p = mma16<true>(X + rt * 16 * kLdt, kLdt, Z + mt * 16 * kLdt, kLdt, 64, lane);
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    if (wave + 4 * u >= n2) continue;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int r = row0 + rt * 16 + (lane >> 4) + 4 * j, m = mt * 16 + (lane & 15);
-      if (r < Ns && m < kk) o1[(long)r * kmax + m] = p[j];
+      const int m = mt2[u] * 16 + lk + 4 * j, c = col0 + ct2[u] * 16 + li;
+      if (m < kk && c < Ns) o2[(long)m * Ns + c] = p2t[u][j];
+      const int r = row0 + rt1[u] * 16 + lk + 4 * j, m1 = mt1[u] * 16 + li;
+      if (r < Ns && m1 < kk) o1[(long)r * kmax + m1] = p1t[u][j];
     }
   }
   __syncthreads();   // every wave is done with Y (U_g): it now takes the P2 part
 #pragma unroll
-  for (int u = 0; u < KP / 16; ++u) {
-    const int tt = wave + 4 * u;
-    if (tt < n2) {
-      const int mt = tt >> 2, ct = tt & 3;
+  for (int u = 0; u < U; ++u) {
+    if (wave + 4 * u >= n2) continue;
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
-        Y[(mt * 16 + (lane >> 4) + 4 * j) * kLdt + ct * 16 + (lane & 15)] = p2t[u][j];
-    }
+    for (int j = 0; j < 4; ++j)
+      Y[(mt2[u] * 16 + lk + 4 * j) * kLdt + ct2[u] * 16 + li] = p2t[u][j];
   }
   __syncthreads();
-  for (int tt = wave; tt < mtk * mtk; tt += 4) {
-    const int mt = tt / mtk, nt2 = tt % mtk;
-    const dbl4 p = mma16<true>(Y + mt * 16 * kLdt, kLdt, Z + nt2 * 16 * kLdt, kLdt, 64, lane);
+  // W0 tiles, depth split in two halves (two accumulators per tile)
+  dbl4 w0t[UW][2];
+  int mtw[UW], ntw[UW];
+#pragma unroll
+  for (int u = 0; u < UW; ++u) {
+    const int tt = wave + 4 * u;
+    const bool v = tt < mtk * mtk;
+    mtw[u] = v ? tt / mtk : 0;
+    ntw[u] = v ? tt % mtk : 0;
+    w0t[u][0] = w0t[u][1] = dbl4{0.0, 0.0, 0.0, 0.0};
+  }
+  for (int k0 = 0; k0 < 32; k0 += 4) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int k = h * 32 + k0 + lk;
+#pragma unroll
+      for (int u = 0; u < UW; ++u)
+        w0t[u][h] = __builtin_amdgcn_mfma_f64_16x16x4f64(Y[(mtw[u] * 16 + li) * kLdt + k],
+                                                         Z[(ntw[u] * 16 + li) * kLdt + k],
+                                                         w0t[u][h], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < UW; ++u) {
+    if (wave + 4 * u >= mtk * mtk) continue;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int m = mt * 16 + (lane >> 4) + 4 * j, n = nt2 * 16 + (lane & 15);
-      if (m < kk && n < kk) ow[m * kmax + n] = p[j];
+      const int m = mtw[u] * 16 + lk + 4 * j, n = ntw[u] * 16 + li;
+      if (m < kk && n < kk) ow[m * kmax + n] = w0t[u][0][j] + w0t[u][1][j];
     }
   }
 }
@@ -1471,8 +1529,7 @@ hipError_t block_decide(const GroupBufs *g, const SweepCtx *c, int nw, int g0, i
 
 template <int KP>
 hipError_t launch_tile(const Batch<TileArgs> &B, int nw, int nt, hipStream_t st) {
-  const size_t flush_lds = (size_t)64 * (KP + 1) + (size_t)KP * (KP + 1) + (size_t)KP * kLdt +
-                           (size_t)64 * kLdt;
+  const size_t flush_lds = (size_t)64 * (KP + 1) + (size_t)KP * (KP + 1) + (size_t)KP * kLdt;
   const size_t panel_lds = (size_t)64 * kLdt + 2 * (size_t)KP * kLdt;
   const size_t lds = sizeof(double) * std::max(flush_lds, panel_lds);
   static bool attr_set = false;
@@ -1483,7 +1540,8 @@ hipError_t launch_tile(const Batch<TileArgs> &B, int nw, int nt, hipStream_t st)
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL(group_tile_kernel<KP>, dim3(nt * nt, 2, nw), dim3(256), lds, st, B);
+  const int total = 2 * nw * nt * nt;
+  hipLaunchKernelGGL(group_tile_kernel<KP>, dim3((total + 7) / 8 * 8), dim3(256), lds, st, B);
   return hipGetLastError();
 }
 
@@ -1504,6 +1562,10 @@ hipError_t group_tile(const SpinMats *m, const GroupBufs *g, int nw, bool flush,
     kmax = max(kmax, g[w].kmax);
   }
   const int nt = max_tiles(m, nw);
+  for (int w = 0; w < nw; ++w) {
+    B.w[w].nmat = 2 * nw;
+    B.w[w].tpm = nt * nt;
+  }
   if (kmax <= 16) return launch_tile<16>(B, nw, nt, st);
   if (kmax <= 32) return launch_tile<32>(B, nw, nt, st);
   if (kmax <= 64) return launch_tile<64>(B, nw, nt, st);
