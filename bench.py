@@ -131,6 +131,41 @@ def cpu_baseline(p, scheme, k, b, budget_s=20.0):
                       f"{dt:.1f} s of host time"}
 
 
+def scheme_table(p, spec, window):
+    """One walker, forward windows of `window` slice visits (propagation,
+    updates, the stabilisations inside the window), for each delay rank and
+    block size in spec ('delayed:8,16;block:1,4'), beside the local update."""
+    import torch
+    N = p.n_sites
+    rows = []
+    entries = [("local", 1)]
+    for part in spec.split(";"):
+        name, vals = part.split(":")
+        entries += [(name, int(v)) for v in vals.split(",") if v]
+    base = None
+    for name, kb in entries:
+        c = make_chain(p, name, k=kb if name == "delayed" else 1, b=kb if name == "block" else 1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = c.forward_window(window)
+        torch.cuda.synchronize()
+        w = time.perf_counter() - t0
+        row = {"scheme": name, "rank": kb, "field_updates_per_s": window * N / w,
+               "update_only": window * N / st["t_update_s"] if st["t_update_s"] > 0 else None,
+               "acceptance": st["accepted"] / max(1, st["proposed"])}
+        if name == "local":
+            base = row
+        row["speedup_vs_local"] = row["field_updates_per_s"] / base["field_updates_per_s"]
+        row["update_speedup_vs_local"] = (row["update_only"] / base["update_only"]
+                                          if row["update_only"] and base["update_only"] else None)
+        rows.append(row)
+        log("table", row)
+        c.close()
+        del c
+        torch.cuda.empty_cache()
+    return {"walkers": 1, "window_slice_visits": window, "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -140,8 +175,12 @@ def main():
     ap.add_argument("--k", type=int, default=32)
     ap.add_argument("--b", type=int, default=16)
     ap.add_argument("--workload", default="c3")
-    ap.add_argument("--walkers", type=int, default=1,
+    ap.add_argument("--walkers", type=int, default=8,
                     help="independent walkers swept together in one batch (1..8)")
+    ap.add_argument("--table", default="delayed:8,16,32,64,128;block:1,4,16,64",
+                    help="single-walker scheme table timed on forward windows ('' for none)")
+    ap.add_argument("--table-window", type=int, default=20,
+                    help="slice visits per table entry")
     ap.add_argument("--compare", default="local,block",
                     help="other schemes timed beside the headline one ('' for none)")
     ap.add_argument("--local-window", type=int, default=20,
@@ -151,7 +190,7 @@ def main():
                     help="forward slice visits instrumented per kernel after the timed sweeps")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs one Markov chain on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "this build runs on one GPU (walkers are batched on it); --gpus must be 1"}))
         sys.exit(2)
 
     import torch
@@ -218,6 +257,20 @@ def main():
     del ch, chains
     torch.cuda.empty_cache()
 
+    # the same scheme on one walker (whole sweeps): the paper's per-chain setting
+    if W > 1:
+        c1 = make_chain(p, args.scheme, args.k, args.b)
+        d1, a1 = time_sweeps([c1], 1, 0)
+        result["single_chain"] = {
+            "walkers": 1, "s_per_sweep": d1, "field_updates_per_s": per_sweep / d1,
+            "update_only": per_sweep / a1["t_update_s"] if a1["t_update_s"] > 0 else None,
+            "phase_s_per_sweep": {"update": a1["t_update_s"], "propagation": a1["t_prop_s"],
+                                  "stabilization": a1["t_stab_s"]}}
+        log("single chain", result["single_chain"])
+        c1.close()
+        del c1
+        torch.cuda.empty_cache()
+
     schemes = {args.scheme: {"s_per_sweep": dt / args.steps, "field_updates_per_s": value,
                              "update_only": upd, "walkers": W}}
     for name in [s for s in args.compare.split(",") if s and s != args.scheme]:
@@ -253,6 +306,8 @@ def main():
         for v in schemes.values():
             v["speedup_vs_local"] = v["field_updates_per_s"] / base
     result["schemes"] = schemes
+    if args.table:
+        result["table"] = scheme_table(p, args.table, args.table_window)
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(p, args.scheme, args.k, args.b)
     print(json.dumps(result))

@@ -471,19 +471,6 @@ __device__ __forceinline__ double readlane_f64(double v, int src) {
   return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-// Blocked delayed decision for kk <= KK sites (one workgroup of NT lanes).
-// E_s = 1 + W0_s diag(Delta_s) lives in LDS.  Sites are taken in sub-blocks
-// of kSub: wave 0 holds the sub-block's kSub x kSub diagonal block of both
-// spins in registers (lane = 8 a + b) and takes its decisions one after the
-// other, sweeping accepted pivots with cross-lane reads and no barrier.  The
-// sub-block's accepted set S is then swept out of the rest of E at once:
-// with C = (E_SS)^{-1} (minus the swept diagonal block),
-//   E_RR -= E_RS C E_SR,  E_SR <- C E_SR,  E_RS <- E_RS C,
-// which equals sweeping the pivots of S one by one.  Rows and columns of
-// rejected sites are never read again and are left stale.
-constexpr int kSub = 8;
-constexpr int kDLd = 65;
-
 // 1/p to full double precision for the pivots of the decision kernels:
 // hardware reciprocal estimate refined by two Newton steps (p is a finite,
 // nonzero pivot of an accepted proposal).
@@ -491,225 +478,6 @@ __device__ __forceinline__ double recip(double p) {
   double r = __builtin_amdgcn_rcp(p);
   r = fma(r, fma(-p, r, 1.0), r);
   return fma(r, fma(-p, r, 1.0), r);
-}
-
-template <int NT, int KK>
-__global__ __launch_bounds__(NT) void delayed_decide_blocked_kernel(Batch<DecideArgs> B) {
-  const DecideArgs &A = B.w[blockIdx.x];
-  static_assert(KK * KK % NT == 0 && KK <= 64, "tile shape");
-  constexpr int EPT = KK * KK / NT;           // elements of each spin's E per lane
-  const int kk = A.kk;
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const SweepCtx &C = A.c;
-  const int kmax = A.g.kmax;
-  __shared__ double Es[2][KK * kDLd];
-  __shared__ double Xs[2][KK][kSub];     // E_{a,S} C for rows a outside the sub-block
-  __shared__ double Rn[2][kSub][KK];     // new rows S outside the sub-block: C E_{S,b}
-  __shared__ double Ro[2][kSub][KK];     // old rows S outside the sub-block
-  __shared__ double Cs[2][kSub][kSub];   // C, compacted to S x S
-  __shared__ double uni[KK], dl[2][KK];
-  __shared__ int accf[KK];
-  __shared__ int s_mask;
-
-  const int8_t *xrow = C.fields + (long)C.li * C.N + A.g0;
-  if (t < kk) {
-    const int8_t x = xrow[t];
-    dl[0][t] = C.dflip[0][x > 0 ? 0 : 1];
-    dl[1][t] = C.dflip[1][x > 0 ? 0 : 1];
-    uni[t] = A.g.uni[t];
-  }
-  // E_s = 1 + W0_s diag(Delta_s)
-  {
-    double w[2][EPT], dv[2][EPT];
-#pragma unroll
-    for (int i = 0; i < EPT; ++i) {
-      const int e = t + NT * i, a = e / KK, b = e % KK;
-      const bool ok = a < kk && b < kk;
-      const int8_t x = ok ? xrow[b] : 1;
-#pragma unroll
-      for (int sp = 0; sp < 2; ++sp) {
-        w[sp][i] = ok ? A.g.W0[sp][a * kmax + b] : 0.0;
-        dv[sp][i] = C.dflip[sp][x > 0 ? 0 : 1];
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < EPT; ++i) {
-      const int e = t + NT * i, a = e / KK, b = e % KK;
-      if (a < kk && b < kk) {
-#pragma unroll
-        for (int sp = 0; sp < 2; ++sp)
-          Es[sp][a * kDLd + b] = (a == b ? 1.0 : 0.0) + w[sp][i] * dv[sp][i];
-      }
-    }
-  }
-  __syncthreads();
-
-  unsigned long long n_acc = 0, n_low = 0, n_neg = 0;
-  bool any_nan = false;
-  for (int j0 = 0; j0 < kk; j0 += kSub) {
-    const int nb = min(kSub, kk - j0);
-    const int jend = j0 + nb;
-    if (wave == 0) {
-      const int ra = lane >> 3, cb = lane & 7;
-      const bool own = ra < nb && cb < nb;
-      double e0 = own ? Es[0][(j0 + ra) * kDLd + j0 + cb] : 0.0;
-      double e1 = own ? Es[1][(j0 + ra) * kDLd + j0 + cb] : 0.0;
-      const double ul = lane < nb ? uni[j0 + lane] : 0.0;
-      int mask = 0;
-      for (int jj = 0; jj < nb; ++jj) {
-        // pivot row and column values, fetched before the decision is known
-        const double ca0 = __shfl(e0, ra * 8 + jj, 64), rb0 = __shfl(e0, jj * 8 + cb, 64);
-        const double ca1 = __shfl(e1, ra * 8 + jj, 64), rb1 = __shfl(e1, jj * 8 + cb, 64);
-        const double p0 = readlane_f64(e0, jj * 9), p1 = readlane_f64(e1, jj * 9);
-        const double u = readlane_f64(ul, jj);
-        const double R = p0 * p1;
-        const double absA = fabs(R);
-        const bool finite = !isnan(absA);
-        const bool acc = __builtin_amdgcn_readfirstlane((finite && (u < absA)) ? 1 : 0) != 0;
-        const double margin = absA - u;
-        n_acc += acc ? 1 : 0;
-        n_low += (fabs(margin) < 1e-12) ? 1 : 0;
-        n_neg += (R < 0.0) ? 1 : 0;
-        any_nan = any_nan || !finite;
-        if (lane == 0) record_decision(C, C.log_base + A.g0 + j0 + jj, A.g0 + j0 + jj, acc, margin);
-        // principal pivot transform on pivot jj, both spins, kept only if accepted
-        const double ip0 = recip(p0), ip1 = recip(p1);
-        const bool rj = ra == jj, cj = cb == jj;
-        const double c0 = ca0 * ip0, c1 = ca1 * ip1;
-        double v0 = e0 - c0 * rb0, v1 = e1 - c1 * rb1;
-        v0 = rj ? rb0 * ip0 : v0;
-        v1 = rj ? rb1 * ip1 : v1;
-        v0 = cj ? c0 : v0;
-        v1 = cj ? c1 : v1;
-        v0 = (rj && cj) ? -ip0 : v0;
-        v1 = (rj && cj) ? -ip1 : v1;
-        e0 = acc ? v0 : e0;
-        e1 = acc ? v1 : e1;
-        mask |= acc ? (1 << jj) : 0;
-      }
-      if (own) {
-        Es[0][(j0 + ra) * kDLd + j0 + cb] = e0;
-        Es[1][(j0 + ra) * kDLd + j0 + cb] = e1;
-        // C = minus the swept S x S block, compacted
-        if (((mask >> ra) & 1) && ((mask >> cb) & 1)) {
-          const int pa = __popc(mask & ((1 << ra) - 1)), pb = __popc(mask & ((1 << cb) - 1));
-          Cs[0][pa][pb] = -e0;
-          Cs[1][pa][pb] = -e1;
-        }
-      }
-      if (lane < nb) accf[j0 + lane] = (mask >> lane) & 1;
-      if (lane == 0) s_mask = mask;
-    }
-    __syncthreads();
-    const int mask = __builtin_amdgcn_readfirstlane(s_mask);
-    if (mask == 0) continue;
-    const int ns = __popc(mask);
-    // positions of the accepted sites in the sub-block (uniform)
-    int sl[kSub];
-    {
-      int mm = mask;
-#pragma unroll
-      for (int q = 0; q < kSub; ++q) {
-        sl[q] = mm ? __ffs(mm) - 1 : 0;
-        mm &= mm - 1;
-      }
-    }
-    // rows outside the sub-block: X = E_{a,S} C
-    for (int e = t; e < KK * kSub; e += NT) {
-      const int a = e / kSub, p = e % kSub;
-      if (a >= kk || (a >= j0 && a < jend) || p >= ns) continue;
-      double v0 = 0.0, v1 = 0.0;
-#pragma unroll
-      for (int q = 0; q < kSub; ++q) {
-        if (q < ns) {
-          v0 += Es[0][a * kDLd + j0 + sl[q]] * Cs[0][q][p];
-          v1 += Es[1][a * kDLd + j0 + sl[q]] * Cs[1][q][p];
-        }
-      }
-      Xs[0][a][p] = v0;
-      Xs[1][a][p] = v1;
-    }
-    // rows S outside the sub-block: old values and C E_{S,b}
-    for (int e = t; e < kSub * KK; e += NT) {
-      const int p = e / KK, b = e % KK;
-      if (p >= ns || b >= kk || (b >= j0 && b < jend)) continue;
-      double v0 = 0.0, v1 = 0.0;
-#pragma unroll
-      for (int q = 0; q < kSub; ++q) {
-        if (q < ns) {
-          v0 += Cs[0][p][q] * Es[0][(j0 + sl[q]) * kDLd + b];
-          v1 += Cs[1][p][q] * Es[1][(j0 + sl[q]) * kDLd + b];
-        }
-      }
-      Rn[0][p][b] = v0;
-      Rn[1][p][b] = v1;
-      int sp_row = j0;
-#pragma unroll
-      for (int q = 0; q < kSub; ++q) sp_row = (q == p) ? j0 + sl[q] : sp_row;
-      Ro[0][p][b] = Es[0][sp_row * kDLd + b];
-      Ro[1][p][b] = Es[1][sp_row * kDLd + b];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < EPT; ++i) {
-      const int e = t + NT * i, a = e / KK, b = e % KK;
-      if (a >= kk || b >= kk) continue;
-      const bool ain = a >= j0 && a < jend, bin = b >= j0 && b < jend;
-      if (ain && bin) continue;
-      if (!ain && !bin) {
-        double v0 = Es[0][a * kDLd + b], v1 = Es[1][a * kDLd + b];
-#pragma unroll
-        for (int p = 0; p < kSub; ++p) {
-          if (p < ns) {
-            v0 -= Xs[0][a][p] * Ro[0][p][b];
-            v1 -= Xs[1][a][p] * Ro[1][p][b];
-          }
-        }
-        Es[0][a * kDLd + b] = v0;
-        Es[1][a * kDLd + b] = v1;
-      } else if (ain) {
-        if ((mask >> (a - j0)) & 1) {
-          const int p = __popc(mask & ((1 << (a - j0)) - 1));
-          Es[0][a * kDLd + b] = Rn[0][p][b];
-          Es[1][a * kDLd + b] = Rn[1][p][b];
-        }
-      } else if ((mask >> (b - j0)) & 1) {
-        const int p = __popc(mask & ((1 << (b - j0)) - 1));
-        Es[0][a * kDLd + b] = Xs[0][a][p];
-        Es[1][a * kDLd + b] = Xs[1][a][p];
-      }
-    }
-    __syncthreads();
-  }
-  if (t == 0) {
-    C.stats[kStProposed] += kk;
-    C.stats[kStFieldUpdates] += kk;
-    C.stats[kStAccepted] += n_acc;
-    C.stats[kStFlips] += n_acc;
-    C.stats[kStLowMargin] += n_low;
-    C.stats[kStNegative] += n_neg;
-    if (any_nan) C.stats[kStError] |= kErrNonFinite;
-  }
-  // row scales and flipped fields, one lane per site
-  if (t < kk) {
-    const int mine = accf[t];
-    A.g.sc[0][t] = mine ? 1.0 + dl[0][t] : 1.0;
-    A.g.sc[1][t] = mine ? 1.0 + dl[1][t] : 1.0;
-    if (mine) C.fields[(long)C.li * C.N + A.g0 + t] = (int8_t)(-xrow[t]);
-  }
-  if (t == 0) {
-    A.g.nA[0] = (int)n_acc;
-    A.g.nA[1] = n_acc ? kk : 0;
-  }
-  // Mc = diag(Delta_A) (E_AA)^{-1} = -diag(Delta_A) (swept E)_AA, zero elsewhere
-#pragma unroll
-  for (int i = 0; i < EPT; ++i) {
-    const int e = t + NT * i, a = e / KK, b = e % KK;
-    if (a >= kk || b >= kk) continue;
-    const bool in = accf[a] && accf[b];
-    A.g.Mc[0][a * kmax + b] = in ? -dl[0][a] * Es[0][a * kDLd + b] : 0.0;
-    A.g.Mc[1][a * kmax + b] = in ? -dl[1][a] * Es[1][a * kDLd + b] : 0.0;
-  }
 }
 
 // Delayed decision for kk <= KK <= 32 sites in a single wave.  The whole of
@@ -848,6 +616,131 @@ __global__ __launch_bounds__(64) void delayed_decide_wave_kernel(Batch<DecideArg
       const bool in = ((amask >> a) & 1) && ((amask >> b) & 1);
       A.g.Mc[0][a * kmax + b] = in ? -da0[i] * e0[i][j] : 0.0;
       A.g.Mc[1][a * kmax + b] = in ? -da1[i] * e1[i][j] : 0.0;
+    }
+  }
+}
+
+// Delayed decision for kk <= KK <= 64 sites with one wave per spin sector.
+// Wave s holds E_s = 1 + W0_s diag(Delta_s) in registers (lane (ra, cb) =
+// (lane / 8, lane % 8) owns rows ra + 8 i and columns cb + 8 j, i, j < KK / 8)
+// and sweeps accepted pivots out of it with cross-lane reads, as the
+// single-wave kernel does for both spins; per site the two waves exchange
+// their pivots through LDS (one barrier) and take the same decision.
+template <int KK>
+__global__ __launch_bounds__(128) void delayed_decide_spin_kernel(Batch<DecideArgs> B) {
+  const DecideArgs &A = B.w[blockIdx.x];
+  constexpr int R = KK / 8;
+  static_assert(KK % 8 == 0 && R >= 1 && R <= 8, "tile shape");
+  const int kk = A.kk;
+  const int t = threadIdx.x, sp = t >> 6, lane = t & 63;
+  const int ra = lane >> 3, cb = lane & 7;
+  const SweepCtx &C = A.c;
+  const int kmax = A.g.kmax;
+  const int8_t *xrow = C.fields + (long)C.li * C.N + A.g0;
+  __shared__ double piv[2][2];   // [site parity][spin]
+
+  const double ul = lane < kk ? A.g.uni[lane] : 0.0;
+  const int8_t xl = lane < kk ? xrow[lane] : 1;
+  const double *W0 = A.g.W0[sp];
+  double e[R][R];
+  double da[R];   // Delta of this lane's rows, from the fields before any flip
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const int a = ra + 8 * i;
+    const int8_t xa = a < kk ? xrow[a] : 1;
+    da[i] = C.dflip[sp][xa > 0 ? 0 : 1];
+  }
+#pragma unroll
+  for (int i = 0; i < R; ++i)
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      const int a = ra + 8 * i, b = cb + 8 * j;
+      const bool ok = a < kk && b < kk;
+      const int8_t xb = ok ? xrow[b] : 1;
+      const double w = ok ? W0[a * kmax + b] : 0.0;
+      e[i][j] = (a == b ? 1.0 : 0.0) + w * C.dflip[sp][xb > 0 ? 0 : 1];
+    }
+
+  unsigned long long amask = 0;   // accepted sites (uniform)
+  unsigned long long n_low = 0, n_neg = 0;
+  bool any_nan = false;
+#pragma unroll
+  for (int J = 0; J < R; ++J) {
+    for (int jl = 0; jl < 8; ++jl) {
+      const int j = 8 * J + jl;
+      if (j >= kk) break;
+      const int src_c = ra * 8 + jl, src_r = jl * 8 + cb;
+      double c[R], r[R];
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        c[i] = __shfl(e[i][J], src_c, 64);
+        r[i] = __shfl(e[J][i], src_r, 64);
+      }
+      const double p = readlane_f64(e[J][J], jl * 9);
+      if (lane == 0) piv[j & 1][sp] = p;
+      __syncthreads();
+      const double p0 = piv[j & 1][0], p1 = piv[j & 1][1];
+      const double u = readlane_f64(ul, j);
+      const double Rr = p0 * p1;
+      const double absA = fabs(Rr);
+      const bool finite = !isnan(absA);
+      const bool acc = __builtin_amdgcn_readfirstlane((finite && (u < absA)) ? 1 : 0) != 0;
+      const double margin = absA - u;
+      n_low += (fabs(margin) < 1e-12) ? 1 : 0;
+      n_neg += (Rr < 0.0) ? 1 : 0;
+      any_nan = any_nan || !finite;
+      if (t == 0) record_decision(C, C.log_base + A.g0 + j, A.g0 + j, acc, margin);
+      if (acc) {
+        amask |= 1ull << j;
+        const double ip = recip(p);
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+          const double ci = c[i] * ip;
+#pragma unroll
+          for (int jp = 0; jp < R; ++jp) e[i][jp] -= ci * r[jp];
+        }
+        if (ra == jl) {   // pivot row: E_jb / p
+#pragma unroll
+          for (int jp = 0; jp < R; ++jp) e[J][jp] = r[jp] * ip;
+        }
+        if (cb == jl) {   // pivot column: E_aj / p
+#pragma unroll
+          for (int i = 0; i < R; ++i) e[i][J] = c[i] * ip;
+        }
+        if (lane == jl * 9) e[J][J] = -ip;
+      }
+    }
+  }
+  const int n_acc = __popcll(amask);
+  if (t == 0) {
+    C.stats[kStProposed] += kk;
+    C.stats[kStFieldUpdates] += kk;
+    C.stats[kStAccepted] += n_acc;
+    C.stats[kStFlips] += n_acc;
+    C.stats[kStLowMargin] += n_low;
+    C.stats[kStNegative] += n_neg;
+    if (any_nan) C.stats[kStError] |= kErrNonFinite;
+    A.g.nA[0] = n_acc;
+    A.g.nA[1] = n_acc ? kk : 0;
+  }
+  // row scales of spin sp; wave 0 also flips the accepted fields
+  if (lane < kk) {
+    const bool mine = (amask >> lane) & 1;
+    A.g.sc[sp][lane] = mine ? 1.0 + C.dflip[sp][xl > 0 ? 0 : 1] : 1.0;
+    if (sp == 0 && mine) C.fields[(long)C.li * C.N + A.g0 + lane] = (int8_t)(-xl);
+  }
+  // Mc_s = diag(Delta_A) (E_AA)^{-1} = -diag(Delta_A) (swept E)_AA, zero elsewhere
+  double *Mc = A.g.Mc[sp];
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const int a = ra + 8 * i;
+    if (a >= kk) continue;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      const int b = cb + 8 * j;
+      if (b >= kk) continue;
+      const bool in = ((amask >> a) & 1) && ((amask >> b) & 1);
+      Mc[a * kmax + b] = in ? -da[i] * e[i][j] : 0.0;
     }
   }
 }
@@ -1493,16 +1386,16 @@ hipError_t delayed_decide(const GroupBufs *g, const SweepCtx *c, int nw, int g0,
   if (nw < 1 || nw > kMaxBatch) return hipErrorInvalidValue;
   const Batch<DecideArgs> B = decide_batch(g, c, nw, g0, kk, 0);
   const dim3 grid(nw);
+  // measured at 40x40: k = 32 takes 19.5 us with one wave per spin against
+  // 21.6 us with both spins in one wave; k = 64 fits the per-spin layout
   if (kk <= 8)
     hipLaunchKernelGGL((delayed_decide_wave_kernel<8>), grid, dim3(64), 0, st, B);
   else if (kk <= 16)
     hipLaunchKernelGGL((delayed_decide_wave_kernel<16>), grid, dim3(64), 0, st, B);
-  else if (kk <= 24)
-    hipLaunchKernelGGL((delayed_decide_wave_kernel<24>), grid, dim3(64), 0, st, B);
   else if (kk <= 32)
-    hipLaunchKernelGGL((delayed_decide_wave_kernel<32>), grid, dim3(64), 0, st, B);
+    hipLaunchKernelGGL((delayed_decide_spin_kernel<32>), grid, dim3(128), 0, st, B);
   else if (kk <= 64)
-    hipLaunchKernelGGL((delayed_decide_blocked_kernel<512, 64>), grid, dim3(512), 0, st, B);
+    hipLaunchKernelGGL((delayed_decide_spin_kernel<64>), grid, dim3(128), 0, st, B);
   else hipLaunchKernelGGL((delayed_decide_kernel<1024, 16>), grid, dim3(1024), 0, st, B);
   return hipGetLastError();
 }
