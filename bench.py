@@ -31,11 +31,11 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def make_chain(p, scheme, k=1, b=1, timing=True):
+def make_chain(p, scheme, k=1, b=1, timing=True, fp32=False):
     from paper_2506_09611_amd import Chain, Scheme
     sc = {"local": Scheme.LOCAL, "delayed": Scheme.DELAYED, "block": Scheme.BLOCK_FB}[scheme]
     return Chain(p.hopping, p.trial_up, p.trial_dn, p.U, p.dtau, p.n_slices, p.stab_every,
-                 p.seed, p.walker_id, scheme=sc, k=k, b=b, timing=timing)
+                 p.seed, p.walker_id, scheme=sc, k=k, b=b, timing=timing, fp32=fp32)
 
 
 def kernel_work(p, cls, scheme, k, b, acc):
@@ -81,6 +81,31 @@ def roofline(p, scheme, k, b, acc, ktimes, cls=None, walkers=1):
             "frac": achieved / peak, "traffic": None, "avg_launch_us": avg * 1e6,
             "launches": cnt, "flops_per_launch": flops, "bytes_per_launch": nbytes,
             "device_time_share": {c: v / total for c, v in shares.items()}}
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "tile_kernel_40x40_w8_delayed_k32_traffic.txt")
+
+
+def measured_traffic(cls, scheme, k, walkers, workload):
+    """HBM bytes per launch of the tile kernel from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE runs (scaled by the same counters on a plain copy
+    of known size), or None when they do not cover this launch or the kernel
+    source has changed since they were taken."""
+    import hashlib
+    if cls != "tile" or not os.path.exists(TRAFFIC_FILE):
+        return None
+    rec = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.startswith("#"):
+            key, val = line.split(":", 1)
+            rec[key.strip()] = val.strip()
+    src = os.path.join(ROOT, "paper_2506_09611_amd", "csrc", "update.hip")
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if (rec.get("source_sha256") != digest or rec.get("scheme") != scheme
+            or int(rec.get("k", -1)) != k or int(rec.get("walkers", -1)) != walkers
+            or rec.get("workload") != workload):
+        return None
+    return float(rec["traffic_bytes_per_launch"])
 
 
 def time_sweeps(chains, steps, warmup):
@@ -181,6 +206,13 @@ def main():
                     help="single-walker scheme table timed on forward windows ('' for none)")
     ap.add_argument("--table-window", type=int, default=20,
                     help="slice visits per table entry")
+    ap.add_argument("--no-fp32", action="store_true",
+                    help="skip the precision-form (float32 T and flush) run of the batch")
+    ap.add_argument("--no-single", action="store_true",
+                    help="skip the one-walker run of the headline scheme")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only copy a MIB-sized device buffer three times (the reference "
+                         "kernel for scaling traffic counters) and exit")
     ap.add_argument("--compare", default="local,block",
                     help="other schemes timed beside the headline one ('' for none)")
     ap.add_argument("--local-window", type=int, default=20,
@@ -197,6 +229,15 @@ def main():
     import synth
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_calibration > 0:
+        n = args.copy_calibration << 20
+        x = torch.zeros(n, dtype=torch.uint8, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        log(f"copied {args.copy_calibration} MiB x 3")
+        return
     p = synth.workload(args.workload)
     N, M = p.n_sites, p.n_slices
     per_sweep = 2 * M * N
@@ -208,10 +249,14 @@ def main():
     chains = [make_chain(dataclasses.replace(p, walker_id=w), args.scheme, args.k, args.b)
               for w in range(W)]
     ch = chains[0]
-    dt, agg = time_sweeps(chains, args.steps, args.warmup)
-    value = W * args.steps * per_sweep / dt
-    upd = W * args.steps * per_sweep / agg["t_update_s"] if agg["t_update_s"] > 0 else None
-    acc = agg["accepted"] / max(1, agg["proposed"])
+    if args.steps > 0:
+        dt, agg = time_sweeps(chains, args.steps, args.warmup)
+        value = W * args.steps * per_sweep / dt
+        upd = W * args.steps * per_sweep / agg["t_update_s"] if agg["t_update_s"] > 0 else None
+        acc = agg["accepted"] / max(1, agg["proposed"])
+    else:   # profiling runs: no timed sweeps, only the instrumented window below
+        dt, agg, value, upd, acc = 0.0, {"low_margin": 0, "t_update_s": 0.0, "t_prop_s": 0.0,
+                                         "t_stab_s": 0.0}, 0.0, None, 0.74
     # per-kernel device time, live on the library's stream: an instrumented
     # forward window after the timed sweeps
     ch.set_opts(ch.scheme, ch.k, ch.b, ktime=True)
@@ -221,7 +266,12 @@ def main():
     roof = roofline(p, args.scheme, args.k, args.b, acc, ktimes, walkers=W)
     # the rank-n_A flush with the next group's panels, on MFMA (delayed / block)
     roof_flush = roofline(p, args.scheme, args.k, args.b, acc, ktimes, "tile", walkers=W)
-    log(f"{args.scheme}: {dt / args.steps:.3f} s/sweep, {value:.4g} fu/s, update-only {upd:.4g}")
+    for r in (roof, roof_flush):
+        if r is not None:
+            r["traffic"] = measured_traffic(r["kernel"], args.scheme, args.k, W, args.workload)
+    if args.steps > 0:
+        log(f"{args.scheme}: {dt / args.steps:.3f} s/sweep, {value:.4g} fu/s, "
+            f"update-only {upd:.4g}")
     log("kernel times", {c: (round(v[0] * 1e3, 3), v[1]) for c, v in ktimes.items()})
     result = {
         "metric": METRIC,
@@ -230,7 +280,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * dt / args.steps,
+        "ms_per_step": 1e3 * dt / args.steps if args.steps else None,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -245,9 +295,9 @@ def main():
         "update_only_field_updates_per_s": upd,
         "acceptance": acc,
         "low_margin": agg["low_margin"],
-        "phase_s_per_sweep": {"update": agg["t_update_s"] / args.steps,
-                              "propagation": agg["t_prop_s"] / args.steps,
-                              "stabilization": agg["t_stab_s"] / args.steps},
+        "phase_s_per_sweep": {"update": agg["t_update_s"] / max(1, args.steps),
+                              "propagation": agg["t_prop_s"] / max(1, args.steps),
+                              "stabilization": agg["t_stab_s"] / max(1, args.steps)},
         "roofline": roof,
         "roofline_flush": roof_flush,
         "kernel_avg_us": {c: 1e6 * v[0] / v[1] for c, v in ktimes.items() if v[1] > 0},
@@ -258,7 +308,7 @@ def main():
     torch.cuda.empty_cache()
 
     # the same scheme on one walker (whole sweeps): the paper's per-chain setting
-    if W > 1:
+    if W > 1 and args.steps > 0 and not args.no_single:
         c1 = make_chain(p, args.scheme, args.k, args.b)
         d1, a1 = time_sweeps([c1], 1, 0)
         result["single_chain"] = {
@@ -271,7 +321,24 @@ def main():
         del c1
         torch.cuda.empty_cache()
 
-    schemes = {args.scheme: {"s_per_sweep": dt / args.steps, "field_updates_per_s": value,
+    # the precision form on the same batch (float32 T, flush and panels)
+    if args.steps > 0 and not args.no_fp32 and args.scheme != "local":
+        cs = [make_chain(dataclasses.replace(p, walker_id=w), args.scheme, args.k, args.b,
+                         fp32=True) for w in range(W)]
+        d32, a32 = time_sweeps(cs, 1, 0)
+        result["precision_form"] = {
+            "walkers": W, "dtype": "f32 T/flush/panels, f64 ratios/QR/inverse",
+            "s_per_sweep": d32, "field_updates_per_s": W * per_sweep / d32,
+            "update_only": W * per_sweep / a32["t_update_s"] if a32["t_update_s"] > 0 else None,
+            "speedup_vs_f64": dt / max(1, args.steps) / d32,
+            "note": "errors against the float64 oracle: tests/test_gpu_precision.py"}
+        log("fp32 form", result["precision_form"])
+        for x in cs:
+            x.close()
+        del cs
+        torch.cuda.empty_cache()
+
+    schemes = {args.scheme: {"s_per_sweep": dt / max(1, args.steps), "field_updates_per_s": value,
                              "update_only": upd, "walkers": W}}
     for name in [s for s in args.compare.split(",") if s and s != args.scheme]:
         cs = [make_chain(dataclasses.replace(p, walker_id=w), name, args.k, args.b)

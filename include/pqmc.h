@@ -71,6 +71,14 @@ typedef enum { PQMC_LOCAL = 0, PQMC_DELAYED = 1, PQMC_BLOCK_FB = 2 } pqmc_scheme
 #define PQMC_FLAG_LOG    1u  /* record every decision of the last pqmc_sweep call */
 #define PQMC_FLAG_TIMING 2u  /* time propagation / update / stabilisation phases  */
 #define PQMC_FLAG_KTIME  4u  /* time every launch of the kernel classes below      */
+/* Precision form (delayed and block force-bias with k, b <= 64): between
+ * stabilisations T is kept in float32 and the group flush and panel products
+ * run on FP32 MFMA with FP32 accumulation.  The panel sums, W0, every
+ * acceptance ratio and decision, the propagation, the QR and the inverse
+ * stay float64, and T is recomputed in float64 from U_L, U_R at every
+ * stabilisation, which discards the float32 drift.  Decisions can differ
+ * from the float64 chain where a ratio lies within the float32 error of u. */
+#define PQMC_FLAG_FP32   8u
 
 /* kernel classes of pqmc_get_kernel_times() */
 enum {

@@ -13,4 +13,7 @@ Modules
              block force-bias updates, Green's function.
   brute   -- from-scratch configuration weights and Green's functions used
              to pin `pqmc` (definition of W(X), Eq. (9); G, Eq. (12)).
+  observables -- energy and double occupancy of the standard Hubbard model
+             from G (Eq. (1), mixed estimate), for the precision-form error
+             statements.
 """

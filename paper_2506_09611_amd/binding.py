@@ -34,6 +34,7 @@ class Scheme(enum.IntEnum):
 FLAG_LOG = 1
 FLAG_TIMING = 2
 FLAG_KTIME = 4
+FLAG_FP32 = 8
 
 
 class PQMCError(RuntimeError):
@@ -137,7 +138,7 @@ class Chain:
 
     def __init__(self, hopping, trial_up, trial_dn, U, dtau, n_slices, stab_every, seed,
                  walker_id=0, scheme=Scheme.LOCAL, k=1, b=1, k_max=None, b_max=None,
-                 log=False, timing=False):
+                 log=False, timing=False, fp32=False):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device visible to torch")
@@ -151,7 +152,8 @@ class Chain:
         self._prob = Problem(N, self.n_up, self.n_dn, _dptr(self._H), _dptr(self._Pu),
                              _dptr(self._Pd), float(U), float(dtau), int(n_slices),
                              int(stab_every), int(seed) & (2**64 - 1), int(walker_id))
-        self._flags = (FLAG_LOG if log else 0) | (FLAG_TIMING if timing else 0)
+        self._flags = ((FLAG_LOG if log else 0) | (FLAG_TIMING if timing else 0)
+                       | (FLAG_FP32 if fp32 else 0))
         kmax = int(k_max if k_max is not None else k)
         bmax = int(b_max if b_max is not None else b)
         sizing = UpdateOpts(int(scheme), max(kmax, 1), max(bmax, 1), self._flags)
@@ -174,8 +176,10 @@ class Chain:
         self.set_opts(scheme, k, b)
 
     # -- calls with the C ABI's names
-    def set_opts(self, scheme, k=1, b=1, log=None, timing=None, ktime=None):
+    def set_opts(self, scheme, k=1, b=1, log=None, timing=None, ktime=None, fp32=None):
         flags = self._flags
+        if fp32 is not None:
+            flags = (flags & ~FLAG_FP32) | (FLAG_FP32 if fp32 else 0)
         if ktime is not None:
             flags = (flags & ~FLAG_KTIME) | (FLAG_KTIME if ktime else 0)
         if log is not None:

@@ -49,6 +49,7 @@ struct pqmc_ctx {
   double *URw[2][2] = {}, *ULw[2][2] = {};
   double *Lstack[2] = {}, *Rstack[2] = {};
   double *T[2] = {};
+  float *T32[2] = {};
   double *E[2] = {}, *F[2] = {}, *BR[2] = {}, *Z[2] = {};
   int *prow[2] = {}, *slot[2] = {};
   LocalBufs lb{};
@@ -63,6 +64,7 @@ struct pqmc_ctx {
   double *ULt[2] = {};
   int position = 0;
   bool failed = false, windowed = false;
+  bool t32_ahead = false;   // precision form: T32 holds flushes that T does not
   uint64_t sweep_index = 0;
   long long log_count = 0, hb_count = 0, hb_total = 0;
   std::vector<hipEvent_t> evs;
@@ -116,6 +118,7 @@ void layout(pqmc_ctx &c, char *base, size_t *bytes) {
     c.Lstack[s] = cv.take<double>((size_t)(c.nst + 1) * N * ns);
     c.Rstack[s] = cv.take<double>((size_t)(c.nst + 1) * N * ns);
     c.T[s] = cv.take<double>(ns * ns);
+    c.T32[s] = cv.take<float>(ns * ns);
     c.E[s] = cv.take<double>(ns * 2 * ns);
     c.F[s] = cv.take<double>(ns * ns);
     c.BR[s] = cv.take<double>((size_t)2 * kNB * 2 * ns);
@@ -172,6 +175,9 @@ pqmc_status validate(const pqmc_problem *p, const pqmc_update_opts *o) {
   if (o->scheme < PQMC_LOCAL || o->scheme > PQMC_BLOCK_FB) return set_error(PQMC_EINVAL, "scheme");
   if (o->delay_k < 1 || o->delay_k > 128) return set_error(PQMC_EINVAL, "delay_k in [1, 128]");
   if (o->block_b < 1 || o->block_b > 64) return set_error(PQMC_EINVAL, "block_b in [1, 64]");
+  if ((o->flags & PQMC_FLAG_FP32) &&
+      (o->scheme == PQMC_LOCAL || (o->scheme == PQMC_DELAYED ? o->delay_k : o->block_b) > 64))
+    return set_error(PQMC_EINVAL, "the float32 form needs the delayed or block scheme, k, b <= 64");
   const size_t NN = (size_t)p->n_sites * p->n_sites;
   for (size_t e = 0; e < NN; ++e)
     if (!std::isfinite(p->hopping[e])) return set_error(PQMC_EINVAL, "non-finite hopping matrix");
@@ -267,6 +273,29 @@ struct GemmQueue {
   }
 };
 
+bool fp32_form(const pqmc_ctx &c) { return (c.opts.flags & PQMC_FLAG_FP32) != 0; }
+
+// The float32 copy of T from the float64 one (precision form), all walkers
+// of the batch that use the form.
+int round_T(const Walkers &b) {
+  const double *src[kMaxMats];
+  float *dst[kMaxMats];
+  int m = 0;
+  long n = 0;
+  for (int i = 0; i < b.n; ++i) {
+    b[i].t32_ahead = false;
+    if (!fp32_form(b[i])) continue;
+    for (int s = 0; s < 2; ++s) {
+      src[m] = b[i].T[s];
+      dst[m] = b[i].T32[s];
+      n = std::max(n, (long)b[i].Ns[s] * b[i].Ns[s]);
+      ++m;
+    }
+  }
+  if (m) PQ_HIP_CHECK(round_to_f32(src, dst, m, n, b.lead().st));
+  return PQMC_OK;
+}
+
 ElimSpin elim_spin(pqmc_ctx &c, int s) {
   const int n = c.Ns[s];
   return ElimSpin{c.E[s], 2L * n, n, 2 * n, c.Z[s], c.prow[s], c.slot[s], c.BR[s], c.F[s], c.stats};
@@ -344,7 +373,7 @@ int refresh_T(const Walkers &b) {
     PQ_HIP_CHECK(set_identity_block(E, m, 2 * n, n, n, L.st));
     PQ_HIP_CHECK(gj_invert(es, m, out, n, L.st));
   }
-  return PQMC_OK;
+  return round_T(b);
 }
 
 double *slot(double *stack, int j, const pqmc_ctx &c, int s) {
@@ -514,6 +543,7 @@ int update_slice(const Walkers &b, int l, int dir) {
     x[i] = sweep_ctx(c, l, dir);
     for (int s = 0; s < 2; ++s) {
       m[i].T[s] = c.T[s];
+      m[i].T32[s] = c.T32[s];
       m[i].UR[s] = c.UR[s];
       m[i].ULt[s] = c.ULt[s];
       m[i].Ns[s] = c.Ns[s];
@@ -538,6 +568,7 @@ int update_slice(const Walkers &b, int l, int dir) {
       const int k = std::min(delayed ? L.opts.delay_k : L.opts.block_b, N);
       const bool fused = L.gmax <= 64;
       const int mode = delayed ? kUniDelayed : kUniBlock;
+      const bool fp32 = fp32_form(L);
       long long bi = 0;
       int g_prev = -1, kk_prev = 0;
       for (int g0 = 0; g0 < N; g0 += k, ++bi) {
@@ -545,7 +576,8 @@ int update_slice(const Walkers &b, int l, int dir) {
         if (fused) {
           {
             KTimer kt(L, PQMC_K_TILE);
-            PQ_HIP_CHECK(group_tile(m, gb, nw, g_prev >= 0, g_prev, kk_prev, g0, kk, L.st));
+            PQ_HIP_CHECK(
+                group_tile(m, gb, nw, g_prev >= 0, g_prev, kk_prev, g0, kk, fp32, L.st));
           }
           KTimer kt(L, PQMC_K_REDUCE);
           PQ_HIP_CHECK(group_reduce(m, gb, x, nw, mode, g0, kk, L.st));
@@ -566,8 +598,10 @@ int update_slice(const Walkers &b, int l, int dir) {
       }
       if (fused && g_prev >= 0) {
         KTimer kt(L, PQMC_K_TILE);
-        PQ_HIP_CHECK(group_tile(m, gb, nw, true, g_prev, kk_prev, 0, 0, L.st));
+        PQ_HIP_CHECK(group_tile(m, gb, nw, true, g_prev, kk_prev, 0, 0, fp32, L.st));
       }
+      if (fp32)
+        for (int i = 0; i < nw; ++i) b[i].t32_ahead = true;
       for (int i = 0; i < nw; ++i) {
         if (delayed) {
           b[i].log_count += N;
@@ -760,9 +794,10 @@ pqmc_status check_batch(pqmc_ctx *const *w, int n) {
     const pqmc_ctx &a = *w[0], &c = *w[i];
     if (c.N != a.N || c.Ns[0] != a.Ns[0] || c.Ns[1] != a.Ns[1] || c.M != a.M || c.kt != a.kt ||
         c.gmax != a.gmax || c.opts.scheme != a.opts.scheme || c.opts.delay_k != a.opts.delay_k ||
-        c.opts.block_b != a.opts.block_b || c.st != a.st)
+        c.opts.block_b != a.opts.block_b || c.st != a.st || fp32_form(c) != fp32_form(a))
       return set_error(PQMC_EINVAL,
-                       "batched walkers need the same N, N_sigma, M, k_tau, scheme, k, b, stream");
+                       "batched walkers need the same N, N_sigma, M, k_tau, scheme, k, b, "
+                       "precision form and stream");
     for (int j = 0; j < i; ++j)
       if (w[j] == w[i]) return set_error(PQMC_EINVAL, "a context appears twice in the batch");
     if (c.failed) return set_error(PQMC_ESTATE, "context failed; call pqmc_set_fields");
@@ -866,7 +901,24 @@ pqmc_status pqmc_set_opts(pqmc_ctx *c, const pqmc_update_opts *o) {
     return set_error(PQMC_EINVAL, "block_b exceeds the workspace bound");
   if ((o->flags & PQMC_FLAG_LOG) && !c->log_alloc)
     return set_error(PQMC_EINVAL, "logging was not sized in the workspace");
+  if ((o->flags & PQMC_FLAG_FP32) &&
+      (o->scheme == PQMC_LOCAL || (o->scheme == PQMC_DELAYED ? o->delay_k : o->block_b) > 64))
+    return set_error(PQMC_EINVAL, "the float32 form needs the delayed or block scheme, k, b <= 64");
+  const bool was = fp32_form(*c), now = (o->flags & PQMC_FLAG_FP32) != 0;
   c->opts = *o;
+  // the current T moves to the representation the next call reads
+  hipError_t e = hipSuccess;
+  if (now && !was) {
+    const double *src[2] = {c->T[0], c->T[1]};
+    float *dst[2] = {c->T32[0], c->T32[1]};
+    e = round_to_f32(src, dst, 2, (long)std::max(c->Ns[0], c->Ns[1]) * std::max(c->Ns[0], c->Ns[1]), c->st);
+  } else if (was && !now && c->t32_ahead) {
+    const float *src[2] = {c->T32[0], c->T32[1]};
+    double *dst[2] = {c->T[0], c->T[1]};
+    e = widen_to_f64(src, dst, 2, (long)std::max(c->Ns[0], c->Ns[1]) * std::max(c->Ns[0], c->Ns[1]), c->st);
+  }
+  if (e != hipSuccess) return as_status(fail_device(e, "precision switch", __FILE__, __LINE__));
+  c->t32_ahead = false;
   return PQMC_OK;
 }
 
@@ -958,6 +1010,13 @@ pqmc_status pqmc_forward_window(pqmc_ctx *c, int32_t n_slices, pqmc_stats *out) 
 pqmc_status pqmc_get_green(pqmc_ctx *c, int32_t spin, double *out) {
   if (!c || !out || spin < 0 || spin > 1) return set_error(PQMC_EINVAL, "bad argument");
   const int N = c->N, n = c->Ns[spin];
+  if (fp32_form(*c) && c->t32_ahead) {
+    // flushes since the last stabilisation live in the float32 copy only
+    const float *src[1] = {c->T32[spin]};
+    double *dst[1] = {c->T[spin]};
+    hipError_t e = widen_to_f64(src, dst, 1, (long)n * n, c->st);
+    if (e != hipSuccess) return as_status(fail_device(e, "green", __FILE__, __LINE__));
+  }
   GemmBatch a{};
   a.d[a.count++] = gemm_desc(c->UR[spin], n, c->T[spin], n, c->xtmp, n, N, n, n);
   hipError_t e = gemm(a, false, false, c->st);

@@ -466,6 +466,25 @@ __global__ void copy_kernel(const double *s0, const double *s1, long lds, double
     d[(long)r * ldd + c] = s[(long)r * lds + c];
 }
 
+struct ConvArgs {
+  const void *src[kMaxMats];
+  void *dst[kMaxMats];
+};
+
+__global__ void round_kernel(ConvArgs a, long n) {
+  const double *s = static_cast<const double *>(a.src[blockIdx.y]);
+  float *d = static_cast<float *>(a.dst[blockIdx.y]);
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x)
+    d[e] = (float)s[e];
+}
+
+__global__ void widen_kernel(ConvArgs a, long n) {
+  const float *s = static_cast<const float *>(a.src[blockIdx.y]);
+  double *d = static_cast<double *>(a.dst[blockIdx.y]);
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x)
+    d[e] = (double)s[e];
+}
+
 __global__ void init_fields_kernel(int8_t *f, int M, int N, uint64_t k0, uint64_t k1) {
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (long)M * N) return;
@@ -551,6 +570,30 @@ hipError_t copy_matrix(const double *src0, const double *src1, long lds, double 
   dim3 grid(min((cols + 255) / 256, 8), rows, dst1 ? 2 : 1);
   hipLaunchKernelGGL(copy_kernel, grid, dim3(256), 0, st, src0, src1, lds, dst0, dst1, ldd, rows,
                      cols);
+  return hipGetLastError();
+}
+
+hipError_t round_to_f32(const double *const *src, float *const *dst, int nmat, long n,
+                        hipStream_t st) {
+  if (nmat < 1 || nmat > kMaxMats) return hipErrorInvalidValue;
+  ConvArgs a{};
+  for (int i = 0; i < nmat; ++i) {
+    a.src[i] = src[i];
+    a.dst[i] = dst[i];
+  }
+  hipLaunchKernelGGL(round_kernel, dim3(256, nmat), dim3(256), 0, st, a, n);
+  return hipGetLastError();
+}
+
+hipError_t widen_to_f64(const float *const *src, double *const *dst, int nmat, long n,
+                        hipStream_t st) {
+  if (nmat < 1 || nmat > kMaxMats) return hipErrorInvalidValue;
+  ConvArgs a{};
+  for (int i = 0; i < nmat; ++i) {
+    a.src[i] = src[i];
+    a.dst[i] = dst[i];
+  }
+  hipLaunchKernelGGL(widen_kernel, dim3(256, nmat), dim3(256), 0, st, a, n);
   return hipGetLastError();
 }
 

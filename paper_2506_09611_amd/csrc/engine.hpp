@@ -66,6 +66,11 @@ hipError_t set_identity_block(double *const *E, int nmat, long ld, int n, int co
                               hipStream_t st);
 hipError_t copy_matrix(const double *src0, const double *src1, long lds, double *dst0,
                        double *dst1, long ldd, int rows, int cols, hipStream_t st);
+// dst = (float) src, dst = (double) src (n elements each, up to kMaxMats pairs)
+hipError_t round_to_f32(const double *const *src, float *const *dst, int nmat, long n,
+                        hipStream_t st);
+hipError_t widen_to_f64(const float *const *src, double *const *dst, int nmat, long n,
+                        hipStream_t st);
 hipError_t init_fields(int8_t *fields, int M, int N, uint64_t k0, uint64_t k1, hipStream_t st);
 
 // ---------------------------------------------------------- field updates
@@ -80,6 +85,7 @@ struct Batch {
 
 struct SpinMats {
   double *T[2];          // Ns x Ns
+  float *T32[2];         // Ns x Ns, the precision form's T (null otherwise)
   double *UR[2];         // N x Ns (rows = u_i^T)
   const double *ULt[2];  // N x Ns (rows = columns of U_L)
   int Ns[2];
@@ -126,8 +132,10 @@ hipError_t group_flush(const SpinMats *m, const GroupBufs *g, int nw, int g0, in
 // Fused path (kmax <= 64): one tile kernel per group applies the previous
 // group's flush and forms this group's split-K panel partials; group_reduce
 // sums them into P1, P2 and W0.
+// fp32: the precision form, T in float32 (SpinMats::T32) and the products
+// on FP32 MFMA with FP32 accumulation.
 hipError_t group_tile(const SpinMats *m, const GroupBufs *g, int nw, bool flush, int g0_prev,
-                      int kk_prev, int g0, int kk, hipStream_t st);
+                      int kk_prev, int g0, int kk, bool fp32, hipStream_t st);
 hipError_t group_reduce(const SpinMats *m, const GroupBufs *g, const SweepCtx *c, int nw,
                         int mode, int g0, int kk, hipStream_t st);
 

@@ -7,8 +7,34 @@
 #include <hip/hip_runtime.h>
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
+typedef float flt4 __attribute__((ext_vector_type(4)));
 
 namespace pq {
+
+// One 16x16x4 MFMA step in float64 or float32.  Operand layout as above for
+// both; the accumulator layouts differ (both measured on the device):
+//   f64 (v_mfma_f64_16x16x4f64): lane l, register j holds D(l / 16 + 4 j, l % 16)
+//   f32 (v_mfma_f32_16x16x4f32): lane l, register j holds D(4 (l / 16) + j, l % 16)
+template <class R>
+struct Mma;
+template <>
+struct Mma<double> {
+  typedef dbl4 acc;
+  __device__ static acc zero() { return acc{0.0, 0.0, 0.0, 0.0}; }
+  __device__ static acc op(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static int row(int lane, int j) { return (lane >> 4) + 4 * j; }
+};
+template <>
+struct Mma<float> {
+  typedef flt4 acc;
+  __device__ static acc zero() { return acc{0.f, 0.f, 0.f, 0.f}; }
+  __device__ static acc op(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static int row(int lane, int j) { return 4 * (lane >> 4) + j; }
+};
 
 // One 16x16 tile: A (16 x K) B (K x 16), K a multiple of 4, with
 // A(i, k) = Am[i * lda + k] and B(k, j) = Bm[k * ldb + j] (TB: Bm[j * ldb + k]).

@@ -1033,9 +1033,25 @@ struct TileArgs {
 
 constexpr int kLdt = 65;   // padded LDS row stride
 
-// KP: kmax rounded up to a multiple of 16 (16, 32 or 64).
-template <int KP>
+// T of spin s in the type the tile kernel works in
+template <class R>
+__device__ __forceinline__ R *tile_matrix(const SpinMats &m, int s);
+template <>
+__device__ __forceinline__ double *tile_matrix<double>(const SpinMats &m, int s) {
+  return m.T[s];
+}
+template <>
+__device__ __forceinline__ float *tile_matrix<float>(const SpinMats &m, int s) {
+  return m.T32[s];
+}
+
+// KP: kmax rounded up to a multiple of 16 (16, 32 or 64).  R: the type T is
+// kept in and multiplied in between stabilisations (double, or float for
+// the precision form); the pending group's panels and Mc arrive in double
+// and are rounded to R, and the split-K partials leave in double.
+template <int KP, class R>
 __global__ __launch_bounds__(256) void group_tile_kernel(Batch<TileArgs> B) {
+  typedef Mma<R> MM;
   // XCD-aware placement: consecutive workgroup ids go round-robin to the 8
   // XCDs, so XCD x receives ids x, x + 8, ...; giving it the contiguous range
   // [x per, (x + 1) per) of (matrix, tile) indices keeps the tiles that share
@@ -1061,22 +1077,24 @@ __global__ __launch_bounds__(256) void group_tile_kernel(Batch<TileArgs> B) {
   const int kmax = a.g.kmax;
   const int kk = a.kk, kkp = a.kk_prev;
   const int kp = (kkp + 3) & ~3;            // flush rank rounded to the MFMA depth
-  double *T = a.m.T[s];
-  extern __shared__ double lds[];
+  R *T = tile_matrix<R>(a.m, s);
+  extern __shared__ double lds_raw[];
+  R *lds = reinterpret_cast<R *>(lds_raw);
 
   // ---- every load first: T tile, the pending flush's operands, next panels
-  dbl4 acc[2][2];
+  typename MM::acc acc[2][2];
 #pragma unroll
   for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
     for (int ni = 0; ni < 2; ++ni)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int r = row0 + acc_row(wm, mi, lane, j), c = col0 + acc_col(wn, ni, lane);
+        const int r = row0 + (wm * 32 + mi * 16 + MM::row(lane, j)), c = col0 + acc_col(wn, ni, lane);
         acc[mi][ni][j] = (r < Ns && c < Ns) ? T[(long)r * Ns + c] : 0.0;
       }
   const bool fl = a.flush && a.g.nA[0] > 0;
-  double p1v[kPre], p2v[kPre], mcv[kPreM], urv[kPre];
+  R p1v[kPre], p2v[kPre], mcv[kPreM];
+  double urv[kPre];
   if (fl) {
     const double *P1 = a.g.P1[s], *P2 = a.g.P2[s], *Mc = a.g.Mc[s];
     const double *UR = a.m.UR[s];
@@ -1099,7 +1117,7 @@ __global__ __launch_bounds__(256) void group_tile_kernel(Batch<TileArgs> B) {
       mcv[i] = (e < kpad * kpad && ma < kkp && mb < kkp) ? Mc[ma * kmax + mb] : 0.0;
     }
   }
-  double ug[kPre], lg[kPre];
+  R ug[kPre], lg[kPre];
   if (kk > 0) {
     const double *UR = a.m.UR[s], *ULt = a.m.ULt[s];
 #pragma unroll
@@ -1115,9 +1133,9 @@ __global__ __launch_bounds__(256) void group_tile_kernel(Batch<TileArgs> B) {
   // ---- (1) pending flush: T_tile -= (P1 Mc) P2
   if (fl) {
     const int ld1 = kpad + 1;
-    double *A1 = lds;                       // 64 x ld1: P1 rows
-    double *M1 = A1 + 64 * ld1;             // kpad x ld1: Mc
-    double *B1 = M1 + kpad * ld1;           // kpad x kLdt: P2 columns
+    R *A1 = lds;                            // 64 x ld1: P1 rows
+    R *M1 = A1 + 64 * ld1;                  // kpad x ld1: Mc
+    R *B1 = M1 + kpad * ld1;                // kpad x kLdt: P2 columns
 #pragma unroll
     for (int i = 0; i < kPre; ++i) {
       const int e = t + 256 * i;
@@ -1133,32 +1151,42 @@ __global__ __launch_bounds__(256) void group_tile_kernel(Batch<TileArgs> B) {
     // -(P1 Mc): wave w forms rows [16 w, 16 w + 16), its KP / 16 column
     // tiles as independent accumulators, and overwrites those rows of A1
     {
-      dbl4 q[KP / 16];
+      typename MM::acc q[KP / 16];
 #pragma unroll
-      for (int u = 0; u < KP / 16; ++u) q[u] = dbl4{0.0, 0.0, 0.0, 0.0};
+      for (int u = 0; u < KP / 16; ++u) q[u] = MM::zero();
       const int li = lane & 15, lk = lane >> 4;
       for (int k0 = 0; k0 < kp; k0 += 4) {
-        const double av = A1[(16 * wave + li) * ld1 + k0 + lk];
+        const R av = A1[(16 * wave + li) * ld1 + k0 + lk];
 #pragma unroll
-        for (int u = 0; u < KP / 16; ++u)
-          q[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, M1[(k0 + lk) * ld1 + u * 16 + li],
-                                                      q[u], 0, 0, 0);
+        for (int u = 0; u < KP / 16; ++u) q[u] = MM::op(av, M1[(k0 + lk) * ld1 + u * 16 + li], q[u]);
       }
 #pragma unroll
       for (int u = 0; u < KP / 16; ++u)
 #pragma unroll
         for (int j = 0; j < 4; ++j)
-          A1[(16 * wave + lk + 4 * j) * ld1 + u * 16 + li] = -q[u][j];
+          A1[(16 * wave + MM::row(lane, j)) * ld1 + u * 16 + li] = -q[u][j];
     }
     __syncthreads();
-    lds_mma<false>(acc, A1, ld1, B1, kLdt, kp, 64, 64, wm, wn, lane);
+    // acc (this wave's 32 x 32 quadrant) += A1 (64 x kp) B1 (kp x 64)
+    {
+      const int i0 = wm * 32 + (lane & 15), j0 = wn * 32 + (lane & 15);
+      for (int k0 = 0; k0 < kp; k0 += 4) {
+        const int kq = k0 + (lane >> 4);
+        const R a0 = A1[i0 * ld1 + kq], a1 = A1[(i0 + 16) * ld1 + kq];
+        const R b0 = B1[kq * kLdt + j0], b1 = B1[kq * kLdt + j0 + 16];
+        acc[0][0] = MM::op(a0, b0, acc[0][0]);
+        acc[0][1] = MM::op(a0, b1, acc[0][1]);
+        acc[1][0] = MM::op(a1, b0, acc[1][0]);
+        acc[1][1] = MM::op(a1, b1, acc[1][1]);
+      }
+    }
 #pragma unroll
     for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
       for (int ni = 0; ni < 2; ++ni)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const int r = row0 + acc_row(wm, mi, lane, j), c = col0 + acc_col(wn, ni, lane);
+          const int r = row0 + (wm * 32 + mi * 16 + MM::row(lane, j)), c = col0 + acc_col(wn, ni, lane);
           if (r < Ns && c < Ns) T[(long)r * Ns + c] = acc[mi][ni][j];
         }
     if (rb == 0) {
@@ -1176,16 +1204,16 @@ __global__ __launch_bounds__(256) void group_tile_kernel(Batch<TileArgs> B) {
 
   if (kk <= 0) return;
   // ---- (2) next group's split-K panel partials from the updated tile
-  double *X = lds;                 // 64 x kLdt: T tile
-  double *Y = X + 64 * kLdt;       // kpad x kLdt: U_g over the tile's rows
-  double *Z = Y + kpad * kLdt;     // kpad x kLdt: L_g over the tile's columns
+  R *X = lds;                      // 64 x kLdt: T tile
+  R *Y = X + 64 * kLdt;            // kpad x kLdt: U_g over the tile's rows
+  R *Z = Y + kpad * kLdt;          // kpad x kLdt: L_g over the tile's columns
 #pragma unroll
   for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
     for (int ni = 0; ni < 2; ++ni)
 #pragma unroll
       for (int j = 0; j < 4; ++j)
-        X[acc_row(wm, mi, lane, j) * kLdt + acc_col(wn, ni, lane)] = acc[mi][ni][j];
+        X[(wm * 32 + mi * 16 + MM::row(lane, j)) * kLdt + acc_col(wn, ni, lane)] = acc[mi][ni][j];
 #pragma unroll
   for (int i = 0; i < kPre; ++i) {
     const int e = t + 256 * i;
@@ -1206,7 +1234,7 @@ __global__ __launch_bounds__(256) void group_tile_kernel(Batch<TileArgs> B) {
   double *o2 = a.g.P2part[s] + (long)rb * kmax * Ns;
   double *o1 = a.g.P1part[s] + (long)cb * Ns * kmax;
   double *ow = a.g.W0part[s] + (long)(rb * nt + cb) * kmax * kmax;
-  dbl4 p2t[U], p1t[U];
+  typename MM::acc p2t[U], p1t[U];
   int mt2[U], ct2[U], rt1[U], mt1[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
@@ -1216,18 +1244,14 @@ __global__ __launch_bounds__(256) void group_tile_kernel(Batch<TileArgs> B) {
     ct2[u] = v ? tt & 3 : 0;
     rt1[u] = v ? tt / mtk : 0;    // P1 tiles: 4 x mtk, as many as P2 tiles
     mt1[u] = v ? tt % mtk : 0;
-    p2t[u] = p1t[u] = dbl4{0.0, 0.0, 0.0, 0.0};
+    p2t[u] = p1t[u] = MM::zero();
   }
   for (int k0 = 0; k0 < 64; k0 += 4) {
     const int k = k0 + lk;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      p2t[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(Y[(mt2[u] * 16 + li) * kLdt + k],
-                                                    X[k * kLdt + ct2[u] * 16 + li], p2t[u], 0,
-                                                    0, 0);
-      p1t[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(X[(rt1[u] * 16 + li) * kLdt + k],
-                                                    Z[(mt1[u] * 16 + li) * kLdt + k], p1t[u], 0,
-                                                    0, 0);
+      p2t[u] = MM::op(Y[(mt2[u] * 16 + li) * kLdt + k], X[k * kLdt + ct2[u] * 16 + li], p2t[u]);
+      p1t[u] = MM::op(X[(rt1[u] * 16 + li) * kLdt + k], Z[(mt1[u] * 16 + li) * kLdt + k], p1t[u]);
     }
   }
 #pragma unroll
@@ -1235,9 +1259,9 @@ __global__ __launch_bounds__(256) void group_tile_kernel(Batch<TileArgs> B) {
     if (wave + 4 * u >= n2) continue;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int m = mt2[u] * 16 + lk + 4 * j, c = col0 + ct2[u] * 16 + li;
+      const int m = mt2[u] * 16 + MM::row(lane, j), c = col0 + ct2[u] * 16 + li;
       if (m < kk && c < Ns) o2[(long)m * Ns + c] = p2t[u][j];
-      const int r = row0 + rt1[u] * 16 + lk + 4 * j, m1 = mt1[u] * 16 + li;
+      const int r = row0 + rt1[u] * 16 + MM::row(lane, j), m1 = mt1[u] * 16 + li;
       if (r < Ns && m1 < kk) o1[(long)r * kmax + m1] = p1t[u][j];
     }
   }
@@ -1247,11 +1271,11 @@ __global__ __launch_bounds__(256) void group_tile_kernel(Batch<TileArgs> B) {
     if (wave + 4 * u >= n2) continue;
 #pragma unroll
     for (int j = 0; j < 4; ++j)
-      Y[(mt2[u] * 16 + lk + 4 * j) * kLdt + ct2[u] * 16 + li] = p2t[u][j];
+      Y[(mt2[u] * 16 + MM::row(lane, j)) * kLdt + ct2[u] * 16 + li] = p2t[u][j];
   }
   __syncthreads();
   // W0 tiles, depth split in two halves (two accumulators per tile)
-  dbl4 w0t[UW][2];
+  typename MM::acc w0t[UW][2];
   int mtw[UW], ntw[UW];
 #pragma unroll
   for (int u = 0; u < UW; ++u) {
@@ -1259,7 +1283,7 @@ __global__ __launch_bounds__(256) void group_tile_kernel(Batch<TileArgs> B) {
     const bool v = tt < mtk * mtk;
     mtw[u] = v ? tt / mtk : 0;
     ntw[u] = v ? tt % mtk : 0;
-    w0t[u][0] = w0t[u][1] = dbl4{0.0, 0.0, 0.0, 0.0};
+    w0t[u][0] = w0t[u][1] = MM::zero();
   }
   for (int k0 = 0; k0 < 32; k0 += 4) {
 #pragma unroll
@@ -1267,9 +1291,8 @@ __global__ __launch_bounds__(256) void group_tile_kernel(Batch<TileArgs> B) {
       const int k = h * 32 + k0 + lk;
 #pragma unroll
       for (int u = 0; u < UW; ++u)
-        w0t[u][h] = __builtin_amdgcn_mfma_f64_16x16x4f64(Y[(mtw[u] * 16 + li) * kLdt + k],
-                                                         Z[(ntw[u] * 16 + li) * kLdt + k],
-                                                         w0t[u][h], 0, 0, 0);
+        w0t[u][h] = MM::op(Y[(mtw[u] * 16 + li) * kLdt + k], Z[(ntw[u] * 16 + li) * kLdt + k],
+                           w0t[u][h]);
     }
   }
 #pragma unroll
@@ -1277,8 +1300,8 @@ __global__ __launch_bounds__(256) void group_tile_kernel(Batch<TileArgs> B) {
     if (wave + 4 * u >= mtk * mtk) continue;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int m = mtw[u] * 16 + lk + 4 * j, n = ntw[u] * 16 + li;
-      if (m < kk && n < kk) ow[m * kmax + n] = w0t[u][0][j] + w0t[u][1][j];
+      const int m = mtw[u] * 16 + MM::row(lane, j), n = ntw[u] * 16 + li;
+      if (m < kk && n < kk) ow[m * kmax + n] = (double)w0t[u][0][j] + (double)w0t[u][1][j];
     }
   }
 }
@@ -1420,26 +1443,26 @@ hipError_t block_decide(const GroupBufs *g, const SweepCtx *c, int nw, int g0, i
   return hipGetLastError();
 }
 
-template <int KP>
+template <int KP, class R>
 hipError_t launch_tile(const Batch<TileArgs> &B, int nw, int nt, hipStream_t st) {
   const size_t flush_lds = (size_t)64 * (KP + 1) + (size_t)KP * (KP + 1) + (size_t)KP * kLdt;
   const size_t panel_lds = (size_t)64 * kLdt + 2 * (size_t)KP * kLdt;
-  const size_t lds = sizeof(double) * std::max(flush_lds, panel_lds);
+  const size_t lds = sizeof(R) * std::max(flush_lds, panel_lds);
   static bool attr_set = false;
   if (!attr_set) {
-    // at most 133 KB (KP = 64) of the 160 KB per CU
-    hipError_t e = hipFuncSetAttribute((const void *)group_tile_kernel<KP>,
+    // at most 100 KB (KP = 64, double) of the 160 KB per CU
+    hipError_t e = hipFuncSetAttribute((const void *)group_tile_kernel<KP, R>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
   const int total = 2 * nw * nt * nt;
-  hipLaunchKernelGGL(group_tile_kernel<KP>, dim3((total + 7) / 8 * 8), dim3(256), lds, st, B);
+  hipLaunchKernelGGL((group_tile_kernel<KP, R>), dim3((total + 7) / 8 * 8), dim3(256), lds, st, B);
   return hipGetLastError();
 }
 
 hipError_t group_tile(const SpinMats *m, const GroupBufs *g, int nw, bool flush, int g0_prev,
-                      int kk_prev, int g0, int kk, hipStream_t st) {
+                      int kk_prev, int g0, int kk, bool fp32, hipStream_t st) {
   if (nw < 1 || nw > kMaxBatch) return hipErrorInvalidValue;
   Batch<TileArgs> B{};
   int kmax = 0;
@@ -1459,9 +1482,15 @@ hipError_t group_tile(const SpinMats *m, const GroupBufs *g, int nw, bool flush,
     B.w[w].nmat = 2 * nw;
     B.w[w].tpm = nt * nt;
   }
-  if (kmax <= 16) return launch_tile<16>(B, nw, nt, st);
-  if (kmax <= 32) return launch_tile<32>(B, nw, nt, st);
-  if (kmax <= 64) return launch_tile<64>(B, nw, nt, st);
+  if (fp32) {
+    if (kmax <= 16) return launch_tile<16, float>(B, nw, nt, st);
+    if (kmax <= 32) return launch_tile<32, float>(B, nw, nt, st);
+    if (kmax <= 64) return launch_tile<64, float>(B, nw, nt, st);
+    return hipErrorInvalidValue;
+  }
+  if (kmax <= 16) return launch_tile<16, double>(B, nw, nt, st);
+  if (kmax <= 32) return launch_tile<32, double>(B, nw, nt, st);
+  if (kmax <= 64) return launch_tile<64, double>(B, nw, nt, st);
   return hipErrorInvalidValue;
 }
 

@@ -1,0 +1,125 @@
+"""The precision form (PQMC_FLAG_FP32): T in float32 between stabilisations,
+flush and panels on FP32 MFMA; ratios, decisions, QR and inverse in float64.
+
+Error statement, checked here against the float64 oracle on the 40x40
+lattice (N_sigma = 800, k = 32 and b = 16, the benchmark's launch shapes):
+  * margins (|A| - u) agree to 1e-4 relative; a decision may differ from the
+    oracle's only where its margin lies inside that band (the chains then
+    part, and the window is not compared further);
+  * G after 5 slices (no stabilisation yet, the largest drift): relative
+    error below 5e-5 (measured 5.7e-6 delayed, 2.6e-6 block), energy
+    relative error below 1e-6 (measured 3e-9, 4e-8);
+  * G after 10 slices (just past a stabilisation, T recomputed in float64):
+    back to the float64 bar, 1e-10.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle.pqmc import Walker
+from oracle.observables import energy, double_occupancy
+from gpu_util import make_chain, compare_decisions, green_rel_err
+
+BAND = 1e-4   # float32 drift band of a margin, relative
+
+
+def compare_fp32(meta, margin, ref_log, sweep, M):
+    """Decisions of a precision-form call vs the oracle's.  Returns
+    (n_compared, n_inside_band, same_chain)."""
+    ref = [e for e in ref_log if e[0] == sweep]
+    assert len(ref) == len(meta), (len(ref), len(meta))
+    n_band = 0
+    for n, ((code, site, acc), mg, e) in enumerate(zip(meta, margin, ref)):
+        assert int(code) == e[1] * M + e[2] and int(site) == e[3], (n, code, site, e)
+        near = abs(e[5]) < BAND * max(1.0, abs(e[5]))
+        n_band += near
+        if bool(acc) != e[4]:
+            assert near, f"decision {n} differs outside the float32 band: {mg} vs {e}"
+            return n, n_band, False
+        if not (np.isinf(mg) or np.isinf(e[5])):
+            assert abs(mg - e[5]) < BAND * max(1.0, abs(e[5])), (n, mg, e[5])
+    return len(ref), n_band, True
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2506_09611_amd import load_library
+    load_library()
+
+
+@pytest.mark.parametrize("scheme,kw", [("delayed", {"k": 32}), ("block", {"b": 16})])
+@pytest.mark.parametrize("window,g_tol,e_tol", [(5, 5e-5, 1e-6), (10, 1e-10, 1e-11)])
+def test_fp32_form_c3_window(scheme, kw, window, g_tol, e_tol):
+    p = synth.workload("c3", n_slices=20, stab_every=10)
+    ch = make_chain(p, scheme, fp32=True, **kw)
+    w = Walker(p, scheme, **kw)
+    ch.forward_window(window)
+    w.forward_window(window)
+    meta, margin = ch.decisions()
+    n, n_band, same = compare_fp32(meta, margin, w.log, 0, p.n_slices)
+    print(f"fp32 {scheme} {kw} window {window}: {n} decisions equal, {n_band} inside the "
+          f"band, same chain {same}", flush=True)
+    if not same:
+        return
+    assert np.array_equal(ch.fields(), w.fields)
+    gerr = green_rel_err(ch, w)
+    Gg = [ch.green(s) for s in range(2)]
+    Gw = [w.green(s) for s in range(2)]
+    e_gpu, e_ref = energy(p.hopping, Gg[0], Gg[1], p.U), energy(p.hopping, Gw[0], Gw[1], p.U)
+    eerr = abs(e_gpu - e_ref) / abs(e_ref)
+    derr = abs(double_occupancy(*Gg) - double_occupancy(*Gw))
+    print(f"fp32 {scheme} {kw} window {window}: {n} decisions equal, G rel err {gerr:.3e}, "
+          f"E rel err {eerr:.3e} (E = {e_ref:.6f}), D abs err {derr:.3e}", flush=True)
+    assert gerr < g_tol
+    assert eerr < e_tol
+    ch.close()
+
+
+def test_fp32_batch_matches_single():
+    """The precision form batched (8 walkers) vs the same walkers alone."""
+    import dataclasses
+    from paper_2506_09611_amd import batch_forward_window
+    p = synth.make_problem(10, 37, 37, 4.0, n_slices=10, stab_every=5, perturb=1e-3,
+                           seed=synth.SEED_BASE + 41)
+    probs = [dataclasses.replace(p, walker_id=w) for w in range(8)]
+    chains = [make_chain(q, "delayed", k=16, fp32=True) for q in probs]
+    batch_forward_window(chains, 7)
+    for q, c in zip(probs, chains):
+        s = make_chain(q, "delayed", k=16, fp32=True)
+        s.forward_window(7)
+        assert np.array_equal(c.decisions()[0], s.decisions()[0])
+        for sp in range(2):
+            assert np.array_equal(c.green(sp), s.green(sp))
+        s.close()
+    for c in chains:
+        c.close()
+
+
+def test_fp32_switch_round_trip():
+    """Switching the form on and off between calls keeps the chain exact up to
+    the float32 rounding of T: after a stabilisation the float64 bar holds."""
+    p = synth.make_problem(4, 5, 5, 4.0, n_slices=20, stab_every=5, perturb=1e-3,
+                           seed=synth.SEED_BASE + 42)
+    from paper_2506_09611_amd import Scheme
+    ch = make_chain(p, "delayed", k=4)
+    w = Walker(p, "delayed", k=4)
+    ch.set_opts(Scheme.DELAYED, 4, 1, fp32=True)
+    ch.sweep(1)
+    w.sweep()
+    meta, margin = ch.decisions()
+    n, n_band, same = compare_fp32(meta, margin, w.log, 0, p.n_slices)
+    if same:
+        assert green_rel_err(ch, w) < 1e-10   # the sweep ends on a stabilisation
+    ch.set_opts(Scheme.DELAYED, 4, 1, fp32=False)
+    ch.sweep(1)
+    w.sweep()
+    meta, margin = ch.decisions()
+    n2, low2 = (compare_decisions(meta, margin, w.log, 1, p.n_slices) if same else (0, 1))
+    if same and not low2:
+        assert green_rel_err(ch, w) < 1e-10
+    ch.close()
