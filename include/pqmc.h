@@ -166,10 +166,16 @@ pqmc_status pqmc_forward_window(pqmc_ctx *ctx, int32_t n_slices, pqmc_stats *out
 /* Batched walkers: run the sweeps of n contexts (1 <= n <= 8) in lockstep,
  * every kernel launch covering all of them (independent Markov chains, each
  * with its own Philox key, fields, stack and statistics).  The contexts must
- * have been created with the same n_sites, n_up, n_dn, n_slices, stab_every,
- * scheme, delay_k, block_b and stream (PQMC_EINVAL otherwise); their
- * hopping matrices, U and seeds may differ.  Each walker's decisions, fields
- * and G are the ones pqmc_sweep would give it alone.  out: n entries or
+ * share n_slices, stab_every, scheme, delay_k, block_b, the precision form
+ * and the stream, and their workspace group bounds (the larger of
+ * min(delay_k, n_sites) and min(block_b, n_sites) at creation) must lie on
+ * the same side of 64 (PQMC_EINVAL otherwise).  With the local scheme they
+ * must also share n_sites, n_up and n_dn; with the delayed and block
+ * force-bias schemes the lattices may differ in size (n_sites, n_up, n_dn):
+ * the batch walks the groups of the largest lattice and a walker takes part
+ * in those that hold its own sites.  Hopping matrices, U and seeds may
+ * differ.  Each walker's decisions, fields and G are the ones pqmc_sweep
+ * would give it alone, bit for bit.  out: n entries or
  * NULL; the timing fields of every entry are those of the whole batch.  The
  * phase and kernel timers are those of ctxs[0]. */
 pqmc_status pqmc_batch_sweep(pqmc_ctx *const *ctxs, int32_t n, int32_t n_sweeps,

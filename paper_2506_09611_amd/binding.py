@@ -266,11 +266,12 @@ def _batch_call(chains, fn, n):
 
 
 def batch_sweep(chains, n=1):
-    """pqmc_batch_sweep: n sweeps of up to 8 chains of one shape in lockstep,
-    one launch per kernel for all of them.  Returns one stats dict per chain."""
+    """pqmc_batch_sweep: n sweeps of up to 8 chains in lockstep, one launch
+    per kernel for all of them (the delayed and block schemes accept chains of
+    different lattice sizes).  Returns one stats dict per chain."""
     return _batch_call(chains, lambda lib: lib.pqmc_batch_sweep, n)
 
 
 def batch_forward_window(chains, n_slices):
-    """pqmc_batch_forward_window for up to 8 chains of one shape."""
+    """pqmc_batch_forward_window for up to 8 chains (rules of batch_sweep)."""
     return _batch_call(chains, lambda lib: lib.pqmc_batch_forward_window, n_slices)

@@ -301,6 +301,31 @@ ElimSpin elim_spin(pqmc_ctx &c, int s) {
   return ElimSpin{c.E[s], 2L * n, n, 2 * n, c.Z[s], c.prow[s], c.slot[s], c.BR[s], c.F[s], c.stats};
 }
 
+// The (walker, spin) matrices of a batch grouped by their size N_sigma, in
+// order of first appearance: one elimination launch per size.
+struct SizeClass {
+  int n, m;
+  int w[kMaxMats], s[kMaxMats];
+};
+std::vector<SizeClass> size_classes(const Walkers &b) {
+  std::vector<SizeClass> out;
+  for (int i = 0; i < b.n; ++i)
+    for (int s = 0; s < 2; ++s) {
+      const int n = b[i].Ns[s];
+      SizeClass *sc = nullptr;
+      for (SizeClass &x : out)
+        if (x.n == n) sc = &x;
+      if (!sc) {
+        out.push_back(SizeClass{n, 0, {}, {}});
+        sc = &out.back();
+      }
+      sc->w[sc->m] = i;
+      sc->s[sc->m] = s;
+      ++sc->m;
+    }
+  return out;
+}
+
 // CholQR of the columns of A (N x Ns per walker and spin, index 2 w + s)
 // into dst: S = A^T A = R^T R, dst = A R^{-1}.  One pass suffices here: the
 // Green's function depends on U_R (U_L) only through its column (row) space,
@@ -317,22 +342,16 @@ int orthonormalize(const Walkers &b, double *const *A, double *const *dst) {
     }
   int rc = gram.flush();
   if (rc) return rc;
-  // spin sectors of equal size go in one elimination call
-  const int nsec = L.Ns[0] == L.Ns[1] ? 1 : 2;
-  for (int sec = 0; sec < nsec; ++sec) {
+  // matrices of equal size go in one elimination call
+  for (const SizeClass &sc : size_classes(b)) {
     ElimSpin es[kMaxMats];
     double *E[kMaxMats];
-    int m = 0;
-    for (int i = 0; i < b.n; ++i)
-      for (int s = 0; s < 2; ++s) {
-        if (nsec == 2 && s != sec) continue;
-        es[m] = elim_spin(b[i], s);
-        E[m] = b[i].E[s];
-        ++m;
-      }
-    const int n = es[0].n;
-    PQ_HIP_CHECK(set_identity_block(E, m, 2 * n, n, n, L.st));
-    PQ_HIP_CHECK(chol_eliminate(es, m, L.st));
+    for (int j = 0; j < sc.m; ++j) {
+      es[j] = elim_spin(b[sc.w[j]], sc.s[j]);
+      E[j] = es[j].E;
+    }
+    PQ_HIP_CHECK(set_identity_block(E, sc.m, 2 * sc.n, sc.n, sc.n, L.st));
+    PQ_HIP_CHECK(chol_eliminate(es, sc.m, L.st));
   }
   GemmQueue q{L.st, false, true};
   for (int i = 0; i < b.n; ++i)
@@ -356,22 +375,16 @@ int refresh_T(const Walkers &b) {
     }
   int rc = q.flush();
   if (rc) return rc;
-  const int nsec = L.Ns[0] == L.Ns[1] ? 1 : 2;
-  for (int sec = 0; sec < nsec; ++sec) {
+  for (const SizeClass &sc : size_classes(b)) {
     ElimSpin es[kMaxMats];
     double *E[kMaxMats], *out[kMaxMats];
-    int m = 0;
-    for (int i = 0; i < b.n; ++i)
-      for (int s = 0; s < 2; ++s) {
-        if (nsec == 2 && s != sec) continue;
-        es[m] = elim_spin(b[i], s);
-        E[m] = b[i].E[s];
-        out[m] = b[i].T[s];
-        ++m;
-      }
-    const int n = es[0].n;
-    PQ_HIP_CHECK(set_identity_block(E, m, 2 * n, n, n, L.st));
-    PQ_HIP_CHECK(gj_invert(es, m, out, n, L.st));
+    for (int j = 0; j < sc.m; ++j) {
+      es[j] = elim_spin(b[sc.w[j]], sc.s[j]);
+      E[j] = es[j].E;
+      out[j] = b[sc.w[j]].T[sc.s[j]];
+    }
+    PQ_HIP_CHECK(set_identity_block(E, sc.m, 2 * sc.n, sc.n, sc.n, L.st));
+    PQ_HIP_CHECK(gj_invert(es, sc.m, out, sc.n, L.st));
   }
   return round_T(b);
 }
@@ -564,20 +577,28 @@ int update_slice(const Walkers &b, int l, int dir) {
     }
     case PQMC_DELAYED:
     default: {
+      // Every walker's groups start at g0 = 0, k_b, 2 k_b, ... with
+      // k_b = min(k, N_max); walker w's group at g0 has
+      // kk[w] = min(k_b, N_w - g0) sites (0 once g0 >= N_w), which are the
+      // groups it forms alone, since min(k, N_w) = min(k_b, N_w).
       const bool delayed = L.opts.scheme == PQMC_DELAYED;
-      const int k = std::min(delayed ? L.opts.delay_k : L.opts.block_b, N);
-      const bool fused = L.gmax <= 64;
+      int Nmax = 0;
+      bool fused = true;
+      for (int i = 0; i < nw; ++i) {
+        Nmax = std::max(Nmax, b[i].N);
+        fused = fused && b[i].gmax <= 64;
+      }
+      const int k = std::min(delayed ? L.opts.delay_k : L.opts.block_b, Nmax);
       const int mode = delayed ? kUniDelayed : kUniBlock;
       const bool fp32 = fp32_form(L);
       long long bi = 0;
-      int g_prev = -1, kk_prev = 0;
-      for (int g0 = 0; g0 < N; g0 += k, ++bi) {
-        const int kk = std::min(k, N - g0);
+      int g_prev = 0, kk[kMaxBatch], kk_prev[kMaxBatch] = {};
+      for (int g0 = 0; g0 < Nmax; g0 += k, ++bi) {
+        for (int i = 0; i < nw; ++i) kk[i] = std::max(0, std::min(k, b[i].N - g0));
         if (fused) {
           {
             KTimer kt(L, PQMC_K_TILE);
-            PQ_HIP_CHECK(
-                group_tile(m, gb, nw, g_prev >= 0, g_prev, kk_prev, g0, kk, fp32, L.st));
+            PQ_HIP_CHECK(group_tile(m, gb, nw, g_prev, kk_prev, g0, kk, fp32, L.st));
           }
           KTimer kt(L, PQMC_K_REDUCE);
           PQ_HIP_CHECK(group_reduce(m, gb, x, nw, mode, g0, kk, L.st));
@@ -591,23 +612,24 @@ int update_slice(const Walkers &b, int l, int dir) {
         }
         if (fused) {
           g_prev = g0;
-          kk_prev = kk;
+          for (int i = 0; i < nw; ++i) kk_prev[i] = kk[i];
         } else {
           PQ_HIP_CHECK(group_flush(m, gb, nw, g0, kk, L.st));
         }
       }
-      if (fused && g_prev >= 0) {
+      if (fused && Nmax > 0) {
+        const int none[kMaxBatch] = {};
         KTimer kt(L, PQMC_K_TILE);
-        PQ_HIP_CHECK(group_tile(m, gb, nw, true, g_prev, kk_prev, 0, 0, fp32, L.st));
+        PQ_HIP_CHECK(group_tile(m, gb, nw, g_prev, kk_prev, 0, none, fp32, L.st));
       }
       if (fp32)
         for (int i = 0; i < nw; ++i) b[i].t32_ahead = true;
       for (int i = 0; i < nw; ++i) {
         if (delayed) {
-          b[i].log_count += N;
+          b[i].log_count += b[i].N;
         } else {
-          b[i].log_count += bi;
-          b[i].hb_count += N;
+          b[i].log_count += ceil_div(b[i].N, k);
+          b[i].hb_count += b[i].N;
         }
       }
       break;
@@ -787,17 +809,24 @@ int run_backward(const Walkers &b, PhaseTimer &tm) {
 }
 
 // Walkers run together must agree on everything that shapes the launches.
+// The grouped schemes (delayed, block force bias) also run lattices of
+// different sizes together: the batch walks the largest lattice's groups and
+// a smaller walker sits out the groups beyond its own sites, so that each
+// walker sees exactly the group boundaries it sees alone.
 pqmc_status check_batch(pqmc_ctx *const *w, int n) {
   if (!w || n < 1 || n > kMaxBatch) return set_error(PQMC_EINVAL, "batch size must be 1..8");
   for (int i = 0; i < n; ++i) {
     if (!w[i]) return set_error(PQMC_EINVAL, "null context in batch");
     const pqmc_ctx &a = *w[0], &c = *w[i];
-    if (c.N != a.N || c.Ns[0] != a.Ns[0] || c.Ns[1] != a.Ns[1] || c.M != a.M || c.kt != a.kt ||
-        c.gmax != a.gmax || c.opts.scheme != a.opts.scheme || c.opts.delay_k != a.opts.delay_k ||
-        c.opts.block_b != a.opts.block_b || c.st != a.st || fp32_form(c) != fp32_form(a))
+    if (c.M != a.M || c.kt != a.kt || c.opts.scheme != a.opts.scheme ||
+        c.opts.delay_k != a.opts.delay_k || c.opts.block_b != a.opts.block_b || c.st != a.st ||
+        fp32_form(c) != fp32_form(a) || (c.gmax <= 64) != (a.gmax <= 64))
       return set_error(PQMC_EINVAL,
-                       "batched walkers need the same N, N_sigma, M, k_tau, scheme, k, b, "
-                       "precision form and stream");
+                       "batched walkers need the same M, k_tau, scheme, k, b, precision form, "
+                       "stream and group-size class (all k <= 64 or all above)");
+    if (a.opts.scheme == PQMC_LOCAL &&
+        (c.N != a.N || c.Ns[0] != a.Ns[0] || c.Ns[1] != a.Ns[1]))
+      return set_error(PQMC_EINVAL, "the local scheme batches walkers of one N and N_sigma only");
     for (int j = 0; j < i; ++j)
       if (w[j] == w[i]) return set_error(PQMC_EINVAL, "a context appears twice in the batch");
     if (c.failed) return set_error(PQMC_ESTATE, "context failed; call pqmc_set_fields");

@@ -121,22 +121,26 @@ struct GroupBufs {
 };
 // Uniforms drawn by the reduce kernel for the decision that follows it.
 enum UniMode { kUniNone = 0, kUniDelayed = 1, kUniBlock = 2 };
+// Group launches over a batch: every walker's group starts at site g0 and
+// has kk[w] sites (0: the walker has no group here, its lattice is smaller).
 hipError_t group_panels(const SpinMats *m, const GroupBufs *g, const SweepCtx *c, int nw,
-                        int mode, int g0, int kk, hipStream_t st);
-hipError_t delayed_decide(const GroupBufs *g, const SweepCtx *c, int nw, int g0, int kk,
+                        int mode, int g0, const int *kk, hipStream_t st);
+hipError_t delayed_decide(const GroupBufs *g, const SweepCtx *c, int nw, int g0, const int *kk,
                           hipStream_t st);
-hipError_t block_decide(const GroupBufs *g, const SweepCtx *c, int nw, int g0, int kk,
+hipError_t block_decide(const GroupBufs *g, const SweepCtx *c, int nw, int g0, const int *kk,
                         long long block_index, hipStream_t st);
-hipError_t group_flush(const SpinMats *m, const GroupBufs *g, int nw, int g0, int kk,
+hipError_t group_flush(const SpinMats *m, const GroupBufs *g, int nw, int g0, const int *kk,
                        hipStream_t st);
 // Fused path (kmax <= 64): one tile kernel per group applies the previous
 // group's flush and forms this group's split-K panel partials; group_reduce
 // sums them into P1, P2 and W0.
 // fp32: the precision form, T in float32 (SpinMats::T32) and the products
 // on FP32 MFMA with FP32 accumulation.
-hipError_t group_tile(const SpinMats *m, const GroupBufs *g, int nw, bool flush, int g0_prev,
-                      int kk_prev, int g0, int kk, bool fp32, hipStream_t st);
+// The pending group of walker w (flushed by this launch) starts at g0_prev
+// and has kk_prev[w] sites (0: nothing pending).
+hipError_t group_tile(const SpinMats *m, const GroupBufs *g, int nw, int g0_prev,
+                      const int *kk_prev, int g0, const int *kk, bool fp32, hipStream_t st);
 hipError_t group_reduce(const SpinMats *m, const GroupBufs *g, const SweepCtx *c, int nw,
-                        int mode, int g0, int kk, hipStream_t st);
+                        int mode, int g0, const int *kk, hipStream_t st);
 
 }  // namespace pq

@@ -44,6 +44,7 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmBatch batch, int nspl
   if (g.ksplit > 0) {
     kbeg = split * g.ksplit;
     kend = min(K, kbeg + g.ksplit);
+    if (kbeg >= K) return;   // beyond this product's depth: it has fewer partials
   } else if (split > 0) {
     return;
   }

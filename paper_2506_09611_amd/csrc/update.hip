@@ -199,6 +199,7 @@ struct ReduceArgs {
   SpinMats m;
   GroupBufs g;
   int g0, kk;
+  int ntm_all;               // column strips of the launch (largest walker)
   int do_panels;             // sum the split-K partials of P1 and P2
   int w0_mode;               // W0 partials to add: 0 none, 1 one per tile (nt^2), 2 per strip (nt)
   int mode;                  // UniMode: uniforms drawn for the following decision
@@ -246,10 +247,10 @@ __global__ __launch_bounds__(kRedThreads) void group_reduce_kernel(Batch<ReduceA
   const int kk = a.kk, kmax = a.g.kmax;
   const int Ns = a.m.Ns[s];
   const int nt = (Ns + 63) / 64;
-  const int ntm = (max(a.m.Ns[0], a.m.Ns[1]) + 63) / 64;
-  const int nP = a.do_panels ? ntm * kRedParts : 0;
+  const int nP = a.do_panels ? a.ntm_all * kRedParts : 0;
   const int nW = a.w0_mode ? kk : 0;
   const int x = blockIdx.x;
+  if (kk <= 0) return;   // this walker has no group here (uneven batch)
   if (x == (int)gridDim.x - 1) {
     if (s == 0 && a.mode != kUniNone) {
       const uint64_t purpose = a.mode == kUniDelayed ? kPurposeMH : kPurposeHB;
@@ -348,6 +349,7 @@ struct DecideArgs {
 template <int kDecThreads, int kDecQ>
 __global__ __launch_bounds__(kDecThreads) void delayed_decide_kernel(Batch<DecideArgs> B) {
   const DecideArgs &A = B.w[blockIdx.x];
+  if (A.kk <= 0) return;   // no group for this walker (uneven batch)
   const int kk = A.kk;
   const int t = threadIdx.x;
   const SweepCtx &C = A.c;
@@ -490,6 +492,7 @@ __device__ __forceinline__ double recip(double p) {
 template <int KK>
 __global__ __launch_bounds__(64) void delayed_decide_wave_kernel(Batch<DecideArgs> B) {
   const DecideArgs &A = B.w[blockIdx.x];
+  if (A.kk <= 0) return;   // no group for this walker (uneven batch)
   constexpr int R = KK / 8;
   static_assert(KK % 8 == 0 && R >= 1 && R <= 4, "tile shape");
   const int kk = A.kk;
@@ -629,6 +632,7 @@ __global__ __launch_bounds__(64) void delayed_decide_wave_kernel(Batch<DecideArg
 template <int KK>
 __global__ __launch_bounds__(128) void delayed_decide_spin_kernel(Batch<DecideArgs> B) {
   const DecideArgs &A = B.w[blockIdx.x];
+  if (A.kk <= 0) return;   // no group for this walker (uneven batch)
   constexpr int R = KK / 8;
   static_assert(KK % 8 == 0 && R >= 1 && R <= 8, "tile shape");
   const int kk = A.kk;
@@ -816,6 +820,7 @@ __device__ double lds_gj_inverse(double *A, int ld, int n, double *colk, double 
 template <int NT>
 __global__ __launch_bounds__(NT) void block_decide_kernel(Batch<DecideArgs> B) {
   const DecideArgs &A = B.w[blockIdx.x];
+  if (A.kk <= 0) return;   // no group for this walker (uneven batch)
   const int kk = A.kk;
   const int t = threadIdx.x;
   const SweepCtx &C = A.c;
@@ -986,7 +991,7 @@ __global__ __launch_bounds__(256) void group_q_kernel(Batch<QArgs> B) {
   const int nt = (Ns + 63) / 64;
   const int strip = blockIdx.x;
   if (strip >= nt) return;
-  if (a.g.nA[0] == 0) return;
+  if (a.kk <= 0 || a.g.nA[0] == 0) return;
   const int kmax = a.g.kmax, kk = a.kk;
   const int t = threadIdx.x;
   const int r0 = strip * 64;
@@ -1331,35 +1336,40 @@ int max_tiles(const SpinMats *m, int nw) {
 }
 
 hipError_t launch_reduce(const SpinMats *m, const GroupBufs *g, const SweepCtx *c, int nw,
-                         int mode, int g0, int kk, int do_panels, int w0_mode, hipStream_t st) {
+                         int mode, int g0, const int *kk, int do_panels, int w0_mode,
+                         hipStream_t st) {
   if (nw < 1 || nw > kMaxBatch) return hipErrorInvalidValue;
   const int ntm = max_tiles(m, nw);
   Batch<ReduceArgs> B{};
-  for (int w = 0; w < nw; ++w)
-    B.w[w] = ReduceArgs{m[w], g[w], g0, kk, do_panels, w0_mode, mode,
+  int kkm = 0;
+  for (int w = 0; w < nw; ++w) {
+    B.w[w] = ReduceArgs{m[w], g[w], g0, kk[w], ntm, do_panels, w0_mode, mode,
                         c[w].key0, c[w].key1, c[w].sweep, c[w].slice_code};
-  const int nP = do_panels ? ntm * kRedParts : 0, nW = w0_mode ? kk : 0;
+    kkm = max(kkm, kk[w]);
+  }
+  const int nP = do_panels ? ntm * kRedParts : 0, nW = w0_mode ? kkm : 0;
   hipLaunchKernelGGL(group_reduce_kernel, dim3(nP + nW + 1, 2, nw), dim3(kRedThreads), 0, st, B);
   return hipGetLastError();
 }
 }  // namespace
 
 hipError_t group_panels(const SpinMats *m, const GroupBufs *g, const SweepCtx *c, int nw,
-                        int mode, int g0, int kk, hipStream_t st) {
+                        int mode, int g0, const int *kk, hipStream_t st) {
   if (nw < 1 || nw > kMaxBatch) return hipErrorInvalidValue;
   // split-K partial panels, then their sums (and the group's uniforms)
   for (int w0 = 0; w0 < nw; w0 += kGemmMaxBatch / 2) {
     GemmBatch b2{}, b1{};
     for (int w = w0; w < min(nw, w0 + kGemmMaxBatch / 2); ++w)
       for (int s = 0; s < 2; ++s) {
+        if (kk[w] <= 0) continue;
         const int Ns = m[w].Ns[s];
         GemmDesc d = gemm_desc(m[w].UR[s] + (long)g0 * Ns, Ns, m[w].T[s], Ns, g[w].P2part[s], Ns,
-                               kk, Ns, Ns);
+                               kk[w], Ns, Ns);
         d.ksplit = 64;
         d.csplit = (long)g[w].kmax * Ns;
         b2.d[b2.count++] = d;
         GemmDesc e = gemm_desc(m[w].T[s], Ns, m[w].ULt[s] + (long)g0 * Ns, Ns, g[w].P1part[s],
-                               g[w].kmax, Ns, kk, Ns);
+                               g[w].kmax, Ns, kk[w], Ns);
         e.ksplit = 64;
         e.csplit = (long)Ns * g[w].kmax;
         b1.d[b1.count++] = e;
@@ -1376,9 +1386,10 @@ hipError_t group_panels(const SpinMats *m, const GroupBufs *g, const SweepCtx *c
     GemmBatch bw{};
     for (int w = w0; w < min(nw, w0 + kGemmMaxBatch / 2); ++w)
       for (int s = 0; s < 2; ++s) {
+        if (kk[w] <= 0) continue;
         const int Ns = m[w].Ns[s];
         GemmDesc d = gemm_desc(g[w].P2[s], Ns, m[w].ULt[s] + (long)g0 * Ns, Ns, g[w].W0part[s],
-                               g[w].kmax, kk, kk, Ns);
+                               g[w].kmax, kk[w], kk[w], Ns);
         d.ksplit = 64;
         d.csplit = (long)g[w].kmax * g[w].kmax;
         bw.d[bw.count++] = d;
@@ -1390,43 +1401,65 @@ hipError_t group_panels(const SpinMats *m, const GroupBufs *g, const SweepCtx *c
 }
 
 namespace {
-Batch<DecideArgs> decide_batch(const GroupBufs *g, const SweepCtx *c, int nw, int g0, int kk,
-                               long long block_index) {
+Batch<DecideArgs> decide_batch(const GroupBufs *g, const SweepCtx *c, int nw, int g0,
+                               const int *kk, long long block_index) {
   Batch<DecideArgs> B{};
   for (int w = 0; w < nw; ++w) {
     B.w[w].g = g[w];
     B.w[w].c = c[w];
     B.w[w].g0 = g0;
-    B.w[w].kk = kk;
+    B.w[w].kk = kk[w];
     B.w[w].block_index = block_index;
   }
   return B;
 }
 }  // namespace
 
-hipError_t delayed_decide(const GroupBufs *g, const SweepCtx *c, int nw, int g0, int kk,
-                          hipStream_t st) {
-  if (nw < 1 || nw > kMaxBatch) return hipErrorInvalidValue;
-  const Batch<DecideArgs> B = decide_batch(g, c, nw, g0, kk, 0);
-  const dim3 grid(nw);
-  // measured at 40x40: k = 32 takes 19.5 us with one wave per spin against
-  // 21.6 us with both spins in one wave; k = 64 fits the per-spin layout
-  if (kk <= 8)
-    hipLaunchKernelGGL((delayed_decide_wave_kernel<8>), grid, dim3(64), 0, st, B);
-  else if (kk <= 16)
-    hipLaunchKernelGGL((delayed_decide_wave_kernel<16>), grid, dim3(64), 0, st, B);
-  else if (kk <= 32)
-    hipLaunchKernelGGL((delayed_decide_spin_kernel<32>), grid, dim3(128), 0, st, B);
-  else if (kk <= 64)
-    hipLaunchKernelGGL((delayed_decide_spin_kernel<64>), grid, dim3(128), 0, st, B);
-  else hipLaunchKernelGGL((delayed_decide_kernel<1024, 16>), grid, dim3(1024), 0, st, B);
-  return hipGetLastError();
+// The decision kernel is chosen by each walker's own group size, so that a
+// walker in a batch of mixed lattice sizes runs the kernel it runs alone (and
+// gets the same bits): walkers are split by kernel class into sub-batches.
+template <class F>
+hipError_t decide_by_class(const Batch<DecideArgs> &B, int nw, const int *kkw, int nclass,
+                           int (*cls)(int), F launch) {
+  for (int k = 0; k < nclass; ++k) {
+    Batch<DecideArgs> S{};
+    int n = 0;
+    for (int w = 0; w < nw; ++w)
+      if (kkw[w] > 0 && cls(kkw[w]) == k) S.w[n++] = B.w[w];
+    if (n == 0) continue;
+    launch(k, S, n);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
-hipError_t block_decide(const GroupBufs *g, const SweepCtx *c, int nw, int g0, int kk,
+int delayed_class(int kk) { return kk <= 8 ? 0 : kk <= 16 ? 1 : kk <= 32 ? 2 : kk <= 64 ? 3 : 4; }
+int block_class(int kk) { return kk <= 16 ? 0 : 1; }
+
+hipError_t delayed_decide(const GroupBufs *g, const SweepCtx *c, int nw, int g0,
+                          const int *kkw, hipStream_t st) {
+  if (nw < 1 || nw > kMaxBatch) return hipErrorInvalidValue;
+  const Batch<DecideArgs> B = decide_batch(g, c, nw, g0, kkw, 0);
+  // measured at 40x40: k = 32 takes 19.5 us with one wave per spin against
+  // 21.6 us with both spins in one wave; k = 64 fits the per-spin layout
+  return decide_by_class(B, nw, kkw, 5, delayed_class,
+                         [&](int k, const Batch<DecideArgs> &S, int n) {
+    const dim3 grid(n);
+    switch (k) {
+      case 0: hipLaunchKernelGGL((delayed_decide_wave_kernel<8>), grid, dim3(64), 0, st, S); break;
+      case 1: hipLaunchKernelGGL((delayed_decide_wave_kernel<16>), grid, dim3(64), 0, st, S); break;
+      case 2: hipLaunchKernelGGL((delayed_decide_spin_kernel<32>), grid, dim3(128), 0, st, S); break;
+      case 3: hipLaunchKernelGGL((delayed_decide_spin_kernel<64>), grid, dim3(128), 0, st, S); break;
+      default: hipLaunchKernelGGL((delayed_decide_kernel<1024, 16>), grid, dim3(1024), 0, st, S);
+    }
+  });
+}
+
+hipError_t block_decide(const GroupBufs *g, const SweepCtx *c, int nw, int g0, const int *kkw,
                         long long block_index, hipStream_t st) {
   if (nw < 1 || nw > kMaxBatch) return hipErrorInvalidValue;
-  const Batch<DecideArgs> B = decide_batch(g, c, nw, g0, kk, block_index);
+  const Batch<DecideArgs> B = decide_batch(g, c, nw, g0, kkw, block_index);
   const size_t lds = sizeof(double) * 2 * 64 * 65;
   static bool attr_set = false;
   if (!attr_set) {
@@ -1438,9 +1471,11 @@ hipError_t block_decide(const GroupBufs *g, const SweepCtx *c, int nw, int g0, i
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  if (kk <= 16) hipLaunchKernelGGL((block_decide_kernel<64>), dim3(nw), dim3(64), lds, st, B);
-  else hipLaunchKernelGGL((block_decide_kernel<256>), dim3(nw), dim3(256), lds, st, B);
-  return hipGetLastError();
+  return decide_by_class(B, nw, kkw, 2, block_class,
+                         [&](int k, const Batch<DecideArgs> &S, int n) {
+    if (k == 0) hipLaunchKernelGGL((block_decide_kernel<64>), dim3(n), dim3(64), lds, st, S);
+    else hipLaunchKernelGGL((block_decide_kernel<256>), dim3(n), dim3(256), lds, st, S);
+  });
 }
 
 template <int KP, class R>
@@ -1461,8 +1496,8 @@ hipError_t launch_tile(const Batch<TileArgs> &B, int nw, int nt, hipStream_t st)
   return hipGetLastError();
 }
 
-hipError_t group_tile(const SpinMats *m, const GroupBufs *g, int nw, bool flush, int g0_prev,
-                      int kk_prev, int g0, int kk, bool fp32, hipStream_t st) {
+hipError_t group_tile(const SpinMats *m, const GroupBufs *g, int nw, int g0_prev,
+                      const int *kk_prev, int g0, const int *kk, bool fp32, hipStream_t st) {
   if (nw < 1 || nw > kMaxBatch) return hipErrorInvalidValue;
   Batch<TileArgs> B{};
   int kmax = 0;
@@ -1470,11 +1505,11 @@ hipError_t group_tile(const SpinMats *m, const GroupBufs *g, int nw, bool flush,
     TileArgs &a = B.w[w];
     a.m = m[w];
     a.g = g[w];
-    a.flush = flush ? 1 : 0;
+    a.flush = kk_prev[w] > 0 ? 1 : 0;
     a.g0_prev = g0_prev;
-    a.kk_prev = flush ? kk_prev : 0;
+    a.kk_prev = kk_prev[w];
     a.g0 = g0;
-    a.kk = kk;
+    a.kk = kk[w];
     kmax = max(kmax, g[w].kmax);
   }
   const int nt = max_tiles(m, nw);
@@ -1495,18 +1530,18 @@ hipError_t group_tile(const SpinMats *m, const GroupBufs *g, int nw, bool flush,
 }
 
 hipError_t group_reduce(const SpinMats *m, const GroupBufs *g, const SweepCtx *c, int nw,
-                        int mode, int g0, int kk, hipStream_t st) {
+                        int mode, int g0, const int *kk, hipStream_t st) {
   return launch_reduce(m, g, c, nw, mode, g0, kk, 1, 1, st);
 }
 
-hipError_t group_flush(const SpinMats *m, const GroupBufs *g, int nw, int g0, int kk,
+hipError_t group_flush(const SpinMats *m, const GroupBufs *g, int nw, int g0, const int *kk,
                        hipStream_t st) {
   if (nw < 1 || nw > kMaxBatch) return hipErrorInvalidValue;
   const int nt = max_tiles(m, nw);
   Batch<QArgs> B{};
   int kmax = 0;
   for (int w = 0; w < nw; ++w) {
-    B.w[w] = QArgs{m[w], g[w], g0, kk};
+    B.w[w] = QArgs{m[w], g[w], g0, kk[w]};
     kmax = max(kmax, g[w].kmax);
   }
   const size_t lds = sizeof(double) * 64 * (size_t)(kmax + 1);
@@ -1524,8 +1559,9 @@ hipError_t group_flush(const SpinMats *m, const GroupBufs *g, int nw, int g0, in
     GemmBatch b{};
     for (int w = w0; w < min(nw, w0 + kGemmMaxBatch / 2); ++w)
       for (int s = 0; s < 2; ++s) {
+        if (kk[w] <= 0) continue;
         const int Ns = m[w].Ns[s];
-        GemmDesc d = gemm_desc(g[w].Q[s], g[w].kmax, g[w].P2[s], Ns, m[w].T[s], Ns, Ns, Ns, kk,
+        GemmDesc d = gemm_desc(g[w].Q[s], g[w].kmax, g[w].P2[s], Ns, m[w].T[s], Ns, Ns, Ns, kk[w],
                                -1.0, 1.0, m[w].T[s], Ns);
         d.Kdev = g[w].nA + 1;   // rank kk, or 0 when nothing was accepted
         b.d[b.count++] = d;

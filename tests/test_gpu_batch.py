@@ -112,3 +112,71 @@ def test_batch_rejects_mismatched_shapes():
         batch_sweep([a, a], 1)
     a.close()
     b.close()
+
+
+def _mixed_problems():
+    """Three lattices of different sizes and uneven spin sectors: 4x4 with
+    5 + 3 fermions, 6x6 with 13 + 10, 10x10 with 70 + 66 (two column tiles)."""
+    specs = [(4, 5, 3), (6, 13, 10), (10, 70, 66)]
+    return [synth.make_problem(L, nu, nd, 4.0, n_slices=20, stab_every=5, perturb=1e-3,
+                               seed=synth.SEED_BASE + 40 + i, walker_id=i)
+            for i, (L, nu, nd) in enumerate(specs)]
+
+
+@pytest.mark.parametrize("scheme,kw", [
+    ("delayed", {"k": 16}),            # groups 16 | 16, 16, 4 | 6 x 16, 4
+    ("delayed", {"k": 32}),            # one sector kernel class per group size
+    ("block", {"b": 8}),
+    ("delayed", {"k": 32, "fp32": True}),
+])
+def test_mixed_sizes_equal_single_runs(scheme, kw):
+    """Lattices of different sizes in one batch: each walker takes exactly the
+    decisions, fields and G (bit for bit) of its run alone."""
+    from paper_2506_09611_amd import batch_sweep
+    probs = _mixed_problems()
+    batched = [make_chain(q, scheme, **kw) for q in probs]
+    batch_sweep(batched, 2)
+    for q, bc in zip(probs, batched):
+        single = make_chain(q, scheme, **kw)
+        single.sweep(2)
+        mb, _ = bc.decisions()
+        ms, _ = single.decisions()
+        print(f"mixed {scheme} {kw} L={q.L}: {len(mb)} decisions", flush=True)
+        assert np.array_equal(mb, ms)
+        assert np.array_equal(bc.fields(), single.fields())
+        for s in range(2):
+            assert np.array_equal(bc.green(s), single.green(s))
+        single.close()
+    for ch in batched:
+        ch.close()
+
+
+@pytest.mark.parametrize("scheme,kw", [("delayed", {"k": 16}), ("block", {"b": 8})])
+def test_mixed_sizes_match_oracle(scheme, kw):
+    """Every walker of a mixed-size batch against the oracle."""
+    from paper_2506_09611_amd import batch_sweep
+    probs = _mixed_problems()
+    chains = [make_chain(q, scheme, **kw) for q in probs]
+    refs = [Walker(q, scheme, **kw) for q in probs]
+    batch_sweep(chains, 1)
+    for ch, w, q in zip(chains, refs, probs):
+        w.sweep()
+        meta, margin = ch.decisions()
+        n, low = compare_decisions(meta, margin, w.log, 0, q.n_slices)
+        print(f"mixed {scheme} L={q.L}: {n} decisions equal, low {low}", flush=True)
+        if low:
+            continue
+        assert np.array_equal(ch.fields(), w.fields)
+        assert green_rel_err(ch, w) < 1e-10
+    for ch in chains:
+        ch.close()
+
+
+def test_local_batch_rejects_mixed_sizes():
+    from paper_2506_09611_amd import batch_sweep, PQMCError
+    a, b = _mixed_problems()[:2]
+    ca, cb = make_chain(a, "local"), make_chain(b, "local")
+    with pytest.raises(PQMCError):
+        batch_sweep([ca, cb], 1)
+    ca.close()
+    cb.close()
