@@ -191,6 +191,48 @@ def scheme_table(p, spec, window):
     return {"walkers": 1, "window_slice_visits": window, "rows": rows}
 
 
+def serve_leg(args):
+    """Jobs of mixed lattice sizes and couplings arriving as a Poisson stream,
+    served by the continuous-batching server under an HBM budget."""
+    import numpy as np
+    import synth
+    from paper_2506_09611_amd import Scheme
+    from paper_2506_09611_amd.serving import GpuBackend, Job, Server, poisson_arrivals
+    Ls = [int(x) for x in args.serve_sizes.split(",")]
+    Us = [2.0, 4.0, 8.0]
+    seed = synth.SEED_BASE + 500
+    gen = np.random.Generator(np.random.Philox(key=[seed, 0x4D4958]))
+    arrivals = poisson_arrivals(args.serve_jobs, args.serve_rate, seed)
+    probs, jobs = {}, []
+    for i in range(args.serve_jobs):
+        L, U = Ls[gen.integers(len(Ls))], Us[gen.integers(len(Us))]
+        if (L, U) not in probs:
+            probs[(L, U)] = synth.make_problem(L, L * L // 2, L * L // 2, U,
+                                               n_slices=args.serve_slices, stab_every=10,
+                                               perturb=1e-3, seed=seed + L)
+        p = probs[(L, U)]
+        jobs.append(Job(job_id=i, arrival=float(arrivals[i]), hopping=p.hopping,
+                        trial_up=p.trial_up, trial_dn=p.trial_dn, U=U, dtau=p.dtau,
+                        n_slices=p.n_slices, stab_every=p.stab_every, seed=seed + 1 + i,
+                        n_walkers=args.serve_walkers, n_sweeps=args.serve_sweeps,
+                        scheme=Scheme.DELAYED, k=args.k, keep_green=False))
+    budget = int(args.serve_budget_gb * 1e9) if args.serve_budget_gb > 0 \
+        else GpuBackend.default_budget()
+    log(f"serving {len(jobs)} jobs at {args.serve_rate}/s, budget {budget / 1e9:.2f} GB")
+    rep = Server(GpuBackend(), budget).run(jobs)
+    out = rep.summary()
+    fu = sum(j.n_walkers * j.n_sweeps * 2 * j.n_slices * j.n_sites for j in jobs)
+    out.update({
+        "arrival_rate_jobs_per_s": args.serve_rate,
+        "field_updates_per_s": fu / rep.makespan_s if rep.makespan_s > 0 else None,
+        "mix": f"L in {{{args.serve_sizes}}} uniform, U/t in {{2,4,8}}, half filling, "
+               f"{args.serve_walkers} walkers x {args.serve_sweeps} sweeps per job, "
+               f"M={args.serve_slices}, k_tau=10, delayed k={args.k}, FCFS admission by "
+               f"workspace bytes, batches of up to 8 walkers re-formed every sweep"})
+    log("serving", out)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -218,6 +260,15 @@ def main():
     ap.add_argument("--local-window", type=int, default=20,
                     help="slice visits timed for the local comparison (0 = full sweeps)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--serve-jobs", type=int, default=24,
+                    help="jobs of the serving leg (0 = skip it)")
+    ap.add_argument("--serve-rate", type=float, default=4.0, help="Poisson arrivals, jobs/s")
+    ap.add_argument("--serve-sizes", default="8,12,16,24,32", help="lattice sides L of the mix")
+    ap.add_argument("--serve-walkers", type=int, default=4)
+    ap.add_argument("--serve-sweeps", type=int, default=1)
+    ap.add_argument("--serve-slices", type=int, default=40, help="M of the serving jobs")
+    ap.add_argument("--serve-budget-gb", type=float, default=2.0,
+                    help="HBM budget of the admitted walkers (0 = 90%% of free memory)")
     ap.add_argument("--ktime-window", type=int, default=10,
                     help="forward slice visits instrumented per kernel after the timed sweeps")
     args = ap.parse_args()
@@ -375,6 +426,8 @@ def main():
     result["schemes"] = schemes
     if args.table:
         result["table"] = scheme_table(p, args.table, args.table_window)
+    if args.serve_jobs > 0:
+        result["serving"] = serve_leg(args)
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(p, args.scheme, args.k, args.b)
     print(json.dumps(result))

@@ -6,7 +6,8 @@ supplies the device workspace and the stream.  There is no CPU fallback:
 importing `Chain` without the built library raises ImportError.
 """
 from .binding import (Chain, Scheme, PQMCError, load_library, library_path,  # noqa: F401
-                      EXPORTED_SYMBOLS, MAX_BATCH, batch_sweep, batch_forward_window)
+                      EXPORTED_SYMBOLS, MAX_BATCH, batch_sweep, batch_forward_window,
+                      workspace_bytes)
 
 __all__ = ["Chain", "Scheme", "PQMCError", "load_library", "library_path", "EXPORTED_SYMBOLS",
-           "MAX_BATCH", "batch_sweep", "batch_forward_window"]
+           "MAX_BATCH", "batch_sweep", "batch_forward_window", "workspace_bytes"]

@@ -241,9 +241,12 @@ class Chain:
         return {k: (tot[i], int(cnt[i])) for i, k in enumerate(KERNEL_CLASSES)}
 
     def close(self):
+        """Destroy the context and release its workspace (to torch's caching
+        allocator, stream-ordered, so work already queued is unaffected)."""
         if getattr(self, "_ctx", None):
             self._lib.pqmc_destroy(self._ctx)
             self._ctx = None
+        self._ws = None
 
     def __del__(self):
         try:
@@ -253,6 +256,23 @@ class Chain:
 
 
 MAX_BATCH = 8
+
+
+def workspace_bytes(n_sites, n_up, n_dn, n_slices, stab_every, scheme=Scheme.DELAYED, k=1,
+                    b=1, fp32=False, log=False):
+    """pqmc_workspace_bytes for a problem of this shape: the whole device
+    footprint of one Chain (the library allocates nothing else), +256 bytes
+    of alignment slack.  Needs the library but no GPU."""
+    lib = load_library()
+    z = np.zeros((n_sites, n_sites))
+    pu, pd = np.zeros((n_sites, n_up)), np.zeros((n_sites, n_dn))
+    prob = Problem(int(n_sites), int(n_up), int(n_dn), _dptr(z), _dptr(pu), _dptr(pd), 0.0,
+                   0.05, int(n_slices), int(stab_every), 0, 0)
+    flags = (FLAG_FP32 if fp32 else 0) | (FLAG_LOG if log else 0)
+    o = UpdateOpts(int(scheme), max(int(k), 1), max(int(b), 1), flags)
+    n = ctypes.c_size_t(0)
+    _check(lib, lib.pqmc_workspace_bytes(ctypes.byref(prob), ctypes.byref(o), ctypes.byref(n)))
+    return n.value + 256
 
 
 def _batch_call(chains, fn, n):
