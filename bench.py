@@ -239,7 +239,7 @@ def main():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--scheme", default="delayed", choices=["local", "delayed", "block"])
-    ap.add_argument("--k", type=int, default=32)
+    ap.add_argument("--k", type=int, default=32, help="delay rank (0: the autotuner's choice)")
     ap.add_argument("--b", type=int, default=16)
     ap.add_argument("--workload", default="c3")
     ap.add_argument("--walkers", type=int, default=8,
@@ -260,6 +260,8 @@ def main():
     ap.add_argument("--local-window", type=int, default=20,
                     help="slice visits timed for the local comparison (0 = full sweeps)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--autotune", default="8,16,32,64,128",
+                    help="delay ranks the autotuner times on the headline batch ('' to skip)")
     ap.add_argument("--serve-jobs", type=int, default=24,
                     help="jobs of the serving leg (0 = skip it)")
     ap.add_argument("--serve-rate", type=float, default=4.0, help="Poisson arrivals, jobs/s")
@@ -297,6 +299,20 @@ def main():
     import dataclasses
     from paper_2506_09611_amd import batch_forward_window
     W = args.walkers
+    tuned = None
+    if args.autotune and args.scheme == "delayed":
+        from paper_2506_09611_amd.autotune import tune_delay
+        r = tune_delay(p.hopping, p.trial_up, p.trial_dn, p.U, p.dtau, p.stab_every,
+                       candidates=[int(x) for x in args.autotune.split(",")], walkers=W)
+        tuned = {"k": r.k, "update_ms_per_slice_visit":
+                 {str(k): 1e3 * v for k, v in sorted(r.update_s_per_slice.items())},
+                 "walkers": W, "window_slice_visits": p.stab_every}
+        log("autotune", tuned)
+        torch.cuda.empty_cache()
+    if args.k == 0:
+        if tuned is None:
+            ap.error("--k 0 needs the delayed scheme and --autotune candidates")
+        args.k = tuned["k"]
     chains = [make_chain(dataclasses.replace(p, walker_id=w), args.scheme, args.k, args.b)
               for w in range(W)]
     ch = chains[0]
@@ -424,6 +440,8 @@ def main():
         for v in schemes.values():
             v["speedup_vs_local"] = v["field_updates_per_s"] / base
     result["schemes"] = schemes
+    if tuned is not None:
+        result["autotune"] = tuned
     if args.table:
         result["table"] = scheme_table(p, args.table, args.table_window)
     if args.serve_jobs > 0:
