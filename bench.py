@@ -108,16 +108,33 @@ def measured_traffic(cls, scheme, k, walkers, workload):
     return float(rec["traffic_bytes_per_launch"])
 
 
+def make_walkers(p, scheme, k, b, W, streams, fp32=False):
+    """W walkers (walker_id 0..W-1) on each of the given streams (walker ids
+    continue across streams): one lockstep batch per stream."""
+    import dataclasses
+    from paper_2506_09611_amd import Chain, Scheme
+    sc = {"local": Scheme.LOCAL, "delayed": Scheme.DELAYED, "block": Scheme.BLOCK_FB}[scheme]
+    out = []
+    for si, st in enumerate(streams):
+        for w in range(W):
+            q = dataclasses.replace(p, walker_id=si * W + w)
+            out.append(Chain(q.hopping, q.trial_up, q.trial_dn, q.U, q.dtau, q.n_slices,
+                             q.stab_every, q.seed, q.walker_id, scheme=sc, k=k, b=b,
+                             timing=True, fp32=fp32, stream=st))
+    return out
+
+
 def time_sweeps(chains, steps, warmup):
-    """Wall time of `steps` sweeps of all chains (one batch, lockstep) and the
-    statistics summed over chains and steps (phase times: the batch's)."""
+    """Wall time of `steps` sweeps of all chains (one lockstep batch per
+    stream, the batches concurrent: pqmc_multi_sweep) and the statistics
+    summed over chains and steps (phase times: the first batch's)."""
     import torch
-    from paper_2506_09611_amd import batch_sweep
+    from paper_2506_09611_amd import multi_sweep
     for _ in range(warmup):
-        batch_sweep(chains, 1)
+        multi_sweep(chains, 1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    st = [batch_sweep(chains, 1) for _ in range(steps)]
+    st = [multi_sweep(chains, 1) for _ in range(steps)]
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     agg = {k: sum(s[0][k] for s in st) for k in st[0][0]}
@@ -244,6 +261,8 @@ def main():
     ap.add_argument("--workload", default="c3")
     ap.add_argument("--walkers", type=int, default=8,
                     help="independent walkers swept together in one batch (1..8)")
+    ap.add_argument("--streams", type=int, default=2,
+                    help="batches of --walkers walkers, one per HIP stream, run concurrently")
     ap.add_argument("--table", default="delayed:8,16,32,64,128;block:1,4,16,64",
                     help="single-walker scheme table timed on forward windows ('' for none)")
     ap.add_argument("--table-window", type=int, default=20,
@@ -298,7 +317,10 @@ def main():
 
     import dataclasses
     from paper_2506_09611_amd import batch_forward_window
-    W = args.walkers
+    W, S = args.walkers, args.streams
+    if not (1 <= W <= 8 and 1 <= S <= 8):
+        ap.error("--walkers and --streams must be 1..8")
+    streams = [torch.cuda.current_stream()] + [torch.cuda.Stream() for _ in range(S - 1)]
     tuned = None
     if args.autotune and args.scheme == "delayed":
         from paper_2506_09611_amd.autotune import tune_delay
@@ -313,12 +335,12 @@ def main():
         if tuned is None:
             ap.error("--k 0 needs the delayed scheme and --autotune candidates")
         args.k = tuned["k"]
-    chains = [make_chain(dataclasses.replace(p, walker_id=w), args.scheme, args.k, args.b)
-              for w in range(W)]
+    chains = make_walkers(p, args.scheme, args.k, args.b, W, streams)
     ch = chains[0]
     if args.steps > 0:
         dt, agg = time_sweeps(chains, args.steps, args.warmup)
-        value = W * args.steps * per_sweep / dt
+        value = S * W * args.steps * per_sweep / dt
+        # update phase of the first batch (its own events; the batches overlap)
         upd = W * args.steps * per_sweep / agg["t_update_s"] if agg["t_update_s"] > 0 else None
         acc = agg["accepted"] / max(1, agg["proposed"])
     else:   # profiling runs: no timed sweeps, only the instrumented window below
@@ -327,8 +349,8 @@ def main():
     # per-kernel device time, live on the library's stream: an instrumented
     # forward window after the timed sweeps
     ch.set_opts(ch.scheme, ch.k, ch.b, ktime=True)
-    if args.ktime_window > 0:
-        batch_forward_window(chains, args.ktime_window)
+    if args.ktime_window > 0:   # the first batch alone, as in the profiled runs
+        batch_forward_window(chains[:W], args.ktime_window)
     ktimes = ch.kernel_times()
     roof = roofline(p, args.scheme, args.k, args.b, acc, ktimes, walkers=W)
     # the rank-n_A flush with the next group's panels, on MFMA (delayed / block)
@@ -357,7 +379,8 @@ def main():
             "workload": "40x40 periodic Hubbard, N=1600, N_sigma=800 per spin, U/t=4, dtau=0.05, "
                         "M=400, k_tau=10, seeded 1e-3 bond perturbation"
                         if args.workload == "c3" else args.workload,
-            "scheme": args.scheme, "delay_k": args.k, "block_b": args.b, "walkers": W,
+            "scheme": args.scheme, "delay_k": args.k, "block_b": args.b, "walkers": S * W,
+            "batches": f"{S} x {W} walkers, one HIP stream each, run concurrently",
         },
         "update_only_field_updates_per_s": upd,
         "acceptance": acc,
@@ -390,12 +413,11 @@ def main():
 
     # the precision form on the same batch (float32 T, flush and panels)
     if args.steps > 0 and not args.no_fp32 and args.scheme != "local":
-        cs = [make_chain(dataclasses.replace(p, walker_id=w), args.scheme, args.k, args.b,
-                         fp32=True) for w in range(W)]
+        cs = make_walkers(p, args.scheme, args.k, args.b, W, streams, fp32=True)
         d32, a32 = time_sweeps(cs, 1, 0)
         result["precision_form"] = {
-            "walkers": W, "dtype": "f32 T/flush/panels, f64 ratios/QR/inverse",
-            "s_per_sweep": d32, "field_updates_per_s": W * per_sweep / d32,
+            "walkers": S * W, "dtype": "f32 T/flush/panels, f64 ratios/QR/inverse",
+            "s_per_sweep": d32, "field_updates_per_s": S * W * per_sweep / d32,
             "update_only": W * per_sweep / a32["t_update_s"] if a32["t_update_s"] > 0 else None,
             "speedup_vs_f64": dt / max(1, args.steps) / d32,
             "note": "errors against the float64 oracle: tests/test_gpu_precision.py"}
@@ -406,13 +428,12 @@ def main():
         torch.cuda.empty_cache()
 
     schemes = {args.scheme: {"s_per_sweep": dt / max(1, args.steps), "field_updates_per_s": value,
-                             "update_only": upd, "walkers": W}}
+                             "update_only": upd, "walkers": S * W}}
     for name in [s for s in args.compare.split(",") if s and s != args.scheme]:
-        cs = [make_chain(dataclasses.replace(p, walker_id=w), name, args.k, args.b)
-              for w in range(W)]
-        c = cs[0]
         if name == "local" and args.local_window > 0:
-            # whole local sweeps take tens of seconds here: time a forward window
+            # whole local sweeps take tens of seconds here: time a forward
+            # window of one batch (windows have no multi-stream entry point)
+            cs = make_walkers(p, name, args.k, args.b, W, streams[:1])
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             st = batch_forward_window(cs, args.local_window)[0]
@@ -423,17 +444,19 @@ def main():
                              "field_updates_per_s": rate,
                              "update_only": W * args.local_window * N / st["t_update_s"]
                              if st["t_update_s"] > 0 else None,
-                             "walkers": W, "note": "forward window, not a whole sweep"}
+                             "walkers": W, "note": "forward window of one batch, not a whole sweep"}
         else:
+            cs = make_walkers(p, name, args.k, args.b, W, streams)
             d2, a2 = time_sweeps(cs, 1, 0)
-            schemes[name] = {"s_per_sweep": d2, "field_updates_per_s": W * per_sweep / d2,
+            schemes[name] = {"s_per_sweep": d2, "field_updates_per_s": S * W * per_sweep / d2,
                              "update_only": W * per_sweep / a2["t_update_s"]
                              if a2["t_update_s"] > 0 else None,
-                             "acceptance": a2["accepted"] / max(1, a2["proposed"]), "walkers": W}
+                             "acceptance": a2["accepted"] / max(1, a2["proposed"]),
+                             "walkers": S * W}
         log(name, schemes[name])
         for x in cs:
             x.close()
-        del c, cs
+        del cs
         torch.cuda.empty_cache()
     if "local" in schemes:
         base = schemes["local"]["field_updates_per_s"]

@@ -185,6 +185,22 @@ pqmc_status pqmc_batch_sweep(pqmc_ctx *const *ctxs, int32_t n, int32_t n_sweeps,
 pqmc_status pqmc_batch_forward_window(pqmc_ctx *const *ctxs, int32_t n, int32_t n_slices,
                                       pqmc_stats *out);
 
+/* Walkers on several streams: the n contexts (1 <= n <= 64) are split by
+ * their stream, in order of first appearance (at most 8 streams); the
+ * walkers of one stream form one pqmc_batch_sweep batch (same rules, at most
+ * 8 walkers), and the batches run concurrently, each driven by its own host
+ * thread, so that the serial phases of one batch (decisions, panel sums)
+ * overlap the MFMA work of another.  Independent chains as in
+ * pqmc_batch_sweep: each walker's decisions, fields and G are the ones it
+ * gets alone.  out: n entries in ctxs order, or NULL; timing fields are
+ * those of the walker's own batch.  Errors: PQMC_EINVAL or PQMC_ESTATE from
+ * the checks, before any work starts; otherwise the status and message of
+ * the first failing batch in stream order (the other batches still finish,
+ * and the failing batch's contexts need pqmc_set_fields).  The calling
+ * thread's current HIP device is used by every worker thread. */
+pqmc_status pqmc_multi_sweep(pqmc_ctx *const *ctxs, int32_t n, int32_t n_sweeps,
+                             pqmc_stats *out);
+
 /* G^s = 1 - U_R T U_L at the walker's current position (Eq. (15)),
  * written to host memory as N_s x N_s row-major float64.  spin: 0 up, 1 down. */
 pqmc_status pqmc_get_green(pqmc_ctx *ctx, int32_t spin, double *out);

@@ -18,7 +18,7 @@ _LIB = None
 EXPORTED_SYMBOLS = (
     "pqmc_workspace_bytes", "pqmc_create", "pqmc_set_opts", "pqmc_set_fields",
     "pqmc_get_fields", "pqmc_sweep", "pqmc_forward_window", "pqmc_batch_sweep",
-    "pqmc_batch_forward_window", "pqmc_get_green",
+    "pqmc_batch_forward_window", "pqmc_multi_sweep", "pqmc_get_green",
     "pqmc_get_decisions", "pqmc_get_heat_bath", "pqmc_get_kernel_times", "pqmc_destroy",
     "pqmc_last_error",
 )
@@ -97,6 +97,8 @@ def load_library():
                              ctypes.POINTER(Stats)],
         "pqmc_batch_forward_window": [ctypes.POINTER(c_void_p), ctypes.c_int32, ctypes.c_int32,
                                       ctypes.POINTER(Stats)],
+        "pqmc_multi_sweep": [ctypes.POINTER(c_void_p), ctypes.c_int32, ctypes.c_int32,
+                             ctypes.POINTER(Stats)],
         "pqmc_get_green": [c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)],
         "pqmc_get_decisions": [c_void_p, ctypes.POINTER(ctypes.c_int32),
                                ctypes.POINTER(ctypes.c_double), c_size_t,
@@ -133,12 +135,14 @@ class Chain:
     hopping: N x N float64; trial_up/trial_dn: N x N_s float64 (orthonormal
     columns); U >= 0; dtau; n_slices = M; stab_every = k_tau; seed, walker_id:
     Philox key.  scheme / k / b: update scheme, delay rank, block size; k_max
-    and b_max bound later set_opts calls (workspace sizing).
+    and b_max bound later set_opts calls (workspace sizing).  stream: the
+    torch.cuda.Stream the walker's work goes to (default: the current one);
+    the workspace is allocated on it.
     """
 
     def __init__(self, hopping, trial_up, trial_dn, U, dtau, n_slices, stab_every, seed,
                  walker_id=0, scheme=Scheme.LOCAL, k=1, b=1, k_max=None, b_max=None,
-                 log=False, timing=False, fp32=False):
+                 log=False, timing=False, fp32=False, stream=None):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device visible to torch")
@@ -162,10 +166,11 @@ class Chain:
                                                          ctypes.byref(sizing),
                                                          ctypes.byref(nbytes)))
         self.workspace_bytes = nbytes.value
-        self._ws = torch.empty(nbytes.value + 256, dtype=torch.uint8, device="cuda")
+        self._stream = stream if stream is not None else torch.cuda.current_stream()
+        with torch.cuda.stream(self._stream):
+            self._ws = torch.empty(nbytes.value + 256, dtype=torch.uint8, device="cuda")
         base = self._ws.data_ptr()
         base = (base + 255) // 256 * 256
-        self._stream = torch.cuda.current_stream()
         handle = ctypes.c_void_p(0)
         _check(self._lib, self._lib.pqmc_create(ctypes.byref(self._prob), ctypes.byref(sizing),
                                                 ctypes.c_void_p(self._stream.cuda_stream),
@@ -275,9 +280,9 @@ def workspace_bytes(n_sites, n_up, n_dn, n_slices, stab_every, scheme=Scheme.DEL
     return n.value + 256
 
 
-def _batch_call(chains, fn, n):
-    if not 1 <= len(chains) <= MAX_BATCH:
-        raise ValueError(f"a batch holds 1..{MAX_BATCH} chains")
+def _batch_call(chains, fn, n, limit=MAX_BATCH):
+    if not 1 <= len(chains) <= limit:
+        raise ValueError(f"a batch holds 1..{limit} chains")
     lib = chains[0]._lib
     ctxs = (ctypes.c_void_p * len(chains))(*[c._ctx.value for c in chains])
     st = (Stats * len(chains))()
@@ -290,6 +295,14 @@ def batch_sweep(chains, n=1):
     per kernel for all of them (the delayed and block schemes accept chains of
     different lattice sizes).  Returns one stats dict per chain."""
     return _batch_call(chains, lambda lib: lib.pqmc_batch_sweep, n)
+
+
+def multi_sweep(chains, n=1):
+    """pqmc_multi_sweep: up to 64 chains on up to 8 streams; the chains of
+    one stream sweep as one batch and the batches run concurrently."""
+    if not 1 <= len(chains) <= 8 * MAX_BATCH:
+        raise ValueError(f"a multi-stream sweep holds 1..{8 * MAX_BATCH} chains")
+    return _batch_call(chains, lambda lib: lib.pqmc_multi_sweep, n, limit=8 * MAX_BATCH)
 
 
 def batch_forward_window(chains, n_slices):

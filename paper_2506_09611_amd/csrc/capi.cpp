@@ -8,6 +8,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/pqmc.h"
@@ -1000,6 +1001,79 @@ pqmc_status pqmc_batch_sweep(pqmc_ctx *const *ctxs, int32_t n, int32_t n_sweeps,
     return as_status(rc);
   }
   return as_status(finish_call(b, tm, t0, out));
+}
+
+pqmc_status pqmc_multi_sweep(pqmc_ctx *const *ctxs, int32_t n, int32_t n_sweeps,
+                             pqmc_stats *out) {
+  constexpr int kMaxStreams = 8;
+  if (!ctxs || n < 1 || n > kMaxStreams * kMaxBatch)
+    return set_error(PQMC_EINVAL, "multi-stream sweep takes 1..64 contexts");
+  if (n_sweeps < 0) return set_error(PQMC_EINVAL, "n_sweeps < 0");
+  // one batch per stream, streams in order of first appearance
+  std::vector<hipStream_t> streams;
+  std::vector<std::vector<pqmc_ctx *>> grp;
+  std::vector<std::vector<int>> pos;
+  for (int i = 0; i < n; ++i) {
+    if (!ctxs[i]) return set_error(PQMC_EINVAL, "null context in batch");
+    size_t g = 0;
+    while (g < streams.size() && streams[g] != ctxs[i]->st) ++g;
+    if (g == streams.size()) {
+      if ((int)g == kMaxStreams) return set_error(PQMC_EINVAL, "more than 8 streams");
+      streams.push_back(ctxs[i]->st);
+      grp.emplace_back();
+      pos.emplace_back();
+    }
+    grp[g].push_back(ctxs[i]);
+    pos[g].push_back(i);
+  }
+  const int G = (int)grp.size();
+  for (int g = 0; g < G; ++g) {
+    pqmc_status v = check_batch(grp[g].data(), (int)grp[g].size());
+    if (v) return v;
+    for (pqmc_ctx *c : grp[g])
+      if (c->windowed || c->position != 0)
+        return set_error(PQMC_ESTATE, "walker is mid-sweep after pqmc_forward_window");
+  }
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return set_error(PQMC_EDEVICE, "hipGetDevice failed");
+  std::vector<std::vector<pqmc_stats>> st(G);
+  std::vector<pqmc_status> rc(G, PQMC_OK);
+  std::vector<std::string> msg(G);
+  auto work = [&](int g, bool own_thread) {
+    try {
+      if (own_thread && hipSetDevice(dev) != hipSuccess) {
+        rc[g] = PQMC_EDEVICE;
+        msg[g] = "hipSetDevice failed in a worker thread";
+        return;
+      }
+      st[g].resize(grp[g].size());
+      rc[g] = pqmc_batch_sweep(grp[g].data(), (int)grp[g].size(), n_sweeps, st[g].data());
+      if (rc[g]) msg[g] = g_last_error;
+    } catch (...) {
+      rc[g] = PQMC_ENOMEM;
+      msg[g] = "host allocation failed in a multi-stream sweep";
+    }
+  };
+  // batch 0 on the calling thread, the others on their own threads; a
+  // thread that cannot be started runs its batch afterwards on this one
+  std::vector<std::thread> th;
+  std::vector<int> inline_g;
+  for (int g = 1; g < G; ++g) {
+    try {
+      th.emplace_back(work, g, true);
+    } catch (...) {
+      inline_g.push_back(g);
+    }
+  }
+  work(0, false);
+  for (std::thread &t : th) t.join();
+  for (int g : inline_g) work(g, false);
+  for (int g = 0; g < G; ++g)
+    if (rc[g]) return set_error(rc[g], msg[g]);
+  if (out)
+    for (int g = 0; g < G; ++g)
+      for (size_t j = 0; j < pos[g].size(); ++j) out[pos[g][j]] = st[g][j];
+  return PQMC_OK;
 }
 
 pqmc_status pqmc_sweep(pqmc_ctx *c, int32_t n_sweeps, pqmc_stats *out) {

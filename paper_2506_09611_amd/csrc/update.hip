@@ -1461,16 +1461,15 @@ hipError_t block_decide(const GroupBufs *g, const SweepCtx *c, int nw, int g0, c
   if (nw < 1 || nw > kMaxBatch) return hipErrorInvalidValue;
   const Batch<DecideArgs> B = decide_batch(g, c, nw, g0, kkw, block_index);
   const size_t lds = sizeof(double) * 2 * 64 * 65;
-  static bool attr_set = false;
-  if (!attr_set) {
+  // set once, thread-safely (batches on several streams run from several host threads)
+  static const hipError_t attr = [lds] {
     hipError_t e = hipFuncSetAttribute((const void *)block_decide_kernel<256>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void *)block_decide_kernel<64>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
+    return hipFuncSetAttribute((const void *)block_decide_kernel<64>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  }();
+  if (attr != hipSuccess) return attr;
   return decide_by_class(B, nw, kkw, 2, block_class,
                          [&](int k, const Batch<DecideArgs> &S, int n) {
     if (k == 0) hipLaunchKernelGGL((block_decide_kernel<64>), dim3(n), dim3(64), lds, st, S);
@@ -1483,14 +1482,10 @@ hipError_t launch_tile(const Batch<TileArgs> &B, int nw, int nt, hipStream_t st)
   const size_t flush_lds = (size_t)64 * (KP + 1) + (size_t)KP * (KP + 1) + (size_t)KP * kLdt;
   const size_t panel_lds = (size_t)64 * kLdt + 2 * (size_t)KP * kLdt;
   const size_t lds = sizeof(R) * std::max(flush_lds, panel_lds);
-  static bool attr_set = false;
-  if (!attr_set) {
-    // at most 100 KB (KP = 64, double) of the 160 KB per CU
-    hipError_t e = hipFuncSetAttribute((const void *)group_tile_kernel<KP, R>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
+  // at most 100 KB (KP = 64, double) of the 160 KB per CU; set once, thread-safely
+  static const hipError_t attr = hipFuncSetAttribute(
+      (const void *)group_tile_kernel<KP, R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (attr != hipSuccess) return attr;
   const int total = 2 * nw * nt * nt;
   hipLaunchKernelGGL((group_tile_kernel<KP, R>), dim3((total + 7) / 8 * 8), dim3(256), lds, st, B);
   return hipGetLastError();
@@ -1545,15 +1540,11 @@ hipError_t group_flush(const SpinMats *m, const GroupBufs *g, int nw, int g0, co
     kmax = max(kmax, g[w].kmax);
   }
   const size_t lds = sizeof(double) * 64 * (size_t)(kmax + 1);
-  static bool attr_set = false;
-  if (!attr_set) {
-    // 66 KB for kmax = 128
-    hipError_t e = hipFuncSetAttribute((const void *)group_q_kernel,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)(sizeof(double) * 64 * 129));
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
+  // 66 KB for kmax = 128; set once, thread-safely
+  static const hipError_t attr = hipFuncSetAttribute(
+      (const void *)group_q_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+      (int)(sizeof(double) * 64 * 129));
+  if (attr != hipSuccess) return attr;
   hipLaunchKernelGGL(group_q_kernel, dim3(nt, 2, nw), dim3(256), lds, st, B);
   for (int w0 = 0; w0 < nw; w0 += kGemmMaxBatch / 2) {
     GemmBatch b{};

@@ -180,3 +180,50 @@ def test_local_batch_rejects_mixed_sizes():
         batch_sweep([ca, cb], 1)
     ca.close()
     cb.close()
+
+
+def test_multi_stream_sweep_equals_single_runs():
+    """pqmc_multi_sweep: three batches on three streams (delayed mixed sizes,
+    block, local), run concurrently from host threads; every walker equals
+    its run alone, bit for bit."""
+    import torch
+    from paper_2506_09611_amd import multi_sweep
+    probs = _mixed_problems()
+    streams = [torch.cuda.Stream() for _ in range(3)]
+    plan = [(probs[0], "delayed", {"k": 16}, 0), (probs[2], "delayed", {"k": 16}, 0),
+            (probs[1], "block", {"b": 8}, 1), (dataclasses.replace(probs[1], walker_id=5),
+                                               "block", {"b": 8}, 1),
+            (probs[0], "local", {}, 2)]
+    chains = [make_chain(q, sc, stream=streams[si], **kw) for q, sc, kw, si in plan]
+    # interleave the streams in the argument order: grouping is by stream
+    order = [0, 2, 4, 1, 3]
+    stats = multi_sweep([chains[i] for i in order], 2)
+    assert len(stats) == 5
+    for (q, sc, kw, _), ch in zip(plan, chains):
+        alone = make_chain(q, sc, **kw)
+        alone.sweep(2)
+        assert np.array_equal(ch.decisions()[0], alone.decisions()[0]), (sc, q.L)
+        assert np.array_equal(ch.fields(), alone.fields())
+        for s in range(2):
+            assert np.array_equal(ch.green(s), alone.green(s))
+        alone.close()
+    for ch in chains:
+        ch.close()
+
+
+def test_multi_stream_sweep_rejects_bad_batches():
+    import torch
+    from paper_2506_09611_amd import multi_sweep, PQMCError
+    probs = _mixed_problems()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    a = make_chain(probs[0], "delayed", k=16, stream=s1)
+    b = make_chain(probs[1], "delayed", k=8, stream=s1)       # k differs within stream 1
+    c = make_chain(probs[1], "delayed", k=8, stream=s2)
+    with pytest.raises(PQMCError):
+        multi_sweep([a, b, c], 1)
+    multi_sweep([a, c], 1)                                      # k may differ across streams
+    c.forward_window(2)
+    with pytest.raises(PQMCError):
+        multi_sweep([a, c], 1)                                  # c is mid-sweep
+    for x in (a, b, c):
+        x.close()
