@@ -208,9 +208,10 @@ def scheme_table(p, spec, window):
     return {"walkers": 1, "window_slice_visits": window, "rows": rows}
 
 
-def serve_leg(args):
-    """Jobs of mixed lattice sizes and couplings arriving as a Poisson stream,
-    served by the continuous-batching server under an HBM budget."""
+def serve_leg(args, rate):
+    """Jobs of mixed lattice sizes and couplings arriving as a Poisson stream
+    of `rate` jobs/s, served by the continuous-batching server under an HBM
+    budget."""
     import numpy as np
     import synth
     from paper_2506_09611_amd import Scheme
@@ -219,7 +220,7 @@ def serve_leg(args):
     Us = [2.0, 4.0, 8.0]
     seed = synth.SEED_BASE + 500
     gen = np.random.Generator(np.random.Philox(key=[seed, 0x4D4958]))
-    arrivals = poisson_arrivals(args.serve_jobs, args.serve_rate, seed)
+    arrivals = poisson_arrivals(args.serve_jobs, rate, seed)
     probs, jobs = {}, []
     for i in range(args.serve_jobs):
         L, U = Ls[gen.integers(len(Ls))], Us[gen.integers(len(Us))]
@@ -235,17 +236,18 @@ def serve_leg(args):
                         scheme=Scheme.DELAYED, k=args.k, keep_green=False))
     budget = int(args.serve_budget_gb * 1e9) if args.serve_budget_gb > 0 \
         else GpuBackend.default_budget()
-    log(f"serving {len(jobs)} jobs at {args.serve_rate}/s, budget {budget / 1e9:.2f} GB")
-    rep = Server(GpuBackend(), budget).run(jobs)
+    log(f"serving {len(jobs)} jobs at {rate}/s, budget {budget / 1e9:.2f} GB")
+    rep = Server(GpuBackend(lanes=args.serve_lanes), budget).run(jobs)
     out = rep.summary()
     fu = sum(j.n_walkers * j.n_sweeps * 2 * j.n_slices * j.n_sites for j in jobs)
     out.update({
-        "arrival_rate_jobs_per_s": args.serve_rate,
+        "arrival_rate_jobs_per_s": rate,
         "field_updates_per_s": fu / rep.makespan_s if rep.makespan_s > 0 else None,
         "mix": f"L in {{{args.serve_sizes}}} uniform, U/t in {{2,4,8}}, half filling, "
                f"{args.serve_walkers} walkers x {args.serve_sweeps} sweeps per job, "
                f"M={args.serve_slices}, k_tau=10, delayed k={args.k}, FCFS admission by "
-               f"workspace bytes, batches of up to 8 walkers re-formed every sweep"})
+               f"workspace bytes, batches of up to 8 walkers re-formed every sweep, "
+               f"{args.serve_lanes} concurrent lanes"})
     log("serving", out)
     return out
 
@@ -281,11 +283,14 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--autotune", default="8,16,32,64,128",
                     help="delay ranks the autotuner times on the headline batch ('' to skip)")
-    ap.add_argument("--serve-jobs", type=int, default=24,
+    ap.add_argument("--serve-jobs", type=int, default=32,
                     help="jobs of the serving leg (0 = skip it)")
-    ap.add_argument("--serve-rate", type=float, default=4.0, help="Poisson arrivals, jobs/s")
+    ap.add_argument("--serve-rate", default="8,64",
+                    help="Poisson arrival rates, jobs/s, one serving run each (comma list)")
     ap.add_argument("--serve-sizes", default="8,12,16,24,32", help="lattice sides L of the mix")
     ap.add_argument("--serve-walkers", type=int, default=4)
+    ap.add_argument("--serve-lanes", type=int, default=2,
+                    help="concurrent batches per serving step, one HIP stream each")
     ap.add_argument("--serve-sweeps", type=int, default=1)
     ap.add_argument("--serve-slices", type=int, default=40, help="M of the serving jobs")
     ap.add_argument("--serve-budget-gb", type=float, default=2.0,
@@ -468,7 +473,7 @@ def main():
     if args.table:
         result["table"] = scheme_table(p, args.table, args.table_window)
     if args.serve_jobs > 0:
-        result["serving"] = serve_leg(args)
+        result["serving"] = [serve_leg(args, float(r)) for r in args.serve_rate.split(",") if r]
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(p, args.scheme, args.k, args.b)
     print(json.dumps(result))

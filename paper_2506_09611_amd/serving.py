@@ -19,6 +19,10 @@ stream).  The server
   lattices of different sizes together;
 * re-forms the batches at every sweep boundary, so the walkers of a newly
   admitted job join at the next step (continuous batching);
+* with several lanes (one HIP stream each), places every admitted walker on
+  the lane with the fewest active walkers, forms one batch per lane at each
+  step and runs the lanes' batches concurrently (pqmc_multi_sweep), so that
+  one batch's serial phases overlap another's matrix work;
 * frees a walker's workspace as soon as it finishes and retires the job with
   its last walker, then admits from the queue.
 
@@ -26,8 +30,8 @@ A walker's fields and G depend only on its own key and on the sweeps it has
 run, never on its batch partners or the interleaving: its result is the same,
 bit for bit, alone or in any mix.
 
-Execution sits behind a small backend interface (footprint, open, sweep,
-collect, close); GpuBackend drives the HIP library.  The clock is also
+Execution sits behind a small backend interface (walker_bytes, open,
+sweep, collect, close); GpuBackend drives the HIP library.  The clock is also
 pluggable, so that the scheduling logic runs on the CPU against a
 simulated backend and clock.
 """
@@ -120,8 +124,8 @@ class ServeReport:
     jobs_per_s: float
     latency_p50_s: float
     latency_p99_s: float
-    steps: int                    # batched sweep launches
-    mean_batch: float             # walkers per step
+    steps: int                    # scheduling steps (one sweep of each lane's batch)
+    mean_batch: float             # walkers per batch
     peak_bytes: int               # largest admitted footprint
     budget_bytes: int
     batch_log: List[List[tuple]]  # per step: (job_id, walker_id) of the batch
@@ -164,12 +168,19 @@ class RealClock:
 
 
 class GpuBackend:
-    """Walkers as library contexts (Chain) on torch's current device and
-    stream; one pqmc_batch_sweep per step."""
+    """Walkers as library contexts (Chain) on torch's current device, lane j
+    on its own HIP stream (lane 0: torch's current stream); one
+    pqmc_multi_sweep per step over the lanes' batches."""
 
-    def __init__(self):
+    def __init__(self, lanes: int = 1):
+        import torch
         from . import binding
+        if not 1 <= lanes <= 8:
+            raise ValueError("lanes must be 1..8")
         self._b = binding
+        self.lanes = lanes
+        self.streams = [torch.cuda.current_stream()] + [torch.cuda.Stream()
+                                                        for _ in range(lanes - 1)]
 
     @staticmethod
     def default_budget(fraction: float = 0.9) -> int:
@@ -181,13 +192,20 @@ class GpuBackend:
         return self._b.workspace_bytes(job.n_sites, job.n_up, job.n_dn, job.n_slices,
                                        job.stab_every, job.scheme, job.k, job.b, job.fp32)
 
-    def open(self, job: Job, walker_id: int):
+    def open(self, job: Job, walker_id: int, lane: int = 0):
         return self._b.Chain(job.hopping, job.trial_up, job.trial_dn, job.U, job.dtau,
                              job.n_slices, job.stab_every, job.seed, walker_id,
-                             scheme=job.scheme, k=job.k, b=job.b, fp32=job.fp32)
+                             scheme=job.scheme, k=job.k, b=job.b, fp32=job.fp32,
+                             stream=self.streams[lane])
 
-    def sweep(self, handles: list) -> List[dict]:
-        return self._b.batch_sweep(handles, 1)
+    def sweep(self, batches: List[list]) -> List[List[dict]]:
+        flat = [h for b in batches for h in b]
+        st = self._b.multi_sweep(flat, 1)
+        out, i = [], 0
+        for b in batches:
+            out.append(st[i:i + len(b)])
+            i += len(b)
+        return out
 
     def collect(self, job: Job, handle):
         green = (handle.green(0), handle.green(1)) if job.keep_green else None
@@ -201,10 +219,11 @@ _STAT_KEYS = ("proposed", "accepted", "flips", "low_margin", "negative", "field_
 
 
 class _Walker:
-    __slots__ = ("job", "wid", "handle", "done", "stats", "key", "order")
+    __slots__ = ("job", "wid", "handle", "done", "stats", "key", "order", "lane")
 
-    def __init__(self, job, wid, handle, key, order):
+    def __init__(self, job, wid, handle, key, order, lane):
         self.job, self.wid, self.handle, self.key, self.order = job, wid, handle, key, order
+        self.lane = lane
         self.done = 0
         self.stats = {k: 0 for k in _STAT_KEYS}
 
@@ -214,10 +233,11 @@ class Server:
 
     budget_bytes: device memory the walkers may hold together.
     policy: "fcfs" (line ordered by job arrival) or "rr" (by sweeps done).
+    lanes: concurrent batches per step (the backend's lanes, e.g. streams).
     """
 
     def __init__(self, backend, budget_bytes: int, policy: str = "fcfs", clock=None,
-                 max_batch: int = MAX_BATCH,
+                 max_batch: int = MAX_BATCH, lanes: Optional[int] = None,
                  on_step: Optional[Callable[[int, list], None]] = None):
         if policy not in ("fcfs", "rr"):
             raise ValueError("policy must be 'fcfs' or 'rr'")
@@ -228,6 +248,9 @@ class Server:
         self.policy = policy
         self.clock = clock or RealClock()
         self.max_batch = max_batch
+        self.lanes = int(lanes if lanes is not None else getattr(backend, "lanes", 1))
+        if self.lanes < 1:
+            raise ValueError("lanes must be >= 1")
         self.on_step = on_step
 
     def _line_key(self, w: _Walker):
@@ -239,6 +262,14 @@ class Server:
         line = sorted(active, key=self._line_key)
         head = line[0]
         return [w for w in line if w.key == head.key][:self.max_batch]
+
+    def _pick_lanes(self, active: List[_Walker]) -> List[List[_Walker]]:
+        out = []
+        for lane in range(self.lanes):
+            mine = [w for w in active if w.lane == lane]
+            if mine:
+                out.append(self._pick(mine))
+        return out
 
     def run(self, jobs: Sequence[Job]) -> ServeReport:
         for j in jobs:
@@ -272,7 +303,13 @@ class Server:
                 j = queue.popleft()
                 key = batch_key(j)
                 for w in range(j.n_walkers):
-                    active.append(_Walker(j, w, self.backend.open(j, w), key, seq))
+                    load = [0] * self.lanes
+                    for x in active:
+                        load[x.lane] += 1
+                    lane = min(range(self.lanes), key=lambda q: (load[q], q))
+                    h = self.backend.open(j, w, lane) if self.lanes > 1 else \
+                        self.backend.open(j, w)
+                    active.append(_Walker(j, w, h, key, seq, lane))
                 seq += 1
                 used += wbytes[j.job_id] * j.n_walkers
                 peak = max(peak, used)
@@ -282,14 +319,15 @@ class Server:
                 if pending:
                     self.clock.sleep_until(t0 + pending[0].arrival)
                 continue
-            batch = self._pick(active)
-            stats = self.backend.sweep([w.handle for w in batch])
+            batches = self._pick_lanes(active)
+            stats = self.backend.sweep([[w.handle for w in b] for b in batches])
             steps += 1
-            walked += len(batch)
-            batch_log.append([(w.job.job_id, w.wid) for w in batch])
+            for b in batches:
+                walked += len(b)
+                batch_log.append([(w.job.job_id, w.wid) for w in b])
             if self.on_step:
-                self.on_step(steps, batch)
-            for w, st in zip(batch, stats):
+                self.on_step(steps, batches)
+            for w, st in ((w, st) for b, sb in zip(batches, stats) for w, st in zip(b, sb)):
                 w.done += 1
                 for k in _STAT_KEYS:
                     w.stats[k] += st.get(k, 0)
@@ -315,5 +353,6 @@ class Server:
             results=out, makespan_s=makespan,
             jobs_per_s=(len(fin) / makespan) if makespan > 0 else float("nan"),
             latency_p50_s=percentile(lat, 50), latency_p99_s=percentile(lat, 99),
-            steps=steps, mean_batch=(walked / steps) if steps else 0.0, peak_bytes=peak,
+            steps=steps, mean_batch=(walked / len(batch_log)) if batch_log else 0.0,
+            peak_bytes=peak,
             budget_bytes=self.budget, batch_log=batch_log)

@@ -33,13 +33,15 @@ def _jobs(scheme, **kw):
     return jobs
 
 
-@pytest.mark.parametrize("scheme_name,kw", [("delayed", {"k": 16}), ("block", {"b": 8})])
-def test_served_results_equal_alone(scheme_name, kw):
+@pytest.mark.parametrize("scheme_name,kw,lanes", [("delayed", {"k": 16}, 1),
+                                                  ("block", {"b": 8}, 1),
+                                                  ("delayed", {"k": 16}, 2)])
+def test_served_results_equal_alone(scheme_name, kw, lanes):
     from paper_2506_09611_amd import Chain, Scheme
     from paper_2506_09611_amd.serving import GpuBackend, Server
     scheme = {"delayed": Scheme.DELAYED, "block": Scheme.BLOCK_FB}[scheme_name]
     jobs = _jobs(scheme, **kw)
-    be = GpuBackend()
+    be = GpuBackend(lanes=lanes)
     per_job = sorted(be.walker_bytes(j) * j.n_walkers for j in jobs)
     budget = per_job[-1] + per_job[-2]          # at most about two jobs at once
     rep = Server(be, budget).run(jobs)

@@ -32,22 +32,30 @@ class SimBackend:
     def walker_bytes(self, job):
         return job.n_sites
 
-    def open(self, job, w):
-        h = {"job": job, "w": w, "sweeps": 0, "id": (job.job_id, w)}
+    def open(self, job, w, lane=0):
+        h = {"job": job, "w": w, "sweeps": 0, "id": (job.job_id, w), "lane": lane}
         self.open_handles.add(h["id"])
         self.held += job.n_sites
         self.peak_held = max(self.peak_held, self.held)
         return h
 
-    def sweep(self, handles):
-        assert 1 <= len(handles) <= 8
-        keys = {batch_key(h["job"]) for h in handles}
-        assert len(keys) == 1, "incompatible walkers batched"
-        for h in handles:
-            assert h["id"] in self.open_handles
-            h["sweeps"] += 1
-        self.clock.t += 1e-3 + 1e-6 * max(h["job"].n_sites for h in handles)
-        return [{"proposed": h["job"].n_sites, "accepted": 1} for h in handles]
+    def sweep(self, batches):
+        """Lanes' batches run concurrently: the step costs the slowest one."""
+        cost = 0.0
+        lanes = [b[0]["lane"] for b in batches]
+        assert len(set(lanes)) == len(lanes), "two batches on one lane"
+        for handles in batches:
+            assert 1 <= len(handles) <= 8
+            keys = {batch_key(h["job"]) for h in handles}
+            assert len(keys) == 1, "incompatible walkers batched"
+            assert len({h["lane"] for h in handles}) == 1, "a batch spans lanes"
+            for h in handles:
+                assert h["id"] in self.open_handles
+                h["sweeps"] += 1
+            cost = max(cost, 1e-3 + 1e-6 * max(h["job"].n_sites for h in handles))
+        self.clock.t += cost
+        return [[{"proposed": h["job"].n_sites, "accepted": 1} for h in handles]
+                for handles in batches]
 
     def collect(self, job, h):
         return ("fields", job.job_id, h["w"], h["sweeps"]), None
@@ -74,13 +82,13 @@ def _mix(n=40, rate=200.0, seed=7):
                  n_sweeps=int(gen.integers(1, 4))) for i in range(n)]
 
 
-@pytest.mark.parametrize("policy", ["fcfs", "rr"])
-def test_every_job_completes_within_budget(policy):
+@pytest.mark.parametrize("policy,lanes", [("fcfs", 1), ("rr", 1), ("fcfs", 3)])
+def test_every_job_completes_within_budget(policy, lanes):
     clock = SimClock()
     be = SimBackend(clock)
     jobs = _mix()
     budget = max(j.n_sites * j.n_walkers for j in jobs)   # the largest job fits alone
-    rep = Server(be, budget, policy=policy, clock=clock).run(jobs)
+    rep = Server(be, budget, policy=policy, clock=clock, lanes=lanes).run(jobs)
     assert be.peak_held <= budget and rep.peak_bytes <= budget
     assert not be.open_handles, "every workspace released"
     for j, r in zip(jobs, rep.results):
@@ -167,3 +175,16 @@ def test_percentile_and_arrivals():
     assert abs(gaps.mean() - 1 / 50.0) < 0.03 / 50.0 * 5       # mean 1/rate
     assert abs(gaps.std() / gaps.mean() - 1.0) < 0.05             # exponential: cv = 1
     assert np.array_equal(t, poisson_arrivals(20000, 50.0, 3))
+
+
+def test_lanes_run_batches_concurrently():
+    """Two lanes: walkers spread evenly over them, two batches per step while
+    both lanes hold walkers, and the same jobs finish sooner than on one."""
+    jobs = [_job(i, 0.0, 8, n_walkers=8, n_sweeps=3) for i in range(4)]
+    ends = {}
+    for lanes in (1, 2):
+        clock = SimClock()
+        rep = Server(SimBackend(clock), 10**6, clock=clock, lanes=lanes).run(jobs)
+        ends[lanes] = max(r.finished for r in rep.results)
+        assert rep.mean_batch == 8.0
+    assert ends[2] < 0.6 * ends[1]
