@@ -13,6 +13,9 @@ Modules
              block force-bias updates, Green's function.
   brute   -- from-scratch configuration weights and Green's functions used
              to pin `pqmc` (definition of W(X), Eq. (9); G, Eq. (12)).
+  soc     -- the spin-orbit coupled (Rashba) Hubbard walker: one 2N-dimensional
+             complex sector, spin-s^y decoupling, rank-two local and delayed
+             updates (Appendix A), with its brute-force weight and G.
   observables -- energy and double occupancy of the standard Hubbard model
              from G (Eq. (1), mixed estimate), for the precision-form error
              statements.

@@ -117,3 +117,74 @@ def workload(name: str, **over) -> Problem:
     kw.update(specs[name])
     kw.update(over)
     return make_problem(**kw)
+
+
+# ---------------------------------------------------------------------------
+# Spin-orbit coupled (Rashba) Hubbard model, paper Eq. (2) and Appendix A:
+# one 2N x 2N complex Hermitian hopping matrix in the basis
+# (c_1up .. c_Nup, c_1dn .. c_Ndn) and a trial determinant of N_e orbitals.
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class SocProblem:
+    """One SOC-Hubbard workload: model inputs plus sweep parameters."""
+    L: int
+    n_e: int
+    U: float               # < 0 (the spin-s^y decoupling needs e^{dtau U/2} <= 1)
+    lam: float             # Rashba strength lambda
+    dtau: float
+    n_slices: int
+    stab_every: int
+    seed: int
+    walker_id: int
+    hopping: np.ndarray    # 2N x 2N complex128, Hermitian
+    trial: np.ndarray      # 2N x n_e complex128, orthonormal columns
+    t: float = 1.0
+    perturb: float = 0.0
+    gap: float = 0.0
+
+    @property
+    def n_sites(self) -> int:
+        return self.L * self.L
+
+
+def rashba_hopping(L: int, t: float = 1.0, lam: float = 0.5, perturb: float = 0.0,
+                   seed: int = SEED_BASE) -> np.ndarray:
+    """2N x 2N hopping of the Rashba model in real space, index s*N + i.
+
+    Spin-diagonal blocks: the square-lattice hopping (with the same seeded
+    bond perturbation as square_lattice_hopping).  Spin-flip block: the
+    Fourier transform of L_k = 2 lambda (sin k_y - i sin k_x) for
+    c+_{k dn} c_{k up}, i.e. for the bond j -> j + d:
+        H[dn (j+x), up j] = +lambda,   H[dn (j-x), up j] = -lambda,
+        H[dn (j+y), up j] = +i lambda, H[dn (j-y), up j] = -i lambda,
+    and the Hermitian conjugate in the up-dn block.
+    """
+    N = L * L
+    H = np.zeros((2 * N, 2 * N), dtype=np.complex128)
+    K = square_lattice_hopping(L, t, perturb, seed)
+    H[:N, :N] = K
+    H[N:, N:] = K
+    for y in range(L):
+        for x in range(L):
+            j = x + L * y
+            for (dx, dy), amp in (((1, 0), lam), ((-1, 0), -lam),
+                                  ((0, 1), 1j * lam), ((0, -1), -1j * lam)):
+                i = ((x + dx) % L) + L * ((y + dy) % L)
+                H[N + i, j] += amp
+                H[j, N + i] += np.conj(amp)
+    return H
+
+
+def make_soc_problem(L: int, n_e: int, U: float, lam: float = 0.5, dtau: float = 0.05,
+                     n_slices: int = 400, stab_every: int = 10, seed: int = SEED_BASE,
+                     walker_id: int = 0, t: float = 1.0, perturb: float = 0.0,
+                     min_gap: float = 1e-8) -> SocProblem:
+    H = rashba_hopping(L, t, lam, perturb, seed)
+    e, V = np.linalg.eigh(H)
+    gap = float(e[n_e] - e[n_e - 1]) if n_e < len(e) else float("inf")
+    if gap <= min_gap:
+        raise ValueError(f"open shell: gap {gap:.3e} <= {min_gap:g}; change n_e or perturb")
+    return SocProblem(L=L, n_e=n_e, U=U, lam=lam, dtau=dtau, n_slices=n_slices,
+                      stab_every=stab_every, seed=seed, walker_id=walker_id, hopping=H,
+                      trial=np.ascontiguousarray(V[:, :n_e]), t=t, perturb=perturb, gap=gap)
