@@ -230,6 +230,70 @@ pqmc_status pqmc_destroy(pqmc_ctx *ctx);
 /* Message of the calling thread's last failure ("" if none). */
 const char *pqmc_last_error(void);
 
+/* ------------------------------------------------------------------------
+ * Spin-orbit coupled Hubbard model (Eq. (2), Appendix A): one complex
+ * sector in the basis (c_1up .. c_Nup, c_1dn .. c_Ndn), 2N orbitals, N_e
+ * fermions, complex128 throughout.  The interaction is decoupled in the
+ * spin-s^y channel, Eq. (A4): gamma = arccos(e^{dtau U/2}) (U <= 0), and
+ * e^{H_I(x)} mixes the row pair (i, N+i) by A(x_i) = e^{gamma x_i i sigma_y},
+ * Eq. (A6).  B_l = e^{H_I(x_l)} e^{-dtau H0}; U_R is 2N x N_e, U_L N_e x 2N,
+ * T = (U_L U_R)^{-1} N_e x N_e, G = 1 - U_R T U_L (2N x 2N).
+ * Updates: PQMC_LOCAL (rank-two Sherman-Morrison per site, Eqs. (A7)-(A9))
+ * and PQMC_DELAYED (delay_k <= 32 sites per flush, the x_m, y_m of
+ * Eqs. (28)-(30) grown to N_e x 2 and 2 x N_e blocks); PQMC_BLOCK_FB is
+ * rejected.  Metropolis: accept iff u < |R|, R = det(1_2 + Y V), with the
+ * uniform of the spin-decoupled path (same Philox counters).  Flags: LOG,
+ * TIMING.  Same workspace, stream and error rules as pqmc_create.
+ * ------------------------------------------------------------------------ */
+typedef struct pqmc_soc_ctx pqmc_soc_ctx;
+
+typedef struct {
+  int32_t n_sites;            /* N (the matrices are 2N x 2N)                          */
+  int32_t n_e;                /* N_e fermions, 1 <= N_e <= min(2N, 1024)                */
+  const double *hopping;      /* 2N x 2N complex128 row-major, (re, im) interleaved,
+                                 Hermitian (copied)                                      */
+  const double *trial;        /* 2N x N_e complex128 row-major, orthonormal columns    */
+  double U;                   /* <= 0                                                  */
+  double dtau;
+  int32_t n_slices;           /* M                                                     */
+  int32_t stab_every;         /* k_tau, divides M                                      */
+  uint64_t seed;
+  uint64_t walker_id;
+} pqmc_soc_problem;
+
+/* Workspace size for this problem (opts->delay_k <= 32 when delayed). */
+pqmc_status pqmc_soc_workspace_bytes(const pqmc_soc_problem *prob, const pqmc_update_opts *opts,
+                                     size_t *bytes);
+
+/* Build a context: e^{-dtau H0} and e^{dtau H0} on the device (Taylor
+ * series with scaling and squaring), Philox fields, the stack of U_L and
+ * the position-0 state.  workspace: device, 256-byte aligned. */
+pqmc_status pqmc_soc_create(const pqmc_soc_problem *prob, const pqmc_update_opts *opts,
+                            void *hip_stream, void *workspace, size_t workspace_bytes,
+                            pqmc_soc_ctx **out);
+
+/* n_sweeps sweeps (forward l = 1..M, backward l = M..1, stabilising every
+ * k_tau slices as pqmc_sweep).  out may be NULL. */
+pqmc_status pqmc_soc_sweep(pqmc_soc_ctx *ctx, int32_t n_sweeps, pqmc_stats *out);
+
+/* Forward pass over slices 1..n_slices only; the context then refuses
+ * further sweeps. */
+pqmc_status pqmc_soc_forward_window(pqmc_soc_ctx *ctx, int32_t n_slices, pqmc_stats *out);
+
+/* G = 1 - U_R T U_L at the current position, 2N x 2N complex128 row-major
+ * interleaved, to host memory. */
+pqmc_status pqmc_soc_get_green(pqmc_soc_ctx *ctx, double *out);
+
+/* Current fields, M x N int8. */
+pqmc_status pqmc_soc_get_fields(pqmc_soc_ctx *ctx, int8_t *fields);
+
+/* Decisions of the last call (PQMC_FLAG_LOG), as pqmc_get_decisions. */
+pqmc_status pqmc_soc_get_decisions(pqmc_soc_ctx *ctx, int32_t *meta, double *margin,
+                                   size_t cap, size_t *n);
+
+/* Release the context (not the workspace). */
+pqmc_status pqmc_soc_destroy(pqmc_soc_ctx *ctx);
+
 #ifdef __cplusplus
 }
 #endif

@@ -21,6 +21,8 @@ EXPORTED_SYMBOLS = (
     "pqmc_batch_forward_window", "pqmc_multi_sweep", "pqmc_get_green",
     "pqmc_get_decisions", "pqmc_get_heat_bath", "pqmc_get_kernel_times", "pqmc_destroy",
     "pqmc_last_error",
+    "pqmc_soc_workspace_bytes", "pqmc_soc_create", "pqmc_soc_sweep", "pqmc_soc_forward_window",
+    "pqmc_soc_get_green", "pqmc_soc_get_fields", "pqmc_soc_get_decisions", "pqmc_soc_destroy",
 )
 KERNEL_CLASSES = ("propagate", "local", "tile", "reduce", "decide")
 
@@ -48,6 +50,15 @@ class Problem(ctypes.Structure):
                 ("hopping", ctypes.POINTER(ctypes.c_double)),
                 ("trial_up", ctypes.POINTER(ctypes.c_double)),
                 ("trial_dn", ctypes.POINTER(ctypes.c_double)),
+                ("U", ctypes.c_double), ("dtau", ctypes.c_double),
+                ("n_slices", ctypes.c_int32), ("stab_every", ctypes.c_int32),
+                ("seed", ctypes.c_uint64), ("walker_id", ctypes.c_uint64)]
+
+
+class SocProblem(ctypes.Structure):
+    _fields_ = [("n_sites", ctypes.c_int32), ("n_e", ctypes.c_int32),
+                ("hopping", ctypes.POINTER(ctypes.c_double)),
+                ("trial", ctypes.POINTER(ctypes.c_double)),
                 ("U", ctypes.c_double), ("dtau", ctypes.c_double),
                 ("n_slices", ctypes.c_int32), ("stab_every", ctypes.c_int32),
                 ("seed", ctypes.c_uint64), ("walker_id", ctypes.c_uint64)]
@@ -109,6 +120,18 @@ def load_library():
         "pqmc_get_kernel_times": [c_void_p, ctypes.POINTER(ctypes.c_double),
                                   ctypes.POINTER(ctypes.c_uint64)],
         "pqmc_destroy": [c_void_p],
+        "pqmc_soc_workspace_bytes": [ctypes.POINTER(SocProblem), ctypes.POINTER(UpdateOpts),
+                                     ctypes.POINTER(c_size_t)],
+        "pqmc_soc_create": [ctypes.POINTER(SocProblem), ctypes.POINTER(UpdateOpts), c_void_p,
+                            c_void_p, c_size_t, ctypes.POINTER(c_void_p)],
+        "pqmc_soc_sweep": [c_void_p, ctypes.c_int32, ctypes.POINTER(Stats)],
+        "pqmc_soc_forward_window": [c_void_p, ctypes.c_int32, ctypes.POINTER(Stats)],
+        "pqmc_soc_get_green": [c_void_p, ctypes.POINTER(ctypes.c_double)],
+        "pqmc_soc_get_fields": [c_void_p, ctypes.POINTER(ctypes.c_int8)],
+        "pqmc_soc_get_decisions": [c_void_p, ctypes.POINTER(ctypes.c_int32),
+                                   ctypes.POINTER(ctypes.c_double), c_size_t,
+                                   ctypes.POINTER(c_size_t)],
+        "pqmc_soc_destroy": [c_void_p],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -250,6 +273,93 @@ class Chain:
         allocator, stream-ordered, so work already queued is unaffected)."""
         if getattr(self, "_ctx", None):
             self._lib.pqmc_destroy(self._ctx)
+            self._ctx = None
+        self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class SocChain:
+    """One walker of the spin-orbit coupled Hubbard model (a pqmc_soc_ctx).
+
+    hopping: 2N x 2N complex128 Hermitian (basis c_1up..c_Nup, c_1dn..c_Ndn);
+    trial: 2N x N_e complex128 with orthonormal columns; U <= 0; scheme
+    LOCAL or DELAYED (k <= 32).
+    """
+
+    def __init__(self, hopping, trial, U, dtau, n_slices, stab_every, seed, walker_id=0,
+                 scheme=Scheme.DELAYED, k=16, log=False, timing=False, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device visible to torch")
+        self._lib = load_library()
+        self._H = np.ascontiguousarray(hopping, dtype=np.complex128)
+        self._P = np.ascontiguousarray(trial, dtype=np.complex128)
+        n2 = self._H.shape[0]
+        self.N, self.M, self.n_e = n2 // 2, int(n_slices), self._P.shape[1]
+        self._prob = SocProblem(self.N, self.n_e, self._H.view(np.float64).ctypes.data_as(
+            ctypes.POINTER(ctypes.c_double)), self._P.view(np.float64).ctypes.data_as(
+            ctypes.POINTER(ctypes.c_double)), float(U), float(dtau), int(n_slices),
+            int(stab_every), int(seed) & (2**64 - 1), int(walker_id))
+        flags = (FLAG_LOG if log else 0) | (FLAG_TIMING if timing else 0)
+        self._opts = UpdateOpts(int(scheme), int(k), 1, flags)
+        nbytes = ctypes.c_size_t(0)
+        _check(self._lib, self._lib.pqmc_soc_workspace_bytes(
+            ctypes.byref(self._prob), ctypes.byref(self._opts), ctypes.byref(nbytes)))
+        self.workspace_bytes = nbytes.value
+        self._stream = stream if stream is not None else torch.cuda.current_stream()
+        with torch.cuda.stream(self._stream):
+            self._ws = torch.empty(nbytes.value + 256, dtype=torch.uint8, device="cuda")
+        base = (self._ws.data_ptr() + 255) // 256 * 256
+        handle = ctypes.c_void_p(0)
+        _check(self._lib, self._lib.pqmc_soc_create(
+            ctypes.byref(self._prob), ctypes.byref(self._opts),
+            ctypes.c_void_p(self._stream.cuda_stream), ctypes.c_void_p(base),
+            ctypes.c_size_t(nbytes.value), ctypes.byref(handle)))
+        self._ctx = handle
+        self.scheme, self.k = Scheme(int(scheme)), int(k)
+
+    def sweep(self, n=1):
+        st = Stats()
+        _check(self._lib, self._lib.pqmc_soc_sweep(self._ctx, int(n), ctypes.byref(st)))
+        return st.as_dict()
+
+    def forward_window(self, n_slices):
+        st = Stats()
+        _check(self._lib, self._lib.pqmc_soc_forward_window(self._ctx, int(n_slices),
+                                                            ctypes.byref(st)))
+        return st.as_dict()
+
+    def green(self):
+        out = np.empty((2 * self.N, 2 * self.N), np.complex128)
+        _check(self._lib, self._lib.pqmc_soc_get_green(
+            self._ctx, out.view(np.float64).ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out
+
+    def fields(self):
+        out = np.empty((self.M, self.N), np.int8)
+        _check(self._lib, self._lib.pqmc_soc_get_fields(
+            self._ctx, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int8))))
+        return out
+
+    def decisions(self):
+        """(meta[n, 3] = (dir*M + l-1, site, accepted), margin[n]) of the last call."""
+        fn = self._lib.pqmc_soc_get_decisions
+        n = ctypes.c_size_t(0)
+        _check(self._lib, fn(self._ctx, None, None, 0, ctypes.byref(n)))
+        meta = np.empty((max(n.value, 1), 3), np.int32)
+        margin = np.empty(max(n.value, 1), np.float64)
+        _check(self._lib, fn(self._ctx, meta.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                             _dptr(margin), n.value, ctypes.byref(n)))
+        return meta[:n.value], margin[:n.value]
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            self._lib.pqmc_soc_destroy(self._ctx)
             self._ctx = None
         self._ws = None
 

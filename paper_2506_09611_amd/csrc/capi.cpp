@@ -24,6 +24,11 @@ pqmc_status set_error(pqmc_status st, const std::string &msg) {
 }  // namespace
 
 namespace pq {
+int api_error(int st, const char *msg) {
+  g_last_error = msg;
+  return st;
+}
+
 int fail_device(hipError_t e, const char *expr, const char *file, int line) {
   char buf[512];
   std::snprintf(buf, sizeof buf, "HIP error %d (%s) in %s at %s:%d", (int)e, hipGetErrorString(e),

@@ -7,6 +7,8 @@
 namespace pq {
 
 int fail_device(hipError_t e, const char *expr, const char *file, int line);
+// sets the calling thread's pqmc_last_error message; returns st
+int api_error(int st, const char *msg);
 
 // ------------------------------------------------------------------ GEMM
 // C = alpha * rs(i) * sum_k op(A)(i,k) ks(k) op(B)(k,j) + beta * Cin(i,j) + [addI && i == j]

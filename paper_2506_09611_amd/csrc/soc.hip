@@ -1,0 +1,509 @@
+// Spin-orbit coupled Hubbard model (Appendix A of the paper): one complex
+// sector of dimension 2N, N_e fermions, spin-s^y decoupling with 2x2 real
+// rotations A(x) = e^{gamma x i sigma_y} on the row pairs (i, N + i).
+//
+// Kernels:
+//   cgemm_kernel     C = alpha op(A) op(B) + beta Cin (+ I), op in {N, T, H},
+//                    64 x 64 complex tiles through LDS, up to 8 products per launch
+//   rotate_kernel    rows (i, N+i) of an n2 x ncols matrix mixed by A(s x_i)
+//   chol_kernel      S = R^H R (upper R) of a Hermitian positive definite S
+//   triinv_kernel    R^{-1} of an upper triangular R
+//   cgj_kernel       M^{-1} by Gauss-Jordan elimination with partial pivoting
+//   soc_decide_kernel  the decisions of one group of k sites in 2k x 2k space
+//                    (rank-two blocks, Eqs. (A7)-(A9) and the delayed update)
+// All matrices are row-major complex128 (interleaved re, im).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include "common.hpp"
+#include "soc.hpp"
+
+namespace pq {
+namespace soc {
+namespace {
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) {
+  return make_double2(a.x + b.x, a.y + b.y);
+}
+__device__ __forceinline__ double2 csub(double2 a, double2 b) {
+  return make_double2(a.x - b.x, a.y - b.y);
+}
+__device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+// acc += a b
+__device__ __forceinline__ void cfma(double2 &acc, double2 a, double2 b) {
+  acc.x = fma(a.x, b.x, acc.x);
+  acc.x = fma(-a.y, b.y, acc.x);
+  acc.y = fma(a.x, b.y, acc.y);
+  acc.y = fma(a.y, b.x, acc.y);
+}
+__device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
+  const double d = b.x * b.x + b.y * b.y;
+  return make_double2((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
+}
+
+// ------------------------------------------------------------------ GEMM
+constexpr int BM = 64, BN = 64, BK = 16;
+
+template <int OP>
+__device__ __forceinline__ double2 op_load(const double2 *A, long ld, int r, int k) {
+  // element (r, k) of op(A): N -> A[r][k], T -> A[k][r], H -> conj(A[k][r])
+  if (OP == kOpN) return A[(long)r * ld + k];
+  const double2 v = A[(long)k * ld + r];
+  return OP == kOpH ? cconj(v) : v;
+}
+
+template <int OPA, int OPB>
+__global__ __launch_bounds__(256) void cgemm_kernel(CgemmBatch b) {
+  const CgemmDesc &g = b.d[blockIdx.z];
+  int K = g.K;
+  if (g.Kdev) K = min(K, *g.Kdev);
+  const int M = g.M, N = g.N;
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  if (m0 >= M || n0 >= N) return;
+  if (K <= 0 && g.Kdev && g.beta.x == 1.0 && g.beta.y == 0.0 && g.Cin == g.C && !g.addI) return;
+  __shared__ double2 As[BK][BM];
+  __shared__ double2 Bs[BK][BN];
+  const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
+  double2 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = make_double2(0.0, 0.0);
+  for (int k0 = 0; k0 < K; k0 += BK) {
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      const int e = t + 256 * p;
+      int r, kk;
+      if (OPA == kOpN) { r = e >> 4; kk = e & 15; } else { kk = e >> 6; r = e & 63; }
+      const int gr = m0 + r, gk = k0 + kk;
+      As[kk][r] = (gr < M && gk < K) ? op_load<OPA>(g.A, g.lda, gr, gk) : make_double2(0.0, 0.0);
+      int c, kb;
+      if (OPB == kOpN) { kb = e >> 6; c = e & 63; } else { c = e >> 4; kb = e & 15; }
+      const int gc = n0 + c, gkb = k0 + kb;
+      // element (k, c) of op(B): N -> B[k][c], T -> B[c][k], H -> conj(B[c][k])
+      double2 v = make_double2(0.0, 0.0);
+      if (gc < N && gkb < K) {
+        if (OPB == kOpN) v = g.B[(long)gkb * g.ldb + gc];
+        else {
+          v = g.B[(long)gc * g.ldb + gkb];
+          if (OPB == kOpH) v = cconj(v);
+        }
+      }
+      Bs[kb][c] = v;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < BK; ++kk) {
+      double2 a[4], bb[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = As[kk][ty + 16 * i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bb[j] = Bs[kk][tx + 16 * j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) cfma(acc[i][j], a[i], bb[j]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int r = m0 + ty + 16 * i, c = n0 + tx + 16 * j;
+      if (r < M && c < N) {
+        double2 v = cmul(g.alpha, acc[i][j]);
+        if (g.Cin && (g.beta.x != 0.0 || g.beta.y != 0.0))
+          v = cadd(v, cmul(g.beta, g.Cin[(long)r * g.ldcin + c]));
+        if (g.addI && r == c) v.x += 1.0;
+        g.C[(long)r * g.ldc + c] = v;
+      }
+    }
+}
+
+// ------------------------------------------------------------- rotations
+// rows (i, N+i) of Y <- A(sign x_i) rows (i, N+i) of X (n2 x ncols, leading
+// dims ldx, ldy; X == Y allowed), A(y) = [[cos gamma y, sin gamma y],
+// [-sin gamma y, cos gamma y]]; x = +-1 so cos(gamma x) = c, sin(gamma x) = x s.
+__global__ __launch_bounds__(256) void rotate_kernel(const double2 *X, long ldx, double2 *Y,
+                                                     long ldy, int ncols, int N,
+                                                     const int8_t *xrow, double c, double s,
+                                                     double sign) {
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (long)N * ncols) return;
+  const int i = (int)(e / ncols), col = (int)(e % ncols);
+  const double sn = sign * (double)xrow[i] * s;
+  const double2 a = X[(long)i * ldx + col], b = X[(long)(N + i) * ldx + col];
+  Y[(long)i * ldy + col] = make_double2(c * a.x + sn * b.x, c * a.y + sn * b.y);
+  Y[(long)(N + i) * ldy + col] = make_double2(-sn * a.x + c * b.x, -sn * a.y + c * b.y);
+}
+
+// Y = conj(X) (n elements)
+__global__ __launch_bounds__(256) void conj_kernel(const double2 *X, double2 *Y, long n) {
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e < n) Y[e] = cconj(X[e]);
+}
+
+// E[r][off + c] = (r == c) for r, c < n (leading dim ld)
+__global__ __launch_bounds__(256) void ident_kernel(double2 *E, long ld, int n, int off) {
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (long)n * n) return;
+  const int r = (int)(e / n), c = (int)(e % n);
+  E[(long)r * ld + off + c] = make_double2(r == c ? 1.0 : 0.0, 0.0);
+}
+
+// ------------------------------------------------------ dense LA, one WG
+constexpr int kLaThreads = 1024;
+
+// In place: the upper triangle of S becomes R with S = R^H R.
+__global__ __launch_bounds__(kLaThreads) void chol_kernel(double2 *S, int n,
+                                                          unsigned long long *stats) {
+  __shared__ double2 rowj[1024];
+  const int t = threadIdx.x;
+  for (int j = 0; j < n; ++j) {
+    const double d2 = S[(long)j * n + j].x;
+    const bool ok = d2 > 0.0 && isfinite(d2);
+    if (!ok) {
+      if (t == 0) stats[kStError] |= kErrSingular;
+      return;
+    }
+    const double inv = 1.0 / sqrt(d2);
+    __syncthreads();   // every thread has read S_jj before row j is overwritten
+    for (int c = j + t; c < n; c += kLaThreads) {
+      const double2 v = S[(long)j * n + c];
+      const double2 r = make_double2(v.x * inv, v.y * inv);
+      rowj[c] = r;
+      S[(long)j * n + c] = r;
+    }
+    __syncthreads();
+    // trailing update of the upper triangle: S_rc -= conj(R_jr) R_jc, r <= c
+    const int m = n - j - 1;
+    const long tot = (long)m * m;
+    for (long e = t; e < tot; e += kLaThreads) {
+      const int r = j + 1 + (int)(e / m), c = j + 1 + (int)(e % m);
+      if (c < r) continue;
+      double2 &x = S[(long)r * n + c];
+      const double2 a = cconj(rowj[r]), b = rowj[c];
+      x = csub(x, cmul(a, b));
+    }
+    __syncthreads();
+  }
+}
+
+// Z = R^{-1} for upper triangular R (n x n); Z is written upper triangular
+// with zeros below the diagonal.
+__global__ __launch_bounds__(kLaThreads) void triinv_kernel(const double2 *R, double2 *Z, int n) {
+  const int t = threadIdx.x;
+  for (long e = t; e < (long)n * n; e += kLaThreads) Z[e] = make_double2(0.0, 0.0);
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    const double2 rjj = R[(long)j * n + j];
+    // Z_ij = -(sum_{i <= k < j} Z_ik R_kj) / R_jj for i < j, Z_jj = 1 / R_jj
+    for (int i = t; i <= j; i += kLaThreads) {
+      if (i == j) {
+        Z[(long)j * n + j] = cdiv(make_double2(1.0, 0.0), rjj);
+      } else {
+        double2 s = make_double2(0.0, 0.0);
+        for (int k = i; k < j; ++k) cfma(s, Z[(long)i * n + k], R[(long)k * n + j]);
+        Z[(long)i * n + j] = cdiv(make_double2(-s.x, -s.y), rjj);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// E = [M | I] (n x 2n, leading dim 2n) -> [I | M^{-1}] up to row order:
+// Gauss-Jordan with partial pivoting, rows swapped explicitly.
+__global__ __launch_bounds__(kLaThreads) void cgj_kernel(double2 *E, int n,
+                                                         unsigned long long *stats) {
+  __shared__ double2 fac[1024];
+  __shared__ double best[kLaThreads / 64];
+  __shared__ int bidx[kLaThreads / 64];
+  __shared__ int piv;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const long ld = 2L * n;
+  for (int j = 0; j < n; ++j) {
+    // pivot: largest |E_rj| over r >= j (ties: smallest r)
+    double bv = -1.0;
+    int bi = n;
+    for (int r = j + t; r < n; r += kLaThreads) {
+      const double2 v = E[(long)r * ld + j];
+      const double a = hypot(v.x, v.y);
+      if (a > bv) { bv = a; bi = r; }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ov = __shfl_down(bv, off, 64);
+      const int oi = __shfl_down(bi, off, 64);
+      if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+    }
+    if (lane == 0) { best[wave] = bv; bidx[wave] = bi; }
+    __syncthreads();
+    if (t == 0) {
+      double b = -1.0;
+      int p = n;
+      for (int w = 0; w < kLaThreads / 64; ++w)
+        if (best[w] > b || (best[w] == b && bidx[w] < p)) { b = best[w]; p = bidx[w]; }
+      piv = (b > 0.0 && isfinite(b)) ? p : -1;
+      if (piv < 0) stats[kStError] |= kErrSingular;
+    }
+    __syncthreads();
+    const int p = piv;
+    if (p < 0) return;
+    // swap rows j and p, then scale row j by 1 / E_jj
+    if (p != j)
+      for (int c = t; c < 2 * n; c += kLaThreads) {
+        const double2 a = E[(long)j * ld + c];
+        E[(long)j * ld + c] = E[(long)p * ld + c];
+        E[(long)p * ld + c] = a;
+      }
+    __syncthreads();
+    const double2 d = E[(long)j * ld + j];
+    __syncthreads();
+    for (int c = t; c < 2 * n; c += kLaThreads)
+      E[(long)j * ld + c] = cdiv(E[(long)j * ld + c], d);
+    for (int r = t; r < n; r += kLaThreads) fac[r] = E[(long)r * ld + j];
+    __syncthreads();
+    // eliminate column j from every other row
+    const long tot = (long)n * (2 * n - j);
+    for (long e = t; e < tot; e += kLaThreads) {
+      const int r = (int)(e / (2 * n - j)), c = j + (int)(e % (2 * n - j));
+      if (r == j) continue;
+      double2 &x = E[(long)r * ld + c];
+      x = csub(x, cmul(fac[r], E[(long)j * ld + c]));
+    }
+    __syncthreads();
+  }
+}
+
+// --------------------------------------------------------------- decisions
+// One workgroup decides the kk sites g0 .. g0 + kk - 1 of one group.
+// n = 2 kk, index a < kk: the up row of site g0 + a, a >= kk: the down row.
+// In: W0p (n x n) = W_g T0 U_L[:, g] (without the flip blocks), the fields.
+// Out: D (n x n) = delta_bd Mc, Mc = (1 + W0_AA)^{-1} spread to n x n (zero
+// outside the accepted set A), so that T = T0 - (T0 U_L[:, g]) D (W_g T0);
+// *nflush = n if A is not empty, else 0; accepted sites' fields flipped and
+// their rows of U_R rotated by A(-2x) = 1 + delta.
+constexpr int kDecThreads = 256;
+
+__global__ __launch_bounds__(kDecThreads) void soc_decide_kernel(SocDecideArgs a) {
+  extern __shared__ double2 lds[];
+  const int kk = a.kk, n = 2 * kk;
+  double2 *W0 = lds;                 // n x n
+  double2 *Mc = W0 + n * n;          // n x n
+  double2 *u = Mc + n * n;           // n x 2: Mc W0[:, jc]
+  double2 *w = u + 2 * n;            // 2 x n: W0[jr, :] Mc
+  __shared__ double2 Sinv[4];
+  __shared__ int accs;
+  __shared__ double xs[64];
+  __shared__ int n_acc;
+  const int t = threadIdx.x;
+  int8_t *xrow = a.fields + (long)a.li * a.N + a.g0;
+  for (int j = t; j < kk; j += kDecThreads) xs[j] = (double)xrow[j];
+  if (t == 0) n_acc = 0;
+  __syncthreads();
+  // W0 with the flip blocks applied to the column pairs (j, kk + j):
+  // delta = [[dd, -x do], [x do, dd]], dd = cos 2gamma - 1, do = sin 2gamma
+  for (int e = t; e < n * kk; e += kDecThreads) {
+    const int r = e / kk, j = e % kk;
+    const double x = xs[j];
+    const double2 w0 = a.W0p[(long)r * n + j], w1 = a.W0p[(long)r * n + kk + j];
+    const double d00 = a.dd, d01 = -x * a.doff, d10 = x * a.doff, d11 = a.dd;
+    W0[r * n + j] = make_double2(w0.x * d00 + w1.x * d10, w0.y * d00 + w1.y * d10);
+    W0[r * n + kk + j] = make_double2(w0.x * d01 + w1.x * d11, w0.y * d01 + w1.y * d11);
+  }
+  for (int e = t; e < n * n; e += kDecThreads) Mc[e] = make_double2(0.0, 0.0);
+  __syncthreads();
+  for (int j = 0; j < kk; ++j) {
+    const int c0 = j, c1 = kk + j;
+    // u = Mc W0[:, (c0, c1)],  w = W0[(c0, c1), :] Mc
+    if (t < 2 * n) {
+      const int q = t / n, r = t % n;
+      const int col = q ? c1 : c0;
+      double2 s = make_double2(0.0, 0.0);
+      for (int b = 0; b < n; ++b) cfma(s, Mc[r * n + b], W0[b * n + col]);
+      u[r * 2 + q] = s;
+    } else if (t < 4 * n) {
+      const int e = t - 2 * n, q = e / n, c = e % n;
+      const int row = q ? c1 : c0;
+      double2 s = make_double2(0.0, 0.0);
+      for (int b = 0; b < n; ++b) cfma(s, W0[row * n + b], Mc[b * n + c]);
+      w[q * n + c] = s;
+    }
+    __syncthreads();
+    if (t == 0) {
+      // S = 1 + W0[jr, jc] - W0[jr, :] u   (the current 1 + W_j T V_j)
+      double2 S[2][2];
+      for (int p = 0; p < 2; ++p)
+        for (int q = 0; q < 2; ++q) {
+          double2 s = W0[(p ? c1 : c0) * n + (q ? c1 : c0)];
+          double2 corr = make_double2(0.0, 0.0);
+          for (int b = 0; b < n; ++b) cfma(corr, W0[(p ? c1 : c0) * n + b], u[b * 2 + q]);
+          s = csub(s, corr);
+          if (p == q) s.x += 1.0;
+          S[p][q] = s;
+        }
+      const double2 R = csub(cmul(S[0][0], S[1][1]), cmul(S[0][1], S[1][0]));
+      const double absR = hypot(R.x, R.y);
+      const int site = a.g0 + j;
+      const double uu = philox_uniform(a.key0, a.key1, a.sweep, a.slice_code, (uint64_t)site,
+                                       kPurposeMH);
+      const bool finite = !isnan(absR);
+      const bool acc = finite && uu < absR;
+      const double margin = absR - uu;
+      a.stats[kStProposed] += 1;
+      a.stats[kStFieldUpdates] += 1;
+      if (acc) { a.stats[kStAccepted] += 1; a.stats[kStFlips] += 1; }
+      if (fabs(margin) < 1e-12) a.stats[kStLowMargin] += 1;
+      if (R.x < 0.0) a.stats[kStNegative] += 1;
+      if (!finite) a.stats[kStError] |= kErrNonFinite;
+      const long long idx = a.log_base + site;
+      if (a.log_meta && idx < a.log_cap) {
+        a.log_meta[3 * idx + 0] = (int32_t)a.slice_code;
+        a.log_meta[3 * idx + 1] = site;
+        a.log_meta[3 * idx + 2] = acc ? 1 : 0;
+        a.log_margin[idx] = margin;
+      }
+      if (acc) {
+        Sinv[0] = cdiv(S[1][1], R);
+        Sinv[1] = cdiv(make_double2(-S[0][1].x, -S[0][1].y), R);
+        Sinv[2] = cdiv(make_double2(-S[1][0].x, -S[1][0].y), R);
+        Sinv[3] = cdiv(S[0][0], R);
+        xrow[j] = (int8_t)(-xrow[j]);
+        n_acc += 1;
+      }
+      accs = acc ? 1 : 0;
+    }
+    __syncthreads();
+    if (accs) {
+      // Mc += (e_jc - u) Sinv (e_jr - w)
+      for (int e = t; e < n * n; e += kDecThreads) {
+        const int r = e / n, c = e % n;
+        double2 l0 = make_double2((r == c0 ? 1.0 : 0.0) - u[r * 2].x, -u[r * 2].y);
+        double2 l1 = make_double2((r == c1 ? 1.0 : 0.0) - u[r * 2 + 1].x, -u[r * 2 + 1].y);
+        double2 r0 = make_double2((c == c0 ? 1.0 : 0.0) - w[c].x, -w[c].y);
+        double2 r1 = make_double2((c == c1 ? 1.0 : 0.0) - w[n + c].x, -w[n + c].y);
+        double2 v = Mc[e];
+        cfma(v, l0, cmul(Sinv[0], r0));
+        cfma(v, l0, cmul(Sinv[1], r1));
+        cfma(v, l1, cmul(Sinv[2], r0));
+        cfma(v, l1, cmul(Sinv[3], r1));
+        Mc[e] = v;
+      }
+      // rows (site, N + site) of U_R <- (1 + delta) rows
+      const double x = xs[j];
+      const double d00 = 1.0 + a.dd, d01 = -x * a.doff, d10 = x * a.doff, d11 = 1.0 + a.dd;
+      double2 *p0 = a.UR + (long)(a.g0 + j) * a.ne, *p1 = a.UR + (long)(a.N + a.g0 + j) * a.ne;
+      for (int c = t; c < a.ne; c += kDecThreads) {
+        const double2 r0 = p0[c], r1 = p1[c];
+        p0[c] = make_double2(d00 * r0.x + d01 * r1.x, d00 * r0.y + d01 * r1.y);
+        p1[c] = make_double2(d10 * r0.x + d11 * r1.x, d10 * r0.y + d11 * r1.y);
+      }
+    }
+    __syncthreads();
+  }
+  // D = delta_bd Mc (rows (j, kk + j) of Mc mixed by the pre-flip delta_j)
+  for (int e = t; e < kk * n; e += kDecThreads) {
+    const int j = e / n, c = e % n;
+    const double x = xs[j];
+    const double d00 = a.dd, d01 = -x * a.doff, d10 = x * a.doff, d11 = a.dd;
+    const double2 m0 = Mc[j * n + c], m1 = Mc[(kk + j) * n + c];
+    a.D[(long)j * n + c] = make_double2(d00 * m0.x + d01 * m1.x, d00 * m0.y + d01 * m1.y);
+    a.D[(long)(kk + j) * n + c] =
+        make_double2(d10 * m0.x + d11 * m1.x, d10 * m0.y + d11 * m1.y);
+  }
+  if (t == 0) *a.nflush = n_acc > 0 ? n : 0;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------- host
+hipError_t cgemm(const CgemmBatch &b, int opA, int opB, hipStream_t st) {
+  if (b.count <= 0) return hipSuccess;
+  if (b.count > kCgemmMaxBatch) return hipErrorInvalidValue;
+  int mt = 0, nt = 0;
+  for (int i = 0; i < b.count; ++i) {
+    mt = max(mt, (b.d[i].M + BM - 1) / BM);
+    nt = max(nt, (b.d[i].N + BN - 1) / BN);
+  }
+  if (mt == 0 || nt == 0) return hipSuccess;
+  const dim3 grid(nt, mt, b.count);
+#define PQ_CG(A_, B_)                                                                  \
+  if (opA == A_ && opB == B_) {                                                        \
+    hipLaunchKernelGGL((cgemm_kernel<A_, B_>), grid, dim3(256), 0, st, b);              \
+    return hipGetLastError();                                                          \
+  }
+  PQ_CG(kOpN, kOpN)
+  PQ_CG(kOpN, kOpT)
+  PQ_CG(kOpT, kOpN)
+  PQ_CG(kOpH, kOpN)
+#undef PQ_CG
+  return hipErrorInvalidValue;
+}
+
+CgemmDesc cdesc(const double2 *A, long lda, const double2 *B, long ldb, double2 *C, long ldc,
+                int M, int N, int K) {
+  CgemmDesc d{};
+  d.A = A; d.B = B; d.C = C;
+  d.lda = lda; d.ldb = ldb; d.ldc = ldc;
+  d.M = M; d.N = N; d.K = K;
+  d.alpha = make_double2(1.0, 0.0);
+  d.beta = make_double2(0.0, 0.0);
+  return d;
+}
+
+hipError_t rotate_rows(const double2 *X, long ldx, double2 *Y, long ldy, int ncols, int N,
+                       const int8_t *xrow, double c, double s, double sign, hipStream_t st) {
+  const long tot = (long)N * ncols;
+  if (tot == 0) return hipSuccess;
+  hipLaunchKernelGGL(rotate_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, X, ldx,
+                     Y, ldy, ncols, N, xrow, c, s, sign);
+  return hipGetLastError();
+}
+
+hipError_t conj_copy(const double2 *X, double2 *Y, long n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(conj_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, X, Y, n);
+  return hipGetLastError();
+}
+
+hipError_t set_identity(double2 *E, long ld, int n, int off, hipStream_t st) {
+  const long tot = (long)n * n;
+  if (tot == 0) return hipSuccess;
+  hipLaunchKernelGGL(ident_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, E, ld, n,
+                     off);
+  return hipGetLastError();
+}
+
+hipError_t cholesky(double2 *S, int n, unsigned long long *stats, hipStream_t st) {
+  if (n > 1024) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(chol_kernel, dim3(1), dim3(kLaThreads), 0, st, S, n, stats);
+  return hipGetLastError();
+}
+
+hipError_t tri_inverse(const double2 *R, double2 *Z, int n, hipStream_t st) {
+  hipLaunchKernelGGL(triinv_kernel, dim3(1), dim3(kLaThreads), 0, st, R, Z, n);
+  return hipGetLastError();
+}
+
+hipError_t gj_inverse(double2 *E, int n, unsigned long long *stats, hipStream_t st) {
+  if (n > 1024) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(cgj_kernel, dim3(1), dim3(kLaThreads), 0, st, E, n, stats);
+  return hipGetLastError();
+}
+
+hipError_t decide(const SocDecideArgs &a, hipStream_t st) {
+  if (a.kk < 1 || a.kk > kSocMaxK) return hipErrorInvalidValue;
+  const int n = 2 * a.kk;
+  const size_t lds = sizeof(double2) * (2 * (size_t)n * n + 4 * (size_t)n);
+  static const hipError_t attr = hipFuncSetAttribute(
+      (const void *)soc_decide_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+      (int)(sizeof(double2) * (2 * 64 * 64 + 4 * 64)));
+  if (attr != hipSuccess) return attr;
+  hipLaunchKernelGGL(soc_decide_kernel, dim3(1), dim3(kDecThreads), lds, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace soc
+}  // namespace pq

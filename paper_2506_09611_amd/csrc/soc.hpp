@@ -1,0 +1,67 @@
+// Internal interface of the spin-orbit coupled (complex, one 2N sector) path.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pq {
+namespace soc {
+
+enum { kOpN = 0, kOpT = 1, kOpH = 2 };   // op(X) = X, X^T, X^H
+
+// C = alpha op(A) op(B) + beta Cin (+ I when addI), op(A) M x K, op(B) K x N;
+// row-major complex128.  Kdev (optional): K = min(K, *Kdev), and a product
+// with K = 0, beta = 1, Cin = C does nothing.
+struct CgemmDesc {
+  const double2 *A, *B, *Cin;
+  double2 *C;
+  long lda, ldb, ldcin, ldc;
+  int M, N, K;
+  const int *Kdev;
+  double2 alpha, beta;
+  int addI;
+};
+constexpr int kCgemmMaxBatch = 8;
+struct CgemmBatch {
+  CgemmDesc d[kCgemmMaxBatch];
+  int count;
+};
+CgemmDesc cdesc(const double2 *A, long lda, const double2 *B, long ldb, double2 *C, long ldc,
+                int M, int N, int K);
+// op pairs supported: (N, N), (N, T), (T, N), (H, N)
+hipError_t cgemm(const CgemmBatch &b, int opA, int opB, hipStream_t st);
+
+// rows (i, N+i) of Y <- A(sign x_i) rows (i, N+i) of X (X == Y allowed),
+// A(y) = [[cos gamma y, sin gamma y], [-sin gamma y, cos gamma y]];
+// c = cos gamma, s = sin gamma.
+hipError_t rotate_rows(const double2 *X, long ldx, double2 *Y, long ldy, int ncols, int N,
+                       const int8_t *xrow, double c, double s, double sign, hipStream_t st);
+// Y = conj(X), n elements
+hipError_t conj_copy(const double2 *X, double2 *Y, long n, hipStream_t st);
+// E[r][off + c] = (r == c), r, c < n
+hipError_t set_identity(double2 *E, long ld, int n, int off, hipStream_t st);
+// upper triangle of S (n x n, Hermitian positive definite) <- R, S = R^H R
+hipError_t cholesky(double2 *S, int n, unsigned long long *stats, hipStream_t st);
+// Z = R^{-1}, R upper triangular (n x n)
+hipError_t tri_inverse(const double2 *R, double2 *Z, int n, hipStream_t st);
+// E = [M | I] (n x 2n) -> [I | M^{-1}], n <= 1024
+hipError_t gj_inverse(double2 *E, int n, unsigned long long *stats, hipStream_t st);
+
+constexpr int kSocMaxK = 32;   // group size of the decision kernel (2k x 2k in LDS)
+struct SocDecideArgs {
+  const double2 *W0p;      // 2kk x 2kk
+  double2 *D;              // 2kk x 2kk out
+  double2 *UR;             // 2N x ne
+  int *nflush;             // out: 2kk or 0
+  int8_t *fields;          // M x N
+  int li, N, ne, g0, kk;
+  double dd, doff;         // delta = [[dd, -x doff], [x doff, dd]]
+  uint64_t key0, key1, sweep, slice_code;
+  unsigned long long *stats;
+  int32_t *log_meta;
+  double *log_margin;
+  long long log_base, log_cap;
+};
+hipError_t decide(const SocDecideArgs &a, hipStream_t st);
+
+}  // namespace soc
+}  // namespace pq

@@ -1,0 +1,585 @@
+// C ABI of the spin-orbit coupled Hubbard path (pqmc_soc_*): one walker per
+// context, one complex sector of dimension 2N (Appendix A of the paper).
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/pqmc.h"
+#include "engine.hpp"
+#include "soc.hpp"
+
+using namespace pq;
+using namespace pq::soc;
+
+struct pqmc_soc_ctx {
+  int N = 0, n2 = 0, ne = 0, M = 0, kt = 0, nst = 0, k = 1;
+  double U = 0, dtau = 0, gamma = 0, c1 = 1, s1 = 0, dd = 0, doff = 0;
+  uint64_t seed = 0, walker = 0;
+  pqmc_update_opts opts{};
+  hipStream_t st = nullptr;
+  // device buffers (complex128 unless noted)
+  double2 *K = nullptr, *Kinv = nullptr, *P = nullptr;
+  double2 *Lstack = nullptr, *Rstack = nullptr;     // (nst + 1) slots of n2 x ne
+  double2 *Rw[2] = {nullptr, nullptr}, *Lw[2] = {nullptr, nullptr}, *Xtmp = nullptr;
+  double2 *UR = nullptr, *ULt = nullptr;            // current (a slot or a work buffer)
+  double2 *E = nullptr;                             // ne x 2ne: [U_L U_R | I] -> [I | T]
+  double2 *T = nullptr;                             // = E + ne, leading dim 2 ne
+  long ldT = 0;
+  double2 *S = nullptr, *Z = nullptr;               // ne x ne: Gram / Cholesky, R^{-1}
+  double2 *P2 = nullptr, *P1 = nullptr, *W0 = nullptr, *D = nullptr, *Q = nullptr;
+  double2 *Tay0 = nullptr, *Tay1 = nullptr;         // n2 x n2 (set-up, then G)
+  int *nflush = nullptr;
+  int8_t *fields = nullptr;
+  unsigned long long *stats = nullptr;
+  int32_t *log_meta = nullptr;
+  double *log_margin = nullptr;
+  long long log_cap = 0, log_count = 0;
+  uint64_t sweep_index = 0;
+  int position = 0;
+  bool windowed = false, failed = false;
+  std::vector<hipEvent_t> ev;
+  size_t ev_used = 0;
+};
+
+namespace {
+
+constexpr unsigned kSocFlags = PQMC_FLAG_LOG | PQMC_FLAG_TIMING;
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+pqmc_status err(pqmc_status st, const char *msg) { return (pqmc_status)api_error(st, msg); }
+
+pqmc_status validate(const pqmc_soc_problem *p, const pqmc_update_opts *o) {
+  if (!p || !o) return err(PQMC_EINVAL, "null problem or options");
+  if (p->n_sites < 1) return err(PQMC_EINVAL, "n_sites must be >= 1");
+  if (p->n_e < 1 || p->n_e > 2 * p->n_sites) return err(PQMC_EINVAL, "need 1 <= n_e <= 2 n_sites");
+  if (p->n_e > 1024) return err(PQMC_EINVAL, "n_e above 1024 is not supported");
+  if (!p->hopping || !p->trial) return err(PQMC_EINVAL, "null input");
+  if (!(p->dtau > 0) || !std::isfinite(p->dtau)) return err(PQMC_EINVAL, "dtau must be > 0");
+  if (!std::isfinite(p->U) || p->U > 0)
+    return err(PQMC_EINVAL, "the spin-s^y decoupling needs a finite U <= 0");
+  if (p->n_slices < 1 || p->stab_every < 1 || p->n_slices % p->stab_every)
+    return err(PQMC_EINVAL, "stab_every must divide n_slices");
+  if (o->scheme != PQMC_LOCAL && o->scheme != PQMC_DELAYED)
+    return err(PQMC_EINVAL, "the SOC path has the local and delayed schemes");
+  if (o->scheme == PQMC_DELAYED && (o->delay_k < 1 || o->delay_k > kSocMaxK))
+    return err(PQMC_EINVAL, "delay_k in [1, 32] for the SOC path");
+  if (o->flags & ~kSocFlags) return err(PQMC_EINVAL, "flags: only LOG and TIMING");
+  const long n2 = 2L * p->n_sites;
+  double asym = 0.0, amax = 0.0;
+  for (long i = 0; i < n2; ++i)
+    for (long j = 0; j < n2; ++j) {
+      const double *a = p->hopping + 2 * (i * n2 + j), *b = p->hopping + 2 * (j * n2 + i);
+      if (!std::isfinite(a[0]) || !std::isfinite(a[1]))
+        return err(PQMC_EINVAL, "non-finite hopping matrix");
+      asym = std::max(asym, std::fabs(a[0] - b[0]) + std::fabs(a[1] + b[1]));
+      amax = std::max(amax, std::fabs(a[0]) + std::fabs(a[1]));
+    }
+  if (asym > 1e-12 * std::max(1.0, amax)) return err(PQMC_EINVAL, "hopping matrix not Hermitian");
+  return PQMC_OK;
+}
+
+void fill(pqmc_soc_ctx &c, const pqmc_soc_problem *p, const pqmc_update_opts *o) {
+  c.N = p->n_sites;
+  c.n2 = 2 * p->n_sites;
+  c.ne = p->n_e;
+  c.M = p->n_slices;
+  c.kt = p->stab_every;
+  c.nst = c.M / c.kt;
+  c.U = p->U;
+  c.dtau = p->dtau;
+  c.gamma = std::acos(std::exp(p->dtau * p->U / 2.0));
+  c.c1 = std::cos(c.gamma);
+  c.s1 = std::sin(c.gamma);
+  // delta = A(-x)^2 - 1 = [[c^2 - s^2 - 1, -x 2cs], [x 2cs, c^2 - s^2 - 1]]
+  c.dd = (c.c1 * c.c1 - c.s1 * c.s1) - 1.0;
+  c.doff = 2.0 * c.c1 * c.s1;
+  c.seed = p->seed;
+  c.walker = p->walker_id;
+  c.opts = *o;
+  c.k = o->scheme == PQMC_DELAYED ? std::min(o->delay_k, c.N) : 1;
+}
+
+struct Carve {
+  char *base;
+  size_t off = 0;
+  template <class T>
+  T *take(size_t n) {
+    off = (off + 255) / 256 * 256;
+    T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+    off += n * sizeof(T);
+    return p;
+  }
+};
+
+void layout(pqmc_soc_ctx &c, char *base, size_t *bytes) {
+  Carve cv{base};
+  const size_t n2 = c.n2, ne = c.ne, kn = 2 * (size_t)kSocMaxK;
+  c.K = cv.take<double2>(n2 * n2);
+  c.Kinv = cv.take<double2>(n2 * n2);
+  c.Tay0 = cv.take<double2>(n2 * n2);
+  c.Tay1 = cv.take<double2>(n2 * n2);
+  c.P = cv.take<double2>(n2 * ne);
+  c.Lstack = cv.take<double2>((c.nst + 1) * n2 * ne);
+  c.Rstack = cv.take<double2>((c.nst + 1) * n2 * ne);
+  for (int i = 0; i < 2; ++i) {
+    c.Rw[i] = cv.take<double2>(n2 * ne);
+    c.Lw[i] = cv.take<double2>(n2 * ne);
+  }
+  c.Xtmp = cv.take<double2>(n2 * ne);
+  c.E = cv.take<double2>(ne * 2 * ne);
+  c.T = c.E ? c.E + ne : nullptr;
+  c.ldT = 2L * (long)ne;
+  c.S = cv.take<double2>(ne * ne);
+  c.Z = cv.take<double2>(ne * ne);
+  c.P2 = cv.take<double2>(kn * ne);
+  c.P1 = cv.take<double2>(ne * kn);
+  c.W0 = cv.take<double2>(kn * kn);
+  c.D = cv.take<double2>(kn * kn);
+  c.Q = cv.take<double2>(ne * kn);
+  c.nflush = cv.take<int>(4);
+  c.fields = cv.take<int8_t>((size_t)c.M * c.N);
+  c.stats = cv.take<unsigned long long>(16);
+  if (c.opts.flags & PQMC_FLAG_LOG) {
+    c.log_cap = 2LL * c.M * c.N;
+    c.log_meta = cv.take<int32_t>(3 * (size_t)c.log_cap);
+    c.log_margin = cv.take<double>((size_t)c.log_cap);
+  }
+  *bytes = cv.off;
+}
+
+double2 *slot(double2 *stack, int j, const pqmc_soc_ctx &c) {
+  return stack + (size_t)j * c.n2 * c.ne;
+}
+double2 *other(const double2 *cur, double2 *const w[2]) { return cur == w[0] ? w[1] : w[0]; }
+
+int gemm1(const CgemmDesc &d, int opA, int opB, hipStream_t st) {
+  CgemmBatch b{};
+  b.d[0] = d;
+  b.count = 1;
+  PQ_HIP_CHECK(cgemm(b, opA, opB, st));
+  return PQMC_OK;
+}
+
+// e^{scale H0} (Taylor of degree 18 after scaling by 2^-sq, then sq squarings),
+// H0 uploaded in Tay0... the result in dst; Tay0 holds H0 throughout.
+int expm(pqmc_soc_ctx &c, double scale, int sq, double2 *dst) {
+  const int n = c.n2;
+  double2 *Y = dst, *Yn = c.Tay1;
+  PQ_HIP_CHECK(set_identity(Y, n, n, 0, c.st));
+  for (int j = 18; j >= 1; --j) {
+    CgemmDesc d = cdesc(c.Tay0, n, Y, n, Yn, n, n, n, n);
+    d.alpha = make_double2(scale / j, 0.0);
+    d.addI = 1;
+    int rc = gemm1(d, kOpN, kOpN, c.st);
+    if (rc) return rc;
+    std::swap(Y, Yn);
+  }
+  for (int q = 0; q < sq; ++q) {
+    int rc = gemm1(cdesc(Y, n, Y, n, Yn, n, n, n, n), kOpN, kOpN, c.st);
+    if (rc) return rc;
+    std::swap(Y, Yn);
+  }
+  if (Y != dst)
+    PQ_HIP_CHECK(hipMemcpyAsync(dst, Y, sizeof(double2) * (size_t)n * n,
+                                hipMemcpyDeviceToDevice, c.st));
+  return PQMC_OK;
+}
+
+// dst = A R^{-1} with A^H A = R^H R (A: n2 x ne): columns orthonormalised.
+int orthonormalize(pqmc_soc_ctx &c, const double2 *A, double2 *dst) {
+  const int n2 = c.n2, ne = c.ne;
+  int rc = gemm1(cdesc(A, ne, A, ne, c.S, ne, ne, ne, n2), kOpH, kOpN, c.st);
+  if (rc) return rc;
+  PQ_HIP_CHECK(cholesky(c.S, ne, c.stats, c.st));
+  PQ_HIP_CHECK(tri_inverse(c.S, c.Z, ne, c.st));
+  return gemm1(cdesc(A, ne, c.Z, ne, dst, ne, n2, ne, ne), kOpN, kOpN, c.st);
+}
+
+// T = (U_L U_R)^{-1} = (ULt^T UR)^{-1}
+int refresh_T(pqmc_soc_ctx &c) {
+  const int n2 = c.n2, ne = c.ne;
+  int rc = gemm1(cdesc(c.ULt, ne, c.UR, ne, c.E, 2L * ne, ne, ne, n2), kOpT, kOpN, c.st);
+  if (rc) return rc;
+  PQ_HIP_CHECK(set_identity(c.E, 2L * ne, ne, ne, c.st));
+  PQ_HIP_CHECK(gj_inverse(c.E, ne, c.stats, c.st));
+  return PQMC_OK;
+}
+
+// position l-1 -> l: U_R <- e^{H_I(x_l)} K U_R; U_L <- U_L K^{-1} e^{-H_I(x_l)},
+// i.e. ULt <- [e^{-H_I}]^T K^{-T} ULt, whose 2x2 blocks are A(x).
+int prop_forward(pqmc_soc_ctx &c, int l) {
+  const int n2 = c.n2, ne = c.ne;
+  const int8_t *x = c.fields + (size_t)(l - 1) * c.N;
+  double2 *nur = other(c.UR, c.Rw), *nul = other(c.ULt, c.Lw);
+  int rc = gemm1(cdesc(c.K, n2, c.UR, ne, nur, ne, n2, ne, n2), kOpN, kOpN, c.st);
+  if (!rc) rc = gemm1(cdesc(c.Kinv, n2, c.ULt, ne, nul, ne, n2, ne, n2), kOpT, kOpN, c.st);
+  if (rc) return rc;
+  PQ_HIP_CHECK(rotate_rows(nur, ne, nur, ne, ne, c.N, x, c.c1, c.s1, 1.0, c.st));
+  PQ_HIP_CHECK(rotate_rows(nul, ne, nul, ne, ne, c.N, x, c.c1, c.s1, 1.0, c.st));
+  c.UR = nur;
+  c.ULt = nul;
+  return PQMC_OK;
+}
+
+// position l -> l-1: U_L <- U_L e^{H_I(x_l)} K, i.e. ULt <- K^T [e^{H_I}]^T ULt
+// (blocks A(-x)); U_R <- K^{-1} e^{-H_I(x_l)} U_R (blocks A(-x)).  The
+// rotations go to a scratch buffer: the current matrices may be stack slots.
+int prop_backward(pqmc_soc_ctx &c, int l, bool with_R) {
+  const int n2 = c.n2, ne = c.ne;
+  const int8_t *x = c.fields + (size_t)(l - 1) * c.N;
+  double2 *nul = other(c.ULt, c.Lw);
+  PQ_HIP_CHECK(rotate_rows(c.ULt, ne, c.Xtmp, ne, ne, c.N, x, c.c1, c.s1, -1.0, c.st));
+  int rc = gemm1(cdesc(c.K, n2, c.Xtmp, ne, nul, ne, n2, ne, n2), kOpT, kOpN, c.st);
+  if (rc) return rc;
+  c.ULt = nul;
+  if (with_R) {
+    double2 *nur = other(c.UR, c.Rw);
+    PQ_HIP_CHECK(rotate_rows(c.UR, ne, c.Xtmp, ne, ne, c.N, x, c.c1, c.s1, -1.0, c.st));
+    rc = gemm1(cdesc(c.Kinv, n2, c.Xtmp, ne, nur, ne, n2, ne, n2), kOpN, kOpN, c.st);
+    if (rc) return rc;
+    c.UR = nur;
+  }
+  return PQMC_OK;
+}
+
+int build_state(pqmc_soc_ctx &c) {
+  const size_t mat = (size_t)c.n2 * c.ne;
+  // U_L = P^+ at position M: ULt = conj(P)
+  PQ_HIP_CHECK(conj_copy(c.P, slot(c.Lstack, c.nst, c), (long)mat, c.st));
+  PQ_HIP_CHECK(hipMemcpyAsync(slot(c.Rstack, 0, c), c.P, sizeof(double2) * mat,
+                              hipMemcpyDeviceToDevice, c.st));
+  c.ULt = slot(c.Lstack, c.nst, c);
+  c.UR = slot(c.Rstack, 0, c);
+  for (int l = c.M; l >= 1; --l) {
+    int rc = prop_backward(c, l, false);
+    if (rc) return rc;
+    if ((l - 1) % c.kt == 0) {
+      double2 *dst = slot(c.Lstack, (l - 1) / c.kt, c);
+      rc = orthonormalize(c, c.ULt, dst);
+      if (rc) return rc;
+      c.ULt = dst;
+    }
+  }
+  c.UR = slot(c.Rstack, 0, c);
+  c.position = 0;
+  c.windowed = false;
+  return refresh_T(c);
+}
+
+int timer_mark(pqmc_soc_ctx &c) {
+  if (!(c.opts.flags & PQMC_FLAG_TIMING)) return PQMC_OK;
+  if (c.ev_used == c.ev.size()) {
+    hipEvent_t e;
+    PQ_HIP_CHECK(hipEventCreate(&e));
+    c.ev.push_back(e);
+  }
+  PQ_HIP_CHECK(hipEventRecord(c.ev[c.ev_used++], c.st));
+  return PQMC_OK;
+}
+
+// Field update of slice l (direction dir): groups of k sites (k = 1: the
+// local update), each: panels P2 = W_g T, P1 = T U_L[:, g], W0' = P2 U_L[:, g],
+// the decisions in 2k x 2k space, then T -= (P1 D) P2.
+int update_slice(pqmc_soc_ctx &c, int l, int dir) {
+  const int N = c.N, ne = c.ne, li = l - 1;
+  int rc = timer_mark(c);
+  if (rc) return rc;
+  for (int g0 = 0; g0 < N; g0 += c.k) {
+    const int kk = std::min(c.k, N - g0), n = 2 * kk;
+    const double2 *ur0 = c.UR + (size_t)g0 * ne, *ur1 = c.UR + (size_t)(N + g0) * ne;
+    const double2 *ul0 = c.ULt + (size_t)g0 * ne, *ul1 = c.ULt + (size_t)(N + g0) * ne;
+    CgemmBatch a{};
+    a.d[a.count++] = cdesc(ur0, ne, c.T, c.ldT, c.P2, ne, kk, ne, ne);
+    a.d[a.count++] = cdesc(ur1, ne, c.T, c.ldT, c.P2 + (size_t)kk * ne, ne, kk, ne, ne);
+    PQ_HIP_CHECK(cgemm(a, kOpN, kOpN, c.st));
+    CgemmBatch b{};
+    b.d[b.count++] = cdesc(c.T, c.ldT, ul0, ne, c.P1, n, ne, kk, ne);
+    b.d[b.count++] = cdesc(c.T, c.ldT, ul1, ne, c.P1 + kk, n, ne, kk, ne);
+    b.d[b.count++] = cdesc(c.P2, ne, ul0, ne, c.W0, n, n, kk, ne);
+    b.d[b.count++] = cdesc(c.P2, ne, ul1, ne, c.W0 + kk, n, n, kk, ne);
+    PQ_HIP_CHECK(cgemm(b, kOpN, kOpT, c.st));
+    SocDecideArgs d{};
+    d.W0p = c.W0;
+    d.D = c.D;
+    d.UR = c.UR;
+    d.nflush = c.nflush;
+    d.fields = c.fields;
+    d.li = li;
+    d.N = N;
+    d.ne = ne;
+    d.g0 = g0;
+    d.kk = kk;
+    d.dd = c.dd;
+    d.doff = c.doff;
+    d.key0 = c.seed;
+    d.key1 = c.walker;
+    d.sweep = c.sweep_index;
+    d.slice_code = (uint64_t)dir * c.M + li;
+    d.stats = c.stats;
+    d.log_meta = c.log_meta;
+    d.log_margin = c.log_margin;
+    d.log_base = c.log_count;
+    d.log_cap = c.log_cap;
+    PQ_HIP_CHECK(decide(d, c.st));
+    CgemmDesc q = cdesc(c.P1, n, c.D, n, c.Q, n, ne, n, n);
+    q.Kdev = c.nflush;
+    rc = gemm1(q, kOpN, kOpN, c.st);
+    if (rc) return rc;
+    CgemmDesc u = cdesc(c.Q, n, c.P2, ne, c.T, c.ldT, ne, ne, n);
+    u.alpha = make_double2(-1.0, 0.0);
+    u.beta = make_double2(1.0, 0.0);
+    u.Cin = c.T;
+    u.ldcin = c.ldT;
+    u.Kdev = c.nflush;
+    rc = gemm1(u, kOpN, kOpN, c.st);
+    if (rc) return rc;
+  }
+  c.log_count += N;
+  return timer_mark(c);
+}
+
+int stab_forward(pqmc_soc_ctx &c, int l) {
+  const int j = l / c.kt;
+  double2 *dst = slot(c.Rstack, j, c);
+  int rc = orthonormalize(c, c.UR, dst);
+  if (rc) return rc;
+  c.UR = dst;
+  c.ULt = slot(c.Lstack, j, c);
+  return refresh_T(c);
+}
+
+int stab_backward(pqmc_soc_ctx &c, int l) {
+  const int j = (l - 1) / c.kt;
+  double2 *dst = slot(c.Lstack, j, c);
+  int rc = orthonormalize(c, c.ULt, dst);
+  if (rc) return rc;
+  c.ULt = dst;
+  c.UR = slot(c.Rstack, j, c);
+  return refresh_T(c);
+}
+
+int begin_call(pqmc_soc_ctx &c) {
+  PQ_HIP_CHECK(hipMemsetAsync(c.stats, 0, sizeof(unsigned long long) * 16, c.st));
+  c.log_count = 0;
+  c.ev_used = 0;
+  return PQMC_OK;
+}
+
+int finish_call(pqmc_soc_ctx &c, double t0, pqmc_stats *out) {
+  PQ_HIP_CHECK(hipStreamSynchronize(c.st));
+  unsigned long long h[16];
+  PQ_HIP_CHECK(hipMemcpy(h, c.stats, sizeof h, hipMemcpyDeviceToHost));
+  if (h[kStError] & kErrSingular) {
+    c.failed = true;
+    return api_error(PQMC_ESINGULAR, "a stabilisation factorisation broke down");
+  }
+  if (h[kStError] & kErrNonFinite) {
+    c.failed = true;
+    return api_error(PQMC_ENONFINITE, "a determinant ratio was not finite");
+  }
+  if (out) {
+    std::memset(out, 0, sizeof *out);
+    out->proposed = h[kStProposed];
+    out->accepted = h[kStAccepted];
+    out->flips = h[kStFlips];
+    out->low_margin = h[kStLowMargin];
+    out->negative = h[kStNegative];
+    out->field_updates = h[kStFieldUpdates];
+    out->t_total_s = now_s() - t0;
+    double upd = 0.0;
+    for (size_t i = 0; i + 1 < c.ev_used; i += 2) {
+      float ms = 0.f;
+      PQ_HIP_CHECK(hipEventElapsedTime(&ms, c.ev[i], c.ev[i + 1]));
+      upd += ms * 1e-3;
+    }
+    out->t_update_s = upd;
+  }
+  return PQMC_OK;
+}
+
+int sync_check(pqmc_soc_ctx &c) {
+  PQ_HIP_CHECK(hipStreamSynchronize(c.st));
+  unsigned long long h[16];
+  PQ_HIP_CHECK(hipMemcpy(h, c.stats, sizeof h, hipMemcpyDeviceToHost));
+  if (h[kStError] & kErrSingular)
+    return api_error(PQMC_ESINGULAR, "a factorisation broke down while building the state");
+  return PQMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pqmc_status pqmc_soc_workspace_bytes(const pqmc_soc_problem *prob, const pqmc_update_opts *opts,
+                                     size_t *bytes) {
+  if (!bytes) return err(PQMC_EINVAL, "null bytes");
+  pqmc_status v = validate(prob, opts);
+  if (v) return v;
+  pqmc_soc_ctx c;
+  fill(c, prob, opts);
+  layout(c, nullptr, bytes);
+  return PQMC_OK;
+}
+
+pqmc_status pqmc_soc_create(const pqmc_soc_problem *prob, const pqmc_update_opts *opts,
+                            void *hip_stream, void *workspace, size_t workspace_bytes,
+                            pqmc_soc_ctx **out) {
+  if (!out) return err(PQMC_EINVAL, "null out");
+  *out = nullptr;
+  pqmc_status v = validate(prob, opts);
+  if (v) return v;
+  if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255))
+    return err(PQMC_EINVAL, "workspace must be a 256-byte aligned device pointer");
+  pqmc_soc_ctx *c = new (std::nothrow) pqmc_soc_ctx;
+  if (!c) return err(PQMC_ENOMEM, "host allocation failed");
+  fill(*c, prob, opts);
+  c->st = (hipStream_t)hip_stream;
+  size_t need = 0;
+  layout(*c, nullptr, &need);
+  if (need > workspace_bytes) {
+    delete c;
+    return err(PQMC_ENOMEM, "workspace too small");
+  }
+  layout(*c, (char *)workspace, &need);
+  auto fail = [&](int rc) {
+    for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+    delete c;
+    return (pqmc_status)rc;
+  };
+  const size_t n2 = c->n2, ne = c->ne;
+  // H0 scaled into Tay0, P into place; host inputs are copied here
+  double norm = 0.0;
+  for (size_t i = 0; i < n2; ++i) {
+    double row = 0.0;
+    for (size_t j = 0; j < n2; ++j)
+      row += std::hypot(prob->hopping[2 * (i * n2 + j)], prob->hopping[2 * (i * n2 + j) + 1]);
+    norm = std::max(norm, row);
+  }
+  hipError_t e = hipMemcpyAsync(c->Tay0, prob->hopping, sizeof(double2) * n2 * n2,
+                                hipMemcpyHostToDevice, c->st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->P, prob->trial, sizeof(double2) * n2 * ne, hipMemcpyHostToDevice, c->st);
+  if (e == hipSuccess) e = hipMemsetAsync(c->stats, 0, sizeof(unsigned long long) * 16, c->st);
+  if (e != hipSuccess) return fail(fail_device(e, "upload", __FILE__, __LINE__));
+  const double x = c->dtau * norm;
+  const int sq = x > 0.5 ? (int)std::ceil(std::log2(x / 0.5)) : 0;
+  const double scale = c->dtau / std::ldexp(1.0, sq);
+  int rc = expm(*c, -scale, sq, c->K);
+  if (!rc) rc = expm(*c, scale, sq, c->Kinv);
+  if (!rc) {
+    e = init_fields(c->fields, c->M, c->N, c->seed, c->walker, c->st);
+    if (e != hipSuccess) rc = fail_device(e, "init_fields", __FILE__, __LINE__);
+  }
+  if (!rc) rc = build_state(*c);
+  if (!rc) rc = sync_check(*c);
+  if (rc) return fail(rc);
+  *out = c;
+  return PQMC_OK;
+}
+
+static pqmc_status soc_run(pqmc_soc_ctx *c, int n_sweeps, int n_slices, pqmc_stats *out) {
+  if (!c) return err(PQMC_EINVAL, "null context");
+  if (c->failed) return err(PQMC_ESTATE, "context failed");
+  if (c->windowed || c->position != 0) return err(PQMC_ESTATE, "walker is mid-sweep");
+  const double t0 = now_s();
+  int rc = begin_call(*c);
+  if (n_slices >= 0) {   // one forward window
+    for (int l = 1; l <= n_slices && !rc; ++l) {
+      rc = prop_forward(*c, l);
+      if (!rc) rc = update_slice(*c, l, 0);
+      if (!rc && l % c->kt == 0) rc = stab_forward(*c, l);
+    }
+    c->position = n_slices;
+    c->windowed = true;
+  } else {
+    for (int s = 0; s < n_sweeps && !rc; ++s) {
+      for (int l = 1; l <= c->M && !rc; ++l) {
+        rc = prop_forward(*c, l);
+        if (!rc) rc = update_slice(*c, l, 0);
+        if (!rc && l % c->kt == 0) rc = stab_forward(*c, l);
+      }
+      for (int l = c->M; l >= 1 && !rc; --l) {
+        rc = update_slice(*c, l, 1);
+        if (!rc) rc = prop_backward(*c, l, true);
+        if (!rc && (l - 1) % c->kt == 0) rc = stab_backward(*c, l);
+      }
+      if (!rc) ++c->sweep_index;
+    }
+  }
+  if (!rc) rc = finish_call(*c, t0, out);
+  if (rc) c->failed = true;
+  return (pqmc_status)rc;
+}
+
+pqmc_status pqmc_soc_sweep(pqmc_soc_ctx *c, int32_t n_sweeps, pqmc_stats *out) {
+  if (n_sweeps < 0) return err(PQMC_EINVAL, "n_sweeps < 0");
+  return soc_run(c, n_sweeps, -1, out);
+}
+
+pqmc_status pqmc_soc_forward_window(pqmc_soc_ctx *c, int32_t n_slices, pqmc_stats *out) {
+  if (c && (n_slices < 0 || n_slices > c->M)) return err(PQMC_EINVAL, "n_slices out of range");
+  return soc_run(c, 0, n_slices, out);
+}
+
+pqmc_status pqmc_soc_get_green(pqmc_soc_ctx *c, double *out) {
+  if (!c || !out) return err(PQMC_EINVAL, "null argument");
+  const int n2 = c->n2, ne = c->ne;
+  // Y = U_R T (n2 x ne, in Xtmp), G = 1 - Y ULt^T (n2 x n2, in Tay1)
+  int rc = gemm1(cdesc(c->UR, ne, c->T, c->ldT, c->Xtmp, ne, n2, ne, ne), kOpN, kOpN, c->st);
+  if (!rc) {
+    CgemmDesc d = cdesc(c->Xtmp, ne, c->ULt, ne, c->Tay1, n2, n2, n2, ne);
+    d.alpha = make_double2(-1.0, 0.0);
+    d.addI = 1;
+    rc = gemm1(d, kOpN, kOpT, c->st);
+  }
+  if (rc) return (pqmc_status)rc;
+  hipError_t e = hipMemcpyAsync(out, c->Tay1, sizeof(double2) * (size_t)n2 * n2,
+                                hipMemcpyDeviceToHost, c->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+  if (e != hipSuccess) return (pqmc_status)fail_device(e, "green", __FILE__, __LINE__);
+  return PQMC_OK;
+}
+
+pqmc_status pqmc_soc_get_fields(pqmc_soc_ctx *c, int8_t *out) {
+  if (!c || !out) return err(PQMC_EINVAL, "null argument");
+  hipError_t e = hipMemcpyAsync(out, c->fields, (size_t)c->M * c->N, hipMemcpyDeviceToHost, c->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+  if (e != hipSuccess) return (pqmc_status)fail_device(e, "fields", __FILE__, __LINE__);
+  return PQMC_OK;
+}
+
+pqmc_status pqmc_soc_get_decisions(pqmc_soc_ctx *c, int32_t *meta, double *margin, size_t cap,
+                                   size_t *n) {
+  if (!c || !n) return err(PQMC_EINVAL, "null argument");
+  if (!c->log_meta) return err(PQMC_EINVAL, "the context was created without PQMC_FLAG_LOG");
+  const size_t cnt = (size_t)std::min(c->log_count, c->log_cap);
+  *n = cnt;
+  if (!meta || !margin || cap == 0) return PQMC_OK;
+  const size_t m = std::min(cnt, cap);
+  hipError_t e = hipMemcpyAsync(meta, c->log_meta, sizeof(int32_t) * 3 * m,
+                                hipMemcpyDeviceToHost, c->st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(margin, c->log_margin, sizeof(double) * m, hipMemcpyDeviceToHost, c->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+  if (e != hipSuccess) return (pqmc_status)fail_device(e, "log copy", __FILE__, __LINE__);
+  return PQMC_OK;
+}
+
+pqmc_status pqmc_soc_destroy(pqmc_soc_ctx *c) {
+  if (!c) return PQMC_OK;
+  (void)hipStreamSynchronize(c->st);
+  for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+  delete c;
+  return PQMC_OK;
+}
+
+}  // extern "C"
