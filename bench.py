@@ -208,6 +208,49 @@ def scheme_table(p, spec, window):
     return {"walkers": 1, "window_slice_visits": window, "rows": rows}
 
 
+def soc_leg(args):
+    """SOC-Hubbard (Rashba lambda = 0.5, U/t = -4, n = 1): local vs delayed
+    update on forward windows of one walker, per lattice size."""
+    import torch
+    import synth
+    from paper_2506_09611_amd import SocChain, Scheme
+    rows = []
+    for L in [int(x) for x in args.soc_sizes.split(",") if x]:
+        N = L * L
+        p = synth.make_soc_problem(L, N, -4.0, lam=0.5, dtau=0.05, n_slices=2 * args.soc_window,
+                                   stab_every=args.soc_window, perturb=1e-3,
+                                   seed=synth.SEED_BASE + 600 + L)
+        base = None
+        for k in [1] + [int(x) for x in args.soc_k.split(",") if x]:
+            sc = Scheme.LOCAL if k == 1 else Scheme.DELAYED
+            c = SocChain(p.hopping, p.trial, p.U, p.dtau, p.n_slices, p.stab_every, p.seed,
+                         scheme=sc, k=k, timing=True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = c.forward_window(args.soc_window)
+            torch.cuda.synchronize()
+            w = time.perf_counter() - t0
+            fu = args.soc_window * N
+            row = {"L": L, "n_e": N, "scheme": "local" if k == 1 else "delayed", "k": k,
+                   "s_window": w, "field_updates_per_s": fu / w,
+                   "update_only": fu / st["t_update_s"] if st["t_update_s"] > 0 else None,
+                   "acceptance": st["accepted"] / max(1, st["proposed"])}
+            if k == 1:
+                base = row
+            row["speedup_vs_local"] = row["field_updates_per_s"] / base["field_updates_per_s"]
+            row["update_speedup_vs_local"] = (row["update_only"] / base["update_only"]
+                                              if row["update_only"] and base["update_only"]
+                                              else None)
+            log("soc", row)
+            rows.append(row)
+            c.close()
+            del c
+            torch.cuda.empty_cache()
+    return {"model": "Rashba SOC-Hubbard, lambda/t = 0.5, U/t = -4, n = 1, dtau = 0.05, "
+                     "one walker, complex128", "window_slice_visits": args.soc_window,
+            "rows": rows}
+
+
 def serve_leg(args, rate):
     """Jobs of mixed lattice sizes and couplings arriving as a Poisson stream
     of `rate` jobs/s, served by the continuous-batching server under an HBM
@@ -283,6 +326,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--autotune", default="8,16,32,64,128",
                     help="delay ranks the autotuner times on the headline batch ('' to skip)")
+    ap.add_argument("--soc-sizes", default="8,16,24",
+                    help="lattice sides of the SOC-Hubbard table ('' for none)")
+    ap.add_argument("--soc-k", default="8,16,32", help="delay ranks of the SOC table")
+    ap.add_argument("--soc-window", type=int, default=10,
+                    help="forward slice visits per SOC table entry (also k_tau)")
     ap.add_argument("--serve-jobs", type=int, default=32,
                     help="jobs of the serving leg (0 = skip it)")
     ap.add_argument("--serve-rate", default="8,64",
@@ -472,6 +520,8 @@ def main():
         result["autotune"] = tuned
     if args.table:
         result["table"] = scheme_table(p, args.table, args.table_window)
+    if args.soc_sizes:
+        result["soc"] = soc_leg(args)
     if args.serve_jobs > 0:
         result["serving"] = [serve_leg(args, float(r)) for r in args.serve_rate.split(",") if r]
     if not args.no_cpu:

@@ -7,8 +7,8 @@
 //                    64 x 64 complex tiles through LDS, up to 8 products per launch
 //   rotate_kernel    rows (i, N+i) of an n2 x ncols matrix mixed by A(s x_i)
 //   chol_kernel      S = R^H R (upper R) of a Hermitian positive definite S
-//   triinv_kernel    R^{-1} of an upper triangular R
-//   cgj_kernel       M^{-1} by Gauss-Jordan elimination with partial pivoting
+//   gj_step_kernel   one pivot column of Gauss-Jordan elimination with partial
+//                    pivoting on [M | I], spread over 64-column workgroups
 //   soc_decide_kernel  the decisions of one group of k sites in 2k x 2k space
 //                    (rank-two blocks, Eqs. (A7)-(A9) and the delayed update)
 // All matrices are row-major complex128 (interleaved re, im).
@@ -157,13 +157,14 @@ __global__ __launch_bounds__(256) void ident_kernel(double2 *E, long ld, int n, 
 // ------------------------------------------------------ dense LA, one WG
 constexpr int kLaThreads = 1024;
 
-// In place: the upper triangle of S becomes R with S = R^H R.
-__global__ __launch_bounds__(kLaThreads) void chol_kernel(double2 *S, int n,
+// In place (leading dim ld): the upper triangle of S becomes R with
+// S = R^H R, and the strict lower triangle is zeroed.
+__global__ __launch_bounds__(kLaThreads) void chol_kernel(double2 *S, long ld, int n,
                                                           unsigned long long *stats) {
   __shared__ double2 rowj[1024];
   const int t = threadIdx.x;
   for (int j = 0; j < n; ++j) {
-    const double d2 = S[(long)j * n + j].x;
+    const double d2 = S[(long)j * ld + j].x;
     const bool ok = d2 > 0.0 && isfinite(d2);
     if (!ok) {
       if (t == 0) stats[kStError] |= kErrSingular;
@@ -172,11 +173,12 @@ __global__ __launch_bounds__(kLaThreads) void chol_kernel(double2 *S, int n,
     const double inv = 1.0 / sqrt(d2);
     __syncthreads();   // every thread has read S_jj before row j is overwritten
     for (int c = j + t; c < n; c += kLaThreads) {
-      const double2 v = S[(long)j * n + c];
+      const double2 v = S[(long)j * ld + c];
       const double2 r = make_double2(v.x * inv, v.y * inv);
       rowj[c] = r;
-      S[(long)j * n + c] = r;
+      S[(long)j * ld + c] = r;
     }
+    for (int r = j + 1 + t; r < n; r += kLaThreads) S[(long)r * ld + j] = make_double2(0.0, 0.0);
     __syncthreads();
     // trailing update of the upper triangle: S_rc -= conj(R_jr) R_jc, r <= c
     const int m = n - j - 1;
@@ -184,97 +186,89 @@ __global__ __launch_bounds__(kLaThreads) void chol_kernel(double2 *S, int n,
     for (long e = t; e < tot; e += kLaThreads) {
       const int r = j + 1 + (int)(e / m), c = j + 1 + (int)(e % m);
       if (c < r) continue;
-      double2 &x = S[(long)r * n + c];
-      const double2 a = cconj(rowj[r]), b = rowj[c];
-      x = csub(x, cmul(a, b));
+      double2 &x = S[(long)r * ld + c];
+      x = csub(x, cmul(cconj(rowj[r]), rowj[c]));
     }
     __syncthreads();
   }
 }
 
-// Z = R^{-1} for upper triangular R (n x n); Z is written upper triangular
-// with zeros below the diagonal.
-__global__ __launch_bounds__(kLaThreads) void triinv_kernel(const double2 *R, double2 *Z, int n) {
-  const int t = threadIdx.x;
-  for (long e = t; e < (long)n * n; e += kLaThreads) Z[e] = make_double2(0.0, 0.0);
-  __syncthreads();
-  for (int j = 0; j < n; ++j) {
-    const double2 rjj = R[(long)j * n + j];
-    // Z_ij = -(sum_{i <= k < j} Z_ik R_kj) / R_jj for i < j, Z_jj = 1 / R_jj
-    for (int i = t; i <= j; i += kLaThreads) {
-      if (i == j) {
-        Z[(long)j * n + j] = cdiv(make_double2(1.0, 0.0), rjj);
-      } else {
-        double2 s = make_double2(0.0, 0.0);
-        for (int k = i; k < j; ++k) cfma(s, Z[(long)i * n + k], R[(long)k * n + j]);
-        Z[(long)i * n + j] = cdiv(make_double2(-s.x, -s.y), rjj);
-      }
-    }
-    __syncthreads();
-  }
-}
-
-// E = [M | I] (n x 2n, leading dim 2n) -> [I | M^{-1}] up to row order:
-// Gauss-Jordan with partial pivoting, rows swapped explicitly.
-__global__ __launch_bounds__(kLaThreads) void cgj_kernel(double2 *E, int n,
-                                                         unsigned long long *stats) {
-  __shared__ double2 fac[1024];
-  __shared__ double best[kLaThreads / 64];
-  __shared__ int bidx[kLaThreads / 64];
+// One Gauss-Jordan step (pivot column j) on E = [A | B] (n x 2n, leading
+// dim ld), spread over workgroups of 64 columns each.  colin holds column j
+// as left by step j - 1; every workgroup finds the same pivot in it (largest
+// modulus over rows >= j, ties to the smaller row), the rows j and p are
+// swapped, row j is divided by the pivot and column j is eliminated from
+// every other row.  The workgroup that owns column j + 1 writes that column,
+// as this step leaves it, to colout for the next step.  Columns left of j
+// are unit vectors already and are skipped.
+constexpr int kGjCols = 64;
+__global__ __launch_bounds__(256) void gj_step_kernel(double2 *E, long ld, int n, int j,
+                                                      const double2 *colin, double2 *colout,
+                                                      unsigned long long *stats) {
+  __shared__ double2 col[1024];
+  __shared__ double wbest[4];
+  __shared__ int wbi[4];
   __shared__ int piv;
+  __shared__ double2 rjv[kGjCols], vpv[kGjCols];
+  const int c0 = blockIdx.x * kGjCols;
+  if (c0 + kGjCols <= j) return;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const long ld = 2L * n;
-  for (int j = 0; j < n; ++j) {
-    // pivot: largest |E_rj| over r >= j (ties: smallest r)
-    double bv = -1.0;
-    int bi = n;
-    for (int r = j + t; r < n; r += kLaThreads) {
-      const double2 v = E[(long)r * ld + j];
-      const double a = hypot(v.x, v.y);
-      if (a > bv) { bv = a; bi = r; }
-    }
-    for (int off = 32; off > 0; off >>= 1) {
-      const double ov = __shfl_down(bv, off, 64);
-      const int oi = __shfl_down(bi, off, 64);
-      if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
-    }
-    if (lane == 0) { best[wave] = bv; bidx[wave] = bi; }
-    __syncthreads();
-    if (t == 0) {
-      double b = -1.0;
-      int p = n;
-      for (int w = 0; w < kLaThreads / 64; ++w)
-        if (best[w] > b || (best[w] == b && bidx[w] < p)) { b = best[w]; p = bidx[w]; }
-      piv = (b > 0.0 && isfinite(b)) ? p : -1;
-      if (piv < 0) stats[kStError] |= kErrSingular;
-    }
-    __syncthreads();
-    const int p = piv;
-    if (p < 0) return;
-    // swap rows j and p, then scale row j by 1 / E_jj
-    if (p != j)
-      for (int c = t; c < 2 * n; c += kLaThreads) {
-        const double2 a = E[(long)j * ld + c];
-        E[(long)j * ld + c] = E[(long)p * ld + c];
-        E[(long)p * ld + c] = a;
-      }
-    __syncthreads();
-    const double2 d = E[(long)j * ld + j];
-    __syncthreads();
-    for (int c = t; c < 2 * n; c += kLaThreads)
-      E[(long)j * ld + c] = cdiv(E[(long)j * ld + c], d);
-    for (int r = t; r < n; r += kLaThreads) fac[r] = E[(long)r * ld + j];
-    __syncthreads();
-    // eliminate column j from every other row
-    const long tot = (long)n * (2 * n - j);
-    for (long e = t; e < tot; e += kLaThreads) {
-      const int r = (int)(e / (2 * n - j)), c = j + (int)(e % (2 * n - j));
-      if (r == j) continue;
-      double2 &x = E[(long)r * ld + c];
-      x = csub(x, cmul(fac[r], E[(long)j * ld + c]));
-    }
-    __syncthreads();
+  for (int r = t; r < n; r += 256) col[r] = colin[r];
+  __syncthreads();
+  double bv = -1.0;
+  int bi = n;
+  for (int r = j + t; r < n; r += 256) {
+    const double a = hypot(col[r].x, col[r].y);
+    if (a > bv) { bv = a; bi = r; }
   }
+  for (int off = 32; off > 0; off >>= 1) {
+    const double ov = __shfl_down(bv, off, 64);
+    const int oi = __shfl_down(bi, off, 64);
+    if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+  }
+  if (lane == 0) { wbest[wave] = bv; wbi[wave] = bi; }
+  __syncthreads();
+  if (t == 0) {
+    double b = -1.0;
+    int p = n;
+    for (int w = 0; w < 4; ++w)
+      if (wbest[w] > b || (wbest[w] == b && wbi[w] < p)) { b = wbest[w]; p = wbi[w]; }
+    piv = (b > 0.0 && isfinite(b)) ? p : -1;
+    if (piv < 0 && blockIdx.x == 0) stats[kStError] |= kErrSingular;
+  }
+  __syncthreads();
+  const int p = piv;
+  if (p < 0) return;
+  const double2 d = col[p];
+  const int cl = t & (kGjCols - 1), rg = t >> 6;
+  const int c = c0 + cl;
+  const bool live = c < 2 * n && (c >= j || c >= n);
+  if (rg == 0 && live) {
+    const double2 vj = E[(long)p * ld + c], vp = E[(long)j * ld + c];
+    const double2 rj = cdiv(vj, d);
+    rjv[cl] = rj;
+    vpv[cl] = vp;
+    E[(long)j * ld + c] = rj;
+    if (c == j + 1) colout[j] = rj;
+  }
+  __syncthreads();
+  if (!live) return;
+  const double2 rj = rjv[cl];
+  for (int r = rg; r < n; r += 4) {
+    if (r == j) continue;
+    const double2 f = (r == p) ? col[j] : col[r];
+    const double2 v = (r == p) ? vpv[cl] : E[(long)r * ld + c];
+    const double2 x = csub(v, cmul(f, rj));
+    E[(long)r * ld + c] = x;
+    if (c == j + 1) colout[r] = x;
+  }
+}
+
+// colout[r] = E[r][0]
+__global__ __launch_bounds__(256) void col0_kernel(const double2 *E, long ld, int n,
+                                                   double2 *colout) {
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  if (r < n) colout[r] = E[(long)r * ld];
 }
 
 // --------------------------------------------------------------- decisions
@@ -476,20 +470,21 @@ hipError_t set_identity(double2 *E, long ld, int n, int off, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t cholesky(double2 *S, int n, unsigned long long *stats, hipStream_t st) {
+hipError_t cholesky(double2 *S, long ld, int n, unsigned long long *stats, hipStream_t st) {
   if (n > 1024) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(chol_kernel, dim3(1), dim3(kLaThreads), 0, st, S, n, stats);
+  hipLaunchKernelGGL(chol_kernel, dim3(1), dim3(kLaThreads), 0, st, S, ld, n, stats);
   return hipGetLastError();
 }
 
-hipError_t tri_inverse(const double2 *R, double2 *Z, int n, hipStream_t st) {
-  hipLaunchKernelGGL(triinv_kernel, dim3(1), dim3(kLaThreads), 0, st, R, Z, n);
-  return hipGetLastError();
-}
-
-hipError_t gj_inverse(double2 *E, int n, unsigned long long *stats, hipStream_t st) {
-  if (n > 1024) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(cgj_kernel, dim3(1), dim3(kLaThreads), 0, st, E, n, stats);
+hipError_t gj_inverse(double2 *E, long ld, int n, double2 *colbuf, unsigned long long *stats,
+                      hipStream_t st) {
+  if (n < 1 || n > 1024) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(col0_kernel, dim3((n + 255) / 256), dim3(256), 0, st, E, ld, n, colbuf);
+  const dim3 grid((2 * n + kGjCols - 1) / kGjCols);
+  for (int j = 0; j < n; ++j) {
+    hipLaunchKernelGGL(gj_step_kernel, grid, dim3(256), 0, st, E, ld, n, j,
+                       colbuf + (size_t)(j & 1) * n, colbuf + (size_t)((j + 1) & 1) * n, stats);
+  }
   return hipGetLastError();
 }
 

@@ -39,12 +39,13 @@ hipError_t rotate_rows(const double2 *X, long ldx, double2 *Y, long ldy, int nco
 hipError_t conj_copy(const double2 *X, double2 *Y, long n, hipStream_t st);
 // E[r][off + c] = (r == c), r, c < n
 hipError_t set_identity(double2 *E, long ld, int n, int off, hipStream_t st);
-// upper triangle of S (n x n, Hermitian positive definite) <- R, S = R^H R
-hipError_t cholesky(double2 *S, int n, unsigned long long *stats, hipStream_t st);
-// Z = R^{-1}, R upper triangular (n x n)
-hipError_t tri_inverse(const double2 *R, double2 *Z, int n, hipStream_t st);
-// E = [M | I] (n x 2n) -> [I | M^{-1}], n <= 1024
-hipError_t gj_inverse(double2 *E, int n, unsigned long long *stats, hipStream_t st);
+// upper triangle of S (n x n, leading dim ld, Hermitian positive definite)
+// <- R with S = R^H R; strict lower triangle <- 0
+hipError_t cholesky(double2 *S, long ld, int n, unsigned long long *stats, hipStream_t st);
+// E = [M | I] (n x 2n, leading dim ld) -> [I | M^{-1}] by Gauss-Jordan with
+// partial pivoting, one launch per pivot column; colbuf: 2n scratch; n <= 1024
+hipError_t gj_inverse(double2 *E, long ld, int n, double2 *colbuf, unsigned long long *stats,
+                      hipStream_t st);
 
 constexpr int kSocMaxK = 32;   // group size of the decision kernel (2k x 2k in LDS)
 struct SocDecideArgs {

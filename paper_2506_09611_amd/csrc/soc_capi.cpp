@@ -30,7 +30,7 @@ struct pqmc_soc_ctx {
   double2 *E = nullptr;                             // ne x 2ne: [U_L U_R | I] -> [I | T]
   double2 *T = nullptr;                             // = E + ne, leading dim 2 ne
   long ldT = 0;
-  double2 *S = nullptr, *Z = nullptr;               // ne x ne: Gram / Cholesky, R^{-1}
+  double2 *colbuf = nullptr;                        // 2 ne: Gauss-Jordan pivot columns
   double2 *P2 = nullptr, *P1 = nullptr, *W0 = nullptr, *D = nullptr, *Q = nullptr;
   double2 *Tay0 = nullptr, *Tay1 = nullptr;         // n2 x n2 (set-up, then G)
   int *nflush = nullptr;
@@ -138,8 +138,7 @@ void layout(pqmc_soc_ctx &c, char *base, size_t *bytes) {
   c.E = cv.take<double2>(ne * 2 * ne);
   c.T = c.E ? c.E + ne : nullptr;
   c.ldT = 2L * (long)ne;
-  c.S = cv.take<double2>(ne * ne);
-  c.Z = cv.take<double2>(ne * ne);
+  c.colbuf = cv.take<double2>(2 * ne);
   c.P2 = cv.take<double2>(kn * ne);
   c.P1 = cv.take<double2>(ne * kn);
   c.W0 = cv.take<double2>(kn * kn);
@@ -169,8 +168,8 @@ int gemm1(const CgemmDesc &d, int opA, int opB, hipStream_t st) {
   return PQMC_OK;
 }
 
-// e^{scale H0} (Taylor of degree 18 after scaling by 2^-sq, then sq squarings),
-// H0 uploaded in Tay0... the result in dst; Tay0 holds H0 throughout.
+// dst = e^{scale H0}: Taylor series of degree 18 in Horner form for the
+// scaled exponent, then sq squarings.  H0 sits in Tay0 (kept); Tay1 is scratch.
 int expm(pqmc_soc_ctx &c, double scale, int sq, double2 *dst) {
   const int n = c.n2;
   double2 *Y = dst, *Yn = c.Tay1;
@@ -195,22 +194,25 @@ int expm(pqmc_soc_ctx &c, double scale, int sq, double2 *dst) {
 }
 
 // dst = A R^{-1} with A^H A = R^H R (A: n2 x ne): columns orthonormalised.
+// E serves as scratch: [A^H A | I] -> [R | I] -> [I | R^{-1}].
 int orthonormalize(pqmc_soc_ctx &c, const double2 *A, double2 *dst) {
   const int n2 = c.n2, ne = c.ne;
-  int rc = gemm1(cdesc(A, ne, A, ne, c.S, ne, ne, ne, n2), kOpH, kOpN, c.st);
+  const long ld = 2L * ne;
+  int rc = gemm1(cdesc(A, ne, A, ne, c.E, ld, ne, ne, n2), kOpH, kOpN, c.st);
   if (rc) return rc;
-  PQ_HIP_CHECK(cholesky(c.S, ne, c.stats, c.st));
-  PQ_HIP_CHECK(tri_inverse(c.S, c.Z, ne, c.st));
-  return gemm1(cdesc(A, ne, c.Z, ne, dst, ne, n2, ne, ne), kOpN, kOpN, c.st);
+  PQ_HIP_CHECK(cholesky(c.E, ld, ne, c.stats, c.st));
+  PQ_HIP_CHECK(set_identity(c.E, ld, ne, ne, c.st));
+  PQ_HIP_CHECK(gj_inverse(c.E, ld, ne, c.colbuf, c.stats, c.st));
+  return gemm1(cdesc(A, ne, c.E + ne, ld, dst, ne, n2, ne, ne), kOpN, kOpN, c.st);
 }
 
-// T = (U_L U_R)^{-1} = (ULt^T UR)^{-1}
+// T = (U_L U_R)^{-1} = (ULt^T UR)^{-1}, in the right half of E
 int refresh_T(pqmc_soc_ctx &c) {
   const int n2 = c.n2, ne = c.ne;
   int rc = gemm1(cdesc(c.ULt, ne, c.UR, ne, c.E, 2L * ne, ne, ne, n2), kOpT, kOpN, c.st);
   if (rc) return rc;
   PQ_HIP_CHECK(set_identity(c.E, 2L * ne, ne, ne, c.st));
-  PQ_HIP_CHECK(gj_inverse(c.E, ne, c.stats, c.st));
+  PQ_HIP_CHECK(gj_inverse(c.E, 2L * ne, ne, c.colbuf, c.stats, c.st));
   return PQMC_OK;
 }
 

@@ -80,3 +80,32 @@ def test_create_rejects_bad_workspace_without_touching_gpu():
     assert lib.pqmc_create(ctypes.byref(pr), ctypes.byref(o), None, None, 0, ctypes.byref(h)) == -1
     assert lib.pqmc_create(ctypes.byref(pr), ctypes.byref(o), None, ctypes.c_void_p(257), 1 << 30,
                            ctypes.byref(h)) == -1
+
+
+def _soc_ws(U=-4.0, scheme=1, k=16, flags=0, hop=None, ne=14):
+    import synth
+    p = synth.make_soc_problem(4, 14, -4.0, seed=synth.SEED_BASE + 95)
+    H = np.ascontiguousarray(p.hopping if hop is None else hop, dtype=np.complex128)
+    P = np.ascontiguousarray(p.trial, dtype=np.complex128)
+    pr = binding.SocProblem(16, ne, H.view(np.float64).ctypes.data_as(
+        ctypes.POINTER(ctypes.c_double)), P.view(np.float64).ctypes.data_as(
+        ctypes.POINTER(ctypes.c_double)), U, 0.05, 20, 5, 1, 0)
+    lib = binding.load_library()
+    n = ctypes.c_size_t(0)
+    o = binding.UpdateOpts(scheme, k, 1, flags)
+    return lib.pqmc_soc_workspace_bytes(ctypes.byref(pr), ctypes.byref(o), ctypes.byref(n)), n.value
+
+
+def test_soc_workspace_bytes_and_rejections():
+    st, n = _soc_ws()
+    assert st == 0 and n > 0
+    st2, n2 = _soc_ws(flags=binding.FLAG_LOG)
+    assert st2 == 0 and n2 > n
+    assert _soc_ws(U=1.0)[0] == -1                  # the spin-s^y decoupling needs U <= 0
+    assert _soc_ws(scheme=2)[0] == -1               # no block force bias on this path
+    assert _soc_ws(k=33)[0] == -1
+    assert _soc_ws(flags=binding.FLAG_FP32)[0] == -1
+    assert _soc_ws(ne=33)[0] == -1                  # more fermions than orbitals
+    bad = np.zeros((32, 32), np.complex128)
+    bad[0, 1] = 1j                                  # not Hermitian
+    assert _soc_ws(hop=bad)[0] == -1
