@@ -221,7 +221,8 @@ def soc_leg(args):
                                    stab_every=args.soc_window, perturb=1e-3,
                                    seed=synth.SEED_BASE + 600 + L)
         base = None
-        for k in [1] + [int(x) for x in args.soc_k.split(",") if x]:
+        ks = [int(x) for x in args.soc_k.split(",") if x]
+        for k in ([] if args.soc_skip_local else [1]) + ks:
             sc = Scheme.LOCAL if k == 1 else Scheme.DELAYED
             c = SocChain(p.hopping, p.trial, p.U, p.dtau, p.n_slices, p.stab_every, p.seed,
                          scheme=sc, k=k, timing=True)
@@ -237,10 +238,12 @@ def soc_leg(args):
                    "acceptance": st["accepted"] / max(1, st["proposed"])}
             if k == 1:
                 base = row
-            row["speedup_vs_local"] = row["field_updates_per_s"] / base["field_updates_per_s"]
-            row["update_speedup_vs_local"] = (row["update_only"] / base["update_only"]
-                                              if row["update_only"] and base["update_only"]
-                                              else None)
+            if base is not None:
+                row["speedup_vs_local"] = (row["field_updates_per_s"]
+                                           / base["field_updates_per_s"])
+                row["update_speedup_vs_local"] = (row["update_only"] / base["update_only"]
+                                                  if row["update_only"] and base["update_only"]
+                                                  else None)
             log("soc", row)
             rows.append(row)
             c.close()
@@ -329,6 +332,8 @@ def main():
     ap.add_argument("--soc-sizes", default="8,16,24",
                     help="lattice sides of the SOC-Hubbard table ('' for none)")
     ap.add_argument("--soc-k", default="8,16,32", help="delay ranks of the SOC table")
+    ap.add_argument("--soc-skip-local", action="store_true",
+                    help="leave the local update out of the SOC table (profiling runs)")
     ap.add_argument("--soc-window", type=int, default=10,
                     help="forward slice visits per SOC table entry (also k_tau)")
     ap.add_argument("--serve-jobs", type=int, default=32,

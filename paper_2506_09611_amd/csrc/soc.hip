@@ -55,13 +55,22 @@ __device__ __forceinline__ double2 op_load(const double2 *A, long ld, int r, int
 }
 
 template <int OPA, int OPB>
-__global__ __launch_bounds__(256) void cgemm_kernel(CgemmBatch b) {
-  const CgemmDesc &g = b.d[blockIdx.z];
+__global__ __launch_bounds__(256) void cgemm_kernel(CgemmBatch b, int ns) {
+  const CgemmDesc &g = b.d[blockIdx.z / ns];
+  const int split = blockIdx.z % ns;
   int K = g.K;
   if (g.Kdev) K = min(K, *g.Kdev);
   const int M = g.M, N = g.N;
   const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
   if (m0 >= M || n0 >= N) return;
+  int kbeg = 0, kend = K;
+  if (g.ksplit > 0) {
+    kbeg = split * g.ksplit;
+    kend = min(K, kbeg + g.ksplit);
+    if (kbeg >= K) return;   // this product has fewer slices
+  } else if (split > 0) {
+    return;
+  }
   if (K <= 0 && g.Kdev && g.beta.x == 1.0 && g.beta.y == 0.0 && g.Cin == g.C && !g.addI) return;
   __shared__ double2 As[BK][BM];
   __shared__ double2 Bs[BK][BN];
@@ -71,20 +80,20 @@ __global__ __launch_bounds__(256) void cgemm_kernel(CgemmBatch b) {
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = make_double2(0.0, 0.0);
-  for (int k0 = 0; k0 < K; k0 += BK) {
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
       const int e = t + 256 * p;
       int r, kk;
       if (OPA == kOpN) { r = e >> 4; kk = e & 15; } else { kk = e >> 6; r = e & 63; }
       const int gr = m0 + r, gk = k0 + kk;
-      As[kk][r] = (gr < M && gk < K) ? op_load<OPA>(g.A, g.lda, gr, gk) : make_double2(0.0, 0.0);
+      As[kk][r] = (gr < M && gk < kend) ? op_load<OPA>(g.A, g.lda, gr, gk) : make_double2(0.0, 0.0);
       int c, kb;
       if (OPB == kOpN) { kb = e >> 6; c = e & 63; } else { c = e >> 4; kb = e & 15; }
       const int gc = n0 + c, gkb = k0 + kb;
       // element (k, c) of op(B): N -> B[k][c], T -> B[c][k], H -> conj(B[c][k])
       double2 v = make_double2(0.0, 0.0);
-      if (gc < N && gkb < K) {
+      if (gc < N && gkb < kend) {
         if (OPB == kOpN) v = g.B[(long)gkb * g.ldb + gc];
         else {
           v = g.B[(long)gc * g.ldb + gkb];
@@ -108,6 +117,17 @@ __global__ __launch_bounds__(256) void cgemm_kernel(CgemmBatch b) {
     }
     __syncthreads();
   }
+  if (g.ksplit > 0) {
+    double2 *C = g.C + (long)split * g.csplit;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int r = m0 + ty + 16 * i, c = n0 + tx + 16 * j;
+        if (r < M && c < N) C[(long)r * g.ldc + c] = acc[i][j];
+      }
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -121,6 +141,16 @@ __global__ __launch_bounds__(256) void cgemm_kernel(CgemmBatch b) {
         g.C[(long)r * g.ldc + c] = v;
       }
     }
+}
+
+__global__ __launch_bounds__(256) void csum_kernel(CsumBatch b) {
+  const CsumDesc &d = b.d[blockIdx.y];
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (long)d.M * d.N) return;
+  const int r = (int)(e / d.N), c = (int)(e % d.N);
+  double2 s = make_double2(0.0, 0.0);
+  for (int q = 0; q < d.ns; ++q) s = cadd(s, d.part[q * d.csplit + (long)r * d.ldp + c]);
+  d.dst[(long)r * d.ldd + c] = s;
 }
 
 // ------------------------------------------------------------- rotations
@@ -181,13 +211,14 @@ __global__ __launch_bounds__(kLaThreads) void chol_kernel(double2 *S, long ld, i
     for (int r = j + 1 + t; r < n; r += kLaThreads) S[(long)r * ld + j] = make_double2(0.0, 0.0);
     __syncthreads();
     // trailing update of the upper triangle: S_rc -= conj(R_jr) R_jc, r <= c
-    const int m = n - j - 1;
-    const long tot = (long)m * m;
-    for (long e = t; e < tot; e += kLaThreads) {
-      const int r = j + 1 + (int)(e / m), c = j + 1 + (int)(e % m);
-      if (c < r) continue;
-      double2 &x = S[(long)r * ld + c];
-      x = csub(x, cmul(cconj(rowj[r]), rowj[c]));
+    // (one wave per row, lanes along the row)
+    const int lane = t & 63, wave = t >> 6;
+    for (int r = j + 1 + wave; r < n; r += kLaThreads / 64) {
+      const double2 a = cconj(rowj[r]);
+      for (int c = r + lane; c < n; c += 64) {
+        double2 &x = S[(long)r * ld + c];
+        x = csub(x, cmul(a, rowj[c]));
+      }
     }
     __syncthreads();
   }
@@ -198,10 +229,11 @@ __global__ __launch_bounds__(kLaThreads) void chol_kernel(double2 *S, long ld, i
 // as left by step j - 1; every workgroup finds the same pivot in it (largest
 // modulus over rows >= j, ties to the smaller row), the rows j and p are
 // swapped, row j is divided by the pivot and column j is eliminated from
-// every other row.  The workgroup that owns column j + 1 writes that column,
+// every other row (8 columns per workgroup, so that a 1024-pivot inverse
+// spreads over 256 workgroups).  The workgroup that owns column j + 1 writes that column,
 // as this step leaves it, to colout for the next step.  Columns left of j
 // are unit vectors already and are skipped.
-constexpr int kGjCols = 64;
+constexpr int kGjCols = 8;    // columns per workgroup (256 threads: 32 row groups)
 __global__ __launch_bounds__(256) void gj_step_kernel(double2 *E, long ld, int n, int j,
                                                       const double2 *colin, double2 *colout,
                                                       unsigned long long *stats) {
@@ -240,7 +272,8 @@ __global__ __launch_bounds__(256) void gj_step_kernel(double2 *E, long ld, int n
   const int p = piv;
   if (p < 0) return;
   const double2 d = col[p];
-  const int cl = t & (kGjCols - 1), rg = t >> 6;
+  const int cl = t & (kGjCols - 1), rg = t / kGjCols;
+  constexpr int kRowGroups = 256 / kGjCols;
   const int c = c0 + cl;
   const bool live = c < 2 * n && (c >= j || c >= n);
   if (rg == 0 && live) {
@@ -254,7 +287,7 @@ __global__ __launch_bounds__(256) void gj_step_kernel(double2 *E, long ld, int n
   __syncthreads();
   if (!live) return;
   const double2 rj = rjv[cl];
-  for (int r = rg; r < n; r += 4) {
+  for (int r = rg; r < n; r += kRowGroups) {
     if (r == j) continue;
     const double2 f = (r == p) ? col[j] : col[r];
     const double2 v = (r == p) ? vpv[cl] : E[(long)r * ld + c];
@@ -289,8 +322,10 @@ __global__ __launch_bounds__(kDecThreads) void soc_decide_kernel(SocDecideArgs a
   double2 *u = Mc + n * n;           // n x 2: Mc W0[:, jc]
   double2 *w = u + 2 * n;            // 2 x n: W0[jr, :] Mc
   __shared__ double2 Sinv[4];
+  __shared__ double2 Sm[4];
   __shared__ int accs;
   __shared__ double xs[64];
+  __shared__ int accm[64];
   __shared__ int n_acc;
   const int t = threadIdx.x;
   int8_t *xrow = a.fields + (long)a.li * a.N + a.g0;
@@ -326,18 +361,27 @@ __global__ __launch_bounds__(kDecThreads) void soc_decide_kernel(SocDecideArgs a
       w[q * n + c] = s;
     }
     __syncthreads();
+    // S = 1 + W0[jr, jc] - W0[jr, :] u  (the current 1 + W_j T V_j): wave q
+    // forms entry (q / 2, q % 2), one product per lane, then a shuffle sum
+    {
+      const int q = t >> 6, lane = t & 63;
+      const int p = q >> 1, qq = q & 1;
+      const int row = p ? c1 : c0;
+      double2 prod = make_double2(0.0, 0.0);
+      if (lane < n) prod = cmul(W0[row * n + lane], u[lane * 2 + qq]);
+      for (int off = 32; off > 0; off >>= 1) {
+        prod.x += __shfl_down(prod.x, off, 64);
+        prod.y += __shfl_down(prod.y, off, 64);
+      }
+      if (lane == 0) {
+        double2 v = csub(W0[row * n + (qq ? c1 : c0)], prod);
+        if (p == qq) v.x += 1.0;
+        Sm[q] = v;
+      }
+    }
+    __syncthreads();
     if (t == 0) {
-      // S = 1 + W0[jr, jc] - W0[jr, :] u   (the current 1 + W_j T V_j)
-      double2 S[2][2];
-      for (int p = 0; p < 2; ++p)
-        for (int q = 0; q < 2; ++q) {
-          double2 s = W0[(p ? c1 : c0) * n + (q ? c1 : c0)];
-          double2 corr = make_double2(0.0, 0.0);
-          for (int b = 0; b < n; ++b) cfma(corr, W0[(p ? c1 : c0) * n + b], u[b * 2 + q]);
-          s = csub(s, corr);
-          if (p == q) s.x += 1.0;
-          S[p][q] = s;
-        }
+      double2 S[2][2] = {{Sm[0], Sm[1]}, {Sm[2], Sm[3]}};
       const double2 R = csub(cmul(S[0][0], S[1][1]), cmul(S[0][1], S[1][0]));
       const double absR = hypot(R.x, R.y);
       const int site = a.g0 + j;
@@ -368,6 +412,7 @@ __global__ __launch_bounds__(kDecThreads) void soc_decide_kernel(SocDecideArgs a
         n_acc += 1;
       }
       accs = acc ? 1 : 0;
+      accm[j] = accs;
     }
     __syncthreads();
     if (accs) {
@@ -385,17 +430,21 @@ __global__ __launch_bounds__(kDecThreads) void soc_decide_kernel(SocDecideArgs a
         cfma(v, l1, cmul(Sinv[3], r1));
         Mc[e] = v;
       }
-      // rows (site, N + site) of U_R <- (1 + delta) rows
-      const double x = xs[j];
-      const double d00 = 1.0 + a.dd, d01 = -x * a.doff, d10 = x * a.doff, d11 = 1.0 + a.dd;
-      double2 *p0 = a.UR + (long)(a.g0 + j) * a.ne, *p1 = a.UR + (long)(a.N + a.g0 + j) * a.ne;
-      for (int c = t; c < a.ne; c += kDecThreads) {
-        const double2 r0 = p0[c], r1 = p1[c];
-        p0[c] = make_double2(d00 * r0.x + d01 * r1.x, d00 * r0.y + d01 * r1.y);
-        p1[c] = make_double2(d10 * r0.x + d11 * r1.x, d10 * r0.y + d11 * r1.y);
-      }
     }
     __syncthreads();
+  }
+  // rows (site, N + site) of U_R <- (1 + delta) rows for the accepted sites
+  // (no later decision of the group reads them)
+  for (int j = 0; j < kk; ++j) {
+    if (!accm[j]) continue;
+    const double x = xs[j];
+    const double d00 = 1.0 + a.dd, d01 = -x * a.doff, d10 = x * a.doff, d11 = 1.0 + a.dd;
+    double2 *p0 = a.UR + (long)(a.g0 + j) * a.ne, *p1 = a.UR + (long)(a.N + a.g0 + j) * a.ne;
+    for (int c = t; c < a.ne; c += kDecThreads) {
+      const double2 r0 = p0[c], r1 = p1[c];
+      p0[c] = make_double2(d00 * r0.x + d01 * r1.x, d00 * r0.y + d01 * r1.y);
+      p1[c] = make_double2(d10 * r0.x + d11 * r1.x, d10 * r0.y + d11 * r1.y);
+    }
   }
   // D = delta_bd Mc (rows (j, kk + j) of Mc mixed by the pre-flip delta_j)
   for (int e = t; e < kk * n; e += kDecThreads) {
@@ -422,10 +471,13 @@ hipError_t cgemm(const CgemmBatch &b, int opA, int opB, hipStream_t st) {
     nt = max(nt, (b.d[i].N + BN - 1) / BN);
   }
   if (mt == 0 || nt == 0) return hipSuccess;
-  const dim3 grid(nt, mt, b.count);
+  int ns = 1;
+  for (int i = 0; i < b.count; ++i)
+    if (b.d[i].ksplit > 0) ns = max(ns, (b.d[i].K + b.d[i].ksplit - 1) / b.d[i].ksplit);
+  const dim3 grid(nt, mt, b.count * ns);
 #define PQ_CG(A_, B_)                                                                  \
   if (opA == A_ && opB == B_) {                                                        \
-    hipLaunchKernelGGL((cgemm_kernel<A_, B_>), grid, dim3(256), 0, st, b);              \
+    hipLaunchKernelGGL((cgemm_kernel<A_, B_>), grid, dim3(256), 0, st, b, ns);          \
     return hipGetLastError();                                                          \
   }
   PQ_CG(kOpN, kOpN)
@@ -434,6 +486,16 @@ hipError_t cgemm(const CgemmBatch &b, int opA, int opB, hipStream_t st) {
   PQ_CG(kOpH, kOpN)
 #undef PQ_CG
   return hipErrorInvalidValue;
+}
+
+hipError_t csum(const CsumBatch &b, hipStream_t st) {
+  if (b.count <= 0) return hipSuccess;
+  if (b.count > kCgemmMaxBatch) return hipErrorInvalidValue;
+  long mx = 0;
+  for (int i = 0; i < b.count; ++i) mx = max(mx, (long)b.d[i].M * b.d[i].N);
+  if (mx == 0) return hipSuccess;
+  hipLaunchKernelGGL(csum_kernel, dim3((unsigned)((mx + 255) / 256), b.count), dim3(256), 0, st, b);
+  return hipGetLastError();
 }
 
 CgemmDesc cdesc(const double2 *A, long lda, const double2 *B, long ldb, double2 *C, long ldc,

@@ -11,6 +11,8 @@ enum { kOpN = 0, kOpT = 1, kOpH = 2 };   // op(X) = X, X^T, X^H
 // C = alpha op(A) op(B) + beta Cin (+ I when addI), op(A) M x K, op(B) K x N;
 // row-major complex128.  Kdev (optional): K = min(K, *Kdev), and a product
 // with K = 0, beta = 1, Cin = C does nothing.
+// Split-K: when ksplit > 0, slice s of the depth, [s ksplit, (s + 1) ksplit),
+// is written raw (no alpha, beta, I) to C + s csplit; csum adds the slices.
 struct CgemmDesc {
   const double2 *A, *B, *Cin;
   double2 *C;
@@ -19,12 +21,27 @@ struct CgemmDesc {
   const int *Kdev;
   double2 alpha, beta;
   int addI;
+  int ksplit;
+  long csplit;
 };
 constexpr int kCgemmMaxBatch = 8;
 struct CgemmBatch {
   CgemmDesc d[kCgemmMaxBatch];
   int count;
 };
+// dst[r][c] = sum_{s < ns} part[s csplit + r ldp + c], slices added in order
+struct CsumDesc {
+  const double2 *part;
+  long csplit, ldp;
+  double2 *dst;
+  long ldd;
+  int M, N, ns;
+};
+struct CsumBatch {
+  CsumDesc d[kCgemmMaxBatch];
+  int count;
+};
+hipError_t csum(const CsumBatch &b, hipStream_t st);
 CgemmDesc cdesc(const double2 *A, long lda, const double2 *B, long ldb, double2 *C, long ldc,
                 int M, int N, int K);
 // op pairs supported: (N, N), (N, T), (T, N), (H, N)

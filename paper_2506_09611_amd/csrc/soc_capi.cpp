@@ -32,6 +32,8 @@ struct pqmc_soc_ctx {
   long ldT = 0;
   double2 *colbuf = nullptr;                        // 2 ne: Gauss-Jordan pivot columns
   double2 *P2 = nullptr, *P1 = nullptr, *W0 = nullptr, *D = nullptr, *Q = nullptr;
+  double2 *P2part = nullptr, *P1part = nullptr, *W0part = nullptr;   // split-K slices
+  int ksplit = 0;                                   // depth per slice (0: no split)
   double2 *Tay0 = nullptr, *Tay1 = nullptr;         // n2 x n2 (set-up, then G)
   int *nflush = nullptr;
   int8_t *fields = nullptr;
@@ -106,6 +108,8 @@ void fill(pqmc_soc_ctx &c, const pqmc_soc_problem *p, const pqmc_update_opts *o)
   c.walker = p->walker_id;
   c.opts = *o;
   c.k = o->scheme == PQMC_DELAYED ? std::min(o->delay_k, c.N) : 1;
+  // panels over the depth N_e in at most 8 slices of >= 64 (none below 128)
+  c.ksplit = c.ne <= 128 ? 0 : std::max(64, ((c.ne + 7) / 8 + 15) / 16 * 16);
 }
 
 struct Carve {
@@ -144,6 +148,12 @@ void layout(pqmc_soc_ctx &c, char *base, size_t *bytes) {
   c.W0 = cv.take<double2>(kn * kn);
   c.D = cv.take<double2>(kn * kn);
   c.Q = cv.take<double2>(ne * kn);
+  if (c.ksplit > 0) {
+    const size_t ns = (ne + c.ksplit - 1) / c.ksplit;
+    c.P2part = cv.take<double2>(ns * kn * ne);
+    c.P1part = cv.take<double2>(ns * ne * kn);
+    c.W0part = cv.take<double2>(ns * kn * kn);
+  }
   c.nflush = cv.take<int>(4);
   c.fields = cv.take<int8_t>((size_t)c.M * c.N);
   c.stats = cv.take<unsigned long long>(16);
@@ -299,16 +309,42 @@ int update_slice(pqmc_soc_ctx &c, int l, int dir) {
     const int kk = std::min(c.k, N - g0), n = 2 * kk;
     const double2 *ur0 = c.UR + (size_t)g0 * ne, *ur1 = c.UR + (size_t)(N + g0) * ne;
     const double2 *ul0 = c.ULt + (size_t)g0 * ne, *ul1 = c.ULt + (size_t)(N + g0) * ne;
+    // P2 = W_g T; then P1 = T U_L[:, g] and W0' = P2 U_L[:, g].  Over a deep
+    // N_e the products run as split-K slices, added in order by csum.
+    const bool split = c.ksplit > 0;
+    const int ns = split ? (ne + c.ksplit - 1) / c.ksplit : 1;
+    const long s2 = (long)n * ne, s1 = (long)ne * n, sw = (long)n * n;
+    double2 *p2 = split ? c.P2part : c.P2, *p1 = split ? c.P1part : c.P1;
+    double2 *w0 = split ? c.W0part : c.W0;
     CgemmBatch a{};
-    a.d[a.count++] = cdesc(ur0, ne, c.T, c.ldT, c.P2, ne, kk, ne, ne);
-    a.d[a.count++] = cdesc(ur1, ne, c.T, c.ldT, c.P2 + (size_t)kk * ne, ne, kk, ne, ne);
+    a.d[a.count++] = cdesc(ur0, ne, c.T, c.ldT, p2, ne, kk, ne, ne);
+    a.d[a.count++] = cdesc(ur1, ne, c.T, c.ldT, p2 + (size_t)kk * ne, ne, kk, ne, ne);
+    for (int i = 0; i < a.count && split; ++i) {
+      a.d[i].ksplit = c.ksplit;
+      a.d[i].csplit = s2;
+    }
     PQ_HIP_CHECK(cgemm(a, kOpN, kOpN, c.st));
+    if (split) {
+      CsumBatch r{};
+      r.d[r.count++] = CsumDesc{c.P2part, s2, ne, c.P2, ne, n, ne, ns};
+      PQ_HIP_CHECK(csum(r, c.st));
+    }
     CgemmBatch b{};
-    b.d[b.count++] = cdesc(c.T, c.ldT, ul0, ne, c.P1, n, ne, kk, ne);
-    b.d[b.count++] = cdesc(c.T, c.ldT, ul1, ne, c.P1 + kk, n, ne, kk, ne);
-    b.d[b.count++] = cdesc(c.P2, ne, ul0, ne, c.W0, n, n, kk, ne);
-    b.d[b.count++] = cdesc(c.P2, ne, ul1, ne, c.W0 + kk, n, n, kk, ne);
+    b.d[b.count++] = cdesc(c.T, c.ldT, ul0, ne, p1, n, ne, kk, ne);
+    b.d[b.count++] = cdesc(c.T, c.ldT, ul1, ne, p1 + kk, n, ne, kk, ne);
+    b.d[b.count++] = cdesc(c.P2, ne, ul0, ne, w0, n, n, kk, ne);
+    b.d[b.count++] = cdesc(c.P2, ne, ul1, ne, w0 + kk, n, n, kk, ne);
+    for (int i = 0; i < b.count && split; ++i) {
+      b.d[i].ksplit = c.ksplit;
+      b.d[i].csplit = i < 2 ? s1 : sw;
+    }
     PQ_HIP_CHECK(cgemm(b, kOpN, kOpT, c.st));
+    if (split) {
+      CsumBatch r{};
+      r.d[r.count++] = CsumDesc{c.P1part, s1, n, c.P1, n, ne, n, ns};
+      r.d[r.count++] = CsumDesc{c.W0part, sw, n, c.W0, n, n, n, ns};
+      PQ_HIP_CHECK(csum(r, c.st));
+    }
     SocDecideArgs d{};
     d.W0p = c.W0;
     d.D = c.D;

@@ -105,3 +105,17 @@ def test_soc_rejects_unsupported():
     with pytest.raises(PQMCError):
         SocChain(p.hopping, p.trial, p.U, p.dtau, p.n_slices, p.stab_every, p.seed,
                  scheme=Scheme.DELAYED, k=64)
+
+
+@pytest.mark.parametrize("scheme,k,window", [("delayed", 32, 10), ("local", 1, 5)])
+def test_soc_12x12_window_split_panels(scheme, k, window):
+    """2N = 288, N_e = 144 > 128: the panel products run as split-K slices
+    (three of depth 64) added by the slice sum; groups 4 x 32 + 16."""
+    p = synth.make_soc_problem(12, 144, -4.0, lam=0.5, dtau=0.05, n_slices=20, stab_every=5,
+                               perturb=1e-3, seed=synth.SEED_BASE + 96)
+    ch = _chain(p, scheme, k)
+    w = SocWalker(p, scheme, k=k)
+    ch.forward_window(window)
+    w.forward_window(window)
+    _check(ch, w, 0, p.n_slices, f"12x12 {scheme} k={k} window {window}")
+    ch.close()
