@@ -6,7 +6,8 @@
 //   cgemm_kernel     C = alpha op(A) op(B) + beta Cin (+ I), op in {N, T, H},
 //                    64 x 64 complex tiles through LDS, up to 8 products per launch
 //   rotate_kernel    rows (i, N+i) of an n2 x ncols matrix mixed by A(s x_i)
-//   chol_kernel      S = R^H R (upper R) of a Hermitian positive definite S
+//   chol_step_kernel S = R^H R (upper R) of a Hermitian positive definite S,
+//                    one launch per pivot row, chol_final_kernel scales the rows
 //   gj_step_kernel   one pivot column of Gauss-Jordan elimination with partial
 //                    pivoting on [M | I], spread over 64-column workgroups
 //   soc_decide_kernel  the decisions of one group of k sites in 2k x 2k space
@@ -184,44 +185,45 @@ __global__ __launch_bounds__(256) void ident_kernel(double2 *E, long ld, int n, 
   E[(long)r * ld + off + c] = make_double2(r == c ? 1.0 : 0.0, 0.0);
 }
 
-// ------------------------------------------------------ dense LA, one WG
-constexpr int kLaThreads = 1024;
+// ------------------------------------------------------------ dense LA
 
-// In place (leading dim ld): the upper triangle of S becomes R with
-// S = R^H R, and the strict lower triangle is zeroed.
-__global__ __launch_bounds__(kLaThreads) void chol_kernel(double2 *S, long ld, int n,
-                                                          unsigned long long *stats) {
-  __shared__ double2 rowj[1024];
-  const int t = threadIdx.x;
-  for (int j = 0; j < n; ++j) {
-    const double d2 = S[(long)j * ld + j].x;
-    const bool ok = d2 > 0.0 && isfinite(d2);
-    if (!ok) {
-      if (t == 0) stats[kStError] |= kErrSingular;
-      return;
-    }
-    const double inv = 1.0 / sqrt(d2);
-    __syncthreads();   // every thread has read S_jj before row j is overwritten
-    for (int c = j + t; c < n; c += kLaThreads) {
-      const double2 v = S[(long)j * ld + c];
-      const double2 r = make_double2(v.x * inv, v.y * inv);
-      rowj[c] = r;
-      S[(long)j * ld + c] = r;
-    }
-    for (int r = j + 1 + t; r < n; r += kLaThreads) S[(long)r * ld + j] = make_double2(0.0, 0.0);
-    __syncthreads();
-    // trailing update of the upper triangle: S_rc -= conj(R_jr) R_jc, r <= c
-    // (one wave per row, lanes along the row)
-    const int lane = t & 63, wave = t >> 6;
-    for (int r = j + 1 + wave; r < n; r += kLaThreads / 64) {
-      const double2 a = cconj(rowj[r]);
-      for (int c = r + lane; c < n; c += 64) {
-        double2 &x = S[(long)r * ld + c];
-        x = csub(x, cmul(a, rowj[c]));
-      }
-    }
-    __syncthreads();
+// Cholesky S = R^H R (upper R) in place, leading dim ld, without square
+// roots until the end: step j (one launch) subtracts conj(U_jr) U_jc / U_jj
+// from the upper triangle of rows r > j, U being the partially eliminated
+// upper triangle; chol_final_kernel then divides row r by sqrt(U_rr) and
+// zeroes the strict lower triangle.  One wave per row, lanes along it.
+__global__ __launch_bounds__(256) void chol_step_kernel(double2 *S, long ld, int n, int j,
+                                                        unsigned long long *stats) {
+  const double2 piv = S[(long)j * ld + j];
+  if (!(piv.x > 0.0) || !isfinite(piv.x)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) stats[kStError] |= kErrSingular;
+    return;
   }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r = j + 1 + blockIdx.x * 4 + wave;
+  if (r >= n) return;
+  const double inv = 1.0 / piv.x;
+  const double2 ujr = S[(long)j * ld + r];
+  const double2 a = make_double2(ujr.x * inv, -ujr.y * inv);   // conj(U_jr) / U_jj
+  const double2 *rowj = S + (long)j * ld;
+  double2 *rowr = S + (long)r * ld;
+  for (int c = r + lane; c < n; c += 64) rowr[c] = csub(rowr[c], cmul(a, rowj[c]));
+}
+
+__global__ __launch_bounds__(256) void chol_final_kernel(double2 *S, long ld, int n,
+                                                         unsigned long long *stats) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r = blockIdx.x * 4 + wave;
+  if (r >= n) return;
+  double2 *row = S + (long)r * ld;
+  const double d2 = row[r].x;
+  if (!(d2 > 0.0) || !isfinite(d2)) {
+    if (lane == 0) stats[kStError] |= kErrSingular;
+    return;
+  }
+  const double inv = 1.0 / sqrt(d2);
+  for (int c = lane; c < n; c += 64)
+    row[c] = c < r ? make_double2(0.0, 0.0) : make_double2(row[c].x * inv, row[c].y * inv);
 }
 
 // One Gauss-Jordan step (pivot column j) on E = [A | B] (n x 2n, leading
@@ -328,6 +330,8 @@ __global__ __launch_bounds__(kDecThreads) void soc_decide_kernel(SocDecideArgs a
   __shared__ int accm[64];
   __shared__ int n_acc;
   const int t = threadIdx.x;
+  int n_low = 0, n_neg = 0;       // thread 0's counters
+  bool nonfinite = false;
   int8_t *xrow = a.fields + (long)a.li * a.N + a.g0;
   for (int j = t; j < kk; j += kDecThreads) xs[j] = (double)xrow[j];
   if (t == 0) n_acc = 0;
@@ -390,12 +394,10 @@ __global__ __launch_bounds__(kDecThreads) void soc_decide_kernel(SocDecideArgs a
       const bool finite = !isnan(absR);
       const bool acc = finite && uu < absR;
       const double margin = absR - uu;
-      a.stats[kStProposed] += 1;
-      a.stats[kStFieldUpdates] += 1;
-      if (acc) { a.stats[kStAccepted] += 1; a.stats[kStFlips] += 1; }
-      if (fabs(margin) < 1e-12) a.stats[kStLowMargin] += 1;
-      if (R.x < 0.0) a.stats[kStNegative] += 1;
-      if (!finite) a.stats[kStError] |= kErrNonFinite;
+      // counters kept in registers, added to memory once per group
+      if (fabs(margin) < 1e-12) ++n_low;
+      if (R.x < 0.0) ++n_neg;
+      if (!finite) nonfinite = true;
       const long long idx = a.log_base + site;
       if (a.log_meta && idx < a.log_cap) {
         a.log_meta[3 * idx + 0] = (int32_t)a.slice_code;
@@ -408,7 +410,7 @@ __global__ __launch_bounds__(kDecThreads) void soc_decide_kernel(SocDecideArgs a
         Sinv[1] = cdiv(make_double2(-S[0][1].x, -S[0][1].y), R);
         Sinv[2] = cdiv(make_double2(-S[1][0].x, -S[1][0].y), R);
         Sinv[3] = cdiv(S[0][0], R);
-        xrow[j] = (int8_t)(-xrow[j]);
+        xrow[j] = (int8_t)(xs[j] > 0.0 ? -1 : 1);
         n_acc += 1;
       }
       accs = acc ? 1 : 0;
@@ -456,7 +458,16 @@ __global__ __launch_bounds__(kDecThreads) void soc_decide_kernel(SocDecideArgs a
     a.D[(long)(kk + j) * n + c] =
         make_double2(d10 * m0.x + d11 * m1.x, d10 * m0.y + d11 * m1.y);
   }
-  if (t == 0) *a.nflush = n_acc > 0 ? n : 0;
+  if (t == 0) {
+    *a.nflush = n_acc > 0 ? n : 0;
+    a.stats[kStProposed] += kk;
+    a.stats[kStFieldUpdates] += kk;
+    a.stats[kStAccepted] += n_acc;
+    a.stats[kStFlips] += n_acc;
+    if (n_low) a.stats[kStLowMargin] += n_low;
+    if (n_neg) a.stats[kStNegative] += n_neg;
+    if (nonfinite) a.stats[kStError] |= kErrNonFinite;
+  }
 }
 
 }  // namespace
@@ -533,8 +544,13 @@ hipError_t set_identity(double2 *E, long ld, int n, int off, hipStream_t st) {
 }
 
 hipError_t cholesky(double2 *S, long ld, int n, unsigned long long *stats, hipStream_t st) {
-  if (n > 1024) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(chol_kernel, dim3(1), dim3(kLaThreads), 0, st, S, ld, n, stats);
+  if (n < 1) return hipSuccess;
+  for (int j = 0; j + 1 < n; ++j) {
+    const int rows = n - j - 1;
+    hipLaunchKernelGGL(chol_step_kernel, dim3((rows + 3) / 4), dim3(256), 0, st, S, ld, n, j,
+                       stats);
+  }
+  hipLaunchKernelGGL(chol_final_kernel, dim3((n + 3) / 4), dim3(256), 0, st, S, ld, n, stats);
   return hipGetLastError();
 }
 
