@@ -319,12 +319,15 @@ constexpr int kDecThreads = 256;
 __global__ __launch_bounds__(kDecThreads) void soc_decide_kernel(SocDecideArgs a) {
   extern __shared__ double2 lds[];
   const int kk = a.kk, n = 2 * kk;
-  double2 *W0 = lds;                 // n x n
-  double2 *Mc = W0 + n * n;          // n x n
-  double2 *u = Mc + n * n;           // n x 2: Mc W0[:, jc]
+  // rows padded by one element: lanes walking down a column hit distinct banks
+  const int ld = n + 1;
+  double2 *W0 = lds;                 // n x n, leading dim ld
+  double2 *Mc = W0 + n * ld;         // n x n, leading dim ld
+  double2 *u = Mc + n * ld;          // n x 2: Mc W0[:, jc]
   double2 *w = u + 2 * n;            // 2 x n: W0[jr, :] Mc
   __shared__ double2 Sinv[4];
   __shared__ double2 Sm[4];
+  __shared__ double2 Gm[2 * 64];
   __shared__ int accs;
   __shared__ double xs[64];
   __shared__ int accm[64];
@@ -343,25 +346,25 @@ __global__ __launch_bounds__(kDecThreads) void soc_decide_kernel(SocDecideArgs a
     const double x = xs[j];
     const double2 w0 = a.W0p[(long)r * n + j], w1 = a.W0p[(long)r * n + kk + j];
     const double d00 = a.dd, d01 = -x * a.doff, d10 = x * a.doff, d11 = a.dd;
-    W0[r * n + j] = make_double2(w0.x * d00 + w1.x * d10, w0.y * d00 + w1.y * d10);
-    W0[r * n + kk + j] = make_double2(w0.x * d01 + w1.x * d11, w0.y * d01 + w1.y * d11);
+    W0[r * ld + j] = make_double2(w0.x * d00 + w1.x * d10, w0.y * d00 + w1.y * d10);
+    W0[r * ld + kk + j] = make_double2(w0.x * d01 + w1.x * d11, w0.y * d01 + w1.y * d11);
   }
-  for (int e = t; e < n * n; e += kDecThreads) Mc[e] = make_double2(0.0, 0.0);
+  for (int e = t; e < n * ld; e += kDecThreads) Mc[e] = make_double2(0.0, 0.0);
   __syncthreads();
   for (int j = 0; j < kk; ++j) {
     const int c0 = j, c1 = kk + j;
     // u = Mc W0[:, (c0, c1)],  w = W0[(c0, c1), :] Mc
     if (t < 2 * n) {
-      const int q = t / n, r = t % n;
+      const int q = t >= n ? 1 : 0, r = t - q * n;
       const int col = q ? c1 : c0;
       double2 s = make_double2(0.0, 0.0);
-      for (int b = 0; b < n; ++b) cfma(s, Mc[r * n + b], W0[b * n + col]);
+      for (int b = 0; b < n; ++b) cfma(s, Mc[r * ld + b], W0[b * ld + col]);
       u[r * 2 + q] = s;
     } else if (t < 4 * n) {
-      const int e = t - 2 * n, q = e / n, c = e % n;
+      const int e = t - 2 * n, q = e >= n ? 1 : 0, c = e - q * n;
       const int row = q ? c1 : c0;
       double2 s = make_double2(0.0, 0.0);
-      for (int b = 0; b < n; ++b) cfma(s, W0[row * n + b], Mc[b * n + c]);
+      for (int b = 0; b < n; ++b) cfma(s, W0[row * ld + b], Mc[b * ld + c]);
       w[q * n + c] = s;
     }
     __syncthreads();
@@ -372,13 +375,13 @@ __global__ __launch_bounds__(kDecThreads) void soc_decide_kernel(SocDecideArgs a
       const int p = q >> 1, qq = q & 1;
       const int row = p ? c1 : c0;
       double2 prod = make_double2(0.0, 0.0);
-      if (lane < n) prod = cmul(W0[row * n + lane], u[lane * 2 + qq]);
+      if (lane < n) prod = cmul(W0[row * ld + lane], u[lane * 2 + qq]);
       for (int off = 32; off > 0; off >>= 1) {
         prod.x += __shfl_down(prod.x, off, 64);
         prod.y += __shfl_down(prod.y, off, 64);
       }
       if (lane == 0) {
-        double2 v = csub(W0[row * n + (qq ? c1 : c0)], prod);
+        double2 v = csub(W0[row * ld + (qq ? c1 : c0)], prod);
         if (p == qq) v.x += 1.0;
         Sm[q] = v;
       }
@@ -406,10 +409,11 @@ __global__ __launch_bounds__(kDecThreads) void soc_decide_kernel(SocDecideArgs a
         a.log_margin[idx] = margin;
       }
       if (acc) {
-        Sinv[0] = cdiv(S[1][1], R);
-        Sinv[1] = cdiv(make_double2(-S[0][1].x, -S[0][1].y), R);
-        Sinv[2] = cdiv(make_double2(-S[1][0].x, -S[1][0].y), R);
-        Sinv[3] = cdiv(S[0][0], R);
+        const double2 iR = cdiv(make_double2(1.0, 0.0), R);
+        Sinv[0] = cmul(S[1][1], iR);
+        Sinv[1] = cmul(make_double2(-S[0][1].x, -S[0][1].y), iR);
+        Sinv[2] = cmul(make_double2(-S[1][0].x, -S[1][0].y), iR);
+        Sinv[3] = cmul(S[0][0], iR);
         xrow[j] = (int8_t)(xs[j] > 0.0 ? -1 : 1);
         n_acc += 1;
       }
@@ -418,19 +422,27 @@ __global__ __launch_bounds__(kDecThreads) void soc_decide_kernel(SocDecideArgs a
     }
     __syncthreads();
     if (accs) {
-      // Mc += (e_jc - u) Sinv (e_jr - w)
-      for (int e = t; e < n * n; e += kDecThreads) {
-        const int r = e / n, c = e % n;
-        double2 l0 = make_double2((r == c0 ? 1.0 : 0.0) - u[r * 2].x, -u[r * 2].y);
-        double2 l1 = make_double2((r == c1 ? 1.0 : 0.0) - u[r * 2 + 1].x, -u[r * 2 + 1].y);
-        double2 r0 = make_double2((c == c0 ? 1.0 : 0.0) - w[c].x, -w[c].y);
-        double2 r1 = make_double2((c == c1 ? 1.0 : 0.0) - w[n + c].x, -w[n + c].y);
-        double2 v = Mc[e];
-        cfma(v, l0, cmul(Sinv[0], r0));
-        cfma(v, l0, cmul(Sinv[1], r1));
-        cfma(v, l1, cmul(Sinv[2], r0));
-        cfma(v, l1, cmul(Sinv[3], r1));
-        Mc[e] = v;
+      // Mc += (e_jc - u) G with G = Sinv (e_jr - w) (2 x n, formed first)
+      if (t < 2 * n) {
+        const int q = t >= n ? 1 : 0, c = t - q * n;
+        const double2 r0 = make_double2((c == c0 ? 1.0 : 0.0) - w[c].x, -w[c].y);
+        const double2 r1 = make_double2((c == c1 ? 1.0 : 0.0) - w[n + c].x, -w[n + c].y);
+        double2 g = cmul(Sinv[2 * q], r0);
+        cfma(g, Sinv[2 * q + 1], r1);
+        Gm[q * 64 + c] = g;
+      }
+      __syncthreads();
+      const int c = t & 63;
+      if (c < n) {
+        const double2 g0 = Gm[c], g1 = Gm[64 + c];
+        for (int r = t >> 6; r < n; r += kDecThreads / 64) {
+          const double2 l0 = make_double2((r == c0 ? 1.0 : 0.0) - u[r * 2].x, -u[r * 2].y);
+          const double2 l1 = make_double2((r == c1 ? 1.0 : 0.0) - u[r * 2 + 1].x, -u[r * 2 + 1].y);
+          double2 v = Mc[r * ld + c];
+          cfma(v, l0, g0);
+          cfma(v, l1, g1);
+          Mc[r * ld + c] = v;
+        }
       }
     }
     __syncthreads();
@@ -453,7 +465,7 @@ __global__ __launch_bounds__(kDecThreads) void soc_decide_kernel(SocDecideArgs a
     const int j = e / n, c = e % n;
     const double x = xs[j];
     const double d00 = a.dd, d01 = -x * a.doff, d10 = x * a.doff, d11 = a.dd;
-    const double2 m0 = Mc[j * n + c], m1 = Mc[(kk + j) * n + c];
+    const double2 m0 = Mc[j * ld + c], m1 = Mc[(kk + j) * ld + c];
     a.D[(long)j * n + c] = make_double2(d00 * m0.x + d01 * m1.x, d00 * m0.y + d01 * m1.y);
     a.D[(long)(kk + j) * n + c] =
         make_double2(d10 * m0.x + d11 * m1.x, d10 * m0.y + d11 * m1.y);
@@ -569,10 +581,10 @@ hipError_t gj_inverse(double2 *E, long ld, int n, double2 *colbuf, unsigned long
 hipError_t decide(const SocDecideArgs &a, hipStream_t st) {
   if (a.kk < 1 || a.kk > kSocMaxK) return hipErrorInvalidValue;
   const int n = 2 * a.kk;
-  const size_t lds = sizeof(double2) * (2 * (size_t)n * n + 4 * (size_t)n);
+  const size_t lds = sizeof(double2) * (2 * (size_t)n * (n + 1) + 4 * (size_t)n);
   static const hipError_t attr = hipFuncSetAttribute(
       (const void *)soc_decide_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-      (int)(sizeof(double2) * (2 * 64 * 64 + 4 * 64)));
+      (int)(sizeof(double2) * (2 * 64 * 65 + 4 * 64)));
   if (attr != hipSuccess) return attr;
   hipLaunchKernelGGL(soc_decide_kernel, dim3(1), dim3(kDecThreads), lds, st, a);
   return hipGetLastError();
