@@ -270,16 +270,25 @@ def serve_leg(args, rate):
     probs, jobs = {}, []
     for i in range(args.serve_jobs):
         L, U = Ls[gen.integers(len(Ls))], Us[gen.integers(len(Us))]
-        if (L, U) not in probs:
-            probs[(L, U)] = synth.make_problem(L, L * L // 2, L * L // 2, U,
-                                               n_slices=args.serve_slices, stab_every=10,
-                                               perturb=1e-3, seed=seed + L)
-        p = probs[(L, U)]
+        soc = args.serve_soc > 0 and gen.random() < args.serve_soc
+        if (L, U, soc) not in probs:
+            if soc:   # Rashba lambda = 0.5 at n = 1; the spin-s^y decoupling needs U < 0
+                probs[(L, U, soc)] = synth.make_soc_problem(
+                    L, L * L, -U, lam=0.5, n_slices=args.serve_slices, stab_every=10,
+                    perturb=1e-3, seed=seed + 100 + L)
+            else:
+                probs[(L, U, soc)] = synth.make_problem(L, L * L // 2, L * L // 2, U,
+                                                        n_slices=args.serve_slices,
+                                                        stab_every=10, perturb=1e-3,
+                                                        seed=seed + L)
+        p = probs[(L, U, soc)]
         jobs.append(Job(job_id=i, arrival=float(arrivals[i]), hopping=p.hopping,
-                        trial_up=p.trial_up, trial_dn=p.trial_dn, U=U, dtau=p.dtau,
+                        trial_up=p.trial if soc else p.trial_up,
+                        trial_dn=None if soc else p.trial_dn, U=p.U, dtau=p.dtau,
                         n_slices=p.n_slices, stab_every=p.stab_every, seed=seed + 1 + i,
                         n_walkers=args.serve_walkers, n_sweeps=args.serve_sweeps,
-                        scheme=Scheme.DELAYED, k=args.k, keep_green=False))
+                        scheme=Scheme.DELAYED, k=16 if soc else args.k, keep_green=False,
+                        soc=soc))
     budget = int(args.serve_budget_gb * 1e9) if args.serve_budget_gb > 0 \
         else GpuBackend.default_budget()
     log(f"serving {len(jobs)} jobs at {rate}/s, budget {budget / 1e9:.2f} GB")
@@ -289,7 +298,10 @@ def serve_leg(args, rate):
     out.update({
         "arrival_rate_jobs_per_s": rate,
         "field_updates_per_s": fu / rep.makespan_s if rep.makespan_s > 0 else None,
-        "mix": f"L in {{{args.serve_sizes}}} uniform, U/t in {{2,4,8}}, half filling, "
+        "soc_jobs": sum(j.soc for j in jobs),
+        "mix": f"L in {{{args.serve_sizes}}} uniform, U/t in {{2,4,8}}, half filling; a "
+               f"fraction {args.serve_soc} of the jobs Rashba (lambda/t = 0.5, U/t in "
+               f"{{-2,-4,-8}}, n = 1, delayed k = 16), "
                f"{args.serve_walkers} walkers x {args.serve_sweeps} sweeps per job, "
                f"M={args.serve_slices}, k_tau=10, delayed k={args.k}, FCFS admission by "
                f"workspace bytes, batches of up to 8 walkers re-formed every sweep, "
@@ -340,13 +352,15 @@ def main():
                     help="jobs of the serving leg (0 = skip it)")
     ap.add_argument("--serve-rate", default="8,64",
                     help="Poisson arrival rates, jobs/s, one serving run each (comma list)")
-    ap.add_argument("--serve-sizes", default="8,12,16,24,32", help="lattice sides L of the mix")
+    ap.add_argument("--serve-sizes", default="8,12,16,24", help="lattice sides L of the mix")
     ap.add_argument("--serve-walkers", type=int, default=4)
+    ap.add_argument("--serve-soc", type=float, default=0.5,
+                    help="fraction of serving jobs on the Rashba SOC model")
     ap.add_argument("--serve-lanes", type=int, default=2,
                     help="concurrent batches per serving step, one HIP stream each")
     ap.add_argument("--serve-sweeps", type=int, default=1)
     ap.add_argument("--serve-slices", type=int, default=40, help="M of the serving jobs")
-    ap.add_argument("--serve-budget-gb", type=float, default=2.0,
+    ap.add_argument("--serve-budget-gb", type=float, default=8.0,
                     help="HBM budget of the admitted walkers (0 = 90%% of free memory)")
     ap.add_argument("--ktime-window", type=int, default=10,
                     help="forward slice visits instrumented per kernel after the timed sweeps")

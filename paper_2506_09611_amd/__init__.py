@@ -7,7 +7,8 @@ importing `Chain` without the built library raises ImportError.
 """
 from .binding import (Chain, Scheme, PQMCError, load_library, library_path,  # noqa: F401
                       EXPORTED_SYMBOLS, MAX_BATCH, batch_sweep, batch_forward_window,
-                      multi_sweep, workspace_bytes, SocChain)
+                      multi_sweep, workspace_bytes, SocChain, soc_workspace_bytes)
 
 __all__ = ["Chain", "Scheme", "PQMCError", "load_library", "library_path", "EXPORTED_SYMBOLS",
-           "MAX_BATCH", "batch_sweep", "batch_forward_window", "multi_sweep", "workspace_bytes", "SocChain"]
+           "MAX_BATCH", "batch_sweep", "batch_forward_window", "multi_sweep", "workspace_bytes", "SocChain",
+           "soc_workspace_bytes"]

@@ -283,6 +283,24 @@ class Chain:
             pass
 
 
+def soc_workspace_bytes(n_sites, n_e, n_slices, stab_every, scheme=Scheme.DELAYED, k=16,
+                        log=False):
+    """pqmc_soc_workspace_bytes for an SOC problem of this shape (+256 bytes
+    of alignment slack): the whole device footprint of one SocChain."""
+    lib = load_library()
+    n2 = 2 * int(n_sites)
+    z = np.zeros((n2, n2), np.complex128)
+    pt = np.zeros((n2, int(n_e)), np.complex128)
+    prob = SocProblem(int(n_sites), int(n_e), z.view(np.float64).ctypes.data_as(
+        ctypes.POINTER(ctypes.c_double)), pt.view(np.float64).ctypes.data_as(
+        ctypes.POINTER(ctypes.c_double)), -1.0, 0.05, int(n_slices), int(stab_every), 0, 0)
+    o = UpdateOpts(int(scheme), max(int(k), 1), 1, FLAG_LOG if log else 0)
+    n = ctypes.c_size_t(0)
+    _check(lib, lib.pqmc_soc_workspace_bytes(ctypes.byref(prob), ctypes.byref(o),
+                                             ctypes.byref(n)))
+    return n.value + 256
+
+
 class SocChain:
     """One walker of the spin-orbit coupled Hubbard model (a pqmc_soc_ctx).
 

@@ -68,10 +68,12 @@ class Job:
     b: int = 16
     fp32: bool = False
     keep_green: bool = True
+    soc: bool = False      # spin-orbit coupled model: hopping 2N x 2N complex, trial_up
+                           # the 2N x N_e trial, trial_dn unused; local or delayed scheme
 
     @property
     def n_sites(self) -> int:
-        return int(self.hopping.shape[0])
+        return int(self.hopping.shape[0]) // (2 if self.soc else 1)
 
     @property
     def n_up(self) -> int:
@@ -79,13 +81,16 @@ class Job:
 
     @property
     def n_dn(self) -> int:
-        return int(self.trial_dn.shape[1])
+        return 0 if self.soc else int(self.trial_dn.shape[1])
 
 
 def batch_key(job: Job) -> tuple:
     """Walkers batch together iff their keys are equal: the library's rule
     for pqmc_batch_sweep (same M, k_tau, scheme, k, b, precision form and
-    group-size class; the local scheme also needs one lattice shape)."""
+    group-size class; the local scheme also needs one lattice shape).  An
+    SOC walker is always a batch of its own."""
+    if job.soc:   # one context per walker, swept on its own (pqmc_soc_sweep)
+        return ("soc", job.job_id)
     N = job.n_sites
     gmax = max(min(job.k, N), min(job.b, N))
     key = (job.n_slices, job.stab_every, int(job.scheme), job.k, job.b, bool(job.fp32),
@@ -99,7 +104,7 @@ def batch_key(job: Job) -> tuple:
 class WalkerResult:
     walker_id: int
     fields: Any
-    green: Any                    # (G_up, G_dn) at the end, or None
+    green: Any                    # (G_up, G_dn) at the end ((G,) for SOC), or None
     stats: Dict[str, float]       # sums over the walker's sweeps
 
 
@@ -168,9 +173,10 @@ class RealClock:
 
 
 class GpuBackend:
-    """Walkers as library contexts (Chain) on torch's current device, lane j
-    on its own HIP stream (lane 0: torch's current stream); one
-    pqmc_multi_sweep per step over the lanes' batches."""
+    """Walkers as library contexts on torch's current device, lane j on its
+    own HIP stream (lane 0: torch's current stream).  One step: the lanes'
+    spin-decoupled batches in one pqmc_multi_sweep, each SOC walker's
+    pqmc_soc_sweep on a host thread of its own, all concurrently."""
 
     def __init__(self, lanes: int = 1):
         import torch
@@ -189,25 +195,51 @@ class GpuBackend:
         return int(free * fraction)
 
     def walker_bytes(self, job: Job) -> int:
+        if job.soc:
+            return self._b.soc_workspace_bytes(job.n_sites, job.n_up, job.n_slices,
+                                               job.stab_every, job.scheme, job.k)
         return self._b.workspace_bytes(job.n_sites, job.n_up, job.n_dn, job.n_slices,
                                        job.stab_every, job.scheme, job.k, job.b, job.fp32)
 
     def open(self, job: Job, walker_id: int, lane: int = 0):
+        if job.soc:
+            return self._b.SocChain(job.hopping, job.trial_up, job.U, job.dtau, job.n_slices,
+                                    job.stab_every, job.seed, walker_id, scheme=job.scheme,
+                                    k=job.k, stream=self.streams[lane])
         return self._b.Chain(job.hopping, job.trial_up, job.trial_dn, job.U, job.dtau,
                              job.n_slices, job.stab_every, job.seed, walker_id,
                              scheme=job.scheme, k=job.k, b=job.b, fp32=job.fp32,
                              stream=self.streams[lane])
 
     def sweep(self, batches: List[list]) -> List[List[dict]]:
-        flat = [h for b in batches for h in b]
-        st = self._b.multi_sweep(flat, 1)
-        out, i = [], 0
-        for b in batches:
-            out.append(st[i:i + len(b)])
-            i += len(b)
+        out: List[Optional[List[dict]]] = [None] * len(batches)
+        plain = [i for i, b in enumerate(batches) if not isinstance(b[0], self._b.SocChain)]
+        socs = [i for i in range(len(batches)) if i not in plain]
+
+        def run_plain():
+            flat = [h for i in plain for h in batches[i]]
+            st = self._b.multi_sweep(flat, 1)
+            k = 0
+            for i in plain:
+                out[i] = st[k:k + len(batches[i])]
+                k += len(batches[i])
+
+        def run_soc(i):
+            out[i] = [batches[i][0].sweep(1)]
+
+        tasks = ([run_plain] if plain else []) + [(lambda i=i: run_soc(i)) for i in socs]
+        if len(tasks) == 1:
+            tasks[0]()
+        else:
+            import concurrent.futures
+            with concurrent.futures.ThreadPoolExecutor(max_workers=len(tasks)) as ex:
+                for f in [ex.submit(t) for t in tasks]:
+                    f.result()
         return out
 
     def collect(self, job: Job, handle):
+        if job.soc:
+            return handle.fields(), ((handle.green(),) if job.keep_green else None)
         green = (handle.green(0), handle.green(1)) if job.keep_green else None
         return handle.fields(), green
 
@@ -261,6 +293,8 @@ class Server:
     def _pick(self, active: List[_Walker]) -> List[_Walker]:
         line = sorted(active, key=self._line_key)
         head = line[0]
+        if head.key[0] == "soc":
+            return [head]
         return [w for w in line if w.key == head.key][:self.max_batch]
 
     def _pick_lanes(self, active: List[_Walker]) -> List[List[_Walker]]:

@@ -60,3 +60,47 @@ def test_served_results_equal_alone(scheme_name, kw, lanes):
             for sp in range(2):
                 assert np.array_equal(w.green[sp], alone.green(sp)), (j.job_id, w.walker_id, sp)
             alone.close()
+
+
+def test_served_mix_with_soc_jobs_equal_alone():
+    """Half spin-decoupled, half spin-orbit coupled jobs on two lanes: each
+    walker's fields and G equal those of its run alone."""
+    from paper_2506_09611_amd import Chain, SocChain, Scheme
+    from paper_2506_09611_amd.serving import GpuBackend, Job, Server, poisson_arrivals
+    t = poisson_arrivals(4, 40.0, synth.SEED_BASE + 66)
+    jobs = []
+    for i in range(4):
+        if i % 2 == 0:
+            p = synth.make_problem(6, 18, 17, 4.0, n_slices=20, stab_every=5, perturb=1e-3,
+                                   seed=synth.SEED_BASE + 67 + i)
+            jobs.append(Job(job_id=i, arrival=float(t[i]), hopping=p.hopping,
+                            trial_up=p.trial_up, trial_dn=p.trial_dn, U=p.U, dtau=p.dtau,
+                            n_slices=p.n_slices, stab_every=p.stab_every, seed=p.seed,
+                            n_walkers=3, n_sweeps=2, scheme=Scheme.DELAYED, k=16))
+        else:
+            q = synth.make_soc_problem(4, 14, -4.0, lam=0.5, n_slices=20, stab_every=5,
+                                       perturb=1e-3, seed=synth.SEED_BASE + 67 + i)
+            jobs.append(Job(job_id=i, arrival=float(t[i]), hopping=q.hopping, trial_up=q.trial,
+                            trial_dn=None, U=q.U, dtau=q.dtau, n_slices=q.n_slices,
+                            stab_every=q.stab_every, seed=q.seed, n_walkers=2, n_sweeps=2,
+                            scheme=Scheme.DELAYED, k=8, soc=True))
+    be = GpuBackend(lanes=2)
+    rep = Server(be, be.default_budget()).run(jobs)
+    print("served mix:", rep.summary(), flush=True)
+    assert rep.summary()["completed"] == 4
+    for j, r in zip(jobs, rep.results):
+        for w in r.walkers:
+            if j.soc:
+                alone = SocChain(j.hopping, j.trial_up, j.U, j.dtau, j.n_slices, j.stab_every,
+                                 j.seed, w.walker_id, scheme=j.scheme, k=j.k)
+                alone.sweep(j.n_sweeps)
+                assert np.array_equal(w.fields, alone.fields())
+                assert np.array_equal(w.green[0], alone.green())
+            else:
+                alone = Chain(j.hopping, j.trial_up, j.trial_dn, j.U, j.dtau, j.n_slices,
+                              j.stab_every, j.seed, w.walker_id, scheme=j.scheme, k=j.k)
+                alone.sweep(j.n_sweeps)
+                assert np.array_equal(w.fields, alone.fields())
+                for sp in range(2):
+                    assert np.array_equal(w.green[sp], alone.green(sp))
+            alone.close()

@@ -188,3 +188,26 @@ def test_lanes_run_batches_concurrently():
         ends[lanes] = max(r.finished for r in rep.results)
         assert rep.mean_batch == 8.0
     assert ends[2] < 0.6 * ends[1]
+
+
+def _soc_job(i, arrival, L, n_walkers=2, n_sweeps=2):
+    N = L * L
+    return Job(job_id=i, arrival=float(arrival), hopping=np.zeros((2 * N, 2 * N), complex),
+               trial_up=np.zeros((2 * N, N), complex), trial_dn=None, U=-4.0, dtau=0.05,
+               n_slices=40, stab_every=10, seed=i, n_walkers=n_walkers, n_sweeps=n_sweeps,
+               scheme=Scheme.DELAYED, k=16, soc=True)
+
+
+def test_soc_walkers_run_alone_beside_batches():
+    """SOC walkers never share a batch (one context each), but run on the
+    lanes beside the spin-decoupled batches."""
+    clock = SimClock()
+    jobs = [_job(0, 0.0, 8, n_walkers=6), _soc_job(1, 0.0, 8), _job(2, 0.0, 12, n_walkers=4),
+            _soc_job(3, 0.001, 4, n_walkers=3)]
+    assert jobs[1].n_sites == 64 and jobs[1].n_up == 64
+    rep = Server(SimBackend(clock), 10**6, clock=clock, lanes=2).run(jobs)
+    for b in rep.batch_log:
+        socs = [j for j, _ in b if jobs[j].soc]
+        assert not socs or len(b) == 1, b
+    assert all(r.finished is not None for r in rep.results)
+    assert batch_key(jobs[1]) != batch_key(jobs[3])
