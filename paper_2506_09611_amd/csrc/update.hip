@@ -1037,6 +1037,7 @@ struct TileArgs {
 };
 
 constexpr int kLdt = 65;   // padded LDS row stride
+constexpr int kTileThreads = 512;
 
 // T of spin s in the type the tile kernel works in
 template <class R>
@@ -1054,8 +1055,13 @@ __device__ __forceinline__ float *tile_matrix<float>(const SpinMats &m, int s) {
 // kept in and multiplied in between stabilisations (double, or float for
 // the precision form); the pending group's panels and Mc arrive in double
 // and are rounded to R, and the split-K partials leave in double.
+//
+// 512 threads (8 waves) per 64 x 64 tile: wave w owns the 32 x 16 block
+// (rows 32 (w / 4), columns 16 (w % 4)) of the tile, so that each lane holds
+// half the registers of a 4-wave layout and two workgroups per CU give four
+// waves per SIMD to hide the load and barrier latencies.
 template <int KP, class R>
-__global__ __launch_bounds__(256) void group_tile_kernel(Batch<TileArgs> B) {
+__global__ __launch_bounds__(kTileThreads) void group_tile_kernel(Batch<TileArgs> B) {
   typedef Mma<R> MM;
   // XCD-aware placement: consecutive workgroup ids go round-robin to the 8
   // XCDs, so XCD x receives ids x, x + 8, ...; giving it the contiguous range
@@ -1067,8 +1073,9 @@ __global__ __launch_bounds__(256) void group_tile_kernel(Batch<TileArgs> B) {
   const int mat = flat / tpm;
   if (mat >= B.w[0].nmat) return;
   const TileArgs &a = B.w[mat >> 1];
-  constexpr int kPre = KP / 4;                       // per lane: a 64 x KP operand
-  constexpr int kPreM = KP * KP >= 256 ? KP * KP / 256 : 1;   // per lane: KP x KP
+  constexpr int NT = kTileThreads, NW = kTileThreads / 64;
+  constexpr int kPre = 64 * KP / NT;                 // per lane: a 64 x KP operand
+  constexpr int kPreM = KP * KP >= NT ? KP * KP / NT : 1;     // per lane: KP x KP
   constexpr int kpad = KP;
   const int s = mat & 1;
   const int Ns = a.m.Ns[s];
@@ -1077,7 +1084,7 @@ __global__ __launch_bounds__(256) void group_tile_kernel(Batch<TileArgs> B) {
   const int rb = tile / nt, cb = tile % nt;
   if (rb >= nt) return;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wm = wave >> 2, wn = wave & 3;   // 32-row half, 16-column quarter
   const int row0 = rb * 64, col0 = cb * 64;
   const int kmax = a.g.kmax;
   const int kk = a.kk, kkp = a.kk_prev;
@@ -1087,16 +1094,15 @@ __global__ __launch_bounds__(256) void group_tile_kernel(Batch<TileArgs> B) {
   R *lds = reinterpret_cast<R *>(lds_raw);
 
   // ---- every load first: T tile, the pending flush's operands, next panels
-  typename MM::acc acc[2][2];
+  const int ccol = wn * 16 + (lane & 15);   // this lane's tile column
+  typename MM::acc acc[2];
 #pragma unroll
   for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
-    for (int ni = 0; ni < 2; ++ni)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int r = row0 + (wm * 32 + mi * 16 + MM::row(lane, j)), c = col0 + acc_col(wn, ni, lane);
-        acc[mi][ni][j] = (r < Ns && c < Ns) ? T[(long)r * Ns + c] : 0.0;
-      }
+    for (int j = 0; j < 4; ++j) {
+      const int r = row0 + (wm * 32 + mi * 16 + MM::row(lane, j)), c = col0 + ccol;
+      acc[mi][j] = (r < Ns && c < Ns) ? T[(long)r * Ns + c] : 0.0;
+    }
   const bool fl = a.flush && a.g.nA[0] > 0;
   R p1v[kPre], p2v[kPre], mcv[kPreM];
   double urv[kPre];
@@ -1105,7 +1111,7 @@ __global__ __launch_bounds__(256) void group_tile_kernel(Batch<TileArgs> B) {
     const double *UR = a.m.UR[s];
 #pragma unroll
     for (int i = 0; i < kPre; ++i) {
-      const int e = t + 256 * i;
+      const int e = t + NT * i;
       // P1 rows of the tile (64 x kpad), P2 columns of the tile (kpad x 64)
       const int r = e / kpad, m = e % kpad;
       p1v[i] = (e < 64 * kpad && m < kkp && row0 + r < Ns) ? P1[(long)(row0 + r) * kmax + m] : 0.0;
@@ -1117,7 +1123,7 @@ __global__ __launch_bounds__(256) void group_tile_kernel(Batch<TileArgs> B) {
     }
 #pragma unroll
     for (int i = 0; i < kPreM; ++i) {
-      const int e = t + 256 * i;
+      const int e = t + NT * i;
       const int ma = e / kpad, mb = e % kpad;
       mcv[i] = (e < kpad * kpad && ma < kkp && mb < kkp) ? Mc[ma * kmax + mb] : 0.0;
     }
@@ -1127,7 +1133,7 @@ __global__ __launch_bounds__(256) void group_tile_kernel(Batch<TileArgs> B) {
     const double *UR = a.m.UR[s], *ULt = a.m.ULt[s];
 #pragma unroll
     for (int i = 0; i < kPre; ++i) {
-      const int e = t + 256 * i;
+      const int e = t + NT * i;
       const int m = e >> 6, c = e & 63;
       const bool ok = m < kk;
       ug[i] = (ok && row0 + c < Ns) ? UR[(long)(a.g0 + m) * Ns + row0 + c] : 0.0;
@@ -1143,63 +1149,69 @@ __global__ __launch_bounds__(256) void group_tile_kernel(Batch<TileArgs> B) {
     R *B1 = M1 + kpad * ld1;                // kpad x kLdt: P2 columns
 #pragma unroll
     for (int i = 0; i < kPre; ++i) {
-      const int e = t + 256 * i;
+      const int e = t + NT * i;
       A1[(e / kpad) * ld1 + e % kpad] = p1v[i];
       B1[(e >> 6) * kLdt + (e & 63)] = p2v[i];
     }
 #pragma unroll
     for (int i = 0; i < kPreM; ++i) {
-      const int e = t + 256 * i;
+      const int e = t + NT * i;
       if (e < kpad * kpad) M1[(e / kpad) * ld1 + e % kpad] = mcv[i];
     }
     __syncthreads();
-    // -(P1 Mc): wave w forms rows [16 w, 16 w + 16), its KP / 16 column
-    // tiles as independent accumulators, and overwrites those rows of A1
+    // -(P1 Mc): wave w forms rows [16 (w % 4), + 16) and the column tiles
+    // w / 4, w / 4 + 2, ...; the rows of A1 are overwritten once every
+    // wave has read them
     {
-      typename MM::acc q[KP / 16];
+      constexpr int QT = KP / 16, QV = (QT + 1) / 2;
+      const int rq = wave & 3, uh = wave >> 2;
+      typename MM::acc q[QV];
 #pragma unroll
-      for (int u = 0; u < KP / 16; ++u) q[u] = MM::zero();
+      for (int v = 0; v < QV; ++v) q[v] = MM::zero();
       const int li = lane & 15, lk = lane >> 4;
       for (int k0 = 0; k0 < kp; k0 += 4) {
-        const R av = A1[(16 * wave + li) * ld1 + k0 + lk];
+        const R av = A1[(16 * rq + li) * ld1 + k0 + lk];
 #pragma unroll
-        for (int u = 0; u < KP / 16; ++u) q[u] = MM::op(av, M1[(k0 + lk) * ld1 + u * 16 + li], q[u]);
+        for (int v = 0; v < QV; ++v) {
+          const int u = uh + 2 * v;
+          if (u < QT) q[v] = MM::op(av, M1[(k0 + lk) * ld1 + u * 16 + li], q[v]);
+        }
       }
+      __syncthreads();
 #pragma unroll
-      for (int u = 0; u < KP / 16; ++u)
+      for (int v = 0; v < QV; ++v) {
+        const int u = uh + 2 * v;
+        if (u < QT)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-          A1[(16 * wave + MM::row(lane, j)) * ld1 + u * 16 + li] = -q[u][j];
+          for (int j = 0; j < 4; ++j)
+            A1[(16 * rq + MM::row(lane, j)) * ld1 + u * 16 + li] = -q[v][j];
+      }
     }
     __syncthreads();
-    // acc (this wave's 32 x 32 quadrant) += A1 (64 x kp) B1 (kp x 64)
+    // acc (this wave's 32 x 16 block) += A1 (64 x kp) B1 (kp x 64)
     {
-      const int i0 = wm * 32 + (lane & 15), j0 = wn * 32 + (lane & 15);
+      const int i0 = wm * 32 + (lane & 15), j0 = wn * 16 + (lane & 15);
       for (int k0 = 0; k0 < kp; k0 += 4) {
         const int kq = k0 + (lane >> 4);
         const R a0 = A1[i0 * ld1 + kq], a1 = A1[(i0 + 16) * ld1 + kq];
-        const R b0 = B1[kq * kLdt + j0], b1 = B1[kq * kLdt + j0 + 16];
-        acc[0][0] = MM::op(a0, b0, acc[0][0]);
-        acc[0][1] = MM::op(a0, b1, acc[0][1]);
-        acc[1][0] = MM::op(a1, b0, acc[1][0]);
-        acc[1][1] = MM::op(a1, b1, acc[1][1]);
+        const R b0 = B1[kq * kLdt + j0];
+        acc[0] = MM::op(a0, b0, acc[0]);
+        acc[1] = MM::op(a1, b0, acc[1]);
       }
     }
 #pragma unroll
     for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
-      for (int ni = 0; ni < 2; ++ni)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int r = row0 + (wm * 32 + mi * 16 + MM::row(lane, j)), c = col0 + acc_col(wn, ni, lane);
-          if (r < Ns && c < Ns) T[(long)r * Ns + c] = acc[mi][ni][j];
-        }
+      for (int j = 0; j < 4; ++j) {
+        const int r = row0 + (wm * 32 + mi * 16 + MM::row(lane, j)), c = col0 + ccol;
+        if (r < Ns && c < Ns) T[(long)r * Ns + c] = acc[mi][j];
+      }
     if (rb == 0) {
       const double *sc = a.g.sc[s];
       double *UR = a.m.UR[s];
 #pragma unroll
       for (int i = 0; i < kPre; ++i) {
-        const int e = t + 256 * i;
+        const int e = t + NT * i;
         const int m = e >> 6, c = col0 + (e & 63);
         if (m < kkp && c < Ns) UR[(long)(a.g0_prev + m) * Ns + c] = urv[i] * sc[m];
       }
@@ -1215,13 +1227,11 @@ __global__ __launch_bounds__(256) void group_tile_kernel(Batch<TileArgs> B) {
 #pragma unroll
   for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
-    for (int ni = 0; ni < 2; ++ni)
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-        X[(wm * 32 + mi * 16 + MM::row(lane, j)) * kLdt + acc_col(wn, ni, lane)] = acc[mi][ni][j];
+    for (int j = 0; j < 4; ++j)
+      X[(wm * 32 + mi * 16 + MM::row(lane, j)) * kLdt + ccol] = acc[mi][j];
 #pragma unroll
   for (int i = 0; i < kPre; ++i) {
-    const int e = t + 256 * i;
+    const int e = t + NT * i;
     Y[(e >> 6) * kLdt + (e & 63)] = ug[i];
     Z[(e >> 6) * kLdt + (e & 63)] = lg[i];
   }
@@ -1231,8 +1241,8 @@ __global__ __launch_bounds__(256) void group_tile_kernel(Batch<TileArgs> B) {
   //   W0 part (kk x kk) = (P2 part) L_g[cols, :]
   // Each wave runs all of its tiles in one depth loop, as independent
   // accumulators, so that consecutive MFMAs do not wait on each other.
-  constexpr int U = KP / 16;          // P2 tiles and P1 tiles per wave
-  constexpr int UW = (U * U + 3) / 4; // W0 tiles per wave
+  constexpr int U = (KP / 16 * 4 + NW - 1) / NW;           // P2 tiles and P1 tiles per wave
+  constexpr int UW = (KP / 16 * KP / 16 + NW - 1) / NW;    // W0 tiles per wave
   const int mtk = (kk + 15) >> 4;
   const int n2 = mtk * 4;
   const int li = lane & 15, lk = lane >> 4;
@@ -1243,7 +1253,7 @@ __global__ __launch_bounds__(256) void group_tile_kernel(Batch<TileArgs> B) {
   int mt2[U], ct2[U], rt1[U], mt1[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
-    const int tt = wave + 4 * u;
+    const int tt = wave + NW * u;
     const bool v = tt < n2;
     mt2[u] = v ? tt >> 2 : 0;
     ct2[u] = v ? tt & 3 : 0;
@@ -1261,7 +1271,7 @@ __global__ __launch_bounds__(256) void group_tile_kernel(Batch<TileArgs> B) {
   }
 #pragma unroll
   for (int u = 0; u < U; ++u) {
-    if (wave + 4 * u >= n2) continue;
+    if (wave + NW * u >= n2) continue;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int m = mt2[u] * 16 + MM::row(lane, j), c = col0 + ct2[u] * 16 + li;
@@ -1273,7 +1283,7 @@ __global__ __launch_bounds__(256) void group_tile_kernel(Batch<TileArgs> B) {
   __syncthreads();   // every wave is done with Y (U_g): it now takes the P2 part
 #pragma unroll
   for (int u = 0; u < U; ++u) {
-    if (wave + 4 * u >= n2) continue;
+    if (wave + NW * u >= n2) continue;
 #pragma unroll
     for (int j = 0; j < 4; ++j)
       Y[(mt2[u] * 16 + MM::row(lane, j)) * kLdt + ct2[u] * 16 + li] = p2t[u][j];
@@ -1284,7 +1294,7 @@ __global__ __launch_bounds__(256) void group_tile_kernel(Batch<TileArgs> B) {
   int mtw[UW], ntw[UW];
 #pragma unroll
   for (int u = 0; u < UW; ++u) {
-    const int tt = wave + 4 * u;
+    const int tt = wave + NW * u;
     const bool v = tt < mtk * mtk;
     mtw[u] = v ? tt / mtk : 0;
     ntw[u] = v ? tt % mtk : 0;
@@ -1302,7 +1312,7 @@ __global__ __launch_bounds__(256) void group_tile_kernel(Batch<TileArgs> B) {
   }
 #pragma unroll
   for (int u = 0; u < UW; ++u) {
-    if (wave + 4 * u >= mtk * mtk) continue;
+    if (wave + NW * u >= mtk * mtk) continue;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int m = mtw[u] * 16 + MM::row(lane, j), n = ntw[u] * 16 + li;
@@ -1487,7 +1497,8 @@ hipError_t launch_tile(const Batch<TileArgs> &B, int nw, int nt, hipStream_t st)
       (const void *)group_tile_kernel<KP, R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (attr != hipSuccess) return attr;
   const int total = 2 * nw * nt * nt;
-  hipLaunchKernelGGL((group_tile_kernel<KP, R>), dim3((total + 7) / 8 * 8), dim3(256), lds, st, B);
+  hipLaunchKernelGGL((group_tile_kernel<KP, R>), dim3((total + 7) / 8 * 8), dim3(kTileThreads),
+                     lds, st, B);
   return hipGetLastError();
 }
 
