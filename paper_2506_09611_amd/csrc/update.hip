@@ -195,13 +195,17 @@ __global__ __launch_bounds__(256) void local_step_kernel(Batch<LocalArgs> B) {
 // ------------------------------------------------------------------------
 // group panels: sums of the split-K partials of P1, P2 and W0
 // ------------------------------------------------------------------------
+// column chunks per row strip of the tile kernel (one P1 partial each)
+__host__ __device__ constexpr int strip_chunks(int nt) { return nt < 2 ? 1 : 2; }
+
 struct ReduceArgs {
   SpinMats m;
   GroupBufs g;
   int g0, kk;
   int ntm_all;               // column strips of the launch (largest walker)
   int do_panels;             // sum the split-K partials of P1 and P2
-  int w0_mode;               // W0 partials to add: 0 none, 1 one per tile (nt^2), 2 per strip (nt)
+  int w0_mode;               // W0 partials to add: 0 none, 1 from the tile kernel (nt x
+                             // strip_chunks(nt), and P1 then has strip_chunks(nt)), 2 per strip (nt)
   int mode;                  // UniMode: uniforms drawn for the following decision
   uint64_t key0, key1, sweep, slice_code;
 };
@@ -247,6 +251,7 @@ __global__ __launch_bounds__(kRedThreads) void group_reduce_kernel(Batch<ReduceA
   const int kk = a.kk, kmax = a.g.kmax;
   const int Ns = a.m.Ns[s];
   const int nt = (Ns + 63) / 64;
+  const int np1 = a.w0_mode == 1 ? strip_chunks(nt) : nt;   // P1 partials
   const int nP = a.do_panels ? a.ntm_all * kRedParts : 0;
   const int nW = a.w0_mode ? kk : 0;
   const int x = blockIdx.x;
@@ -270,7 +275,9 @@ __global__ __launch_bounds__(kRedThreads) void group_reduce_kernel(Batch<ReduceA
     if (mrow >= nW) return;
     __shared__ double red[4][64];
     const long stride = (long)kmax * kmax;
-    const int np = a.w0_mode == 1 ? nt * nt : nt;
+    // W0 partials: one per (row strip, column chunk) from the tile kernel,
+    // one per column strip from the split-K GEMM
+    const int np = a.w0_mode == 1 ? nt * strip_chunks(nt) : nt;
     const int q = t >> 6, ln = t & 63;
     for (int n0 = 0; n0 < kk; n0 += 64) {
       const int n = n0 + ln;
@@ -325,7 +332,7 @@ __global__ __launch_bounds__(kRedThreads) void group_reduce_kernel(Batch<ReduceA
     const long ob = (long)(c0 + r0 + e2 / kk) * kmax + e2 % kk;
     const bool vb = e2 < n1;
     double sa, sb;
-    sum_pair(a.g.P1part[s] + oa, a.g.P1part[s] + (vb ? ob : oa), true, vb, (long)Ns * kmax, nt,
+    sum_pair(a.g.P1part[s] + oa, a.g.P1part[s] + (vb ? ob : oa), true, vb, (long)Ns * kmax, np1,
              sa, sb);
     a.g.P1[s][oa] = sa;
     if (vb) a.g.P1[s][ob] = sb;
@@ -1030,7 +1037,8 @@ __global__ __launch_bounds__(256) void group_q_kernel(Batch<QArgs> B) {
 struct TileArgs {
   SpinMats m;
   GroupBufs g;   // pending group: panels P1, P2, its Mc, sc and nA
-  int nmat, tpm; // matrices (2 spins x walkers) and tiles per matrix of the launch
+  int nmat, tpm; // matrices (2 spins x walkers) and (strip, chunk) slots per matrix
+  int chm;       // column-chunk slots per strip
   int flush;     // a group is pending (its flush is skipped on the device if nA == 0)
   int g0_prev, kk_prev;
   int g0, kk;    // next group (kk == 0: flush only)
@@ -1054,121 +1062,104 @@ __device__ __forceinline__ float *tile_matrix<float>(const SpinMats &m, int s) {
 // KP: kmax rounded up to a multiple of 16 (16, 32 or 64).  R: the type T is
 // kept in and multiplied in between stabilisations (double, or float for
 // the precision form); the pending group's panels and Mc arrive in double
-// and are rounded to R, and the split-K partials leave in double.
+// and are rounded to R, and the partial panels leave in double.
 //
-// 512 threads (8 waves) per 64 x 64 tile: wave w owns the 32 x 16 block
-// (rows 32 (w / 4), columns 16 (w % 4)) of the tile, so that each lane holds
-// half the registers of a 4-wave layout and two workgroups per CU give four
-// waves per SIMD to hide the load and barrier latencies.
+// One workgroup of 512 threads (8 waves) per (matrix, row strip of 64 rows,
+// column chunk).  It forms the pending group's -(P1 Mc) rows of the strip
+// once, then walks the chunk's 64 x 64 tiles of T: applies the flush to the
+// tile (wave w owns the 32 x 16 block at rows 32 (w / 4), columns 16 (w % 4),
+// and the flush operand -(P1 Mc) is held in registers in the MFMA A layout),
+// writes the tile back, writes the next group's P2 partial of the tile
+// (P2 is split over row strips) and adds the tile's share of the strip's P1
+// rows into accumulators.  P1 therefore has one partial per column chunk
+// and W0 = U_g P1 one per (strip, chunk), instead of one per tile.
 template <int KP, class R>
-__global__ __launch_bounds__(kTileThreads) void group_tile_kernel(Batch<TileArgs> B) {
+__global__ __launch_bounds__(kTileThreads, KP <= 32 ? 4 : 1) void group_tile_kernel(Batch<TileArgs> B) {
   typedef Mma<R> MM;
-  // XCD-aware placement: consecutive workgroup ids go round-robin to the 8
-  // XCDs, so XCD x receives ids x, x + 8, ...; giving it the contiguous range
-  // [x per, (x + 1) per) of (matrix, tile) indices keeps the tiles that share
-  // panel operands (same matrix, neighbouring row strips) in one L2.
-  const int per = gridDim.x >> 3;   // the grid is a multiple of 8
-  const int flat = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
-  const int tpm = B.w[0].tpm;
-  const int mat = flat / tpm;
-  if (mat >= B.w[0].nmat) return;
-  const TileArgs &a = B.w[mat >> 1];
   constexpr int NT = kTileThreads, NW = kTileThreads / 64;
-  constexpr int kPre = 64 * KP / NT;                 // per lane: a 64 x KP operand
+  constexpr int kPre = 64 * KP / NT;                 // per lane: a KP x 64 operand
   constexpr int kPreM = KP * KP >= NT ? KP * KP / NT : 1;     // per lane: KP x KP
   constexpr int kpad = KP;
+  constexpr int QS = KP / 4;                         // depth steps of the flush
+  // XCD-aware placement: consecutive workgroup ids go round-robin to the 8
+  // XCDs, so XCD x receives ids x, x + 8, ...; giving it the contiguous range
+  // [x per, (x + 1) per) of (matrix, strip, chunk) indices keeps the strips
+  // that share panel operands (same matrix) in one L2.
+  const int per = gridDim.x >> 3;   // the grid is a multiple of 8
+  const int flat = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  const int spm = B.w[0].tpm;       // (strip, chunk) slots per matrix
+  const int chm = B.w[0].chm;       // chunk slots per strip
+  const int mat = flat / spm;
+  if (mat >= B.w[0].nmat) return;
+  const TileArgs &a = B.w[mat >> 1];
   const int s = mat & 1;
   const int Ns = a.m.Ns[s];
-  const int nt = (Ns + 63) / 64;
-  const int tile = flat % tpm;
-  const int rb = tile / nt, cb = tile % nt;
-  if (rb >= nt) return;
+  const int nt = (Ns + 63) / 64, nch = strip_chunks(nt);
+  const int slot = flat % spm;
+  const int rb = slot / chm, ch = slot % chm;
+  if (rb >= nt || ch >= nch) return;
+  const int cper = (nt + nch - 1) / nch;
+  const int cb0 = ch * cper, cb1 = min(nt, cb0 + cper);
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int wm = wave >> 2, wn = wave & 3;   // 32-row half, 16-column quarter
-  const int row0 = rb * 64, col0 = cb * 64;
+  const int li = lane & 15, lk = lane >> 4;
+  const int row0 = rb * 64;
   const int kmax = a.g.kmax;
   const int kk = a.kk, kkp = a.kk_prev;
   const int kp = (kkp + 3) & ~3;            // flush rank rounded to the MFMA depth
   R *T = tile_matrix<R>(a.m, s);
   extern __shared__ double lds_raw[];
   R *lds = reinterpret_cast<R *>(lds_raw);
-
-  // ---- every load first: T tile, the pending flush's operands, next panels
-  const int ccol = wn * 16 + (lane & 15);   // this lane's tile column
-  typename MM::acc acc[2];
-#pragma unroll
-  for (int mi = 0; mi < 2; ++mi)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int r = row0 + (wm * 32 + mi * 16 + MM::row(lane, j)), c = col0 + ccol;
-      acc[mi][j] = (r < Ns && c < Ns) ? T[(long)r * Ns + c] : 0.0;
-    }
+  R *Y = lds;                      // KP x kLdt: U_g over the strip's rows (whole walk)
+  R *X = Y + KP * kLdt;            // 64 x kLdt: the current tile of T
+  R *Zb = X + 64 * kLdt;           // KP x kLdt: the tile's P2 columns, then its L_g columns
   const bool fl = a.flush && a.g.nA[0] > 0;
-  R p1v[kPre], p2v[kPre], mcv[kPreM];
-  double urv[kPre];
-  if (fl) {
-    const double *P1 = a.g.P1[s], *P2 = a.g.P2[s], *Mc = a.g.Mc[s];
+
+  // accepted rows of U_R over the chunk's columns, by the first strip
+  if (fl && rb == 0) {
+    const double *sc = a.g.sc[s];
+    double *UR = a.m.UR[s];
+    const int c0 = cb0 * 64, w = min(Ns, cb1 * 64) - c0;
+    for (int e = t; e < kkp * w; e += NT) {
+      const int m = e / w, c = c0 + e % w;
+      UR[(long)(a.g0_prev + m) * Ns + c] *= sc[m];
+    }
+  }
+  // U_g over the strip's rows (the next group's panels)
+  if (kk > 0) {
     const double *UR = a.m.UR[s];
+    for (int e = t; e < KP * 64; e += NT) {
+      const int m = e >> 6, c = e & 63;
+      Y[m * kLdt + c] = (m < kk && row0 + c < Ns) ? UR[(long)(a.g0 + m) * Ns + row0 + c] : 0.0;
+    }
+  }
+  // -(P1 Mc) rows of the strip, then into registers in the A layout of the
+  // flush: qa[mi][q] = Q[wm 32 + mi 16 + li][4 q + lk]
+  R qa[2][QS];
+  if (fl) {
+    const int ld1 = kpad + 1;
+    R *A1 = X;                       // 64 x ld1 (aliases X and Zb before the walk)
+    R *M1 = A1 + 64 * ld1;           // kpad x ld1
+    const double *P1 = a.g.P1[s], *Mc = a.g.Mc[s];
 #pragma unroll
     for (int i = 0; i < kPre; ++i) {
       const int e = t + NT * i;
-      // P1 rows of the tile (64 x kpad), P2 columns of the tile (kpad x 64)
       const int r = e / kpad, m = e % kpad;
-      p1v[i] = (e < 64 * kpad && m < kkp && row0 + r < Ns) ? P1[(long)(row0 + r) * kmax + m] : 0.0;
-      const int m2 = e >> 6, c2 = e & 63;
-      p2v[i] = (m2 < kkp && col0 + c2 < Ns) ? P2[(long)m2 * Ns + col0 + c2] : 0.0;
-      // accepted rows of U_R over this tile's columns (row-block 0 only)
-      urv[i] = (rb == 0 && m2 < kkp && col0 + c2 < Ns)
-                   ? UR[(long)(a.g0_prev + m2) * Ns + col0 + c2] : 0.0;
+      A1[r * ld1 + m] = (m < kkp && row0 + r < Ns) ? (R)P1[(long)(row0 + r) * kmax + m] : (R)0.0;
     }
 #pragma unroll
     for (int i = 0; i < kPreM; ++i) {
       const int e = t + NT * i;
       const int ma = e / kpad, mb = e % kpad;
-      mcv[i] = (e < kpad * kpad && ma < kkp && mb < kkp) ? Mc[ma * kmax + mb] : 0.0;
-    }
-  }
-  R ug[kPre], lg[kPre];
-  if (kk > 0) {
-    const double *UR = a.m.UR[s], *ULt = a.m.ULt[s];
-#pragma unroll
-    for (int i = 0; i < kPre; ++i) {
-      const int e = t + NT * i;
-      const int m = e >> 6, c = e & 63;
-      const bool ok = m < kk;
-      ug[i] = (ok && row0 + c < Ns) ? UR[(long)(a.g0 + m) * Ns + row0 + c] : 0.0;
-      lg[i] = (ok && col0 + c < Ns) ? ULt[(long)(a.g0 + m) * Ns + col0 + c] : 0.0;
-    }
-  }
-
-  // ---- (1) pending flush: T_tile -= (P1 Mc) P2
-  if (fl) {
-    const int ld1 = kpad + 1;
-    R *A1 = lds;                            // 64 x ld1: P1 rows
-    R *M1 = A1 + 64 * ld1;                  // kpad x ld1: Mc
-    R *B1 = M1 + kpad * ld1;                // kpad x kLdt: P2 columns
-#pragma unroll
-    for (int i = 0; i < kPre; ++i) {
-      const int e = t + NT * i;
-      A1[(e / kpad) * ld1 + e % kpad] = p1v[i];
-      B1[(e >> 6) * kLdt + (e & 63)] = p2v[i];
-    }
-#pragma unroll
-    for (int i = 0; i < kPreM; ++i) {
-      const int e = t + NT * i;
-      if (e < kpad * kpad) M1[(e / kpad) * ld1 + e % kpad] = mcv[i];
+      if (e < kpad * kpad) M1[ma * ld1 + mb] = (ma < kkp && mb < kkp) ? (R)Mc[ma * kmax + mb] : (R)0.0;
     }
     __syncthreads();
-    // -(P1 Mc): wave w forms rows [16 (w % 4), + 16) and the column tiles
-    // w / 4, w / 4 + 2, ...; the rows of A1 are overwritten once every
-    // wave has read them
     {
       constexpr int QT = KP / 16, QV = (QT + 1) / 2;
       const int rq = wave & 3, uh = wave >> 2;
       typename MM::acc q[QV];
 #pragma unroll
       for (int v = 0; v < QV; ++v) q[v] = MM::zero();
-      const int li = lane & 15, lk = lane >> 4;
       for (int k0 = 0; k0 < kp; k0 += 4) {
         const R av = A1[(16 * rq + li) * ld1 + k0 + lk];
 #pragma unroll
@@ -1188,135 +1179,140 @@ __global__ __launch_bounds__(kTileThreads) void group_tile_kernel(Batch<TileArgs
       }
     }
     __syncthreads();
-    // acc (this wave's 32 x 16 block) += A1 (64 x kp) B1 (kp x 64)
-    {
-      const int i0 = wm * 32 + (lane & 15), j0 = wn * 16 + (lane & 15);
-      for (int k0 = 0; k0 < kp; k0 += 4) {
-        const int kq = k0 + (lane >> 4);
-        const R a0 = A1[i0 * ld1 + kq], a1 = A1[(i0 + 16) * ld1 + kq];
-        const R b0 = B1[kq * kLdt + j0];
-        acc[0] = MM::op(a0, b0, acc[0]);
-        acc[1] = MM::op(a1, b0, acc[1]);
-      }
-    }
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+      for (int q = 0; q < QS; ++q) qa[mi][q] = A1[(wm * 32 + mi * 16 + li) * ld1 + 4 * q + lk];
+  }
+  __syncthreads();   // Y staged; A1 / M1 free
+
+  // accumulators of the strip's P1 rows over the chunk: 4 row tiles x mtk
+  // column tiles of 16 x 16, round robin over the waves
+  const int mtk = (kk + 15) >> 4;
+  constexpr int U1 = (4 * (KP / 16) + NW - 1) / NW;
+  typename MM::acc p1acc[U1];
+  int rt1[U1], mt1[U1];
+#pragma unroll
+  for (int u = 0; u < U1; ++u) {
+    const int tt = wave + NW * u;
+    const bool v = tt < 4 * mtk;
+    rt1[u] = v ? tt / mtk : 0;
+    mt1[u] = v ? tt % mtk : 0;
+    p1acc[u] = MM::zero();
+  }
+  constexpr int U2 = (4 * (KP / 16) + NW - 1) / NW;  // P2 tiles per wave and tile of T
+  const double *P2 = a.g.P2[s];
+  const double *ULt = a.m.ULt[s];
+  double *o2 = a.g.P2part[s] + (long)rb * kmax * Ns;
+
+  for (int cb = cb0; cb < cb1; ++cb) {
+    const int col0 = cb * 64;
+    // this wave's 32 x 16 block of the tile, and the tile's P2 columns
+    typename MM::acc acc[2];
 #pragma unroll
     for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int r = row0 + (wm * 32 + mi * 16 + MM::row(lane, j)), c = col0 + ccol;
-        if (r < Ns && c < Ns) T[(long)r * Ns + c] = acc[mi][j];
+        const int r = row0 + (wm * 32 + mi * 16 + MM::row(lane, j)), c = col0 + wn * 16 + li;
+        acc[mi][j] = (r < Ns && c < Ns) ? T[(long)r * Ns + c] : (R)0.0;
       }
-    if (rb == 0) {
-      const double *sc = a.g.sc[s];
-      double *UR = a.m.UR[s];
+    if (fl) {
 #pragma unroll
       for (int i = 0; i < kPre; ++i) {
         const int e = t + NT * i;
         const int m = e >> 6, c = col0 + (e & 63);
-        if (m < kkp && c < Ns) UR[(long)(a.g0_prev + m) * Ns + c] = urv[i] * sc[m];
+        Zb[m * kLdt + (e & 63)] = (m < kkp && c < Ns) ? (R)P2[(long)m * Ns + c] : (R)0.0;
       }
     }
-    __syncthreads();
+    if (fl) {
+      __syncthreads();
+      // acc (32 x 16) += -(P1 Mc) (strip rows x kp) P2 (kp x tile columns)
+#pragma unroll
+      for (int q = 0; q < QS; ++q) {
+        if (4 * q < kp) {
+          const R b0 = Zb[(4 * q + lk) * kLdt + wn * 16 + li];
+          acc[0] = MM::op(qa[0][q], b0, acc[0]);
+          acc[1] = MM::op(qa[1][q], b0, acc[1]);
+        }
+      }
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int r = row0 + (wm * 32 + mi * 16 + MM::row(lane, j)), c = col0 + wn * 16 + li;
+          if (r < Ns && c < Ns) T[(long)r * Ns + c] = acc[mi][j];
+        }
+    }
+    if (kk > 0) {
+      __syncthreads();   // every wave is done with the P2 columns in Zb
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          X[(wm * 32 + mi * 16 + MM::row(lane, j)) * kLdt + wn * 16 + li] = acc[mi][j];
+#pragma unroll
+      for (int i = 0; i < kPre; ++i) {
+        const int e = t + NT * i;
+        const int m = e >> 6, c = col0 + (e & 63);
+        Zb[m * kLdt + (e & 63)] = (m < kk && c < Ns) ? (R)ULt[(long)(a.g0 + m) * Ns + c] : (R)0.0;
+      }
+      __syncthreads();
+      // P2 partial of the tile: U_g[:, strip rows] T_tile (kk x 64)
+#pragma unroll
+      for (int u = 0; u < U2; ++u) {
+        const int tt = wave + NW * u;
+        if (tt >= 4 * mtk) continue;
+        const int mt2 = tt >> 2, ct2 = tt & 3;
+        typename MM::acc p2t = MM::zero();
+        for (int k0 = 0; k0 < 64; k0 += 4)
+          p2t = MM::op(Y[(mt2 * 16 + li) * kLdt + k0 + lk], X[(k0 + lk) * kLdt + ct2 * 16 + li], p2t);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int m = mt2 * 16 + MM::row(lane, j), c = col0 + ct2 * 16 + li;
+          if (m < kk && c < Ns) o2[(long)m * Ns + c] = p2t[j];
+        }
+      }
+      // P1 rows of the strip += T_tile L_g[tile columns, :]
+#pragma unroll
+      for (int u = 0; u < U1; ++u) {
+        if (wave + NW * u >= 4 * mtk) continue;
+        for (int k0 = 0; k0 < 64; k0 += 4)
+          p1acc[u] = MM::op(X[(rt1[u] * 16 + li) * kLdt + k0 + lk],
+                            Zb[(mt1[u] * 16 + li) * kLdt + k0 + lk], p1acc[u]);
+      }
+    }
+    __syncthreads();   // X and Zb are free for the next tile
   }
-
   if (kk <= 0) return;
-  // ---- (2) next group's split-K panel partials from the updated tile
-  R *X = lds;                      // 64 x kLdt: T tile
-  R *Y = X + 64 * kLdt;            // kpad x kLdt: U_g over the tile's rows
-  R *Z = Y + kpad * kLdt;          // kpad x kLdt: L_g over the tile's columns
+
+  // P1 partial of this chunk, then W0 partial (strip, chunk) = U_g P1_chunk
+  double *o1 = a.g.P1part[s] + (long)ch * Ns * kmax;
 #pragma unroll
-  for (int mi = 0; mi < 2; ++mi)
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-      X[(wm * 32 + mi * 16 + MM::row(lane, j)) * kLdt + ccol] = acc[mi][j];
-#pragma unroll
-  for (int i = 0; i < kPre; ++i) {
-    const int e = t + NT * i;
-    Y[(e >> 6) * kLdt + (e & 63)] = ug[i];
-    Z[(e >> 6) * kLdt + (e & 63)] = lg[i];
-  }
-  __syncthreads();
-  // 16x16 output tiles, round robin over the waves:
-  //   P2 part (kk x 64) = U_g[:, rows] T_tile,  P1 part (64 x kk) = T_tile L_g[cols, :],
-  //   W0 part (kk x kk) = (P2 part) L_g[cols, :]
-  // Each wave runs all of its tiles in one depth loop, as independent
-  // accumulators, so that consecutive MFMAs do not wait on each other.
-  constexpr int U = (KP / 16 * 4 + NW - 1) / NW;           // P2 tiles and P1 tiles per wave
-  constexpr int UW = (KP / 16 * KP / 16 + NW - 1) / NW;    // W0 tiles per wave
-  const int mtk = (kk + 15) >> 4;
-  const int n2 = mtk * 4;
-  const int li = lane & 15, lk = lane >> 4;
-  double *o2 = a.g.P2part[s] + (long)rb * kmax * Ns;
-  double *o1 = a.g.P1part[s] + (long)cb * Ns * kmax;
-  double *ow = a.g.W0part[s] + (long)(rb * nt + cb) * kmax * kmax;
-  typename MM::acc p2t[U], p1t[U];
-  int mt2[U], ct2[U], rt1[U], mt1[U];
-#pragma unroll
-  for (int u = 0; u < U; ++u) {
-    const int tt = wave + NW * u;
-    const bool v = tt < n2;
-    mt2[u] = v ? tt >> 2 : 0;
-    ct2[u] = v ? tt & 3 : 0;
-    rt1[u] = v ? tt / mtk : 0;    // P1 tiles: 4 x mtk, as many as P2 tiles
-    mt1[u] = v ? tt % mtk : 0;
-    p2t[u] = p1t[u] = MM::zero();
-  }
-  for (int k0 = 0; k0 < 64; k0 += 4) {
-    const int k = k0 + lk;
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      p2t[u] = MM::op(Y[(mt2[u] * 16 + li) * kLdt + k], X[k * kLdt + ct2[u] * 16 + li], p2t[u]);
-      p1t[u] = MM::op(X[(rt1[u] * 16 + li) * kLdt + k], Z[(mt1[u] * 16 + li) * kLdt + k], p1t[u]);
-    }
-  }
-#pragma unroll
-  for (int u = 0; u < U; ++u) {
-    if (wave + NW * u >= n2) continue;
+  for (int u = 0; u < U1; ++u) {
+    if (wave + NW * u >= 4 * mtk) continue;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int m = mt2[u] * 16 + MM::row(lane, j), c = col0 + ct2[u] * 16 + li;
-      if (m < kk && c < Ns) o2[(long)m * Ns + c] = p2t[u][j];
       const int r = row0 + rt1[u] * 16 + MM::row(lane, j), m1 = mt1[u] * 16 + li;
-      if (r < Ns && m1 < kk) o1[(long)r * kmax + m1] = p1t[u][j];
+      if (r < Ns && m1 < kk) o1[(long)r * kmax + m1] = p1acc[u][j];
+      X[(rt1[u] * 16 + MM::row(lane, j)) * kLdt + mt1[u] * 16 + li] = p1acc[u][j];
     }
   }
-  __syncthreads();   // every wave is done with Y (U_g): it now takes the P2 part
-#pragma unroll
-  for (int u = 0; u < U; ++u) {
-    if (wave + NW * u >= n2) continue;
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-      Y[(mt2[u] * 16 + MM::row(lane, j)) * kLdt + ct2[u] * 16 + li] = p2t[u][j];
-  }
+  // columns m >= kk of X are never read below (the W0 tiles stop at kk)
   __syncthreads();
-  // W0 tiles, depth split in two halves (two accumulators per tile)
-  typename MM::acc w0t[UW][2];
-  int mtw[UW], ntw[UW];
+  constexpr int UW = (KP / 16 * KP / 16 + NW - 1) / NW;
+  double *ow = a.g.W0part[s] + (long)(rb * nch + ch) * kmax * kmax;
 #pragma unroll
   for (int u = 0; u < UW; ++u) {
     const int tt = wave + NW * u;
-    const bool v = tt < mtk * mtk;
-    mtw[u] = v ? tt / mtk : 0;
-    ntw[u] = v ? tt % mtk : 0;
-    w0t[u][0] = w0t[u][1] = MM::zero();
-  }
-  for (int k0 = 0; k0 < 32; k0 += 4) {
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int k = h * 32 + k0 + lk;
-#pragma unroll
-      for (int u = 0; u < UW; ++u)
-        w0t[u][h] = MM::op(Y[(mtw[u] * 16 + li) * kLdt + k], Z[(ntw[u] * 16 + li) * kLdt + k],
-                           w0t[u][h]);
-    }
-  }
-#pragma unroll
-  for (int u = 0; u < UW; ++u) {
-    if (wave + NW * u >= mtk * mtk) continue;
+    if (tt >= mtk * mtk) continue;
+    const int mw = tt / mtk, nw2 = tt % mtk;
+    typename MM::acc w0 = MM::zero();
+    for (int k0 = 0; k0 < 64; k0 += 4)
+      w0 = MM::op(Y[(mw * 16 + li) * kLdt + k0 + lk], X[(k0 + lk) * kLdt + nw2 * 16 + li], w0);
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int m = mtw[u] * 16 + MM::row(lane, j), n = ntw[u] * 16 + li;
-      if (m < kk && n < kk) ow[m * kmax + n] = (double)w0t[u][0][j] + (double)w0t[u][1][j];
+      const int m = mw * 16 + MM::row(lane, j), n = nw2 * 16 + li;
+      if (m < kk && n < kk) ow[m * kmax + n] = w0[j];
     }
   }
 }
@@ -1489,14 +1485,13 @@ hipError_t block_decide(const GroupBufs *g, const SweepCtx *c, int nw, int g0, c
 
 template <int KP, class R>
 hipError_t launch_tile(const Batch<TileArgs> &B, int nw, int nt, hipStream_t st) {
-  const size_t flush_lds = (size_t)64 * (KP + 1) + (size_t)KP * (KP + 1) + (size_t)KP * kLdt;
-  const size_t panel_lds = (size_t)64 * kLdt + 2 * (size_t)KP * kLdt;
-  const size_t lds = sizeof(R) * std::max(flush_lds, panel_lds);
-  // at most 100 KB (KP = 64, double) of the 160 KB per CU; set once, thread-safely
+  // Y, X and Zb (the set-up's P1 rows and Mc alias X and Zb): at most 66.5 KB
+  // (KP = 32, double) so that two workgroups share a CU
+  const size_t lds = sizeof(R) * ((size_t)2 * KP + 64) * kLdt;
   static const hipError_t attr = hipFuncSetAttribute(
       (const void *)group_tile_kernel<KP, R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (attr != hipSuccess) return attr;
-  const int total = 2 * nw * nt * nt;
+  const int total = 2 * nw * nt * strip_chunks(nt);
   hipLaunchKernelGGL((group_tile_kernel<KP, R>), dim3((total + 7) / 8 * 8), dim3(kTileThreads),
                      lds, st, B);
   return hipGetLastError();
@@ -1521,7 +1516,8 @@ hipError_t group_tile(const SpinMats *m, const GroupBufs *g, int nw, int g0_prev
   const int nt = max_tiles(m, nw);
   for (int w = 0; w < nw; ++w) {
     B.w[w].nmat = 2 * nw;
-    B.w[w].tpm = nt * nt;
+    B.w[w].chm = strip_chunks(nt);
+    B.w[w].tpm = nt * strip_chunks(nt);
   }
   if (fp32) {
     if (kmax <= 16) return launch_tile<16, float>(B, nw, nt, st);
