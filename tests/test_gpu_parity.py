@@ -146,3 +146,58 @@ def test_c3_window_parity(scheme, kw, window):
     if not low:
         assert np.array_equal(ch.fields(), w.fields)
         assert green_rel_err(ch, w) < 1e-10
+
+
+@pytest.mark.parametrize("scheme,kw", [("local", {}), ("delayed", {"k": 3}), ("block", {"b": 2})])
+def test_full_filling_degenerate(scheme, kw):
+    """N_sigma = N (U_R square): every ratio is 1 up to rounding for the
+    local and delayed updates, so every flip is accepted, and G = 0."""
+    p = synth.make_problem(2, 4, 4, 4.0, n_slices=10, stab_every=5, perturb=1e-2,
+                           seed=synth.SEED_BASE + 120)
+    ch = make_chain(p, scheme, **kw)
+    w = Walker(p, scheme, **kw)
+    ch.sweep(1)
+    w.sweep()
+    meta, margin = ch.decisions()
+    n, low = compare_decisions(meta, margin, w.log, 0, p.n_slices)
+    print(f"full filling {scheme}: {n} decisions, low {low}", flush=True)
+    if scheme != "block":
+        assert bool(meta[:, 2].all())
+    for s in range(2):
+        assert np.max(np.abs(ch.green(s))) < 1e-10
+    ch.close()
+
+
+@pytest.mark.parametrize("scheme,kw", [("local", {}), ("delayed", {"k": 4}), ("block", {"b": 4})])
+def test_single_site_lattice(scheme, kw):
+    """N = 1 (one site, one fermion per spin; k and b clipped to 1)."""
+    p = synth.make_problem(1, 1, 1, 4.0, n_slices=10, stab_every=5, seed=synth.SEED_BASE + 122)
+    ch = make_chain(p, scheme, **kw)
+    w = Walker(p, scheme, **kw)
+    for sw in range(2):
+        ch.sweep(1)
+        w.sweep()
+        n, low = compare_decisions(*ch.decisions(), w.log, sw, p.n_slices)
+        if low:
+            break
+        assert np.array_equal(ch.fields(), w.fields)
+        assert green_rel_err(ch, w) < 1e-10
+    ch.close()
+
+
+@pytest.mark.parametrize("scheme,kw", [("local", {}), ("delayed", {"k": 64}), ("block", {"b": 16})])
+def test_largest_sector_window(scheme, kw):
+    """The library's largest sector, N_sigma = 1024 (and 1000 down) on 46 x 46
+    (N = 2116): a one-slice forward window against the oracle."""
+    p = synth.make_problem(46, 1024, 1000, 4.0, n_slices=10, stab_every=5, perturb=1e-3,
+                           seed=synth.SEED_BASE + 121)
+    ch = make_chain(p, scheme, **kw)
+    w = Walker(p, scheme, **kw)
+    ch.forward_window(1)
+    w.forward_window(1)
+    n, low = compare_decisions(*ch.decisions(), w.log, 0, p.n_slices)
+    print(f"46x46 {scheme}: {n} decisions equal, low {low}", flush=True)
+    if not low:
+        assert np.array_equal(ch.fields(), w.fields)
+        assert green_rel_err(ch, w) < 1e-10
+    ch.close()

@@ -119,3 +119,28 @@ def test_soc_12x12_window_split_panels(scheme, k, window):
     w.forward_window(window)
     _check(ch, w, 0, p.n_slices, f"12x12 {scheme} k={k} window {window}")
     ch.close()
+
+
+def test_soc_full_filling_and_single_site():
+    """N_e = 2N (U_R square): every ratio is det A(-2x) = 1, so every flip is
+    accepted and G = 0; and the single-site lattice (2 orbitals, both filled:
+    one fermion would leave a Kramers pair half filled)."""
+    p = synth.make_soc_problem(2, 8, -4.0, lam=0.5, dtau=0.05, n_slices=10, stab_every=5,
+                               perturb=1e-2, seed=synth.SEED_BASE + 97)
+    ch = _chain(p, "delayed", 3)
+    w = SocWalker(p, "delayed", k=3)
+    ch.sweep(1)
+    w.sweep()
+    meta, margin = ch.decisions()
+    n, low = compare_decisions(meta, margin, w.log, 0, p.n_slices)
+    assert bool(meta[:, 2].all()) and np.max(np.abs(ch.green())) < 1e-10
+    ch.close()
+    q = synth.make_soc_problem(1, 2, -4.0, lam=0.5, dtau=0.05, n_slices=10, stab_every=5,
+                               seed=synth.SEED_BASE + 98)
+    for scheme, k in (("local", 1), ("delayed", 4)):
+        ch = _chain(q, scheme, k)
+        w = SocWalker(q, scheme, k=k)
+        ch.sweep(1)
+        w.sweep()
+        _check(ch, w, 0, q.n_slices, f"1x1 soc {scheme}")
+        ch.close()

@@ -56,7 +56,7 @@ def test_workspace_bytes_valid_problem():
 
 
 @pytest.mark.parametrize("bad", [
-    dict(U=-4.0), dict(stab=7), dict(n_slices=0),
+    dict(U=-4.0), dict(stab=7), dict(n_slices=0), dict(n_up=0),
     dict(hop=np.full((16, 16), np.nan)),
 ])
 def test_workspace_bytes_rejects(bad):
@@ -109,3 +109,19 @@ def test_soc_workspace_bytes_and_rejections():
     bad = np.zeros((32, 32), np.complex128)
     bad[0, 1] = 1j                                  # not Hermitian
     assert _soc_ws(hop=bad)[0] == -1
+
+
+def test_sector_size_limit():
+    """N_sigma up to 1024 is accepted, 1025 is rejected (the stabilisation
+    kernels hold a pivot column of at most 1024 rows)."""
+    N = 1100
+    H = np.zeros((N, N))
+    for n_up, want in ((1024, 0), (1025, -1)):
+        P = np.zeros((N, n_up))
+        Pd = np.zeros((N, 4))
+        pr = binding.Problem(N, n_up, 4, binding._dptr(H), binding._dptr(P), binding._dptr(Pd),
+                             4.0, 0.05, 10, 5, 1, 0)
+        st, nbytes = _ws(pr, binding.UpdateOpts(1, 32, 1, 0))
+        assert st == want, (n_up, st)
+        if want == 0:
+            assert nbytes > 0
