@@ -16,7 +16,9 @@ Sec. IV C (the SOC-Hubbard tests):
   * local update of rank two, Eqs. (A7)-(A9): delta_i = A(x') A(x)^{-1} - 1,
     V = (v_i | v_{N+i}) delta_i, Y = (u_i | u_{N+i})^T T, R = det(1_2 + Y V);
   * delayed update with the x_m, y_m of Eqs. (28)-(30) grown into N_e x 2 and
-    2 x N_e blocks (end of Appendix A).
+    2 x N_e blocks (end of Appendix A);
+  * block force-bias update (Sec. III B, Eqs. (31)-(36), with the force bias
+    of the spin-s^y decoupling as Appendix A describes it).
 
 Readings (each listed in the design notes):
   * The T upgrade of Eq. (A9) is written with X = T V / R; for the rank-two
@@ -25,7 +27,14 @@ Readings (each listed in the design notes):
   * Accept iff u < |R| (R is real and non-negative up to rounding: the
     decoupling keeps time-reversal symmetry, so the weight has no sign
     problem, Sec. II A); the sign of Re R is logged.
-  * The block force-bias update is not part of this walker.
+  * Block force bias: the block's fields are removed by rotating its row
+    pairs of U_R by A(-x_i); the exponent is s_i = gamma <O_i> with
+    O_i = c+_{i up} c_{i dn} - c+_{i dn} c_{i up} (the operator of Eq. (A4)),
+    whose mixed estimate is real here; <c+_p c_q> = [R (L R)^{-1} L]_{q p}
+    (the paper prints the index pair as (i, N+i); the Fock-space pin fixes
+    the order).  Heat bath P(x' = +1) = 1 / (1 + e^{-2 s}); an empty flip set
+    is an accepted no-op; accept iff u < |R prior| with
+    prior = prod_F e^{s_i (x_i - x'_i)}, as in the spin-decoupled walker.
 """
 from __future__ import annotations
 
@@ -34,7 +43,7 @@ import numpy as np
 
 from . import philox
 
-SOC_SCHEMES = ("local", "delayed")
+SOC_SCHEMES = ("local", "delayed", "block")
 
 
 def soc_coupling(U: float, dtau: float) -> float:
@@ -97,9 +106,10 @@ class SocWalker:
     fields[l-1, i] = x_{l,i} = +-1; UR (2N x N_e), UL (N_e x 2N), T (N_e x N_e).
     """
 
-    def __init__(self, prob, scheme="local", k=1, fields=None):
+    def __init__(self, prob, scheme="local", k=1, b=1, fields=None):
         if scheme not in SOC_SCHEMES:
             raise ValueError(scheme)
+        self.b = max(1, int(b))
         self.p = prob
         self.N = prob.hopping.shape[0] // 2
         self.M = prob.n_slices
@@ -116,6 +126,7 @@ class SocWalker:
             fields = self.initial_fields()
         self.fields = np.array(fields, dtype=np.int8).reshape(self.M, self.N)
         self.log = []          # (sweep, dir, slice, site, accept, margin, sign)
+        self.hb_log = []       # block force bias: (sweep, dir, slice, site, x_new, margin)
         self.n_proposed = self.n_accepted = self.n_flips = 0
         self.build_initial_state()
 
@@ -200,8 +211,10 @@ class SocWalker:
     def update_slice(self, l, d):
         if self.scheme == "local":
             self.local_slice(l, d)
-        else:
+        elif self.scheme == "delayed":
             self.delayed_slice(l, d)
+        else:
+            self.block_slice(l, d)
 
     # ---------------------------------------------------------- decisions
     def flip_block(self, li, i):
@@ -209,8 +222,10 @@ class SocWalker:
         x = float(self.fields[li, i])
         return rotation(self.gamma, -x) @ rotation(self.gamma, -x) - np.eye(2)
 
-    def metropolis(self, d, li, site, R):
-        absR = abs(R)
+    def metropolis(self, d, li, site, R, extra=1.0):
+        with np.errstate(over="ignore", invalid="ignore"):
+            R = R * extra
+            absR = abs(R)
         if np.isnan(absR):
             raise FloatingPointError("acceptance ratio is NaN")
         u = philox.uniform(self.key, self.sweep_index, d * self.M + li, site, philox.PURPOSE_MH)
@@ -269,6 +284,88 @@ class SocWalker:
                     Ys = np.concatenate([Ys, Y], axis=0)
                     self._accept_rows(li, i, delta)
             self.T = T0 - Xs @ Ys
+
+    # ---------------------------------------------------- block force bias
+    def _pairs(self, sites):
+        return list(sites) + [self.N + i for i in sites]
+
+    def block_force_bias(self, li, sites):
+        """s_i = gamma <O_i>, O_i = c+_{i up} c_{i dn} - c+_{i dn} c_{i up}, with
+        the block's own fields removed: UU_R = e^{-H_I^(b)(x)} U_R (row pairs of
+        the block rotated by A(-x_i)) and (U_L UU_R)^{-1} from T by the matrix
+        Sherman-Morrison form (Eq. (35)); <c+_p c_q> = [UU_R (U_L UU_R)^{-1} U_L]_{qp}."""
+        N, nb = self.N, len(sites)
+        rows = self._pairs(sites)
+        Db = np.zeros((2 * nb, 2 * nb))
+        for j in range(nb):
+            x = float(self.fields[li, sites[j]])
+            Db[np.ix_([j, nb + j], [j, nb + j])] = rotation(self.gamma, -x) - np.eye(2)
+        V = self.UL[:, rows] @ Db
+        Um = self.UR[rows, :]
+        T = self.T
+        TV, UT = T @ V, Um @ T
+        Tb = T - TV @ np.linalg.inv(np.eye(2 * nb) + UT @ V) @ UT
+        URb = (np.eye(2 * nb) + Db) @ Um
+        svec = np.empty(nb)
+        for j, i in enumerate(sites):
+            c_up_dn = URb[nb + j] @ Tb @ self.UL[:, i]          # <c+_{i up} c_{i dn}>
+            c_dn_up = URb[j] @ Tb @ self.UL[:, N + i]           # <c+_{i dn} c_{i up}>
+            o = self.gamma * (c_up_dn - c_dn_up)
+            if abs(np.imag(o)) > 1e-10 * (1.0 + abs(o)):
+                raise FloatingPointError("force bias exponent is not real")
+            svec[j] = float(np.real(o))
+        return svec
+
+    @staticmethod
+    def heat_bath_prob(svec):
+        with np.errstate(over="ignore"):
+            return np.array([1.0 / (1.0 + np.exp(-2.0 * float(s))) for s in svec])
+
+    def block_ratio(self, li, sites, xnew, svec):
+        """R = det[1 + (U' T) V'] over the row pairs of the flip set F (the
+        rank-2|F| form of Eq. (A7)) and the prior ratio prod_F e^{s_i (x_i - x'_i)}."""
+        xold = self.fields[li, sites].astype(np.int64)
+        F = [j for j in range(len(sites)) if xnew[j] != xold[j]]
+        idx = [sites[j] for j in F]
+        nf = len(F)
+        dF = np.zeros((2 * nf, 2 * nf))
+        for q, j in enumerate(F):
+            dF[np.ix_([q, nf + q], [q, nf + q])] = self.flip_block(li, sites[j])
+        rows = self._pairs(idx)
+        Vp = self.UL[:, rows] @ dF
+        Up = self.UR[rows, :]
+        Wp = np.eye(2 * nf) + (Up @ self.T) @ Vp
+        with np.errstate(over="ignore"):
+            prior = float(np.exp(float(np.sum(svec[F] * (xold[F] - xnew[F])))))
+        return F, idx, np.linalg.det(Wp), Vp, Up, Wp, dF, prior
+
+    def block_slice(self, l, d):
+        """Block force-bias update of slice l (Sec. III B) for the spin-coupled
+        model: blocks of b consecutive sites, each with its own force bias."""
+        li = l - 1
+        N, b = self.N, min(self.b, self.N)
+        for b0 in range(0, N, b):
+            sites = list(range(b0, min(b0 + b, N)))
+            svec = self.block_force_bias(li, sites)
+            p_up = self.heat_bath_prob(svec)
+            xnew = np.empty(len(sites), np.int64)
+            for j, i in enumerate(sites):
+                u = philox.uniform(self.key, self.sweep_index, d * self.M + li, i,
+                                   philox.PURPOSE_HB)
+                xnew[j] = 1 if u < p_up[j] else -1
+                self.hb_log.append((self.sweep_index, d, li, i, int(xnew[j]), p_up[j] - u))
+            F, idx, R, Vp, Up, Wp, dF, prior = self.block_ratio(li, sites, xnew, svec)
+            if not F:
+                self.metropolis(d, li, b0, 1.0)          # empty flip set: accepted no-op
+                continue
+            if self.metropolis(d, li, b0, R, prior):
+                T = self.T
+                self.T = T - (T @ Vp) @ np.linalg.inv(Wp) @ (Up @ T)   # Eq. (36)
+                rows = self._pairs(idx)
+                self.UR[rows, :] = (np.eye(2 * len(F)) + dF) @ self.UR[rows, :]
+                for j in F:
+                    self.fields[li, sites[j]] = xnew[j]
+                self.n_flips += len(F)
 
     # ------------------------------------------------------------ observables
     def green(self):

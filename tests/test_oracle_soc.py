@@ -211,3 +211,129 @@ def test_zero_coupling_accepts_everything():
     w = SocWalker(p, "local")
     w.sweep()
     assert all(e[4] for e in w.log) and w.n_flips == w.n_proposed
+
+
+# ------------------------------------------------------------ block force bias
+def test_mixed_one_body_density_index_order():
+    """<L| c+_p c_q |R> / <L|R> = [R (L R)^{-1} L]_{qp} for Slater determinants
+    (8 modes, random complex orbitals): the order the force bias uses."""
+    rng = np.random.default_rng(11)
+    n, ne = 8, 3
+    R = rng.normal(size=(n, ne)) + 1j * rng.normal(size=(n, ne))
+    Lh = rng.normal(size=(n, ne)) + 1j * rng.normal(size=(n, ne))   # |L> has orbitals Lh
+    cdag = _fock_ops(n)
+    c = [C.T for C in cdag]
+    vr, vl = _slater(cdag, R), _slater(cdag, Lh)
+    L = Lh.conj().T
+    M = R @ np.linalg.inv(L @ R) @ L
+    ov = vl.conj() @ vr
+    for p_, q_ in [(0, 1), (3, 5), (6, 2), (4, 4)]:
+        amp = vl.conj() @ (cdag[p_] @ c[q_]) @ vr / ov
+        assert abs(amp - M[q_, p_]) < 1e-12
+
+
+def _walker_at_slice(p, X, scheme="block", b=4):
+    w = SocWalker(p, scheme, b=b, fields=X)
+    w.prop_forward(1)
+    return w
+
+
+def test_force_bias_is_the_fock_space_mixed_estimate():
+    """s_i / gamma = <psi_l| O_i |psi_r> / <psi_l|psi_r> with O_i the operator of
+    Eq. (A4), <psi_l| = U_L and |psi_r> = U_R with the block's fields removed,
+    evaluated in the 2^8-dimensional Fock space of a 2x2 lattice."""
+    p = synth.make_soc_problem(2, 4, -4.0, lam=0.5, dtau=0.1, n_slices=2, stab_every=1,
+                               perturb=5e-2, seed=synth.SEED_BASE + 86)
+    rng = np.random.default_rng(5)
+    X = rng.choice([-1, 1], size=(p.n_slices, 4)).astype(np.int8)
+    w = _walker_at_slice(p, X)
+    N, sites = 4, [0, 1, 2, 3]
+    svec = w.block_force_bias(0, sites)
+    URb = w.UR.copy()
+    for i in sites:
+        URb[[i, N + i], :] = soc.rotation(w.gamma, -float(X[0, i])) @ w.UR[[i, N + i], :]
+    cdag = _fock_ops(2 * N)
+    c = [C.T for C in cdag]
+    vr, vl = _slater(cdag, URb), _slater(cdag, w.UL.conj().T)
+    ov = vl.conj() @ vr
+    for i in sites:
+        O = cdag[i] @ c[N + i] - cdag[N + i] @ c[i]
+        o = vl.conj() @ O @ vr / ov
+        assert abs(w.gamma * o - svec[i]) < 1e-10 * max(1.0, abs(svec[i])), (i, o, svec[i])
+    assert np.max(np.abs(svec)) > 1e-3
+
+
+def test_block_ratios_equal_brute_force():
+    """R of a block proposal equals W(X') / W(X) from scratch, and whole
+    sweeps of the block update keep G equal to its definition."""
+    p = synth.make_soc_problem(2, 4, -4.0, lam=0.5, dtau=0.1, n_slices=4, stab_every=2,
+                               perturb=5e-2, seed=synth.SEED_BASE + 87)
+
+    g = soc.soc_coupling(p.U, p.dtau)
+    K, _ = soc.kinetic_propagators(p.hopping, p.dtau)
+    # one proposal (3 of 4 fields flipped) against W(X') / W(X)
+    w2 = SocWalker(p, "block", b=4)
+    w2.prop_forward(1)
+    sites = [0, 1, 2, 3]
+    svec = w2.block_force_bias(0, sites)
+    xnew = -w2.fields[0, sites].astype(np.int64)
+    xnew[1] = w2.fields[0, 1]
+    F, idx, R, *_ = w2.block_ratio(0, sites, xnew, svec)
+    Xp = w2.fields.copy()
+    Xp[0, sites] = xnew
+    ref = soc.weight(p.trial, K, g, Xp) / soc.weight(p.trial, K, g, w2.fields)
+    assert len(F) == 3 and abs(R - ref) < 1e-9 * abs(ref)
+    # every proposal of two sweeps (T upgraded between them by Eq. (36))
+    class Traced(SocWalker):
+        def block_ratio(self, li, sites, xnew, svec):
+            out = super().block_ratio(li, sites, xnew, svec)
+            self.trace.append((li, list(sites), np.array(xnew), self.fields.copy(), out[2]))
+            return out
+
+    w3 = Traced(p, "block", b=3)
+    w3.trace = []
+    w3.sweep()
+    w3.sweep()
+    n = 0
+    for li, sites, xnew, X, R in w3.trace:
+        Xp = X.copy()
+        Xp[li, sites] = xnew
+        if np.array_equal(Xp, X):
+            continue
+        ref = soc.weight(p.trial, K, g, Xp) / soc.weight(p.trial, K, g, X)
+        assert abs(R - ref) < 1e-9 * max(1.0, abs(ref)), (li, sites, R, ref)
+        n += 1
+    assert n > 10 and w3.n_flips > 0
+
+
+def test_block_update_detailed_balance_by_enumeration():
+    """2x2 lattice, M = 2 with slice 2 fixed, one block of the 4 sites of
+    slice 1: the Markov kernel
+    K(X -> X') = q(X') min(1, pi(X') q(X) / (pi(X) q(X'))) built from the
+    walker's force bias and ratios satisfies pi(X) K(X -> X') = pi(X') K(X' -> X)
+    with pi = |W| (16 configurations)."""
+    p = synth.make_soc_problem(2, 4, -4.0, lam=0.5, dtau=0.1, n_slices=2, stab_every=1,
+                               perturb=5e-2, seed=synth.SEED_BASE + 88)
+    g = soc.soc_coupling(p.U, p.dtau)
+    K, _ = soc.kinetic_propagators(p.hopping, p.dtau)
+    x2 = np.array([1, -1, -1, 1], np.int8)          # slice 2 fixed: the force bias is not 0
+    confs = [np.array([1 if (c >> i) & 1 else -1 for i in range(4)], np.int8) for c in range(16)]
+    pi = [abs(soc.weight(p.trial, K, g, np.stack([x, x2]))) for x in confs]
+    sites = [0, 1, 2, 3]
+    Km = np.zeros((16, 16))
+    for a, xa in enumerate(confs):
+        w = _walker_at_slice(p, np.stack([xa, x2]))
+        if a == 0:
+            assert np.max(np.abs(w.block_force_bias(0, sites))) > 1e-2
+        svec = w.block_force_bias(0, sites)
+        pu = w.heat_bath_prob(svec)
+        for bidx, xb in enumerate(confs):
+            q = np.prod([pu[j] if xb[j] > 0 else 1.0 - pu[j] for j in range(4)])
+            if bidx == a:
+                continue
+            F, idx, R, Vp, Up, Wp, dF, prior = w.block_ratio(0, sites, xb.astype(np.int64), svec)
+            Km[a, bidx] = q * min(1.0, abs(R * prior))
+    for a in range(16):
+        for bidx in range(16):
+            assert abs(pi[a] * Km[a, bidx] - pi[bidx] * Km[bidx, a]) < 1e-12 * max(pi)
+    assert Km.sum() > 0
