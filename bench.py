@@ -209,8 +209,8 @@ def scheme_table(p, spec, window):
 
 
 def soc_leg(args):
-    """SOC-Hubbard (Rashba lambda = 0.5, U/t = -4, n = 1): local vs delayed
-    update on forward windows of one walker, per lattice size."""
+    """SOC-Hubbard (Rashba lambda = 0.5, U/t = -4, n = 1): local, delayed and
+    block force-bias updates on forward windows of one walker, per lattice size."""
     import torch
     import synth
     from paper_2506_09611_amd import SocChain, Scheme
@@ -222,8 +222,12 @@ def soc_leg(args):
                                    seed=synth.SEED_BASE + 600 + L)
         base = None
         ks = [int(x) for x in args.soc_k.split(",") if x]
-        for k in ([] if args.soc_skip_local else [1]) + ks:
-            sc = Scheme.LOCAL if k == 1 else Scheme.DELAYED
+        bs = [int(x) for x in args.soc_b.split(",") if x]
+        runs = ([] if args.soc_skip_local else [("local", 1)]) + [("delayed", k) for k in ks] \
+            + [("block", b) for b in bs]
+        for name, k in runs:
+            sc = {"local": Scheme.LOCAL, "delayed": Scheme.DELAYED,
+                  "block": Scheme.BLOCK_FB}[name]
             c = SocChain(p.hopping, p.trial, p.U, p.dtau, p.n_slices, p.stab_every, p.seed,
                          scheme=sc, k=k, timing=True)
             torch.cuda.synchronize()
@@ -232,11 +236,11 @@ def soc_leg(args):
             torch.cuda.synchronize()
             w = time.perf_counter() - t0
             fu = args.soc_window * N
-            row = {"L": L, "n_e": N, "scheme": "local" if k == 1 else "delayed", "k": k,
+            row = {"L": L, "n_e": N, "scheme": name, "k": k,
                    "s_window": w, "field_updates_per_s": fu / w,
                    "update_only": fu / st["t_update_s"] if st["t_update_s"] > 0 else None,
                    "acceptance": st["accepted"] / max(1, st["proposed"])}
-            if k == 1:
+            if name == "local":
                 base = row
             if base is not None:
                 row["speedup_vs_local"] = (row["field_updates_per_s"]
@@ -344,6 +348,8 @@ def main():
     ap.add_argument("--soc-sizes", default="8,16,24",
                     help="lattice sides of the SOC-Hubbard table ('' for none)")
     ap.add_argument("--soc-k", default="8,16,32", help="delay ranks of the SOC table")
+    ap.add_argument("--soc-b", default="4,16",
+                    help="block sizes of the SOC block force-bias rows (empty: none)")
     ap.add_argument("--soc-skip-local", action="store_true",
                     help="leave the local update out of the SOC table (profiling runs)")
     ap.add_argument("--soc-window", type=int, default=10,

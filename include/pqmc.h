@@ -238,12 +238,16 @@ const char *pqmc_last_error(void);
  * e^{H_I(x)} mixes the row pair (i, N+i) by A(x_i) = e^{gamma x_i i sigma_y},
  * Eq. (A6).  B_l = e^{H_I(x_l)} e^{-dtau H0}; U_R is 2N x N_e, U_L N_e x 2N,
  * T = (U_L U_R)^{-1} N_e x N_e, G = 1 - U_R T U_L (2N x 2N).
- * Updates: PQMC_LOCAL (rank-two Sherman-Morrison per site, Eqs. (A7)-(A9))
- * and PQMC_DELAYED (delay_k <= 32 sites per flush, the x_m, y_m of
- * Eqs. (28)-(30) grown to N_e x 2 and 2 x N_e blocks); PQMC_BLOCK_FB is
- * rejected.  Metropolis: accept iff u < |R|, R = det(1_2 + Y V), with the
- * uniform of the spin-decoupled path (same Philox counters).  Flags: LOG,
- * TIMING.  Same workspace, stream and error rules as pqmc_create.
+ * Updates: PQMC_LOCAL (rank-two Sherman-Morrison per site, Eqs. (A7)-(A9)),
+ * PQMC_DELAYED (delay_k <= 32 sites per flush, the x_m, y_m of
+ * Eqs. (28)-(30) grown to N_e x 2 and 2 x N_e blocks) and PQMC_BLOCK_FB
+ * (block_b <= 32 sites per block, Sec. III B with the force bias
+ * s_i = gamma <c+_{i up} c_{i dn} - c+_{i dn} c_{i up}> of the spin-s^y
+ * channel, the block's own fields removed; one decision and one log entry
+ * per block, at its first site).  Metropolis: accept iff u < |R| (times the
+ * prior ratio for blocks), R = det(1 + Y V), with the uniforms of the
+ * spin-decoupled path (same Philox counters).  Flags: LOG, TIMING.  Same
+ * workspace, stream and error rules as pqmc_create.
  * ------------------------------------------------------------------------ */
 typedef struct pqmc_soc_ctx pqmc_soc_ctx;
 

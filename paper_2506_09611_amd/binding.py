@@ -294,7 +294,7 @@ def soc_workspace_bytes(n_sites, n_e, n_slices, stab_every, scheme=Scheme.DELAYE
     prob = SocProblem(int(n_sites), int(n_e), z.view(np.float64).ctypes.data_as(
         ctypes.POINTER(ctypes.c_double)), pt.view(np.float64).ctypes.data_as(
         ctypes.POINTER(ctypes.c_double)), -1.0, 0.05, int(n_slices), int(stab_every), 0, 0)
-    o = UpdateOpts(int(scheme), max(int(k), 1), 1, FLAG_LOG if log else 0)
+    o = UpdateOpts(int(scheme), max(int(k), 1), max(int(k), 1), FLAG_LOG if log else 0)
     n = ctypes.c_size_t(0)
     _check(lib, lib.pqmc_soc_workspace_bytes(ctypes.byref(prob), ctypes.byref(o),
                                              ctypes.byref(n)))
@@ -306,7 +306,7 @@ class SocChain:
 
     hopping: 2N x 2N complex128 Hermitian (basis c_1up..c_Nup, c_1dn..c_Ndn);
     trial: 2N x N_e complex128 with orthonormal columns; U <= 0; scheme
-    LOCAL or DELAYED (k <= 32).
+    LOCAL, DELAYED (k sites per flush) or BLOCK_FB (blocks of k sites); k <= 32.
     """
 
     def __init__(self, hopping, trial, U, dtau, n_slices, stab_every, seed, walker_id=0,
@@ -324,7 +324,7 @@ class SocChain:
             ctypes.POINTER(ctypes.c_double)), float(U), float(dtau), int(n_slices),
             int(stab_every), int(seed) & (2**64 - 1), int(walker_id))
         flags = (FLAG_LOG if log else 0) | (FLAG_TIMING if timing else 0)
-        self._opts = UpdateOpts(int(scheme), int(k), 1, flags)
+        self._opts = UpdateOpts(int(scheme), int(k), int(k), flags)
         nbytes = ctypes.c_size_t(0)
         _check(self._lib, self._lib.pqmc_soc_workspace_bytes(
             ctypes.byref(self._prob), ctypes.byref(self._opts), ctypes.byref(nbytes)))

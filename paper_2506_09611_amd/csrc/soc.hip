@@ -12,6 +12,8 @@
 //                    pivoting on [M | I], spread over 64-column workgroups
 //   soc_decide_kernel  the decisions of one group of k sites in 2k x 2k space
 //                    (rank-two blocks, Eqs. (A7)-(A9) and the delayed update)
+//   soc_block_decide_kernel  one block force-bias update of b sites in 2b x 2b
+//                    space (Sec. III B with the spin-s^y force bias)
 // All matrices are row-major complex128 (interleaved re, im).
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -482,6 +484,222 @@ __global__ __launch_bounds__(kDecThreads) void soc_decide_kernel(SocDecideArgs a
   }
 }
 
+// Gauss-Jordan elimination with partial pivoting of the n x n left part of
+// A (n rows, ncols columns, leading dim ld; n <= 64) in LDS, by one
+// workgroup: A <- [I | A_left^{-1} A_right] up to rounding, *det <- det(A_left)
+// (thread 0; 0 if singular).  All threads call it.
+__device__ void gj_lds(double2 *A, int n, int ncols, int ld, double2 *det, int *ok) {
+  __shared__ double bestv[kDecThreads / 64];
+  __shared__ int besti[kDecThreads / 64];
+  __shared__ int pv;
+  __shared__ double2 fcol[64];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  if (t == 0) {
+    *det = make_double2(1.0, 0.0);
+    *ok = 1;
+  }
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    double bv = -1.0;
+    int bi = n;
+    if (wave == 0) {
+      const int r = j + lane;
+      if (r < n) {
+        bv = hypot(A[r * ld + j].x, A[r * ld + j].y);
+        bi = r;
+      }
+      for (int off = 32; off > 0; off >>= 1) {
+        const double ov = __shfl_down(bv, off, 64);
+        const int oi = __shfl_down(bi, off, 64);
+        if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+      }
+      if (lane == 0) {
+        const bool good = bv > 0.0 && isfinite(bv);
+        pv = good ? bi : -1;
+        if (!good) {
+          *ok = 0;
+          *det = make_double2(0.0, 0.0);
+        }
+      }
+    }
+    __syncthreads();
+    const int p = pv;
+    if (p < 0) return;
+    if (p != j) {
+      for (int c = t; c < ncols; c += kDecThreads) {
+        const double2 x = A[j * ld + c];
+        A[j * ld + c] = A[p * ld + c];
+        A[p * ld + c] = x;
+      }
+    }
+    __syncthreads();
+    const double2 d = A[j * ld + j];
+    if (t < n) fcol[t] = A[t * ld + j];
+    if (t == 0) {
+      double2 dt = cmul(*det, d);
+      if (p != j) dt = make_double2(-dt.x, -dt.y);
+      *det = dt;
+    }
+    __syncthreads();
+    const double2 inv = cdiv(make_double2(1.0, 0.0), d);
+    for (int c = t; c < ncols; c += kDecThreads) A[j * ld + c] = cmul(A[j * ld + c], inv);
+    __syncthreads();
+    for (int e = t; e < n * ncols; e += kDecThreads) {
+      const int r = e / ncols, c = e - r * ncols;
+      if (r == j || c < j) continue;
+      A[r * ld + c] = csub(A[r * ld + c], cmul(fcol[r], A[j * ld + c]));
+    }
+    __syncthreads();
+  }
+}
+
+// Block force-bias decision for the kk sites g0 .. g0 + kk - 1 (n = 2 kk,
+// index a < kk: the up row of site g0 + a, a >= kk: the down row).
+// In: W0p = W_b T U_L[:, b] (n x n, no flip blocks).  Steps: force bias
+// s_j = gamma <O_j> with the block's fields removed from the small matrix
+// M = A_bd W0p (1 + Db W0p)^{-1} (A_bd = blocks A(-x_j), Db = A_bd - 1);
+// heat-bath fields x'_j; flip set F; R = det(1 + W0p_FF delta_F),
+// prior = prod_F e^{2 s_j x_j}; accept iff u < |R prior| (u at site g0).
+// Out: D = delta_F (1 + W0p_FF delta_F)^{-1} spread to n x n, *nflush,
+// fields and U_R row pairs of F when accepted.
+__global__ __launch_bounds__(kDecThreads) void soc_block_decide_kernel(SocDecideArgs a) {
+  extern __shared__ double2 lds[];
+  const int kk = a.kk, n = 2 * kk;
+  const int ld = 2 * n + 1;
+  double2 *Aug = lds;                // n x ld
+  __shared__ double xs[64], sv[64];
+  __shared__ int flip[64], fidx[64], nf_s, acc_s, ok_s;
+  __shared__ double2 det_s;
+  const int t = threadIdx.x;
+  int8_t *xrow = a.fields + (long)a.li * a.N + a.g0;
+  for (int j = t; j < kk; j += kDecThreads) xs[j] = (double)xrow[j];
+  __syncthreads();
+  // [E^T | W0p^T] with E = 1 + Db W0p: row r of E^T is column r of E
+  for (int e = t; e < n * n; e += kDecThreads) {
+    const int r = e / n, c = e - r * n;   // Aug[r][c] = E[c][r], Aug[r][n + c] = W0p[c][r]
+    const int jc = c < kk ? c : c - kk;
+    const double x = xs[jc];
+    // row c of Db W0p: Db rows (jc, kk + jc) = A(-x) - 1 = [[cg - 1, -x sg], [x sg, cg - 1]]
+    const double d0 = c < kk ? a.c1 - 1.0 : x * a.s1;    // coefficient of W0p[jc][r]
+    const double d1 = c < kk ? -x * a.s1 : a.c1 - 1.0;   // coefficient of W0p[kk + jc][r]
+    const double2 w0 = a.W0p[(long)jc * n + r], w1 = a.W0p[(long)(kk + jc) * n + r];
+    double2 v = make_double2(d0 * w0.x + d1 * w1.x, d0 * w0.y + d1 * w1.y);
+    if (r == c) v.x += 1.0;
+    Aug[r * ld + c] = v;
+    Aug[r * ld + n + c] = a.W0p[(long)c * n + r];
+  }
+  __syncthreads();
+  gj_lds(Aug, n, 2 * n, ld, &det_s, &ok_s);
+  // Y = W0p E^{-1}: Y[a][b] = Aug[b][n + a]; M rows of site j = A(-x_j) Y rows
+  if (t < kk) {
+    const int j = t;
+    const double x = xs[j];
+    const double2 yjj = Aug[j * ld + n + j], ydj = Aug[j * ld + n + kk + j];
+    const double2 yjd = Aug[(kk + j) * ld + n + j], ydd = Aug[(kk + j) * ld + n + kk + j];
+    // <c+_up c_dn> = M[kk + j][j] = x sg Y[j][j] + cg Y[kk + j][j]
+    // <c+_dn c_up> = M[j][kk + j] = cg Y[j][kk + j] - x sg Y[kk + j][kk + j]
+    const double up_dn = x * a.s1 * yjj.x + a.c1 * ydj.x;
+    const double dn_up = a.c1 * yjd.x - x * a.s1 * ydd.x;
+    sv[j] = ok_s ? a.gamma * (up_dn - dn_up) : 0.0;
+  }
+  __syncthreads();
+  // heat bath and the flip set
+  if (t == 0) {
+    int nf = 0;
+    for (int j = 0; j < kk; ++j) {
+      const double pu = 1.0 / (1.0 + exp(-2.0 * sv[j]));
+      const double u = philox_uniform(a.key0, a.key1, a.sweep, a.slice_code,
+                                      (uint64_t)(a.g0 + j), kPurposeHB);
+      const double xn = u < pu ? 1.0 : -1.0;
+      flip[j] = xn != xs[j];
+      if (flip[j]) fidx[nf++] = j;
+    }
+    nf_s = nf;
+    if (!ok_s) a.stats[kStError] |= kErrSingular;
+  }
+  __syncthreads();
+  const int nf = nf_s, m = 2 * nf;
+  // [S_F | I], S_F = 1 + W0p[pF, pF] delta_F, pF = (up rows of F, down rows of F)
+  const int ldf = 2 * m + 1;
+  for (int e = t; e < m * m; e += kDecThreads) {
+    const int r = e / m, c = e - r * m;
+    const int jr = fidx[r < nf ? r : r - nf], jc = fidx[c < nf ? c : c - nf];
+    const int ar = r < nf ? jr : kk + jr;
+    const double x = xs[jc];
+    // column c of W0p[pF, pF] delta_F: delta = [[dd, -x do], [x do, dd]] on (jc, kk + jc)
+    const double2 wu = a.W0p[(long)ar * n + jc], wd = a.W0p[(long)ar * n + kk + jc];
+    const double q0 = c < nf ? a.dd : -x * a.doff;       // delta[0][cc]
+    const double q1 = c < nf ? x * a.doff : a.dd;        // delta[1][cc]
+    double2 v = make_double2(wu.x * q0 + wd.x * q1, wu.y * q0 + wd.y * q1);
+    if (r == c) v.x += 1.0;
+    Aug[r * ldf + c] = v;
+    Aug[r * ldf + m + c] = make_double2(r == c ? 1.0 : 0.0, 0.0);
+  }
+  __syncthreads();
+  if (nf > 0) gj_lds(Aug, m, 2 * m, ldf, &det_s, &ok_s);
+  if (t == 0) {
+    double2 R = nf > 0 ? det_s : make_double2(1.0, 0.0);
+    double pe = 0.0;
+    for (int q = 0; q < nf; ++q) pe += 2.0 * sv[fidx[q]] * xs[fidx[q]];
+    const double prior = exp(pe);
+    const double absA = hypot(R.x, R.y) * prior;
+    const double u = philox_uniform(a.key0, a.key1, a.sweep, a.slice_code, (uint64_t)a.g0,
+                                    kPurposeMH);
+    const bool finite = !isnan(absA);
+    const bool acc = finite && u < absA && (nf == 0 || ok_s);
+    const double margin = absA - u;
+    a.stats[kStProposed] += 1;
+    a.stats[kStFieldUpdates] += kk;
+    if (acc) {
+      a.stats[kStAccepted] += 1;
+      a.stats[kStFlips] += nf;
+    }
+    if (fabs(margin) < 1e-12) a.stats[kStLowMargin] += 1;
+    if (R.x < 0.0) a.stats[kStNegative] += 1;
+    if (!finite) a.stats[kStError] |= kErrNonFinite;
+    const long long idx = a.log_base;
+    if (a.log_meta && idx < a.log_cap) {
+      a.log_meta[3 * idx + 0] = (int32_t)a.slice_code;
+      a.log_meta[3 * idx + 1] = a.g0;
+      a.log_meta[3 * idx + 2] = acc ? 1 : 0;
+      a.log_margin[idx] = margin;
+    }
+    acc_s = acc && nf > 0;
+    *a.nflush = (acc && nf > 0) ? n : 0;
+  }
+  __syncthreads();
+  // D = delta_F S_F^{-1} spread to the block's n x n (zero elsewhere)
+  for (int e = t; e < n * n; e += kDecThreads) a.D[e] = make_double2(0.0, 0.0);
+  __syncthreads();
+  if (!acc_s) return;
+  for (int e = t; e < m * m; e += kDecThreads) {
+    const int r = e / m, c = e - r * m;
+    const int q = r < nf ? r : r - nf;
+    const int j = fidx[q];
+    const double x = xs[j];
+    // rows (q, nf + q) of S_F^{-1} mixed by delta_j
+    const double2 m0 = Aug[q * ldf + m + c], m1 = Aug[(nf + q) * ldf + m + c];
+    const double e0 = r < nf ? a.dd : x * a.doff;
+    const double e1 = r < nf ? -x * a.doff : a.dd;
+    const int jc = fidx[c < nf ? c : c - nf];
+    const int ar = r < nf ? j : kk + j, ac = c < nf ? jc : kk + jc;
+    a.D[(long)ar * n + ac] = make_double2(e0 * m0.x + e1 * m1.x, e0 * m0.y + e1 * m1.y);
+  }
+  // fields and U_R row pairs of the flip set
+  for (int q = 0; q < nf; ++q) {
+    const int j = fidx[q];
+    const double x = xs[j];
+    const double d00 = 1.0 + a.dd, d01 = -x * a.doff, d10 = x * a.doff, d11 = 1.0 + a.dd;
+    double2 *p0 = a.UR + (long)(a.g0 + j) * a.ne, *p1 = a.UR + (long)(a.N + a.g0 + j) * a.ne;
+    for (int c = t; c < a.ne; c += kDecThreads) {
+      const double2 r0 = p0[c], r1 = p1[c];
+      p0[c] = make_double2(d00 * r0.x + d01 * r1.x, d00 * r0.y + d01 * r1.y);
+      p1[c] = make_double2(d10 * r0.x + d11 * r1.x, d10 * r0.y + d11 * r1.y);
+    }
+    if (t == 0) xrow[j] = (int8_t)(x > 0.0 ? -1 : 1);
+  }
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------- host
@@ -575,6 +793,18 @@ hipError_t gj_inverse(double2 *E, long ld, int n, double2 *colbuf, unsigned long
     hipLaunchKernelGGL(gj_step_kernel, grid, dim3(256), 0, st, E, ld, n, j,
                        colbuf + (size_t)(j & 1) * n, colbuf + (size_t)((j + 1) & 1) * n, stats);
   }
+  return hipGetLastError();
+}
+
+hipError_t block_decide(const SocDecideArgs &a, hipStream_t st) {
+  if (a.kk < 1 || a.kk > kSocMaxK) return hipErrorInvalidValue;
+  const int n = 2 * a.kk;
+  const size_t lds = sizeof(double2) * (size_t)n * (2 * n + 1);
+  static const hipError_t attr = hipFuncSetAttribute(
+      (const void *)soc_block_decide_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+      (int)(sizeof(double2) * 64 * 129));
+  if (attr != hipSuccess) return attr;
+  hipLaunchKernelGGL(soc_block_decide_kernel, dim3(1), dim3(kDecThreads), lds, st, a);
   return hipGetLastError();
 }
 

@@ -73,6 +73,7 @@ struct SocDecideArgs {
   int8_t *fields;          // M x N
   int li, N, ne, g0, kk;
   double dd, doff;         // delta = [[dd, -x doff], [x doff, dd]]
+  double c1, s1, gamma;    // cos gamma, sin gamma, gamma (block force bias)
   uint64_t key0, key1, sweep, slice_code;
   unsigned long long *stats;
   int32_t *log_meta;
@@ -80,6 +81,8 @@ struct SocDecideArgs {
   long long log_base, log_cap;
 };
 hipError_t decide(const SocDecideArgs &a, hipStream_t st);
+// block force bias over the kk sites of the group (log entry at log_base)
+hipError_t block_decide(const SocDecideArgs &a, hipStream_t st);
 
 }  // namespace soc
 }  // namespace pq

@@ -44,6 +44,7 @@ struct pqmc_soc_ctx {
   uint64_t sweep_index = 0;
   int position = 0;
   bool windowed = false, failed = false;
+  bool block = false;   // block force bias: one decision per group of k sites
   std::vector<hipEvent_t> ev;
   size_t ev_used = 0;
 };
@@ -70,10 +71,12 @@ pqmc_status validate(const pqmc_soc_problem *p, const pqmc_update_opts *o) {
     return err(PQMC_EINVAL, "the spin-s^y decoupling needs a finite U <= 0");
   if (p->n_slices < 1 || p->stab_every < 1 || p->n_slices % p->stab_every)
     return err(PQMC_EINVAL, "stab_every must divide n_slices");
-  if (o->scheme != PQMC_LOCAL && o->scheme != PQMC_DELAYED)
-    return err(PQMC_EINVAL, "the SOC path has the local and delayed schemes");
+  if (o->scheme != PQMC_LOCAL && o->scheme != PQMC_DELAYED && o->scheme != PQMC_BLOCK_FB)
+    return err(PQMC_EINVAL, "unknown scheme");
   if (o->scheme == PQMC_DELAYED && (o->delay_k < 1 || o->delay_k > kSocMaxK))
     return err(PQMC_EINVAL, "delay_k in [1, 32] for the SOC path");
+  if (o->scheme == PQMC_BLOCK_FB && (o->block_b < 1 || o->block_b > kSocMaxK))
+    return err(PQMC_EINVAL, "block_b in [1, 32] for the SOC path");
   if (o->flags & ~kSocFlags) return err(PQMC_EINVAL, "flags: only LOG and TIMING");
   const long n2 = 2L * p->n_sites;
   double asym = 0.0, amax = 0.0;
@@ -107,7 +110,10 @@ void fill(pqmc_soc_ctx &c, const pqmc_soc_problem *p, const pqmc_update_opts *o)
   c.seed = p->seed;
   c.walker = p->walker_id;
   c.opts = *o;
-  c.k = o->scheme == PQMC_DELAYED ? std::min(o->delay_k, c.N) : 1;
+  c.k = o->scheme == PQMC_DELAYED    ? std::min(o->delay_k, c.N)
+        : o->scheme == PQMC_BLOCK_FB ? std::min(o->block_b, c.N)
+                                     : 1;
+  c.block = o->scheme == PQMC_BLOCK_FB;
   // panels over the depth N_e in at most 8 slices of >= 64 (none below 128)
   c.ksplit = c.ne <= 128 ? 0 : std::max(64, ((c.ne + 7) / 8 + 15) / 16 * 16);
 }
@@ -300,12 +306,14 @@ int timer_mark(pqmc_soc_ctx &c) {
 
 // Field update of slice l (direction dir): groups of k sites (k = 1: the
 // local update), each: panels P2 = W_g T, P1 = T U_L[:, g], W0' = P2 U_L[:, g],
-// the decisions in 2k x 2k space, then T -= (P1 D) P2.
+// the decisions in 2k x 2k space (one decision per site, or one block
+// force-bias decision per group), then T -= (P1 D) P2.
 int update_slice(pqmc_soc_ctx &c, int l, int dir) {
   const int N = c.N, ne = c.ne, li = l - 1;
   int rc = timer_mark(c);
   if (rc) return rc;
-  for (int g0 = 0; g0 < N; g0 += c.k) {
+  int nblk = 0;
+  for (int g0 = 0; g0 < N; g0 += c.k, ++nblk) {
     const int kk = std::min(c.k, N - g0), n = 2 * kk;
     const double2 *ur0 = c.UR + (size_t)g0 * ne, *ur1 = c.UR + (size_t)(N + g0) * ne;
     const double2 *ul0 = c.ULt + (size_t)g0 * ne, *ul1 = c.ULt + (size_t)(N + g0) * ne;
@@ -358,6 +366,9 @@ int update_slice(pqmc_soc_ctx &c, int l, int dir) {
     d.kk = kk;
     d.dd = c.dd;
     d.doff = c.doff;
+    d.c1 = c.c1;
+    d.s1 = c.s1;
+    d.gamma = c.gamma;
     d.key0 = c.seed;
     d.key1 = c.walker;
     d.sweep = c.sweep_index;
@@ -365,9 +376,12 @@ int update_slice(pqmc_soc_ctx &c, int l, int dir) {
     d.stats = c.stats;
     d.log_meta = c.log_meta;
     d.log_margin = c.log_margin;
-    d.log_base = c.log_count;
+    d.log_base = c.block ? c.log_count + nblk : c.log_count;
     d.log_cap = c.log_cap;
-    PQ_HIP_CHECK(decide(d, c.st));
+    if (c.block)
+      PQ_HIP_CHECK(block_decide(d, c.st));
+    else
+      PQ_HIP_CHECK(decide(d, c.st));
     CgemmDesc q = cdesc(c.P1, n, c.D, n, c.Q, n, ne, n, n);
     q.Kdev = c.nflush;
     rc = gemm1(q, kOpN, kOpN, c.st);
@@ -381,7 +395,7 @@ int update_slice(pqmc_soc_ctx &c, int l, int dir) {
     rc = gemm1(u, kOpN, kOpN, c.st);
     if (rc) return rc;
   }
-  c.log_count += N;
+  c.log_count += c.block ? nblk : N;
   return timer_mark(c);
 }
 

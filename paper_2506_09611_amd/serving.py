@@ -194,10 +194,14 @@ class GpuBackend:
         free, _ = torch.cuda.mem_get_info()
         return int(free * fraction)
 
+    def _soc_k(self, job: Job) -> int:
+        """The SOC context's group size: the block size for block force bias."""
+        return job.b if int(job.scheme) == int(self._b.Scheme.BLOCK_FB) else job.k
+
     def walker_bytes(self, job: Job) -> int:
         if job.soc:
             return self._b.soc_workspace_bytes(job.n_sites, job.n_up, job.n_slices,
-                                               job.stab_every, job.scheme, job.k)
+                                               job.stab_every, job.scheme, self._soc_k(job))
         return self._b.workspace_bytes(job.n_sites, job.n_up, job.n_dn, job.n_slices,
                                        job.stab_every, job.scheme, job.k, job.b, job.fp32)
 
@@ -205,7 +209,7 @@ class GpuBackend:
         if job.soc:
             return self._b.SocChain(job.hopping, job.trial_up, job.U, job.dtau, job.n_slices,
                                     job.stab_every, job.seed, walker_id, scheme=job.scheme,
-                                    k=job.k, stream=self.streams[lane])
+                                    k=self._soc_k(job), stream=self.streams[lane])
         return self._b.Chain(job.hopping, job.trial_up, job.trial_dn, job.U, job.dtau,
                              job.n_slices, job.stab_every, job.seed, walker_id,
                              scheme=job.scheme, k=job.k, b=job.b, fp32=job.fp32,

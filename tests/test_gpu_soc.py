@@ -1,6 +1,6 @@
 """GPU parity of the spin-orbit coupled Hubbard path (pqmc_soc_*) against the
 oracle (oracle/soc.py): exact decisions up to the first low-margin one, the
-same fields, and G to 1e-10 relative."""
+same fields, and G to 1e-10 (relative to max(1, max |G|))."""
 import numpy as np
 import pytest
 
@@ -22,9 +22,13 @@ def _gpu():
 
 def _chain(p, scheme, k=1, **kw):
     from paper_2506_09611_amd import SocChain, Scheme
-    sc = {"local": Scheme.LOCAL, "delayed": Scheme.DELAYED}[scheme]
+    sc = {"local": Scheme.LOCAL, "delayed": Scheme.DELAYED, "block": Scheme.BLOCK_FB}[scheme]
     return SocChain(p.hopping, p.trial, p.U, p.dtau, p.n_slices, p.stab_every, p.seed,
                     p.walker_id, scheme=sc, k=k, log=True, **kw)
+
+
+def _walker(p, scheme, k):
+    return SocWalker(p, scheme, k=k, b=k)
 
 
 def _check(ch, w, sweep, M, label):
@@ -35,19 +39,20 @@ def _check(ch, w, sweep, M, label):
         return False
     assert np.array_equal(ch.fields(), w.fields), label
     G, Gr = ch.green(), w.green()
-    err = np.max(np.abs(G - Gr)) / np.max(np.abs(Gr))
+    err = np.max(np.abs(G - Gr)) / max(1.0, np.max(np.abs(Gr)))   # G = 0 at full filling
     print(f"{label}: G rel err {err:.2e}", flush=True)
     assert err < 1e-10, label
     return True
 
 
 @pytest.mark.parametrize("scheme,k", [("local", 1), ("delayed", 4), ("delayed", 16),
-                                      ("delayed", 32)])
+                                      ("delayed", 32), ("block", 1), ("block", 3),
+                                      ("block", 16)])
 def test_soc_4x4_two_sweeps(scheme, k):
     p = synth.make_soc_problem(4, 14, -4.0, lam=0.5, dtau=0.05, n_slices=20, stab_every=5,
                                perturb=1e-3, seed=synth.SEED_BASE + 90)
     ch = _chain(p, scheme, k)
-    w = SocWalker(p, scheme, k=k)
+    w = _walker(p, scheme, k)
     for sw in range(2):
         ch.sweep(1)
         w.sweep()
@@ -56,13 +61,14 @@ def test_soc_4x4_two_sweeps(scheme, k):
     ch.close()
 
 
-@pytest.mark.parametrize("scheme,k", [("local", 1), ("delayed", 8), ("delayed", 32)])
+@pytest.mark.parametrize("scheme,k", [("local", 1), ("delayed", 8), ("delayed", 32),
+                                      ("block", 4), ("block", 32)])
 def test_soc_6x6_half_filling(scheme, k):
     """2N = 72 orbitals (two GEMM tiles), N_e = 36, groups 32 + 4 at k = 32."""
     p = synth.make_soc_problem(6, 36, -4.0, lam=0.5, dtau=0.05, n_slices=10, stab_every=5,
                                perturb=1e-3, seed=synth.SEED_BASE + 91)
     ch = _chain(p, scheme, k)
-    w = SocWalker(p, scheme, k=k)
+    w = _walker(p, scheme, k)
     ch.sweep(1)
     w.sweep()
     _check(ch, w, 0, p.n_slices, f"6x6 {scheme} k={k}")
@@ -101,20 +107,21 @@ def test_soc_rejects_unsupported():
     from paper_2506_09611_amd import SocChain
     with pytest.raises(PQMCError):
         SocChain(p.hopping, p.trial, p.U, p.dtau, p.n_slices, p.stab_every, p.seed,
-                 scheme=Scheme.BLOCK_FB)
+                 scheme=Scheme.BLOCK_FB, k=33)
     with pytest.raises(PQMCError):
         SocChain(p.hopping, p.trial, p.U, p.dtau, p.n_slices, p.stab_every, p.seed,
                  scheme=Scheme.DELAYED, k=64)
 
 
-@pytest.mark.parametrize("scheme,k,window", [("delayed", 32, 10), ("local", 1, 5)])
+@pytest.mark.parametrize("scheme,k,window", [("delayed", 32, 10), ("local", 1, 5),
+                                             ("block", 32, 10), ("block", 6, 5)])
 def test_soc_12x12_window_split_panels(scheme, k, window):
     """2N = 288, N_e = 144 > 128: the panel products run as split-K slices
     (three of depth 64) added by the slice sum; groups 4 x 32 + 16."""
     p = synth.make_soc_problem(12, 144, -4.0, lam=0.5, dtau=0.05, n_slices=20, stab_every=5,
                                perturb=1e-3, seed=synth.SEED_BASE + 96)
     ch = _chain(p, scheme, k)
-    w = SocWalker(p, scheme, k=k)
+    w = _walker(p, scheme, k)
     ch.forward_window(window)
     w.forward_window(window)
     _check(ch, w, 0, p.n_slices, f"12x12 {scheme} k={k} window {window}")
@@ -127,19 +134,21 @@ def test_soc_full_filling_and_single_site():
     one fermion would leave a Kramers pair half filled)."""
     p = synth.make_soc_problem(2, 8, -4.0, lam=0.5, dtau=0.05, n_slices=10, stab_every=5,
                                perturb=1e-2, seed=synth.SEED_BASE + 97)
-    ch = _chain(p, "delayed", 3)
-    w = SocWalker(p, "delayed", k=3)
-    ch.sweep(1)
-    w.sweep()
-    meta, margin = ch.decisions()
-    n, low = compare_decisions(meta, margin, w.log, 0, p.n_slices)
-    assert bool(meta[:, 2].all()) and np.max(np.abs(ch.green())) < 1e-10
-    ch.close()
+    for scheme in ("delayed", "block"):
+        ch = _chain(p, scheme, 3)
+        w = _walker(p, scheme, 3)
+        ch.sweep(1)
+        w.sweep()
+        meta, margin = ch.decisions()
+        n, low = compare_decisions(meta, margin, w.log, 0, p.n_slices)
+        assert bool(meta[:, 2].all()) and np.max(np.abs(ch.green())) < 1e-10
+        assert np.array_equal(ch.fields(), w.fields)
+        ch.close()
     q = synth.make_soc_problem(1, 2, -4.0, lam=0.5, dtau=0.05, n_slices=10, stab_every=5,
                                seed=synth.SEED_BASE + 98)
-    for scheme, k in (("local", 1), ("delayed", 4)):
+    for scheme, k in (("local", 1), ("delayed", 4), ("block", 4)):
         ch = _chain(q, scheme, k)
-        w = SocWalker(q, scheme, k=k)
+        w = _walker(q, scheme, k)
         ch.sweep(1)
         w.sweep()
         _check(ch, w, 0, q.n_slices, f"1x1 soc {scheme}")

@@ -82,7 +82,7 @@ def test_create_rejects_bad_workspace_without_touching_gpu():
                            ctypes.byref(h)) == -1
 
 
-def _soc_ws(U=-4.0, scheme=1, k=16, flags=0, hop=None, ne=14):
+def _soc_ws(U=-4.0, scheme=1, k=16, flags=0, hop=None, ne=14, b=1):
     import synth
     p = synth.make_soc_problem(4, 14, -4.0, seed=synth.SEED_BASE + 95)
     H = np.ascontiguousarray(p.hopping if hop is None else hop, dtype=np.complex128)
@@ -92,7 +92,7 @@ def _soc_ws(U=-4.0, scheme=1, k=16, flags=0, hop=None, ne=14):
         ctypes.POINTER(ctypes.c_double)), U, 0.05, 20, 5, 1, 0)
     lib = binding.load_library()
     n = ctypes.c_size_t(0)
-    o = binding.UpdateOpts(scheme, k, 1, flags)
+    o = binding.UpdateOpts(scheme, k, b, flags)
     return lib.pqmc_soc_workspace_bytes(ctypes.byref(pr), ctypes.byref(o), ctypes.byref(n)), n.value
 
 
@@ -102,7 +102,10 @@ def test_soc_workspace_bytes_and_rejections():
     st2, n2 = _soc_ws(flags=binding.FLAG_LOG)
     assert st2 == 0 and n2 > n
     assert _soc_ws(U=1.0)[0] == -1                  # the spin-s^y decoupling needs U <= 0
-    assert _soc_ws(scheme=2)[0] == -1               # no block force bias on this path
+    assert _soc_ws(scheme=2, b=32)[0] == 0          # block force bias, b <= 32
+    assert _soc_ws(scheme=2, b=33)[0] == -1
+    assert _soc_ws(scheme=2, b=0)[0] == -1
+    assert _soc_ws(scheme=3)[0] == -1
     assert _soc_ws(k=33)[0] == -1
     assert _soc_ws(flags=binding.FLAG_FP32)[0] == -1
     assert _soc_ws(ne=33)[0] == -1                  # more fermions than orbitals
