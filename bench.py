@@ -32,10 +32,13 @@ def log(*a):
 
 
 def make_chain(p, scheme, k=1, b=1, timing=True, fp32=False):
+    """One walker run alone: one 64 x 64 tile of T per workgroup of the flush
+    kernel (tile_chunks = 64), so that a single chain still fills the GPU."""
     from paper_2506_09611_amd import Chain, Scheme
     sc = {"local": Scheme.LOCAL, "delayed": Scheme.DELAYED, "block": Scheme.BLOCK_FB}[scheme]
     return Chain(p.hopping, p.trial_up, p.trial_dn, p.U, p.dtau, p.n_slices, p.stab_every,
-                 p.seed, p.walker_id, scheme=sc, k=k, b=b, timing=timing, fp32=fp32)
+                 p.seed, p.walker_id, scheme=sc, k=k, b=b, timing=timing, fp32=fp32,
+                 tile_chunks=64)
 
 
 def kernel_work(p, cls, scheme, k, b, acc):

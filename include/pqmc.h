@@ -109,6 +109,13 @@ typedef struct {
   int32_t delay_k;            /* n_d for PQMC_DELAYED, 1 <= k <= 128 (clipped to N_s)   */
   int32_t block_b;            /* n_b for PQMC_BLOCK_FB, 1 <= b <= 64 (clipped to N_s)   */
   uint32_t flags;             /* PQMC_FLAG_*                                           */
+  int32_t tile_chunks;        /* column chunks per 64-row strip of T in the fused flush
+                                 kernel (delayed / block): 0 = 2, suited to batches of
+                                 several walkers; larger values give shorter chunks and
+                                 more workgroups (a value >= N_s/64 gives one 64 x 64
+                                 tile each, suited to one walker).  The summation order
+                                 of the panel partials, and hence G to rounding, depends
+                                 on it and on nothing else of the batch.              */
 } pqmc_update_opts;
 
 typedef struct {

@@ -96,7 +96,8 @@ def tune_delay(hopping, trial_up, trial_dn, U, dtau, stab_every, *,
     times: Dict[int, float] = {}
     for k in cands:
         chains = [Chain(hopping, trial_up, trial_dn, U, dtau, M, stab_every, seed, w,
-                        scheme=Scheme.DELAYED, k=k, timing=True, fp32=fp32)
+                        scheme=Scheme.DELAYED, k=k, timing=True, fp32=fp32,
+                        tile_chunks=64 if walkers == 1 else 0)
                   for w in range(walkers)]
         try:
             start = [c.fields() for c in chains]

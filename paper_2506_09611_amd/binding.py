@@ -66,7 +66,8 @@ class SocProblem(ctypes.Structure):
 
 class UpdateOpts(ctypes.Structure):
     _fields_ = [("scheme", ctypes.c_int32), ("delay_k", ctypes.c_int32),
-                ("block_b", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+                ("block_b", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("tile_chunks", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -160,12 +161,14 @@ class Chain:
     Philox key.  scheme / k / b: update scheme, delay rank, block size; k_max
     and b_max bound later set_opts calls (workspace sizing).  stream: the
     torch.cuda.Stream the walker's work goes to (default: the current one);
-    the workspace is allocated on it.
+    the workspace is allocated on it.  tile_chunks: column chunks per row
+    strip of the fused flush kernel (0: two, for batches; a large value: one
+    tile per workgroup, for a walker run alone).
     """
 
     def __init__(self, hopping, trial_up, trial_dn, U, dtau, n_slices, stab_every, seed,
                  walker_id=0, scheme=Scheme.LOCAL, k=1, b=1, k_max=None, b_max=None,
-                 log=False, timing=False, fp32=False, stream=None):
+                 log=False, timing=False, fp32=False, stream=None, tile_chunks=0):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device visible to torch")
@@ -183,7 +186,9 @@ class Chain:
                        | (FLAG_FP32 if fp32 else 0))
         kmax = int(k_max if k_max is not None else k)
         bmax = int(b_max if b_max is not None else b)
-        sizing = UpdateOpts(int(scheme), max(kmax, 1), max(bmax, 1), self._flags)
+        self.tile_chunks = int(tile_chunks)
+        sizing = UpdateOpts(int(scheme), max(kmax, 1), max(bmax, 1), self._flags,
+                            self.tile_chunks)
         nbytes = ctypes.c_size_t(0)
         _check(self._lib, self._lib.pqmc_workspace_bytes(ctypes.byref(self._prob),
                                                          ctypes.byref(sizing),
@@ -204,8 +209,11 @@ class Chain:
         self.set_opts(scheme, k, b)
 
     # -- calls with the C ABI's names
-    def set_opts(self, scheme, k=1, b=1, log=None, timing=None, ktime=None, fp32=None):
+    def set_opts(self, scheme, k=1, b=1, log=None, timing=None, ktime=None, fp32=None,
+                 tile_chunks=None):
         flags = self._flags
+        if tile_chunks is not None:
+            self.tile_chunks = int(tile_chunks)
         if fp32 is not None:
             flags = (flags & ~FLAG_FP32) | (FLAG_FP32 if fp32 else 0)
         if ktime is not None:
@@ -214,7 +222,7 @@ class Chain:
             flags = (flags & ~FLAG_LOG) | (FLAG_LOG if log else 0)
         if timing is not None:
             flags = (flags & ~FLAG_TIMING) | (FLAG_TIMING if timing else 0)
-        o = UpdateOpts(int(scheme), int(k), int(b), flags)
+        o = UpdateOpts(int(scheme), int(k), int(b), flags, self.tile_chunks)
         _check(self._lib, self._lib.pqmc_set_opts(self._ctx, ctypes.byref(o)))
         self.scheme, self.k, self.b, self._flags = Scheme(int(scheme)), int(k), int(b), flags
 

@@ -151,6 +151,7 @@ void layout(pqmc_ctx &c, char *base, size_t *bytes) {
   c.gb.nA = cv.take<int>(2);
   c.gb.uni = cv.take<double>(kmax + 1);
   c.gb.kmax = kmax;
+  c.gb.chunks = c.opts.tile_chunks > 0 ? c.opts.tile_chunks : 2;
   c.gb.Ns[0] = c.Ns[0];
   c.gb.Ns[1] = c.Ns[1];
   c.xtmp = cv.take<double>(N * (size_t)std::max(c.Ns[0], c.Ns[1]));
@@ -181,6 +182,7 @@ pqmc_status validate(const pqmc_problem *p, const pqmc_update_opts *o) {
   if (o->scheme < PQMC_LOCAL || o->scheme > PQMC_BLOCK_FB) return set_error(PQMC_EINVAL, "scheme");
   if (o->delay_k < 1 || o->delay_k > 128) return set_error(PQMC_EINVAL, "delay_k in [1, 128]");
   if (o->block_b < 1 || o->block_b > 64) return set_error(PQMC_EINVAL, "block_b in [1, 64]");
+  if (o->tile_chunks < 0) return set_error(PQMC_EINVAL, "tile_chunks must be >= 0");
   if ((o->flags & PQMC_FLAG_FP32) &&
       (o->scheme == PQMC_LOCAL || (o->scheme == PQMC_DELAYED ? o->delay_k : o->block_b) > 64))
     return set_error(PQMC_EINVAL, "the float32 form needs the delayed or block scheme, k, b <= 64");
@@ -936,11 +938,13 @@ pqmc_status pqmc_set_opts(pqmc_ctx *c, const pqmc_update_opts *o) {
     return set_error(PQMC_EINVAL, "block_b exceeds the workspace bound");
   if ((o->flags & PQMC_FLAG_LOG) && !c->log_alloc)
     return set_error(PQMC_EINVAL, "logging was not sized in the workspace");
+  if (o->tile_chunks < 0) return set_error(PQMC_EINVAL, "tile_chunks must be >= 0");
   if ((o->flags & PQMC_FLAG_FP32) &&
       (o->scheme == PQMC_LOCAL || (o->scheme == PQMC_DELAYED ? o->delay_k : o->block_b) > 64))
     return set_error(PQMC_EINVAL, "the float32 form needs the delayed or block scheme, k, b <= 64");
   const bool was = fp32_form(*c), now = (o->flags & PQMC_FLAG_FP32) != 0;
   c->opts = *o;
+  c->gb.chunks = o->tile_chunks > 0 ? o->tile_chunks : 2;
   // the current T moves to the representation the next call reads
   hipError_t e = hipSuccess;
   if (now && !was) {

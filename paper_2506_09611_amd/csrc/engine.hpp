@@ -120,6 +120,7 @@ struct GroupBufs {
   int *nA;                         // 2: |A|, and the flush rank (kk, or 0 when A is empty)
   int kmax;
   int Ns[2];                       // particles per spin
+  int chunks;                      // tile kernel: column chunks asked per row strip
 };
 // Uniforms drawn by the reduce kernel for the decision that follows it.
 enum UniMode { kUniNone = 0, kUniDelayed = 1, kUniBlock = 2 };

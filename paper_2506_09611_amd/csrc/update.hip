@@ -195,8 +195,17 @@ __global__ __launch_bounds__(256) void local_step_kernel(Batch<LocalArgs> B) {
 // ------------------------------------------------------------------------
 // group panels: sums of the split-K partials of P1, P2 and W0
 // ------------------------------------------------------------------------
-// column chunks per row strip of the tile kernel (one P1 partial each)
-__host__ __device__ constexpr int strip_chunks(int nt) { return nt < 2 ? 1 : 2; }
+// Column chunks per row strip of the tile kernel (one P1 partial each) for a
+// matrix of nt column strips when `want` chunks are asked for: the
+// chunks are ceil(nt / c) strips wide, and only non-empty ones count.
+__host__ __device__ inline int strip_chunk_width(int nt, int want) {
+  const int c = min(max(want, 1), nt);
+  return (nt + c - 1) / c;
+}
+__host__ __device__ inline int strip_chunks(int nt, int want) {
+  const int per = strip_chunk_width(nt, want);
+  return (nt + per - 1) / per;
+}
 
 struct ReduceArgs {
   SpinMats m;
@@ -205,7 +214,8 @@ struct ReduceArgs {
   int ntm_all;               // column strips of the launch (largest walker)
   int do_panels;             // sum the split-K partials of P1 and P2
   int w0_mode;               // W0 partials to add: 0 none, 1 from the tile kernel (nt x
-                             // strip_chunks(nt), and P1 then has strip_chunks(nt)), 2 per strip (nt)
+                             // strip_chunks(nt, g.chunks), and P1 then has
+                             // strip_chunks(nt, g.chunks)), 2 per strip (nt)
   int mode;                  // UniMode: uniforms drawn for the following decision
   uint64_t key0, key1, sweep, slice_code;
 };
@@ -251,7 +261,7 @@ __global__ __launch_bounds__(kRedThreads) void group_reduce_kernel(Batch<ReduceA
   const int kk = a.kk, kmax = a.g.kmax;
   const int Ns = a.m.Ns[s];
   const int nt = (Ns + 63) / 64;
-  const int np1 = a.w0_mode == 1 ? strip_chunks(nt) : nt;   // P1 partials
+  const int np1 = a.w0_mode == 1 ? strip_chunks(nt, a.g.chunks) : nt;   // P1 partials
   const int nP = a.do_panels ? a.ntm_all * kRedParts : 0;
   const int nW = a.w0_mode ? kk : 0;
   const int x = blockIdx.x;
@@ -277,7 +287,7 @@ __global__ __launch_bounds__(kRedThreads) void group_reduce_kernel(Batch<ReduceA
     const long stride = (long)kmax * kmax;
     // W0 partials: one per (row strip, column chunk) from the tile kernel,
     // one per column strip from the split-K GEMM
-    const int np = a.w0_mode == 1 ? nt * strip_chunks(nt) : nt;
+    const int np = a.w0_mode == 1 ? nt * strip_chunks(nt, a.g.chunks) : nt;
     const int q = t >> 6, ln = t & 63;
     for (int n0 = 0; n0 < kk; n0 += 64) {
       const int n = n0 + ln;
@@ -1094,11 +1104,11 @@ __global__ __launch_bounds__(kTileThreads, KP <= 32 ? 4 : 1) void group_tile_ker
   const TileArgs &a = B.w[mat >> 1];
   const int s = mat & 1;
   const int Ns = a.m.Ns[s];
-  const int nt = (Ns + 63) / 64, nch = strip_chunks(nt);
+  const int nt = (Ns + 63) / 64, nch = strip_chunks(nt, a.g.chunks);
   const int slot = flat % spm;
   const int rb = slot / chm, ch = slot % chm;
   if (rb >= nt || ch >= nch) return;
-  const int cper = (nt + nch - 1) / nch;
+  const int cper = strip_chunk_width(nt, a.g.chunks);
   const int cb0 = ch * cper, cb1 = min(nt, cb0 + cper);
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int wm = wave >> 2, wn = wave & 3;   // 32-row half, 16-column quarter
@@ -1484,14 +1494,14 @@ hipError_t block_decide(const GroupBufs *g, const SweepCtx *c, int nw, int g0, c
 }
 
 template <int KP, class R>
-hipError_t launch_tile(const Batch<TileArgs> &B, int nw, int nt, hipStream_t st) {
+hipError_t launch_tile(const Batch<TileArgs> &B, int nw, hipStream_t st) {
   // Y, X and Zb (the set-up's P1 rows and Mc alias X and Zb): at most 66.5 KB
   // (KP = 32, double) so that two workgroups share a CU
   const size_t lds = sizeof(R) * ((size_t)2 * KP + 64) * kLdt;
   static const hipError_t attr = hipFuncSetAttribute(
       (const void *)group_tile_kernel<KP, R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (attr != hipSuccess) return attr;
-  const int total = 2 * nw * nt * strip_chunks(nt);
+  const int total = 2 * nw * B.w[0].tpm;
   hipLaunchKernelGGL((group_tile_kernel<KP, R>), dim3((total + 7) / 8 * 8), dim3(kTileThreads),
                      lds, st, B);
   return hipGetLastError();
@@ -1514,20 +1524,23 @@ hipError_t group_tile(const SpinMats *m, const GroupBufs *g, int nw, int g0_prev
     kmax = max(kmax, g[w].kmax);
   }
   const int nt = max_tiles(m, nw);
+  int chm = 1;
+  for (int w = 0; w < nw; ++w)
+    for (int s = 0; s < 2; ++s) chm = max(chm, strip_chunks((m[w].Ns[s] + 63) / 64, g[w].chunks));
   for (int w = 0; w < nw; ++w) {
     B.w[w].nmat = 2 * nw;
-    B.w[w].chm = strip_chunks(nt);
-    B.w[w].tpm = nt * strip_chunks(nt);
+    B.w[w].chm = chm;
+    B.w[w].tpm = nt * chm;
   }
   if (fp32) {
-    if (kmax <= 16) return launch_tile<16, float>(B, nw, nt, st);
-    if (kmax <= 32) return launch_tile<32, float>(B, nw, nt, st);
-    if (kmax <= 64) return launch_tile<64, float>(B, nw, nt, st);
+    if (kmax <= 16) return launch_tile<16, float>(B, nw, st);
+    if (kmax <= 32) return launch_tile<32, float>(B, nw, st);
+    if (kmax <= 64) return launch_tile<64, float>(B, nw, st);
     return hipErrorInvalidValue;
   }
-  if (kmax <= 16) return launch_tile<16, double>(B, nw, nt, st);
-  if (kmax <= 32) return launch_tile<32, double>(B, nw, nt, st);
-  if (kmax <= 64) return launch_tile<64, double>(B, nw, nt, st);
+  if (kmax <= 16) return launch_tile<16, double>(B, nw, st);
+  if (kmax <= 32) return launch_tile<32, double>(B, nw, st);
+  if (kmax <= 64) return launch_tile<64, double>(B, nw, st);
   return hipErrorInvalidValue;
 }
 

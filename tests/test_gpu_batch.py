@@ -101,6 +101,33 @@ def test_batch_c3_window(scheme, kw, window):
         ch.close()
 
 
+def test_tile_chunks_mixed_in_one_batch():
+    """40x40: three walkers asking the flush kernel for 2, 3 and 64 (one tile
+    each) column chunks per row strip, in one batch: each takes its oracle's
+    decisions and G, and the one-tile walker equals its single run bitwise."""
+    from paper_2506_09611_amd import batch_forward_window
+    p = synth.workload("c3", n_slices=20, stab_every=10)
+    probs = _walkers(p, 3)
+    chunks = [0, 3, 64]
+    chains = [make_chain(q, "delayed", k=32, tile_chunks=c) for q, c in zip(probs, chunks)]
+    batch_forward_window(chains, 10)
+    for q, c, ch in zip(probs, chunks, chains):
+        w = Walker(q, "delayed", k=32)
+        w.forward_window(10)
+        meta, margin = ch.decisions()
+        n, low = compare_decisions(meta, margin, w.log, 0, p.n_slices)
+        print(f"tile_chunks {c}: {n} decisions equal, low {low}", flush=True)
+        if not low:
+            assert np.array_equal(ch.fields(), w.fields)
+            assert green_rel_err(ch, w) < 1e-10
+    single = make_chain(probs[2], "delayed", k=32, tile_chunks=64)
+    single.forward_window(10)
+    for s in range(2):
+        assert np.array_equal(chains[2].green(s), single.green(s))
+    for ch in chains + [single]:
+        ch.close()
+
+
 def test_batch_rejects_mismatched_shapes():
     from paper_2506_09611_amd import batch_sweep, PQMCError
     p = synth.make_problem(4, 5, 5, 4.0, n_slices=20, stab_every=5, perturb=1e-3, seed=3)

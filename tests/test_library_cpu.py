@@ -66,7 +66,8 @@ def test_workspace_bytes_rejects(bad):
 
 
 @pytest.mark.parametrize("opts", [binding.UpdateOpts(0, 0, 1, 0), binding.UpdateOpts(1, 129, 1, 0),
-                                  binding.UpdateOpts(2, 1, 65, 0), binding.UpdateOpts(5, 1, 1, 0)])
+                                  binding.UpdateOpts(2, 1, 65, 0), binding.UpdateOpts(5, 1, 1, 0),
+                                  binding.UpdateOpts(1, 16, 1, 0, -1)])
 def test_workspace_bytes_rejects_options(opts):
     st, _ = _ws(_problem(), opts)
     assert st == -1
