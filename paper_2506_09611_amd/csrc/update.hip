@@ -1077,7 +1077,7 @@ __device__ __forceinline__ float *tile_matrix<float>(const SpinMats &m, int s) {
 // One workgroup of 512 threads (8 waves) per (matrix, row strip of 64 rows,
 // column chunk).  It forms the pending group's -(P1 Mc) rows of the strip
 // once, then walks the chunk's 64 x 64 tiles of T: applies the flush to the
-// tile (wave w owns the 32 x 16 block at rows 32 (w / 4), columns 16 (w % 4),
+// tile (wave w owns the 16 x 32 block at rows 16 (w / 2), columns 32 (w % 2),
 // and the flush operand -(P1 Mc) is held in registers in the MFMA A layout),
 // writes the tile back, writes the next group's P2 partial of the tile
 // (P2 is split over row strips) and adds the tile's share of the strip's P1
@@ -1111,7 +1111,7 @@ __global__ __launch_bounds__(kTileThreads, KP <= 32 ? 4 : 1) void group_tile_ker
   const int cper = strip_chunk_width(nt, a.g.chunks);
   const int cb0 = ch * cper, cb1 = min(nt, cb0 + cper);
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int wm = wave >> 2, wn = wave & 3;   // 32-row half, 16-column quarter
+  const int wm = wave >> 1, wn = wave & 1;   // 16-row quarter, 32-column half
   const int li = lane & 15, lk = lane >> 4;
   const int row0 = rb * 64;
   const int kmax = a.g.kmax;
@@ -1144,8 +1144,8 @@ __global__ __launch_bounds__(kTileThreads, KP <= 32 ? 4 : 1) void group_tile_ker
     }
   }
   // -(P1 Mc) rows of the strip, then into registers in the A layout of the
-  // flush: qa[mi][q] = Q[wm 32 + mi 16 + li][4 q + lk]
-  R qa[2][QS];
+  // flush: qa[q] = Q[wm 16 + li][4 q + lk]
+  R qa[QS];
   if (fl) {
     const int ld1 = kpad + 1;
     R *A1 = X;                       // 64 x ld1 (aliases X and Zb before the walk)
@@ -1190,9 +1190,7 @@ __global__ __launch_bounds__(kTileThreads, KP <= 32 ? 4 : 1) void group_tile_ker
     }
     __syncthreads();
 #pragma unroll
-    for (int mi = 0; mi < 2; ++mi)
-#pragma unroll
-      for (int q = 0; q < QS; ++q) qa[mi][q] = A1[(wm * 32 + mi * 16 + li) * ld1 + 4 * q + lk];
+    for (int q = 0; q < QS; ++q) qa[q] = A1[(wm * 16 + li) * ld1 + 4 * q + lk];
   }
   __syncthreads();   // Y staged; A1 / M1 free
 
@@ -1217,14 +1215,16 @@ __global__ __launch_bounds__(kTileThreads, KP <= 32 ? 4 : 1) void group_tile_ker
 
   for (int cb = cb0; cb < cb1; ++cb) {
     const int col0 = cb * 64;
-    // this wave's 32 x 16 block of the tile, and the tile's P2 columns
+    // this wave's 16 x 32 block of the tile (two 16 x 16 column tiles), the
+    // tile's P2 columns into LDS, and its L_g rows into registers (stored to
+    // LDS once the flush is done with the P2 columns)
     typename MM::acc acc[2];
 #pragma unroll
-    for (int mi = 0; mi < 2; ++mi)
+    for (int ni = 0; ni < 2; ++ni)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int r = row0 + (wm * 32 + mi * 16 + MM::row(lane, j)), c = col0 + wn * 16 + li;
-        acc[mi][j] = (r < Ns && c < Ns) ? T[(long)r * Ns + c] : (R)0.0;
+        const int r = row0 + wm * 16 + MM::row(lane, j), c = col0 + wn * 32 + ni * 16 + li;
+        acc[ni][j] = (r < Ns && c < Ns) ? T[(long)r * Ns + c] : (R)0.0;
       }
     if (fl) {
 #pragma unroll
@@ -1234,37 +1234,46 @@ __global__ __launch_bounds__(kTileThreads, KP <= 32 ? 4 : 1) void group_tile_ker
         Zb[m * kLdt + (e & 63)] = (m < kkp && c < Ns) ? (R)P2[(long)m * Ns + c] : (R)0.0;
       }
     }
+    R lg[kPre];
+    if (kk > 0) {
+#pragma unroll
+      for (int i = 0; i < kPre; ++i) {
+        const int e = t + NT * i;
+        const int m = e >> 6, c = col0 + (e & 63);
+        lg[i] = (m < kk && c < Ns) ? (R)ULt[(long)(a.g0 + m) * Ns + c] : (R)0.0;
+      }
+    }
     if (fl) {
       __syncthreads();
-      // acc (32 x 16) += -(P1 Mc) (strip rows x kp) P2 (kp x tile columns)
+      // acc (16 x 32) += -(P1 Mc) (strip rows x kp) P2 (kp x tile columns)
 #pragma unroll
       for (int q = 0; q < QS; ++q) {
         if (4 * q < kp) {
-          const R b0 = Zb[(4 * q + lk) * kLdt + wn * 16 + li];
-          acc[0] = MM::op(qa[0][q], b0, acc[0]);
-          acc[1] = MM::op(qa[1][q], b0, acc[1]);
+          const R b0 = Zb[(4 * q + lk) * kLdt + wn * 32 + li];
+          const R b1 = Zb[(4 * q + lk) * kLdt + wn * 32 + 16 + li];
+          acc[0] = MM::op(qa[q], b0, acc[0]);
+          acc[1] = MM::op(qa[q], b1, acc[1]);
         }
       }
 #pragma unroll
-      for (int mi = 0; mi < 2; ++mi)
+      for (int ni = 0; ni < 2; ++ni)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const int r = row0 + (wm * 32 + mi * 16 + MM::row(lane, j)), c = col0 + wn * 16 + li;
-          if (r < Ns && c < Ns) T[(long)r * Ns + c] = acc[mi][j];
+          const int r = row0 + wm * 16 + MM::row(lane, j), c = col0 + wn * 32 + ni * 16 + li;
+          if (r < Ns && c < Ns) T[(long)r * Ns + c] = acc[ni][j];
         }
     }
     if (kk > 0) {
       __syncthreads();   // every wave is done with the P2 columns in Zb
 #pragma unroll
-      for (int mi = 0; mi < 2; ++mi)
+      for (int ni = 0; ni < 2; ++ni)
 #pragma unroll
         for (int j = 0; j < 4; ++j)
-          X[(wm * 32 + mi * 16 + MM::row(lane, j)) * kLdt + wn * 16 + li] = acc[mi][j];
+          X[(wm * 16 + MM::row(lane, j)) * kLdt + wn * 32 + ni * 16 + li] = acc[ni][j];
 #pragma unroll
       for (int i = 0; i < kPre; ++i) {
         const int e = t + NT * i;
-        const int m = e >> 6, c = col0 + (e & 63);
-        Zb[m * kLdt + (e & 63)] = (m < kk && c < Ns) ? (R)ULt[(long)(a.g0 + m) * Ns + c] : (R)0.0;
+        Zb[(e >> 6) * kLdt + (e & 63)] = lg[i];
       }
       __syncthreads();
       // P2 partial of the tile: U_g[:, strip rows] T_tile (kk x 64)
