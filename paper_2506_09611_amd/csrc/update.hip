@@ -1213,95 +1213,130 @@ __global__ __launch_bounds__(kTileThreads, KP <= 32 ? 4 : 1) void group_tile_ker
   const double *ULt = a.m.ULt[s];
   double *o2 = a.g.P2part[s] + (long)rb * kmax * Ns;
 
-  for (int cb = cb0; cb < cb1; ++cb) {
+  // this wave's 16 x 32 block of a tile (two 16 x 16 column tiles) and the
+  // tile's L_g rows, into registers: for the first tile here, for the next
+  // one while the current tile's panel products run
+  typename MM::acc acc[2];
+  R lg[kPre];
+  // Loads are unconditional, so that all of a tile's loads are in flight
+  // together: out-of-range elements read a clamped in-range address.  Such
+  // elements of T and P2 are finite and only ever meet a zero factor (L_g
+  // past N_s, U_g and -(P1 Mc) past the group) or a store that skips them;
+  // L_g is masked to zero past N_s when it is stored to LDS (a multiply, so
+  // that the load is not waited for early, nor sunk into a branch).
+  auto load_tile = [&](int cb, typename MM::acc *acc, double *lg) {
     const int col0 = cb * 64;
-    // this wave's 16 x 32 block of the tile (two 16 x 16 column tiles), the
-    // tile's P2 columns into LDS, and its L_g rows into registers (stored to
-    // LDS once the flush is done with the P2 columns)
-    typename MM::acc acc[2];
 #pragma unroll
     for (int ni = 0; ni < 2; ++ni)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int r = row0 + wm * 16 + MM::row(lane, j), c = col0 + wn * 32 + ni * 16 + li;
-        acc[ni][j] = (r < Ns && c < Ns) ? T[(long)r * Ns + c] : (R)0.0;
+        acc[ni][j] = T[(long)min(r, Ns - 1) * Ns + min(c, Ns - 1)];
       }
-    if (fl) {
-#pragma unroll
-      for (int i = 0; i < kPre; ++i) {
-        const int e = t + NT * i;
-        const int m = e >> 6, c = col0 + (e & 63);
-        Zb[m * kLdt + (e & 63)] = (m < kkp && c < Ns) ? (R)P2[(long)m * Ns + c] : (R)0.0;
-      }
-    }
-    R lg[kPre];
     if (kk > 0) {
 #pragma unroll
       for (int i = 0; i < kPre; ++i) {
         const int e = t + NT * i;
         const int m = e >> 6, c = col0 + (e & 63);
-        lg[i] = (m < kk && c < Ns) ? (R)ULt[(long)(a.g0 + m) * Ns + c] : (R)0.0;
+        lg[i] = ULt[(long)(a.g0 + min(m, kk - 1)) * Ns + min(c, Ns - 1)];
       }
     }
-    if (fl) {
-      __syncthreads();
-      // acc (16 x 32) += -(P1 Mc) (strip rows x kp) P2 (kp x tile columns)
+  };
+  // The walk over the chunk's tiles, one instantiation per (flush pending,
+  // next group) case, so that the compiler's wait counts know where the
+  // tile's registers come from.
+  auto walk = [&](auto flc, auto nxc) {
+    constexpr bool FL = decltype(flc)::value, NX = decltype(nxc)::value;
+    // this wave's 16 x 32 block of a tile (two 16 x 16 column tiles) and the
+    // tile's L_g rows: for the first tile here, for the next one while the
+    // current tile's panel products run
+    typename MM::acc acc[2];
+    double lg[kPre];
+    load_tile(cb0, acc, lg);
+    for (int cb = cb0; cb < cb1; ++cb) {
+      const int col0 = cb * 64;
+      const bool more = cb + 1 < cb1;
+      if (FL) {
+        // the tile's P2 columns into LDS (all loads issued before the stores)
+        R pv[kPre];
 #pragma unroll
-      for (int q = 0; q < QS; ++q) {
-        if (4 * q < kp) {
-          const R b0 = Zb[(4 * q + lk) * kLdt + wn * 32 + li];
-          const R b1 = Zb[(4 * q + lk) * kLdt + wn * 32 + 16 + li];
-          acc[0] = MM::op(qa[q], b0, acc[0]);
-          acc[1] = MM::op(qa[q], b1, acc[1]);
+        for (int i = 0; i < kPre; ++i) {
+          const int e = t + NT * i;
+          const int m = e >> 6, c = col0 + (e & 63);
+          pv[i] = (R)P2[(long)min(m, kkp - 1) * Ns + min(c, Ns - 1)];
         }
+#pragma unroll
+        for (int i = 0; i < kPre; ++i) {
+          const int e = t + NT * i;
+          Zb[(e >> 6) * kLdt + (e & 63)] = pv[i];
+        }
+        __syncthreads();
+        // acc (16 x 32) += -(P1 Mc) (strip rows x kp) P2 (kp x tile columns)
+#pragma unroll
+        for (int q = 0; q < QS; ++q) {
+          if (4 * q < kp) {
+            const R b0 = Zb[(4 * q + lk) * kLdt + wn * 32 + li];
+            const R b1 = Zb[(4 * q + lk) * kLdt + wn * 32 + 16 + li];
+            acc[0] = MM::op(qa[q], b0, acc[0]);
+            acc[1] = MM::op(qa[q], b1, acc[1]);
+          }
+        }
+#pragma unroll
+        for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int r = row0 + wm * 16 + MM::row(lane, j), c = col0 + wn * 32 + ni * 16 + li;
+            if (r < Ns && c < Ns) T[(long)r * Ns + c] = acc[ni][j];
+          }
       }
+      if (NX) {
+        if (FL) __syncthreads();   // every wave is done with the P2 columns in Zb
 #pragma unroll
-      for (int ni = 0; ni < 2; ++ni)
+        for (int ni = 0; ni < 2; ++ni)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int r = row0 + wm * 16 + MM::row(lane, j), c = col0 + wn * 32 + ni * 16 + li;
-          if (r < Ns && c < Ns) T[(long)r * Ns + c] = acc[ni][j];
+          for (int j = 0; j < 4; ++j)
+            X[(wm * 16 + MM::row(lane, j)) * kLdt + wn * 32 + ni * 16 + li] = acc[ni][j];
+#pragma unroll
+        for (int i = 0; i < kPre; ++i) {
+          const int e = t + NT * i;
+          const int m = e >> 6, c = col0 + (e & 63);
+          Zb[m * kLdt + (e & 63)] = (R)(lg[i] * ((m < kk && c < Ns) ? 1.0 : 0.0));
         }
+        if (more) load_tile(cb + 1, acc, lg);
+        __syncthreads();
+        // P2 partial of the tile: U_g[:, strip rows] T_tile (kk x 64)
+#pragma unroll
+        for (int u = 0; u < U2; ++u) {
+          const int tt = wave + NW * u;
+          if (tt >= 4 * mtk) continue;
+          const int mt2 = tt >> 2, ct2 = tt & 3;
+          typename MM::acc p2t = MM::zero();
+          for (int k0 = 0; k0 < 64; k0 += 4)
+            p2t = MM::op(Y[(mt2 * 16 + li) * kLdt + k0 + lk], X[(k0 + lk) * kLdt + ct2 * 16 + li],
+                         p2t);
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int m = mt2 * 16 + MM::row(lane, j), c = col0 + ct2 * 16 + li;
+            if (m < kk && c < Ns) o2[(long)m * Ns + c] = p2t[j];
+          }
+        }
+        // P1 rows of the strip += T_tile L_g[tile columns, :]
+#pragma unroll
+        for (int u = 0; u < U1; ++u) {
+          if (wave + NW * u >= 4 * mtk) continue;
+          for (int k0 = 0; k0 < 64; k0 += 4)
+            p1acc[u] = MM::op(X[(rt1[u] * 16 + li) * kLdt + k0 + lk],
+                              Zb[(mt1[u] * 16 + li) * kLdt + k0 + lk], p1acc[u]);
+        }
+      } else if (more) {
+        load_tile(cb + 1, acc, lg);
+      }
+      __syncthreads();   // X and Zb are free for the next tile
     }
-    if (kk > 0) {
-      __syncthreads();   // every wave is done with the P2 columns in Zb
-#pragma unroll
-      for (int ni = 0; ni < 2; ++ni)
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-          X[(wm * 16 + MM::row(lane, j)) * kLdt + wn * 32 + ni * 16 + li] = acc[ni][j];
-#pragma unroll
-      for (int i = 0; i < kPre; ++i) {
-        const int e = t + NT * i;
-        Zb[(e >> 6) * kLdt + (e & 63)] = lg[i];
-      }
-      __syncthreads();
-      // P2 partial of the tile: U_g[:, strip rows] T_tile (kk x 64)
-#pragma unroll
-      for (int u = 0; u < U2; ++u) {
-        const int tt = wave + NW * u;
-        if (tt >= 4 * mtk) continue;
-        const int mt2 = tt >> 2, ct2 = tt & 3;
-        typename MM::acc p2t = MM::zero();
-        for (int k0 = 0; k0 < 64; k0 += 4)
-          p2t = MM::op(Y[(mt2 * 16 + li) * kLdt + k0 + lk], X[(k0 + lk) * kLdt + ct2 * 16 + li], p2t);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int m = mt2 * 16 + MM::row(lane, j), c = col0 + ct2 * 16 + li;
-          if (m < kk && c < Ns) o2[(long)m * Ns + c] = p2t[j];
-        }
-      }
-      // P1 rows of the strip += T_tile L_g[tile columns, :]
-#pragma unroll
-      for (int u = 0; u < U1; ++u) {
-        if (wave + NW * u >= 4 * mtk) continue;
-        for (int k0 = 0; k0 < 64; k0 += 4)
-          p1acc[u] = MM::op(X[(rt1[u] * 16 + li) * kLdt + k0 + lk],
-                            Zb[(mt1[u] * 16 + li) * kLdt + k0 + lk], p1acc[u]);
-      }
-    }
-    __syncthreads();   // X and Zb are free for the next tile
-  }
+  };
+  if (fl && kk > 0) walk(std::true_type{}, std::true_type{});
+  else if (kk > 0) walk(std::false_type{}, std::true_type{});
+  else if (fl) walk(std::true_type{}, std::false_type{});
   if (kk <= 0) return;
 
   // P1 partial of this chunk, then W0 partial (strip, chunk) = U_g P1_chunk
