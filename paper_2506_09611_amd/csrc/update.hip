@@ -1252,24 +1252,29 @@ __global__ __launch_bounds__(kTileThreads, KP <= 32 ? 4 : 1) void group_tile_ker
     // current tile's panel products run
     typename MM::acc acc[2];
     double lg[kPre];
+    // the P2 columns of a tile, in registers from one tile to the next
+    double pv[kPre];
+    auto load_p2 = [&](int cb) {
+#pragma unroll
+      for (int i = 0; i < kPre; ++i) {
+        const int e = t + NT * i;
+        const int m = e >> 6, c = cb * 64 + (e & 63);
+        pv[i] = P2[(long)min(m, kkp - 1) * Ns + min(c, Ns - 1)];
+      }
+    };
     load_tile(cb0, acc, lg);
+    if (FL) load_p2(cb0);
     for (int cb = cb0; cb < cb1; ++cb) {
       const int col0 = cb * 64;
       const bool more = cb + 1 < cb1;
       if (FL) {
-        // the tile's P2 columns into LDS (all loads issued before the stores)
-        R pv[kPre];
+        // the tile's P2 columns into LDS, then the next tile's into registers
 #pragma unroll
         for (int i = 0; i < kPre; ++i) {
           const int e = t + NT * i;
-          const int m = e >> 6, c = col0 + (e & 63);
-          pv[i] = (R)P2[(long)min(m, kkp - 1) * Ns + min(c, Ns - 1)];
+          Zb[(e >> 6) * kLdt + (e & 63)] = (R)pv[i];
         }
-#pragma unroll
-        for (int i = 0; i < kPre; ++i) {
-          const int e = t + NT * i;
-          Zb[(e >> 6) * kLdt + (e & 63)] = pv[i];
-        }
+        if (more) load_p2(cb + 1);
         __syncthreads();
         // acc (16 x 32) += -(P1 Mc) (strip rows x kp) P2 (kp x tile columns)
 #pragma unroll
