@@ -547,6 +547,7 @@ __global__ __launch_bounds__(64) void delayed_decide_wave_kernel(Batch<DecideArg
   unsigned long long amask = 0;   // accepted sites (uniform)
   unsigned long long n_low = 0, n_neg = 0;
   bool any_nan = false;
+  double my_margin = 0.0;         // lane j: the margin of site j (logged after the loop)
 #pragma unroll
   for (int J = 0; J < R; ++J) {
     for (int jl = 0; jl < 8; ++jl) {
@@ -562,6 +563,9 @@ __global__ __launch_bounds__(64) void delayed_decide_wave_kernel(Batch<DecideArg
         r1[i] = __shfl(e1[J][i], src_r, 64);
       }
       const double p0 = readlane_f64(e0[J][J], jl * 9), p1 = readlane_f64(e1[J][J], jl * 9);
+      // used only on acceptance; computed here, off the decision's critical path
+      const double ip0 = recip(p0), ip1 = recip(p1);
+      asm volatile("" ::"v"(ip0), "v"(ip1));
       const double u = readlane_f64(ul, j);
       const double Rr = p0 * p1;
       const double absA = fabs(Rr);
@@ -571,10 +575,9 @@ __global__ __launch_bounds__(64) void delayed_decide_wave_kernel(Batch<DecideArg
       n_low += (fabs(margin) < 1e-12) ? 1 : 0;
       n_neg += (Rr < 0.0) ? 1 : 0;
       any_nan = any_nan || !finite;
-      if (lane == 0) record_decision(C, C.log_base + A.g0 + j, A.g0 + j, acc, margin);
+      my_margin = lane == j ? margin : my_margin;
       if (acc) {
         amask |= 1ull << j;
-        const double ip0 = recip(p0), ip1 = recip(p1);
 #pragma unroll
         for (int i = 0; i < R; ++i) {
           const double ci0 = c0[i] * ip0, ci1 = c1[i] * ip1;
@@ -617,6 +620,8 @@ __global__ __launch_bounds__(64) void delayed_decide_wave_kernel(Batch<DecideArg
     A.g.nA[0] = n_acc;
     A.g.nA[1] = n_acc ? kk : 0;
   }
+  if (lane < kk)
+    record_decision(C, C.log_base + A.g0 + lane, A.g0 + lane, (amask >> lane) & 1, my_margin);
   // row scales and flipped fields, one lane per site
   if (lane < kk) {
     const bool mine = (amask >> lane) & 1;
@@ -685,6 +690,7 @@ __global__ __launch_bounds__(128) void delayed_decide_spin_kernel(Batch<DecideAr
   unsigned long long amask = 0;   // accepted sites (uniform)
   unsigned long long n_low = 0, n_neg = 0;
   bool any_nan = false;
+  double my_margin = 0.0;         // lane j: the margin of site j (logged after the loop)
 #pragma unroll
   for (int J = 0; J < R; ++J) {
     for (int jl = 0; jl < 8; ++jl) {
@@ -698,6 +704,9 @@ __global__ __launch_bounds__(128) void delayed_decide_spin_kernel(Batch<DecideAr
         r[i] = __shfl(e[J][i], src_r, 64);
       }
       const double p = readlane_f64(e[J][J], jl * 9);
+      // used only on acceptance; computed here, while the pivots are exchanged
+      const double ip = recip(p);
+      asm volatile("" ::"v"(ip));
       if (lane == 0) piv[j & 1][sp] = p;
       __syncthreads();
       const double p0 = piv[j & 1][0], p1 = piv[j & 1][1];
@@ -710,10 +719,9 @@ __global__ __launch_bounds__(128) void delayed_decide_spin_kernel(Batch<DecideAr
       n_low += (fabs(margin) < 1e-12) ? 1 : 0;
       n_neg += (Rr < 0.0) ? 1 : 0;
       any_nan = any_nan || !finite;
-      if (t == 0) record_decision(C, C.log_base + A.g0 + j, A.g0 + j, acc, margin);
+      my_margin = lane == j ? margin : my_margin;
       if (acc) {
         amask |= 1ull << j;
-        const double ip = recip(p);
 #pragma unroll
         for (int i = 0; i < R; ++i) {
           const double ci = c[i] * ip;
@@ -744,6 +752,8 @@ __global__ __launch_bounds__(128) void delayed_decide_spin_kernel(Batch<DecideAr
     A.g.nA[0] = n_acc;
     A.g.nA[1] = n_acc ? kk : 0;
   }
+  if (sp == 0 && lane < kk)
+    record_decision(C, C.log_base + A.g0 + lane, A.g0 + lane, (amask >> lane) & 1, my_margin);
   // row scales of spin sp; wave 0 also flips the accepted fields
   if (lane < kk) {
     const bool mine = (amask >> lane) & 1;
