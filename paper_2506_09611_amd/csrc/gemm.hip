@@ -61,30 +61,34 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmBatch batch, int nspl
   const double *A = g.A, *B = g.B;
   const long lda = g.lda, ldb = g.ldb;
 
+  // Loads are unconditional (clamped in-range addresses) and issue together;
+  // the depth tail is zeroed and the field scaling applied when the slice is
+  // stored to LDS, after the current slice's products, so that no load is
+  // waited for early.  Rows and columns past M and N only reach outputs that
+  // are not stored.
+  const int8_t *ksf = g.ks_field;
+  const double ks_pos = g.ks_pos, ks_neg = g.ks_neg;
   double ra[NA], rb[NB];
+  int8_t fb[NB];
+  int kload = 0;   // depth offset of the slice in ra / rb
   auto load = [&](int k0) {
+    kload = k0;
 #pragma unroll
     for (int p = 0; p < NA; ++p) {
       int mm, kk;
       if (!TA) { kk = t % BK; mm = t / BK + (256 / BK) * p; }
       else     { mm = t % BM; kk = t / BM + (256 / BM) * p; }
-      const int gi = m0 + mm, gk = k0 + kk;
-      double v = 0.0;
-      if (gi < M && gk < kend) v = TA ? A[(long)gk * lda + gi] : A[(long)gi * lda + gk];
-      ra[p] = v;
+      const int gi = min(m0 + mm, M - 1), gk = min(k0 + kk, kend - 1);
+      ra[p] = TA ? A[(long)gk * lda + gi] : A[(long)gi * lda + gk];
     }
 #pragma unroll
     for (int p = 0; p < NB; ++p) {
       int nn, kk;
       if (!TB) { nn = t % BN; kk = t / BN + (256 / BN) * p; }
       else     { kk = t % BK; nn = t / BK + (256 / BK) * p; }
-      const int gj = n0 + nn, gk = k0 + kk;
-      double v = 0.0;
-      if (gj < N && gk < kend) {
-        v = TB ? B[(long)gj * ldb + gk] : B[(long)gk * ldb + gj];
-        if (g.ks_field) v *= (g.ks_field[gk] > 0) ? g.ks_pos : g.ks_neg;
-      }
-      rb[p] = v;
+      const int gj = min(n0 + nn, N - 1), gk = min(k0 + kk, kend - 1);
+      rb[p] = TB ? B[(long)gj * ldb + gk] : B[(long)gk * ldb + gj];
+      fb[p] = ksf ? ksf[gk] : (int8_t)1;
     }
   };
   auto store = [&](int buf) {
@@ -93,16 +97,32 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmBatch batch, int nspl
       int mm, kk;
       if (!TA) { kk = t % BK; mm = t / BK + (256 / BK) * p; }
       else     { mm = t % BM; kk = t / BM + (256 / BM) * p; }
-      As[buf][kk][mm] = ra[p];
+      As[buf][kk][mm] = ra[p] * (kload + kk < kend ? 1.0 : 0.0);
     }
 #pragma unroll
     for (int p = 0; p < NB; ++p) {
       int nn, kk;
       if (!TB) { nn = t % BN; kk = t / BN + (256 / BN) * p; }
       else     { kk = t % BK; nn = t / BK + (256 / BK) * p; }
-      Bs[buf][kk][nn] = rb[p];
+      Bs[buf][kk][nn] = rb[p] * (fb[p] > 0 ? ks_pos : ks_neg);
     }
   };
+
+  // fields of the output rows (epilogue scaling), loaded before the depth loop
+  const int8_t *rsf = g.rs_field;
+  int rf[MI][4];   // one register each: packing bytes would wait for every load
+  if (rsf) {
+#pragma unroll
+    for (int mi = 0; mi < MI; ++mi)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        rf[mi][j] = rsf[min(m0 + wm * WM + mi * 16 + (lane >> 4) + 4 * j, M - 1)];
+  } else {
+#pragma unroll
+    for (int mi = 0; mi < MI; ++mi)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) rf[mi][j] = 1;
+  }
 
   dbl4 acc[MI][NI];
 #pragma unroll
@@ -142,6 +162,21 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmBatch batch, int nspl
   double *C = g.C;
   if (g.ksplit > 0) C += (long)split * g.csplit;
   const bool split_out = g.ksplit > 0;
+  const double rs_pos = g.rs_pos, rs_neg = g.rs_neg, alpha = g.alpha, beta = g.beta;
+  // the epilogue's Cin operands are loaded together first
+  double cin[MI][NI][4];
+  const bool use_cin = !split_out && beta != 0.0;
+#pragma unroll
+  for (int mi = 0; mi < MI; ++mi)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int row = min(m0 + wm * WM + mi * 16 + (lane >> 4) + 4 * j, M - 1);
+#pragma unroll
+      for (int ni = 0; ni < NI; ++ni) {
+        const int col = min(n0 + wn * WN + ni * 16 + (lane & 15), N - 1);
+        cin[mi][ni][j] = use_cin ? g.Cin[(long)row * g.ldcin + col] : 0.0;
+      }
+    }
 #pragma unroll
   for (int mi = 0; mi < MI; ++mi)
 #pragma unroll
@@ -151,10 +186,10 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmBatch batch, int nspl
         const int row = m0 + wm * WM + mi * 16 + (lane >> 4) + 4 * j;
         const int col = n0 + wn * WN + ni * 16 + (lane & 15);
         if (row < M && col < N) {
-          double v = g.alpha * acc[mi][ni][j];
-          if (g.rs_field) v *= (g.rs_field[row] > 0) ? g.rs_pos : g.rs_neg;
+          double v = alpha * acc[mi][ni][j];
+          if (rsf) v *= (rf[mi][j] > 0) ? rs_pos : rs_neg;
           if (!split_out) {
-            if (g.beta != 0.0) v += g.beta * g.Cin[(long)row * g.ldcin + col];
+            if (use_cin) v += beta * cin[mi][ni][j];
             if (g.addI && row == col) v += 1.0;
           }
           C[(long)row * g.ldc + col] = v;
