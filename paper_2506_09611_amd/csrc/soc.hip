@@ -75,50 +75,78 @@ __global__ __launch_bounds__(256) void cgemm_kernel(CgemmBatch b, int ns) {
     return;
   }
   if (K <= 0 && g.Kdev && g.beta.x == 1.0 && g.beta.y == 0.0 && g.Cin == g.C && !g.addI) return;
-  __shared__ double2 As[BK][BM];
-  __shared__ double2 Bs[BK][BN];
+  // Two LDS buffers: the next depth slice is loaded into registers while the
+  // current one is multiplied, then stored to the other buffer.  Loads are
+  // unconditional (clamped in-range addresses) so that they issue together;
+  // the conjugation and the zeroing of the depth tail are applied when the
+  // slice is stored.  Rows and columns past M and N only reach outputs that
+  // are not stored.
+  __shared__ double2 As[2][BK][BM];
+  __shared__ double2 Bs[2][BK][BN];
   const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
   double2 acc[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = make_double2(0.0, 0.0);
-  for (int k0 = kbeg; k0 < kend; k0 += BK) {
+  double2 ra[4], rb[4];
+  auto a_index = [&](int p, int &r, int &kk) {
+    const int e = t + 256 * p;
+    if (OPA == kOpN) { r = e >> 4; kk = e & 15; } else { kk = e >> 6; r = e & 63; }
+  };
+  auto b_index = [&](int p, int &c, int &kb) {
+    const int e = t + 256 * p;
+    if (OPB == kOpN) { kb = e >> 6; c = e & 63; } else { c = e >> 4; kb = e & 15; }
+  };
+  auto load = [&](int k0) {
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
-      const int e = t + 256 * p;
-      int r, kk;
-      if (OPA == kOpN) { r = e >> 4; kk = e & 15; } else { kk = e >> 6; r = e & 63; }
-      const int gr = m0 + r, gk = k0 + kk;
-      As[kk][r] = (gr < M && gk < kend) ? op_load<OPA>(g.A, g.lda, gr, gk) : make_double2(0.0, 0.0);
-      int c, kb;
-      if (OPB == kOpN) { kb = e >> 6; c = e & 63; } else { c = e >> 4; kb = e & 15; }
-      const int gc = n0 + c, gkb = k0 + kb;
+      int r, kk, c, kb;
+      a_index(p, r, kk);
+      const int gr = min(m0 + r, M - 1), gk = min(k0 + kk, kend - 1);
+      ra[p] = OPA == kOpN ? g.A[(long)gr * g.lda + gk] : g.A[(long)gk * g.lda + gr];
+      b_index(p, c, kb);
+      const int gc = min(n0 + c, N - 1), gkb = min(k0 + kb, kend - 1);
       // element (k, c) of op(B): N -> B[k][c], T -> B[c][k], H -> conj(B[c][k])
-      double2 v = make_double2(0.0, 0.0);
-      if (gc < N && gkb < kend) {
-        if (OPB == kOpN) v = g.B[(long)gkb * g.ldb + gc];
-        else {
-          v = g.B[(long)gc * g.ldb + gkb];
-          if (OPB == kOpH) v = cconj(v);
-        }
-      }
-      Bs[kb][c] = v;
+      rb[p] = OPB == kOpN ? g.B[(long)gkb * g.ldb + gc] : g.B[(long)gc * g.ldb + gkb];
     }
-    __syncthreads();
+  };
+  auto store = [&](int buf, int k0) {
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      int r, kk, c, kb;
+      a_index(p, r, kk);
+      const double m = k0 + kk < kend ? 1.0 : 0.0;
+      As[buf][kk][r] = make_double2(ra[p].x * m, (OPA == kOpH ? -ra[p].y : ra[p].y) * m);
+      b_index(p, c, kb);
+      Bs[buf][kb][c] = OPB == kOpH ? cconj(rb[p]) : rb[p];
+    }
+  };
+  if (kbeg < kend) {
+    load(kbeg);
+    store(0, kbeg);
+  }
+  __syncthreads();
+  int buf = 0;
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
+    const bool more = k0 + BK < kend;
+    if (more) load(k0 + BK);
 #pragma unroll 4
     for (int kk = 0; kk < BK; ++kk) {
       double2 a[4], bb[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = As[kk][ty + 16 * i];
+      for (int i = 0; i < 4; ++i) a[i] = As[buf][kk][ty + 16 * i];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) bb[j] = Bs[kk][tx + 16 * j];
+      for (int j = 0; j < 4; ++j) bb[j] = Bs[buf][kk][tx + 16 * j];
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) cfma(acc[i][j], a[i], bb[j]);
     }
+    // the other buffer was last read before the previous barrier
+    if (more) store(buf ^ 1, k0 + BK);
     __syncthreads();
+    buf ^= 1;
   }
   if (g.ksplit > 0) {
     double2 *C = g.C + (long)split * g.csplit;
