@@ -615,8 +615,8 @@ int update_slice(const Walkers &b, int l, int dir) {
         }
         {
           KTimer kt(L, PQMC_K_DECIDE);
-          if (delayed) PQ_HIP_CHECK(delayed_decide(gb, x, nw, g0, kk, L.st));
-          else PQ_HIP_CHECK(block_decide(gb, x, nw, g0, kk, bi, L.st));
+          if (delayed) PQ_HIP_CHECK(delayed_decide(gb, x, nw, g0, kk, fused, L.st));
+          else PQ_HIP_CHECK(block_decide(gb, x, nw, g0, kk, bi, fused, L.st));
         }
         if (fused) {
           g_prev = g0;

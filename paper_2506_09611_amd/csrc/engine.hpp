@@ -128,15 +128,17 @@ enum UniMode { kUniNone = 0, kUniDelayed = 1, kUniBlock = 2 };
 // has kk[w] sites (0: the walker has no group here, its lattice is smaller).
 hipError_t group_panels(const SpinMats *m, const GroupBufs *g, const SweepCtx *c, int nw,
                         int mode, int g0, const int *kk, hipStream_t st);
+// panels: the launch also sums the group's split-K panel partials (the fused
+// path, whose reduce kernel leaves them for the decision launch)
 hipError_t delayed_decide(const GroupBufs *g, const SweepCtx *c, int nw, int g0, const int *kk,
-                          hipStream_t st);
+                          bool panels, hipStream_t st);
 hipError_t block_decide(const GroupBufs *g, const SweepCtx *c, int nw, int g0, const int *kk,
-                        long long block_index, hipStream_t st);
+                        long long block_index, bool panels, hipStream_t st);
 hipError_t group_flush(const SpinMats *m, const GroupBufs *g, int nw, int g0, const int *kk,
                        hipStream_t st);
 // Fused path (kmax <= 64): one tile kernel per group applies the previous
 // group's flush and forms this group's split-K panel partials; group_reduce
-// sums them into P1, P2 and W0.
+// sums those of W0 and the decision launch (panels = true) those of P1, P2.
 // fp32: the precision form, T in float32 (SpinMats::T32) and the products
 // on FP32 MFMA with FP32 accumulation.
 // The pending group of walker w (flushed by this launch) starts at g0_prev

@@ -248,6 +248,50 @@ __device__ __forceinline__ void sum_pair(const double *p, const double *q, bool 
   }
 }
 
+// Sums of the split-K partials of a group's panels over column strip
+// `strip`, share `part` of kRedParts, by the NT threads of one workgroup:
+// P2 rows [m0, m1) (one partial per row strip of T, added in order) and P1
+// rows of the strip (np1 partials).  Every element is summed by one thread
+// in a fixed order, so the sums do not depend on the launch that runs them.
+template <int NT>
+__device__ void panel_sums(const GroupBufs &g, int s, int kk, int strip, int part, int np1) {
+  const int t = threadIdx.x;
+  const int Ns = g.Ns[s], kmax = g.kmax;
+  const int nt = (Ns + 63) / 64;
+  if (strip >= nt) return;
+  const int c0 = strip * 64;
+  const int w = min(64, Ns - c0);
+  const int mper = (kk + kRedParts - 1) / kRedParts;
+  const int m0 = part * mper, m1 = min(kk, m0 + mper);
+  const int r0 = part * (64 / kRedParts), r1 = min(w, r0 + 64 / kRedParts);
+  // P2 rows [m0, m1) over the strip
+  const int n2 = max(0, m1 - m0) * 64;
+  for (int e = t; e < n2; e += 2 * NT) {
+    const int e2 = e + NT;
+    const int ma = m0 + (e >> 6), ca = e & 63;
+    const int mb = m0 + (e2 >> 6), cb = e2 & 63;
+    const bool va = ca < w, vb = e2 < n2 && cb < w;
+    const long oa = (long)ma * Ns + c0 + ca, ob = (long)mb * Ns + c0 + cb;
+    double sa, sb;
+    sum_pair(g.P2part[s] + oa, g.P2part[s] + (vb ? ob : oa), va, vb, (long)kmax * Ns, nt, sa, sb);
+    if (va) g.P2[s][oa] = sa;
+    if (vb) g.P2[s][ob] = sb;
+  }
+  // P1 rows [c0 + r0, c0 + r1)
+  const int n1 = max(0, r1 - r0) * kk;
+  for (int e = t; e < n1; e += 2 * NT) {
+    const int e2 = e + NT;
+    const long oa = (long)(c0 + r0 + e / kk) * kmax + e % kk;
+    const long ob = (long)(c0 + r0 + e2 / kk) * kmax + e2 % kk;
+    const bool vb = e2 < n1;
+    double sa, sb;
+    sum_pair(g.P1part[s] + oa, g.P1part[s] + (vb ? ob : oa), true, vb, (long)Ns * kmax, np1, sa,
+             sb);
+    g.P1[s][oa] = sa;
+    if (vb) g.P1[s][ob] = sb;
+  }
+}
+
 // Grid (nP + nW + 1, 2 spins) with nP = nt * kRedParts panel workgroups and
 // nW = kk W0 workgroups per spin.  Panel workgroup (strip, part) sums its
 // share of the split-K partials of P2[:, strip] (rows of P2) and of
@@ -313,40 +357,7 @@ __global__ __launch_bounds__(kRedThreads) void group_reduce_kernel(Batch<ReduceA
     return;
   }
   // ---- panel workgroup
-  const int strip = x / kRedParts, part = x % kRedParts;
-  if (strip >= nt) return;
-  const int c0 = strip * 64;
-  const int w = min(64, Ns - c0);
-  const int mper = (kk + kRedParts - 1) / kRedParts;
-  const int m0 = part * mper, m1 = min(kk, m0 + mper);
-  const int r0 = part * (64 / kRedParts), r1 = min(w, r0 + 64 / kRedParts);
-  // P2 rows [m0, m1) over the strip
-  const int n2 = max(0, m1 - m0) * 64;
-  for (int e = t; e < n2; e += 2 * kRedThreads) {
-    const int e2 = e + kRedThreads;
-    const int ma = m0 + (e >> 6), ca = e & 63;
-    const int mb = m0 + (e2 >> 6), cb = e2 & 63;
-    const bool va = ca < w, vb = e2 < n2 && cb < w;
-    const long oa = (long)ma * Ns + c0 + ca, ob = (long)mb * Ns + c0 + cb;
-    double sa, sb;
-    sum_pair(a.g.P2part[s] + oa, a.g.P2part[s] + (vb ? ob : oa), va, vb, (long)kmax * Ns, nt, sa,
-             sb);
-    if (va) a.g.P2[s][oa] = sa;
-    if (vb) a.g.P2[s][ob] = sb;
-  }
-  // P1 rows [c0 + r0, c0 + r1)
-  const int n1 = max(0, r1 - r0) * kk;
-  for (int e = t; e < n1; e += 2 * kRedThreads) {
-    const int e2 = e + kRedThreads;
-    const long oa = (long)(c0 + r0 + e / kk) * kmax + e % kk;
-    const long ob = (long)(c0 + r0 + e2 / kk) * kmax + e2 % kk;
-    const bool vb = e2 < n1;
-    double sa, sb;
-    sum_pair(a.g.P1part[s] + oa, a.g.P1part[s] + (vb ? ob : oa), true, vb, (long)Ns * kmax, np1,
-             sa, sb);
-    a.g.P1[s][oa] = sa;
-    if (vb) a.g.P1[s][ob] = sb;
-  }
+  panel_sums<kRedThreads>(a.g, s, kk, x / kRedParts, x % kRedParts, np1);
 }
 
 // ------------------------------------------------------------------------
@@ -360,12 +371,26 @@ struct DecideArgs {
   long long block_index;
 };
 
+// Rows y > 0 of a decision launch's grid sum the group's panel partials for
+// the next flush (row y - 1 = 2 (strip kRedParts + part) + spin), beside the
+// decisions of row 0, which need only W0.
+template <int NT>
+__device__ __forceinline__ bool decide_panel_block(const DecideArgs &A) {
+  if (blockIdx.y == 0) return false;
+  const int q = blockIdx.y - 1, s = q & 1, x = q >> 1;
+  if (A.kk > 0)
+    panel_sums<NT>(A.g, s, A.kk, x / kRedParts, x % kRedParts,
+                   strip_chunks((A.g.Ns[s] + 63) / 64, A.g.chunks));
+  return true;
+}
+
 
 // kDecThreads lanes, kDecQ = ceil(kk * kk / kDecThreads) elements of each
 // spin's E per lane (kk <= kDecThreads).
 template <int kDecThreads, int kDecQ>
 __global__ __launch_bounds__(kDecThreads) void delayed_decide_kernel(Batch<DecideArgs> B) {
   const DecideArgs &A = B.w[blockIdx.x];
+  if (decide_panel_block<kDecThreads>(A)) return;
   if (A.kk <= 0) return;   // no group for this walker (uneven batch)
   const int kk = A.kk;
   const int t = threadIdx.x;
@@ -509,6 +534,7 @@ __device__ __forceinline__ double recip(double p) {
 template <int KK>
 __global__ __launch_bounds__(64) void delayed_decide_wave_kernel(Batch<DecideArgs> B) {
   const DecideArgs &A = B.w[blockIdx.x];
+  if (decide_panel_block<64>(A)) return;
   if (A.kk <= 0) return;   // no group for this walker (uneven batch)
   constexpr int R = KK / 8;
   static_assert(KK % 8 == 0 && R >= 1 && R <= 4, "tile shape");
@@ -654,6 +680,7 @@ __global__ __launch_bounds__(64) void delayed_decide_wave_kernel(Batch<DecideArg
 template <int KK>
 __global__ __launch_bounds__(128) void delayed_decide_spin_kernel(Batch<DecideArgs> B) {
   const DecideArgs &A = B.w[blockIdx.x];
+  if (decide_panel_block<128>(A)) return;
   if (A.kk <= 0) return;   // no group for this walker (uneven batch)
   constexpr int R = KK / 8;
   static_assert(KK % 8 == 0 && R >= 1 && R <= 8, "tile shape");
@@ -847,6 +874,7 @@ __device__ double lds_gj_inverse(double *A, int ld, int n, double *colk, double 
 template <int NT>
 __global__ __launch_bounds__(NT) void block_decide_kernel(Batch<DecideArgs> B) {
   const DecideArgs &A = B.w[blockIdx.x];
+  if (decide_panel_block<NT>(A)) return;
   if (A.kk <= 0) return;   // no group for this walker (uneven batch)
   const int kk = A.kk;
   const int t = threadIdx.x;
@@ -1509,18 +1537,28 @@ hipError_t decide_by_class(const Batch<DecideArgs> &B, int nw, const int *kkw, i
   return hipSuccess;
 }
 
+// grid rows of a decision launch: the decisions, and with `panels` one row per
+// (spin, column strip, part) of the panel sums of the class's largest walker
+int decide_rows(const Batch<DecideArgs> &S, int n, bool panels) {
+  if (!panels) return 1;
+  int nt = 0;
+  for (int w = 0; w < n; ++w)
+    nt = max(nt, (max(S.w[w].g.Ns[0], S.w[w].g.Ns[1]) + 63) / 64);
+  return 1 + 2 * nt * kRedParts;
+}
+
 int delayed_class(int kk) { return kk <= 8 ? 0 : kk <= 16 ? 1 : kk <= 32 ? 2 : kk <= 64 ? 3 : 4; }
 int block_class(int kk) { return kk <= 16 ? 0 : 1; }
 
 hipError_t delayed_decide(const GroupBufs *g, const SweepCtx *c, int nw, int g0,
-                          const int *kkw, hipStream_t st) {
+                          const int *kkw, bool panels, hipStream_t st) {
   if (nw < 1 || nw > kMaxBatch) return hipErrorInvalidValue;
   const Batch<DecideArgs> B = decide_batch(g, c, nw, g0, kkw, 0);
   // measured at 40x40: k = 32 takes 19.5 us with one wave per spin against
   // 21.6 us with both spins in one wave; k = 64 fits the per-spin layout
   return decide_by_class(B, nw, kkw, 5, delayed_class,
                          [&](int k, const Batch<DecideArgs> &S, int n) {
-    const dim3 grid(n);
+    const dim3 grid(n, decide_rows(S, n, panels));
     switch (k) {
       case 0: hipLaunchKernelGGL((delayed_decide_wave_kernel<8>), grid, dim3(64), 0, st, S); break;
       case 1: hipLaunchKernelGGL((delayed_decide_wave_kernel<16>), grid, dim3(64), 0, st, S); break;
@@ -1532,7 +1570,7 @@ hipError_t delayed_decide(const GroupBufs *g, const SweepCtx *c, int nw, int g0,
 }
 
 hipError_t block_decide(const GroupBufs *g, const SweepCtx *c, int nw, int g0, const int *kkw,
-                        long long block_index, hipStream_t st) {
+                        long long block_index, bool panels, hipStream_t st) {
   if (nw < 1 || nw > kMaxBatch) return hipErrorInvalidValue;
   const Batch<DecideArgs> B = decide_batch(g, c, nw, g0, kkw, block_index);
   const size_t lds = sizeof(double) * 2 * 64 * 65;
@@ -1547,8 +1585,9 @@ hipError_t block_decide(const GroupBufs *g, const SweepCtx *c, int nw, int g0, c
   if (attr != hipSuccess) return attr;
   return decide_by_class(B, nw, kkw, 2, block_class,
                          [&](int k, const Batch<DecideArgs> &S, int n) {
-    if (k == 0) hipLaunchKernelGGL((block_decide_kernel<64>), dim3(n), dim3(64), lds, st, S);
-    else hipLaunchKernelGGL((block_decide_kernel<256>), dim3(n), dim3(256), lds, st, S);
+    const dim3 grid(n, decide_rows(S, n, panels));
+    if (k == 0) hipLaunchKernelGGL((block_decide_kernel<64>), grid, dim3(64), lds, st, S);
+    else hipLaunchKernelGGL((block_decide_kernel<256>), grid, dim3(256), lds, st, S);
   });
 }
 
@@ -1605,7 +1644,8 @@ hipError_t group_tile(const SpinMats *m, const GroupBufs *g, int nw, int g0_prev
 
 hipError_t group_reduce(const SpinMats *m, const GroupBufs *g, const SweepCtx *c, int nw,
                         int mode, int g0, const int *kk, hipStream_t st) {
-  return launch_reduce(m, g, c, nw, mode, g0, kk, 1, 1, st);
+  // W0 and the uniforms only: the panel sums run in the decision launch
+  return launch_reduce(m, g, c, nw, mode, g0, kk, 0, 1, st);
 }
 
 hipError_t group_flush(const SpinMats *m, const GroupBufs *g, int nw, int g0, const int *kk,
