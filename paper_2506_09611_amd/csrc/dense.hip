@@ -84,7 +84,8 @@ __device__ void tri_lower_inverse(double (*X)[kNB + 1], double (*Tm)[kNB + 1], b
 // with U from the elimination, L = D U^{-1} and Z = U^{-1} L^{-1}.
 constexpr int kLuThreads = 512;
 constexpr int kLuWaves = kLuThreads / 64;
-constexpr int kLuChunk = 128;   // rows staged through LDS at a time
+constexpr int kLuChunk = 256;   // rows staged through LDS at a time
+constexpr int kLuLoads = kLuChunk * kNB / kLuThreads;   // loads in flight per thread
 
 __device__ __forceinline__ unsigned long long pivot_key(double x, int r) {
   const unsigned long long b = (unsigned long long)__double_as_longlong(fabs(x));
@@ -116,9 +117,21 @@ __global__ __launch_bounds__(kLuThreads) void lu_panel_kernel(ElimArgs a) {
 #pragma unroll
   for (int c = 0; c < kNB; ++c) v0[c] = v1[c] = 0.0;
   for (int c0 = 0; c0 < n; c0 += kLuChunk) {
-    for (int e = t; e < kLuChunk * kNB; e += kLuThreads) {
-      const int i = e / kNB, c = e % kNB, row = c0 + i;
-      stage[i][c] = (row < n && c < nb) ? S.E[(long)row * S.ld + kb + c] : 0.0;
+    // all of a chunk's loads in flight together: clamped in-range addresses,
+    // the panel's columns past nb zeroed when staged (rows past n are never
+    // read back)
+    double sv[kLuLoads];
+#pragma unroll
+    for (int q = 0; q < kLuLoads; ++q) {
+      const int e = t + q * kLuThreads;
+      const int i = e / kNB, c = e % kNB, row = min(c0 + i, n - 1);
+      sv[q] = S.E[(long)row * S.ld + kb + min(c, nb - 1)];
+    }
+#pragma unroll
+    for (int q = 0; q < kLuLoads; ++q) {
+      const int e = t + q * kLuThreads;
+      const int i = e / kNB, c = e % kNB;
+      stage[i][c] = sv[q] * (c < nb ? 1.0 : 0.0);
     }
     __syncthreads();
     const bool in0 = cand0 && rr0 >= c0 && rr0 < c0 + kLuChunk;
@@ -315,7 +328,7 @@ __global__ __launch_bounds__(256) void elim_update_kernel(ElimArgs a) {
     const int r = r0 + t;
     const double *p = nullptr;
     int cur = -1;
-    if (r < n) {
+    if (r < n) {   // rows past n keep p = nullptr (read as row 0, never stored)
       p = S.E + (long)r * ld;
       if (GJ) {
         const int sl = S.slot[r];
@@ -331,25 +344,47 @@ __global__ __launch_bounds__(256) void elim_update_kernel(ElimArgs a) {
     rsrc[t] = p;
     rcur[t] = cur;
   }
-  for (int e = t; e < kNB * kNB; e += 256) {
-    const int i = e / kNB, j = e % kNB;
-    Zs[i * LZ + j] = (i < nb && j < nb) ? S.Z[i * kNB + j] : 0.0;
+  // Loads are unconditional so that they issue together: clamped addresses
+  // inside the data the guarded reads would touch (written, finite), with the
+  // entries outside the panel zeroed when stored (a multiply: a select would
+  // become a branch around the load and a wait).
+  constexpr int QZ = kNB * kNB / 256, QE = kNB * 64 / 256;
+  double zv[QZ], ev[QE];
+  int prw[QE];
+#pragma unroll
+  for (int q = 0; q < QE; ++q) {
+    const int b = (t + 256 * q) >> 6;
+    prw[q] = GJ ? S.prow[kb + min(b, nb - 1)] : kb + min(b, nb - 1);
   }
-  for (int e = t; e < kNB * 64; e += 256) {
-    const int b = e >> 6, cc = e & 63, c = c0 + cc;
-    double v = 0.0;
-    if (b < nb && c < c1) {
-      const int pr = GJ ? S.prow[kb + b] : kb + b;
-      v = S.E[(long)pr * ld + c];
-    }
-    EB[b * LB + cc] = v;
+  // Z holds only its leading nb x nb block: read inside it
+#pragma unroll
+  for (int q = 0; q < QZ; ++q) {
+    const int e = t + 256 * q, i = e / kNB, j = e % kNB;
+    zv[q] = S.Z[min(i, nb - 1) * kNB + min(j, nb - 1)];
+  }
+#pragma unroll
+  for (int q = 0; q < QE; ++q) {
+    const int cc = (t + 256 * q) & 63;
+    ev[q] = S.E[(long)prw[q] * ld + min(c0 + cc, c1 - 1)];
+  }
+#pragma unroll
+  for (int q = 0; q < QZ; ++q) {
+    const int e = t + 256 * q, i = e / kNB, j = e % kNB;
+    Zs[i * LZ + j] = zv[q] * ((i < nb && j < nb) ? 1.0 : 0.0);
+  }
+#pragma unroll
+  for (int q = 0; q < QE; ++q) {
+    const int e = t + 256 * q, b = e >> 6, cc = e & 63;
+    EB[b * LB + cc] = ev[q] * ((b < nb && c0 + cc < c1) ? 1.0 : 0.0);
   }
   __syncthreads();
-  for (int e = t; e < 64 * kNB; e += 256) {
-    const int rr = e / kNB, b = e % kNB;
+  constexpr int QL = 64 * kNB / 256;
+  double lv[QL];
+#pragma unroll
+  for (int q = 0; q < QL; ++q) {
+    const int e = t + 256 * q, rr = e / kNB, b = e % kNB;
     const double *p = rsrc[rr];
-    const double v = (p && b < nb) ? p[kb + b] : 0.0;
-    Lp[rr * LZ + b] = GJ ? -v : v;
+    lv[q] = (p ? p : S.E)[kb + min(b, nb - 1)];
   }
   dbl4 acc[2][2];
 #pragma unroll
@@ -360,8 +395,14 @@ __global__ __launch_bounds__(256) void elim_update_kernel(ElimArgs a) {
       for (int j = 0; j < 4; ++j) {
         const int rr = acc_row(wm, mi, lane, j), c = c0 + acc_col(wn, ni, lane);
         const double *p = rsrc[rr];
-        acc[mi][ni][j] = (p && c < c1) ? p[c] : 0.0;
+        acc[mi][ni][j] = (p ? p : S.E)[min(c, c1 - 1)];
       }
+#pragma unroll
+  for (int q = 0; q < QL; ++q) {
+    const int e = t + 256 * q, rr = e / kNB, b = e % kNB;
+    const double v = lv[q] * ((rsrc[rr] && b < nb) ? 1.0 : 0.0);
+    Lp[rr * LZ + b] = GJ ? -v : v;
+  }
   __syncthreads();
   // block rows B = Z EB: 2 x 4 tiles of 16 x 16, two per wave
 #pragma unroll
