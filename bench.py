@@ -111,7 +111,7 @@ def measured_traffic(cls, scheme, k, walkers, workload):
     return float(rec["traffic_bytes_per_launch"])
 
 
-def make_walkers(p, scheme, k, b, W, streams, fp32=False):
+def make_walkers(p, scheme, k, b, W, streams, fp32=False, tile_chunks=0):
     """W walkers (walker_id 0..W-1) on each of the given streams (walker ids
     continue across streams): one lockstep batch per stream."""
     import dataclasses
@@ -123,7 +123,7 @@ def make_walkers(p, scheme, k, b, W, streams, fp32=False):
             q = dataclasses.replace(p, walker_id=si * W + w)
             out.append(Chain(q.hopping, q.trial_up, q.trial_dn, q.U, q.dtau, q.n_slices,
                              q.stab_every, q.seed, q.walker_id, scheme=sc, k=k, b=b,
-                             timing=True, fp32=fp32, stream=st))
+                             timing=True, fp32=fp32, stream=st, tile_chunks=tile_chunks))
     return out
 
 
@@ -371,6 +371,9 @@ def main():
     ap.add_argument("--serve-slices", type=int, default=40, help="M of the serving jobs")
     ap.add_argument("--serve-budget-gb", type=float, default=8.0,
                     help="HBM budget of the admitted walkers (0 = 90%% of free memory)")
+    ap.add_argument("--tile-chunks", type=int, default=0,
+                    help="column chunks per row strip of the flush kernel for the batched "
+                         "walkers (0: the library default)")
     ap.add_argument("--ktime-window", type=int, default=10,
                     help="forward slice visits instrumented per kernel after the timed sweeps")
     args = ap.parse_args()
@@ -416,7 +419,8 @@ def main():
         if tuned is None:
             ap.error("--k 0 needs the delayed scheme and --autotune candidates")
         args.k = tuned["k"]
-    chains = make_walkers(p, args.scheme, args.k, args.b, W, streams)
+    chains = make_walkers(p, args.scheme, args.k, args.b, W, streams,
+                          tile_chunks=args.tile_chunks)
     ch = chains[0]
     if args.steps > 0:
         dt, agg = time_sweeps(chains, args.steps, args.warmup)
