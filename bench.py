@@ -347,7 +347,8 @@ def main():
                     help="slice visits timed for the local comparison (0 = full sweeps)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--autotune", default="8,16,32,64,128",
-                    help="delay ranks the autotuner times on the headline batch ('' to skip)")
+                    help="delay ranks the autotuner times on the headline batch, then the flush "
+                         "kernel's tile chunks at the chosen rank ('' to skip)")
     ap.add_argument("--soc-sizes", default="8,16,24",
                     help="lattice sides of the SOC-Hubbard table ('' for none)")
     ap.add_argument("--soc-k", default="8,16,32", help="delay ranks of the SOC table")
@@ -412,6 +413,8 @@ def main():
                        candidates=[int(x) for x in args.autotune.split(",")], walkers=W)
         tuned = {"k": r.k, "update_ms_per_slice_visit":
                  {str(k): 1e3 * v for k, v in sorted(r.update_s_per_slice.items())},
+                 "tile_chunks": r.tile_chunks, "chunks_update_ms_per_slice_visit":
+                 {str(c): 1e3 * v for c, v in sorted(r.chunk_s_per_slice.items())},
                  "walkers": W, "window_slice_visits": p.stab_every}
         log("autotune", tuned)
         torch.cuda.empty_cache()
@@ -419,6 +422,8 @@ def main():
         if tuned is None:
             ap.error("--k 0 needs the delayed scheme and --autotune candidates")
         args.k = tuned["k"]
+        if args.tile_chunks == 0:
+            args.tile_chunks = tuned["tile_chunks"]
     chains = make_walkers(p, args.scheme, args.k, args.b, W, streams,
                           tile_chunks=args.tile_chunks)
     ch = chains[0]
