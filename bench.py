@@ -51,11 +51,12 @@ def kernel_work(p, cls, scheme, k, b, acc):
         return 8.0 * N * N * Ns, 2 * 2 * (N * N + 2 * N * Ns) * 8.0, "mfma"
     if cls == "tile":          # flush T -= Q P2_A (rank n_A) + panels U_g T, T L_g
         return 2 * (2.0 * Ns * Ns * n_a + 4.0 * Ns * Ns * kk), 2 * 2 * Ns * Ns * 8.0, "mfma"
-    if cls == "reduce":        # read split-K partials of P1, P2 (ceil(Ns/64) each)
-        nt = -(-Ns // 64)
-        return 2 * 2.0 * nt * kk * Ns, 2 * (2 * nt * kk * Ns + 2 * kk * Ns) * 8.0, "hbm"
-    if cls == "decide":        # kk x kk pivot sweeps, two spins
-        return 2 * 2.0 * n_a * kk * kk, 2 * kk * kk * 8.0, "alu"
+    nt = -(-Ns // 64)
+    if cls == "reduce":        # sum the W0 partials (ceil(Ns/64) strips x 2 chunks), two spins
+        return 2.0 * 2 * nt * kk * kk, 2 * (2 * nt + 1) * kk * kk * 8.0, "hbm"
+    if cls == "decide":        # kk x kk pivot sweeps, and the P2 (nt) and P1 (2) partial sums
+        return (2 * 2.0 * n_a * kk * kk + 2 * (nt + 2) * kk * Ns,
+                2 * ((nt + 2) * kk * Ns + 2 * kk * Ns + kk * kk) * 8.0, "alu")
     if cls == "local":         # read T (partials of y, Tv), rank-1 write when accepted
         return 2 * (2.0 + 4.0 * acc) * Ns * Ns, 2 * (1.0 + acc) * Ns * Ns * 8.0, "hbm"
     raise KeyError(cls)
