@@ -360,13 +360,18 @@ __global__ __launch_bounds__(kDecThreads) void soc_decide_kernel(SocDecideArgs a
   __shared__ double2 Gm[2 * 64];
   __shared__ int accs;
   __shared__ double xs[64];
+  __shared__ double us[64];       // the group's Metropolis uniforms (independent of decisions)
   __shared__ int accm[64];
   __shared__ int n_acc;
   const int t = threadIdx.x;
   int n_low = 0, n_neg = 0;       // thread 0's counters
   bool nonfinite = false;
   int8_t *xrow = a.fields + (long)a.li * a.N + a.g0;
-  for (int j = t; j < kk; j += kDecThreads) xs[j] = (double)xrow[j];
+  for (int j = t; j < kk; j += kDecThreads) {
+    xs[j] = (double)xrow[j];
+    us[j] = philox_uniform(a.key0, a.key1, a.sweep, a.slice_code, (uint64_t)(a.g0 + j),
+                           kPurposeMH);
+  }
   if (t == 0) n_acc = 0;
   __syncthreads();
   // W0 with the flip blocks applied to the column pairs (j, kk + j):
@@ -422,8 +427,7 @@ __global__ __launch_bounds__(kDecThreads) void soc_decide_kernel(SocDecideArgs a
       const double2 R = csub(cmul(S[0][0], S[1][1]), cmul(S[0][1], S[1][0]));
       const double absR = hypot(R.x, R.y);
       const int site = a.g0 + j;
-      const double uu = philox_uniform(a.key0, a.key1, a.sweep, a.slice_code, (uint64_t)site,
-                                       kPurposeMH);
+      const double uu = us[j];
       const bool finite = !isnan(absR);
       const bool acc = finite && uu < absR;
       const double margin = absR - uu;
