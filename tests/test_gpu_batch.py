@@ -128,6 +128,29 @@ def test_tile_chunks_mixed_in_one_batch():
         ch.close()
 
 
+def test_tile_chunks_precision_form_equals_single_runs():
+    """The float32 form with walkers asking for 2, 3 and 64 column chunks in
+    one batch: each walker equals its single run with the same option
+    bitwise (the chunking fixes the summation order, the batch does not)."""
+    from paper_2506_09611_amd import batch_forward_window
+    p = synth.make_problem(16, 121, 121, 4.0, n_slices=20, stab_every=10, perturb=1e-3,
+                           seed=synth.SEED_BASE + 45)
+    probs = _walkers(p, 3)
+    chunks = [0, 3, 64]
+    chains = [make_chain(q, "delayed", k=32, fp32=True, tile_chunks=c)
+              for q, c in zip(probs, chunks)]
+    batch_forward_window(chains, 10)
+    for q, c, ch in zip(probs, chunks, chains):
+        single = make_chain(q, "delayed", k=32, fp32=True, tile_chunks=c)
+        single.forward_window(10)
+        assert np.array_equal(ch.decisions()[0], single.decisions()[0]), c
+        for s in range(2):
+            assert np.array_equal(ch.green(s), single.green(s)), c
+        single.close()
+    for ch in chains:
+        ch.close()
+
+
 def test_batch_rejects_mismatched_shapes():
     from paper_2506_09611_amd import batch_sweep, PQMCError
     p = synth.make_problem(4, 5, 5, 4.0, n_slices=20, stab_every=5, perturb=1e-3, seed=3)
