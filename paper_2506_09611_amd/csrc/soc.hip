@@ -521,10 +521,9 @@ __global__ __launch_bounds__(kDecThreads) void soc_decide_kernel(SocDecideArgs a
 // workgroup: A <- [I | A_left^{-1} A_right] up to rounding, *det <- det(A_left)
 // (thread 0; 0 if singular).  All threads call it.
 __device__ void gj_lds(double2 *A, int n, int ncols, int ld, double2 *det, int *ok) {
-  __shared__ double bestv[kDecThreads / 64];
-  __shared__ int besti[kDecThreads / 64];
   __shared__ int pv;
-  __shared__ double2 fcol[64];
+  __shared__ double2 pd;          // the pivot value, published with its row
+  __shared__ double2 fcol[64];    // each row's multiplier of the pivot row
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   if (t == 0) {
     *det = make_double2(1.0, 0.0);
@@ -548,6 +547,7 @@ __device__ void gj_lds(double2 *A, int n, int ncols, int ld, double2 *det, int *
       if (lane == 0) {
         const bool good = bv > 0.0 && isfinite(bv);
         pv = good ? bi : -1;
+        if (good) pd = A[bi * ld + j];
         if (!good) {
           *ok = 0;
           *det = make_double2(0.0, 0.0);
@@ -557,24 +557,26 @@ __device__ void gj_lds(double2 *A, int n, int ncols, int ld, double2 *det, int *
     __syncthreads();
     const int p = pv;
     if (p < 0) return;
-    if (p != j) {
-      for (int c = t; c < ncols; c += kDecThreads) {
-        const double2 x = A[j * ld + c];
-        A[j * ld + c] = A[p * ld + c];
-        A[p * ld + c] = x;
+    // One phase: swap rows j and p, scale the new row j by 1/d and keep the
+    // multipliers (column j after the swap, before the scaling).  Only rows
+    // j and p are written, so the other rows' column j is read freely; the
+    // thread of column j hands row p its multiplier, the old A[j][j].
+    const double2 d = pd;
+    const double2 inv = cdiv(make_double2(1.0, 0.0), d);
+    if (t < n && t != j && t != p) fcol[t] = A[t * ld + j];
+    for (int c = t; c < ncols; c += kDecThreads) {
+      const double2 aj = A[j * ld + c], ap = A[p * ld + c];
+      A[j * ld + c] = cmul(ap, inv);
+      if (p != j) {
+        A[p * ld + c] = aj;
+        if (c == j) fcol[p] = aj;
       }
     }
-    __syncthreads();
-    const double2 d = A[j * ld + j];
-    if (t < n) fcol[t] = A[t * ld + j];
     if (t == 0) {
       double2 dt = cmul(*det, d);
       if (p != j) dt = make_double2(-dt.x, -dt.y);
       *det = dt;
     }
-    __syncthreads();
-    const double2 inv = cdiv(make_double2(1.0, 0.0), d);
-    for (int c = t; c < ncols; c += kDecThreads) A[j * ld + c] = cmul(A[j * ld + c], inv);
     __syncthreads();
     for (int e = t; e < n * ncols; e += kDecThreads) {
       const int r = e / ncols, c = e - r * ncols;
