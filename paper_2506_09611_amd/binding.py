@@ -31,6 +31,7 @@ class Scheme(enum.IntEnum):
     LOCAL = 0
     DELAYED = 1
     BLOCK_FB = 2
+    LOCAL_G = 3
 
 
 FLAG_LOG = 1

@@ -70,8 +70,6 @@ def test_small_parity_two_sweeps(scheme, kw):
         meta, margin = ch.decisions()
         n, low = compare_decisions(meta, margin, w.log, sw, p.n_slices)
         print(f"{scheme} {kw} sweep {sw}: {n} decisions equal, low-margin {low}", flush=True)
-        if low:
-            return
         assert np.array_equal(ch.fields(), w.fields)
         assert green_rel_err(ch, w) < 1e-10
 
@@ -87,8 +85,6 @@ def test_c1_parity(scheme, kw):
         ch.sweep(1)
         meta, margin = ch.decisions()
         n, low = compare_decisions(meta, margin, w.log, sw, p.n_slices)
-        if low:
-            return
         assert np.array_equal(ch.fields(), w.fields)
         assert green_rel_err(ch, w) < 1e-10
 
@@ -107,9 +103,8 @@ def test_wide_groups_10x10(scheme, kw):
     ch.sweep(1)
     meta, margin = ch.decisions()
     n, low = compare_decisions(meta, margin, w.log, 0, p.n_slices)
-    if not low:
-        assert np.array_equal(ch.fields(), w.fields)
-        assert green_rel_err(ch, w) < 1e-10
+    assert np.array_equal(ch.fields(), w.fields)
+    assert green_rel_err(ch, w) < 1e-10
 
 
 @pytest.mark.parametrize("scheme,kw", [("local", {}), ("delayed", {"k": 16}), ("block", {"b": 8})])
@@ -123,9 +118,8 @@ def test_c2_parity_one_sweep(scheme, kw):
     meta, margin = ch.decisions()
     n, low = compare_decisions(meta, margin, w.log, 0, p.n_slices)
     print(f"c2 {scheme} {kw}: {n} decisions equal, low-margin {low}", flush=True)
-    if not low:
-        assert np.array_equal(ch.fields(), w.fields)
-        assert green_rel_err(ch, w) < 1e-10
+    assert np.array_equal(ch.fields(), w.fields)
+    assert green_rel_err(ch, w) < 1e-10
 
 
 @pytest.mark.parametrize("scheme,kw,window", [("local", {}, 1), ("delayed", {"k": 32}, 10),
@@ -143,9 +137,8 @@ def test_c3_window_parity(scheme, kw, window):
     meta, margin = ch.decisions()
     n, low = compare_decisions(meta, margin, w.log, 0, p.n_slices)
     print(f"c3 {scheme} {kw} window {window}: {n} decisions equal, low-margin {low}", flush=True)
-    if not low:
-        assert np.array_equal(ch.fields(), w.fields)
-        assert green_rel_err(ch, w) < 1e-10
+    assert np.array_equal(ch.fields(), w.fields)
+    assert green_rel_err(ch, w) < 1e-10
 
 
 @pytest.mark.parametrize("scheme,kw", [("local", {}), ("delayed", {"k": 3}), ("block", {"b": 2})])
@@ -178,8 +171,6 @@ def test_single_site_lattice(scheme, kw):
         ch.sweep(1)
         w.sweep()
         n, low = compare_decisions(*ch.decisions(), w.log, sw, p.n_slices)
-        if low:
-            break
         assert np.array_equal(ch.fields(), w.fields)
         assert green_rel_err(ch, w) < 1e-10
     ch.close()
@@ -197,7 +188,6 @@ def test_largest_sector_window(scheme, kw):
     w.forward_window(1)
     n, low = compare_decisions(*ch.decisions(), w.log, 0, p.n_slices)
     print(f"46x46 {scheme}: {n} decisions equal, low {low}", flush=True)
-    if not low:
-        assert np.array_equal(ch.fields(), w.fields)
-        assert green_rel_err(ch, w) < 1e-10
+    assert np.array_equal(ch.fields(), w.fields)
+    assert green_rel_err(ch, w) < 1e-10
     ch.close()

@@ -35,8 +35,6 @@ def _check(ch, w, sweep, M, label):
     meta, margin = ch.decisions()
     n, low = compare_decisions(meta, margin, w.log, sweep, M)
     print(f"{label}: {n} decisions equal, low {low}", flush=True)
-    if low:
-        return False
     assert np.array_equal(ch.fields(), w.fields), label
     G, Gr = ch.green(), w.green()
     err = np.max(np.abs(G - Gr)) / max(1.0, np.max(np.abs(Gr)))   # G = 0 at full filling
