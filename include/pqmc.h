@@ -129,6 +129,10 @@ typedef struct {
   double t_update_s;          /* with PQMC_FLAG_TIMING: field-update phase             */
   double t_prop_s;            /* with PQMC_FLAG_TIMING: B-matrix propagation phase     */
   double t_stab_s;            /* with PQMC_FLAG_TIMING: QR + inverse phase             */
+  double max_stab_drift;      /* largest |G_running - G_fresh| entry that a QR
+                                 stabilisation corrected (Sec. II B), over 16 sampled
+                                 columns of G per stabilisation and spin: how far the
+                                 updated state had drifted from the recomputed one   */
 } pqmc_stats;
 
 /* Size of the device workspace for this problem and the largest delay_k /
@@ -207,6 +211,24 @@ pqmc_status pqmc_batch_forward_window(pqmc_ctx *const *ctxs, int32_t n, int32_t 
  * thread's current HIP device is used by every worker thread. */
 pqmc_status pqmc_multi_sweep(pqmc_ctx *const *ctxs, int32_t n, int32_t n_sweeps,
                              pqmc_stats *out);
+
+/* Replay: one sweep (forward then backward, as pqmc_sweep) in which every
+ * outcome is forced instead of drawn.  flips: host, 2 M x N_s int8, row
+ * v = dir*M + l-1 (dir 0 forward, 1 backward) for the visit of slice l;
+ * flips[v*N_s + i] != 0 means that the field of site i flips on that visit.
+ *   PQMC_LOCAL, PQMC_DELAYED: the Metropolis test of site i is accepted iff
+ *     listed (its ratio is still computed, logged and checked for NaN);
+ *   PQMC_BLOCK_FB: each block's heat-bath proposal is the listed flip set
+ *     and the block's Metropolis test is accepted (an empty set is the usual
+ *     no-op).
+ * The same list through the three schemes yields the same fields and, in
+ * exact arithmetic, the same G: the cross-scheme invariant of the updates
+ * (Secs. II D, III A, III B all apply Eq. (19) to the accepted flips).
+ * Forced outcomes are implemented as uniforms u = -1 (take) and u = +inf
+ * (do not take) in place of the Philox draws, so the log's margins are
+ * |A| + 1 and -inf.  The walker must be at position 0 (PQMC_ESTATE
+ * otherwise); the sweep counter advances as after pqmc_sweep. */
+pqmc_status pqmc_replay(pqmc_ctx *ctx, const int8_t *flips, pqmc_stats *out);
 
 /* G^s = 1 - U_R T U_L at the walker's current position (Eq. (15)),
  * written to host memory as N_s x N_s row-major float64.  spin: 0 up, 1 down. */

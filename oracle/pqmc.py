@@ -93,6 +93,7 @@ class Walker:
         self.n_accepted = 0
         self.n_flips = 0
         self.trace = None      # when a list: (dir, slice, site, R, prior, fields before)
+        self.replay = None     # when set: 2M x N forced outcomes (see replay_sweep)
         self.build_initial_state()
 
     # ------------------------------------------------------------------ setup
@@ -191,11 +192,32 @@ class Walker:
         else:
             self.block_slice(l, d)
 
+    def replay_sweep(self, flips):
+        """One sweep with every outcome forced instead of drawn (the invariant
+        that all three schemes apply Eq. (19) to the same accepted flips).
+        flips[d*M + l-1, i] != 0: site i flips on that visit of slice l.
+        Local / delayed: the site's Metropolis test is accepted iff listed.
+        Block: the heat-bath proposal is the listed flip set and the block's
+        Metropolis test is accepted.  A forced outcome is the uniform -1
+        (taken for any finite |A|) or +inf (not taken) in place of the draw."""
+        self.replay = np.asarray(flips, dtype=np.int8).reshape(2 * self.M, self.N)
+        try:
+            self.sweep()
+        finally:
+            self.replay = None
+
     # ---------------------------------------------------------- decisions
     def mh_uniform(self, d, li, site):
+        if self.replay is not None:
+            take = self.scheme == "block" or self.replay[d * self.M + li, site] != 0
+            return -1.0 if take else math.inf
         return philox.uniform(self.key, self.sweep_index, d * self.M + li, site, philox.PURPOSE_MH)
 
     def hb_uniform(self, d, li, site):
+        if self.replay is not None:
+            x = int(self.fields[li, site])
+            target = -x if self.replay[d * self.M + li, site] != 0 else x
+            return -1.0 if target > 0 else math.inf
         return philox.uniform(self.key, self.sweep_index, d * self.M + li, site, philox.PURPOSE_HB)
 
     def flip_delta(self, li, i, s):

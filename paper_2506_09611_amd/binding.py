@@ -20,6 +20,7 @@ EXPORTED_SYMBOLS = (
     "pqmc_get_fields", "pqmc_sweep", "pqmc_forward_window", "pqmc_batch_sweep",
     "pqmc_batch_forward_window", "pqmc_multi_sweep", "pqmc_get_green",
     "pqmc_get_decisions", "pqmc_get_heat_bath", "pqmc_get_kernel_times", "pqmc_destroy",
+    "pqmc_replay",
     "pqmc_last_error",
     "pqmc_soc_workspace_bytes", "pqmc_soc_create", "pqmc_soc_sweep", "pqmc_soc_forward_window",
     "pqmc_soc_get_green", "pqmc_soc_get_fields", "pqmc_soc_get_decisions", "pqmc_soc_destroy",
@@ -76,7 +77,8 @@ class Stats(ctypes.Structure):
                 ("flips", ctypes.c_uint64), ("low_margin", ctypes.c_uint64),
                 ("negative", ctypes.c_uint64), ("field_updates", ctypes.c_uint64),
                 ("t_total_s", ctypes.c_double), ("t_update_s", ctypes.c_double),
-                ("t_prop_s", ctypes.c_double), ("t_stab_s", ctypes.c_double)]
+                ("t_prop_s", ctypes.c_double), ("t_stab_s", ctypes.c_double),
+                ("max_stab_drift", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -122,6 +124,7 @@ def load_library():
         "pqmc_get_kernel_times": [c_void_p, ctypes.POINTER(ctypes.c_double),
                                   ctypes.POINTER(ctypes.c_uint64)],
         "pqmc_destroy": [c_void_p],
+        "pqmc_replay": [c_void_p, ctypes.POINTER(ctypes.c_int8), ctypes.POINTER(Stats)],
         "pqmc_soc_workspace_bytes": [ctypes.POINTER(SocProblem), ctypes.POINTER(UpdateOpts),
                                      ctypes.POINTER(c_size_t)],
         "pqmc_soc_create": [ctypes.POINTER(SocProblem), ctypes.POINTER(UpdateOpts), c_void_p,
@@ -236,6 +239,15 @@ class Chain:
         st = Stats()
         _check(self._lib, self._lib.pqmc_forward_window(self._ctx, int(n_slices),
                                                         ctypes.byref(st)))
+        return st.as_dict()
+
+    def replay(self, flips):
+        """pqmc_replay: one sweep with every outcome forced by flips (2M x N,
+        nonzero = the site's field flips on that slice visit)."""
+        f = np.ascontiguousarray(flips, dtype=np.int8).reshape(2 * self.M, self.N)
+        st = Stats()
+        _check(self._lib, self._lib.pqmc_replay(
+            self._ctx, f.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)), ctypes.byref(st)))
         return st.as_dict()
 
     def green(self, spin):

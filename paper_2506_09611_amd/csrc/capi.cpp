@@ -51,6 +51,8 @@ struct pqmc_ctx {
 
   double *K = nullptr, *Kinv = nullptr, *Tay0 = nullptr, *Tay1 = nullptr;
   int8_t *fields = nullptr;
+  int8_t *replay = nullptr;   // 2 M x N forced outcomes of pqmc_replay
+  bool replaying = false;
   double *P[2] = {nullptr, nullptr};
   double *URw[2][2] = {}, *ULw[2][2] = {};
   double *Lstack[2] = {}, *Rstack[2] = {};
@@ -65,6 +67,8 @@ struct pqmc_ctx {
   double *log_margin = nullptr, *hb_margin = nullptr;
   long long log_cap = 0;
   double *gtmp = nullptr, *xtmp = nullptr;
+  // stabilisation drift: sampled columns of U_R T U_L before / after
+  double *drift_y[2] = {}, *drift_z[2][2] = {};
 
   double *UR[2] = {};
   double *ULt[2] = {};
@@ -85,6 +89,8 @@ struct pqmc_ctx {
 namespace {
 
 constexpr size_t kAlign = 256;
+// columns of G sampled for the stabilisation drift statistic
+constexpr int kDriftCols = 16;
 
 struct Carver {
   char *base;
@@ -111,6 +117,7 @@ void layout(pqmc_ctx &c, char *base, size_t *bytes) {
   c.Tay1 = cv.take<double>(NN);
   c.gtmp = c.Tay0;   // Green's function output reuses the Taylor scratch
   c.fields = cv.take<int8_t>((size_t)c.M * N);
+  c.replay = cv.take<int8_t>((size_t)2 * c.M * N);
   c.stats = cv.take<unsigned long long>(16);
   const int kmax = c.gmax;
   for (int s = 0; s < 2; ++s) {
@@ -155,6 +162,11 @@ void layout(pqmc_ctx &c, char *base, size_t *bytes) {
   c.gb.Ns[0] = c.Ns[0];
   c.gb.Ns[1] = c.Ns[1];
   c.xtmp = cv.take<double>(N * (size_t)std::max(c.Ns[0], c.Ns[1]));
+  for (int s = 0; s < 2; ++s) {
+    c.drift_y[s] = cv.take<double>((size_t)kDriftCols * c.Ns[s]);
+    c.drift_z[s][0] = cv.take<double>((size_t)kDriftCols * N);
+    c.drift_z[s][1] = cv.take<double>((size_t)kDriftCols * N);
+  }
   if (c.log_alloc) {
     c.log_cap = 2LL * c.M * c.N;
     c.log_meta = cv.take<int32_t>(3 * (size_t)c.log_cap);
@@ -334,12 +346,9 @@ std::vector<SizeClass> size_classes(const Walkers &b) {
   return out;
 }
 
-// CholQR of the columns of A (N x Ns per walker and spin, index 2 w + s)
-// into dst: S = A^T A = R^T R, dst = A R^{-1}.  One pass suffices here: the
-// Green's function depends on U_R (U_L) only through its column (row) space,
-// which A R^{-1} keeps to within kappa(A) eps; the re-orthonormalisation only
-// has to keep the basis well conditioned for the next k_tau slices.
-int orthonormalize(const Walkers &b, double *const *A, double *const *dst) {
+// One pass of Cholesky QR on the columns of A (N x Ns per walker and spin,
+// index 2 w + s) into dst: S = A^T A = R^T R, dst = A R^{-1}.
+int cholqr_pass(const Walkers &b, double *const *A, double *const *dst) {
   pqmc_ctx &L = b.lead();
   GemmQueue gram{L.st, true, false};
   for (int i = 0; i < b.n; ++i)
@@ -369,6 +378,19 @@ int orthonormalize(const Walkers &b, double *const *A, double *const *dst) {
       if (rc) return rc;
     }
   return q.flush();
+}
+
+// QR stabilisation of Sec. II B: the columns of A orthonormalised into dst by
+// Cholesky QR applied twice (A -> tmp -> dst).  One pass leaves Q^T Q - 1 of
+// order kappa(A)^2 eps; the second pass starts from a basis with condition
+// number close to one and leaves it at the rounding level.  A Cholesky
+// breakdown (kappa(A)^2 eps near one) sets the singular-factorisation error.
+// The Green's function depends on U_R (U_L) only through its column (row)
+// space; tmp is a free work buffer of the same shape.
+int orthonormalize(const Walkers &b, double *const *A, double *const *tmp, double *const *dst) {
+  int rc = cholqr_pass(b, A, tmp);
+  if (rc) return rc;
+  return cholqr_pass(b, tmp, dst);
 }
 
 // T = (U_L U_R)^{-1} by blocked Gauss-Jordan with partial pivoting.
@@ -477,13 +499,14 @@ int build_state(const Walkers &b) {
     if (rc) return rc;
     if ((l - 1) % L.kt == 0) {
       const int j = (l - 1) / L.kt;
-      double *src[kMaxMats], *dst[kMaxMats];
+      double *src[kMaxMats], *tmp[kMaxMats], *dst[kMaxMats];
       for (int i = 0; i < b.n; ++i)
         for (int s = 0; s < 2; ++s) {
           src[2 * i + s] = b[i].ULt[s];
+          tmp[2 * i + s] = other(b[i].ULt[s], b[i].ULw[s]);
           dst[2 * i + s] = slot(b[i].Lstack[s], j, b[i], s);
         }
-      rc = orthonormalize(b, src, dst);
+      rc = orthonormalize(b, src, tmp, dst);
       if (rc) return rc;
       for (int i = 0; i < b.n; ++i)
         for (int s = 0; s < 2; ++s) b[i].ULt[s] = dst[2 * i + s];
@@ -550,6 +573,7 @@ SweepCtx sweep_ctx(pqmc_ctx &c, int l, int dir) {
   x.log_base = c.log_count;
   x.hb_base = c.hb_count;
   x.log_cap = c.log_cap;
+  x.force = c.replaying ? c.replay + (size_t)x.slice_code * c.N : nullptr;
   return x;
 }
 
@@ -646,40 +670,110 @@ int update_slice(const Walkers &b, int l, int dir) {
   return PQMC_OK;
 }
 
+// Stabilisation drift: the largest change of G = 1 - U_R T U_L that a
+// stabilisation makes, over kDriftCols sampled columns j (stride N / cols):
+// Z_j = (U_R T U_L)[:, j] = U_R (T ULt[j, :]^T), formed from the running
+// state before the QR and inverse (which = 0) and from the fresh state
+// after (which = 1).  The identity cancels in the difference.
+int drift_cols(const Walkers &b) { return std::min(kDriftCols, b.lead().N); }
+
+int drift_columns(const Walkers &b, int which) {
+  pqmc_ctx &L = b.lead();
+  if (which == 0) {
+    // the precision form's running T lives in float32
+    const float *src[kMaxMats];
+    double *dst[kMaxMats];
+    int m = 0;
+    long n = 0;
+    for (int i = 0; i < b.n; ++i) {
+      if (!(fp32_form(b[i]) && b[i].t32_ahead)) continue;
+      for (int s = 0; s < 2; ++s) {
+        src[m] = b[i].T32[s];
+        dst[m] = b[i].T[s];
+        n = std::max(n, (long)b[i].Ns[s] * b[i].Ns[s]);
+        ++m;
+      }
+    }
+    if (m) PQ_HIP_CHECK(widen_to_f64(src, dst, m, n, L.st));
+  }
+  GemmQueue qy{L.st, false, true};
+  for (int i = 0; i < b.n; ++i)
+    for (int s = 0; s < 2; ++s) {
+      pqmc_ctx &c = b[i];
+      const int n = c.Ns[s], nc = std::min(kDriftCols, c.N), stride = c.N / nc;
+      // Y^T (nc x n) = ULt[J, :] T^T
+      int rc = qy.add(gemm_desc(c.ULt[s], (long)stride * n, c.T[s], n, c.drift_y[s], n, nc, n, n));
+      if (rc) return rc;
+    }
+  int rc = qy.flush();
+  if (rc) return rc;
+  GemmQueue qz{L.st, false, true};
+  for (int i = 0; i < b.n; ++i)
+    for (int s = 0; s < 2; ++s) {
+      pqmc_ctx &c = b[i];
+      const int n = c.Ns[s], nc = std::min(kDriftCols, c.N);
+      // Z^T (nc x N) = Y^T U_R^T
+      rc = qz.add(gemm_desc(c.drift_y[s], n, c.UR[s], n, c.drift_z[s][which], c.N, nc, c.N, n));
+      if (rc) return rc;
+    }
+  rc = qz.flush();
+  if (rc || which == 0) return rc;
+  const double *za[kMaxMats], *zb[kMaxMats];
+  unsigned long long *out[kMaxMats];
+  long cnt[kMaxMats];
+  for (int i = 0; i < b.n; ++i)
+    for (int s = 0; s < 2; ++s) {
+      za[2 * i + s] = b[i].drift_z[s][0];
+      zb[2 * i + s] = b[i].drift_z[s][1];
+      out[2 * i + s] = b[i].stats + kStDrift;
+      cnt[2 * i + s] = (long)std::min(kDriftCols, b[i].N) * b[i].N;
+    }
+  PQ_HIP_CHECK(max_abs_diff(za, zb, cnt, out, 2 * b.n, L.st));
+  return PQMC_OK;
+}
+
 int stab_forward(const Walkers &b, int l) {
   const int j = l / b.lead().kt;
-  double *src[kMaxMats], *dst[kMaxMats];
+  double *src[kMaxMats], *tmp[kMaxMats], *dst[kMaxMats];
   for (int i = 0; i < b.n; ++i)
     for (int s = 0; s < 2; ++s) {
       src[2 * i + s] = b[i].UR[s];
+      tmp[2 * i + s] = other(b[i].UR[s], b[i].URw[s]);
       dst[2 * i + s] = slot(b[i].Rstack[s], j, b[i], s);
     }
-  int rc = orthonormalize(b, src, dst);
+  int rc = drift_columns(b, 0);
+  if (!rc) rc = orthonormalize(b, src, tmp, dst);
   if (rc) return rc;
   for (int i = 0; i < b.n; ++i)
     for (int s = 0; s < 2; ++s) {
       b[i].UR[s] = dst[2 * i + s];
       b[i].ULt[s] = slot(b[i].Lstack[s], j, b[i], s);
     }
-  return refresh_T(b);
+  rc = refresh_T(b);
+  if (!rc) rc = drift_columns(b, 1);
+  return rc;
 }
 
 int stab_backward(const Walkers &b, int l) {
   const int j = (l - 1) / b.lead().kt;
-  double *src[kMaxMats], *dst[kMaxMats];
+  double *src[kMaxMats], *tmp[kMaxMats], *dst[kMaxMats];
   for (int i = 0; i < b.n; ++i)
     for (int s = 0; s < 2; ++s) {
       src[2 * i + s] = b[i].ULt[s];
+      tmp[2 * i + s] = other(b[i].ULt[s], b[i].ULw[s]);
       dst[2 * i + s] = slot(b[i].Lstack[s], j, b[i], s);
     }
-  int rc = orthonormalize(b, src, dst);
+  int rc = drift_columns(b, 0);
+  if (!rc) rc = orthonormalize(b, src, tmp, dst);
   if (rc) return rc;
   for (int i = 0; i < b.n; ++i)
     for (int s = 0; s < 2; ++s) {
       b[i].ULt[s] = dst[2 * i + s];
       b[i].UR[s] = slot(b[i].Rstack[s], j, b[i], s);
     }
-  return refresh_T(b);
+  rc = refresh_T(b);
+  if (!rc) rc = drift_columns(b, 1);
+  return rc;
 }
 
 // phase timing: events recorded at boundaries, summed per phase at the end
@@ -761,6 +855,7 @@ int finish_walker(pqmc_ctx &c, const double ph[3], double t_total, pqmc_stats *o
     out->t_update_s = ph[kPhUpdate];
     out->t_prop_s = ph[kPhProp];
     out->t_stab_s = ph[kPhStab];
+    std::memcpy(&out->max_stab_drift, &h[kStDrift], sizeof(double));
   }
   c.hb_total = c.hb_count;
   return rc;
@@ -1089,6 +1184,22 @@ pqmc_status pqmc_sweep(pqmc_ctx *c, int32_t n_sweeps, pqmc_stats *out) {
   if (!c) return set_error(PQMC_EINVAL, "null context");
   pqmc_ctx *one[1] = {c};
   return pqmc_batch_sweep(one, 1, n_sweeps, out);
+}
+
+pqmc_status pqmc_replay(pqmc_ctx *c, const int8_t *flips, pqmc_stats *out) {
+  if (!c || !flips) return set_error(PQMC_EINVAL, "null argument");
+  if (c->failed) return set_error(PQMC_ESTATE, "context failed; call pqmc_set_fields");
+  if (c->windowed || c->position != 0)
+    return set_error(PQMC_ESTATE, "walker is mid-sweep after pqmc_forward_window");
+  const size_t n = (size_t)2 * c->M * c->N;
+  hipError_t e = hipMemcpyAsync(c->replay, flips, n, hipMemcpyHostToDevice, c->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->st);   // the host array may go away
+  if (e != hipSuccess) return as_status(fail_device(e, "upload replay", __FILE__, __LINE__));
+  c->replaying = true;
+  pqmc_ctx *one[1] = {c};
+  const pqmc_status st = pqmc_batch_sweep(one, 1, 1, out);
+  c->replaying = false;
+  return st;
 }
 
 pqmc_status pqmc_batch_forward_window(pqmc_ctx *const *ctxs, int32_t n, int32_t n_slices,

@@ -63,11 +63,21 @@ struct SweepCtx {
   long long log_base;       // index of this slice's first decision in the log
   long long hb_base;        // index of this slice's first heat-bath draw (+ site)
   long long log_cap;
+  // Replay (null otherwise): this slice visit's forced outcomes, one per site
+  // (nonzero: the site's field flips).  A forced Metropolis test draws
+  // u = -1 (accepted for any finite ratio) or u = +inf (rejected); a forced
+  // heat-bath draw proposes the listed field by the same two values.
+  const int8_t *force;
 };
+
+// uniform that forces an outcome of "accept iff u < a" for any finite a >= 0
+__device__ __forceinline__ double forced_uniform(bool take) {
+  return take ? -1.0 : __builtin_inf();
+}
 
 // stats slots
 enum { kStProposed = 0, kStAccepted = 1, kStFlips = 2, kStLowMargin = 3, kStNegative = 4,
-       kStFieldUpdates = 5, kStError = 8 };
+       kStFieldUpdates = 5, kStError = 8, kStDrift = 9 };
 enum { kErrNonFinite = 1, kErrSingular = 2 };
 
 // sum_{i < n} p[i * stride] in index order; loads issued eight at a time so

@@ -526,6 +526,30 @@ __global__ void widen_kernel(ConvArgs a, long n) {
     d[e] = (double)s[e];
 }
 
+struct DiffArgs {
+  const double *a[kMaxMats], *b[kMaxMats];
+  unsigned long long *out[kMaxMats];
+  long n[kMaxMats];
+};
+
+// *out = max(*out, max_e |a[e] - b[e]|) as the bit pattern of a non-negative
+// double (whose integer order is its numeric order; a NaN difference wins).
+__global__ __launch_bounds__(256) void max_abs_diff_kernel(DiffArgs d) {
+  const int m = blockIdx.y;
+  double v = 0.0;
+  for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < d.n[m]; e += (long)gridDim.x * 256) {
+    const double x = fabs(d.a[m][e] - d.b[m][e]);
+    v = (x > v || x != x) ? x : v;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const double x = __shfl_xor(v, o, 64);
+    v = (x > v || x != x) ? x : v;
+  }
+  if ((threadIdx.x & 63) == 0)
+    atomicMax(d.out[m], (unsigned long long)__double_as_longlong(v));
+}
+
 __global__ void init_fields_kernel(int8_t *f, int M, int N, uint64_t k0, uint64_t k1) {
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (long)M * N) return;
@@ -635,6 +659,20 @@ hipError_t widen_to_f64(const float *const *src, double *const *dst, int nmat, l
     a.dst[i] = dst[i];
   }
   hipLaunchKernelGGL(widen_kernel, dim3(256, nmat), dim3(256), 0, st, a, n);
+  return hipGetLastError();
+}
+
+hipError_t max_abs_diff(const double *const *a, const double *const *b, const long *n,
+                        unsigned long long *const *out, int nmat, hipStream_t st) {
+  if (nmat < 1 || nmat > kMaxMats) return hipErrorInvalidValue;
+  DiffArgs d{};
+  for (int i = 0; i < nmat; ++i) {
+    d.a[i] = a[i];
+    d.b[i] = b[i];
+    d.n[i] = n[i];
+    d.out[i] = out[i];
+  }
+  hipLaunchKernelGGL(max_abs_diff_kernel, dim3(16, nmat), dim3(256), 0, st, d);
   return hipGetLastError();
 }
 

@@ -74,6 +74,10 @@ hipError_t round_to_f32(const double *const *src, float *const *dst, int nmat, l
 hipError_t widen_to_f64(const float *const *src, double *const *dst, int nmat, long n,
                         hipStream_t st);
 hipError_t init_fields(int8_t *fields, int M, int N, uint64_t k0, uint64_t k1, hipStream_t st);
+// *out[i] = max(*out[i], max_e |a_i[e] - b_i[e]|), e < n[i], stored as the bits
+// of a non-negative double (atomicMax on the integer pattern)
+hipError_t max_abs_diff(const double *const *a, const double *const *b, const long *n,
+                        unsigned long long *const *out, int nmat, hipStream_t st);
 
 // ---------------------------------------------------------- field updates
 // Batched launches: every update kernel takes one argument record per walker

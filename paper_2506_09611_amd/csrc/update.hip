@@ -100,8 +100,9 @@ __global__ __launch_bounds__(256) void local_step_kernel(Batch<LocalArgs> B) {
     const double r0 = s_r[0], r1 = s_r[1];
     const double R = r0 * r1;
     const double absA = fabs(R);
-    const double u = philox_uniform(C.key0, C.key1, C.sweep, C.slice_code, (uint64_t)(i - 1),
-                                    kPurposeMH);
+    const double u = C.force ? forced_uniform(C.force[i - 1] != 0)
+                             : philox_uniform(C.key0, C.key1, C.sweep, C.slice_code,
+                                              (uint64_t)(i - 1), kPurposeMH);
     const bool finite = !isnan(absA);
     // every lane computes the same value; make it an explicit scalar
     const bool acc = __builtin_amdgcn_readfirstlane((finite && (u < absA)) ? 1 : 0) != 0;
@@ -218,6 +219,8 @@ struct ReduceArgs {
                              // strip_chunks(nt, g.chunks)), 2 per strip (nt)
   int mode;                  // UniMode: uniforms drawn for the following decision
   uint64_t key0, key1, sweep, slice_code;
+  const int8_t *force;       // replay: forced outcomes of the slice visit (or null)
+  const int8_t *xrow;        // the slice's fields (forced heat-bath proposals)
 };
 
 constexpr int kRedThreads = 256;
@@ -311,7 +314,16 @@ __global__ __launch_bounds__(kRedThreads) void group_reduce_kernel(Batch<ReduceA
   const int x = blockIdx.x;
   if (kk <= 0) return;   // this walker has no group here (uneven batch)
   if (x == (int)gridDim.x - 1) {
-    if (s == 0 && a.mode != kUniNone) {
+    if (s == 0 && a.mode != kUniNone && a.force) {
+      // replay: delayed sites accepted iff listed; block proposals set to the
+      // listed fields and the block's Metropolis test accepted
+      if (t < kk) {
+        const bool fl = a.force[a.g0 + t] != 0;
+        const int x = a.xrow[a.g0 + t];
+        a.g.uni[t] = a.mode == kUniDelayed ? forced_uniform(fl) : forced_uniform((fl ? -x : x) > 0);
+      }
+      if (a.mode == kUniBlock && t == kk) a.g.uni[kk] = forced_uniform(true);
+    } else if (s == 0 && a.mode != kUniNone) {
       const uint64_t purpose = a.mode == kUniDelayed ? kPurposeMH : kPurposeHB;
       if (t < kk)
         a.g.uni[t] = philox_uniform(a.key0, a.key1, a.sweep, a.slice_code, (uint64_t)(a.g0 + t),
@@ -1447,7 +1459,8 @@ hipError_t launch_reduce(const SpinMats *m, const GroupBufs *g, const SweepCtx *
   int kkm = 0;
   for (int w = 0; w < nw; ++w) {
     B.w[w] = ReduceArgs{m[w], g[w], g0, kk[w], ntm, do_panels, w0_mode, mode,
-                        c[w].key0, c[w].key1, c[w].sweep, c[w].slice_code};
+                        c[w].key0, c[w].key1, c[w].sweep, c[w].slice_code, c[w].force,
+                        c[w].fields + (long)c[w].li * c[w].N};
     kkm = max(kkm, kk[w]);
   }
   const int nP = do_panels ? ntm * kRedParts : 0, nW = w0_mode ? kkm : 0;

@@ -191,3 +191,45 @@ def test_largest_sector_window(scheme, kw):
     assert np.array_equal(ch.fields(), w.fields)
     assert green_rel_err(ch, w) < 1e-10
     ch.close()
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("scheme,kw", [("delayed", {"k": 32}), ("block", {"b": 16})])
+def test_c3_u8_full_sweep(scheme, kw):
+    """40x40, U/t = 8, N_sigma = 800: one whole sweep with the projection
+    shortened to M = 20 (20 forward and 20 backward slice visits, four
+    stabilisations, slice 20 visited twice in a row), at the benchmark's
+    launch configuration."""
+    p = synth.workload("c3u8", n_slices=20, stab_every=10)
+    w = Walker(p, scheme, **kw)
+    ch = make_chain(p, scheme, **kw)
+    w.sweep()
+    ch.sweep(1)
+    meta, margin = ch.decisions()
+    n, low = compare_decisions(meta, margin, w.log, 0, p.n_slices)
+    print(f"c3 U=8 {scheme} {kw} sweep: {n} decisions equal", flush=True)
+    assert n == (2 * 20 * 1600 if scheme == "delayed" else 2 * 20 * 100)
+    assert np.array_equal(ch.fields(), w.fields)
+    assert green_rel_err(ch, w) < 1e-10
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("scheme,kw,window", [("delayed", {"k": 8}, 10), ("delayed", {"k": 16}, 10),
+                                              ("delayed", {"k": 64}, 10),
+                                              ("delayed", {"k": 128}, 10),
+                                              ("block", {"b": 1}, 1), ("block", {"b": 4}, 2),
+                                              ("block", {"b": 64}, 2)])
+def test_c3_rank_table_windows(scheme, kw, window):
+    """40x40, U/t = 4: every delay rank and block size of the benchmark's
+    table (k = 128 takes the unfused panel / flush path, b = 1 a one-site
+    block per site), forward windows against the oracle."""
+    p = synth.workload("c3", n_slices=20, stab_every=10)
+    w = Walker(p, scheme, **kw)
+    ch = make_chain(p, scheme, **kw)
+    w.forward_window(window)
+    ch.forward_window(window)
+    meta, margin = ch.decisions()
+    n, low = compare_decisions(meta, margin, w.log, 0, p.n_slices)
+    print(f"c3 {scheme} {kw} window {window}: {n} decisions equal", flush=True)
+    assert np.array_equal(ch.fields(), w.fields)
+    assert green_rel_err(ch, w) < 1e-10

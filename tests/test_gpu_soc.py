@@ -126,6 +126,35 @@ def test_soc_12x12_window_split_panels(scheme, k, window):
     ch.close()
 
 
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("scheme,k", [("delayed", 32), ("block", 16), ("local", 1)])
+def test_soc_16x16_full_sweep(scheme, k):
+    """L = 16 at n = 1 (2N = 512, N_e = 256, the benchmark's SOC sizes): one
+    whole sweep of M = 10 (two stabilisations each way)."""
+    p = synth.make_soc_problem(16, 256, -4.0, lam=0.5, dtau=0.05, n_slices=10, stab_every=5,
+                               perturb=1e-3, seed=synth.SEED_BASE + 99)
+    ch = _chain(p, scheme, k)
+    w = _walker(p, scheme, k)
+    ch.sweep(1)
+    w.sweep()
+    _check(ch, w, 0, p.n_slices, f"16x16 soc {scheme} k={k} sweep")
+    ch.close()
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("scheme,k", [("delayed", 32), ("block", 16)])
+def test_soc_24x24_full_sweep(scheme, k):
+    """L = 24 at n = 1 (2N = 1152, N_e = 576): one whole sweep of M = 10."""
+    p = synth.make_soc_problem(24, 576, -4.0, lam=0.5, dtau=0.05, n_slices=10, stab_every=5,
+                               perturb=1e-3, seed=synth.SEED_BASE + 99)
+    ch = _chain(p, scheme, k)
+    w = _walker(p, scheme, k)
+    ch.sweep(1)
+    w.sweep()
+    _check(ch, w, 0, p.n_slices, f"24x24 soc {scheme} k={k} sweep")
+    ch.close()
+
+
 def test_soc_full_filling_and_single_site():
     """N_e = 2N (U_R square): every ratio is det A(-2x) = 1, so every flip is
     accepted and G = 0; and the single-site lattice (2 orbitals, both filled:
