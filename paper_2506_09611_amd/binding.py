@@ -161,7 +161,8 @@ class Chain:
     """One PQMC walker on the GPU (a pqmc_ctx).
 
     hopping: N x N float64; trial_up/trial_dn: N x N_s float64 (orthonormal
-    columns); U >= 0; dtau; n_slices = M; stab_every = k_tau; seed, walker_id:
+    columns); U (U < 0: one complex sector, G complex); dtau; n_slices = M;
+    stab_every = k_tau; seed, walker_id:
     Philox key.  scheme / k / b: update scheme, delay rank, block size; k_max
     and b_max bound later set_opts calls (workspace sizing).  stream: the
     torch.cuda.Stream the walker's work goes to (default: the current one);
@@ -182,6 +183,8 @@ class Chain:
         self._Pd = np.ascontiguousarray(trial_dn, dtype=np.float64)
         N = self._H.shape[0]
         self.N, self.M = N, int(n_slices)
+        # U < 0: the paper's one complex sector (spin down = its conjugate)
+        self.complex = float(U) < 0
         self.n_up, self.n_dn = self._Pu.shape[1], self._Pd.shape[1]
         self._prob = Problem(N, self.n_up, self.n_dn, _dptr(self._H), _dptr(self._Pu),
                              _dptr(self._Pd), float(U), float(dtau), int(n_slices),
@@ -251,8 +254,11 @@ class Chain:
         return st.as_dict()
 
     def green(self, spin):
-        out = np.empty((self.N, self.N), np.float64)
-        _check(self._lib, self._lib.pqmc_get_green(self._ctx, int(spin), _dptr(out)))
+        """G of the spin sector (N x N); complex128 when U < 0."""
+        out = np.empty((self.N, self.N), np.complex128 if self.complex else np.float64)
+        _check(self._lib, self._lib.pqmc_get_green(
+            self._ctx, int(spin), out.view(np.float64).ctypes.data_as(
+                ctypes.POINTER(ctypes.c_double))))
         return out
 
     def fields(self):

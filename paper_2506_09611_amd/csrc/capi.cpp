@@ -13,6 +13,7 @@
 
 #include "../../include/pqmc.h"
 #include "engine.hpp"
+#include "soc.hpp"
 
 namespace {
 thread_local std::string g_last_error;
@@ -41,6 +42,9 @@ int fail_device(hipError_t e, const char *expr, const char *file, int line) {
 using namespace pq;
 
 struct pqmc_ctx {
+  // U < 0: the paper's one-sector complex model, run by the complex engine;
+  // every call below forwards to it
+  pqmc_soc_ctx *cx = nullptr;
   int N = 0, Ns[2] = {0, 0}, M = 0, kt = 0, nst = 0;
   double U = 0, dtau = 0, alpha = 0;
   uint64_t seed = 0, walker = 0;
@@ -187,8 +191,6 @@ pqmc_status validate(const pqmc_problem *p, const pqmc_update_opts *o) {
   if (!p->hopping || !p->trial_up || !p->trial_dn) return set_error(PQMC_EINVAL, "null input");
   if (!(p->dtau > 0) || !std::isfinite(p->dtau)) return set_error(PQMC_EINVAL, "dtau must be > 0");
   if (!std::isfinite(p->U)) return set_error(PQMC_EINVAL, "U must be finite");
-  if (p->U < 0)
-    return set_error(PQMC_EINVAL, "U < 0 (complex coupling) is not supported by this build");
   if (p->n_slices < 1 || p->stab_every < 1 || p->n_slices % p->stab_every)
     return set_error(PQMC_EINVAL, "stab_every must divide n_slices");
   if (o->scheme < PQMC_LOCAL || o->scheme > PQMC_BLOCK_FB) return set_error(PQMC_EINVAL, "scheme");
@@ -300,15 +302,15 @@ bool fp32_form(const pqmc_ctx &c) { return (c.opts.flags & PQMC_FLAG_FP32) != 0;
 int round_T(const Walkers &b) {
   const double *src[kMaxMats];
   float *dst[kMaxMats];
+  long n[kMaxMats];
   int m = 0;
-  long n = 0;
   for (int i = 0; i < b.n; ++i) {
     b[i].t32_ahead = false;
     if (!fp32_form(b[i])) continue;
     for (int s = 0; s < 2; ++s) {
       src[m] = b[i].T[s];
       dst[m] = b[i].T32[s];
-      n = std::max(n, (long)b[i].Ns[s] * b[i].Ns[s]);
+      n[m] = (long)b[i].Ns[s] * b[i].Ns[s];
       ++m;
     }
   }
@@ -683,14 +685,14 @@ int drift_columns(const Walkers &b, int which) {
     // the precision form's running T lives in float32
     const float *src[kMaxMats];
     double *dst[kMaxMats];
+    long n[kMaxMats];
     int m = 0;
-    long n = 0;
     for (int i = 0; i < b.n; ++i) {
       if (!(fp32_form(b[i]) && b[i].t32_ahead)) continue;
       for (int s = 0; s < 2; ++s) {
         src[m] = b[i].T32[s];
         dst[m] = b[i].T[s];
-        n = std::max(n, (long)b[i].Ns[s] * b[i].Ns[s]);
+        n[m] = (long)b[i].Ns[s] * b[i].Ns[s];
         ++m;
       }
     }
@@ -920,6 +922,9 @@ pqmc_status check_batch(pqmc_ctx *const *w, int n) {
   if (!w || n < 1 || n > kMaxBatch) return set_error(PQMC_EINVAL, "batch size must be 1..8");
   for (int i = 0; i < n; ++i) {
     if (!w[i]) return set_error(PQMC_EINVAL, "null context in batch");
+    if ((w[i]->cx != nullptr) != (w[0]->cx != nullptr))
+      return set_error(PQMC_EINVAL, "U < 0 and U >= 0 walkers cannot share a batch");
+    if (w[i]->cx) continue;
     const pqmc_ctx &a = *w[0], &c = *w[i];
     if (c.M != a.M || c.kt != a.kt || c.opts.scheme != a.opts.scheme ||
         c.opts.delay_k != a.opts.delay_k || c.opts.block_b != a.opts.block_b || c.st != a.st ||
@@ -948,6 +953,7 @@ const char *pqmc_last_error(void) { return g_last_error.c_str(); }
 pqmc_status pqmc_workspace_bytes(const pqmc_problem *prob, const pqmc_update_opts *opts,
                                  size_t *bytes) {
   if (!bytes) return set_error(PQMC_EINVAL, "null bytes");
+  if (prob && prob->U < 0) return pq::soc::one_sector_workspace_bytes(prob, opts, bytes);
   pqmc_status v = validate(prob, opts);
   if (v) return v;
   pqmc_ctx c;
@@ -960,6 +966,21 @@ pqmc_status pqmc_create(const pqmc_problem *prob, const pqmc_update_opts *opts, 
                         void *workspace, size_t workspace_bytes, pqmc_ctx **out) {
   if (!out) return set_error(PQMC_EINVAL, "null out");
   *out = nullptr;
+  if (prob && prob->U < 0) {
+    pqmc_ctx *c = new (std::nothrow) pqmc_ctx();
+    if (!c) return set_error(PQMC_ENOMEM, "host allocation failed");
+    pqmc_status st = pq::soc::one_sector_create(prob, opts, hip_stream, workspace,
+                                                workspace_bytes, &c->cx);
+    if (st) {
+      delete c;
+      return st;
+    }
+    pq::soc::one_sector_dims(c->cx, &c->N, &c->M);
+    c->st = static_cast<hipStream_t>(hip_stream);
+    c->opts = *opts;
+    *out = c;
+    return PQMC_OK;
+  }
   pqmc_status v = validate(prob, opts);
   if (v) return v;
   if (!workspace || (reinterpret_cast<uintptr_t>(workspace) % kAlign))
@@ -1026,6 +1047,11 @@ pqmc_status pqmc_create(const pqmc_problem *prob, const pqmc_update_opts *opts, 
 
 pqmc_status pqmc_set_opts(pqmc_ctx *c, const pqmc_update_opts *o) {
   if (!c || !o) return set_error(PQMC_EINVAL, "null argument");
+  if (c->cx) {
+    pqmc_status st = pq::soc::one_sector_set_opts(c->cx, o);
+    if (!st) c->opts = *o;
+    return st;
+  }
   if (o->scheme < PQMC_LOCAL || o->scheme > PQMC_BLOCK_FB) return set_error(PQMC_EINVAL, "scheme");
   if (o->delay_k < 1 || std::min(o->delay_k, c->N) > c->gmax)
     return set_error(PQMC_EINVAL, "delay_k exceeds the workspace bound");
@@ -1042,14 +1068,15 @@ pqmc_status pqmc_set_opts(pqmc_ctx *c, const pqmc_update_opts *o) {
   c->gb.chunks = o->tile_chunks > 0 ? o->tile_chunks : 2;
   // the current T moves to the representation the next call reads
   hipError_t e = hipSuccess;
+  const long cnt[2] = {(long)c->Ns[0] * c->Ns[0], (long)c->Ns[1] * c->Ns[1]};
   if (now && !was) {
     const double *src[2] = {c->T[0], c->T[1]};
     float *dst[2] = {c->T32[0], c->T32[1]};
-    e = round_to_f32(src, dst, 2, (long)std::max(c->Ns[0], c->Ns[1]) * std::max(c->Ns[0], c->Ns[1]), c->st);
+    e = round_to_f32(src, dst, 2, cnt, c->st);
   } else if (was && !now && c->t32_ahead) {
     const float *src[2] = {c->T32[0], c->T32[1]};
     double *dst[2] = {c->T[0], c->T[1]};
-    e = widen_to_f64(src, dst, 2, (long)std::max(c->Ns[0], c->Ns[1]) * std::max(c->Ns[0], c->Ns[1]), c->st);
+    e = widen_to_f64(src, dst, 2, cnt, c->st);
   }
   if (e != hipSuccess) return as_status(fail_device(e, "precision switch", __FILE__, __LINE__));
   c->t32_ahead = false;
@@ -1058,6 +1085,7 @@ pqmc_status pqmc_set_opts(pqmc_ctx *c, const pqmc_update_opts *o) {
 
 pqmc_status pqmc_set_fields(pqmc_ctx *c, const int8_t *fields) {
   if (!c || !fields) return set_error(PQMC_EINVAL, "null argument");
+  if (c->cx) return pq::soc::one_sector_set_fields(c->cx, fields);
   const size_t n = (size_t)c->M * c->N;
   for (size_t e = 0; e < n; ++e)
     if (fields[e] != 1 && fields[e] != -1) return set_error(PQMC_EINVAL, "fields must be +-1");
@@ -1074,6 +1102,7 @@ pqmc_status pqmc_set_fields(pqmc_ctx *c, const int8_t *fields) {
 
 pqmc_status pqmc_get_fields(pqmc_ctx *c, int8_t *fields) {
   if (!c || !fields) return set_error(PQMC_EINVAL, "null argument");
+  if (c->cx) return pqmc_soc_get_fields(c->cx, fields);
   hipError_t e = hipStreamSynchronize(c->st);
   if (e == hipSuccess)
     e = hipMemcpy(fields, c->fields, (size_t)c->M * c->N, hipMemcpyDeviceToHost);
@@ -1086,6 +1115,13 @@ pqmc_status pqmc_batch_sweep(pqmc_ctx *const *ctxs, int32_t n, int32_t n_sweeps,
   pqmc_status v = check_batch(ctxs, n);
   if (v) return v;
   if (n_sweeps < 0) return set_error(PQMC_EINVAL, "n_sweeps < 0");
+  if (ctxs[0]->cx) {   // U < 0: one walker after the other
+    for (int i = 0; i < n; ++i) {
+      v = pqmc_soc_sweep(ctxs[i]->cx, n_sweeps, out ? out + i : nullptr);
+      if (v) return v;
+    }
+    return PQMC_OK;
+  }
   for (int i = 0; i < n; ++i)
     if (ctxs[i]->windowed || ctxs[i]->position != 0)
       return set_error(PQMC_ESTATE, "walker is mid-sweep after pqmc_forward_window");
@@ -1188,6 +1224,7 @@ pqmc_status pqmc_sweep(pqmc_ctx *c, int32_t n_sweeps, pqmc_stats *out) {
 
 pqmc_status pqmc_replay(pqmc_ctx *c, const int8_t *flips, pqmc_stats *out) {
   if (!c || !flips) return set_error(PQMC_EINVAL, "null argument");
+  if (c->cx) return pq::soc::one_sector_replay(c->cx, flips, out);
   if (c->failed) return set_error(PQMC_ESTATE, "context failed; call pqmc_set_fields");
   if (c->windowed || c->position != 0)
     return set_error(PQMC_ESTATE, "walker is mid-sweep after pqmc_forward_window");
@@ -1207,6 +1244,13 @@ pqmc_status pqmc_batch_forward_window(pqmc_ctx *const *ctxs, int32_t n, int32_t 
   pqmc_status v = check_batch(ctxs, n);
   if (v) return v;
   if (n_slices < 0 || n_slices > ctxs[0]->M) return set_error(PQMC_EINVAL, "n_slices out of range");
+  if (ctxs[0]->cx) {   // U < 0: one walker after the other
+    for (int i = 0; i < n; ++i) {
+      v = pqmc_soc_forward_window(ctxs[i]->cx, n_slices, out ? out + i : nullptr);
+      if (v) return v;
+    }
+    return PQMC_OK;
+  }
   for (int i = 0; i < n; ++i)
     if (ctxs[i]->windowed || ctxs[i]->position != 0)
       return set_error(PQMC_ESTATE, "walker is mid-sweep");
@@ -1232,12 +1276,14 @@ pqmc_status pqmc_forward_window(pqmc_ctx *c, int32_t n_slices, pqmc_stats *out) 
 
 pqmc_status pqmc_get_green(pqmc_ctx *c, int32_t spin, double *out) {
   if (!c || !out || spin < 0 || spin > 1) return set_error(PQMC_EINVAL, "bad argument");
+  if (c->cx) return pq::soc::one_sector_green(c->cx, spin, out);
   const int N = c->N, n = c->Ns[spin];
   if (fp32_form(*c) && c->t32_ahead) {
     // flushes since the last stabilisation live in the float32 copy only
     const float *src[1] = {c->T32[spin]};
     double *dst[1] = {c->T[spin]};
-    hipError_t e = widen_to_f64(src, dst, 1, (long)n * n, c->st);
+    const long cnt[1] = {(long)n * n};
+    hipError_t e = widen_to_f64(src, dst, 1, cnt, c->st);
     if (e != hipSuccess) return as_status(fail_device(e, "green", __FILE__, __LINE__));
   }
   GemmBatch a{};
@@ -1275,12 +1321,14 @@ static pqmc_status copy_log(pqmc_ctx *c, const int32_t *dmeta, const double *dma
 pqmc_status pqmc_get_decisions(pqmc_ctx *c, int32_t *meta, double *margin, size_t cap,
                                size_t *n) {
   if (!c) return set_error(PQMC_EINVAL, "null context");
+  if (c->cx) return pqmc_soc_get_decisions(c->cx, meta, margin, cap, n);
   return copy_log(c, c->log_meta, c->log_margin, c->log_count, meta, margin, cap, n);
 }
 
 pqmc_status pqmc_get_heat_bath(pqmc_ctx *c, int32_t *meta, double *margin, size_t cap,
                                size_t *n) {
   if (!c) return set_error(PQMC_EINVAL, "null context");
+  if (c->cx) return set_error(PQMC_EINVAL, "heat-bath draws are not logged for U < 0");
   return copy_log(c, c->hb_meta, c->hb_margin, c->hb_total, meta, margin, cap, n);
 }
 
@@ -1295,6 +1343,11 @@ pqmc_status pqmc_get_kernel_times(pqmc_ctx *c, double *totals, uint64_t *counts)
 
 pqmc_status pqmc_destroy(pqmc_ctx *c) {
   if (!c) return PQMC_OK;
+  if (c->cx) {
+    pqmc_soc_destroy(c->cx);
+    delete c;
+    return PQMC_OK;
+  }
   (void)hipStreamSynchronize(c->st);
   for (hipEvent_t e : c->evs) (void)hipEventDestroy(e);
   for (hipEvent_t e : c->kevs) (void)hipEventDestroy(e);

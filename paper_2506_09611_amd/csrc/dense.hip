@@ -510,18 +510,21 @@ __global__ void copy_kernel(const double *s0, const double *s1, long lds, double
 struct ConvArgs {
   const void *src[kMaxMats];
   void *dst[kMaxMats];
+  long n[kMaxMats];    // elements of each pair
 };
 
-__global__ void round_kernel(ConvArgs a, long n) {
+__global__ void round_kernel(ConvArgs a) {
   const double *s = static_cast<const double *>(a.src[blockIdx.y]);
   float *d = static_cast<float *>(a.dst[blockIdx.y]);
+  const long n = a.n[blockIdx.y];
   for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x)
     d[e] = (float)s[e];
 }
 
-__global__ void widen_kernel(ConvArgs a, long n) {
+__global__ void widen_kernel(ConvArgs a) {
   const float *s = static_cast<const float *>(a.src[blockIdx.y]);
   double *d = static_cast<double *>(a.dst[blockIdx.y]);
+  const long n = a.n[blockIdx.y];
   for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x)
     d[e] = (double)s[e];
 }
@@ -638,27 +641,29 @@ hipError_t copy_matrix(const double *src0, const double *src1, long lds, double 
   return hipGetLastError();
 }
 
-hipError_t round_to_f32(const double *const *src, float *const *dst, int nmat, long n,
+hipError_t round_to_f32(const double *const *src, float *const *dst, int nmat, const long *n,
                         hipStream_t st) {
   if (nmat < 1 || nmat > kMaxMats) return hipErrorInvalidValue;
   ConvArgs a{};
   for (int i = 0; i < nmat; ++i) {
     a.src[i] = src[i];
     a.dst[i] = dst[i];
+    a.n[i] = n[i];
   }
-  hipLaunchKernelGGL(round_kernel, dim3(256, nmat), dim3(256), 0, st, a, n);
+  hipLaunchKernelGGL(round_kernel, dim3(256, nmat), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 
-hipError_t widen_to_f64(const float *const *src, double *const *dst, int nmat, long n,
+hipError_t widen_to_f64(const float *const *src, double *const *dst, int nmat, const long *n,
                         hipStream_t st) {
   if (nmat < 1 || nmat > kMaxMats) return hipErrorInvalidValue;
   ConvArgs a{};
   for (int i = 0; i < nmat; ++i) {
     a.src[i] = src[i];
     a.dst[i] = dst[i];
+    a.n[i] = n[i];
   }
-  hipLaunchKernelGGL(widen_kernel, dim3(256, nmat), dim3(256), 0, st, a, n);
+  hipLaunchKernelGGL(widen_kernel, dim3(256, nmat), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 

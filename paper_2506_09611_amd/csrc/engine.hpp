@@ -68,10 +68,10 @@ hipError_t set_identity_block(double *const *E, int nmat, long ld, int n, int co
                               hipStream_t st);
 hipError_t copy_matrix(const double *src0, const double *src1, long lds, double *dst0,
                        double *dst1, long ldd, int rows, int cols, hipStream_t st);
-// dst = (float) src, dst = (double) src (n elements each, up to kMaxMats pairs)
-hipError_t round_to_f32(const double *const *src, float *const *dst, int nmat, long n,
+// dst_i = (float) src_i, dst_i = (double) src_i (n[i] elements, up to kMaxMats pairs)
+hipError_t round_to_f32(const double *const *src, float *const *dst, int nmat, const long *n,
                         hipStream_t st);
-hipError_t widen_to_f64(const float *const *src, double *const *dst, int nmat, long n,
+hipError_t widen_to_f64(const float *const *src, double *const *dst, int nmat, const long *n,
                         hipStream_t st);
 hipError_t init_fields(int8_t *fields, int M, int N, uint64_t k0, uint64_t k1, hipStream_t st);
 // *out[i] = max(*out[i], max_e |a_i[e] - b_i[e]|), e < n[i], stored as the bits

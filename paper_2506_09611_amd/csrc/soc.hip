@@ -734,6 +734,263 @@ __global__ __launch_bounds__(kDecThreads) void soc_block_decide_kernel(SocDecide
   }
 }
 
+// ---------------------------------------------------- one sector (w = 1)
+// The paper's own U < 0 model (Sec. II B, Eqs. (13)-(14)): the imaginary
+// coupling alpha = i gamma gives B_dn = conj(B_up), so only the spin-up
+// sector (N orbitals, N_up fermions) is propagated and every ratio is
+// R = r_up r_dn = |r_up|^2.  The field of site i multiplies row i by the
+// phase e^{i gamma x_i}; a flip x -> -x is the scalar
+// delta(x) = e^{-2 i gamma x} - 1 = (dd, -x doff) with dd = cos 2 gamma - 1,
+// doff = sin 2 gamma (the same numbers as the rank-two path's delta block).
+
+// Y[i, :] = e^{i sign gamma x_i} X[i, :] (X == Y allowed); c = cos gamma, s = sin gamma
+__global__ __launch_bounds__(256) void phase_kernel(const double2 *X, long ldx, double2 *Y,
+                                                    long ldy, int ncols, int N,
+                                                    const int8_t *xrow, double c, double s,
+                                                    double sign) {
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (long)N * ncols) return;
+  const int i = (int)(e / ncols), col = (int)(e % ncols);
+  const double sn = sign * (double)xrow[i] * s;
+  const double2 v = X[(long)i * ldx + col];
+  Y[(long)i * ldy + col] = make_double2(c * v.x - sn * v.y, c * v.y + sn * v.x);
+}
+
+__device__ __forceinline__ double2 flip_delta(const SocDecideArgs &a, double x) {
+  return make_double2(a.dd, -x * a.doff);
+}
+
+// Delayed (and, with kk = 1, local) decisions of one group of kk <= 64 sites
+// of the one-sector model.  In: W0p = U_g T0 U_L[:, g] (kk x kk).  With
+// W0 = W0p diag(delta) and Mc = (1 + W0_AA)^{-1} spread to kk x kk (zero
+// outside the accepted set A), site j's ratio is the Schur complement
+// r = 1 + W0_jj - W0_j,: Mc W0_:,j (the recursion of Eq. (28)) and the test
+// is u < |r|^2; accepting j borders Mc by one row and column.  Out: D =
+// diag(delta) Mc, so that T = T0 - (T0 U_L[:, g]) D (U_g T0) (Eq. (30)).
+__global__ __launch_bounds__(kDecThreads) void cplx_decide_kernel(SocDecideArgs a) {
+  extern __shared__ double2 lds[];
+  const int n = a.kk;
+  const int ld = n + 1;
+  double2 *W0 = lds;                 // n x n, leading dim ld
+  double2 *Mc = W0 + n * ld;         // n x n, leading dim ld
+  double2 *u = Mc + n * ld;          // Mc W0[:, j]
+  double2 *w = u + n;                // W0[j, :] Mc
+  __shared__ double2 Sinv;
+  __shared__ int accs;
+  __shared__ double xs[64], us[64];
+  __shared__ int accm[64];
+  __shared__ int n_acc;
+  const int t = threadIdx.x, lane = t & 63;
+  int n_low = 0;
+  bool nonfinite = false;
+  int8_t *xrow = a.fields + (long)a.li * a.N + a.g0;
+  for (int j = t; j < n; j += kDecThreads) {
+    xs[j] = (double)xrow[j];
+    us[j] = a.force ? (a.force[a.g0 + j] ? -1.0 : __builtin_inf())
+                    : philox_uniform(a.key0, a.key1, a.sweep, a.slice_code,
+                                     (uint64_t)(a.g0 + j), kPurposeMH);
+  }
+  if (t == 0) n_acc = 0;
+  __syncthreads();
+  for (int e = t; e < n * n; e += kDecThreads) {
+    const int r = e / n, j = e - r * n;
+    W0[r * ld + j] = cmul(a.W0p[(long)r * n + j], flip_delta(a, xs[j]));
+  }
+  for (int e = t; e < n * ld; e += kDecThreads) Mc[e] = make_double2(0.0, 0.0);
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    if (t < n) {
+      double2 s = make_double2(0.0, 0.0);
+      for (int b = 0; b < n; ++b) cfma(s, Mc[t * ld + b], W0[b * ld + j]);
+      u[t] = s;
+    } else if (t >= 64 && t < 64 + n) {
+      const int c = t - 64;
+      double2 s = make_double2(0.0, 0.0);
+      for (int b = 0; b < n; ++b) cfma(s, W0[j * ld + b], Mc[b * ld + c]);
+      w[c] = s;
+    }
+    __syncthreads();
+    if (t < 64) {
+      double2 prod = lane < n ? cmul(W0[j * ld + lane], u[lane]) : make_double2(0.0, 0.0);
+      for (int off = 32; off > 0; off >>= 1) {
+        prod.x += __shfl_down(prod.x, off, 64);
+        prod.y += __shfl_down(prod.y, off, 64);
+      }
+      if (lane == 0) {
+        double2 r = csub(W0[j * ld + j], prod);
+        r.x += 1.0;
+        const double R = r.x * r.x + r.y * r.y;   // r_up r_dn with r_dn = conj(r_up)
+        const double uu = us[j];
+        const bool finite = !isnan(R);
+        const bool acc = finite && uu < R;
+        const double margin = R - uu;
+        if (fabs(margin) < 1e-12) ++n_low;
+        if (!finite) nonfinite = true;
+        const int site = a.g0 + j;
+        const long long idx = a.log_base + site;
+        if (a.log_meta && idx < a.log_cap) {
+          a.log_meta[3 * idx + 0] = (int32_t)a.slice_code;
+          a.log_meta[3 * idx + 1] = site;
+          a.log_meta[3 * idx + 2] = acc ? 1 : 0;
+          a.log_margin[idx] = margin;
+        }
+        if (acc) {
+          Sinv = cdiv(make_double2(1.0, 0.0), r);
+          xrow[j] = (int8_t)(xs[j] > 0.0 ? -1 : 1);
+          n_acc += 1;
+        }
+        accs = acc ? 1 : 0;
+        accm[j] = accs;
+      }
+    }
+    __syncthreads();
+    if (accs) {
+      // Mc += (e_j - u) Sinv (e_j - w)^T
+      const double2 si = Sinv;
+      for (int e = t; e < n * n; e += kDecThreads) {
+        const int r = e / n, c = e - r * n;
+        const double2 l = make_double2((r == j ? 1.0 : 0.0) - u[r].x, -u[r].y);
+        const double2 g = cmul(si, make_double2((c == j ? 1.0 : 0.0) - w[c].x, -w[c].y));
+        cfma(Mc[r * ld + c], l, g);
+      }
+    }
+    __syncthreads();
+  }
+  // rows of U_R of the accepted sites <- (1 + delta) rows
+  for (int j = 0; j < n; ++j) {
+    if (!accm[j]) continue;
+    const double2 f = make_double2(1.0 + a.dd, -xs[j] * a.doff);
+    double2 *p0 = a.UR + (long)(a.g0 + j) * a.ne;
+    for (int c = t; c < a.ne; c += kDecThreads) p0[c] = cmul(f, p0[c]);
+  }
+  for (int e = t; e < n * n; e += kDecThreads) {
+    const int j = e / n, c = e - j * n;
+    a.D[(long)j * n + c] = cmul(flip_delta(a, xs[j]), Mc[j * ld + c]);
+  }
+  if (t == 0) {
+    *a.nflush = n_acc > 0 ? n : 0;
+    a.stats[kStProposed] += n;
+    a.stats[kStFieldUpdates] += n;
+    a.stats[kStAccepted] += n_acc;
+    a.stats[kStFlips] += n_acc;
+    if (n_low) a.stats[kStLowMargin] += n_low;
+    if (nonfinite) a.stats[kStError] |= kErrNonFinite;
+  }
+}
+
+// Block force-bias decision for kk <= 64 sites of the one-sector model
+// (Sec. III B).  Force bias with the block's fields removed,
+// Db = diag(e^{-i gamma x} - 1): nbar_j = (1 + Db_j) [W0p (1 + Db W0p)^{-1}]_jj
+// for spin up, nbar_dn = conj(nbar_up), so s_j = alpha (nbar_up - nbar_dn)
+// = -2 gamma Im nbar_j.  Heat bath, flip set F, r = det(1 + W0p_FF delta_F),
+// prior prod_F e^{2 s_j x_j}, accept iff u < |r|^2 prior.  Out as the
+// rank-two kernel: D = delta_F (1 + W0p_FF delta_F)^{-1} spread to kk x kk.
+__global__ __launch_bounds__(kDecThreads) void cplx_block_decide_kernel(SocDecideArgs a) {
+  extern __shared__ double2 lds[];
+  const int n = a.kk;
+  const int ld = 2 * n + 1;
+  double2 *Aug = lds;                // n x ld
+  __shared__ double xs[64], sv[64];
+  __shared__ int fidx[64], nf_s, acc_s, ok_s;
+  __shared__ double2 det_s;
+  const int t = threadIdx.x;
+  int8_t *xrow = a.fields + (long)a.li * a.N + a.g0;
+  for (int j = t; j < n; j += kDecThreads) xs[j] = (double)xrow[j];
+  __syncthreads();
+  // [E^T | W0p^T], E = 1 + Db W0p
+  for (int e = t; e < n * n; e += kDecThreads) {
+    const int r = e / n, c = e - r * n;
+    const double2 db = make_double2(a.c1 - 1.0, -xs[c] * a.s1);
+    double2 v = cmul(db, a.W0p[(long)c * n + r]);
+    if (r == c) v.x += 1.0;
+    Aug[r * ld + c] = v;
+    Aug[r * ld + n + c] = a.W0p[(long)c * n + r];
+  }
+  __syncthreads();
+  gj_lds(Aug, n, 2 * n, ld, &det_s, &ok_s);
+  if (t < n) {
+    const int j = t;
+    const double2 nb = cmul(make_double2(a.c1, -xs[j] * a.s1), Aug[j * ld + n + j]);
+    sv[j] = ok_s ? -2.0 * a.gamma * nb.y : 0.0;
+  }
+  __syncthreads();
+  if (t == 0) {
+    int nf = 0;
+    for (int j = 0; j < n; ++j) {
+      const double pu = 1.0 / (1.0 + exp(-2.0 * sv[j]));
+      double u;
+      if (a.force) {
+        const double xt = a.force[a.g0 + j] ? -xs[j] : xs[j];
+        u = xt > 0.0 ? -1.0 : __builtin_inf();
+      } else {
+        u = philox_uniform(a.key0, a.key1, a.sweep, a.slice_code, (uint64_t)(a.g0 + j),
+                           kPurposeHB);
+      }
+      const double xn = u < pu ? 1.0 : -1.0;
+      if (xn != xs[j]) fidx[nf++] = j;
+    }
+    nf_s = nf;
+    if (!ok_s) a.stats[kStError] |= kErrSingular;
+  }
+  __syncthreads();
+  const int nf = nf_s, m = nf;
+  const int ldf = 2 * m + 1;
+  for (int e = t; e < m * m; e += kDecThreads) {
+    const int r = e / m, c = e - r * m;
+    double2 v = cmul(a.W0p[(long)fidx[r] * n + fidx[c]], flip_delta(a, xs[fidx[c]]));
+    if (r == c) v.x += 1.0;
+    Aug[r * ldf + c] = v;
+    Aug[r * ldf + m + c] = make_double2(r == c ? 1.0 : 0.0, 0.0);
+  }
+  __syncthreads();
+  if (nf > 0) gj_lds(Aug, m, 2 * m, ldf, &det_s, &ok_s);
+  if (t == 0) {
+    const double2 r = nf > 0 ? det_s : make_double2(1.0, 0.0);
+    double pe = 0.0;
+    for (int q = 0; q < nf; ++q) pe += 2.0 * sv[fidx[q]] * xs[fidx[q]];
+    const double prior = exp(pe);
+    const double absA = (r.x * r.x + r.y * r.y) * prior;
+    const double u = a.force ? -1.0
+                             : philox_uniform(a.key0, a.key1, a.sweep, a.slice_code,
+                                              (uint64_t)a.g0, kPurposeMH);
+    const bool finite = !isnan(absA);
+    const bool acc = finite && u < absA && (nf == 0 || ok_s);
+    const double margin = absA - u;
+    a.stats[kStProposed] += 1;
+    a.stats[kStFieldUpdates] += n;
+    if (acc) {
+      a.stats[kStAccepted] += 1;
+      a.stats[kStFlips] += nf;
+    }
+    if (fabs(margin) < 1e-12) a.stats[kStLowMargin] += 1;
+    if (!finite) a.stats[kStError] |= kErrNonFinite;
+    const long long idx = a.log_base;
+    if (a.log_meta && idx < a.log_cap) {
+      a.log_meta[3 * idx + 0] = (int32_t)a.slice_code;
+      a.log_meta[3 * idx + 1] = a.g0;
+      a.log_meta[3 * idx + 2] = acc ? 1 : 0;
+      a.log_margin[idx] = margin;
+    }
+    acc_s = acc && nf > 0;
+    *a.nflush = (acc && nf > 0) ? n : 0;
+  }
+  __syncthreads();
+  for (int e = t; e < n * n; e += kDecThreads) a.D[e] = make_double2(0.0, 0.0);
+  __syncthreads();
+  if (!acc_s) return;
+  for (int e = t; e < m * m; e += kDecThreads) {
+    const int r = e / m, c = e - r * m;
+    a.D[(long)fidx[r] * n + fidx[c]] = cmul(flip_delta(a, xs[fidx[r]]), Aug[r * ldf + m + c]);
+  }
+  for (int q = 0; q < nf; ++q) {
+    const int j = fidx[q];
+    const double2 f = make_double2(1.0 + a.dd, -xs[j] * a.doff);
+    double2 *p0 = a.UR + (long)(a.g0 + j) * a.ne;
+    for (int c = t; c < a.ne; c += kDecThreads) p0[c] = cmul(f, p0[c]);
+    if (t == 0) xrow[j] = (int8_t)(xs[j] > 0.0 ? -1 : 1);
+  }
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------- host
@@ -839,6 +1096,39 @@ hipError_t block_decide(const SocDecideArgs &a, hipStream_t st) {
       (int)(sizeof(double2) * 64 * 129));
   if (attr != hipSuccess) return attr;
   hipLaunchKernelGGL(soc_block_decide_kernel, dim3(1), dim3(kDecThreads), lds, st, a);
+  return hipGetLastError();
+}
+
+hipError_t phase_rows(const double2 *X, long ldx, double2 *Y, long ldy, int ncols, int N,
+                      const int8_t *xrow, double c, double s, double sign, hipStream_t st) {
+  const long tot = (long)N * ncols;
+  if (tot == 0) return hipSuccess;
+  hipLaunchKernelGGL(phase_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, X, ldx,
+                     Y, ldy, ncols, N, xrow, c, s, sign);
+  return hipGetLastError();
+}
+
+hipError_t decide1(const SocDecideArgs &a, hipStream_t st) {
+  if (a.kk < 1 || a.kk > 2 * kSocMaxK) return hipErrorInvalidValue;
+  const int n = a.kk;
+  const size_t lds = sizeof(double2) * (2 * (size_t)n * (n + 1) + 2 * (size_t)n);
+  static const hipError_t attr = hipFuncSetAttribute(
+      (const void *)cplx_decide_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+      (int)(sizeof(double2) * (2 * 64 * 65 + 2 * 64)));
+  if (attr != hipSuccess) return attr;
+  hipLaunchKernelGGL(cplx_decide_kernel, dim3(1), dim3(kDecThreads), lds, st, a);
+  return hipGetLastError();
+}
+
+hipError_t block_decide1(const SocDecideArgs &a, hipStream_t st) {
+  if (a.kk < 1 || a.kk > 2 * kSocMaxK) return hipErrorInvalidValue;
+  const int n = a.kk;
+  const size_t lds = sizeof(double2) * (size_t)n * (2 * n + 1);
+  static const hipError_t attr = hipFuncSetAttribute(
+      (const void *)cplx_block_decide_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+      (int)(sizeof(double2) * 64 * 129));
+  if (attr != hipSuccess) return attr;
+  hipLaunchKernelGGL(cplx_block_decide_kernel, dim3(1), dim3(kDecThreads), lds, st, a);
   return hipGetLastError();
 }
 

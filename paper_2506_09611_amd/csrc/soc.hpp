@@ -79,10 +79,36 @@ struct SocDecideArgs {
   int32_t *log_meta;
   double *log_margin;
   long long log_base, log_cap;
+  const int8_t *force;     // replay: forced outcomes of the slice visit (or null)
 };
 hipError_t decide(const SocDecideArgs &a, hipStream_t st);
+// The one-sector model (U < 0 of Sec. II B, w = 1): rows scaled by the
+// phases e^{i sign gamma x_i}; decisions of kk <= 64 sites with a scalar
+// flip delta per site (delayed / local, and block force bias).
+hipError_t phase_rows(const double2 *X, long ldx, double2 *Y, long ldy, int ncols, int N,
+                      const int8_t *xrow, double c, double s, double sign, hipStream_t st);
+hipError_t decide1(const SocDecideArgs &a, hipStream_t st);
+hipError_t block_decide1(const SocDecideArgs &a, hipStream_t st);
 // block force bias over the kk sites of the group (log entry at log_base)
 hipError_t block_decide(const SocDecideArgs &a, hipStream_t st);
 
+}  // namespace soc
+}  // namespace pq
+
+// The paper's U < 0 model behind the spin-decoupled calls (soc_capi.cpp):
+// one complex spin-up sector run by the width-one form of this engine.
+#include "../../include/pqmc.h"
+namespace pq {
+namespace soc {
+pqmc_status one_sector_workspace_bytes(const pqmc_problem *p, const pqmc_update_opts *o,
+                                       size_t *bytes);
+pqmc_status one_sector_create(const pqmc_problem *p, const pqmc_update_opts *o,
+                              void *hip_stream, void *workspace, size_t workspace_bytes,
+                              pqmc_soc_ctx **out);
+pqmc_status one_sector_set_opts(pqmc_soc_ctx *c, const pqmc_update_opts *o);
+pqmc_status one_sector_set_fields(pqmc_soc_ctx *c, const int8_t *fields);
+pqmc_status one_sector_replay(pqmc_soc_ctx *c, const int8_t *flips, pqmc_stats *out);
+pqmc_status one_sector_green(pqmc_soc_ctx *c, int spin, double *out);
+int one_sector_dims(const pqmc_soc_ctx *c, int *N, int *M);
 }  // namespace soc
 }  // namespace pq

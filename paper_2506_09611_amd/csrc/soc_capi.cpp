@@ -17,6 +17,11 @@ using namespace pq;
 using namespace pq::soc;
 
 struct pqmc_soc_ctx {
+  // w: orbitals per site in the sector.  2: the spin-orbit coupled model
+  // (rows i and N + i, 2 x 2 rotations).  1: the paper's U < 0 model of
+  // Sec. II B, one complex spin-up sector with diagonal phases (spin down is
+  // its complex conjugate and is never stored).
+  int w = 2;
   int N = 0, n2 = 0, ne = 0, M = 0, kt = 0, nst = 0, k = 1;
   double U = 0, dtau = 0, gamma = 0, c1 = 1, s1 = 0, dd = 0, doff = 0;
   uint64_t seed = 0, walker = 0;
@@ -37,6 +42,8 @@ struct pqmc_soc_ctx {
   double2 *Tay0 = nullptr, *Tay1 = nullptr;         // n2 x n2 (set-up, then G)
   int *nflush = nullptr;
   int8_t *fields = nullptr;
+  int8_t *replay = nullptr;                         // 2 M x N forced outcomes (w = 1)
+  bool replaying = false;
   unsigned long long *stats = nullptr;
   int32_t *log_meta = nullptr;
   double *log_margin = nullptr;
@@ -162,6 +169,7 @@ void layout(pqmc_soc_ctx &c, char *base, size_t *bytes) {
   }
   c.nflush = cv.take<int>(4);
   c.fields = cv.take<int8_t>((size_t)c.M * c.N);
+  if (c.w == 1) c.replay = cv.take<int8_t>((size_t)2 * c.M * c.N);
   c.stats = cv.take<unsigned long long>(16);
   if (c.opts.flags & PQMC_FLAG_LOG) {
     c.log_cap = 2LL * c.M * c.N;
@@ -241,8 +249,14 @@ int prop_forward(pqmc_soc_ctx &c, int l) {
   int rc = gemm1(cdesc(c.K, n2, c.UR, ne, nur, ne, n2, ne, n2), kOpN, kOpN, c.st);
   if (!rc) rc = gemm1(cdesc(c.Kinv, n2, c.ULt, ne, nul, ne, n2, ne, n2), kOpT, kOpN, c.st);
   if (rc) return rc;
-  PQ_HIP_CHECK(rotate_rows(nur, ne, nur, ne, ne, c.N, x, c.c1, c.s1, 1.0, c.st));
-  PQ_HIP_CHECK(rotate_rows(nul, ne, nul, ne, ne, c.N, x, c.c1, c.s1, 1.0, c.st));
+  if (c.w == 1) {
+    // U_R <- diag(e^{i gamma x}) K U_R; ULt <- diag(e^{-i gamma x}) K^{-T} ULt
+    PQ_HIP_CHECK(phase_rows(nur, ne, nur, ne, ne, c.N, x, c.c1, c.s1, 1.0, c.st));
+    PQ_HIP_CHECK(phase_rows(nul, ne, nul, ne, ne, c.N, x, c.c1, c.s1, -1.0, c.st));
+  } else {
+    PQ_HIP_CHECK(rotate_rows(nur, ne, nur, ne, ne, c.N, x, c.c1, c.s1, 1.0, c.st));
+    PQ_HIP_CHECK(rotate_rows(nul, ne, nul, ne, ne, c.N, x, c.c1, c.s1, 1.0, c.st));
+  }
   c.UR = nur;
   c.ULt = nul;
   return PQMC_OK;
@@ -255,13 +269,20 @@ int prop_backward(pqmc_soc_ctx &c, int l, bool with_R) {
   const int n2 = c.n2, ne = c.ne;
   const int8_t *x = c.fields + (size_t)(l - 1) * c.N;
   double2 *nul = other(c.ULt, c.Lw);
-  PQ_HIP_CHECK(rotate_rows(c.ULt, ne, c.Xtmp, ne, ne, c.N, x, c.c1, c.s1, -1.0, c.st));
+  // ULt <- K^T diag(e^{i gamma x}) ULt; U_R <- K^{-1} diag(e^{-i gamma x}) U_R (w = 1)
+  if (c.w == 1)
+    PQ_HIP_CHECK(phase_rows(c.ULt, ne, c.Xtmp, ne, ne, c.N, x, c.c1, c.s1, 1.0, c.st));
+  else
+    PQ_HIP_CHECK(rotate_rows(c.ULt, ne, c.Xtmp, ne, ne, c.N, x, c.c1, c.s1, -1.0, c.st));
   int rc = gemm1(cdesc(c.K, n2, c.Xtmp, ne, nul, ne, n2, ne, n2), kOpT, kOpN, c.st);
   if (rc) return rc;
   c.ULt = nul;
   if (with_R) {
     double2 *nur = other(c.UR, c.Rw);
-    PQ_HIP_CHECK(rotate_rows(c.UR, ne, c.Xtmp, ne, ne, c.N, x, c.c1, c.s1, -1.0, c.st));
+    if (c.w == 1)
+      PQ_HIP_CHECK(phase_rows(c.UR, ne, c.Xtmp, ne, ne, c.N, x, c.c1, c.s1, -1.0, c.st));
+    else
+      PQ_HIP_CHECK(rotate_rows(c.UR, ne, c.Xtmp, ne, ne, c.N, x, c.c1, c.s1, -1.0, c.st));
     rc = gemm1(cdesc(c.Kinv, n2, c.Xtmp, ne, nur, ne, n2, ne, n2), kOpN, kOpN, c.st);
     if (rc) return rc;
     c.UR = nur;
@@ -314,7 +335,7 @@ int update_slice(pqmc_soc_ctx &c, int l, int dir) {
   if (rc) return rc;
   int nblk = 0;
   for (int g0 = 0; g0 < N; g0 += c.k, ++nblk) {
-    const int kk = std::min(c.k, N - g0), n = 2 * kk;
+    const int kk = std::min(c.k, N - g0), n = c.w * kk;
     const double2 *ur0 = c.UR + (size_t)g0 * ne, *ur1 = c.UR + (size_t)(N + g0) * ne;
     const double2 *ul0 = c.ULt + (size_t)g0 * ne, *ul1 = c.ULt + (size_t)(N + g0) * ne;
     // P2 = W_g T; then P1 = T U_L[:, g] and W0' = P2 U_L[:, g].  Over a deep
@@ -326,7 +347,7 @@ int update_slice(pqmc_soc_ctx &c, int l, int dir) {
     double2 *w0 = split ? c.W0part : c.W0;
     CgemmBatch a{};
     a.d[a.count++] = cdesc(ur0, ne, c.T, c.ldT, p2, ne, kk, ne, ne);
-    a.d[a.count++] = cdesc(ur1, ne, c.T, c.ldT, p2 + (size_t)kk * ne, ne, kk, ne, ne);
+    if (c.w == 2) a.d[a.count++] = cdesc(ur1, ne, c.T, c.ldT, p2 + (size_t)kk * ne, ne, kk, ne, ne);
     for (int i = 0; i < a.count && split; ++i) {
       a.d[i].ksplit = c.ksplit;
       a.d[i].csplit = s2;
@@ -339,12 +360,13 @@ int update_slice(pqmc_soc_ctx &c, int l, int dir) {
     }
     CgemmBatch b{};
     b.d[b.count++] = cdesc(c.T, c.ldT, ul0, ne, p1, n, ne, kk, ne);
-    b.d[b.count++] = cdesc(c.T, c.ldT, ul1, ne, p1 + kk, n, ne, kk, ne);
+    if (c.w == 2) b.d[b.count++] = cdesc(c.T, c.ldT, ul1, ne, p1 + kk, n, ne, kk, ne);
+    const int np1 = b.count;
     b.d[b.count++] = cdesc(c.P2, ne, ul0, ne, w0, n, n, kk, ne);
-    b.d[b.count++] = cdesc(c.P2, ne, ul1, ne, w0 + kk, n, n, kk, ne);
+    if (c.w == 2) b.d[b.count++] = cdesc(c.P2, ne, ul1, ne, w0 + kk, n, n, kk, ne);
     for (int i = 0; i < b.count && split; ++i) {
       b.d[i].ksplit = c.ksplit;
-      b.d[i].csplit = i < 2 ? s1 : sw;
+      b.d[i].csplit = i < np1 ? s1 : sw;
     }
     PQ_HIP_CHECK(cgemm(b, kOpN, kOpT, c.st));
     if (split) {
@@ -378,7 +400,10 @@ int update_slice(pqmc_soc_ctx &c, int l, int dir) {
     d.log_margin = c.log_margin;
     d.log_base = c.block ? c.log_count + nblk : c.log_count;
     d.log_cap = c.log_cap;
-    if (c.block)
+    d.force = c.replaying ? c.replay + ((size_t)dir * c.M + li) * N : nullptr;
+    if (c.w == 1)
+      PQ_HIP_CHECK(c.block ? block_decide1(d, c.st) : decide1(d, c.st));
+    else if (c.block)
       PQ_HIP_CHECK(block_decide(d, c.st));
     else
       PQ_HIP_CHECK(decide(d, c.st));
@@ -482,18 +507,16 @@ pqmc_status pqmc_soc_workspace_bytes(const pqmc_soc_problem *prob, const pqmc_up
   return PQMC_OK;
 }
 
-pqmc_status pqmc_soc_create(const pqmc_soc_problem *prob, const pqmc_update_opts *opts,
-                            void *hip_stream, void *workspace, size_t workspace_bytes,
-                            pqmc_soc_ctx **out) {
-  if (!out) return err(PQMC_EINVAL, "null out");
-  *out = nullptr;
-  pqmc_status v = validate(prob, opts);
-  if (v) return v;
-  if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255))
+// Set-up shared by both widths: workspace checks, H0 (n2 x n2 complex,
+// interleaved) and the trial state to the device, e^{-+dtau H0}, Philox
+// fields, the L-stack and the position-0 state.  Takes ownership of c.
+static pqmc_status create_common(pqmc_soc_ctx *c, const double *hopping, const double *trial,
+                                 void *hip_stream, void *workspace, size_t workspace_bytes,
+                                 pqmc_soc_ctx **out) {
+  if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255)) {
+    delete c;
     return err(PQMC_EINVAL, "workspace must be a 256-byte aligned device pointer");
-  pqmc_soc_ctx *c = new (std::nothrow) pqmc_soc_ctx;
-  if (!c) return err(PQMC_ENOMEM, "host allocation failed");
-  fill(*c, prob, opts);
+  }
   c->st = (hipStream_t)hip_stream;
   size_t need = 0;
   layout(*c, nullptr, &need);
@@ -513,14 +536,17 @@ pqmc_status pqmc_soc_create(const pqmc_soc_problem *prob, const pqmc_update_opts
   for (size_t i = 0; i < n2; ++i) {
     double row = 0.0;
     for (size_t j = 0; j < n2; ++j)
-      row += std::hypot(prob->hopping[2 * (i * n2 + j)], prob->hopping[2 * (i * n2 + j) + 1]);
+      row += std::hypot(hopping[2 * (i * n2 + j)], hopping[2 * (i * n2 + j) + 1]);
     norm = std::max(norm, row);
   }
-  hipError_t e = hipMemcpyAsync(c->Tay0, prob->hopping, sizeof(double2) * n2 * n2,
+  hipError_t e = hipMemcpyAsync(c->Tay0, hopping, sizeof(double2) * n2 * n2,
                                 hipMemcpyHostToDevice, c->st);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(c->P, prob->trial, sizeof(double2) * n2 * ne, hipMemcpyHostToDevice, c->st);
+    e = hipMemcpyAsync(c->P, trial, sizeof(double2) * n2 * ne, hipMemcpyHostToDevice, c->st);
   if (e == hipSuccess) e = hipMemsetAsync(c->stats, 0, sizeof(unsigned long long) * 16, c->st);
+  // the uploads read pageable host memory: finish them before the caller's
+  // (possibly temporary) arrays can go away
+  if (e == hipSuccess) e = hipStreamSynchronize(c->st);
   if (e != hipSuccess) return fail(fail_device(e, "upload", __FILE__, __LINE__));
   const double x = c->dtau * norm;
   const int sq = x > 0.5 ? (int)std::ceil(std::log2(x / 0.5)) : 0;
@@ -536,6 +562,19 @@ pqmc_status pqmc_soc_create(const pqmc_soc_problem *prob, const pqmc_update_opts
   if (rc) return fail(rc);
   *out = c;
   return PQMC_OK;
+}
+
+pqmc_status pqmc_soc_create(const pqmc_soc_problem *prob, const pqmc_update_opts *opts,
+                            void *hip_stream, void *workspace, size_t workspace_bytes,
+                            pqmc_soc_ctx **out) {
+  if (!out) return err(PQMC_EINVAL, "null out");
+  *out = nullptr;
+  pqmc_status v = validate(prob, opts);
+  if (v) return v;
+  pqmc_soc_ctx *c = new (std::nothrow) pqmc_soc_ctx;
+  if (!c) return err(PQMC_ENOMEM, "host allocation failed");
+  fill(*c, prob, opts);
+  return create_common(c, prob->hopping, prob->trial, hip_stream, workspace, workspace_bytes, out);
 }
 
 static pqmc_status soc_run(pqmc_soc_ctx *c, int n_sweeps, int n_slices, pqmc_stats *out) {
@@ -635,3 +674,158 @@ pqmc_status pqmc_soc_destroy(pqmc_soc_ctx *c) {
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------------
+// The paper's U < 0 model (Sec. II B, Eqs. (13)-(14)) behind the spin-
+// decoupled calls: one complex spin-up sector (w = 1) of N orbitals with
+// N_up = N_dn fermions and P_dn = P_up, alpha = i gamma,
+// gamma = arccos(e^{dtau U/2}); spin down is the complex conjugate.
+// ------------------------------------------------------------------------
+namespace pq {
+namespace soc {
+
+namespace {
+constexpr unsigned kOneFlags = PQMC_FLAG_LOG | PQMC_FLAG_TIMING;
+
+pqmc_status one_check_opts(const pqmc_update_opts *o) {
+  if (o->scheme != PQMC_LOCAL && o->scheme != PQMC_DELAYED && o->scheme != PQMC_BLOCK_FB)
+    return err(PQMC_EINVAL, "U < 0 runs the local, delayed and block force-bias schemes");
+  if (o->scheme == PQMC_DELAYED && (o->delay_k < 1 || o->delay_k > 2 * kSocMaxK))
+    return err(PQMC_EINVAL, "delay_k in [1, 64] for U < 0");
+  if (o->scheme == PQMC_BLOCK_FB && (o->block_b < 1 || o->block_b > 2 * kSocMaxK))
+    return err(PQMC_EINVAL, "block_b in [1, 64] for U < 0");
+  if (o->flags & ~kOneFlags) return err(PQMC_EINVAL, "flags for U < 0: only LOG and TIMING");
+  return PQMC_OK;
+}
+
+pqmc_status one_validate(const pqmc_problem *p, const pqmc_update_opts *o) {
+  if (!p || !o) return err(PQMC_EINVAL, "null problem or options");
+  if (p->n_sites < 1) return err(PQMC_EINVAL, "n_sites must be >= 1");
+  if (p->n_up < 1 || p->n_up > p->n_sites || p->n_up > 1024)
+    return err(PQMC_EINVAL, "need 1 <= n_up <= min(n_sites, 1024)");
+  if (!p->hopping || !p->trial_up || !p->trial_dn) return err(PQMC_EINVAL, "null input");
+  if (p->n_dn != p->n_up ||
+      std::memcmp(p->trial_up, p->trial_dn, sizeof(double) * p->n_sites * p->n_up) != 0)
+    return err(PQMC_EINVAL, "U < 0 simulates the spin-up sector only: it needs n_dn = n_up "
+                            "and trial_dn = trial_up");
+  if (!(p->dtau > 0) || !std::isfinite(p->dtau)) return err(PQMC_EINVAL, "dtau must be > 0");
+  if (!std::isfinite(p->U) || !(p->U < 0)) return err(PQMC_EINVAL, "U must be finite and < 0");
+  if (p->n_slices < 1 || p->stab_every < 1 || p->n_slices % p->stab_every)
+    return err(PQMC_EINVAL, "stab_every must divide n_slices");
+  const size_t NN = (size_t)p->n_sites * p->n_sites;
+  for (size_t e = 0; e < NN; ++e)
+    if (!std::isfinite(p->hopping[e])) return err(PQMC_EINVAL, "non-finite hopping matrix");
+  return one_check_opts(o);
+}
+
+void one_set_scheme(pqmc_soc_ctx &c, const pqmc_update_opts *o) {
+  c.opts = *o;
+  c.k = o->scheme == PQMC_DELAYED    ? std::min(o->delay_k, c.N)
+        : o->scheme == PQMC_BLOCK_FB ? std::min(o->block_b, c.N)
+                                     : 1;
+  c.block = o->scheme == PQMC_BLOCK_FB;
+}
+
+void one_fill(pqmc_soc_ctx &c, const pqmc_problem *p, const pqmc_update_opts *o) {
+  c.w = 1;
+  c.N = p->n_sites;
+  c.n2 = p->n_sites;
+  c.ne = p->n_up;
+  c.M = p->n_slices;
+  c.kt = p->stab_every;
+  c.nst = c.M / c.kt;
+  c.U = p->U;
+  c.dtau = p->dtau;
+  c.gamma = std::acos(std::exp(p->dtau * p->U / 2.0));
+  c.c1 = std::cos(c.gamma);
+  c.s1 = std::sin(c.gamma);
+  c.dd = std::cos(2.0 * c.gamma) - 1.0;   // delta(x) = e^{-2 i gamma x} - 1 = (dd, -x doff)
+  c.doff = std::sin(2.0 * c.gamma);
+  c.seed = p->seed;
+  c.walker = p->walker_id;
+  one_set_scheme(c, o);
+  c.ksplit = c.ne <= 128 ? 0 : std::max(64, ((c.ne + 7) / 8 + 15) / 16 * 16);
+}
+}  // namespace
+
+pqmc_status one_sector_workspace_bytes(const pqmc_problem *p, const pqmc_update_opts *o,
+                                       size_t *bytes) {
+  pqmc_status v = one_validate(p, o);
+  if (v) return v;
+  pqmc_soc_ctx c;
+  one_fill(c, p, o);
+  layout(c, nullptr, bytes);
+  return PQMC_OK;
+}
+
+pqmc_status one_sector_create(const pqmc_problem *p, const pqmc_update_opts *o,
+                              void *hip_stream, void *workspace, size_t workspace_bytes,
+                              pqmc_soc_ctx **out) {
+  *out = nullptr;
+  pqmc_status v = one_validate(p, o);
+  if (v) return v;
+  pqmc_soc_ctx *c = new (std::nothrow) pqmc_soc_ctx;
+  if (!c) return err(PQMC_ENOMEM, "host allocation failed");
+  one_fill(*c, p, o);
+  // the real H0 and P as complex128
+  const size_t N = c->N, ne = c->ne;
+  std::vector<double> h(2 * N * N, 0.0), t(2 * N * ne, 0.0);
+  for (size_t e = 0; e < N * N; ++e) h[2 * e] = p->hopping[e];
+  for (size_t e = 0; e < N * ne; ++e) t[2 * e] = p->trial_up[e];
+  return create_common(c, h.data(), t.data(), hip_stream, workspace, workspace_bytes, out);
+}
+
+pqmc_status one_sector_set_opts(pqmc_soc_ctx *c, const pqmc_update_opts *o) {
+  pqmc_status v = one_check_opts(o);
+  if (v) return v;
+  if ((o->flags & PQMC_FLAG_LOG) && !c->log_meta)
+    return err(PQMC_EINVAL, "logging was not sized in the workspace");
+  one_set_scheme(*c, o);
+  return PQMC_OK;
+}
+
+pqmc_status one_sector_set_fields(pqmc_soc_ctx *c, const int8_t *fields) {
+  const size_t n = (size_t)c->M * c->N;
+  for (size_t e = 0; e < n; ++e)
+    if (fields[e] != 1 && fields[e] != -1) return err(PQMC_EINVAL, "fields must be +-1");
+  hipError_t e = hipMemcpyAsync(c->fields, fields, n, hipMemcpyHostToDevice, c->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+  if (e == hipSuccess) e = hipMemsetAsync(c->stats, 0, 16 * sizeof(unsigned long long), c->st);
+  if (e != hipSuccess) return (pqmc_status)fail_device(e, "upload fields", __FILE__, __LINE__);
+  c->failed = false;
+  int rc = build_state(*c);
+  if (!rc) rc = sync_check(*c);
+  if (rc) c->failed = true;
+  return (pqmc_status)rc;
+}
+
+pqmc_status one_sector_replay(pqmc_soc_ctx *c, const int8_t *flips, pqmc_stats *out) {
+  if (c->failed) return err(PQMC_ESTATE, "context failed; call pqmc_set_fields");
+  if (c->windowed || c->position != 0) return err(PQMC_ESTATE, "walker is mid-sweep");
+  const size_t n = (size_t)2 * c->M * c->N;
+  hipError_t e = hipMemcpyAsync(c->replay, flips, n, hipMemcpyHostToDevice, c->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+  if (e != hipSuccess) return (pqmc_status)fail_device(e, "upload replay", __FILE__, __LINE__);
+  c->replaying = true;
+  const pqmc_status st = pqmc_soc_sweep(c, 1, out);
+  c->replaying = false;
+  return st;
+}
+
+// G of spin 0 (N x N complex128 interleaved); spin 1 is its complex conjugate
+pqmc_status one_sector_green(pqmc_soc_ctx *c, int spin, double *out) {
+  pqmc_status st = pqmc_soc_get_green(c, out);
+  if (st || spin == 0) return st;
+  const size_t n = (size_t)c->N * c->N;
+  for (size_t e = 0; e < n; ++e) out[2 * e + 1] = -out[2 * e + 1];
+  return PQMC_OK;
+}
+
+int one_sector_dims(const pqmc_soc_ctx *c, int *N, int *M) {
+  *N = c->N;
+  *M = c->M;
+  return c->w;
+}
+
+}  // namespace soc
+}  // namespace pq
