@@ -55,8 +55,19 @@ def test_workspace_bytes_valid_problem():
     assert st2 == 0 and n2 > n      # the decision log is sized in
 
 
+def test_workspace_bytes_negative_u():
+    """U < 0 is the one-sector complex model: valid with equal sectors, and
+    rejected with unequal ones (n_up != n_dn) or options it does not run."""
+    st, n = _ws(_problem(U=-4.0), binding.UpdateOpts(1, 16, 8, 0))
+    assert st == 0 and n > 0
+    assert _ws(_problem(U=-4.0, n_up=4), binding.UpdateOpts(1, 16, 8, 0))[0] == -1
+    assert _ws(_problem(U=-4.0), binding.UpdateOpts(1, 65, 8, 0))[0] == -1
+    assert _ws(_problem(U=-4.0), binding.UpdateOpts(3, 1, 1, 0))[0] == -1
+    assert _ws(_problem(U=-4.0), binding.UpdateOpts(1, 16, 8, binding.FLAG_FP32))[0] == -1
+
+
 @pytest.mark.parametrize("bad", [
-    dict(U=-4.0), dict(stab=7), dict(n_slices=0), dict(n_up=0),
+    dict(stab=7), dict(n_slices=0), dict(n_up=0),
     dict(hop=np.full((16, 16), np.nan)),
 ])
 def test_workspace_bytes_rejects(bad):
