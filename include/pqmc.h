@@ -13,10 +13,16 @@
  *   updates     local (Eqs. (20)-(21)), delayed (Sec. III A, Eqs. (27)-(30)),
  *               block force-bias (Sec. III B, Eqs. (31)-(36))
  *
- * All matrices are float64.  U > 0 uses the real coupling
- * alpha = arccosh(e^{dtau U/2}) with two spin sectors (f_up = +1, f_dn = -1);
- * U = 0 gives alpha = 0.  U < 0 (the paper's complex coupling) is rejected
- * with PQMC_EINVAL by this build.
+ * U > 0 uses the real coupling alpha = arccosh(e^{dtau U/2}) with two real
+ * float64 spin sectors (f_up = +1, f_dn = -1); U = 0 gives alpha = 0.
+ * U < 0 is the paper's own convention (Sec. II B, Eqs. (13)-(14)):
+ * alpha = i gamma, gamma = arccos(e^{dtau U/2}), so B_dn = conj(B_up) and
+ * only the spin-up sector is simulated, in complex128, with
+ * R = r_up r_dn = |r_up|^2.  It needs n_dn = n_up and trial_dn = trial_up,
+ * runs the local (as groups of one site), delayed (k <= 64) and block
+ * force-bias (b <= 64) schemes with the LOG and TIMING flags, and returns
+ * complex G from pqmc_get_green; batches of U < 0 walkers run one walker
+ * after the other.
  *
  * Memory: the library allocates no device memory.  The caller obtains the
  * size from pqmc_workspace_bytes() and passes one device buffer of at least
@@ -58,14 +64,29 @@ typedef enum {
 
 /* Update schemes.
  *   PQMC_LOCAL    sites i = 1..N of a slice one by one, Sherman-Morrison
- *                 rank-1 upgrade of T per accepted flip (Sec. II D).
+ *                 rank-1 upgrade of T per accepted flip (Sec. II D,
+ *                 Eqs. (20)-(21)).  A single walker runs it as one
+ *                 cooperative launch per slice with T held in registers
+ *                 across the GPU and one grid barrier per site (N_up, N_dn
+ *                 <= 1024); batches of walkers, or PQMC_FLAG_SITE_LAUNCHES,
+ *                 run one launch per site.
  *   PQMC_DELAYED  groups of delay_k consecutive sites; ratios from the
  *                 delayed recursion and one rank-n_A flush of T per group
  *                 (Sec. III A, first strategy: n_d = proposals).
  *   PQMC_BLOCK_FB blocks of block_b consecutive sites proposed together from
  *                 the force-bias heat-bath prior, one Metropolis test per
- *                 block and a rank-n_F Woodbury upgrade (Sec. III B).     */
-typedef enum { PQMC_LOCAL = 0, PQMC_DELAYED = 1, PQMC_BLOCK_FB = 2 } pqmc_scheme;
+ *                 block and a rank-n_F Woodbury upgrade (Sec. III B).
+ *   PQMC_LOCAL_G  the local update on the equal-time Green's function
+ *                 itself: r_s = 1 + Delta_s (1 - G_s,ii) and
+ *                 G <- G - (Delta / r) G[:, i] (e_i^T - G[i, :]), O(N^2) per
+ *                 site (the G-form that Sec. III A contrasts with the
+ *                 T-form); G is propagated as B G B^{-1} between slices and
+ *                 rebuilt from U_L, U_R at every stabilisation.  Same
+ *                 decisions as PQMC_LOCAL.  One cooperative launch per slice
+ *                 with G held in registers (N_s <= 2048); the context must be
+ *                 created with this scheme (G is sized in the workspace).  */
+typedef enum { PQMC_LOCAL = 0, PQMC_DELAYED = 1, PQMC_BLOCK_FB = 2,
+               PQMC_LOCAL_G = 3 } pqmc_scheme;
 
 /* flags of pqmc_update_opts */
 #define PQMC_FLAG_LOG    1u  /* record every decision of the last pqmc_sweep call */
@@ -79,11 +100,14 @@ typedef enum { PQMC_LOCAL = 0, PQMC_DELAYED = 1, PQMC_BLOCK_FB = 2 } pqmc_scheme
  * stabilisation, which discards the float32 drift.  Decisions can differ
  * from the float64 chain where a ratio lies within the float32 error of u. */
 #define PQMC_FLAG_FP32   8u
+/* PQMC_LOCAL with one launch per site (the form batches use) instead of the
+ * persistent kernel, for comparisons. */
+#define PQMC_FLAG_SITE_LAUNCHES 16u
 
 /* kernel classes of pqmc_get_kernel_times() */
 enum {
   PQMC_K_PROPAGATE = 0,  /* batched B-matrix propagation GEMM (one per slice visit)  */
-  PQMC_K_LOCAL = 1,      /* local-update site step                                  */
+  PQMC_K_LOCAL = 1,      /* local update: a site step, or a whole persistent slice   */
   PQMC_K_TILE = 2,       /* group flush + next group's panel products (MFMA)        */
   PQMC_K_REDUCE = 3,     /* panel partial sums and W0                                */
   PQMC_K_DECIDE = 4,     /* delayed / block force-bias decision kernel              */
@@ -96,7 +120,7 @@ typedef struct {
   const double *hopping;      /* H0, N_s x N_s row-major, real symmetric (Sec. II B)   */
   const double *trial_up;     /* P_up, N_s x N_up row-major, orthonormal columns       */
   const double *trial_dn;     /* P_dn, N_s x N_dn row-major, orthonormal columns       */
-  double U;                   /* on-site interaction, U >= 0 in this build             */
+  double U;                   /* on-site interaction (U < 0: see above)                */
   double dtau;                /* imaginary-time step                                   */
   int32_t n_slices;           /* M = 2 Theta / dtau                                     */
   int32_t stab_every;         /* k_tau: QR stabilisation period, must divide M         */
@@ -231,7 +255,9 @@ pqmc_status pqmc_multi_sweep(pqmc_ctx *const *ctxs, int32_t n, int32_t n_sweeps,
 pqmc_status pqmc_replay(pqmc_ctx *ctx, const int8_t *flips, pqmc_stats *out);
 
 /* G^s = 1 - U_R T U_L at the walker's current position (Eq. (15)),
- * written to host memory as N_s x N_s row-major float64.  spin: 0 up, 1 down. */
+ * written to host memory as N_s x N_s row-major float64.  spin: 0 up, 1 down.
+ * U < 0: complex128, (re, im) interleaved (2 N_s^2 doubles); spin 1 is the
+ * complex conjugate of spin 0. */
 pqmc_status pqmc_get_green(pqmc_ctx *ctx, int32_t spin, double *out);
 
 /* Decisions of the last pqmc_sweep / pqmc_forward_window call made with

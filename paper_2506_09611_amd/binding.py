@@ -39,6 +39,7 @@ FLAG_LOG = 1
 FLAG_TIMING = 2
 FLAG_KTIME = 4
 FLAG_FP32 = 8
+FLAG_SITE_LAUNCHES = 16
 
 
 class PQMCError(RuntimeError):
@@ -217,8 +218,10 @@ class Chain:
 
     # -- calls with the C ABI's names
     def set_opts(self, scheme, k=1, b=1, log=None, timing=None, ktime=None, fp32=None,
-                 tile_chunks=None):
+                 tile_chunks=None, site_launches=None):
         flags = self._flags
+        if site_launches is not None:
+            flags = (flags & ~FLAG_SITE_LAUNCHES) | (FLAG_SITE_LAUNCHES if site_launches else 0)
         if tile_chunks is not None:
             self.tile_chunks = int(tile_chunks)
         if fp32 is not None:

@@ -73,6 +73,14 @@ struct pqmc_ctx {
   double *gtmp = nullptr, *xtmp = nullptr;
   // stabilisation drift: sampled columns of U_R T U_L before / after
   double *drift_y[2] = {}, *drift_z[2][2] = {};
+  // persistent local kernels: partial buffers and the grid barrier
+  double *lp_y[2] = {}, *lp_x[2] = {}, *lp_s[2] = {};
+  unsigned *lp_sync = nullptr;
+  // G-form local update (sized when created with PQMC_LOCAL_G): G_s, a
+  // work copy for the propagation and the stabilisation, published rows
+  bool gsized = false;
+  bool g_valid = false;   // G holds the current G-form state
+  double *G[2] = {}, *Gw[2] = {}, *grow_buf[2] = {};
 
   double *UR[2] = {};
   double *ULt[2] = {};
@@ -167,6 +175,19 @@ void layout(pqmc_ctx &c, char *base, size_t *bytes) {
   c.gb.Ns[1] = c.Ns[1];
   c.xtmp = cv.take<double>(N * (size_t)std::max(c.Ns[0], c.Ns[1]));
   for (int s = 0; s < 2; ++s) {
+    int pr = 1, pc = 1;
+    local_persist_grid(c.Ns[s], &pr, &pc);
+    c.lp_y[s] = cv.take<double>((size_t)2 * pr * c.Ns[s]);
+    c.lp_x[s] = cv.take<double>((size_t)2 * pc * c.Ns[s]);
+    c.lp_s[s] = cv.take<double>((size_t)2 * pr * pc);
+    if (c.gsized) {
+      c.G[s] = cv.take<double>(NN);
+      c.Gw[s] = cv.take<double>(NN);
+      c.grow_buf[s] = cv.take<double>(2 * N);
+    }
+  }
+  c.lp_sync = cv.take<unsigned>(2);
+  for (int s = 0; s < 2; ++s) {
     c.drift_y[s] = cv.take<double>((size_t)kDriftCols * c.Ns[s]);
     c.drift_z[s][0] = cv.take<double>((size_t)kDriftCols * N);
     c.drift_z[s][1] = cv.take<double>((size_t)kDriftCols * N);
@@ -193,12 +214,15 @@ pqmc_status validate(const pqmc_problem *p, const pqmc_update_opts *o) {
   if (!std::isfinite(p->U)) return set_error(PQMC_EINVAL, "U must be finite");
   if (p->n_slices < 1 || p->stab_every < 1 || p->n_slices % p->stab_every)
     return set_error(PQMC_EINVAL, "stab_every must divide n_slices");
-  if (o->scheme < PQMC_LOCAL || o->scheme > PQMC_BLOCK_FB) return set_error(PQMC_EINVAL, "scheme");
+  if (o->scheme < PQMC_LOCAL || o->scheme > PQMC_LOCAL_G) return set_error(PQMC_EINVAL, "scheme");
+  if (o->scheme == PQMC_LOCAL_G && !local_persist_fits(p->n_up, p->n_dn, p->n_sites, true))
+    return set_error(PQMC_EINVAL, "the G-form local update holds N <= 2048 sites");
   if (o->delay_k < 1 || o->delay_k > 128) return set_error(PQMC_EINVAL, "delay_k in [1, 128]");
   if (o->block_b < 1 || o->block_b > 64) return set_error(PQMC_EINVAL, "block_b in [1, 64]");
   if (o->tile_chunks < 0) return set_error(PQMC_EINVAL, "tile_chunks must be >= 0");
   if ((o->flags & PQMC_FLAG_FP32) &&
-      (o->scheme == PQMC_LOCAL || (o->scheme == PQMC_DELAYED ? o->delay_k : o->block_b) > 64))
+      (o->scheme == PQMC_LOCAL || o->scheme == PQMC_LOCAL_G ||
+       (o->scheme == PQMC_DELAYED ? o->delay_k : o->block_b) > 64))
     return set_error(PQMC_EINVAL, "the float32 form needs the delayed or block scheme, k, b <= 64");
   const size_t NN = (size_t)p->n_sites * p->n_sites;
   for (size_t e = 0; e < NN; ++e)
@@ -223,6 +247,7 @@ void fill_problem(pqmc_ctx &c, const pqmc_problem *p, const pqmc_update_opts *o)
   c.bmax = std::min(o->block_b, c.N);
   c.gmax = std::max(c.kmax, c.bmax);
   c.log_alloc = (o->flags & PQMC_FLAG_LOG) != 0;
+  c.gsized = o->scheme == PQMC_LOCAL_G;
 }
 
 const double kSpin[2] = {1.0, -1.0};
@@ -265,6 +290,10 @@ int sync_check(pqmc_ctx &c) {
     c.failed = true;
     return set_error(PQMC_ENONFINITE, "non-finite determinant ratio");
   }
+  if (h[kStError] & kErrBarrier) {
+    c.failed = true;
+    return set_error(PQMC_EDEVICE, "persistent local update: a grid barrier timed out");
+  }
   return PQMC_OK;
 }
 
@@ -296,6 +325,55 @@ struct GemmQueue {
 };
 
 bool fp32_form(const pqmc_ctx &c) { return (c.opts.flags & PQMC_FLAG_FP32) != 0; }
+// the G-form local update: G (not T) is the updated state between stabilisations
+bool gform(const pqmc_ctx &c) { return c.opts.scheme == PQMC_LOCAL_G; }
+
+// G_s = 1 - U_R T U_L (Eq. (15)) into dst[s], both spins (xtmp as scratch)
+int assemble_G(pqmc_ctx &c, double *const *dst) {
+  const int N = c.N;
+  for (int s = 0; s < 2; ++s) {
+    const int n = c.Ns[s];
+    GemmBatch a{};
+    a.d[a.count++] = gemm_desc(c.UR[s], n, c.T[s], n, c.xtmp, n, N, n, n);
+    PQ_HIP_CHECK(gemm(a, false, false, c.st));
+    GemmBatch b{};
+    GemmDesc d = gemm_desc(c.xtmp, n, c.ULt[s], n, dst[s], N, N, N, n, -1.0);
+    d.addI = 1;
+    b.d[b.count++] = d;
+    PQ_HIP_CHECK(gemm(b, false, true, c.st));
+  }
+  return PQMC_OK;
+}
+
+// G-form propagation of G with the slice-l propagator B_l = diag(e^{alpha f x_l}) K:
+// forward G <- B_l G B_l^{-1}, backward G <- B_l^{-1} G B_l (the same moves as
+// U_R and U_L, Eq. (9)); the field scalings ride on the GEMM epilogue / depth.
+int wrap_G(pqmc_ctx &c, int l, bool forward) {
+  const int N = c.N;
+  const int8_t *row = c.fields + (size_t)(l - 1) * N;
+  GemmBatch g1{}, g2{};
+  for (int s = 0; s < 2; ++s) {
+    const double ep = std::exp(c.alpha * (s ? -1.0 : 1.0)), em = 1.0 / ep;
+    if (forward) {
+      GemmDesc d1 = gemm_desc(c.K, N, c.G[s], N, c.Gw[s], N, N, N, N);
+      d1.rs_field = row; d1.rs_pos = ep; d1.rs_neg = em;
+      GemmDesc d2 = gemm_desc(c.Gw[s], N, c.Kinv, N, c.G[s], N, N, N, N);
+      d2.cs_field = row; d2.cs_pos = em; d2.cs_neg = ep;
+      g1.d[g1.count++] = d1;
+      g2.d[g2.count++] = d2;
+    } else {
+      GemmDesc d1 = gemm_desc(c.Kinv, N, c.G[s], N, c.Gw[s], N, N, N, N);
+      d1.ks_field = row; d1.ks_pos = em; d1.ks_neg = ep;
+      GemmDesc d2 = gemm_desc(c.Gw[s], N, c.K, N, c.G[s], N, N, N, N);
+      d2.ks_field = row; d2.ks_pos = ep; d2.ks_neg = em;
+      g1.d[g1.count++] = d1;
+      g2.d[g2.count++] = d2;
+    }
+  }
+  PQ_HIP_CHECK(gemm(g1, false, false, c.st));
+  PQ_HIP_CHECK(gemm(g2, false, false, c.st));
+  return PQMC_OK;
+}
 
 // The float32 copy of T from the float64 one (precision form), all walkers
 // of the batch that use the form.
@@ -449,7 +527,10 @@ int prop_forward(const Walkers &b, int l) {
       c.ULt[s] = nul;
     }
   }
-  return q.flush();
+  int rc = q.flush();
+  for (int i = 0; i < b.n && !rc; ++i)
+    if (gform(b[i])) rc = wrap_G(b[i], l, true);
+  return rc;
 }
 
 // position l -> l-1: U_L <- U_L B_l, U_R <- B_l^{-1} U_R
@@ -479,7 +560,10 @@ int prop_backward(const Walkers &b, int l, bool with_R) {
       }
     }
   }
-  return q.flush();
+  int rc = q.flush();
+  for (int i = 0; i < b.n && !rc && with_R; ++i)
+    if (gform(b[i])) rc = wrap_G(b[i], l, false);
+  return rc;
 }
 
 // Initial stack of row-orthonormalised U_L and position-0 state (Sec. II B).
@@ -600,11 +684,39 @@ int update_slice(const Walkers &b, int l, int dir) {
   }
   const int N = L.N, nw = b.n;
   switch (L.opts.scheme) {
+    case PQMC_LOCAL_G:
     case PQMC_LOCAL: {
-      const int nt = ceil_div(std::max(L.Ns[0], L.Ns[1]), 64);
-      for (int i = 0; i <= N; ++i) {
-        KTimer kt(L, PQMC_K_LOCAL);
-        PQ_HIP_CHECK(local_step(m, lb, x, nw, i, nt, L.st));
+      const bool gf = L.opts.scheme == PQMC_LOCAL_G;
+      const bool persistent =
+          gf || (nw == 1 && !(L.opts.flags & PQMC_FLAG_SITE_LAUNCHES) &&
+                 local_persist_fits(L.Ns[0], L.Ns[1], N, false));
+      if (persistent) {
+        // one cooperative launch per walker and slice (walkers one after another)
+        for (int w = 0; w < nw; ++w) {
+          pqmc_ctx &c = b[w];
+          LocalPersistArgs a{};
+          a.m = m[w];
+          a.c = x[w];
+          a.g = GridSync{c.lp_sync, c.lp_sync + 1, 1u << 22};
+          for (int s = 0; s < 2; ++s) {
+            local_persist_grid(c.Ns[s], &a.pr[s], &a.pc[s]);
+            a.P[s] = a.pr[s] * a.pc[s];
+            a.ypart[s] = c.lp_y[s];
+            a.xpart[s] = c.lp_x[s];
+            a.spart[s] = c.lp_s[s];
+            a.Gm[s] = c.G[s];
+            a.grow_buf[s] = c.grow_buf[s];
+          }
+          a.grow = std::max(1, ceil_div(c.N, 256));
+          KTimer kt(L, PQMC_K_LOCAL);
+          PQ_HIP_CHECK(local_persist(a, gf, L.st));
+        }
+      } else {
+        const int nt = ceil_div(std::max(L.Ns[0], L.Ns[1]), 64);
+        for (int i = 0; i <= N; ++i) {
+          KTimer kt(L, PQMC_K_LOCAL);
+          PQ_HIP_CHECK(local_step(m, lb, x, nw, i, nt, L.st));
+        }
       }
       for (int i = 0; i < nw; ++i) b[i].log_count += N;
       break;
@@ -700,7 +812,7 @@ int drift_columns(const Walkers &b, int which) {
   }
   GemmQueue qy{L.st, false, true};
   for (int i = 0; i < b.n; ++i)
-    for (int s = 0; s < 2; ++s) {
+    for (int s = 0; s < 2 && !gform(b[i]); ++s) {
       pqmc_ctx &c = b[i];
       const int n = c.Ns[s], nc = std::min(kDriftCols, c.N), stride = c.N / nc;
       // Y^T (nc x n) = ULt[J, :] T^T
@@ -711,7 +823,7 @@ int drift_columns(const Walkers &b, int which) {
   if (rc) return rc;
   GemmQueue qz{L.st, false, true};
   for (int i = 0; i < b.n; ++i)
-    for (int s = 0; s < 2; ++s) {
+    for (int s = 0; s < 2 && !gform(b[i]); ++s) {
       pqmc_ctx &c = b[i];
       const int n = c.Ns[s], nc = std::min(kDriftCols, c.N);
       // Z^T (nc x N) = Y^T U_R^T
@@ -723,14 +835,31 @@ int drift_columns(const Walkers &b, int which) {
   const double *za[kMaxMats], *zb[kMaxMats];
   unsigned long long *out[kMaxMats];
   long cnt[kMaxMats];
+  int m = 0;
   for (int i = 0; i < b.n; ++i)
     for (int s = 0; s < 2; ++s) {
-      za[2 * i + s] = b[i].drift_z[s][0];
-      zb[2 * i + s] = b[i].drift_z[s][1];
-      out[2 * i + s] = b[i].stats + kStDrift;
-      cnt[2 * i + s] = (long)std::min(kDriftCols, b[i].N) * b[i].N;
+      pqmc_ctx &c = b[i];
+      if (gform(c)) {
+        // G-form: the running G against the one rebuilt from the fresh state,
+        // every entry; the fresh one is kept
+        if (s == 0) {
+          rc = assemble_G(c, c.Gw);
+          if (rc) return rc;
+        }
+        za[m] = c.G[s];
+        zb[m] = c.Gw[s];
+        cnt[m] = (long)c.N * c.N;
+      } else {
+        za[m] = c.drift_z[s][0];
+        zb[m] = c.drift_z[s][1];
+        cnt[m] = (long)std::min(kDriftCols, c.N) * c.N;
+      }
+      out[m] = c.stats + kStDrift;
+      ++m;
     }
-  PQ_HIP_CHECK(max_abs_diff(za, zb, cnt, out, 2 * b.n, L.st));
+  PQ_HIP_CHECK(max_abs_diff(za, zb, cnt, out, m, L.st));
+  for (int i = 0; i < b.n; ++i)
+    if (gform(b[i])) std::swap(b[i].G, b[i].Gw);
   return PQMC_OK;
 }
 
@@ -813,6 +942,13 @@ enum { kPhUpdate = 0, kPhProp = 1, kPhStab = 2, kPhEnd = -1 };
 
 int begin_call(pqmc_ctx &c) {
   PQ_HIP_CHECK(hipMemsetAsync(c.stats, 0, 16 * sizeof(unsigned long long), c.st));
+  if (gform(c)) {
+    int rc = assemble_G(c, c.G);
+    if (rc) return rc;
+    c.g_valid = true;
+  } else {
+    c.g_valid = false;
+  }
   c.log_count = 0;
   c.hb_count = 0;
   c.kused = 0;
@@ -1052,7 +1188,9 @@ pqmc_status pqmc_set_opts(pqmc_ctx *c, const pqmc_update_opts *o) {
     if (!st) c->opts = *o;
     return st;
   }
-  if (o->scheme < PQMC_LOCAL || o->scheme > PQMC_BLOCK_FB) return set_error(PQMC_EINVAL, "scheme");
+  if (o->scheme < PQMC_LOCAL || o->scheme > PQMC_LOCAL_G) return set_error(PQMC_EINVAL, "scheme");
+  if (o->scheme == PQMC_LOCAL_G && !c->gsized)
+    return set_error(PQMC_EINVAL, "the G-form local update needs a context created with it");
   if (o->delay_k < 1 || std::min(o->delay_k, c->N) > c->gmax)
     return set_error(PQMC_EINVAL, "delay_k exceeds the workspace bound");
   if (o->block_b < 1 || o->block_b > 64 || std::min(o->block_b, c->N) > c->gmax)
@@ -1061,10 +1199,12 @@ pqmc_status pqmc_set_opts(pqmc_ctx *c, const pqmc_update_opts *o) {
     return set_error(PQMC_EINVAL, "logging was not sized in the workspace");
   if (o->tile_chunks < 0) return set_error(PQMC_EINVAL, "tile_chunks must be >= 0");
   if ((o->flags & PQMC_FLAG_FP32) &&
-      (o->scheme == PQMC_LOCAL || (o->scheme == PQMC_DELAYED ? o->delay_k : o->block_b) > 64))
+      (o->scheme == PQMC_LOCAL || o->scheme == PQMC_LOCAL_G ||
+       (o->scheme == PQMC_DELAYED ? o->delay_k : o->block_b) > 64))
     return set_error(PQMC_EINVAL, "the float32 form needs the delayed or block scheme, k, b <= 64");
   const bool was = fp32_form(*c), now = (o->flags & PQMC_FLAG_FP32) != 0;
   c->opts = *o;
+  c->g_valid = false;
   c->gb.chunks = o->tile_chunks > 0 ? o->tile_chunks : 2;
   // the current T moves to the representation the next call reads
   hipError_t e = hipSuccess;
@@ -1094,6 +1234,7 @@ pqmc_status pqmc_set_fields(pqmc_ctx *c, const int8_t *fields) {
   e = hipMemsetAsync(c->stats, 0, 16 * sizeof(unsigned long long), c->st);
   if (e != hipSuccess) return as_status(fail_device(e, "memset", __FILE__, __LINE__));
   c->failed = false;
+  c->g_valid = false;
   pqmc_ctx *one[1] = {c};
   int rc = build_state(Walkers{one, 1});
   if (!rc) rc = sync_check(*c);
@@ -1278,6 +1419,20 @@ pqmc_status pqmc_get_green(pqmc_ctx *c, int32_t spin, double *out) {
   if (!c || !out || spin < 0 || spin > 1) return set_error(PQMC_EINVAL, "bad argument");
   if (c->cx) return pq::soc::one_sector_green(c->cx, spin, out);
   const int N = c->N, n = c->Ns[spin];
+  if (gform(*c)) {
+    // the G-form's state: G itself (at position 0 of a fresh context, or
+    // before any G-form call, it is assembled first)
+    hipError_t e = hipSuccess;
+    if (!c->g_valid) {
+      if (assemble_G(*c, c->G)) return PQMC_EDEVICE;
+      c->g_valid = true;
+    }
+    e = hipStreamSynchronize(c->st);
+    if (e == hipSuccess)
+      e = hipMemcpy(out, c->G[spin], sizeof(double) * N * N, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return as_status(fail_device(e, "green", __FILE__, __LINE__));
+    return PQMC_OK;
+  }
   if (fp32_form(*c) && c->t32_ahead) {
     // flushes since the last stabilisation live in the float32 copy only
     const float *src[1] = {c->T32[spin]};

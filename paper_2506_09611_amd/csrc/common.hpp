@@ -78,7 +78,7 @@ __device__ __forceinline__ double forced_uniform(bool take) {
 // stats slots
 enum { kStProposed = 0, kStAccepted = 1, kStFlips = 2, kStLowMargin = 3, kStNegative = 4,
        kStFieldUpdates = 5, kStError = 8, kStDrift = 9 };
-enum { kErrNonFinite = 1, kErrSingular = 2 };
+enum { kErrNonFinite = 1, kErrSingular = 2, kErrBarrier = 4 };
 
 // sum_{i < n} p[i * stride] in index order; loads issued eight at a time so
 // the partial-sum chains are not serialised on memory latency.

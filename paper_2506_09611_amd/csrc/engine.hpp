@@ -11,7 +11,7 @@ int fail_device(hipError_t e, const char *expr, const char *file, int line);
 int api_error(int st, const char *msg);
 
 // ------------------------------------------------------------------ GEMM
-// C = alpha * rs(i) * sum_k op(A)(i,k) ks(k) op(B)(k,j) + beta * Cin(i,j) + [addI && i == j]
+// C = alpha * rs(i) cs(j) * sum_k op(A)(i,k) ks(k) op(B)(k,j) + beta * Cin(i,j) + [addI && i == j]
 // Row-major storage; op(A) is M x K (A stored K x M when transA), op(B) K x N.
 // rs / ks: optional diagonal scalings read from a field row: x > 0 -> pos, else neg.
 // Split-K: when ksplit > 0, z-slice s of the grid handles k in [s*ksplit, (s+1)*ksplit)
@@ -26,6 +26,8 @@ struct GemmDesc {
   double rs_pos, rs_neg;
   const int8_t *ks_field;
   double ks_pos, ks_neg;
+  const int8_t *cs_field;         // optional scaling of the output columns (epilogue)
+  double cs_pos, cs_neg;
   double alpha, beta;
   int addI;
   int ksplit;
@@ -151,5 +153,36 @@ hipError_t group_tile(const SpinMats *m, const GroupBufs *g, int nw, int g0_prev
                       const int *kk_prev, int g0, const int *kk, bool fp32, hipStream_t st);
 hipError_t group_reduce(const SpinMats *m, const GroupBufs *g, const SweepCtx *c, int nw,
                         int mode, int g0, const int *kk, hipStream_t st);
+
+// ------------------------------------------------- persistent local updates
+// Grid-wide barrier of a cooperative launch: arrivals counted on *count
+// (zeroed before the launch), bounded wait; *abort set when a wait exceeds
+// spin_limit polls, and then every workgroup leaves the kernel.
+struct GridSync {
+  unsigned *count;
+  unsigned *abort;
+  unsigned spin_limit;
+};
+struct LocalPersistArgs {
+  SpinMats m;
+  SweepCtx c;
+  GridSync g;
+  // T-form: per spin pr x pc blocks (P = pr pc workgroups) and the partial
+  // buffers of one site, double-buffered by site parity:
+  //   ypart[s]: 2 x pr x Ns, xpart[s]: 2 x pc x Ns, spart[s]: 2 x P
+  int P[2], pr[2], pc[2];
+  double *ypart[2], *xpart[2], *spart[2];
+  // G-form: G_s (N x N), the published rows (2 x N per spin), rows per workgroup
+  double *Gm[2];
+  double *grow_buf[2];
+  int grow;
+};
+// T-form blocks of at most 64 x 128 (pr = ceil(n / 64), pc = ceil(n / 128))
+void local_persist_grid(int n, int *pr, int *pc);
+// whether the persistent kernel holds this problem (at most 256 workgroups)
+bool local_persist_fits(int n_up, int n_dn, int N, bool gform);
+// one slice of the local update (gform: on G) as one cooperative launch
+hipError_t local_persist(const LocalPersistArgs &a, bool gform, hipStream_t st);
+constexpr int kLocalGRows = 8;   // G-form rows per workgroup (upper bound)
 
 }  // namespace pq

@@ -124,6 +124,13 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmBatch batch, int nspl
       for (int j = 0; j < 4; ++j) rf[mi][j] = 1;
   }
 
+  // fields of the output columns (epilogue column scaling)
+  const int8_t *csf = g.cs_field;
+  int cf[NI];
+#pragma unroll
+  for (int ni = 0; ni < NI; ++ni)
+    cf[ni] = csf ? csf[min(n0 + wn * WN + ni * 16 + (lane & 15), N - 1)] : 1;
+
   dbl4 acc[MI][NI];
 #pragma unroll
   for (int i = 0; i < MI; ++i)
@@ -188,6 +195,7 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmBatch batch, int nspl
         if (row < M && col < N) {
           double v = alpha * acc[mi][ni][j];
           if (rsf) v *= (rf[mi][j] > 0) ? rs_pos : rs_neg;
+          if (csf) v *= (cf[ni] > 0) ? g.cs_pos : g.cs_neg;
           if (!split_out) {
             if (use_cin) v += beta * cin[mi][ni][j];
             if (g.addI && row == col) v += 1.0;
@@ -206,7 +214,7 @@ GemmDesc gemm_desc(const double *A, long lda, const double *B, long ldb, double 
   d.lda = lda; d.ldb = ldb; d.ldc = ldc; d.ldcin = Cin ? ldcin : ldc;
   d.M = M; d.N = N; d.K = K;
   d.alpha = alpha; d.beta = beta;
-  d.rs_pos = d.rs_neg = d.ks_pos = d.ks_neg = 1.0;
+  d.rs_pos = d.rs_neg = d.ks_pos = d.ks_neg = d.cs_pos = d.cs_neg = 1.0;
   return d;
 }
 
