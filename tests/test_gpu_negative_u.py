@@ -93,11 +93,13 @@ def test_negative_u_replay_cross_scheme():
 
 def test_negative_u_rejects_unequal_sectors():
     from paper_2506_09611_amd import Chain, PQMCError, Scheme
-    p = synth.make_problem(4, 5, 3, -4.0, n_slices=20, stab_every=5, seed=synth.SEED_BASE + 73)
+    p = synth.make_problem(4, 5, 3, -4.0, n_slices=20, stab_every=5, perturb=1e-3,
+                           seed=synth.SEED_BASE + 73)
     with pytest.raises(PQMCError):
         Chain(p.hopping, p.trial_up, p.trial_dn, p.U, p.dtau, p.n_slices, p.stab_every, p.seed,
               scheme=Scheme.DELAYED, k=4)
-    q = synth.make_problem(4, 5, 5, -4.0, n_slices=20, stab_every=5, seed=synth.SEED_BASE + 73)
+    q = synth.make_problem(4, 5, 5, -4.0, n_slices=20, stab_every=5, perturb=1e-3,
+                           seed=synth.SEED_BASE + 73)
     with pytest.raises(PQMCError):
         Chain(q.hopping, q.trial_up, q.trial_dn, q.U, q.dtau, q.n_slices, q.stab_every, q.seed,
               scheme=Scheme.DELAYED, k=4, fp32=True)
