@@ -147,34 +147,105 @@ def time_sweeps(chains, steps, warmup):
     return t1 - t0, agg
 
 
-def cpu_baseline(p, scheme, k, b, budget_s=20.0):
-    """The oracle on the host cores: a window of forward slice visits
-    (propagation + update of each slice) on the same 40x40 lattice, with the
-    projection shortened to M = 40 slices so its setup stays small."""
+def host_description():
+    """CPU model, logical cores and the BLAS the oracle's NumPy calls."""
     import numpy as np
-    import synth
-    from oracle.pqmc import Walker
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    blas = {}
+    try:
+        dep = np.show_config(mode="dicts").get("Build Dependencies", {}).get("blas", {})
+        blas = {"name": dep.get("name"), "version": dep.get("version")}
+    except Exception:  # pragma: no cover
+        pass
     try:
         from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+        info = [i for i in threadpool_info() if i.get("user_api") == "blas"]
+        if info:
+            blas.update({"internal_api": info[0].get("internal_api"),
+                         "threads": info[0].get("num_threads"),
+                         "architecture": info[0].get("architecture")})
     except Exception:  # pragma: no cover
-        threads = os.cpu_count()
-    q = synth.workload("c3", n_slices=40, stab_every=10)
+        pass
+    return {"cpu_model": model, "logical_cores": os.cpu_count(), "blas": blas}
+
+
+def _oracle_forward(q, scheme, k, b, visits):
+    """Seconds per forward slice visit (propagation + update, with the
+    stabilisations that fall inside) of the oracle walker, after its set-up."""
+    import numpy as np
+    from oracle.pqmc import Walker
     w = Walker(q, scheme, k=k, b=b)
     t0 = time.perf_counter()
-    n = 0
-    for l in range(1, q.n_slices + 1):
+    for l in range(1, visits + 1):
         w.prop_forward(l)
         w.update_slice(l, 0)
-        n += 1
-        if time.perf_counter() - t0 > budget_s:
-            break
-    dt = time.perf_counter() - t0
-    return {"value": n * q.n_sites / dt, "unit": "field-updates/s", "cores": int(threads),
-            "kind": "oracle",
-            "sample": f"{scheme} k={k} b={b}: {n} forward slice visits (propagation + update) of "
-                      f"the 40x40 lattice, N_sigma=800, projection shortened to M=40, "
-                      f"{dt:.1f} s of host time"}
+        if l % w.kt == 0:
+            for s in range(2):
+                w.UR[s] = np.linalg.qr(w.UR[s])[0]
+                w.UL[s] = w.Lstack[s][l // w.kt].copy()
+            w.refresh_T()
+    return (time.perf_counter() - t0) / visits
+
+
+def cpu_baseline(p, scheme, k, b, visits=20, one_core_visits=4):
+    """The oracle timed on the host cores (SURVEY-style CPU baseline):
+      * the 40x40 workload: `visits` forward slice visits of the headline
+        scheme (two stabilisations at k_tau = 10) on all cores, and
+        `one_core_visits` on one BLAS thread; a sweep is 2 M = 800 visits, so
+        the per-visit rate is the sweep rate and s/sweep is extrapolated x 40;
+      * 4x4 (c1) whole sweeps of the local, delayed (k = 16) and block (b = 8)
+        updates, and one whole 16x16 (c2) sweep of the delayed update (k = 16),
+        all cores.
+    The projection of the 40x40 sample is shortened to M = 20 (the cost of a
+    slice visit does not depend on M; the set-up of M = 400 would take
+    minutes)."""
+    import synth
+    from oracle.pqmc import Walker
+    host = host_description()
+    try:
+        from threadpoolctl import threadpool_limits
+    except Exception:  # pragma: no cover
+        threadpool_limits = None
+    threads = host["blas"].get("threads") or os.cpu_count()
+    q = synth.workload("c3", n_slices=20, stab_every=10)
+    sv = _oracle_forward(q, scheme, k, b, visits)
+    rate = q.n_sites / sv
+    one = None
+    if threadpool_limits is not None:
+        with threadpool_limits(limits=1, user_api="blas"):
+            sv1 = _oracle_forward(q, scheme, k, b, one_core_visits)
+        one = {"value": q.n_sites / sv1, "cores": 1, "s_per_slice_visit": sv1,
+               "extrapolated_s_per_sweep": sv1 * 800, "visits": one_core_visits}
+    whole = {}
+    for name, wl, sch, kk, bb in [("c1 local", "c1", "local", 1, 1),
+                                  ("c1 delayed k=16", "c1", "delayed", 16, 1),
+                                  ("c1 block b=8", "c1", "block", 1, 8),
+                                  ("c2 delayed k=16", "c2", "delayed", 16, 1)]:
+        qq = synth.workload(wl)
+        w = Walker(qq, sch, k=kk, b=bb)
+        t0 = time.perf_counter()
+        w.sweep()
+        dt = time.perf_counter() - t0
+        whole[name] = {"s_per_sweep": dt,
+                       "field_updates_per_s": 2 * qq.n_slices * qq.n_sites / dt,
+                       "acceptance": w.n_accepted / max(1, w.n_proposed)}
+    c1l = whole["c1 local"]["s_per_sweep"]
+    for name in ("c1 delayed k=16", "c1 block b=8"):
+        whole[name]["speedup_vs_local"] = c1l / whole[name]["s_per_sweep"]
+    return {"value": rate, "unit": "field-updates/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{scheme} k={k} b={b}: {visits} forward slice visits (propagation, "
+                      f"update, two stabilisations) of the 40x40 lattice, N_sigma=800, "
+                      f"projection shortened to M=20; per-visit rate = sweep rate "
+                      f"({sv * 800:.0f} s per 800-visit sweep, extrapolated x40)",
+            "s_per_slice_visit": sv, "extrapolated_s_per_sweep": sv * 800,
+            "one_core": one, "whole_sweeps_all_cores": whole, "host": host}
 
 
 def scheme_table(p, spec, window):

@@ -186,7 +186,7 @@ void layout(pqmc_ctx &c, char *base, size_t *bytes) {
       c.grow_buf[s] = cv.take<double>(2 * N);
     }
   }
-  c.lp_sync = cv.take<unsigned>(2);
+  c.lp_sync = cv.take<unsigned>(kLocalMaxGroups + 1);
   for (int s = 0; s < 2; ++s) {
     c.drift_y[s] = cv.take<double>((size_t)kDriftCols * c.Ns[s]);
     c.drift_z[s][0] = cv.take<double>((size_t)kDriftCols * N);
@@ -697,7 +697,7 @@ int update_slice(const Walkers &b, int l, int dir) {
           LocalPersistArgs a{};
           a.m = m[w];
           a.c = x[w];
-          a.g = GridSync{c.lp_sync, c.lp_sync + 1, 1u << 22};
+          a.g = GridSync{c.lp_sync, c.lp_sync + kLocalMaxGroups, 1u << 22};
           for (int s = 0; s < 2; ++s) {
             local_persist_grid(c.Ns[s], &a.pr[s], &a.pc[s]);
             a.P[s] = a.pr[s] * a.pc[s];

@@ -155,11 +155,13 @@ hipError_t group_reduce(const SpinMats *m, const GroupBufs *g, const SweepCtx *c
                         int mode, int g0, const int *kk, hipStream_t st);
 
 // ------------------------------------------------- persistent local updates
-// Grid-wide barrier of a cooperative launch: arrivals counted on *count
-// (zeroed before the launch), bounded wait; *abort set when a wait exceeds
-// spin_limit polls, and then every workgroup leaves the kernel.
+// Grid-wide barrier of a cooperative launch: one epoch flag per workgroup
+// (flags[kLocalMaxGroups], zeroed before the launch), bounded wait; *abort
+// set when a wait exceeds spin_limit polls, and then every workgroup leaves
+// the kernel.
+constexpr int kLocalMaxGroups = 256;
 struct GridSync {
-  unsigned *count;
+  unsigned *flags;
   unsigned *abort;
   unsigned spin_limit;
 };

@@ -20,12 +20,12 @@
 // after the barrier, every workgroup takes r_s = 1 + Delta_s (1 - G_s,ii)
 // and applies G <- G - (Delta / r) G[:, i] (e_i^T - G[i, :]) to its rows.
 //
-// Barrier: a monotone arrival counter (device-scope atomics, agent-scope
-// fences around it) and a bounded wait: a workgroup that has waited more
-// than the spin limit sets an abort flag, which every waiting workgroup
-// also watches, so that every wave leaves the kernel whatever happens; the
-// host reports the abort as a device error.  The launch is cooperative, so
-// all workgroups are resident at once.
+// Barrier: one epoch flag per workgroup, written once the workgroup's
+// shared stores have completed and watched by the others, and a bounded
+// wait: a workgroup that has waited more than the spin limit sets an abort
+// flag, which every waiting workgroup also watches, so that every wave leaves
+// the kernel whatever happens; the host reports the abort as a device
+// error.  The launch is cooperative, so all workgroups are resident at once.
 #include "engine.hpp"
 
 namespace pq {
@@ -42,34 +42,49 @@ __device__ __forceinline__ void record(const SweepCtx &c, long long idx, int sit
   }
 }
 
-// All threads call it.  Returns false when the barrier was abandoned.
-__device__ bool grid_barrier(const GridSync &g, unsigned target) {
-  __shared__ int ok;
+// Data that one workgroup writes and others read within the launch moves
+// through agent-scope relaxed atomic stores and loads: such an access is
+// coherent across the GPU's L2 caches by itself, so no cache-wide fence
+// (L2 write-back or invalidate) is needed around the barrier.
+__device__ __forceinline__ void put(double *p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double get(const double *p) {
+  return __hip_atomic_load(const_cast<double *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Grid barrier on a flag array: workgroup w stores the epoch to flags[w]
+// once every thread's shared stores have completed (s_waitcnt before the
+// workgroup barrier), then thread t watches flags[t], t < gridDim.x, so the
+// waits are spread over distinct words instead of one counter.  Bounded:
+// past spin_limit polls a waiter sets *abort, which every waiter also
+// watches.  All threads call it; returns false when abandoned.
+__device__ bool grid_barrier(const GridSync &g, unsigned epoch) {
+  __shared__ int s_abort;
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0) {
-    __threadfence();   // release this workgroup's writes (agent scope)
-    atomicAdd(g.count, 1u);
+    s_abort = 0;
+    __hip_atomic_store(g.flags + blockIdx.x, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __syncthreads();
+  for (unsigned w = threadIdx.x; w < gridDim.x; w += blockDim.x) {
     unsigned spins = 0;
-    int good = 1;
-    for (;;) {
-      const unsigned v = __hip_atomic_load(g.count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (v >= target) break;
-      if (__hip_atomic_load(g.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-        good = 0;
+    while (__hip_atomic_load(g.flags + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
+      if (__hip_atomic_load(g.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+        s_abort = 1;
         break;
       }
       if (++spins > g.spin_limit) {
         atomicMax(g.abort, 1u);
-        good = 0;
+        s_abort = 1;
         break;
       }
       __builtin_amdgcn_s_sleep(1);
     }
-    __threadfence();   // acquire the other workgroups' writes
-    ok = good;
   }
   __syncthreads();
-  return ok != 0;
+  return s_abort == 0;
 }
 
 constexpr int kLpThreads = 256;
@@ -92,7 +107,6 @@ __global__ __launch_bounds__(kLpThreads) void local_t_kernel(LocalPersistArgs a)
   double *T = a.m.T[s];
   const double *UR = a.m.UR[s];
   const double *ULt = a.m.ULt[s];
-  const int G = (int)gridDim.x;
 
   __shared__ double su[kLpBR], sv[kLpBC];
   __shared__ double yred[2][kLpBC];
@@ -141,23 +155,23 @@ __global__ __launch_bounds__(kLpThreads) void local_t_kernel(LocalPersistArgs a)
     __syncthreads();
     double *yout = a.ypart[s] + ((long)par * pr + ra) * n;
     double *xout = a.xpart[s] + ((long)par * pc + cb) * n;
-    if (t < nc) yout[col0 + t] = yred[0][t] + yred[1][t];
+    if (t < nc) put(yout + col0 + t, yred[0][t] + yred[1][t]);
     if (wave == 2) {
       // x partial of row r (= rp + 2 q) from the two waves of its parity
       const int r = lane;
       const double xp = (r < nr) ? xred[2 * (r & 1)][r >> 1] + xred[2 * (r & 1) + 1][r >> 1] : 0.0;
-      if (r < nr) xout[row0 + r] = xp;
+      if (r < nr) put(xout + row0 + r, xp);
       const double sp = wave_sum(xp * su[r]);
-      if (lane == 0) a.spart[s][par * a.P[s] + lid] = sp;
+      if (lane == 0) put(a.spart[s] + par * a.P[s] + lid, sp);
     }
-    alive = grid_barrier(a.g, (unsigned)(i + 1) * G);
+    alive = grid_barrier(a.g, (unsigned)(i + 1));
     if (!alive) break;
     // r_s = 1 + u^T T v for both spins, summed in the same order everywhere
     if (wave < 2) {
       const int ss = wave, P = a.P[ss];
       const double *sp = a.spart[ss] + par * P;
       double acc = 0.0;
-      for (int e = lane; e < P; e += 64) acc += sp[e];
+      for (int e = lane; e < P; e += 64) acc += get(sp + e);
       acc = wave_sum(acc);
       if (lane == 0) rr[ss] = 1.0 + acc;
     }
@@ -184,13 +198,13 @@ __global__ __launch_bounds__(kLpThreads) void local_t_kernel(LocalPersistArgs a)
       if (t < nc) {
         const double *yp2 = a.ypart[s] + (long)par * pr * n + col0 + t;
         double y = 0.0;
-        for (int e = 0; e < pr; ++e) y += yp2[(long)e * n];
+        for (int e = 0; e < pr; ++e) y += get(yp2 + (long)e * n);
         ys[t] = y;
       } else if (t >= kLpBC && t - kLpBC < nr) {
         const int r = t - kLpBC;
         const double *xp2 = a.xpart[s] + (long)par * pc * n + row0 + r;
         double x = 0.0;
-        for (int e = 0; e < pc; ++e) x += xp2[(long)e * n];
+        for (int e = 0; e < pc; ++e) x += get(xp2 + (long)e * n);
         xs[r] = x / rs;
       }
       __syncthreads();
@@ -233,7 +247,6 @@ __global__ __launch_bounds__(kLgThreads) void local_g_kernel(LocalPersistArgs a)
   const int N = C.N, BR = a.grow;
   const int row0 = w * BR;
   const int nr = max(0, min(BR, N - row0));
-  const int G = (int)gridDim.x;
   __shared__ double pub[2][2048];      // the published row i of both spins
   __shared__ double gcol[2][kLgRows];  // G[r][i] of this workgroup's rows
   __shared__ double gii[2];
@@ -260,7 +273,7 @@ __global__ __launch_bounds__(kLgThreads) void local_g_kernel(LocalPersistArgs a)
 #pragma unroll
           for (int j = 0; j < kLgCols; ++j) {
             const int c = t + kLgThreads * j;
-            if (c < N) a.grow_buf[s][(long)(i & 1) * N + c] = g[s][rr][j];
+            if (c < N) put(a.grow_buf[s] + (long)(i & 1) * N + c, g[s][rr][j]);
           }
   };
   publish(0);
@@ -271,12 +284,12 @@ __global__ __launch_bounds__(kLgThreads) void local_g_kernel(LocalPersistArgs a)
     // x_i before the barrier: workgroup 0 flips it only after every
     // workgroup has arrived there
     const int8_t xi = C.fields[(long)C.li * N + i];
-    alive = grid_barrier(a.g, (unsigned)(i + 1) * G);
+    alive = grid_barrier(a.g, (unsigned)(i + 1));
     if (!alive) break;
     const int par = i & 1;
     for (int e = t; e < 2 * N; e += kLgThreads) {
       const int s = e >= N ? 1 : 0, c = e - s * N;
-      pub[s][c] = a.grow_buf[s][(long)par * N + c];
+      pub[s][c] = get(a.grow_buf[s] + (long)par * N + c);
     }
     // this workgroup's G[r][i], from the thread holding column i
     {
@@ -358,11 +371,9 @@ __global__ __launch_bounds__(kLgThreads) void local_g_kernel(LocalPersistArgs a)
   }
 }
 
-__global__ void zero_sync_kernel(GridSync g) {
-  if (threadIdx.x == 0) {
-    *g.count = 0u;
-    *g.abort = 0u;
-  }
+__global__ void zero_sync_kernel(GridSync g, int n) {
+  for (int w = threadIdx.x; w < n; w += blockDim.x) g.flags[w] = 0u;
+  if (threadIdx.x == 0) *g.abort = 0u;
 }
 
 hipError_t cooperative_ok() {
@@ -396,7 +407,7 @@ void local_persist_grid(int n, int *pr, int *pc) {
 hipError_t local_persist(const LocalPersistArgs &a0, bool gform, hipStream_t st) {
   hipError_t e = cooperative_ok();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(zero_sync_kernel, dim3(1), dim3(64), 0, st, a0.g);
+  hipLaunchKernelGGL(zero_sync_kernel, dim3(1), dim3(256), 0, st, a0.g, kLocalMaxGroups);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   LocalPersistArgs a = a0;
