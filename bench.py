@@ -35,7 +35,8 @@ def make_chain(p, scheme, k=1, b=1, timing=True, fp32=False):
     """One walker run alone: one 64 x 64 tile of T per workgroup of the flush
     kernel (tile_chunks = 64), so that a single chain still fills the GPU."""
     from paper_2506_09611_amd import Chain, Scheme
-    sc = {"local": Scheme.LOCAL, "delayed": Scheme.DELAYED, "block": Scheme.BLOCK_FB}[scheme]
+    sc = {"local": Scheme.LOCAL, "delayed": Scheme.DELAYED, "block": Scheme.BLOCK_FB,
+          "local_g": Scheme.LOCAL_G}[scheme]
     return Chain(p.hopping, p.trial_up, p.trial_dn, p.U, p.dtau, p.n_slices, p.stab_every,
                  p.seed, p.walker_id, scheme=sc, k=k, b=b, timing=timing, fp32=fp32,
                  tile_chunks=64)
@@ -144,6 +145,7 @@ def time_sweeps(chains, steps, warmup):
     agg = {k: sum(s[0][k] for s in st) for k in st[0][0]}
     for k in ("proposed", "accepted", "flips", "low_margin", "negative", "field_updates"):
         agg[k] = sum(w[k] for s in st for w in s)
+    agg["max_stab_drift"] = max(w["max_stab_drift"] for s in st for w in s)
     return t1 - t0, agg
 
 
@@ -413,10 +415,15 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized device buffer three times (the reference "
                          "kernel for scaling traffic counters) and exit")
-    ap.add_argument("--compare", default="local,block",
+    ap.add_argument("--compare", default="local,local_g,block",
                     help="other schemes timed beside the headline one ('' for none)")
-    ap.add_argument("--local-window", type=int, default=20,
-                    help="slice visits timed for the local comparison (0 = full sweeps)")
+    ap.add_argument("--local-window", type=int, default=10,
+                    help="slice visits of the per-site-launch local form timed beside the "
+                         "persistent one (0: skip it)")
+    ap.add_argument("--u8", action="store_true", default=True,
+                    help="also sweep the headline batch at U/t = 8 (the second coupling of "
+                         "the 40x40 workload)")
+    ap.add_argument("--no-u8", dest="u8", action="store_false")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--autotune", default="8,16,32,64,128",
                     help="delay ranks the autotuner times on the headline batch, then the flush "
@@ -547,6 +554,7 @@ def main():
         "update_only_field_updates_per_s": upd,
         "acceptance": acc,
         "low_margin": agg["low_margin"],
+        "max_stab_drift": agg.get("max_stab_drift"),
         "phase_s_per_sweep": {"update": agg["t_update_s"] / max(1, args.steps),
                               "propagation": agg["t_prop_s"] / max(1, args.steps),
                               "stabilization": agg["t_stab_s"] / max(1, args.steps)},
@@ -589,24 +597,54 @@ def main():
         del cs
         torch.cuda.empty_cache()
 
+    # the same batch at U/t = 8 (c3u8): one whole sweep
+    if args.steps > 0 and args.u8 and args.workload == "c3":
+        p8 = synth.workload("c3u8")
+        cs = make_walkers(p8, args.scheme, args.k, args.b, W, streams)
+        d8, a8 = time_sweeps(cs, 1, 0)
+        result["u8"] = {"workload": "40x40, U/t=8 (otherwise as the headline)",
+                        "walkers": S * W, "s_per_sweep": d8,
+                        "field_updates_per_s": S * W * per_sweep / d8,
+                        "update_only": W * per_sweep / a8["t_update_s"]
+                        if a8["t_update_s"] > 0 else None,
+                        "acceptance": a8["accepted"] / max(1, a8["proposed"]),
+                        "negative": a8["negative"], "max_stab_drift": a8["max_stab_drift"]}
+        log("U/t=8", result["u8"])
+        for x in cs:
+            x.close()
+        del cs
+        torch.cuda.empty_cache()
+
     schemes = {args.scheme: {"s_per_sweep": dt / max(1, args.steps), "field_updates_per_s": value,
                              "update_only": upd, "walkers": S * W}}
     for name in [s for s in args.compare.split(",") if s and s != args.scheme]:
-        if name == "local" and args.local_window > 0:
-            # whole local sweeps take tens of seconds here: time a forward
-            # window of one batch (windows have no multi-stream entry point)
-            cs = make_walkers(p, name, args.k, args.b, W, streams[:1])
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            st = batch_forward_window(cs, args.local_window)[0]
-            torch.cuda.synchronize()
-            w = time.perf_counter() - t0
-            rate = W * args.local_window * N / w
-            schemes[name] = {"window_slice_visits": args.local_window, "s_window": w,
-                             "field_updates_per_s": rate,
-                             "update_only": W * args.local_window * N / st["t_update_s"]
-                             if st["t_update_s"] > 0 else None,
-                             "walkers": W, "note": "forward window of one batch, not a whole sweep"}
+        if name in ("local", "local_g"):
+            # the local baselines: one walker, whole sweeps, the persistent
+            # kernel (T-form, or the G-form on G itself) over the whole GPU
+            c1 = make_chain(p, name)
+            d2, a2 = time_sweeps([c1], 1, 0)
+            schemes[name] = {"s_per_sweep": d2, "field_updates_per_s": per_sweep / d2,
+                             "update_only": per_sweep / a2["t_update_s"]
+                             if a2["t_update_s"] > 0 else None,
+                             "acceptance": a2["accepted"] / max(1, a2["proposed"]),
+                             "max_stab_drift": a2["max_stab_drift"], "walkers": 1,
+                             "form": "persistent cooperative kernel, one grid barrier per site"}
+            cs = [c1]
+            if name == "local" and args.local_window > 0:
+                # the per-site-launch form (the one batches of walkers use)
+                sl = make_walkers(p, name, args.k, args.b, W, streams[:1])
+                for x in sl:
+                    x.set_opts(x.scheme, x.k, x.b, site_launches=True)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                st = batch_forward_window(sl, args.local_window)[0]
+                torch.cuda.synchronize()
+                w = time.perf_counter() - t0
+                schemes["local_site_launches"] = {
+                    "window_slice_visits": args.local_window, "s_window": w,
+                    "field_updates_per_s": W * args.local_window * N / w, "walkers": W,
+                    "note": "one launch per site, one batch, forward window"}
+                cs += sl
         else:
             cs = make_walkers(p, name, args.k, args.b, W, streams)
             d2, a2 = time_sweeps(cs, 1, 0)
@@ -614,16 +652,20 @@ def main():
                              "update_only": W * per_sweep / a2["t_update_s"]
                              if a2["t_update_s"] > 0 else None,
                              "acceptance": a2["accepted"] / max(1, a2["proposed"]),
-                             "walkers": S * W}
+                             "max_stab_drift": a2["max_stab_drift"], "walkers": S * W}
         log(name, schemes[name])
         for x in cs:
             x.close()
         del cs
         torch.cuda.empty_cache()
-    if "local" in schemes:
-        base = schemes["local"]["field_updates_per_s"]
-        for v in schemes.values():
-            v["speedup_vs_local"] = v["field_updates_per_s"] / base
+    for base_name in ("local", "local_g"):
+        if base_name in schemes:
+            base = schemes[base_name]["field_updates_per_s"]
+            for v in schemes.values():
+                v[f"speedup_vs_{base_name}"] = v["field_updates_per_s"] / base
+            if "single_chain" in result:
+                result["single_chain"][f"speedup_vs_{base_name}"] = (
+                    result["single_chain"]["field_updates_per_s"] / base)
     result["schemes"] = schemes
     if tuned is not None:
         result["autotune"] = tuned

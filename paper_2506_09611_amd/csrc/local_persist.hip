@@ -89,6 +89,8 @@ __device__ bool grid_barrier(const GridSync &g, unsigned epoch) {
 
 constexpr int kLpThreads = 256;
 constexpr int kLpBR = 64, kLpBC = 128, kLpQ = kLpBR / 2;
+// at most 256 workgroups: n <= 1024 gives pr <= 16 row blocks, pc <= 8 column blocks
+constexpr int kLpMaxPr = 16, kLpMaxPc = 8;
 
 // ------------------------------------------------------------------ T-form
 __global__ __launch_bounds__(kLpThreads) void local_t_kernel(LocalPersistArgs a) {
@@ -170,8 +172,8 @@ __global__ __launch_bounds__(kLpThreads) void local_t_kernel(LocalPersistArgs a)
     if (wave < 2) {
       const int ss = wave, P = a.P[ss];
       const double *sp = a.spart[ss] + par * P;
-      double acc = 0.0;
-      for (int e = lane; e < P; e += 64) acc += get(sp + e);
+      const double v0 = get(sp + min(lane, P - 1)), v1 = get(sp + min(lane + 64, P - 1));
+      double acc = (lane < P ? v0 : 0.0) + (lane + 64 < P ? v1 : 0.0);
       acc = wave_sum(acc);
       if (lane == 0) rr[ss] = 1.0 + acc;
     }
@@ -195,16 +197,26 @@ __global__ __launch_bounds__(kLpThreads) void local_t_kernel(LocalPersistArgs a)
     }
     if (acc) {
       const double rs = s ? r1 : r0;
+      // all partials in flight together (clamped in-range addresses), then
+      // summed in index order
       if (t < nc) {
         const double *yp2 = a.ypart[s] + (long)par * pr * n + col0 + t;
+        double v[kLpMaxPr];
+#pragma unroll
+        for (int e = 0; e < kLpMaxPr; ++e) v[e] = get(yp2 + (long)min(e, pr - 1) * n);
         double y = 0.0;
-        for (int e = 0; e < pr; ++e) y += get(yp2 + (long)e * n);
+#pragma unroll
+        for (int e = 0; e < kLpMaxPr; ++e) y += e < pr ? v[e] : 0.0;
         ys[t] = y;
       } else if (t >= kLpBC && t - kLpBC < nr) {
         const int r = t - kLpBC;
         const double *xp2 = a.xpart[s] + (long)par * pc * n + row0 + r;
+        double v[kLpMaxPc];
+#pragma unroll
+        for (int e = 0; e < kLpMaxPc; ++e) v[e] = get(xp2 + (long)min(e, pc - 1) * n);
         double x = 0.0;
-        for (int e = 0; e < pc; ++e) x += get(xp2 + (long)e * n);
+#pragma unroll
+        for (int e = 0; e < kLpMaxPc; ++e) x += e < pc ? v[e] : 0.0;
         xs[r] = x / rs;
       }
       __syncthreads();
@@ -287,9 +299,19 @@ __global__ __launch_bounds__(kLgThreads) void local_g_kernel(LocalPersistArgs a)
     alive = grid_barrier(a.g, (unsigned)(i + 1));
     if (!alive) break;
     const int par = i & 1;
-    for (int e = t; e < 2 * N; e += kLgThreads) {
-      const int s = e >= N ? 1 : 0, c = e - s * N;
-      pub[s][c] = get(a.grow_buf[s] + (long)par * N + c);
+    {
+      // the published rows, all loads in flight together
+      double v[2][kLgCols];
+#pragma unroll
+      for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int j = 0; j < kLgCols; ++j)
+          v[s][j] = get(a.grow_buf[s] + (long)par * N + min(t + kLgThreads * j, N - 1));
+#pragma unroll
+      for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int j = 0; j < kLgCols; ++j)
+          if (t + kLgThreads * j < N) pub[s][t + kLgThreads * j] = v[s][j];
     }
     // this workgroup's G[r][i], from the thread holding column i
     {
