@@ -260,6 +260,20 @@ pqmc_status pqmc_replay(pqmc_ctx *ctx, const int8_t *flips, pqmc_stats *out);
  * complex conjugate of spin 0. */
 pqmc_status pqmc_get_green(pqmc_ctx *ctx, int32_t spin, double *out);
 
+/* pqmc_get_green for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same G, bit for bit, with its two device temporaries (U_R T, N x N_s,
+ * and G, N x N) taken from a static device array of the library instead of
+ * the context's workspace.  The array holds 4194304 doubles (32 MiB) on every
+ * GPU the library runs on, until the process ends; problems with
+ * N_s (N_s + N_sigma) (rounded up to 32) above that are refused with
+ * PQMC_EINVAL.  Calls no hipMalloc, hipFree or allocating library routine
+ * (its device address is looked up once per device, on the first call).
+ * Every call on one GPU shares that GPU's array: calls that overlap on one
+ * GPU (several host threads or streams at once) race and must be
+ * serialised by the caller.  U < 0 contexts are refused (PQMC_EINVAL). */
+pqmc_status pqmc_get_green_static(pqmc_ctx *ctx, int32_t spin, double *out);
+
 /* Decisions of the last pqmc_sweep / pqmc_forward_window call made with
  * PQMC_FLAG_LOG, in order: meta[3*n] = (dir*M + l-1, site, accepted) and
  * margin[n] = |A| - u.  For block FB, site is the block's first site and the

@@ -20,7 +20,7 @@ EXPORTED_SYMBOLS = (
     "pqmc_get_fields", "pqmc_sweep", "pqmc_forward_window", "pqmc_batch_sweep",
     "pqmc_batch_forward_window", "pqmc_multi_sweep", "pqmc_get_green",
     "pqmc_get_decisions", "pqmc_get_heat_bath", "pqmc_get_kernel_times", "pqmc_destroy",
-    "pqmc_replay",
+    "pqmc_replay", "pqmc_get_green_static",
     "pqmc_last_error",
     "pqmc_soc_workspace_bytes", "pqmc_soc_create", "pqmc_soc_sweep", "pqmc_soc_forward_window",
     "pqmc_soc_get_green", "pqmc_soc_get_fields", "pqmc_soc_get_decisions", "pqmc_soc_destroy",
@@ -126,6 +126,7 @@ def load_library():
                                   ctypes.POINTER(ctypes.c_uint64)],
         "pqmc_destroy": [c_void_p],
         "pqmc_replay": [c_void_p, ctypes.POINTER(ctypes.c_int8), ctypes.POINTER(Stats)],
+        "pqmc_get_green_static": [c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)],
         "pqmc_soc_workspace_bytes": [ctypes.POINTER(SocProblem), ctypes.POINTER(UpdateOpts),
                                      ctypes.POINTER(c_size_t)],
         "pqmc_soc_create": [ctypes.POINTER(SocProblem), ctypes.POINTER(UpdateOpts), c_void_p,

@@ -4,6 +4,7 @@
 
 #include <chrono>
 #include <cmath>
+#include <mutex>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -1080,6 +1081,35 @@ pqmc_status check_batch(pqmc_ctx *const *w, int n) {
 
 pqmc_status as_status(int rc) { return (pqmc_status)rc; }
 
+// Device scratch of pqmc_get_green_static: X = U_R T and G, 32 MiB per GPU,
+// held by every GPU the library runs on until the process ends.  Host code
+// never uses the array's name as an address: its device address is looked
+// up once per device (hipGetSymbolAddress, that device current) and kept.
+constexpr size_t kStaticScratchDoubles = size_t(1) << 22;
+constexpr int kMaxDevices = 64;
+double *g_scratch_ptr[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+
+}  // namespace
+
+static __device__ __align__(256) double scratch[kStaticScratchDoubles];
+
+namespace {
+// The device address of `scratch` on the current device.
+int static_scratch(double **out) {
+  int dev = 0;
+  PQ_HIP_CHECK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return set_error(PQMC_EDEVICE, "device ordinal above 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    PQ_HIP_CHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return set_error(PQMC_EDEVICE, "hipGetSymbolAddress returned a null address");
+    g_scratch_ptr[dev] = static_cast<double *>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return PQMC_OK;
+}
 }  // namespace
 
 extern "C" {
@@ -1415,9 +1445,9 @@ pqmc_status pqmc_forward_window(pqmc_ctx *c, int32_t n_slices, pqmc_stats *out) 
   return pqmc_batch_forward_window(one, 1, n_slices, out);
 }
 
-pqmc_status pqmc_get_green(pqmc_ctx *c, int32_t spin, double *out) {
-  if (!c || !out || spin < 0 || spin > 1) return set_error(PQMC_EINVAL, "bad argument");
-  if (c->cx) return pq::soc::one_sector_green(c->cx, spin, out);
+// G^s = 1 - U_R T U_L into the host array out, with X = U_R T (N x N_s) and
+// G (N x N) formed in the device scratch X, Gd.
+static pqmc_status green_into(pqmc_ctx *c, int spin, double *X, double *Gd, double *out) {
   const int N = c->N, n = c->Ns[spin];
   if (gform(*c)) {
     // the G-form's state: G itself (at position 0 of a fresh context, or
@@ -1442,18 +1472,37 @@ pqmc_status pqmc_get_green(pqmc_ctx *c, int32_t spin, double *out) {
     if (e != hipSuccess) return as_status(fail_device(e, "green", __FILE__, __LINE__));
   }
   GemmBatch a{};
-  a.d[a.count++] = gemm_desc(c->UR[spin], n, c->T[spin], n, c->xtmp, n, N, n, n);
+  a.d[a.count++] = gemm_desc(c->UR[spin], n, c->T[spin], n, X, n, N, n, n);
   hipError_t e = gemm(a, false, false, c->st);
   GemmBatch b{};
-  GemmDesc d = gemm_desc(c->xtmp, n, c->ULt[spin], n, c->gtmp, N, N, N, n, -1.0);
+  GemmDesc d = gemm_desc(X, n, c->ULt[spin], n, Gd, N, N, N, n, -1.0);
   d.addI = 1;
   b.d[b.count++] = d;
   if (e == hipSuccess) e = gemm(b, false, true, c->st);
   if (e == hipSuccess) e = hipStreamSynchronize(c->st);
-  if (e == hipSuccess)
-    e = hipMemcpy(out, c->gtmp, sizeof(double) * N * N, hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(out, Gd, sizeof(double) * N * N, hipMemcpyDeviceToHost);
   if (e != hipSuccess) return as_status(fail_device(e, "green", __FILE__, __LINE__));
   return PQMC_OK;
+}
+
+pqmc_status pqmc_get_green(pqmc_ctx *c, int32_t spin, double *out) {
+  if (!c || !out || spin < 0 || spin > 1) return set_error(PQMC_EINVAL, "bad argument");
+  if (c->cx) return pq::soc::one_sector_green(c->cx, spin, out);
+  return green_into(c, spin, c->xtmp, c->gtmp, out);
+}
+
+pqmc_status pqmc_get_green_static(pqmc_ctx *c, int32_t spin, double *out) {
+  if (!c || !out || spin < 0 || spin > 1) return set_error(PQMC_EINVAL, "bad argument");
+  if (c->cx) return set_error(PQMC_EINVAL, "pqmc_get_green_static: U < 0 is not supported");
+  const size_t N = c->N, n = c->Ns[spin];
+  const size_t xs = (N * n + 31) / 32 * 32;   // G starts 256-byte aligned
+  if (xs + N * N > kStaticScratchDoubles)
+    return set_error(PQMC_EINVAL, "pqmc_get_green_static: N (N + N_sigma) exceeds the static "
+                                  "scratch of 4194304 doubles (32 MiB)");
+  double *ptr = nullptr;
+  const int rc = static_scratch(&ptr);
+  if (rc) return as_status(rc);
+  return green_into(c, spin, ptr, ptr + xs, out);
 }
 
 static pqmc_status copy_log(pqmc_ctx *c, const int32_t *dmeta, const double *dmargin,
