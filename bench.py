@@ -335,6 +335,81 @@ def soc_leg(args):
             "rows": rows}
 
 
+def mixed_energy(H0, Gu, Gd, U):
+    """Mixed-estimate energy of the Hubbard Hamiltonian from the two spin
+    sectors' G (G_ij = <c_i c+_j>, so <c+_i c_j> = delta_ij - G_ji)."""
+    import numpy as np
+    nu, nd = 1.0 - np.diag(Gu), 1.0 - np.diag(Gd)
+    kin = sum(np.trace(H0) - np.sum(H0 * G.T) for G in (Gu, Gd))
+    return float(kin + U * np.sum(nu * nd - 0.5 * (nu + nd))), float(np.mean(nu * nd))
+
+
+def c4_leg(args):
+    """Batched walkers with the precision form: 64 walkers of 24x24 (N=576,
+    N_sigma=288, U/t=6) and 64 of 12x12 (N=144, N_sigma=72, U/t=6), four of
+    each in every batch of 8 (lattices of two sizes in one launch), 16 batches
+    on 16 HIP streams, delayed k=32 with the float32 flush (float64 ratios,
+    QR and G every 10 slices), one whole sweep (M=400); then the same walkers
+    in float64.  Reports jobs/s (a job = 64 walkers x 1 sweep of one lattice)
+    and the mean energy and double occupancy of each job's walkers at the
+    sweep's end with their standard errors (independent chains)."""
+    import dataclasses
+    import numpy as np
+    import torch
+    import synth
+    from paper_2506_09611_amd import Chain, Scheme, multi_sweep
+    p24 = synth.make_problem(24, 288, 288, 6.0, perturb=1e-3, seed=synth.SEED_BASE + 4)
+    p12 = synth.make_problem(12, 72, 72, 6.0, perturb=1e-3, seed=synth.SEED_BASE + 5)
+    out = {"workload": "64 walkers of 24x24 (N=576, N_sigma=288) + 64 of 12x12 (N=144, "
+                       "N_sigma=72), U/t=6, dtau=0.05, M=400, k_tau=10, seeded 1e-3 bond "
+                       "perturbation; 16 batches of 4+4 mixed walkers on 16 streams; delayed k=32"}
+    for fp32 in (True, False):
+        streams = [torch.cuda.Stream() for _ in range(16)]
+        chains, jobs = [], []
+        for si, st in enumerate(streams):
+            for j, q in enumerate((p24, p12)):
+                for w in range(4):
+                    qq = dataclasses.replace(q, walker_id=si * 4 + w)
+                    chains.append(Chain(qq.hopping, qq.trial_up, qq.trial_dn, qq.U, qq.dtau,
+                                        qq.n_slices, qq.stab_every, qq.seed, qq.walker_id,
+                                        scheme=Scheme.DELAYED, k=32, fp32=fp32, stream=st))
+                    jobs.append(j)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        stats = multi_sweep(chains, 1)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        fu = 64 * 2 * 400 * (576 + 144)
+        rec = {"s_per_sweep": dt, "jobs_per_s": 2.0 / dt, "field_updates_per_s": fu / dt,
+               "acceptance": sum(x["accepted"] for x in stats) / sum(x["proposed"] for x in stats),
+               "max_stab_drift": max(x["max_stab_drift"] for x in stats)}
+        for j, (q, name) in enumerate(((p24, "24x24"), (p12, "12x12"))):
+            ed = [mixed_energy(q.hopping, c.green(0), c.green(1), q.U)
+                  for c, jj in zip(chains, jobs) if jj == j]
+            e = np.array([x[0] for x in ed]) / q.n_sites
+            d = np.array([x[1] for x in ed])
+            rec[name] = {"energy_per_site": float(e.mean()),
+                         "energy_per_site_stderr": float(e.std(ddof=1) / np.sqrt(len(e))),
+                         "double_occupancy": float(d.mean()),
+                         "double_occupancy_stderr": float(d.std(ddof=1) / np.sqrt(len(d)))}
+        out["fp32" if fp32 else "fp64"] = rec
+        log("c4", "fp32" if fp32 else "fp64", rec)
+        for c in chains:
+            c.close()
+        del chains
+        torch.cuda.empty_cache()
+    out["fp32_speedup"] = out["fp64"]["s_per_sweep"] / out["fp32"]["s_per_sweep"]
+    for name in ("24x24", "12x12"):
+        a, b = out["fp32"][name], out["fp64"][name]
+        out[f"{name}_energy_difference_in_stderr"] = abs(
+            a["energy_per_site"] - b["energy_per_site"]) / np.hypot(
+            a["energy_per_site_stderr"], b["energy_per_site_stderr"])
+    out["note"] = ("the float32 and float64 chains are independent (their decisions part "
+                   "where a ratio lies within the float32 error of u); the per-proposal "
+                   "error statement on identical decisions is tests/test_gpu_precision.py")
+    return out
+
+
 def serve_leg(args, rate):
     """Jobs of mixed lattice sizes and couplings arriving as a Poisson stream
     of `rate` jobs/s, served by the continuous-batching server under an HBM
@@ -424,6 +499,8 @@ def main():
                     help="also sweep the headline batch at U/t = 8 (the second coupling of "
                          "the 40x40 workload)")
     ap.add_argument("--no-u8", dest="u8", action="store_false")
+    ap.add_argument("--no-c4", action="store_true",
+                    help="skip the batched precision-form leg (24x24 + 12x12 walkers)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--autotune", default="8,16,32,64,128",
                     help="delay ranks the autotuner times on the headline batch, then the flush "
@@ -669,6 +746,8 @@ def main():
     result["schemes"] = schemes
     if tuned is not None:
         result["autotune"] = tuned
+    if args.steps > 0 and not args.no_c4:
+        result["batched_precision"] = c4_leg(args)
     if args.table:
         result["table"] = scheme_table(p, args.table, args.table_window)
     if args.soc_sizes:

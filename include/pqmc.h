@@ -220,8 +220,8 @@ pqmc_status pqmc_batch_sweep(pqmc_ctx *const *ctxs, int32_t n, int32_t n_sweeps,
 pqmc_status pqmc_batch_forward_window(pqmc_ctx *const *ctxs, int32_t n, int32_t n_slices,
                                       pqmc_stats *out);
 
-/* Walkers on several streams: the n contexts (1 <= n <= 64) are split by
- * their stream, in order of first appearance (at most 8 streams); the
+/* Walkers on several streams: the n contexts (1 <= n <= 128) are split by
+ * their stream, in order of first appearance (at most 16 streams); the
  * walkers of one stream form one pqmc_batch_sweep batch (same rules, at most
  * 8 walkers), and the batches run concurrently, each driven by its own host
  * thread, so that the serial phases of one batch (decisions, panel sums)
@@ -248,9 +248,9 @@ pqmc_status pqmc_multi_sweep(pqmc_ctx *const *ctxs, int32_t n, int32_t n_sweeps,
  * The same list through the three schemes yields the same fields and, in
  * exact arithmetic, the same G: the cross-scheme invariant of the updates
  * (Secs. II D, III A, III B all apply Eq. (19) to the accepted flips).
- * Forced outcomes are implemented as uniforms u = -1 (take) and u = +inf
- * (do not take) in place of the Philox draws, so the log's margins are
- * |A| + 1 and -inf.  The walker must be at position 0 (PQMC_ESTATE
+ * Forced outcomes are implemented as uniforms u = -0 (take) and u = +inf
+ * (do not take) in place of the Philox draws, so the log's margin field
+ * holds |A| itself for a taken outcome and -inf otherwise.  The walker must be at position 0 (PQMC_ESTATE
  * otherwise); the sweep counter advances as after pqmc_sweep. */
 pqmc_status pqmc_replay(pqmc_ctx *ctx, const int8_t *flips, pqmc_stats *out);
 

@@ -198,8 +198,9 @@ class Walker:
         flips[d*M + l-1, i] != 0: site i flips on that visit of slice l.
         Local / delayed: the site's Metropolis test is accepted iff listed.
         Block: the heat-bath proposal is the listed flip set and the block's
-        Metropolis test is accepted.  A forced outcome is the uniform -1
-        (taken for any finite |A|) or +inf (not taken) in place of the draw."""
+        Metropolis test is accepted.  A forced outcome is the uniform -0
+        (taken for any nonzero finite |A|, and the logged margin is |A|) or
+        +inf (not taken) in place of the draw."""
         self.replay = np.asarray(flips, dtype=np.int8).reshape(2 * self.M, self.N)
         try:
             self.sweep()
@@ -210,14 +211,14 @@ class Walker:
     def mh_uniform(self, d, li, site):
         if self.replay is not None:
             take = self.scheme == "block" or self.replay[d * self.M + li, site] != 0
-            return -1.0 if take else math.inf
+            return -0.0 if take else math.inf
         return philox.uniform(self.key, self.sweep_index, d * self.M + li, site, philox.PURPOSE_MH)
 
     def hb_uniform(self, d, li, site):
         if self.replay is not None:
             x = int(self.fields[li, site])
             target = -x if self.replay[d * self.M + li, site] != 0 else x
-            return -1.0 if target > 0 else math.inf
+            return -0.0 if target > 0 else math.inf
         return philox.uniform(self.key, self.sweep_index, d * self.M + li, site, philox.PURPOSE_HB)
 
     def flip_delta(self, li, i, s):

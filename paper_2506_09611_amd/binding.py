@@ -457,11 +457,11 @@ def batch_sweep(chains, n=1):
 
 
 def multi_sweep(chains, n=1):
-    """pqmc_multi_sweep: up to 64 chains on up to 8 streams; the chains of
+    """pqmc_multi_sweep: up to 128 chains on up to 16 streams; the chains of
     one stream sweep as one batch and the batches run concurrently."""
-    if not 1 <= len(chains) <= 8 * MAX_BATCH:
-        raise ValueError(f"a multi-stream sweep holds 1..{8 * MAX_BATCH} chains")
-    return _batch_call(chains, lambda lib: lib.pqmc_multi_sweep, n, limit=8 * MAX_BATCH)
+    if not 1 <= len(chains) <= 16 * MAX_BATCH:
+        raise ValueError(f"a multi-stream sweep holds 1..{16 * MAX_BATCH} chains")
+    return _batch_call(chains, lambda lib: lib.pqmc_multi_sweep, n, limit=16 * MAX_BATCH)
 
 
 def batch_forward_window(chains, n_slices):

@@ -1316,9 +1316,9 @@ pqmc_status pqmc_batch_sweep(pqmc_ctx *const *ctxs, int32_t n, int32_t n_sweeps,
 
 pqmc_status pqmc_multi_sweep(pqmc_ctx *const *ctxs, int32_t n, int32_t n_sweeps,
                              pqmc_stats *out) {
-  constexpr int kMaxStreams = 8;
+  constexpr int kMaxStreams = 16;
   if (!ctxs || n < 1 || n > kMaxStreams * kMaxBatch)
-    return set_error(PQMC_EINVAL, "multi-stream sweep takes 1..64 contexts");
+    return set_error(PQMC_EINVAL, "multi-stream sweep takes 1..128 contexts");
   if (n_sweeps < 0) return set_error(PQMC_EINVAL, "n_sweeps < 0");
   // one batch per stream, streams in order of first appearance
   std::vector<hipStream_t> streams;
@@ -1329,7 +1329,7 @@ pqmc_status pqmc_multi_sweep(pqmc_ctx *const *ctxs, int32_t n, int32_t n_sweeps,
     size_t g = 0;
     while (g < streams.size() && streams[g] != ctxs[i]->st) ++g;
     if (g == streams.size()) {
-      if ((int)g == kMaxStreams) return set_error(PQMC_EINVAL, "more than 8 streams");
+      if ((int)g == kMaxStreams) return set_error(PQMC_EINVAL, "more than 16 streams");
       streams.push_back(ctxs[i]->st);
       grp.emplace_back();
       pos.emplace_back();

@@ -65,14 +65,15 @@ struct SweepCtx {
   long long log_cap;
   // Replay (null otherwise): this slice visit's forced outcomes, one per site
   // (nonzero: the site's field flips).  A forced Metropolis test draws
-  // u = -1 (accepted for any finite ratio) or u = +inf (rejected); a forced
-  // heat-bath draw proposes the listed field by the same two values.
+  // u = -0 (accepted for any nonzero finite ratio, and the logged margin
+  // |A| - u is |A| itself) or u = +inf (rejected); a forced heat-bath draw
+  // proposes the listed field by the same two values.
   const int8_t *force;
 };
 
-// uniform that forces an outcome of "accept iff u < a" for any finite a >= 0
+// uniform that forces an outcome of "accept iff u < a" for any finite a > 0
 __device__ __forceinline__ double forced_uniform(bool take) {
-  return take ? -1.0 : __builtin_inf();
+  return take ? -0.0 : __builtin_inf();
 }
 
 // stats slots

@@ -786,7 +786,7 @@ __global__ __launch_bounds__(kDecThreads) void cplx_decide_kernel(SocDecideArgs 
   int8_t *xrow = a.fields + (long)a.li * a.N + a.g0;
   for (int j = t; j < n; j += kDecThreads) {
     xs[j] = (double)xrow[j];
-    us[j] = a.force ? (a.force[a.g0 + j] ? -1.0 : __builtin_inf())
+    us[j] = a.force ? (a.force[a.g0 + j] ? -0.0 : __builtin_inf())
                     : philox_uniform(a.key0, a.key1, a.sweep, a.slice_code,
                                      (uint64_t)(a.g0 + j), kPurposeMH);
   }
@@ -921,7 +921,7 @@ __global__ __launch_bounds__(kDecThreads) void cplx_block_decide_kernel(SocDecid
       double u;
       if (a.force) {
         const double xt = a.force[a.g0 + j] ? -xs[j] : xs[j];
-        u = xt > 0.0 ? -1.0 : __builtin_inf();
+        u = xt > 0.0 ? -0.0 : __builtin_inf();
       } else {
         u = philox_uniform(a.key0, a.key1, a.sweep, a.slice_code, (uint64_t)(a.g0 + j),
                            kPurposeHB);
@@ -950,7 +950,7 @@ __global__ __launch_bounds__(kDecThreads) void cplx_block_decide_kernel(SocDecid
     for (int q = 0; q < nf; ++q) pe += 2.0 * sv[fidx[q]] * xs[fidx[q]];
     const double prior = exp(pe);
     const double absA = (r.x * r.x + r.y * r.y) * prior;
-    const double u = a.force ? -1.0
+    const double u = a.force ? -0.0
                              : philox_uniform(a.key0, a.key1, a.sweep, a.slice_code,
                                               (uint64_t)a.g0, kPurposeMH);
     const bool finite = !isnan(absA);

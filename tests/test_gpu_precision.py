@@ -123,3 +123,80 @@ def test_fp32_switch_round_trip():
     if same and not low2:
         assert green_rel_err(ch, w) < 1e-10
     ch.close()
+
+
+def _flips_from(meta, M, N):
+    flips = np.zeros((2 * M, N), np.int8)
+    for code, site, acc in meta:
+        if acc:
+            flips[int(code), int(site)] = 1
+    return flips
+
+
+@pytest.mark.timeout(600)
+def test_fp32_form_whole_sweep_c4():
+    """The batched-walker workload's lattice (24x24, N_sigma = 288, U/t = 6,
+    dtau = 0.05, M = 400, k_tau = 10, k = 32): error statement over a whole
+    sweep.  The float32 chain's own accepted flips are replayed (forced
+    outcomes) through the float32 form and through the float64 oracle; every
+    accepted proposal's |A| (the margin a replay logs) over the 800 slice
+    visits is compared, and G, E and D at the sweep's end (just past a
+    stabilisation: the float64 bar)."""
+    p = synth.make_problem(24, 288, 288, 6.0, perturb=1e-3, seed=synth.SEED_BASE + 4)
+    ch = make_chain(p, "delayed", k=32, fp32=True)
+    ch.sweep(1)
+    meta, _ = ch.decisions()
+    flips = _flips_from(meta, p.n_slices, p.n_sites)
+    ch.close()
+    r32 = make_chain(p, "delayed", k=32, fp32=True)
+    st = r32.replay(flips)
+    m32, a32 = r32.decisions()
+    w = Walker(p, "delayed", k=32)
+    w.replay_sweep(flips)
+    a64 = np.array([e[5] for e in w.log])
+    acc = m32[:, 2].astype(bool)
+    assert np.array_equal(acc, np.array([e[4] for e in w.log]))
+    assert np.array_equal(r32.fields(), w.fields)
+    rel = np.abs(a32[acc] - a64[acc]) / np.abs(a64[acc])
+    print(f"c4 fp32 whole sweep: {acc.sum()} accepted ratios, |A| rel err max {rel.max():.2e}, "
+          f"median {np.median(rel):.2e}, 99th pct {np.percentile(rel, 99):.2e}; "
+          f"drift {st['max_stab_drift']:.2e}", flush=True)
+    assert rel.max() < 1e-3
+    assert np.median(rel) < 1e-5
+    Gg = [r32.green(s) for s in range(2)]
+    Gw = [w.green(s) for s in range(2)]
+    gerr = max(np.max(np.abs(Gg[s] - Gw[s])) / np.max(np.abs(Gw[s])) for s in range(2))
+    e_gpu, e_ref = energy(p.hopping, Gg[0], Gg[1], p.U), energy(p.hopping, Gw[0], Gw[1], p.U)
+    derr = abs(double_occupancy(*Gg) - double_occupancy(*Gw))
+    print(f"c4 fp32 end of sweep: G rel err {gerr:.2e}, E rel err "
+          f"{abs(e_gpu - e_ref) / abs(e_ref):.2e}, D abs err {derr:.2e}", flush=True)
+    assert gerr < 1e-10
+    r32.close()
+
+
+@pytest.mark.parametrize("window", [5, 15])
+def test_fp32_form_c4_windows(window):
+    """24x24, U/t = 6: G, E and D errors of the float32 form against the
+    float64 oracle 5 slices after a stabilisation (the largest drift of a
+    period), on the chain's own decisions."""
+    p = synth.make_problem(24, 288, 288, 6.0, n_slices=20, stab_every=10, perturb=1e-3,
+                           seed=synth.SEED_BASE + 4)
+    ch = make_chain(p, "delayed", k=32, fp32=True)
+    w = Walker(p, "delayed", k=32)
+    ch.forward_window(window)
+    w.forward_window(window)
+    meta, margin = ch.decisions()
+    n, n_band, same = compare_fp32(meta, margin, w.log, 0, p.n_slices)
+    assert same or n > 0.9 * len(meta)
+    if not same:
+        return
+    gerr = green_rel_err(ch, w)
+    Gg = [ch.green(s) for s in range(2)]
+    Gw = [w.green(s) for s in range(2)]
+    e_gpu, e_ref = energy(p.hopping, Gg[0], Gg[1], p.U), energy(p.hopping, Gw[0], Gw[1], p.U)
+    eerr = abs(e_gpu - e_ref) / abs(e_ref)
+    derr = abs(double_occupancy(*Gg) - double_occupancy(*Gw))
+    print(f"c4 fp32 window {window}: G rel err {gerr:.2e}, E rel err {eerr:.2e}, "
+          f"D abs err {derr:.2e}", flush=True)
+    assert gerr < 5e-5 and eerr < 1e-6 and derr < 1e-6
+    ch.close()
