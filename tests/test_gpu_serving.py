@@ -84,10 +84,35 @@ def test_served_mix_with_soc_jobs_equal_alone():
                             trial_dn=None, U=q.U, dtau=q.dtau, n_slices=q.n_slices,
                             stab_every=q.stab_every, seed=q.seed, n_walkers=2, n_sweeps=2,
                             scheme=Scheme.DELAYED, k=8, soc=True))
+    probs = {}
+    for i in range(4):
+        probs[i] = (synth.make_problem(6, 18, 17, 4.0, n_slices=20, stab_every=5, perturb=1e-3,
+                                       seed=synth.SEED_BASE + 67 + i) if i % 2 == 0 else
+                    synth.make_soc_problem(4, 14, -4.0, lam=0.5, n_slices=20, stab_every=5,
+                                           perturb=1e-3, seed=synth.SEED_BASE + 67 + i))
     be = GpuBackend(lanes=2)
     rep = Server(be, be.default_budget()).run(jobs)
     print("served mix:", rep.summary(), flush=True)
     assert rep.summary()["completed"] == 4
+    # one served walker of each model against the oracle (decisions and G)
+    import dataclasses
+    from oracle.pqmc import Walker
+    from oracle.soc import SocWalker
+    for ji in (0, 1):
+        j, r = jobs[ji], rep.results[ji]
+        w = r.walkers[-1]
+        q = dataclasses.replace(probs[ji], walker_id=w.walker_id)
+        ref = SocWalker(q, "delayed", k=j.k) if j.soc else Walker(q, "delayed", k=j.k)
+        for _ in range(j.n_sweeps):
+            ref.sweep()
+        assert np.array_equal(w.fields, ref.fields), ("oracle fields", ji)
+        Gs = [w.green[0]] if j.soc else [w.green[0], w.green[1]]
+        Gr = [ref.green()] if j.soc else [ref.green(0), ref.green(1)]
+        for G, R in zip(Gs, Gr):
+            err = np.max(np.abs(G - R)) / max(1.0, np.max(np.abs(R)))
+            print(f"served job {ji} ({'soc' if j.soc else 'hubbard'}) walker {w.walker_id} "
+                  f"vs oracle: G err {err:.2e}", flush=True)
+            assert err < 1e-10
     for j, r in zip(jobs, rep.results):
         for w in r.walkers:
             if j.soc:
