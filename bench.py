@@ -349,10 +349,12 @@ def c4_leg(args):
     N_sigma=288, U/t=6) and 64 of 12x12 (N=144, N_sigma=72, U/t=6), four of
     each in every batch of 8 (lattices of two sizes in one launch), 16 batches
     on 16 HIP streams, delayed k=32 with the float32 flush (float64 ratios,
-    QR and G every 10 slices), one whole sweep (M=400); then the same walkers
-    in float64.  Reports jobs/s (a job = 64 walkers x 1 sweep of one lattice)
-    and the mean energy and double occupancy of each job's walkers at the
-    sweep's end with their standard errors (independent chains)."""
+    QR and G every 10 slices), two whole sweeps (M=400), the second timed;
+    then the same with every sweep one captured HIP graph per batch, and the
+    same walkers in float64.  Reports jobs/s (a job = 64 walkers x 1 sweep of
+    one lattice) and the mean energy and double occupancy of each job's
+    walkers after the second sweep with their standard errors (independent
+    chains)."""
     import dataclasses
     import numpy as np
     import torch
@@ -363,7 +365,8 @@ def c4_leg(args):
     out = {"workload": "64 walkers of 24x24 (N=576, N_sigma=288) + 64 of 12x12 (N=144, "
                        "N_sigma=72), U/t=6, dtau=0.05, M=400, k_tau=10, seeded 1e-3 bond "
                        "perturbation; 16 batches of 4+4 mixed walkers on 16 streams; delayed k=32"}
-    for fp32 in (True, False):
+    for form, fp32, graph in (("fp32", True, False), ("fp32_graph", True, True),
+                              ("fp64", False, False)):
         streams = [torch.cuda.Stream() for _ in range(16)]
         chains, jobs = [], []
         for si, st in enumerate(streams):
@@ -373,14 +376,21 @@ def c4_leg(args):
                     chains.append(Chain(qq.hopping, qq.trial_up, qq.trial_dn, qq.U, qq.dtau,
                                         qq.n_slices, qq.stab_every, qq.seed, qq.walker_id,
                                         scheme=Scheme.DELAYED, k=32, fp32=fp32, stream=st))
+                    if graph:
+                        chains[-1].set_opts(Scheme.DELAYED, k=32, graph=True)
                     jobs.append(j)
         torch.cuda.synchronize()
+        # sweep 1 (with the graph form, its capture), then the timed sweep 2
         t0 = time.perf_counter()
+        multi_sweep(chains, 1)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
         stats = multi_sweep(chains, 1)
         torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
+        dt = time.perf_counter() - t1
         fu = 64 * 2 * 400 * (576 + 144)
-        rec = {"s_per_sweep": dt, "jobs_per_s": 2.0 / dt, "field_updates_per_s": fu / dt,
+        rec = {"s_per_sweep": dt, "first_sweep_s": t1 - t0, "jobs_per_s": 2.0 / dt,
+               "field_updates_per_s": fu / dt,
                "acceptance": sum(x["accepted"] for x in stats) / sum(x["proposed"] for x in stats),
                "max_stab_drift": max(x["max_stab_drift"] for x in stats)}
         for j, (q, name) in enumerate(((p24, "24x24"), (p12, "12x12"))):
@@ -392,13 +402,17 @@ def c4_leg(args):
                          "energy_per_site_stderr": float(e.std(ddof=1) / np.sqrt(len(e))),
                          "double_occupancy": float(d.mean()),
                          "double_occupancy_stderr": float(d.std(ddof=1) / np.sqrt(len(d)))}
-        out["fp32" if fp32 else "fp64"] = rec
-        log("c4", "fp32" if fp32 else "fp64", rec)
+        if graph:   # captured sweeps are bit for bit the launched ones
+            rec["bitwise_equal_to_launched"] = all(
+                rec[n] == out["fp32"][n] for n in ("24x24", "12x12"))
+        out[form] = rec
+        log("c4", form, rec)
         for c in chains:
             c.close()
         del chains
         torch.cuda.empty_cache()
     out["fp32_speedup"] = out["fp64"]["s_per_sweep"] / out["fp32"]["s_per_sweep"]
+    out["graph_speedup"] = out["fp32"]["s_per_sweep"] / out["fp32_graph"]["s_per_sweep"]
     for name in ("24x24", "12x12"):
         a, b = out["fp32"][name], out["fp64"][name]
         out[f"{name}_energy_difference_in_stderr"] = abs(

@@ -103,6 +103,16 @@ typedef enum { PQMC_LOCAL = 0, PQMC_DELAYED = 1, PQMC_BLOCK_FB = 2,
 /* PQMC_LOCAL with one launch per site (the form batches use) instead of the
  * persistent kernel, for comparisons. */
 #define PQMC_FLAG_SITE_LAUNCHES 16u
+/* Graph-captured sweeps (delayed and block force-bias): the first sweep of
+ * a batch records its whole forward and backward pass -- every propagation,
+ * panel, decision, flush and stabilisation launch -- into one HIP graph, and
+ * every sweep (that one included) is one graph launch; the Philox sweep
+ * counter is read from device memory.  The graph is kept by the batch's
+ * first context and captured again when the batch or any walker's options,
+ * fields or position change.  Needs a non-null stream; phase and kernel
+ * timers are off; with n_sweeps > 1 the decision log holds the last sweep.
+ * Results are bit for bit those of the sweeps launched one by one. */
+#define PQMC_FLAG_GRAPH  32u
 
 /* kernel classes of pqmc_get_kernel_times() */
 enum {

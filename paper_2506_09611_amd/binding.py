@@ -40,6 +40,7 @@ FLAG_TIMING = 2
 FLAG_KTIME = 4
 FLAG_FP32 = 8
 FLAG_SITE_LAUNCHES = 16
+FLAG_GRAPH = 32
 
 
 class PQMCError(RuntimeError):
@@ -219,8 +220,10 @@ class Chain:
 
     # -- calls with the C ABI's names
     def set_opts(self, scheme, k=1, b=1, log=None, timing=None, ktime=None, fp32=None,
-                 tile_chunks=None, site_launches=None):
+                 tile_chunks=None, site_launches=None, graph=None):
         flags = self._flags
+        if graph is not None:
+            flags = (flags & ~FLAG_GRAPH) | (FLAG_GRAPH if graph else 0)
         if site_launches is not None:
             flags = (flags & ~FLAG_SITE_LAUNCHES) | (FLAG_SITE_LAUNCHES if site_launches else 0)
         if tile_chunks is not None:

@@ -81,6 +81,16 @@ struct pqmc_ctx {
   // work copy for the propagation and the stabilisation, published rows
   bool gsized = false;
   bool g_valid = false;   // G holds the current G-form state
+  // graph-captured sweeps (PQMC_FLAG_GRAPH): the sweep counter on the device,
+  // and, in a batch's first context, the captured sweep of that batch
+  uint64_t *sweep_dev = nullptr;
+  bool capturing = false;
+  uint64_t generation = 0;   // bumped by every change that a captured sweep bakes in
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  std::vector<pqmc_ctx *> gkey;
+  std::vector<uint64_t> ggen;
+  long long glog = 0, ghb = 0;   // log entries one captured sweep writes
   double *G[2] = {}, *Gw[2] = {}, *grow_buf[2] = {};
 
   double *UR[2] = {};
@@ -131,6 +141,7 @@ void layout(pqmc_ctx &c, char *base, size_t *bytes) {
   c.gtmp = c.Tay0;   // Green's function output reuses the Taylor scratch
   c.fields = cv.take<int8_t>((size_t)c.M * N);
   c.replay = cv.take<int8_t>((size_t)2 * c.M * N);
+  c.sweep_dev = cv.take<uint64_t>(1);
   c.stats = cv.take<unsigned long long>(16);
   const int kmax = c.gmax;
   for (int s = 0; s < 2; ++s) {
@@ -259,7 +270,8 @@ struct KTimer {
   int cls;
   size_t i0 = 0;
   bool on;
-  KTimer(pqmc_ctx &cc, int k) : c(cc), cls(k), on((cc.opts.flags & PQMC_FLAG_KTIME) != 0) {
+  KTimer(pqmc_ctx &cc, int k)
+      : c(cc), cls(k), on((cc.opts.flags & PQMC_FLAG_KTIME) != 0 && !cc.capturing) {
     if (!on) return;
     while (c.kevs.size() < c.kused + 2) {
       hipEvent_t e;
@@ -661,6 +673,7 @@ SweepCtx sweep_ctx(pqmc_ctx &c, int l, int dir) {
   x.hb_base = c.hb_count;
   x.log_cap = c.log_cap;
   x.force = c.replaying ? c.replay + (size_t)x.slice_code * c.N : nullptr;
+  x.sweep_dev = c.capturing ? c.sweep_dev : nullptr;
   return x;
 }
 
@@ -914,7 +927,8 @@ struct PhaseTimer {
   bool on;
   std::vector<std::pair<int, size_t>> marks;  // (phase, event index of start)
   size_t used = 0;
-  explicit PhaseTimer(pqmc_ctx &cc) : c(cc), on((cc.opts.flags & PQMC_FLAG_TIMING) != 0) {}
+  explicit PhaseTimer(pqmc_ctx &cc)
+      : c(cc), on((cc.opts.flags & PQMC_FLAG_TIMING) != 0 && !(cc.opts.flags & PQMC_FLAG_GRAPH)) {}
   int mark(int phase) {
     if (!on) return PQMC_OK;
     if (used == c.evs.size()) {
@@ -1081,6 +1095,64 @@ pqmc_status check_batch(pqmc_ctx *const *w, int n) {
 
 pqmc_status as_status(int rc) { return (pqmc_status)rc; }
 
+void drop_graph(pqmc_ctx &c) {
+  if (c.gexec) (void)hipGraphExecDestroy(c.gexec);
+  if (c.graph) (void)hipGraphDestroy(c.graph);
+  c.gexec = nullptr;
+  c.graph = nullptr;
+  c.gkey.clear();
+  c.ggen.clear();
+}
+
+bool graph_mode(const Walkers &b) {
+  for (int i = 0; i < b.n; ++i)
+    if (!(b[i].opts.flags & PQMC_FLAG_GRAPH)) return false;
+  const int sch = b.lead().opts.scheme;
+  return sch == PQMC_DELAYED || sch == PQMC_BLOCK_FB;
+}
+
+// The batch's captured sweep: reused while the batch and every walker's
+// generation are unchanged, captured (one forward and one backward pass,
+// recorded but not run) otherwise.  Capturing leaves the host-side state
+// where a real sweep leaves it, which is where it started.
+int sweep_graph(const Walkers &b) {
+  pqmc_ctx &L = b.lead();
+  bool same = L.gexec && (int)L.gkey.size() == b.n;
+  for (int i = 0; same && i < b.n; ++i)
+    same = L.gkey[i] == &b[i] && L.ggen[i] == b[i].generation;
+  if (same) return PQMC_OK;
+  drop_graph(L);
+  if (!L.st) return set_error(PQMC_EINVAL, "graph-captured sweeps need a non-null stream");
+  for (int i = 0; i < b.n; ++i) b[i].capturing = true;
+  PQ_HIP_CHECK(hipStreamBeginCapture(L.st, hipStreamCaptureModeRelaxed));
+  PhaseTimer off(L);
+  int rc = run_forward(b, L.M, off);
+  if (!rc) rc = run_backward(b, off);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(L.st, &g);
+  for (int i = 0; i < b.n; ++i) {
+    // the host-side log positions the capture advanced are those every
+    // launch of the graph fills; each call starts them again from zero
+    b[i].capturing = false;
+    b[i].glog = b[i].log_count;
+    b[i].ghb = b[i].hb_count;
+    b[i].log_count = 0;
+    b[i].hb_count = 0;
+  }
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return fail_device(e, "hipStreamEndCapture", __FILE__, __LINE__);
+  L.graph = g;
+  PQ_HIP_CHECK(hipGraphInstantiate(&L.gexec, g, nullptr, nullptr, 0));
+  for (int i = 0; i < b.n; ++i) {
+    L.gkey.push_back(&b[i]);
+    L.ggen.push_back(b[i].generation);
+  }
+  return PQMC_OK;
+}
+
 // Device scratch of pqmc_get_green_static: X = U_R T and G, 32 MiB per GPU,
 // held by every GPU the library runs on until the process ends.  Host code
 // never uses the array's name as an address: its device address is looked
@@ -1235,6 +1307,7 @@ pqmc_status pqmc_set_opts(pqmc_ctx *c, const pqmc_update_opts *o) {
   const bool was = fp32_form(*c), now = (o->flags & PQMC_FLAG_FP32) != 0;
   c->opts = *o;
   c->g_valid = false;
+  ++c->generation;
   c->gb.chunks = o->tile_chunks > 0 ? o->tile_chunks : 2;
   // the current T moves to the representation the next call reads
   hipError_t e = hipSuccess;
@@ -1265,6 +1338,7 @@ pqmc_status pqmc_set_fields(pqmc_ctx *c, const int8_t *fields) {
   if (e != hipSuccess) return as_status(fail_device(e, "memset", __FILE__, __LINE__));
   c->failed = false;
   c->g_valid = false;
+  ++c->generation;
   pqmc_ctx *one[1] = {c};
   int rc = build_state(Walkers{one, 1});
   if (!rc) rc = sync_check(*c);
@@ -1301,14 +1375,39 @@ pqmc_status pqmc_batch_sweep(pqmc_ctx *const *ctxs, int32_t n, int32_t n_sweeps,
   int rc = PQMC_OK;
   for (int i = 0; i < n && !rc; ++i) rc = begin_call(b[i]);
   PhaseTimer tm(b.lead());
-  for (int k = 0; k < n_sweeps && !rc; ++k) {
-    rc = run_forward(b, b.lead().M, tm);
-    if (!rc) rc = run_backward(b, tm);
-    if (!rc)
-      for (int i = 0; i < n; ++i) ++b[i].sweep_index;
+  if (!rc && n_sweeps > 0 && graph_mode(b)) {
+    // one graph launch per sweep; the sweep counter goes to the device first
+    rc = sweep_graph(b);
+    for (int k = 0; k < n_sweeps && !rc; ++k) {
+      uint64_t *ptr[kMaxBatch];
+      uint64_t val[kMaxBatch];
+      for (int i = 0; i < n; ++i) {
+        ptr[i] = b[i].sweep_dev;
+        val[i] = b[i].sweep_index;
+      }
+      hipError_t e = set_u64(ptr, val, n, b.lead().st);
+      if (e == hipSuccess) e = hipGraphLaunch(b.lead().gexec, b.lead().st);
+      if (e != hipSuccess) rc = fail_device(e, "hipGraphLaunch", __FILE__, __LINE__);
+      if (!rc)
+        for (int i = 0; i < n; ++i) {
+          ++b[i].sweep_index;
+          b[i].log_count = b[i].glog;
+          b[i].hb_count = b[i].ghb;
+        }
+    }
+  } else {
+    for (int k = 0; k < n_sweeps && !rc; ++k) {
+      rc = run_forward(b, b.lead().M, tm);
+      if (!rc) rc = run_backward(b, tm);
+      if (!rc)
+        for (int i = 0; i < n; ++i) ++b[i].sweep_index;
+    }
   }
   if (rc) {
-    for (int i = 0; i < n; ++i) b[i].failed = true;
+    for (int i = 0; i < n; ++i) {
+      b[i].failed = true;
+      ++b[i].generation;
+    }
     return as_status(rc);
   }
   return as_status(finish_call(b, tm, t0, out));
@@ -1404,9 +1503,11 @@ pqmc_status pqmc_replay(pqmc_ctx *c, const int8_t *flips, pqmc_stats *out) {
   if (e == hipSuccess) e = hipStreamSynchronize(c->st);   // the host array may go away
   if (e != hipSuccess) return as_status(fail_device(e, "upload replay", __FILE__, __LINE__));
   c->replaying = true;
+  ++c->generation;
   pqmc_ctx *one[1] = {c};
   const pqmc_status st = pqmc_batch_sweep(one, 1, 1, out);
   c->replaying = false;
+  ++c->generation;
   return st;
 }
 
@@ -1431,7 +1532,10 @@ pqmc_status pqmc_batch_forward_window(pqmc_ctx *const *ctxs, int32_t n, int32_t 
   for (int i = 0; i < n && !rc; ++i) rc = begin_call(b[i]);
   PhaseTimer tm(b.lead());
   if (!rc) rc = run_forward(b, n_slices, tm);
-  for (int i = 0; i < n; ++i) b[i].windowed = true;
+  for (int i = 0; i < n; ++i) {
+    b[i].windowed = true;
+    ++b[i].generation;
+  }
   if (rc) {
     for (int i = 0; i < n; ++i) b[i].failed = true;
     return as_status(rc);
@@ -1553,6 +1657,7 @@ pqmc_status pqmc_destroy(pqmc_ctx *c) {
     return PQMC_OK;
   }
   (void)hipStreamSynchronize(c->st);
+  drop_graph(*c);
   for (hipEvent_t e : c->evs) (void)hipEventDestroy(e);
   for (hipEvent_t e : c->kevs) (void)hipEventDestroy(e);
   delete c;

@@ -47,7 +47,8 @@ __device__ __forceinline__ double philox_uniform(uint64_t k0, uint64_t k1, uint6
 // Sweep-wide constants every update kernel needs.
 struct SweepCtx {
   uint64_t key0, key1;      // Philox key (seed, walker id)
-  uint64_t sweep;           // counter word 0
+  uint64_t sweep;           // counter word 0 (unless sweep_dev is set)
+  const uint64_t *sweep_dev;  // graph-captured sweeps: counter word 0 read from here
   uint64_t slice_code;      // counter word 1: dir * M + (l - 1)
   int li;                   // slice index l - 1 into the field array
   int N;                    // sites
@@ -70,6 +71,12 @@ struct SweepCtx {
   // proposes the listed field by the same two values.
   const int8_t *force;
 };
+
+// Philox counter word 0 of the current sweep: a value baked into the launch,
+// or read from device memory when the sweep is a replayed graph
+__device__ __forceinline__ uint64_t sweep_of(uint64_t v, const uint64_t *dev) {
+  return dev ? *dev : v;
+}
 
 // uniform that forces an outcome of "accept iff u < a" for any finite a > 0
 __device__ __forceinline__ double forced_uniform(bool take) {

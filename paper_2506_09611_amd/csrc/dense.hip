@@ -529,6 +529,14 @@ __global__ void widen_kernel(ConvArgs a) {
     d[e] = (double)s[e];
 }
 
+struct SetArgs {
+  uint64_t *p[kMaxMats];
+  uint64_t v[kMaxMats];
+};
+__global__ void set_u64_kernel(SetArgs a, int n) {
+  if ((int)threadIdx.x < n) *a.p[threadIdx.x] = a.v[threadIdx.x];
+}
+
 struct DiffArgs {
   const double *a[kMaxMats], *b[kMaxMats];
   unsigned long long *out[kMaxMats];
@@ -664,6 +672,17 @@ hipError_t widen_to_f64(const float *const *src, double *const *dst, int nmat, c
     a.n[i] = n[i];
   }
   hipLaunchKernelGGL(widen_kernel, dim3(256, nmat), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t set_u64(uint64_t *const *p, const uint64_t *v, int n, hipStream_t st) {
+  if (n < 1 || n > kMaxMats) return hipErrorInvalidValue;
+  SetArgs a{};
+  for (int i = 0; i < n; ++i) {
+    a.p[i] = p[i];
+    a.v[i] = v[i];
+  }
+  hipLaunchKernelGGL(set_u64_kernel, dim3(1), dim3(64), 0, st, a, n);
   return hipGetLastError();
 }
 

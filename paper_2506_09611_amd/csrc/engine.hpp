@@ -76,6 +76,8 @@ hipError_t round_to_f32(const double *const *src, float *const *dst, int nmat, c
 hipError_t widen_to_f64(const float *const *src, double *const *dst, int nmat, const long *n,
                         hipStream_t st);
 hipError_t init_fields(int8_t *fields, int M, int N, uint64_t k0, uint64_t k1, hipStream_t st);
+// *p[i] = v[i], i < n (a kernel: safe inside captured graphs)
+hipError_t set_u64(uint64_t *const *p, const uint64_t *v, int n, hipStream_t st);
 // *out[i] = max(*out[i], max_e |a_i[e] - b_i[e]|), e < n[i], stored as the bits
 // of a non-negative double (atomicMax on the integer pattern)
 hipError_t max_abs_diff(const double *const *a, const double *const *b, const long *n,

@@ -182,8 +182,8 @@ __global__ __launch_bounds__(kLpThreads) void local_t_kernel(LocalPersistArgs a)
     const double R = r0 * r1;
     const double absA = fabs(R);
     const double u = C.force ? forced_uniform(C.force[i] != 0)
-                             : philox_uniform(C.key0, C.key1, C.sweep, C.slice_code, (uint64_t)i,
-                                              kPurposeMH);
+                             : philox_uniform(C.key0, C.key1, sweep_of(C.sweep, C.sweep_dev),
+                                              C.slice_code, (uint64_t)i, kPurposeMH);
     const bool finite = !isnan(absA);
     const bool acc = __builtin_amdgcn_readfirstlane((finite && (u < absA)) ? 1 : 0) != 0;
     if (id == 0 && t == 0) {
@@ -332,8 +332,8 @@ __global__ __launch_bounds__(kLgThreads) void local_g_kernel(LocalPersistArgs a)
     const double R = r0 * r1;
     const double absA = fabs(R);
     const double u = C.force ? forced_uniform(C.force[i] != 0)
-                             : philox_uniform(C.key0, C.key1, C.sweep, C.slice_code, (uint64_t)i,
-                                              kPurposeMH);
+                             : philox_uniform(C.key0, C.key1, sweep_of(C.sweep, C.sweep_dev),
+                                              C.slice_code, (uint64_t)i, kPurposeMH);
     const bool finite = !isnan(absA);
     const bool acc = __builtin_amdgcn_readfirstlane((finite && (u < absA)) ? 1 : 0) != 0;
     if (w == 0 && t == 0) {

@@ -101,7 +101,8 @@ __global__ __launch_bounds__(256) void local_step_kernel(Batch<LocalArgs> B) {
     const double R = r0 * r1;
     const double absA = fabs(R);
     const double u = C.force ? forced_uniform(C.force[i - 1] != 0)
-                             : philox_uniform(C.key0, C.key1, C.sweep, C.slice_code,
+                             : philox_uniform(C.key0, C.key1, sweep_of(C.sweep, C.sweep_dev),
+                                              C.slice_code,
                                               (uint64_t)(i - 1), kPurposeMH);
     const bool finite = !isnan(absA);
     // every lane computes the same value; make it an explicit scalar
@@ -221,6 +222,7 @@ struct ReduceArgs {
   uint64_t key0, key1, sweep, slice_code;
   const int8_t *force;       // replay: forced outcomes of the slice visit (or null)
   const int8_t *xrow;        // the slice's fields (forced heat-bath proposals)
+  const uint64_t *sweep_dev; // graph-captured sweeps: the sweep counter on the device
 };
 
 constexpr int kRedThreads = 256;
@@ -325,11 +327,12 @@ __global__ __launch_bounds__(kRedThreads) void group_reduce_kernel(Batch<ReduceA
       if (a.mode == kUniBlock && t == kk) a.g.uni[kk] = forced_uniform(true);
     } else if (s == 0 && a.mode != kUniNone) {
       const uint64_t purpose = a.mode == kUniDelayed ? kPurposeMH : kPurposeHB;
+      const uint64_t sw = sweep_of(a.sweep, a.sweep_dev);
       if (t < kk)
-        a.g.uni[t] = philox_uniform(a.key0, a.key1, a.sweep, a.slice_code, (uint64_t)(a.g0 + t),
+        a.g.uni[t] = philox_uniform(a.key0, a.key1, sw, a.slice_code, (uint64_t)(a.g0 + t),
                                     purpose);
       if (a.mode == kUniBlock && t == kk)
-        a.g.uni[kk] = philox_uniform(a.key0, a.key1, a.sweep, a.slice_code, (uint64_t)a.g0,
+        a.g.uni[kk] = philox_uniform(a.key0, a.key1, sw, a.slice_code, (uint64_t)a.g0,
                                      kPurposeMH);
     }
     return;
@@ -1460,7 +1463,7 @@ hipError_t launch_reduce(const SpinMats *m, const GroupBufs *g, const SweepCtx *
   for (int w = 0; w < nw; ++w) {
     B.w[w] = ReduceArgs{m[w], g[w], g0, kk[w], ntm, do_panels, w0_mode, mode,
                         c[w].key0, c[w].key1, c[w].sweep, c[w].slice_code, c[w].force,
-                        c[w].fields + (long)c[w].li * c[w].N};
+                        c[w].fields + (long)c[w].li * c[w].N, c[w].sweep_dev};
     kkm = max(kkm, kk[w]);
   }
   const int nP = do_panels ? ntm * kRedParts : 0, nW = w0_mode ? kkm : 0;
