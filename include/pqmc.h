@@ -111,8 +111,19 @@ typedef enum { PQMC_LOCAL = 0, PQMC_DELAYED = 1, PQMC_BLOCK_FB = 2,
  * first context and captured again when the batch or any walker's options,
  * fields or position change.  Needs a non-null stream; phase and kernel
  * timers are off; with n_sweeps > 1 the decision log holds the last sweep.
- * Results are bit for bit those of the sweeps launched one by one. */
+ * Results are bit for bit those of the sweeps launched one by one.  While a
+ * capture runs (the first graph sweep of a batch, or the first after a
+ * change), no other thread of the process may use the legacy (null) stream
+ * or synchronise the device; the library's own calls copy on the contexts'
+ * streams, so concurrent batches of pqmc_multi_sweep are safe. */
 #define PQMC_FLAG_GRAPH  32u
+/* Propagate with the dense K = e^{-dtau H0} and K^{-1} (GEMMs) even when H0
+ * is sparse.  By default a walker whose H0 has at most 8 nonzeros per row,
+ * N <= 4096 and ||dtau H0||_1 <= 1 applies e^{-+dtau H0} as the Taylor series
+ * of the sparse H0 (degree J with a dropped term below 2^-60; the same
+ * operator to rounding), which costs 2 J nnz(H0) N_sigma flops per product
+ * instead of 2 N^2 N_sigma. */
+#define PQMC_FLAG_DENSE_PROP 64u
 
 /* kernel classes of pqmc_get_kernel_times() */
 enum {

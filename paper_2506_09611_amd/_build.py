@@ -10,8 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libpqmc.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-SOURCES = ["gemm.hip", "dense.hip", "update.hip", "local_persist.hip", "soc.hip", "capi.cpp",
-           "soc_capi.cpp"]
+SOURCES = ["gemm.hip", "dense.hip", "update.hip", "local_persist.hip", "propagate.hip", "soc.hip",
+           "capi.cpp", "soc_capi.cpp"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-pthread",
          # no packed FP32 instructions anywhere in the device code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

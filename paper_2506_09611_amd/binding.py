@@ -41,6 +41,7 @@ FLAG_KTIME = 4
 FLAG_FP32 = 8
 FLAG_SITE_LAUNCHES = 16
 FLAG_GRAPH = 32
+FLAG_DENSE_PROP = 64
 
 
 class PQMCError(RuntimeError):
@@ -171,12 +172,15 @@ class Chain:
     torch.cuda.Stream the walker's work goes to (default: the current one);
     the workspace is allocated on it.  tile_chunks: column chunks per row
     strip of the fused flush kernel (0: two, for batches; a large value: one
-    tile per workgroup, for a walker run alone).
+    tile per workgroup, for a walker run alone).  dense_prop: propagate
+    with the dense K = e^{-dtau H0} (GEMMs) even when H0 is sparse enough
+    for the Taylor-series propagation (the default where it applies).
     """
 
     def __init__(self, hopping, trial_up, trial_dn, U, dtau, n_slices, stab_every, seed,
                  walker_id=0, scheme=Scheme.LOCAL, k=1, b=1, k_max=None, b_max=None,
-                 log=False, timing=False, fp32=False, stream=None, tile_chunks=0):
+                 log=False, timing=False, fp32=False, stream=None, tile_chunks=0,
+                 dense_prop=False):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device visible to torch")
@@ -193,7 +197,7 @@ class Chain:
                              _dptr(self._Pd), float(U), float(dtau), int(n_slices),
                              int(stab_every), int(seed) & (2**64 - 1), int(walker_id))
         self._flags = ((FLAG_LOG if log else 0) | (FLAG_TIMING if timing else 0)
-                       | (FLAG_FP32 if fp32 else 0))
+                       | (FLAG_FP32 if fp32 else 0) | (FLAG_DENSE_PROP if dense_prop else 0))
         kmax = int(k_max if k_max is not None else k)
         bmax = int(b_max if b_max is not None else b)
         self.tile_chunks = int(tile_chunks)
@@ -220,8 +224,10 @@ class Chain:
 
     # -- calls with the C ABI's names
     def set_opts(self, scheme, k=1, b=1, log=None, timing=None, ktime=None, fp32=None,
-                 tile_chunks=None, site_launches=None, graph=None):
+                 tile_chunks=None, site_launches=None, graph=None, dense_prop=None):
         flags = self._flags
+        if dense_prop is not None:
+            flags = (flags & ~FLAG_DENSE_PROP) | (FLAG_DENSE_PROP if dense_prop else 0)
         if graph is not None:
             flags = (flags & ~FLAG_GRAPH) | (FLAG_GRAPH if graph else 0)
         if site_launches is not None:

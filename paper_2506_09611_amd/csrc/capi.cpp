@@ -55,6 +55,12 @@ struct pqmc_ctx {
   hipStream_t st = nullptr;
 
   double *K = nullptr, *Kinv = nullptr, *Tay0 = nullptr, *Tay1 = nullptr;
+  // H0 as ELL rows (sparse propagation): ell_w entries per row, Taylor degree
+  // taylor_J; sparse_prop when H0 qualifies (see setup_sparse)
+  int *ell_idx = nullptr;
+  double *ell_val = nullptr;
+  int ell_w = 0, taylor_J = 0;
+  bool sparse_prop = false;
   int8_t *fields = nullptr;
   int8_t *replay = nullptr;   // 2 M x N forced outcomes of pqmc_replay
   bool replaying = false;
@@ -139,6 +145,8 @@ void layout(pqmc_ctx &c, char *base, size_t *bytes) {
   c.Tay0 = cv.take<double>(NN);
   c.Tay1 = cv.take<double>(NN);
   c.gtmp = c.Tay0;   // Green's function output reuses the Taylor scratch
+  c.ell_idx = cv.take<int>(N * kExpMaxW);
+  c.ell_val = cv.take<double>(N * kExpMaxW);
   c.fields = cv.take<int8_t>((size_t)c.M * N);
   c.replay = cv.take<int8_t>((size_t)2 * c.M * N);
   c.sweep_dev = cv.take<uint64_t>(1);
@@ -294,7 +302,7 @@ double *other(double *cur, double *const w[2]) { return cur == w[0] ? w[1] : w[0
 int sync_check(pqmc_ctx &c) {
   PQ_HIP_CHECK(hipStreamSynchronize(c.st));
   unsigned long long h[16];
-  PQ_HIP_CHECK(hipMemcpy(h, c.stats, sizeof h, hipMemcpyDeviceToHost));
+  PQ_HIP_CHECK(d2h(h, c.stats, sizeof h, c.st));
   if (h[kStError] & kErrSingular) {
     c.failed = true;
     return set_error(PQMC_ESINGULAR, "stabilisation factorisation broke down (zero pivot)");
@@ -336,6 +344,50 @@ struct GemmQueue {
     return PQMC_OK;
   }
 };
+
+struct ExpvQueue {
+  hipStream_t st;
+  ExpvBatch cur{};
+  int add(const ExpvDesc &d) {
+    cur.d[cur.count++] = d;
+    return cur.count == kExpvMaxBatch ? flush() : PQMC_OK;
+  }
+  int flush() {
+    if (cur.count == 0) return PQMC_OK;
+    hipError_t e = expv(cur, st);
+    cur.count = 0;
+    if (e != hipSuccess) return fail_device(e, "sparse propagation", __FILE__, __LINE__);
+    return PQMC_OK;
+  }
+};
+
+// the walker propagates with the sparse H0 (and not the dense K, K^{-1})
+bool sparse(const pqmc_ctx &c) {
+  return c.sparse_prop && !(c.opts.flags & PQMC_FLAG_DENSE_PROP);
+}
+
+// Y = rs * e^{sign dtau H0} (ks * X) for the N x n matrix X (field row
+// scaling after the product, or before it when pre)
+ExpvDesc expv_desc(const pqmc_ctx &c, const double *X, double *Y, int n, double sign,
+                   const int8_t *row, double pos, double neg, bool pre) {
+  ExpvDesc d{};
+  d.X = X;
+  d.ldx = n;
+  d.Y = Y;
+  d.ldy = n;
+  d.N = c.N;
+  d.n = n;
+  d.idx = c.ell_idx;
+  d.val = c.ell_val;
+  d.w = c.ell_w;
+  d.J = c.taylor_J;
+  d.a = sign * c.dtau;
+  d.field = row;
+  d.pos = pos;
+  d.neg = neg;
+  d.pre = pre ? 1 : 0;
+  return d;
+}
 
 bool fp32_form(const pqmc_ctx &c) { return (c.opts.flags & PQMC_FLAG_FP32) != 0; }
 // the G-form local update: G (not T) is the updated state between stabilisations
@@ -520,6 +572,7 @@ double *slot(double *stack, int j, const pqmc_ctx &c, int s) {
 int prop_forward(const Walkers &b, int l) {
   pqmc_ctx &L = b.lead();
   GemmQueue q{L.st, false, false};
+  ExpvQueue xq{L.st};
   KTimer kt(L, PQMC_K_PROPAGATE);
   for (int i = 0; i < b.n; ++i) {
     pqmc_ctx &c = b[i];
@@ -529,18 +582,25 @@ int prop_forward(const Walkers &b, int l) {
       const double ep = std::exp(c.alpha * kSpin[s]), em = std::exp(-c.alpha * kSpin[s]);
       double *nur = other(c.UR[s], c.URw[s]);
       double *nul = other(c.ULt[s], c.ULw[s]);
-      GemmDesc d = gemm_desc(c.K, c.N, c.UR[s], n, nur, n, c.N, n, c.N);
-      d.rs_field = row; d.rs_pos = ep; d.rs_neg = em;
-      int rc = q.add(d);
-      GemmDesc e = gemm_desc(c.Kinv, c.N, c.ULt[s], n, nul, n, c.N, n, c.N);
-      e.rs_field = row; e.rs_pos = em; e.rs_neg = ep;
-      if (!rc) rc = q.add(e);
+      int rc;
+      if (sparse(c)) {
+        rc = xq.add(expv_desc(c, c.UR[s], nur, n, -1.0, row, ep, em, false));
+        if (!rc) rc = xq.add(expv_desc(c, c.ULt[s], nul, n, +1.0, row, em, ep, false));
+      } else {
+        GemmDesc d = gemm_desc(c.K, c.N, c.UR[s], n, nur, n, c.N, n, c.N);
+        d.rs_field = row; d.rs_pos = ep; d.rs_neg = em;
+        rc = q.add(d);
+        GemmDesc e = gemm_desc(c.Kinv, c.N, c.ULt[s], n, nul, n, c.N, n, c.N);
+        e.rs_field = row; e.rs_pos = em; e.rs_neg = ep;
+        if (!rc) rc = q.add(e);
+      }
       if (rc) return rc;
       c.UR[s] = nur;
       c.ULt[s] = nul;
     }
   }
   int rc = q.flush();
+  if (!rc) rc = xq.flush();
   for (int i = 0; i < b.n && !rc; ++i)
     if (gform(b[i])) rc = wrap_G(b[i], l, true);
   return rc;
@@ -550,6 +610,7 @@ int prop_forward(const Walkers &b, int l) {
 int prop_backward(const Walkers &b, int l, bool with_R) {
   pqmc_ctx &L = b.lead();
   GemmQueue q{L.st, false, false};
+  ExpvQueue xq{L.st};
   KTimer kt(L, with_R ? PQMC_K_PROPAGATE : -1);
   for (int i = 0; i < b.n; ++i) {
     pqmc_ctx &c = b[i];
@@ -558,22 +619,32 @@ int prop_backward(const Walkers &b, int l, bool with_R) {
       const int n = c.Ns[s];
       const double ep = std::exp(c.alpha * kSpin[s]), em = std::exp(-c.alpha * kSpin[s]);
       double *nul = other(c.ULt[s], c.ULw[s]);
-      GemmDesc d = gemm_desc(c.K, c.N, c.ULt[s], n, nul, n, c.N, n, c.N);
-      d.ks_field = row; d.ks_pos = ep; d.ks_neg = em;
-      int rc = q.add(d);
+      int rc;
+      if (sparse(c)) {
+        rc = xq.add(expv_desc(c, c.ULt[s], nul, n, -1.0, row, ep, em, true));
+      } else {
+        GemmDesc d = gemm_desc(c.K, c.N, c.ULt[s], n, nul, n, c.N, n, c.N);
+        d.ks_field = row; d.ks_pos = ep; d.ks_neg = em;
+        rc = q.add(d);
+      }
       if (rc) return rc;
       c.ULt[s] = nul;
       if (with_R) {
         double *nur = other(c.UR[s], c.URw[s]);
-        GemmDesc e = gemm_desc(c.Kinv, c.N, c.UR[s], n, nur, n, c.N, n, c.N);
-        e.ks_field = row; e.ks_pos = em; e.ks_neg = ep;
-        rc = q.add(e);
+        if (sparse(c)) {
+          rc = xq.add(expv_desc(c, c.UR[s], nur, n, +1.0, row, em, ep, true));
+        } else {
+          GemmDesc e = gemm_desc(c.Kinv, c.N, c.UR[s], n, nur, n, c.N, n, c.N);
+          e.ks_field = row; e.ks_pos = em; e.ks_neg = ep;
+          rc = q.add(e);
+        }
         if (rc) return rc;
         c.UR[s] = nur;
       }
     }
   }
   int rc = q.flush();
+  if (!rc) rc = xq.flush();
   for (int i = 0; i < b.n && !rc && with_R; ++i)
     if (gform(b[i])) rc = wrap_G(b[i], l, false);
   return rc;
@@ -619,6 +690,56 @@ int build_state(const Walkers &b) {
     b[i].position = 0;
     b[i].windowed = false;
   }
+  return PQMC_OK;
+}
+
+// Sparse propagation set-up: H0 qualifies when it has at most kExpMaxW
+// nonzeros in every row, N <= kExpMaxN and ||dtau H0||_1 <= 1.  Its rows go
+// to the workspace as ELL (zero-padded), and the Taylor degree J is the
+// smallest for which the first dropped term, ||dtau H0||_1^(J+1) / (J+1)!,
+// is at most 2^-60 (J = 13 at ||dtau H0||_1 = 0.2).
+int setup_sparse(pqmc_ctx &c, const double *H, double norm1) {
+  const int N = c.N;
+  c.sparse_prop = false;
+  int w = 0;
+  for (int i = 0; i < N; ++i) {
+    int nz = 0;
+    for (int j = 0; j < N; ++j) nz += H[(size_t)i * N + j] != 0.0;
+    w = std::max(w, nz);
+  }
+  if (w > kExpMaxW || N > kExpMaxN || !(norm1 <= 1.0)) return PQMC_OK;
+  w = std::max(w, 1);
+  std::vector<int> idx((size_t)N * w);
+  std::vector<double> val((size_t)N * w);
+  for (int i = 0; i < N; ++i) {
+    int m = 0;
+    for (int j = 0; j < N; ++j)
+      if (H[(size_t)i * N + j] != 0.0) {
+        idx[(size_t)i * w + m] = j;
+        val[(size_t)i * w + m] = H[(size_t)i * N + j];
+        ++m;
+      }
+    for (; m < w; ++m) {
+      idx[(size_t)i * w + m] = i;
+      val[(size_t)i * w + m] = 0.0;
+    }
+  }
+  int J = 0;
+  double term = 1.0;   // norm1^J / J!
+  while (norm1 > 0.0 && term * norm1 / (J + 1) > std::ldexp(1.0, -60)) {
+    ++J;
+    term *= norm1 / J;
+  }
+  hipError_t e = hipMemcpyAsync(c.ell_idx, idx.data(), sizeof(int) * idx.size(),
+                                hipMemcpyHostToDevice, c.st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c.ell_val, val.data(), sizeof(double) * val.size(),
+                       hipMemcpyHostToDevice, c.st);
+  if (e == hipSuccess) e = hipStreamSynchronize(c.st);   // the host vectors go away
+  if (e != hipSuccess) return fail_device(e, "upload H0 rows", __FILE__, __LINE__);
+  c.ell_w = w;
+  c.taylor_J = J;
+  c.sparse_prop = true;
   return PQMC_OK;
 }
 
@@ -996,7 +1117,7 @@ int finish_walker(pqmc_ctx &c, const double ph[3], double t_total, pqmc_stats *o
   int rc = sync_check(c);
   if (out) {
     unsigned long long h[16];
-    PQ_HIP_CHECK(hipMemcpy(h, c.stats, sizeof h, hipMemcpyDeviceToHost));
+    PQ_HIP_CHECK(d2h(h, c.stats, sizeof h, c.st));
     std::memset(out, 0, sizeof *out);
     out->proposed = h[kStProposed];
     out->accepted = h[kStAccepted];
@@ -1260,6 +1381,8 @@ pqmc_status pqmc_create(const pqmc_problem *prob, const pqmc_update_opts *opts, 
     norm1 = std::max(norm1, s);
   }
   norm1 *= prob->dtau;
+  rc = setup_sparse(*c, prob->hopping, norm1);
+  if (rc) return fail(rc);
   int sq = 0;
   while (norm1 / std::ldexp(1.0, sq) > 0.5) ++sq;
   const double sc = prob->dtau / std::ldexp(1.0, sq);
@@ -1350,7 +1473,7 @@ pqmc_status pqmc_get_fields(pqmc_ctx *c, int8_t *fields) {
   if (c->cx) return pqmc_soc_get_fields(c->cx, fields);
   hipError_t e = hipStreamSynchronize(c->st);
   if (e == hipSuccess)
-    e = hipMemcpy(fields, c->fields, (size_t)c->M * c->N, hipMemcpyDeviceToHost);
+    e = d2h(fields, c->fields, (size_t)c->M * c->N, c->st);
   if (e != hipSuccess) return as_status(fail_device(e, "download fields", __FILE__, __LINE__));
   return PQMC_OK;
 }
@@ -1563,7 +1686,7 @@ static pqmc_status green_into(pqmc_ctx *c, int spin, double *X, double *Gd, doub
     }
     e = hipStreamSynchronize(c->st);
     if (e == hipSuccess)
-      e = hipMemcpy(out, c->G[spin], sizeof(double) * N * N, hipMemcpyDeviceToHost);
+      e = d2h(out, c->G[spin], sizeof(double) * N * N, c->st);
     if (e != hipSuccess) return as_status(fail_device(e, "green", __FILE__, __LINE__));
     return PQMC_OK;
   }
@@ -1584,7 +1707,7 @@ static pqmc_status green_into(pqmc_ctx *c, int spin, double *X, double *Gd, doub
   b.d[b.count++] = d;
   if (e == hipSuccess) e = gemm(b, false, true, c->st);
   if (e == hipSuccess) e = hipStreamSynchronize(c->st);
-  if (e == hipSuccess) e = hipMemcpy(out, Gd, sizeof(double) * N * N, hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = d2h(out, Gd, sizeof(double) * N * N, c->st);
   if (e != hipSuccess) return as_status(fail_device(e, "green", __FILE__, __LINE__));
   return PQMC_OK;
 }
@@ -1619,9 +1742,9 @@ static pqmc_status copy_log(pqmc_ctx *c, const int32_t *dmeta, const double *dma
   const size_t m = std::min(cnt, cap);
   hipError_t e = hipStreamSynchronize(c->st);
   if (e == hipSuccess && m && meta)
-    e = hipMemcpy(meta, dmeta, 3 * sizeof(int32_t) * m, hipMemcpyDeviceToHost);
+    e = d2h(meta, dmeta, 3 * sizeof(int32_t) * m, c->st);
   if (e == hipSuccess && m && margin)
-    e = hipMemcpy(margin, dmargin, sizeof(double) * m, hipMemcpyDeviceToHost);
+    e = d2h(margin, dmargin, sizeof(double) * m, c->st);
   if (e != hipSuccess) return as_status(fail_device(e, "log copy", __FILE__, __LINE__));
   return PQMC_OK;
 }

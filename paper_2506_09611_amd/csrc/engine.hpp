@@ -43,6 +43,35 @@ GemmDesc gemm_desc(const double *A, long lda, const double *B, long ldb, double 
                    const double *Cin = nullptr, long ldcin = 0);
 hipError_t gemm(const GemmBatch &b, bool transA, bool transB, hipStream_t st);
 
+// ------------------------------------------------------- sparse propagation
+// Y = rs * e^{a H0} (ks * X) for an N x n row-major X (leading dim ldx), H0
+// given as ELL rows of w (column, value) pairs (zero-padded), the Taylor
+// series of degree J in Horner form; the field diagonal (x > 0 -> pos, else
+// neg) scales X's rows first when pre, Y's rows last otherwise (none when
+// field is null).  X and Y must not overlap.
+struct ExpvDesc {
+  const double *X;
+  long ldx;
+  double *Y;
+  long ldy;
+  int N, n;
+  const int *idx;
+  const double *val;
+  int w, J;
+  double a;
+  const int8_t *field;
+  double pos, neg;
+  int pre;
+};
+constexpr int kExpvMaxBatch = 16;
+constexpr int kExpMaxN = 4096;   // LDS: two iterates of N x 2 doubles
+constexpr int kExpMaxW = 8;      // nonzeros per row of H0
+struct ExpvBatch {
+  ExpvDesc d[kExpvMaxBatch];
+  int count;
+};
+hipError_t expv(const ExpvBatch &b, hipStream_t st);
+
 // ------------------------------------------------------------- dense LA
 constexpr int kNB = 32;   // panel width of the blocked eliminations
 struct ElimSpin {
@@ -88,6 +117,16 @@ hipError_t max_abs_diff(const double *const *a, const double *const *b, const lo
 // (blockIdx.z, or blockIdx.x for the single-workgroup decision kernels), so
 // kMaxBatch independent walkers of the same shape share each launch.
 constexpr int kMaxBatch = 8;
+// Device-to-host copy on the caller's own stream, waited for.  Copies are
+// never made on the legacy (null) stream: another thread of the process may be
+// capturing a graph on a blocking stream, which a legacy-stream copy would
+// have to wait for.
+inline hipError_t d2h(void *dst, const void *src, size_t bytes, hipStream_t st) {
+  hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  return e;
+}
+
 template <class T>
 struct Batch {
   T w[kMaxBatch];

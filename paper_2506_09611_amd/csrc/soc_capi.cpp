@@ -454,7 +454,7 @@ int begin_call(pqmc_soc_ctx &c) {
 int finish_call(pqmc_soc_ctx &c, double t0, pqmc_stats *out) {
   PQ_HIP_CHECK(hipStreamSynchronize(c.st));
   unsigned long long h[16];
-  PQ_HIP_CHECK(hipMemcpy(h, c.stats, sizeof h, hipMemcpyDeviceToHost));
+  PQ_HIP_CHECK(d2h(h, c.stats, sizeof h, c.st));
   if (h[kStError] & kErrSingular) {
     c.failed = true;
     return api_error(PQMC_ESINGULAR, "a stabilisation factorisation broke down");
@@ -486,7 +486,7 @@ int finish_call(pqmc_soc_ctx &c, double t0, pqmc_stats *out) {
 int sync_check(pqmc_soc_ctx &c) {
   PQ_HIP_CHECK(hipStreamSynchronize(c.st));
   unsigned long long h[16];
-  PQ_HIP_CHECK(hipMemcpy(h, c.stats, sizeof h, hipMemcpyDeviceToHost));
+  PQ_HIP_CHECK(d2h(h, c.stats, sizeof h, c.st));
   if (h[kStError] & kErrSingular)
     return api_error(PQMC_ESINGULAR, "a factorisation broke down while building the state");
   return PQMC_OK;

@@ -127,3 +127,29 @@ def test_graph_fp32_form_mixed_batch():
         _same(ga, gb, "fp32 mixed batch")
     for ch in ga + gb:
         ch.close()
+
+
+def test_graph_multi_stream_captures_concurrently():
+    """Six batches on six streams captured at once by the multi-stream sweep's
+    threads (their captures overlap each other's copies and launches), two
+    sweeps, bitwise against the same walkers launched."""
+    import torch
+    from paper_2506_09611_amd import Scheme, multi_sweep
+    probs = []
+    for i in range(12):
+        L, n = [(4, 5), (6, 13)][i % 2]
+        q = synth.make_problem(L, n, n, 4.0, n_slices=20, stab_every=5, perturb=1e-3,
+                               seed=synth.SEED_BASE + 93)
+        probs.append(dataclasses.replace(q, walker_id=i))
+    sa = [torch.cuda.Stream() for _ in range(6)]
+    sb = [torch.cuda.Stream() for _ in range(6)]
+    ga = [make_chain(q, "delayed", k=4, stream=sa[i // 2]) for i, q in enumerate(probs)]
+    gb = [make_chain(q, "delayed", k=4, stream=sb[i // 2]) for i, q in enumerate(probs)]
+    for ch in ga:
+        ch.set_opts(Scheme.DELAYED, k=4, graph=True)
+    for sw in range(2):
+        multi_sweep(ga, 1)
+        multi_sweep(gb, 1)
+        _same(ga, gb, f"multi-stream sweep {sw}")
+    for ch in ga + gb:
+        ch.close()
