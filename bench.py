@@ -42,13 +42,35 @@ def make_chain(p, scheme, k=1, b=1, timing=True, fp32=False):
                  tile_chunks=64)
 
 
+def sparse_propagation(p):
+    """(J, nnz) when the library propagates this problem with the Taylor
+    series of the sparse H0 (at most 8 nonzeros per row, N <= 4096,
+    ||dtau H0||_1 <= 1; J: the degree whose first dropped term is below
+    2^-60), else None."""
+    import numpy as np
+    H = p.hopping
+    w = int(max(np.count_nonzero(H[i]) for i in range(H.shape[0])))
+    norm1 = p.dtau * float(np.max(np.sum(np.abs(H), axis=0)))
+    if w > 8 or H.shape[0] > 4096 or norm1 > 1.0:
+        return None
+    J, term = 0, 1.0
+    while norm1 > 0.0 and term * norm1 / (J + 1) > 2.0 ** -60:
+        J += 1
+        term *= norm1 / J
+    return J, int(np.count_nonzero(H))
+
+
 def kernel_work(p, cls, scheme, k, b, acc):
     """Algorithmic work of one launch of a kernel class: (flops, bytes, bound).
     Two spin sectors; Ns = N_sigma; T is Ns x Ns; U_R, U_L^T are N x Ns."""
     N, Ns = p.n_sites, p.n_up
     kk = k if scheme == "delayed" else b
     n_a = acc * kk
-    if cls == "propagate":     # U_R and U_L^T: 2 spins x 2 products of N x N by N x Ns
+    if cls == "propagate":     # U_R and U_L^T: 2 spins x 2 products by e^{-+dtau H0}
+        sp = sparse_propagation(p)
+        if sp is not None:     # Taylor series of the sparse H0: read X, write Y once
+            J, nnz = sp
+            return 2 * 2 * 2.0 * J * nnz * Ns, 2 * 2 * 2 * N * Ns * 8.0, "hbm"
         return 8.0 * N * N * Ns, 2 * 2 * (N * N + 2 * N * Ns) * 8.0, "mfma"
     if cls == "tile":          # flush T -= Q P2_A (rank n_A) + panels U_g T, T L_g
         return 2 * (2.0 * Ns * Ns * n_a + 4.0 * Ns * Ns * kk), 2 * 2 * Ns * Ns * 8.0, "mfma"
@@ -58,6 +80,8 @@ def kernel_work(p, cls, scheme, k, b, acc):
     if cls == "decide":        # kk x kk pivot sweeps, and the P2 (nt) and P1 (2) partial sums
         return (2 * 2.0 * n_a * kk * kk + 2 * (nt + 2) * kk * Ns,
                 2 * ((nt + 2) * kk * Ns + 2 * kk * Ns + kk * kk) * 8.0, "alu")
+    if cls == "local" and scheme == "local_g":   # read G, rank-1 write when accepted
+        return 2 * 2.0 * acc * N * N, 2 * (1.0 + acc) * N * N * 8.0, "hbm"
     if cls == "local":         # read T (partials of y, Tv), rank-1 write when accepted
         return 2 * (2.0 + 4.0 * acc) * Ns * Ns, 2 * (1.0 + acc) * Ns * Ns * 8.0, "hbm"
     raise KeyError(cls)
@@ -118,7 +142,8 @@ def make_walkers(p, scheme, k, b, W, streams, fp32=False, tile_chunks=0):
     continue across streams): one lockstep batch per stream."""
     import dataclasses
     from paper_2506_09611_amd import Chain, Scheme
-    sc = {"local": Scheme.LOCAL, "delayed": Scheme.DELAYED, "block": Scheme.BLOCK_FB}[scheme]
+    sc = {"local": Scheme.LOCAL, "local_g": Scheme.LOCAL_G, "delayed": Scheme.DELAYED,
+          "block": Scheme.BLOCK_FB}[scheme]
     out = []
     for si, st in enumerate(streams):
         for w in range(W):
@@ -469,6 +494,9 @@ def serve_leg(args, rate):
         "arrival_rate_jobs_per_s": rate,
         "field_updates_per_s": fu / rep.makespan_s if rep.makespan_s > 0 else None,
         "soc_jobs": sum(j.soc for j in jobs),
+        "scale": f"{args.serve_jobs} of the 512 jobs of the full mix, M={args.serve_slices} "
+                 f"of 400 (2 Theta = {args.serve_slices * 0.05:g} of 20), "
+                 f"{args.serve_walkers} of 16 walkers per job",
         "mix": f"L in {{{args.serve_sizes}}} uniform, U/t in {{2,4,8}}, half filling; a "
                f"fraction {args.serve_soc} of the jobs Rashba (lambda/t = 0.5, U/t in "
                f"{{-2,-4,-8}}, n = 1, delayed k = 16), "
@@ -485,7 +513,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--scheme", default="delayed", choices=["local", "delayed", "block"])
+    ap.add_argument("--scheme", default="delayed", choices=["local", "local_g", "delayed", "block"])
     ap.add_argument("--k", type=int, default=32, help="delay rank (0: the autotuner's choice)")
     ap.add_argument("--b", type=int, default=16)
     ap.add_argument("--workload", default="c3")
@@ -530,17 +558,17 @@ def main():
                     help="forward slice visits per SOC table entry (also k_tau)")
     ap.add_argument("--serve-jobs", type=int, default=32,
                     help="jobs of the serving leg (0 = skip it)")
-    ap.add_argument("--serve-rate", default="8,64",
+    ap.add_argument("--serve-rate", default="1,16",
                     help="Poisson arrival rates, jobs/s, one serving run each (comma list)")
-    ap.add_argument("--serve-sizes", default="8,12,16,24", help="lattice sides L of the mix")
-    ap.add_argument("--serve-walkers", type=int, default=4)
+    ap.add_argument("--serve-sizes", default="8,12,16,24,32", help="lattice sides L of the mix")
+    ap.add_argument("--serve-walkers", type=int, default=16)
     ap.add_argument("--serve-soc", type=float, default=0.5,
                     help="fraction of serving jobs on the Rashba SOC model")
-    ap.add_argument("--serve-lanes", type=int, default=2,
+    ap.add_argument("--serve-lanes", type=int, default=4,
                     help="concurrent batches per serving step, one HIP stream each")
     ap.add_argument("--serve-sweeps", type=int, default=1)
-    ap.add_argument("--serve-slices", type=int, default=40, help="M of the serving jobs")
-    ap.add_argument("--serve-budget-gb", type=float, default=8.0,
+    ap.add_argument("--serve-slices", type=int, default=20, help="M of the serving jobs")
+    ap.add_argument("--serve-budget-gb", type=float, default=64.0,
                     help="HBM budget of the admitted walkers (0 = 90%% of free memory)")
     ap.add_argument("--tile-chunks", type=int, default=0,
                     help="column chunks per row strip of the flush kernel for the batched "

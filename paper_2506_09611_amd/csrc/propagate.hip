@@ -26,7 +26,11 @@ constexpr int kExpThreads = 512;
 template <int R, int WD>
 __global__ __launch_bounds__(kExpThreads) void expv_kernel(ExpvBatch B) {
   const ExpvDesc &d = B.d[blockIdx.y];
-  const int N = d.N, n = d.n, c0 = 2 * (int)blockIdx.x;
+  // XCD-aware: consecutive workgroup ids go round-robin to the 8 XCDs, so
+  // XCD x takes the contiguous range [x per, (x + 1) per) of column pairs;
+  // the pairs that share a cache line of X and Y then share one L2
+  const int per = gridDim.x >> 3;   // the grid is a multiple of 8
+  const int N = d.N, n = d.n, c0 = 2 * ((int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3));
   if (c0 >= n) return;
   const bool two = c0 + 1 < n;
   extern __shared__ double zs[];
@@ -110,8 +114,9 @@ hipError_t launch_expv(const ExpvBatch &b, int nmax, int Nmax, hipStream_t st) {
         (int)(sizeof(double) * 4 * kExpMaxN));
     if (attr != hipSuccess) return attr;
   }
-  hipLaunchKernelGGL((expv_kernel<R, WD>), dim3((nmax + 1) / 2, b.count), dim3(kExpThreads), lds,
-                     st, b);
+  const int pairs = (nmax + 1) / 2;
+  hipLaunchKernelGGL((expv_kernel<R, WD>), dim3((pairs + 7) / 8 * 8, b.count), dim3(kExpThreads),
+                     lds, st, b);
   return hipGetLastError();
 }
 

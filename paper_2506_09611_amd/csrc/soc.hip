@@ -4,7 +4,8 @@
 //
 // Kernels:
 //   cgemm_kernel     C = alpha op(A) op(B) + beta Cin (+ I), op in {N, T, H},
-//                    64 x 64 complex tiles through LDS, up to 8 products per launch
+//                    64 x 64 complex tiles through LDS on FP64 MFMA, up to 8
+//                    products per launch
 //   rotate_kernel    rows (i, N+i) of an n2 x ncols matrix mixed by A(s x_i)
 //   chol_step_kernel S = R^H R (upper R) of a Hermitian positive definite S,
 //                    one launch per pivot row, chol_final_kernel scales the rows
@@ -19,6 +20,7 @@
 #include <math.h>
 #include "common.hpp"
 #include "soc.hpp"
+#include "mfma.hpp"
 
 namespace pq {
 namespace soc {
@@ -81,14 +83,26 @@ __global__ __launch_bounds__(256) void cgemm_kernel(CgemmBatch b, int ns) {
   // the conjugation and the zeroing of the depth tail are applied when the
   // slice is stored.  Rows and columns past M and N only reach outputs that
   // are not stored.
+  //
+  // The products run on FP64 MFMA (16 x 16 x 4): wave w owns the 32 x 32
+  // quadrant (w / 2, w % 2) of the 64 x 64 tile as 2 x 2 blocks, each with a
+  // real and an imaginary accumulator; per depth step of 4 a block takes
+  // four MFMAs, re += a_re b_re - a_im b_im and im += a_re b_im + a_im b_re,
+  // with a and b read from LDS as complex pairs in the A and B operand
+  // layouts (lane l: row l % 16, depth l / 16; depth l / 16, column l % 16).
   __shared__ double2 As[2][BK][BM];
   __shared__ double2 Bs[2][BK][BN];
-  const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
-  double2 acc[4][4];
+  const int t = threadIdx.x;
+  const int lane = t & 63, wave = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int wm = wave >> 1, wn = wave & 1, li = lane & 15, lk = lane >> 4;
+  dbl4 accR[2][2], accI[2][2];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = make_double2(0.0, 0.0);
+    for (int j = 0; j < 2; ++j) {
+      accR[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+      accI[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+    }
   double2 ra[4], rb[4];
   auto a_index = [&](int p, int &r, int &kk) {
     const int e = t + 256 * p;
@@ -131,47 +145,47 @@ __global__ __launch_bounds__(256) void cgemm_kernel(CgemmBatch b, int ns) {
   for (int k0 = kbeg; k0 < kend; k0 += BK) {
     const bool more = k0 + BK < kend;
     if (more) load(k0 + BK);
-#pragma unroll 4
-    for (int kk = 0; kk < BK; ++kk) {
-      double2 a[4], bb[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = As[buf][kk][ty + 16 * i];
+    for (int q = 0; q < BK; q += 4) {
+      double2 a[2], bb[2];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) bb[j] = Bs[buf][kk][tx + 16 * j];
+      for (int i = 0; i < 2; ++i) a[i] = As[buf][q + lk][wm * 32 + 16 * i + li];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 2; ++j) bb[j] = Bs[buf][q + lk][wn * 32 + 16 * j + li];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) cfma(acc[i][j], a[i], bb[j]);
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          accR[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].x, bb[j].x, accR[i][j], 0, 0, 0);
+          accR[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[i].y, bb[j].y, accR[i][j], 0, 0, 0);
+          accI[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].x, bb[j].y, accI[i][j], 0, 0, 0);
+          accI[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i].y, bb[j].x, accI[i][j], 0, 0, 0);
+        }
     }
     // the other buffer was last read before the previous barrier
     if (more) store(buf ^ 1, k0 + BK);
     __syncthreads();
     buf ^= 1;
   }
-  if (g.ksplit > 0) {
-    double2 *C = g.C + (long)split * g.csplit;
+  // register e of lane l holds element (l / 16 + 4 e, l % 16) of a block
+  double2 *C = g.ksplit > 0 ? g.C + (long)split * g.csplit : g.C;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int r = m0 + ty + 16 * i, c = n0 + tx + 16 * j;
-        if (r < M && c < N) C[(long)r * g.ldc + c] = acc[i][j];
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = m0 + wm * 32 + 16 * i + lk + 4 * e, c = n0 + wn * 32 + 16 * j + li;
+        if (r >= M || c >= N) continue;
+        double2 v = make_double2(accR[i][j][e], accI[i][j][e]);
+        if (g.ksplit <= 0) {
+          v = cmul(g.alpha, v);
+          if (g.Cin && (g.beta.x != 0.0 || g.beta.y != 0.0))
+            v = cadd(v, cmul(g.beta, g.Cin[(long)r * g.ldcin + c]));
+          if (g.addI && r == c) v.x += 1.0;
+        }
+        C[(long)r * g.ldc + c] = v;
       }
-    return;
-  }
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int r = m0 + ty + 16 * i, c = n0 + tx + 16 * j;
-      if (r < M && c < N) {
-        double2 v = cmul(g.alpha, acc[i][j]);
-        if (g.Cin && (g.beta.x != 0.0 || g.beta.y != 0.0))
-          v = cadd(v, cmul(g.beta, g.Cin[(long)r * g.ldcin + c]));
-        if (g.addI && r == c) v.x += 1.0;
-        g.C[(long)r * g.ldc + c] = v;
-      }
-    }
 }
 
 __global__ __launch_bounds__(256) void csum_kernel(CsumBatch b) {
