@@ -222,7 +222,7 @@ def _oracle_forward(q, scheme, k, b, visits):
 
 
 def cpu_baseline(p, scheme, k, b, visits=20, one_core_visits=4):
-    """The oracle timed on the host cores (SURVEY-style CPU baseline):
+    """The oracle timed on the host cores:
       * the 40x40 workload: `visits` forward slice visits of the headline
         scheme (two stabilisations at k_tau = 10) on all cores, and
         `one_core_visits` on one BLAS thread; a sweep is 2 M = 800 visits, so
