@@ -374,6 +374,17 @@ pqmc_status pqmc_soc_sweep(pqmc_soc_ctx *ctx, int32_t n_sweeps, pqmc_stats *out)
  * further sweeps. */
 pqmc_status pqmc_soc_forward_window(pqmc_soc_ctx *ctx, int32_t n_slices, pqmc_stats *out);
 
+/* pqmc_soc_sweep / pqmc_soc_forward_window for a batch of n <= 8 walkers
+ * (Appendix A model, independent Markov chains) in lockstep: every launch
+ * (complex GEMMs, decisions, eliminations) serves all of them.  The walkers
+ * need the same lattice, N_e, M, k_tau, scheme, k (or b) and stream; each
+ * takes exactly the decisions and reaches the G it reaches alone.  out: n
+ * entries or NULL.  Errors mark every walker of the batch failed. */
+pqmc_status pqmc_soc_batch_sweep(pqmc_soc_ctx *const *ctxs, int32_t n, int32_t n_sweeps,
+                                 pqmc_stats *out);
+pqmc_status pqmc_soc_batch_forward_window(pqmc_soc_ctx *const *ctxs, int32_t n,
+                                          int32_t n_slices, pqmc_stats *out);
+
 /* G = 1 - U_R T U_L at the current position, 2N x 2N complex128 row-major
  * interleaved, to host memory. */
 pqmc_status pqmc_soc_get_green(pqmc_soc_ctx *ctx, double *out);

@@ -7,8 +7,9 @@ importing `Chain` without the built library raises ImportError.
 """
 from .binding import (Chain, Scheme, PQMCError, load_library, library_path,  # noqa: F401
                       EXPORTED_SYMBOLS, MAX_BATCH, batch_sweep, batch_forward_window,
-                      multi_sweep, workspace_bytes, SocChain, soc_workspace_bytes)
+                      multi_sweep, workspace_bytes, SocChain, soc_workspace_bytes,
+                      soc_batch_sweep, soc_batch_forward_window)
 
 __all__ = ["Chain", "Scheme", "PQMCError", "load_library", "library_path", "EXPORTED_SYMBOLS",
            "MAX_BATCH", "batch_sweep", "batch_forward_window", "multi_sweep", "workspace_bytes", "SocChain",
-           "soc_workspace_bytes"]
+           "soc_workspace_bytes", "soc_batch_sweep", "soc_batch_forward_window"]

@@ -24,6 +24,7 @@ EXPORTED_SYMBOLS = (
     "pqmc_last_error",
     "pqmc_soc_workspace_bytes", "pqmc_soc_create", "pqmc_soc_sweep", "pqmc_soc_forward_window",
     "pqmc_soc_get_green", "pqmc_soc_get_fields", "pqmc_soc_get_decisions", "pqmc_soc_destroy",
+    "pqmc_soc_batch_sweep", "pqmc_soc_batch_forward_window",
 )
 KERNEL_CLASSES = ("propagate", "local", "tile", "reduce", "decide")
 
@@ -141,6 +142,10 @@ def load_library():
                                    ctypes.POINTER(ctypes.c_double), c_size_t,
                                    ctypes.POINTER(c_size_t)],
         "pqmc_soc_destroy": [c_void_p],
+        "pqmc_soc_batch_sweep": [ctypes.POINTER(c_void_p), ctypes.c_int32, ctypes.c_int32,
+                                 ctypes.POINTER(Stats)],
+        "pqmc_soc_batch_forward_window": [ctypes.POINTER(c_void_p), ctypes.c_int32,
+                                          ctypes.c_int32, ctypes.POINTER(Stats)],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -476,3 +481,16 @@ def multi_sweep(chains, n=1):
 def batch_forward_window(chains, n_slices):
     """pqmc_batch_forward_window for up to 8 chains (rules of batch_sweep)."""
     return _batch_call(chains, lambda lib: lib.pqmc_batch_forward_window, n_slices)
+
+
+def soc_batch_sweep(chains, n=1):
+    """pqmc_soc_batch_sweep: n sweeps of up to 8 SocChains of one lattice,
+    N_e, M, k_tau, scheme, k and stream in lockstep (one launch per kernel for
+    all of them).  Returns one stats dict per chain."""
+    return _batch_call(chains, lambda lib: lib.pqmc_soc_batch_sweep, n)
+
+
+def soc_batch_forward_window(chains, n_slices):
+    """pqmc_soc_batch_forward_window for up to 8 SocChains (rules of
+    soc_batch_sweep)."""
+    return _batch_call(chains, lambda lib: lib.pqmc_soc_batch_forward_window, n_slices)

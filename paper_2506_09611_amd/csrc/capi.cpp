@@ -1216,6 +1216,31 @@ pqmc_status check_batch(pqmc_ctx *const *w, int n) {
 
 pqmc_status as_status(int rc) { return (pqmc_status)rc; }
 
+// U < 0 walkers of a batch: the one-sector engine batches walkers of the
+// same size, scheme and k; the others form batches of their own (in order of
+// first appearance), run one after the other.
+pqmc_status run_one_sector(pqmc_ctx *const *ctxs, int n, int n_sweeps, int n_slices,
+                           pqmc_stats *out) {
+  std::vector<bool> done(n, false);
+  for (int i = 0; i < n; ++i) {
+    if (done[i]) continue;
+    pqmc_soc_ctx *grp[kMaxBatch];
+    int pos[kMaxBatch], m = 0;
+    for (int j = i; j < n; ++j)
+      if (!done[j] && pq::soc::batch_compatible(ctxs[j]->cx, ctxs[i]->cx)) {
+        grp[m] = ctxs[j]->cx;
+        pos[m++] = j;
+        done[j] = true;
+      }
+    pqmc_stats st[kMaxBatch];
+    const pqmc_status v = pq::soc::batch_run(grp, m, n_sweeps, n_slices, out ? st : nullptr);
+    if (v) return v;
+    if (out)
+      for (int j = 0; j < m; ++j) out[pos[j]] = st[j];
+  }
+  return PQMC_OK;
+}
+
 void drop_graph(pqmc_ctx &c) {
   if (c.gexec) (void)hipGraphExecDestroy(c.gexec);
   if (c.graph) (void)hipGraphDestroy(c.graph);
@@ -1483,13 +1508,7 @@ pqmc_status pqmc_batch_sweep(pqmc_ctx *const *ctxs, int32_t n, int32_t n_sweeps,
   pqmc_status v = check_batch(ctxs, n);
   if (v) return v;
   if (n_sweeps < 0) return set_error(PQMC_EINVAL, "n_sweeps < 0");
-  if (ctxs[0]->cx) {   // U < 0: one walker after the other
-    for (int i = 0; i < n; ++i) {
-      v = pqmc_soc_sweep(ctxs[i]->cx, n_sweeps, out ? out + i : nullptr);
-      if (v) return v;
-    }
-    return PQMC_OK;
-  }
+  if (ctxs[0]->cx) return run_one_sector(ctxs, n, n_sweeps, -1, out);
   for (int i = 0; i < n; ++i)
     if (ctxs[i]->windowed || ctxs[i]->position != 0)
       return set_error(PQMC_ESTATE, "walker is mid-sweep after pqmc_forward_window");
@@ -1639,13 +1658,7 @@ pqmc_status pqmc_batch_forward_window(pqmc_ctx *const *ctxs, int32_t n, int32_t 
   pqmc_status v = check_batch(ctxs, n);
   if (v) return v;
   if (n_slices < 0 || n_slices > ctxs[0]->M) return set_error(PQMC_EINVAL, "n_slices out of range");
-  if (ctxs[0]->cx) {   // U < 0: one walker after the other
-    for (int i = 0; i < n; ++i) {
-      v = pqmc_soc_forward_window(ctxs[i]->cx, n_slices, out ? out + i : nullptr);
-      if (v) return v;
-    }
-    return PQMC_OK;
-  }
+  if (ctxs[0]->cx) return run_one_sector(ctxs, n, 0, n_slices, out);
   for (int i = 0; i < n; ++i)
     if (ctxs[i]->windowed || ctxs[i]->position != 0)
       return set_error(PQMC_ESTATE, "walker is mid-sweep");

@@ -236,8 +236,9 @@ __global__ __launch_bounds__(256) void ident_kernel(double2 *E, long ld, int n, 
 // from the upper triangle of rows r > j, U being the partially eliminated
 // upper triangle; chol_final_kernel then divides row r by sqrt(U_rr) and
 // zeroes the strict lower triangle.  One wave per row, lanes along it.
-__global__ __launch_bounds__(256) void chol_step_kernel(double2 *S, long ld, int n, int j,
-                                                        unsigned long long *stats) {
+__global__ __launch_bounds__(256) void chol_step_kernel(SocElimBatch B, long ld, int n, int j) {
+  double2 *S = B.E[blockIdx.y];   // one grid row per walker
+  unsigned long long *stats = B.stats[blockIdx.y];
   const double2 piv = S[(long)j * ld + j];
   if (!(piv.x > 0.0) || !isfinite(piv.x)) {
     if (blockIdx.x == 0 && threadIdx.x == 0) stats[kStError] |= kErrSingular;
@@ -254,8 +255,9 @@ __global__ __launch_bounds__(256) void chol_step_kernel(double2 *S, long ld, int
   for (int c = r + lane; c < n; c += 64) rowr[c] = csub(rowr[c], cmul(a, rowj[c]));
 }
 
-__global__ __launch_bounds__(256) void chol_final_kernel(double2 *S, long ld, int n,
-                                                         unsigned long long *stats) {
+__global__ __launch_bounds__(256) void chol_final_kernel(SocElimBatch B, long ld, int n) {
+  double2 *S = B.E[blockIdx.y];
+  unsigned long long *stats = B.stats[blockIdx.y];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r = blockIdx.x * 4 + wave;
   if (r >= n) return;
@@ -280,9 +282,11 @@ __global__ __launch_bounds__(256) void chol_final_kernel(double2 *S, long ld, in
 // as this step leaves it, to colout for the next step.  Columns left of j
 // are unit vectors already and are skipped.
 constexpr int kGjCols = 8;    // columns per workgroup (256 threads: 32 row groups)
-__global__ __launch_bounds__(256) void gj_step_kernel(double2 *E, long ld, int n, int j,
-                                                      const double2 *colin, double2 *colout,
-                                                      unsigned long long *stats) {
+__global__ __launch_bounds__(256) void gj_step_kernel(SocElimBatch B, long ld, int n, int j) {
+  double2 *E = B.E[blockIdx.y];   // one grid row per walker
+  const double2 *colin = B.col[blockIdx.y] + (size_t)(j & 1) * n;
+  double2 *colout = B.col[blockIdx.y] + (size_t)((j + 1) & 1) * n;
+  unsigned long long *stats = B.stats[blockIdx.y];
   __shared__ double2 col[1024];
   __shared__ double wbest[4];
   __shared__ int wbi[4];
@@ -344,8 +348,9 @@ __global__ __launch_bounds__(256) void gj_step_kernel(double2 *E, long ld, int n
 }
 
 // colout[r] = E[r][0]
-__global__ __launch_bounds__(256) void col0_kernel(const double2 *E, long ld, int n,
-                                                   double2 *colout) {
+__global__ __launch_bounds__(256) void col0_kernel(SocElimBatch B, long ld, int n) {
+  const double2 *E = B.E[blockIdx.y];
+  double2 *colout = B.col[blockIdx.y];
   const int r = blockIdx.x * 256 + threadIdx.x;
   if (r < n) colout[r] = E[(long)r * ld];
 }
@@ -360,7 +365,8 @@ __global__ __launch_bounds__(256) void col0_kernel(const double2 *E, long ld, in
 // their rows of U_R rotated by A(-2x) = 1 + delta.
 constexpr int kDecThreads = 256;
 
-__global__ __launch_bounds__(kDecThreads) void soc_decide_kernel(SocDecideArgs a) {
+__global__ __launch_bounds__(kDecThreads) void soc_decide_kernel(SocDecideBatch B) {
+  const SocDecideArgs &a = B.a[blockIdx.x];   // one workgroup per walker
   extern __shared__ double2 lds[];
   const int kk = a.kk, n = 2 * kk;
   // rows padded by one element: lanes walking down a column hit distinct banks
@@ -610,7 +616,8 @@ __device__ void gj_lds(double2 *A, int n, int ncols, int ld, double2 *det, int *
 // prior = prod_F e^{2 s_j x_j}; accept iff u < |R prior| (u at site g0).
 // Out: D = delta_F (1 + W0p_FF delta_F)^{-1} spread to n x n, *nflush,
 // fields and U_R row pairs of F when accepted.
-__global__ __launch_bounds__(kDecThreads) void soc_block_decide_kernel(SocDecideArgs a) {
+__global__ __launch_bounds__(kDecThreads) void soc_block_decide_kernel(SocDecideBatch B) {
+  const SocDecideArgs &a = B.a[blockIdx.x];   // one workgroup per walker
   extern __shared__ double2 lds[];
   const int kk = a.kk, n = 2 * kk;
   const int ld = 2 * n + 1;
@@ -781,7 +788,8 @@ __device__ __forceinline__ double2 flip_delta(const SocDecideArgs &a, double x) 
 // r = 1 + W0_jj - W0_j,: Mc W0_:,j (the recursion of Eq. (28)) and the test
 // is u < |r|^2; accepting j borders Mc by one row and column.  Out: D =
 // diag(delta) Mc, so that T = T0 - (T0 U_L[:, g]) D (U_g T0) (Eq. (30)).
-__global__ __launch_bounds__(kDecThreads) void cplx_decide_kernel(SocDecideArgs a) {
+__global__ __launch_bounds__(kDecThreads) void cplx_decide_kernel(SocDecideBatch B) {
+  const SocDecideArgs &a = B.a[blockIdx.x];   // one workgroup per walker
   extern __shared__ double2 lds[];
   const int n = a.kk;
   const int ld = n + 1;
@@ -899,7 +907,8 @@ __global__ __launch_bounds__(kDecThreads) void cplx_decide_kernel(SocDecideArgs 
 // = -2 gamma Im nbar_j.  Heat bath, flip set F, r = det(1 + W0p_FF delta_F),
 // prior prod_F e^{2 s_j x_j}, accept iff u < |r|^2 prior.  Out as the
 // rank-two kernel: D = delta_F (1 + W0p_FF delta_F)^{-1} spread to kk x kk.
-__global__ __launch_bounds__(kDecThreads) void cplx_block_decide_kernel(SocDecideArgs a) {
+__global__ __launch_bounds__(kDecThreads) void cplx_block_decide_kernel(SocDecideBatch B) {
+  const SocDecideArgs &a = B.a[blockIdx.x];   // one workgroup per walker
   extern __shared__ double2 lds[];
   const int n = a.kk;
   const int ld = 2 * n + 1;
@@ -1078,39 +1087,48 @@ hipError_t set_identity(double2 *E, long ld, int n, int off, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t cholesky(double2 *S, long ld, int n, unsigned long long *stats, hipStream_t st) {
-  if (n < 1) return hipSuccess;
+hipError_t cholesky(const SocElimBatch &b, long ld, int n, hipStream_t st) {
+  if (n < 1 || b.n < 1) return hipSuccess;
+  if (b.n > kSocMaxBatch) return hipErrorInvalidValue;
   for (int j = 0; j + 1 < n; ++j) {
     const int rows = n - j - 1;
-    hipLaunchKernelGGL(chol_step_kernel, dim3((rows + 3) / 4), dim3(256), 0, st, S, ld, n, j,
-                       stats);
+    hipLaunchKernelGGL(chol_step_kernel, dim3((rows + 3) / 4, b.n), dim3(256), 0, st, b, ld, n, j);
   }
-  hipLaunchKernelGGL(chol_final_kernel, dim3((n + 3) / 4), dim3(256), 0, st, S, ld, n, stats);
+  hipLaunchKernelGGL(chol_final_kernel, dim3((n + 3) / 4, b.n), dim3(256), 0, st, b, ld, n);
   return hipGetLastError();
 }
 
-hipError_t gj_inverse(double2 *E, long ld, int n, double2 *colbuf, unsigned long long *stats,
-                      hipStream_t st) {
-  if (n < 1 || n > 1024) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(col0_kernel, dim3((n + 255) / 256), dim3(256), 0, st, E, ld, n, colbuf);
-  const dim3 grid((2 * n + kGjCols - 1) / kGjCols);
-  for (int j = 0; j < n; ++j) {
-    hipLaunchKernelGGL(gj_step_kernel, grid, dim3(256), 0, st, E, ld, n, j,
-                       colbuf + (size_t)(j & 1) * n, colbuf + (size_t)((j + 1) & 1) * n, stats);
-  }
+hipError_t gj_inverse(const SocElimBatch &b, long ld, int n, hipStream_t st) {
+  if (n < 1 || n > 1024 || b.n < 1 || b.n > kSocMaxBatch) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(col0_kernel, dim3((n + 255) / 256, b.n), dim3(256), 0, st, b, ld, n);
+  const dim3 grid((2 * n + kGjCols - 1) / kGjCols, b.n);
+  for (int j = 0; j < n; ++j)
+    hipLaunchKernelGGL(gj_step_kernel, grid, dim3(256), 0, st, b, ld, n, j);
   return hipGetLastError();
 }
 
-hipError_t block_decide(const SocDecideArgs &a, hipStream_t st) {
-  if (a.kk < 1 || a.kk > kSocMaxK) return hipErrorInvalidValue;
-  const int n = 2 * a.kk;
+namespace {
+// one decision workgroup per walker of the batch (all with the same kk)
+template <class F>
+hipError_t launch_decide(F kernel, const SocDecideArgs *a, int nb, size_t lds, hipStream_t st,
+                         const hipError_t &attr) {
+  if (nb < 1 || nb > kSocMaxBatch) return hipErrorInvalidValue;
+  if (attr != hipSuccess) return attr;
+  SocDecideBatch B{};
+  for (int i = 0; i < nb; ++i) B.a[i] = a[i];
+  hipLaunchKernelGGL(kernel, dim3(nb), dim3(kDecThreads), lds, st, B);
+  return hipGetLastError();
+}
+}  // namespace
+
+hipError_t block_decide(const SocDecideArgs *a, int nb, hipStream_t st) {
+  if (a[0].kk < 1 || a[0].kk > kSocMaxK) return hipErrorInvalidValue;
+  const int n = 2 * a[0].kk;
   const size_t lds = sizeof(double2) * (size_t)n * (2 * n + 1);
   static const hipError_t attr = hipFuncSetAttribute(
       (const void *)soc_block_decide_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
       (int)(sizeof(double2) * 64 * 129));
-  if (attr != hipSuccess) return attr;
-  hipLaunchKernelGGL(soc_block_decide_kernel, dim3(1), dim3(kDecThreads), lds, st, a);
-  return hipGetLastError();
+  return launch_decide(soc_block_decide_kernel, a, nb, lds, st, attr);
 }
 
 hipError_t phase_rows(const double2 *X, long ldx, double2 *Y, long ldy, int ncols, int N,
@@ -1122,40 +1140,34 @@ hipError_t phase_rows(const double2 *X, long ldx, double2 *Y, long ldy, int ncol
   return hipGetLastError();
 }
 
-hipError_t decide1(const SocDecideArgs &a, hipStream_t st) {
-  if (a.kk < 1 || a.kk > 2 * kSocMaxK) return hipErrorInvalidValue;
-  const int n = a.kk;
+hipError_t decide1(const SocDecideArgs *a, int nb, hipStream_t st) {
+  if (a[0].kk < 1 || a[0].kk > 2 * kSocMaxK) return hipErrorInvalidValue;
+  const int n = a[0].kk;
   const size_t lds = sizeof(double2) * (2 * (size_t)n * (n + 1) + 2 * (size_t)n);
   static const hipError_t attr = hipFuncSetAttribute(
       (const void *)cplx_decide_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
       (int)(sizeof(double2) * (2 * 64 * 65 + 2 * 64)));
-  if (attr != hipSuccess) return attr;
-  hipLaunchKernelGGL(cplx_decide_kernel, dim3(1), dim3(kDecThreads), lds, st, a);
-  return hipGetLastError();
+  return launch_decide(cplx_decide_kernel, a, nb, lds, st, attr);
 }
 
-hipError_t block_decide1(const SocDecideArgs &a, hipStream_t st) {
-  if (a.kk < 1 || a.kk > 2 * kSocMaxK) return hipErrorInvalidValue;
-  const int n = a.kk;
+hipError_t block_decide1(const SocDecideArgs *a, int nb, hipStream_t st) {
+  if (a[0].kk < 1 || a[0].kk > 2 * kSocMaxK) return hipErrorInvalidValue;
+  const int n = a[0].kk;
   const size_t lds = sizeof(double2) * (size_t)n * (2 * n + 1);
   static const hipError_t attr = hipFuncSetAttribute(
       (const void *)cplx_block_decide_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
       (int)(sizeof(double2) * 64 * 129));
-  if (attr != hipSuccess) return attr;
-  hipLaunchKernelGGL(cplx_block_decide_kernel, dim3(1), dim3(kDecThreads), lds, st, a);
-  return hipGetLastError();
+  return launch_decide(cplx_block_decide_kernel, a, nb, lds, st, attr);
 }
 
-hipError_t decide(const SocDecideArgs &a, hipStream_t st) {
-  if (a.kk < 1 || a.kk > kSocMaxK) return hipErrorInvalidValue;
-  const int n = 2 * a.kk;
+hipError_t decide(const SocDecideArgs *a, int nb, hipStream_t st) {
+  if (a[0].kk < 1 || a[0].kk > kSocMaxK) return hipErrorInvalidValue;
+  const int n = 2 * a[0].kk;
   const size_t lds = sizeof(double2) * (2 * (size_t)n * (n + 1) + 4 * (size_t)n);
   static const hipError_t attr = hipFuncSetAttribute(
       (const void *)soc_decide_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
       (int)(sizeof(double2) * (2 * 64 * 65 + 4 * 64)));
-  if (attr != hipSuccess) return attr;
-  hipLaunchKernelGGL(soc_decide_kernel, dim3(1), dim3(kDecThreads), lds, st, a);
-  return hipGetLastError();
+  return launch_decide(soc_decide_kernel, a, nb, lds, st, attr);
 }
 
 }  // namespace soc

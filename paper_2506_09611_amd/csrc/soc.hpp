@@ -56,13 +56,23 @@ hipError_t rotate_rows(const double2 *X, long ldx, double2 *Y, long ldy, int nco
 hipError_t conj_copy(const double2 *X, double2 *Y, long n, hipStream_t st);
 // E[r][off + c] = (r == c), r, c < n
 hipError_t set_identity(double2 *E, long ld, int n, int off, hipStream_t st);
-// upper triangle of S (n x n, leading dim ld, Hermitian positive definite)
-// <- R with S = R^H R; strict lower triangle <- 0
-hipError_t cholesky(double2 *S, long ld, int n, unsigned long long *stats, hipStream_t st);
-// E = [M | I] (n x 2n, leading dim ld) -> [I | M^{-1}] by Gauss-Jordan with
-// partial pivoting, one launch per pivot column; colbuf: 2n scratch; n <= 1024
-hipError_t gj_inverse(double2 *E, long ld, int n, double2 *colbuf, unsigned long long *stats,
-                      hipStream_t st);
+// Walkers of one SOC batch: all share n2, n_e, M, k_tau, the scheme and k.
+constexpr int kSocMaxBatch = 8;
+// The matrices of a batched elimination, one per walker: E (n x 2n or
+// n x n, leading dim ld), its pivot-column scratch (2n) and error flags.
+struct SocElimBatch {
+  double2 *E[kSocMaxBatch];
+  double2 *col[kSocMaxBatch];
+  unsigned long long *stats[kSocMaxBatch];
+  int n;
+};
+// upper triangle of each S = E[w] (n x n, leading dim ld, Hermitian positive
+// definite) <- R with S = R^H R; strict lower triangle <- 0
+hipError_t cholesky(const SocElimBatch &b, long ld, int n, hipStream_t st);
+// each E[w] = [M | I] (n x 2n, leading dim ld) -> [I | M^{-1}] by Gauss-Jordan
+// with partial pivoting, one launch per pivot column for the whole batch;
+// col[w]: 2n scratch; n <= 1024
+hipError_t gj_inverse(const SocElimBatch &b, long ld, int n, hipStream_t st);
 
 constexpr int kSocMaxK = 32;   // group size of the decision kernel (2k x 2k in LDS)
 struct SocDecideArgs {
@@ -81,16 +91,20 @@ struct SocDecideArgs {
   long long log_base, log_cap;
   const int8_t *force;     // replay: forced outcomes of the slice visit (or null)
 };
-hipError_t decide(const SocDecideArgs &a, hipStream_t st);
+// one workgroup per walker: a[0..nb) (nb <= kSocMaxBatch), all with the same kk
+struct SocDecideBatch {
+  SocDecideArgs a[kSocMaxBatch];
+};
+hipError_t decide(const SocDecideArgs *a, int nb, hipStream_t st);
 // The one-sector model (U < 0 of Sec. II B, w = 1): rows scaled by the
 // phases e^{i sign gamma x_i}; decisions of kk <= 64 sites with a scalar
 // flip delta per site (delayed / local, and block force bias).
 hipError_t phase_rows(const double2 *X, long ldx, double2 *Y, long ldy, int ncols, int N,
                       const int8_t *xrow, double c, double s, double sign, hipStream_t st);
-hipError_t decide1(const SocDecideArgs &a, hipStream_t st);
-hipError_t block_decide1(const SocDecideArgs &a, hipStream_t st);
+hipError_t decide1(const SocDecideArgs *a, int nb, hipStream_t st);
+hipError_t block_decide1(const SocDecideArgs *a, int nb, hipStream_t st);
 // block force bias over the kk sites of the group (log entry at log_base)
-hipError_t block_decide(const SocDecideArgs &a, hipStream_t st);
+hipError_t block_decide(const SocDecideArgs *a, int nb, hipStream_t st);
 
 }  // namespace soc
 }  // namespace pq
@@ -110,5 +124,10 @@ pqmc_status one_sector_set_fields(pqmc_soc_ctx *c, const int8_t *fields);
 pqmc_status one_sector_replay(pqmc_soc_ctx *c, const int8_t *flips, pqmc_stats *out);
 pqmc_status one_sector_green(pqmc_soc_ctx *c, int spin, double *out);
 int one_sector_dims(const pqmc_soc_ctx *c, int *N, int *M);
+// Sweeps (n_slices < 0) or one forward window of a batch of SOC or one-sector
+// contexts (soc_capi.cpp); batch_compatible: a and b may share a batch.
+pqmc_status batch_run(pqmc_soc_ctx *const *cs, int n, int n_sweeps, int n_slices,
+                      pqmc_stats *out);
+bool batch_compatible(const pqmc_soc_ctx *a, const pqmc_soc_ctx *b);
 }  // namespace soc
 }  // namespace pq

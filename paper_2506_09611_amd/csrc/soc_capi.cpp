@@ -217,81 +217,179 @@ int expm(pqmc_soc_ctx &c, double scale, int sq, double2 *dst) {
   return PQMC_OK;
 }
 
-// dst = A R^{-1} with A^H A = R^H R (A: n2 x ne): columns orthonormalised.
+// The walkers of one call: one, or a batch that shares n2, n_e, M, k_tau, the
+// scheme, k, the width w and the stream.  Every launch of the engine serves
+// all of them: the complex GEMMs take one descriptor per walker and matrix,
+// the decisions and the eliminations one workgroup (row) per walker.  A
+// walker's results do not depend on its batch partners.
+struct SocWalkers {
+  pqmc_soc_ctx *const *w;
+  int n;
+  pqmc_soc_ctx &operator[](int i) const { return *w[i]; }
+  pqmc_soc_ctx &lead() const { return *w[0]; }
+};
+
+struct CgemmQueue {
+  hipStream_t st;
+  int opA, opB;
+  CgemmBatch cur{};
+  int add(const CgemmDesc &d) {
+    cur.d[cur.count++] = d;
+    return cur.count == kCgemmMaxBatch ? flush() : PQMC_OK;
+  }
+  int flush() {
+    if (cur.count == 0) return PQMC_OK;
+    hipError_t e = cgemm(cur, opA, opB, st);
+    cur.count = 0;
+    if (e != hipSuccess) return fail_device(e, "cgemm", __FILE__, __LINE__);
+    return PQMC_OK;
+  }
+};
+
+struct CsumQueue {
+  hipStream_t st;
+  CsumBatch cur{};
+  int add(const CsumDesc &d) {
+    cur.d[cur.count++] = d;
+    return cur.count == kCgemmMaxBatch ? flush() : PQMC_OK;
+  }
+  int flush() {
+    if (cur.count == 0) return PQMC_OK;
+    hipError_t e = csum(cur, st);
+    cur.count = 0;
+    if (e != hipSuccess) return fail_device(e, "csum", __FILE__, __LINE__);
+    return PQMC_OK;
+  }
+};
+
+SocElimBatch elim_batch(const SocWalkers &b) {
+  SocElimBatch e{};
+  for (int i = 0; i < b.n; ++i) {
+    e.E[i] = b[i].E;
+    e.col[i] = b[i].colbuf;
+    e.stats[i] = b[i].stats;
+  }
+  e.n = b.n;
+  return e;
+}
+
+// dst[i] = A[i] R^{-1} with A^H A = R^H R (A: n2 x ne): columns orthonormalised.
 // E serves as scratch: [A^H A | I] -> [R | I] -> [I | R^{-1}].
-int orthonormalize(pqmc_soc_ctx &c, const double2 *A, double2 *dst) {
-  const int n2 = c.n2, ne = c.ne;
+int orthonormalize(const SocWalkers &b, const double2 *const *A, double2 *const *dst) {
+  pqmc_soc_ctx &L = b.lead();
+  const int n2 = L.n2, ne = L.ne;
   const long ld = 2L * ne;
-  int rc = gemm1(cdesc(A, ne, A, ne, c.E, ld, ne, ne, n2), kOpH, kOpN, c.st);
+  CgemmQueue gram{L.st, kOpH, kOpN};
+  for (int i = 0; i < b.n; ++i) {
+    int rc = gram.add(cdesc(A[i], ne, A[i], ne, b[i].E, ld, ne, ne, n2));
+    if (rc) return rc;
+  }
+  int rc = gram.flush();
   if (rc) return rc;
-  PQ_HIP_CHECK(cholesky(c.E, ld, ne, c.stats, c.st));
-  PQ_HIP_CHECK(set_identity(c.E, ld, ne, ne, c.st));
-  PQ_HIP_CHECK(gj_inverse(c.E, ld, ne, c.colbuf, c.stats, c.st));
-  return gemm1(cdesc(A, ne, c.E + ne, ld, dst, ne, n2, ne, ne), kOpN, kOpN, c.st);
+  const SocElimBatch eb = elim_batch(b);
+  PQ_HIP_CHECK(cholesky(eb, ld, ne, L.st));
+  for (int i = 0; i < b.n; ++i) PQ_HIP_CHECK(set_identity(b[i].E, ld, ne, ne, L.st));
+  PQ_HIP_CHECK(gj_inverse(eb, ld, ne, L.st));
+  CgemmQueue out{L.st, kOpN, kOpN};
+  for (int i = 0; i < b.n; ++i) {
+    rc = out.add(cdesc(A[i], ne, b[i].E + ne, ld, dst[i], ne, n2, ne, ne));
+    if (rc) return rc;
+  }
+  return out.flush();
 }
 
 // T = (U_L U_R)^{-1} = (ULt^T UR)^{-1}, in the right half of E
-int refresh_T(pqmc_soc_ctx &c) {
-  const int n2 = c.n2, ne = c.ne;
-  int rc = gemm1(cdesc(c.ULt, ne, c.UR, ne, c.E, 2L * ne, ne, ne, n2), kOpT, kOpN, c.st);
+int refresh_T(const SocWalkers &b) {
+  pqmc_soc_ctx &L = b.lead();
+  const int n2 = L.n2, ne = L.ne;
+  CgemmQueue q{L.st, kOpT, kOpN};
+  for (int i = 0; i < b.n; ++i) {
+    int rc = q.add(cdesc(b[i].ULt, ne, b[i].UR, ne, b[i].E, 2L * ne, ne, ne, n2));
+    if (rc) return rc;
+  }
+  int rc = q.flush();
   if (rc) return rc;
-  PQ_HIP_CHECK(set_identity(c.E, 2L * ne, ne, ne, c.st));
-  PQ_HIP_CHECK(gj_inverse(c.E, 2L * ne, ne, c.colbuf, c.stats, c.st));
+  for (int i = 0; i < b.n; ++i) PQ_HIP_CHECK(set_identity(b[i].E, 2L * ne, ne, ne, L.st));
+  PQ_HIP_CHECK(gj_inverse(elim_batch(b), 2L * ne, ne, L.st));
   return PQMC_OK;
 }
 
 // position l-1 -> l: U_R <- e^{H_I(x_l)} K U_R; U_L <- U_L K^{-1} e^{-H_I(x_l)},
 // i.e. ULt <- [e^{-H_I}]^T K^{-T} ULt, whose 2x2 blocks are A(x).
-int prop_forward(pqmc_soc_ctx &c, int l) {
-  const int n2 = c.n2, ne = c.ne;
-  const int8_t *x = c.fields + (size_t)(l - 1) * c.N;
-  double2 *nur = other(c.UR, c.Rw), *nul = other(c.ULt, c.Lw);
-  int rc = gemm1(cdesc(c.K, n2, c.UR, ne, nur, ne, n2, ne, n2), kOpN, kOpN, c.st);
-  if (!rc) rc = gemm1(cdesc(c.Kinv, n2, c.ULt, ne, nul, ne, n2, ne, n2), kOpT, kOpN, c.st);
-  if (rc) return rc;
-  if (c.w == 1) {
-    // U_R <- diag(e^{i gamma x}) K U_R; ULt <- diag(e^{-i gamma x}) K^{-T} ULt
-    PQ_HIP_CHECK(phase_rows(nur, ne, nur, ne, ne, c.N, x, c.c1, c.s1, 1.0, c.st));
-    PQ_HIP_CHECK(phase_rows(nul, ne, nul, ne, ne, c.N, x, c.c1, c.s1, -1.0, c.st));
-  } else {
-    PQ_HIP_CHECK(rotate_rows(nur, ne, nur, ne, ne, c.N, x, c.c1, c.s1, 1.0, c.st));
-    PQ_HIP_CHECK(rotate_rows(nul, ne, nul, ne, ne, c.N, x, c.c1, c.s1, 1.0, c.st));
+int prop_forward(const SocWalkers &b, int l) {
+  pqmc_soc_ctx &L = b.lead();
+  const int n2 = L.n2, ne = L.ne;
+  CgemmQueue qr{L.st, kOpN, kOpN}, ql{L.st, kOpT, kOpN};
+  for (int i = 0; i < b.n; ++i) {
+    pqmc_soc_ctx &c = b[i];
+    int rc = qr.add(cdesc(c.K, n2, c.UR, ne, other(c.UR, c.Rw), ne, n2, ne, n2));
+    if (!rc) rc = ql.add(cdesc(c.Kinv, n2, c.ULt, ne, other(c.ULt, c.Lw), ne, n2, ne, n2));
+    if (rc) return rc;
   }
-  c.UR = nur;
-  c.ULt = nul;
+  int rc = qr.flush();
+  if (!rc) rc = ql.flush();
+  if (rc) return rc;
+  for (int i = 0; i < b.n; ++i) {
+    pqmc_soc_ctx &c = b[i];
+    const int8_t *x = c.fields + (size_t)(l - 1) * c.N;
+    double2 *nur = other(c.UR, c.Rw), *nul = other(c.ULt, c.Lw);
+    if (c.w == 1) {
+      // U_R <- diag(e^{i gamma x}) K U_R; ULt <- diag(e^{-i gamma x}) K^{-T} ULt
+      PQ_HIP_CHECK(phase_rows(nur, ne, nur, ne, ne, c.N, x, c.c1, c.s1, 1.0, c.st));
+      PQ_HIP_CHECK(phase_rows(nul, ne, nul, ne, ne, c.N, x, c.c1, c.s1, -1.0, c.st));
+    } else {
+      PQ_HIP_CHECK(rotate_rows(nur, ne, nur, ne, ne, c.N, x, c.c1, c.s1, 1.0, c.st));
+      PQ_HIP_CHECK(rotate_rows(nul, ne, nul, ne, ne, c.N, x, c.c1, c.s1, 1.0, c.st));
+    }
+    c.UR = nur;
+    c.ULt = nul;
+  }
   return PQMC_OK;
 }
 
 // position l -> l-1: U_L <- U_L e^{H_I(x_l)} K, i.e. ULt <- K^T [e^{H_I}]^T ULt
 // (blocks A(-x)); U_R <- K^{-1} e^{-H_I(x_l)} U_R (blocks A(-x)).  The
 // rotations go to a scratch buffer: the current matrices may be stack slots.
-int prop_backward(pqmc_soc_ctx &c, int l, bool with_R) {
-  const int n2 = c.n2, ne = c.ne;
-  const int8_t *x = c.fields + (size_t)(l - 1) * c.N;
-  double2 *nul = other(c.ULt, c.Lw);
+int prop_backward(const SocWalkers &b, int l, bool with_R) {
+  pqmc_soc_ctx &L = b.lead();
+  const int n2 = L.n2, ne = L.ne;
   // ULt <- K^T diag(e^{i gamma x}) ULt; U_R <- K^{-1} diag(e^{-i gamma x}) U_R (w = 1)
-  if (c.w == 1)
-    PQ_HIP_CHECK(phase_rows(c.ULt, ne, c.Xtmp, ne, ne, c.N, x, c.c1, c.s1, 1.0, c.st));
-  else
-    PQ_HIP_CHECK(rotate_rows(c.ULt, ne, c.Xtmp, ne, ne, c.N, x, c.c1, c.s1, -1.0, c.st));
-  int rc = gemm1(cdesc(c.K, n2, c.Xtmp, ne, nul, ne, n2, ne, n2), kOpT, kOpN, c.st);
+  CgemmQueue ql{L.st, kOpT, kOpN};
+  for (int i = 0; i < b.n; ++i) {
+    pqmc_soc_ctx &c = b[i];
+    const int8_t *x = c.fields + (size_t)(l - 1) * c.N;
+    if (c.w == 1)
+      PQ_HIP_CHECK(phase_rows(c.ULt, ne, c.Xtmp, ne, ne, c.N, x, c.c1, c.s1, 1.0, c.st));
+    else
+      PQ_HIP_CHECK(rotate_rows(c.ULt, ne, c.Xtmp, ne, ne, c.N, x, c.c1, c.s1, -1.0, c.st));
+    int rc = ql.add(cdesc(c.K, n2, c.Xtmp, ne, other(c.ULt, c.Lw), ne, n2, ne, n2));
+    if (rc) return rc;
+  }
+  int rc = ql.flush();
   if (rc) return rc;
-  c.ULt = nul;
-  if (with_R) {
-    double2 *nur = other(c.UR, c.Rw);
+  for (int i = 0; i < b.n; ++i) b[i].ULt = other(b[i].ULt, b[i].Lw);
+  if (!with_R) return PQMC_OK;
+  CgemmQueue qr{L.st, kOpN, kOpN};
+  for (int i = 0; i < b.n; ++i) {
+    pqmc_soc_ctx &c = b[i];
+    const int8_t *x = c.fields + (size_t)(l - 1) * c.N;
     if (c.w == 1)
       PQ_HIP_CHECK(phase_rows(c.UR, ne, c.Xtmp, ne, ne, c.N, x, c.c1, c.s1, -1.0, c.st));
     else
       PQ_HIP_CHECK(rotate_rows(c.UR, ne, c.Xtmp, ne, ne, c.N, x, c.c1, c.s1, -1.0, c.st));
-    rc = gemm1(cdesc(c.Kinv, n2, c.Xtmp, ne, nur, ne, n2, ne, n2), kOpN, kOpN, c.st);
+    rc = qr.add(cdesc(c.Kinv, n2, c.Xtmp, ne, other(c.UR, c.Rw), ne, n2, ne, n2));
     if (rc) return rc;
-    c.UR = nur;
   }
+  rc = qr.flush();
+  if (rc) return rc;
+  for (int i = 0; i < b.n; ++i) b[i].UR = other(b[i].UR, b[i].Rw);
   return PQMC_OK;
 }
 
 int build_state(pqmc_soc_ctx &c) {
   const size_t mat = (size_t)c.n2 * c.ne;
+  pqmc_soc_ctx *one[1] = {&c};
+  const SocWalkers b{one, 1};
   // U_L = P^+ at position M: ULt = conj(P)
   PQ_HIP_CHECK(conj_copy(c.P, slot(c.Lstack, c.nst, c), (long)mat, c.st));
   PQ_HIP_CHECK(hipMemcpyAsync(slot(c.Rstack, 0, c), c.P, sizeof(double2) * mat,
@@ -299,11 +397,13 @@ int build_state(pqmc_soc_ctx &c) {
   c.ULt = slot(c.Lstack, c.nst, c);
   c.UR = slot(c.Rstack, 0, c);
   for (int l = c.M; l >= 1; --l) {
-    int rc = prop_backward(c, l, false);
+    int rc = prop_backward(b, l, false);
     if (rc) return rc;
     if ((l - 1) % c.kt == 0) {
       double2 *dst = slot(c.Lstack, (l - 1) / c.kt, c);
-      rc = orthonormalize(c, c.ULt, dst);
+      const double2 *src[1] = {c.ULt};
+      double2 *dd[1] = {dst};
+      rc = orthonormalize(b, src, dd);
       if (rc) return rc;
       c.ULt = dst;
     }
@@ -311,7 +411,7 @@ int build_state(pqmc_soc_ctx &c) {
   c.UR = slot(c.Rstack, 0, c);
   c.position = 0;
   c.windowed = false;
-  return refresh_T(c);
+  return refresh_T(b);
 }
 
 int timer_mark(pqmc_soc_ctx &c) {
@@ -328,120 +428,178 @@ int timer_mark(pqmc_soc_ctx &c) {
 // Field update of slice l (direction dir): groups of k sites (k = 1: the
 // local update), each: panels P2 = W_g T, P1 = T U_L[:, g], W0' = P2 U_L[:, g],
 // the decisions in 2k x 2k space (one decision per site, or one block
-// force-bias decision per group), then T -= (P1 D) P2.
-int update_slice(pqmc_soc_ctx &c, int l, int dir) {
-  const int N = c.N, ne = c.ne, li = l - 1;
-  int rc = timer_mark(c);
-  if (rc) return rc;
-  int nblk = 0;
-  for (int g0 = 0; g0 < N; g0 += c.k, ++nblk) {
-    const int kk = std::min(c.k, N - g0), n = c.w * kk;
-    const double2 *ur0 = c.UR + (size_t)g0 * ne, *ur1 = c.UR + (size_t)(N + g0) * ne;
-    const double2 *ul0 = c.ULt + (size_t)g0 * ne, *ul1 = c.ULt + (size_t)(N + g0) * ne;
-    // P2 = W_g T; then P1 = T U_L[:, g] and W0' = P2 U_L[:, g].  Over a deep
-    // N_e the products run as split-K slices, added in order by csum.
-    const bool split = c.ksplit > 0;
-    const int ns = split ? (ne + c.ksplit - 1) / c.ksplit : 1;
-    const long s2 = (long)n * ne, s1 = (long)ne * n, sw = (long)n * n;
-    double2 *p2 = split ? c.P2part : c.P2, *p1 = split ? c.P1part : c.P1;
-    double2 *w0 = split ? c.W0part : c.W0;
-    CgemmBatch a{};
-    a.d[a.count++] = cdesc(ur0, ne, c.T, c.ldT, p2, ne, kk, ne, ne);
-    if (c.w == 2) a.d[a.count++] = cdesc(ur1, ne, c.T, c.ldT, p2 + (size_t)kk * ne, ne, kk, ne, ne);
-    for (int i = 0; i < a.count && split; ++i) {
-      a.d[i].ksplit = c.ksplit;
-      a.d[i].csplit = s2;
-    }
-    PQ_HIP_CHECK(cgemm(a, kOpN, kOpN, c.st));
-    if (split) {
-      CsumBatch r{};
-      r.d[r.count++] = CsumDesc{c.P2part, s2, ne, c.P2, ne, n, ne, ns};
-      PQ_HIP_CHECK(csum(r, c.st));
-    }
-    CgemmBatch b{};
-    b.d[b.count++] = cdesc(c.T, c.ldT, ul0, ne, p1, n, ne, kk, ne);
-    if (c.w == 2) b.d[b.count++] = cdesc(c.T, c.ldT, ul1, ne, p1 + kk, n, ne, kk, ne);
-    const int np1 = b.count;
-    b.d[b.count++] = cdesc(c.P2, ne, ul0, ne, w0, n, n, kk, ne);
-    if (c.w == 2) b.d[b.count++] = cdesc(c.P2, ne, ul1, ne, w0 + kk, n, n, kk, ne);
-    for (int i = 0; i < b.count && split; ++i) {
-      b.d[i].ksplit = c.ksplit;
-      b.d[i].csplit = i < np1 ? s1 : sw;
-    }
-    PQ_HIP_CHECK(cgemm(b, kOpN, kOpT, c.st));
-    if (split) {
-      CsumBatch r{};
-      r.d[r.count++] = CsumDesc{c.P1part, s1, n, c.P1, n, ne, n, ns};
-      r.d[r.count++] = CsumDesc{c.W0part, sw, n, c.W0, n, n, n, ns};
-      PQ_HIP_CHECK(csum(r, c.st));
-    }
-    SocDecideArgs d{};
-    d.W0p = c.W0;
-    d.D = c.D;
-    d.UR = c.UR;
-    d.nflush = c.nflush;
-    d.fields = c.fields;
-    d.li = li;
-    d.N = N;
-    d.ne = ne;
-    d.g0 = g0;
-    d.kk = kk;
-    d.dd = c.dd;
-    d.doff = c.doff;
-    d.c1 = c.c1;
-    d.s1 = c.s1;
-    d.gamma = c.gamma;
-    d.key0 = c.seed;
-    d.key1 = c.walker;
-    d.sweep = c.sweep_index;
-    d.slice_code = (uint64_t)dir * c.M + li;
-    d.stats = c.stats;
-    d.log_meta = c.log_meta;
-    d.log_margin = c.log_margin;
-    d.log_base = c.block ? c.log_count + nblk : c.log_count;
-    d.log_cap = c.log_cap;
-    d.force = c.replaying ? c.replay + ((size_t)dir * c.M + li) * N : nullptr;
-    if (c.w == 1)
-      PQ_HIP_CHECK(c.block ? block_decide1(d, c.st) : decide1(d, c.st));
-    else if (c.block)
-      PQ_HIP_CHECK(block_decide(d, c.st));
-    else
-      PQ_HIP_CHECK(decide(d, c.st));
-    CgemmDesc q = cdesc(c.P1, n, c.D, n, c.Q, n, ne, n, n);
-    q.Kdev = c.nflush;
-    rc = gemm1(q, kOpN, kOpN, c.st);
-    if (rc) return rc;
-    CgemmDesc u = cdesc(c.Q, n, c.P2, ne, c.T, c.ldT, ne, ne, n);
-    u.alpha = make_double2(-1.0, 0.0);
-    u.beta = make_double2(1.0, 0.0);
-    u.Cin = c.T;
-    u.ldcin = c.ldT;
-    u.Kdev = c.nflush;
-    rc = gemm1(u, kOpN, kOpN, c.st);
+// force-bias decision per group), then T -= (P1 D) P2; every step one launch
+// for the whole batch.
+int update_slice(const SocWalkers &b, int l, int dir) {
+  pqmc_soc_ctx &L = b.lead();
+  const int N = L.N, ne = L.ne, li = l - 1;
+  for (int i = 0; i < b.n; ++i) {
+    int rc = timer_mark(b[i]);
     if (rc) return rc;
   }
-  c.log_count += c.block ? nblk : N;
-  return timer_mark(c);
+  int nblk = 0;
+  for (int g0 = 0; g0 < N; g0 += L.k, ++nblk) {
+    const int kk = std::min(L.k, N - g0), n = L.w * kk;
+    // P2 = W_g T; then P1 = T U_L[:, g] and W0' = P2 U_L[:, g].  Over a deep
+    // N_e the products run as split-K slices, added in order by csum.
+    const bool split = L.ksplit > 0;
+    const int ns = split ? (ne + L.ksplit - 1) / L.ksplit : 1;
+    const long s2 = (long)n * ne, s1 = (long)ne * n, sw = (long)n * n;
+    CgemmQueue qa{L.st, kOpN, kOpN};
+    for (int i = 0; i < b.n; ++i) {
+      pqmc_soc_ctx &c = b[i];
+      double2 *p2 = split ? c.P2part : c.P2;
+      const double2 *ur0 = c.UR + (size_t)g0 * ne, *ur1 = c.UR + (size_t)(N + g0) * ne;
+      CgemmDesc d0 = cdesc(ur0, ne, c.T, c.ldT, p2, ne, kk, ne, ne);
+      CgemmDesc d1 = cdesc(ur1, ne, c.T, c.ldT, p2 + (size_t)kk * ne, ne, kk, ne, ne);
+      if (split) {
+        d0.ksplit = d1.ksplit = c.ksplit;
+        d0.csplit = d1.csplit = s2;
+      }
+      int rc = qa.add(d0);
+      if (!rc && c.w == 2) rc = qa.add(d1);
+      if (rc) return rc;
+    }
+    int rc = qa.flush();
+    if (rc) return rc;
+    if (split) {
+      CsumQueue r{L.st};
+      for (int i = 0; i < b.n && !rc; ++i)
+        rc = r.add(CsumDesc{b[i].P2part, s2, ne, b[i].P2, ne, n, ne, ns});
+      if (!rc) rc = r.flush();
+      if (rc) return rc;
+    }
+    CgemmQueue qb{L.st, kOpN, kOpT};
+    for (int i = 0; i < b.n; ++i) {
+      pqmc_soc_ctx &c = b[i];
+      double2 *p1 = split ? c.P1part : c.P1, *w0 = split ? c.W0part : c.W0;
+      const double2 *ul0 = c.ULt + (size_t)g0 * ne, *ul1 = c.ULt + (size_t)(N + g0) * ne;
+      CgemmDesc d[4];
+      int m = 0;
+      d[m++] = cdesc(c.T, c.ldT, ul0, ne, p1, n, ne, kk, ne);
+      if (c.w == 2) d[m++] = cdesc(c.T, c.ldT, ul1, ne, p1 + kk, n, ne, kk, ne);
+      const int np1 = m;
+      d[m++] = cdesc(c.P2, ne, ul0, ne, w0, n, n, kk, ne);
+      if (c.w == 2) d[m++] = cdesc(c.P2, ne, ul1, ne, w0 + kk, n, n, kk, ne);
+      for (int j = 0; j < m; ++j) {
+        if (split) {
+          d[j].ksplit = c.ksplit;
+          d[j].csplit = j < np1 ? s1 : sw;
+        }
+        rc = qb.add(d[j]);
+        if (rc) return rc;
+      }
+    }
+    rc = qb.flush();
+    if (rc) return rc;
+    if (split) {
+      CsumQueue r{L.st};
+      for (int i = 0; i < b.n && !rc; ++i) {
+        rc = r.add(CsumDesc{b[i].P1part, s1, n, b[i].P1, n, ne, n, ns});
+        if (!rc) rc = r.add(CsumDesc{b[i].W0part, sw, n, b[i].W0, n, n, n, ns});
+      }
+      if (!rc) rc = r.flush();
+      if (rc) return rc;
+    }
+    SocDecideArgs da[kSocMaxBatch];
+    for (int i = 0; i < b.n; ++i) {
+      pqmc_soc_ctx &c = b[i];
+      SocDecideArgs d{};
+      d.W0p = c.W0;
+      d.D = c.D;
+      d.UR = c.UR;
+      d.nflush = c.nflush;
+      d.fields = c.fields;
+      d.li = li;
+      d.N = N;
+      d.ne = ne;
+      d.g0 = g0;
+      d.kk = kk;
+      d.dd = c.dd;
+      d.doff = c.doff;
+      d.c1 = c.c1;
+      d.s1 = c.s1;
+      d.gamma = c.gamma;
+      d.key0 = c.seed;
+      d.key1 = c.walker;
+      d.sweep = c.sweep_index;
+      d.slice_code = (uint64_t)dir * c.M + li;
+      d.stats = c.stats;
+      d.log_meta = c.log_meta;
+      d.log_margin = c.log_margin;
+      d.log_base = c.block ? c.log_count + nblk : c.log_count;
+      d.log_cap = c.log_cap;
+      d.force = c.replaying ? c.replay + ((size_t)dir * c.M + li) * N : nullptr;
+      da[i] = d;
+    }
+    if (L.w == 1)
+      PQ_HIP_CHECK(L.block ? block_decide1(da, b.n, L.st) : decide1(da, b.n, L.st));
+    else if (L.block)
+      PQ_HIP_CHECK(block_decide(da, b.n, L.st));
+    else
+      PQ_HIP_CHECK(decide(da, b.n, L.st));
+    CgemmQueue qq{L.st, kOpN, kOpN};
+    for (int i = 0; i < b.n && !rc; ++i) {
+      CgemmDesc q = cdesc(b[i].P1, n, b[i].D, n, b[i].Q, n, ne, n, n);
+      q.Kdev = b[i].nflush;
+      rc = qq.add(q);
+    }
+    if (!rc) rc = qq.flush();
+    if (rc) return rc;
+    CgemmQueue qu{L.st, kOpN, kOpN};
+    for (int i = 0; i < b.n && !rc; ++i) {
+      pqmc_soc_ctx &c = b[i];
+      CgemmDesc u = cdesc(c.Q, n, c.P2, ne, c.T, c.ldT, ne, ne, n);
+      u.alpha = make_double2(-1.0, 0.0);
+      u.beta = make_double2(1.0, 0.0);
+      u.Cin = c.T;
+      u.ldcin = c.ldT;
+      u.Kdev = c.nflush;
+      rc = qu.add(u);
+    }
+    if (!rc) rc = qu.flush();
+    if (rc) return rc;
+  }
+  for (int i = 0; i < b.n; ++i) {
+    b[i].log_count += L.block ? nblk : N;
+    int rc = timer_mark(b[i]);
+    if (rc) return rc;
+  }
+  return PQMC_OK;
 }
 
-int stab_forward(pqmc_soc_ctx &c, int l) {
-  const int j = l / c.kt;
-  double2 *dst = slot(c.Rstack, j, c);
-  int rc = orthonormalize(c, c.UR, dst);
+int stab_forward(const SocWalkers &b, int l) {
+  const int j = l / b.lead().kt;
+  const double2 *src[kSocMaxBatch];
+  double2 *dst[kSocMaxBatch];
+  for (int i = 0; i < b.n; ++i) {
+    src[i] = b[i].UR;
+    dst[i] = slot(b[i].Rstack, j, b[i]);
+  }
+  int rc = orthonormalize(b, src, dst);
   if (rc) return rc;
-  c.UR = dst;
-  c.ULt = slot(c.Lstack, j, c);
-  return refresh_T(c);
+  for (int i = 0; i < b.n; ++i) {
+    b[i].UR = dst[i];
+    b[i].ULt = slot(b[i].Lstack, j, b[i]);
+  }
+  return refresh_T(b);
 }
 
-int stab_backward(pqmc_soc_ctx &c, int l) {
-  const int j = (l - 1) / c.kt;
-  double2 *dst = slot(c.Lstack, j, c);
-  int rc = orthonormalize(c, c.ULt, dst);
+int stab_backward(const SocWalkers &b, int l) {
+  const int j = (l - 1) / b.lead().kt;
+  const double2 *src[kSocMaxBatch];
+  double2 *dst[kSocMaxBatch];
+  for (int i = 0; i < b.n; ++i) {
+    src[i] = b[i].ULt;
+    dst[i] = slot(b[i].Lstack, j, b[i]);
+  }
+  int rc = orthonormalize(b, src, dst);
   if (rc) return rc;
-  c.ULt = dst;
-  c.UR = slot(c.Rstack, j, c);
-  return refresh_T(c);
+  for (int i = 0; i < b.n; ++i) {
+    b[i].ULt = dst[i];
+    b[i].UR = slot(b[i].Rstack, j, b[i]);
+  }
+  return refresh_T(b);
 }
 
 int begin_call(pqmc_soc_ctx &c) {
@@ -577,48 +735,104 @@ pqmc_status pqmc_soc_create(const pqmc_soc_problem *prob, const pqmc_update_opts
   return create_common(c, prob->hopping, prob->trial, hip_stream, workspace, workspace_bytes, out);
 }
 
-static pqmc_status soc_run(pqmc_soc_ctx *c, int n_sweeps, int n_slices, pqmc_stats *out) {
-  if (!c) return err(PQMC_EINVAL, "null context");
-  if (c->failed) return err(PQMC_ESTATE, "context failed");
-  if (c->windowed || c->position != 0) return err(PQMC_ESTATE, "walker is mid-sweep");
+}  // extern "C"
+
+namespace pq {
+namespace soc {
+
+bool batch_compatible(const pqmc_soc_ctx *c, const pqmc_soc_ctx *a) {
+  return c->N == a->N && c->ne == a->ne && c->M == a->M && c->kt == a->kt && c->k == a->k &&
+         c->block == a->block && c->w == a->w && c->st == a->st &&
+         c->opts.scheme == a->opts.scheme;
+}
+
+// n sweeps (n_slices < 0) or one forward window of n_slices slice visits for
+// a batch of walkers (out: one entry per walker, or null).
+pqmc_status batch_run(pqmc_soc_ctx *const *cs, int n, int n_sweeps, int n_slices,
+                      pqmc_stats *out) {
+  if (!cs || n < 1 || n > kSocMaxBatch) return err(PQMC_EINVAL, "batch size must be 1..8");
+  for (int i = 0; i < n; ++i) {
+    const pqmc_soc_ctx *c = cs[i];
+    if (!c) return err(PQMC_EINVAL, "null context");
+    if (!batch_compatible(c, cs[0]))
+      return err(PQMC_EINVAL,
+                 "batched SOC walkers need the same lattice, N_e, M, k_tau, scheme, k and "
+                 "stream");
+    for (int j = 0; j < i; ++j)
+      if (cs[j] == c) return err(PQMC_EINVAL, "a context appears twice in the batch");
+    if (c->failed) return err(PQMC_ESTATE, "context failed");
+    if (c->windowed || c->position != 0) return err(PQMC_ESTATE, "walker is mid-sweep");
+  }
+  const SocWalkers b{cs, n};
+  pqmc_soc_ctx &L = b.lead();
   const double t0 = now_s();
-  int rc = begin_call(*c);
+  int rc = PQMC_OK;
+  for (int i = 0; i < n && !rc; ++i) rc = begin_call(b[i]);
   if (n_slices >= 0) {   // one forward window
     for (int l = 1; l <= n_slices && !rc; ++l) {
-      rc = prop_forward(*c, l);
-      if (!rc) rc = update_slice(*c, l, 0);
-      if (!rc && l % c->kt == 0) rc = stab_forward(*c, l);
+      rc = prop_forward(b, l);
+      if (!rc) rc = update_slice(b, l, 0);
+      if (!rc && l % L.kt == 0) rc = stab_forward(b, l);
     }
-    c->position = n_slices;
-    c->windowed = true;
+    for (int i = 0; i < n; ++i) {
+      b[i].position = n_slices;
+      b[i].windowed = true;
+    }
   } else {
     for (int s = 0; s < n_sweeps && !rc; ++s) {
-      for (int l = 1; l <= c->M && !rc; ++l) {
-        rc = prop_forward(*c, l);
-        if (!rc) rc = update_slice(*c, l, 0);
-        if (!rc && l % c->kt == 0) rc = stab_forward(*c, l);
+      for (int l = 1; l <= L.M && !rc; ++l) {
+        rc = prop_forward(b, l);
+        if (!rc) rc = update_slice(b, l, 0);
+        if (!rc && l % L.kt == 0) rc = stab_forward(b, l);
       }
-      for (int l = c->M; l >= 1 && !rc; --l) {
-        rc = update_slice(*c, l, 1);
-        if (!rc) rc = prop_backward(*c, l, true);
-        if (!rc && (l - 1) % c->kt == 0) rc = stab_backward(*c, l);
+      for (int l = L.M; l >= 1 && !rc; --l) {
+        rc = update_slice(b, l, 1);
+        if (!rc) rc = prop_backward(b, l, true);
+        if (!rc && (l - 1) % L.kt == 0) rc = stab_backward(b, l);
       }
-      if (!rc) ++c->sweep_index;
+      if (!rc)
+        for (int i = 0; i < n; ++i) ++b[i].sweep_index;
     }
   }
-  if (!rc) rc = finish_call(*c, t0, out);
-  if (rc) c->failed = true;
-  return (pqmc_status)rc;
+  int first = rc;
+  for (int i = 0; i < n; ++i) {
+    const int r = rc ? rc : finish_call(b[i], t0, out ? out + i : nullptr);
+    if (r) {
+      b[i].failed = true;
+      if (!first) first = r;
+    }
+  }
+  return (pqmc_status)first;
 }
+
+}  // namespace soc
+}  // namespace pq
+
+extern "C" {
 
 pqmc_status pqmc_soc_sweep(pqmc_soc_ctx *c, int32_t n_sweeps, pqmc_stats *out) {
   if (n_sweeps < 0) return err(PQMC_EINVAL, "n_sweeps < 0");
-  return soc_run(c, n_sweeps, -1, out);
+  pqmc_soc_ctx *one[1] = {c};
+  return batch_run(one, 1, n_sweeps, -1, out);
 }
 
 pqmc_status pqmc_soc_forward_window(pqmc_soc_ctx *c, int32_t n_slices, pqmc_stats *out) {
   if (c && (n_slices < 0 || n_slices > c->M)) return err(PQMC_EINVAL, "n_slices out of range");
-  return soc_run(c, 0, n_slices, out);
+  pqmc_soc_ctx *one[1] = {c};
+  return batch_run(one, 1, 0, n_slices, out);
+}
+
+pqmc_status pqmc_soc_batch_sweep(pqmc_soc_ctx *const *ctxs, int32_t n, int32_t n_sweeps,
+                                 pqmc_stats *out) {
+  if (n_sweeps < 0) return err(PQMC_EINVAL, "n_sweeps < 0");
+  return batch_run(ctxs, n, n_sweeps, -1, out);
+}
+
+pqmc_status pqmc_soc_batch_forward_window(pqmc_soc_ctx *const *ctxs, int32_t n, int32_t n_slices,
+                                          pqmc_stats *out) {
+  if (ctxs && n >= 1 && ctxs[0] && (n_slices < 0 || n_slices > ctxs[0]->M))
+    return err(PQMC_EINVAL, "n_slices out of range");
+  return batch_run(ctxs, n, 0, n_slices, out);
 }
 
 pqmc_status pqmc_soc_get_green(pqmc_soc_ctx *c, double *out) {

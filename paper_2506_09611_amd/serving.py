@@ -12,7 +12,7 @@ stream).  The server
   the library uses on the device; a job larger than the whole budget is
   rejected;
 * runs one sweep per step for a batch of up to MAX_BATCH compatible walkers
-  (pqmc_batch_sweep).  The walker first in line picks the batch and the
+  (pqmc_batch_sweep, or pqmc_soc_batch_sweep for spin-orbit coupled ones).  The walker first in line picks the batch and the
   compatible walkers behind it fill it, in line order.  The line is
   ordered by job arrival, then by sweeps done ("fcfs"), or by sweeps done,
   then arrival ("rr", round robin).  The delayed and block schemes batch
@@ -87,10 +87,14 @@ class Job:
 def batch_key(job: Job) -> tuple:
     """Walkers batch together iff their keys are equal: the library's rule
     for pqmc_batch_sweep (same M, k_tau, scheme, k, b, precision form and
-    group-size class; the local scheme also needs one lattice shape).  An
-    SOC walker is always a batch of its own."""
-    if job.soc:   # one context per walker, swept on its own (pqmc_soc_sweep)
-        return ("soc", job.job_id)
+    group-size class; the local scheme also needs one lattice shape), and for
+    pqmc_soc_batch_sweep (SOC walkers of one lattice, N_e, M, k_tau, scheme
+    and group size)."""
+    if job.soc:
+        gk = job.b if job.scheme == Scheme.BLOCK_FB else (job.k if job.scheme == Scheme.DELAYED
+                                                          else 1)
+        return ("soc", job.n_sites, job.n_up, job.n_slices, job.stab_every, int(job.scheme),
+                min(gk, job.n_sites))
     N = job.n_sites
     gmax = max(min(job.k, N), min(job.b, N))
     key = (job.n_slices, job.stab_every, int(job.scheme), job.k, job.b, bool(job.fp32),
@@ -175,8 +179,8 @@ class RealClock:
 class GpuBackend:
     """Walkers as library contexts on torch's current device, lane j on its
     own HIP stream (lane 0: torch's current stream).  One step: the lanes'
-    spin-decoupled batches in one pqmc_multi_sweep, each SOC walker's
-    pqmc_soc_sweep on a host thread of its own, all concurrently."""
+    spin-decoupled batches in one pqmc_multi_sweep, each SOC batch's
+    pqmc_soc_batch_sweep on a host thread of its own, all concurrently."""
 
     def __init__(self, lanes: int = 1):
         import torch
@@ -229,7 +233,7 @@ class GpuBackend:
                 k += len(batches[i])
 
         def run_soc(i):
-            out[i] = [batches[i][0].sweep(1)]
+            out[i] = self._b.soc_batch_sweep(batches[i], 1)
 
         tasks = ([run_plain] if plain else []) + [(lambda i=i: run_soc(i)) for i in socs]
         if len(tasks) == 1:
@@ -297,8 +301,6 @@ class Server:
     def _pick(self, active: List[_Walker]) -> List[_Walker]:
         line = sorted(active, key=self._line_key)
         head = line[0]
-        if head.key[0] == "soc":
-            return [head]
         return [w for w in line if w.key == head.key][:self.max_batch]
 
     def _pick_lanes(self, active: List[_Walker]) -> List[List[_Walker]]:

@@ -198,16 +198,22 @@ def _soc_job(i, arrival, L, n_walkers=2, n_sweeps=2):
                scheme=Scheme.DELAYED, k=16, soc=True)
 
 
-def test_soc_walkers_run_alone_beside_batches():
-    """SOC walkers never share a batch (one context each), but run on the
-    lanes beside the spin-decoupled batches."""
+def test_soc_walkers_batch_by_shape_beside_batches():
+    """SOC walkers batch only with SOC walkers of the same shape (lattice,
+    N_e, M, k_tau, scheme, group size), never with spin-decoupled ones, and
+    run on the lanes beside the spin-decoupled batches."""
     clock = SimClock()
     jobs = [_job(0, 0.0, 8, n_walkers=6), _soc_job(1, 0.0, 8), _job(2, 0.0, 12, n_walkers=4),
-            _soc_job(3, 0.001, 4, n_walkers=3)]
+            _soc_job(3, 0.001, 4, n_walkers=3), _soc_job(4, 0.002, 8, n_walkers=3)]
     assert jobs[1].n_sites == 64 and jobs[1].n_up == 64
     rep = Server(SimBackend(clock), 10**6, clock=clock, lanes=2).run(jobs)
+    shared = False
     for b in rep.batch_log:
         socs = [j for j, _ in b if jobs[j].soc]
-        assert not socs or len(b) == 1, b
+        assert not socs or len(socs) == len(b), b                       # never mixed
+        assert len({batch_key(jobs[j]) for j, _ in b}) == 1, b          # one shape
+        shared |= len({j for j, _ in b if jobs[j].soc}) > 1
+    assert shared   # the two 8x8 SOC jobs (same shape) share batches
     assert all(r.finished is not None for r in rep.results)
     assert batch_key(jobs[1]) != batch_key(jobs[3])
+    assert batch_key(jobs[1]) == batch_key(jobs[4])
