@@ -315,7 +315,7 @@ def soc_leg(args):
     block force-bias updates on forward windows of one walker, per lattice size."""
     import torch
     import synth
-    from paper_2506_09611_amd import SocChain, Scheme
+    from paper_2506_09611_amd import SocChain, Scheme, soc_batch_forward_window
     rows = []
     for L in [int(x) for x in args.soc_sizes.split(",") if x]:
         N = L * L
@@ -355,9 +355,33 @@ def soc_leg(args):
             c.close()
             del c
             torch.cuda.empty_cache()
+        if args.soc_batch > 1 and ks:
+            # the same window for a batch of walkers (pqmc_soc_batch_forward_window)
+            k = ks[-1]
+            cs = [SocChain(p.hopping, p.trial, p.U, p.dtau, p.n_slices, p.stab_every, p.seed,
+                           walker_id=w, scheme=Scheme.DELAYED, k=k)
+                  for w in range(args.soc_batch)]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            soc_batch_forward_window(cs, args.soc_window)
+            torch.cuda.synchronize()
+            w = time.perf_counter() - t0
+            one = next((r for r in rows if r["L"] == L and r["scheme"] == "delayed"
+                        and r["k"] == k), None)
+            row = {"L": L, "n_e": N, "scheme": "delayed", "k": k, "walkers": args.soc_batch,
+                   "s_window": w,
+                   "field_updates_per_s": args.soc_batch * args.soc_window * N / w}
+            if one is not None:
+                row["speedup_vs_one_walker"] = row["field_updates_per_s"] / one["field_updates_per_s"]
+            log("soc batch", row)
+            rows.append(row)
+            for c in cs:
+                c.close()
+            del cs
+            torch.cuda.empty_cache()
     return {"model": "Rashba SOC-Hubbard, lambda/t = 0.5, U/t = -4, n = 1, dtau = 0.05, "
-                     "one walker, complex128", "window_slice_visits": args.soc_window,
-            "rows": rows}
+                     "one walker (batched rows: pqmc_soc_batch_forward_window), complex128",
+            "window_slice_visits": args.soc_window, "rows": rows}
 
 
 def mixed_energy(H0, Gu, Gd, U):
@@ -554,6 +578,8 @@ def main():
                     help="block sizes of the SOC block force-bias rows (empty: none)")
     ap.add_argument("--soc-skip-local", action="store_true",
                     help="leave the local update out of the SOC table (profiling runs)")
+    ap.add_argument("--soc-batch", type=int, default=8,
+                    help="walkers of the batched SOC row per lattice size (1: none)")
     ap.add_argument("--soc-window", type=int, default=10,
                     help="forward slice visits per SOC table entry (also k_tau)")
     ap.add_argument("--serve-jobs", type=int, default=32,
