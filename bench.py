@@ -112,26 +112,30 @@ def roofline(p, scheme, k, b, acc, ktimes, cls=None, walkers=1):
             "device_time_share": {c: v / total for c, v in shares.items()}}
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "tile_kernel_40x40_w8_delayed_k32_traffic.txt")
+TRAFFIC_FILES = {
+    "tile": os.path.join(ROOT, "profiles", "tile_kernel_40x40_w8_delayed_k32_traffic.txt"),
+    "local": os.path.join(ROOT, "profiles", "local_site_kernel_40x40_w8_traffic.txt"),
+}
 
 
 def measured_traffic(cls, scheme, k, walkers, workload):
-    """HBM bytes per launch of the tile kernel from the committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE runs (scaled by the same counters on a plain copy
-    of known size), or None when they do not cover this launch or the kernel
-    source has changed since they were taken."""
+    """HBM bytes per launch of the tile kernel or the per-site local kernel
+    from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE runs (scaled by the
+    same counters on a plain copy of known size), or None when they do not
+    cover this launch or the kernel source has changed since they were taken."""
     import hashlib
-    if cls != "tile" or not os.path.exists(TRAFFIC_FILE):
+    path = TRAFFIC_FILES.get(cls)
+    if path is None or not os.path.exists(path):
         return None
     rec = {}
-    for line in open(TRAFFIC_FILE):
+    for line in open(path):
         if ":" in line and not line.startswith("#"):
             key, val = line.split(":", 1)
             rec[key.strip()] = val.strip()
     src = os.path.join(ROOT, "paper_2506_09611_amd", "csrc", "update.hip")
     digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
     if (rec.get("source_sha256") != digest or rec.get("scheme") != scheme
-            or int(rec.get("k", -1)) != k or int(rec.get("walkers", -1)) != walkers
+            or ("k" in rec and int(rec["k"]) != k) or int(rec.get("walkers", -1)) != walkers
             or rec.get("workload") != workload):
         return None
     return float(rec["traffic_bytes_per_launch"])
@@ -664,7 +668,9 @@ def main():
     # forward window after the timed sweeps
     ch.set_opts(ch.scheme, ch.k, ch.b, ktime=True)
     if args.ktime_window > 0:   # the first batch alone, as in the profiled runs
-        batch_forward_window(chains[:W], args.ktime_window)
+        kst = batch_forward_window(chains[:W], args.ktime_window)
+        if args.steps == 0:     # profiling runs: the window's own acceptance
+            acc = sum(x["accepted"] for x in kst) / max(1, sum(x["proposed"] for x in kst))
     ktimes = ch.kernel_times()
     roof = roofline(p, args.scheme, args.k, args.b, acc, ktimes, walkers=W)
     # the rank-n_A flush with the next group's panels, on MFMA (delayed / block)
@@ -782,13 +788,25 @@ def main():
                     x.set_opts(x.scheme, x.k, x.b, site_launches=True)
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
-                st = batch_forward_window(sl, args.local_window)[0]
+                batch_forward_window(sl, args.local_window)
                 torch.cuda.synchronize()
                 w = time.perf_counter() - t0
+                # the per-site kernel against the HBM roofline: one more slice
+                # visit with per-launch events, at that visit's acceptance
+                sl[0].set_opts(sl[0].scheme, sl[0].k, sl[0].b, ktime=True)
+                kst = batch_forward_window(sl, 1)
+                acc_l = sum(x["accepted"] for x in kst) / max(1, sum(x["proposed"] for x in kst))
+                roof_l = roofline(p, "local", args.k, args.b, acc_l, sl[0].kernel_times(),
+                                  "local", walkers=W)
+                if roof_l is not None:
+                    roof_l["traffic"] = measured_traffic("local", "local", args.k, W,
+                                                         args.workload)
+                    roof_l["acceptance"] = acc_l
                 schemes["local_site_launches"] = {
                     "window_slice_visits": args.local_window, "s_window": w,
                     "field_updates_per_s": W * args.local_window * N / w, "walkers": W,
-                    "note": "one launch per site, one batch, forward window"}
+                    "note": "one launch per site, one batch, forward window",
+                    "roofline": roof_l}
                 cs += sl
         else:
             cs = make_walkers(p, name, args.k, args.b, W, streams)
@@ -804,7 +822,7 @@ def main():
         del cs
         torch.cuda.empty_cache()
     for base_name in ("local", "local_g"):
-        if base_name in schemes:
+        if base_name in schemes and schemes[base_name]["field_updates_per_s"] > 0:
             base = schemes[base_name]["field_updates_per_s"]
             for v in schemes.values():
                 v[f"speedup_vs_{base_name}"] = v["field_updates_per_s"] / base

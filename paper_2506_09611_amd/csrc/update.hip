@@ -53,12 +53,24 @@ __device__ __forceinline__ void record_decision(const SweepCtx &c, long long idx
   }
 }
 
-__global__ __launch_bounds__(256) void local_step_kernel(Batch<LocalArgs> B) {
-  const LocalArgs &a = B.w[blockIdx.z];
-  const int s = blockIdx.y;
+// One 256-thread workgroup per 64 x 64 tile of T (16 elements a thread); the
+// flat grid covers (walker, spin, tile) with nt_max^2 tiles per matrix and is
+// padded to a multiple of 8.  XCD-aware: consecutive workgroup ids go
+// round-robin to the 8 XCDs, so XCD x takes the contiguous range
+// [x per, (x + 1) per) of matrix tiles, and the split-K partials of one
+// matrix, which all of its tiles read, are fetched into one L2 rather than
+// eight.  At most 128 VGPRs: four workgroups per CU.
+__global__ __launch_bounds__(256, 4) void local_step_kernel(Batch<LocalArgs> B, int nt2,
+                                                            int total) {
+  const int per = (int)(gridDim.x >> 3);
+  const int lid = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+  if (lid >= total) return;
+  const int mat = lid / nt2;
+  const LocalArgs &a = B.w[mat >> 1];
+  const int s = mat & 1;
   const int Ns = a.m.Ns[s];
   const int nt = (Ns + 63) / 64;
-  const int tile = blockIdx.x;
+  const int tile = lid - mat * nt2;
   const int rb = tile / nt, cb = tile % nt;
   if (rb >= nt) return;
   const int t = threadIdx.x, c = t & 63, rq = t >> 6;
@@ -76,12 +88,14 @@ __global__ __launch_bounds__(256) void local_step_kernel(Batch<LocalArgs> B) {
   __shared__ double s_r[2];
   __shared__ double xs[64], ys[64];
 
+  // unconditional loads from clamped addresses (all sixteen in flight), the
+  // elements outside T zeroed afterwards
   double tv[16];
+  const int colc = min(col, Ns - 1);
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int r = row0 + rq + 4 * q;
-    tv[q] = (r < Ns && colok) ? T[(long)r * Ns + col] : 0.0;
-  }
+  for (int q = 0; q < 16; ++q) tv[q] = T[(long)min(row0 + rq + 4 * q, Ns - 1) * Ns + colc];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) tv[q] = (row0 + rq + 4 * q < Ns && colok) ? tv[q] : 0.0;
   bool dirty = false;
 
   if (i > 0) {
@@ -91,8 +105,17 @@ __global__ __launch_bounds__(256) void local_step_kernel(Batch<LocalArgs> B) {
       const int ss = rq;
       const int nts = (a.m.Ns[ss] + 63) / 64;
       const int ntot = nts * nts;
+      // added in the order e = lane, lane + 64, ...; four loads in flight
+      const double *sp = a.b.spart[ss][par];
       double p = 0.0;
-      for (int e = lane; e < ntot; e += 64) p += a.b.spart[ss][par][e];
+      for (int e0 = lane; e0 < ntot; e0 += 256) {
+        double v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] = sp[min(e0 + 64 * q, ntot - 1)];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (e0 + 64 * q < ntot) p += v[q];
+      }
       p = wave_sum(p);
       if (lane == 0) s_r[ss] = 1.0 + p;
     }
@@ -154,11 +177,11 @@ __global__ __launch_bounds__(256) void local_step_kernel(Batch<LocalArgs> B) {
     const double dl = C.dflip[s][x > 0 ? 0 : 1];
     const double vc = colok ? dl * a.m.ULt[s][(long)i * Ns + col] : 0.0;
     double ur[16];
+    const double *urow = a.m.UR[s] + (long)i * Ns;
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int r = row0 + rq + 4 * q;
-      ur[q] = (r < Ns) ? a.m.UR[s][(long)i * Ns + r] : 0.0;
-    }
+    for (int q = 0; q < 16; ++q) ur[q] = urow[min(row0 + rq + 4 * q, Ns - 1)];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) ur[q] = (row0 + rq + 4 * q < Ns) ? ur[q] : 0.0;
     // y partial (column c, this tile's rows) and (T v) partial (rows, this tile's columns)
     double yp = 0.0, sp = 0.0;
 #pragma unroll
@@ -1442,7 +1465,9 @@ hipError_t local_step(const SpinMats *m, const LocalBufs *b, const SweepCtx *c, 
   if (nw < 1 || nw > kMaxBatch) return hipErrorInvalidValue;
   Batch<LocalArgs> B{};
   for (int w = 0; w < nw; ++w) B.w[w] = LocalArgs{m[w], b[w], c[w], i};
-  hipLaunchKernelGGL(local_step_kernel, dim3(nt_max * nt_max, 2, nw), dim3(256), 0, st, B);
+  const int nt2 = nt_max * nt_max, total = nt2 * 2 * nw;
+  hipLaunchKernelGGL(local_step_kernel, dim3((total + 7) / 8 * 8), dim3(256), 0, st, B, nt2,
+                     total);
   return hipGetLastError();
 }
 

@@ -43,24 +43,37 @@ def test_roofline_fraction_from_launch_times():
     assert sum(r["device_time_share"].values()) == pytest.approx(1.0)
 
 
-def test_traffic_record_matches_only_its_launch():
-    """The committed rocprofv3 traffic covers the 8-walker k = 32 launch of the
-    40x40 workload while the kernel source is the one it was taken on (then it
-    is the recorded figure, above the algorithmic bytes), and nothing else."""
-    import hashlib
+def _record(cls):
     rec = {}
-    for line in open(bench.TRAFFIC_FILE):
+    path = bench.TRAFFIC_FILES[cls]
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
         if ":" in line and not line.startswith("#"):
             key, val = line.split(":", 1)
             rec[key.strip()] = val.strip()
+    return rec
+
+
+def test_traffic_record_matches_only_its_launch():
+    """The committed rocprofv3 traffic covers the 8-walker k = 32 launch of the
+    tile kernel and the 8-walker launch of the per-site local kernel on the
+    40x40 workload while the kernel source is the one it was taken on (then it
+    is the recorded figure, above the algorithmic bytes), and nothing else."""
+    import hashlib
     src = os.path.join(ROOT, "paper_2506_09611_amd", "csrc", "update.hip")
-    fresh = rec["source_sha256"] == hashlib.sha256(open(src, "rb").read()).hexdigest()
-    t = bench.measured_traffic("tile", "delayed", 32, 8, "c3")
-    if fresh:
-        assert t == float(rec["traffic_bytes_per_launch"])
-        assert t > float(rec["algorithmic_bytes_per_launch"])
-    else:
-        assert t is None
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    for cls, scheme in (("tile", "delayed"), ("local", "local")):
+        rec = _record(cls)
+        t = bench.measured_traffic(cls, scheme, 32, 8, "c3")
+        if rec is not None and rec["source_sha256"] == digest:
+            assert t == float(rec["traffic_bytes_per_launch"])
+            assert t > float(rec["algorithmic_bytes_per_launch"])
+        else:
+            assert t is None
+        assert bench.measured_traffic(cls, scheme, 32, 4, "c3") is None
+        assert bench.measured_traffic(cls, scheme, 32, 8, "c2") is None
     assert bench.measured_traffic("tile", "delayed", 16, 8, "c3") is None
-    assert bench.measured_traffic("tile", "delayed", 32, 4, "c3") is None
+    assert bench.measured_traffic("tile", "block", 32, 8, "c3") is None
+    assert bench.measured_traffic("local", "delayed", 32, 8, "c3") is None
     assert bench.measured_traffic("decide", "delayed", 32, 8, "c3") is None
