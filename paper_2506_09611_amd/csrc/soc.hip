@@ -7,10 +7,12 @@
 //                    64 x 64 complex tiles through LDS on FP64 MFMA, up to 8
 //                    products per launch
 //   rotate_kernel    rows (i, N+i) of an n2 x ncols matrix mixed by A(s x_i)
-//   chol_step_kernel S = R^H R (upper R) of a Hermitian positive definite S,
-//                    one launch per pivot row, chol_final_kernel scales the rows
-//   gj_step_kernel   one pivot column of Gauss-Jordan elimination with partial
-//                    pivoting on [M | I], spread over 64-column workgroups
+//   ch_panel_kernel, ch_rows_kernel  R^{-1} for S = R^H R (S Hermitian
+//                    positive definite) by blocked Cholesky-normalised forward
+//                    elimination on [S | I], the trailing update by cgemm
+//   gj_panel_kernel, gj_rows_kernel  blocked Gauss-Jordan inverse with partial
+//                    pivoting on [M | I], 16 pivots a panel, the trailing
+//                    rank-16 update by cgemm
 //   soc_decide_kernel  the decisions of one group of k sites in 2k x 2k space
 //                    (rank-two blocks, Eqs. (A7)-(A9) and the delayed update)
 //   soc_block_decide_kernel  one block force-bias update of b sites in 2b x 2b
@@ -231,128 +233,320 @@ __global__ __launch_bounds__(256) void ident_kernel(double2 *E, long ld, int n, 
 
 // ------------------------------------------------------------ dense LA
 
-// Cholesky S = R^H R (upper R) in place, leading dim ld, without square
-// roots until the end: step j (one launch) subtracts conj(U_jr) U_jc / U_jj
-// from the upper triangle of rows r > j, U being the partially eliminated
-// upper triangle; chol_final_kernel then divides row r by sqrt(U_rr) and
-// zeroes the strict lower triangle.  One wave per row, lanes along it.
-__global__ __launch_bounds__(256) void chol_step_kernel(SocElimBatch B, long ld, int n, int j) {
-  double2 *S = B.E[blockIdx.y];   // one grid row per walker
-  unsigned long long *stats = B.stats[blockIdx.y];
-  const double2 piv = S[(long)j * ld + j];
-  if (!(piv.x > 0.0) || !isfinite(piv.x)) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) stats[kStError] |= kErrSingular;
-    return;
+// ------------------------------------------ blocked Cholesky elimination
+// E = [S | I] (n x 2n, leading dim ld), S Hermitian positive definite.
+// Panel kb (nbp columns), with S11 = C C^H (C lower triangular, positive
+// diagonal) the current diagonal block:
+//   ch_panel_kernel  Z = C^{-1} and W = S11^{-1} = Z^H Z (one workgroup a
+//                    matrix, in LDS);
+//   ch_rows_kernel   the block rows become Z E[b, c], and Bk = W E[b, c], for
+//                    the live columns c in [kb + nbp, n + kb + nbp);
+//   cgemm            E[i, c] -= E[i, panel] Bk[:, c] for the rows below.
+// Row operations only add multiples of earlier rows, so the right half ends
+// as the lower triangular G with G S = R: G = R^{-H}.  During panel kb the
+// right-half entries of the block rows at columns >= n + kb + nbp are still
+// the identity's zeros, which bounds the live columns.  ch_adjoint_kernel
+// finally writes R^{-1} = G^H into the left half.
+__global__ __launch_bounds__(256) void ch_panel_kernel(SocElimBatch B, long ld, int n, int kb) {
+  const int w = blockIdx.x;
+  const double2 *E = B.E[w];
+  double2 *Zg = B.B[w] + (size_t)kGjNb * 2 * n;   // Z, then W
+  const int nbp = min(kGjNb, n - kb);
+  const int t = threadIdx.x, ra = t >> 4, cb = t & 15;
+  static_assert(kGjNb * kGjNb == 256, "one block entry a thread");
+  __shared__ double2 S[kGjNb][kGjNb];   // the block, then C in its lower triangle
+  __shared__ double2 X[kGjNb][kGjNb];   // Z = C^{-1}
+  S[ra][cb] = (ra < nbp && cb < nbp) ? E[(long)(kb + ra) * ld + kb + cb]
+                                     : make_double2(ra == cb ? 1.0 : 0.0, 0.0);
+  __syncthreads();
+  // right-looking: column j of C, then the trailing block loses C_:j C_:j^H
+  bool bad = false;
+  for (int j = 0; j < nbp; ++j) {
+    const double d = S[j][j].x;
+    bad = bad || !(d > 0.0) || !isfinite(d);
+    const double2 sij = S[ra][j], skj = S[cb][j], x = S[ra][cb];
+    __syncthreads();
+    const double cj = sqrt(d), ic = 1.0 / cj, id = 1.0 / d;
+    if (cb == j && ra >= j)
+      S[ra][j] = ra == j ? make_double2(cj, 0.0) : make_double2(sij.x * ic, sij.y * ic);
+    else if (ra > j && cb > j) {
+      const double2 p = cmul(sij, cconj(skj));
+      S[ra][cb] = make_double2(x.x - p.x * id, x.y - p.y * id);
+    }
+    __syncthreads();
   }
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int r = j + 1 + blockIdx.x * 4 + wave;
-  if (r >= n) return;
-  const double inv = 1.0 / piv.x;
-  const double2 ujr = S[(long)j * ld + r];
-  const double2 a = make_double2(ujr.x * inv, -ujr.y * inv);   // conj(U_jr) / U_jj
-  const double2 *rowj = S + (long)j * ld;
-  double2 *rowr = S + (long)r * ld;
-  for (int c = r + lane; c < n; c += 64) rowr[c] = csub(rowr[c], cmul(a, rowj[c]));
+  // Z = C^{-1} by forward substitution, one row of Z a step
+  for (int i = 0; i < kGjNb; ++i) {
+    if (ra == i) {
+      double2 acc = make_double2(0.0, 0.0);
+      for (int k = cb; k < i; ++k) cfma(acc, S[i][k], X[k][cb]);
+      const double ici = 1.0 / S[i][i].x;
+      X[i][cb] = cb > i    ? make_double2(0.0, 0.0)
+                 : cb == i ? make_double2(ici, 0.0)
+                           : make_double2(-acc.x * ici, -acc.y * ici);
+    }
+    __syncthreads();
+  }
+  double2 wv = make_double2(0.0, 0.0);
+#pragma unroll
+  for (int k = 0; k < kGjNb; ++k) cfma(wv, cconj(X[k][ra]), X[k][cb]);
+  const bool in = ra < nbp && cb < nbp;
+  Zg[t] = in ? X[ra][cb] : make_double2(0.0, 0.0);
+  Zg[kGjNb * kGjNb + t] = in ? wv : make_double2(0.0, 0.0);
+  if (bad && t == 0) B.stats[w][kStError] |= kErrSingular;
 }
 
-__global__ __launch_bounds__(256) void chol_final_kernel(SocElimBatch B, long ld, int n) {
-  double2 *S = B.E[blockIdx.y];
-  unsigned long long *stats = B.stats[blockIdx.y];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int r = blockIdx.x * 4 + wave;
-  if (r >= n) return;
-  double2 *row = S + (long)r * ld;
-  const double d2 = row[r].x;
-  if (!(d2 > 0.0) || !isfinite(d2)) {
-    if (lane == 0) stats[kStError] |= kErrSingular;
-    return;
+// Block rows E[kb + a][c] <- (Z x)_a and Bk[a][c] = (W x)_a with x = E[kb .. kb
+// + nbp)[c], for c in [kb + nbp, n + kb + nbp); 64 columns a workgroup, four
+// output rows a thread.  The block rows are staged in LDS, so every read of
+// a column precedes (by a barrier) its rewrite.
+__global__ __launch_bounds__(256) void ch_rows_kernel(SocElimBatch B, long ld, int n, int kb) {
+  const int w = blockIdx.y;
+  double2 *E = B.E[w];
+  const double2 *Zg = B.B[w] + (size_t)kGjNb * 2 * n;
+  double2 *Bk = B.B[w];
+  const int nbp = min(kGjNb, n - kb), c0 = kb + nbp, c1 = n + c0, n2 = 2 * n;
+  const int t = threadIdx.x, g = t >> 6, lc = t & 63;
+  const int col = c0 + (int)blockIdx.x * 64 + lc;
+  __shared__ double2 Zs[kGjNb][kGjNb], Ws[kGjNb][kGjNb], Xs[kGjNb][64];
+  Zs[t >> 4][t & 15] = Zg[t];
+  Ws[t >> 4][t & 15] = Zg[kGjNb * kGjNb + t];
+  const int cc = min(col, c1 - 1);
+#pragma unroll
+  for (int q = 0; q < kGjNb / 4; ++q)
+    Xs[g + 4 * q][lc] = E[(long)(kb + min(g + 4 * q, nbp - 1)) * ld + cc];
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kGjNb / 4; ++q) {
+    const int a = g + 4 * q;
+    double2 y = make_double2(0.0, 0.0), v = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int b = 0; b < kGjNb; ++b) {
+      const double2 xb = Xs[b][lc];
+      cfma(y, Zs[a][b], xb);
+      cfma(v, Ws[a][b], xb);
+    }
+    if (a < nbp && col < c1) {
+      E[(long)(kb + a) * ld + col] = y;
+      Bk[(long)a * n2 + col] = v;
+    }
   }
-  const double inv = 1.0 / sqrt(d2);
-  for (int c = lane; c < n; c += 64)
-    row[c] = c < r ? make_double2(0.0, 0.0) : make_double2(row[c].x * inv, row[c].y * inv);
 }
 
-// One Gauss-Jordan step (pivot column j) on E = [A | B] (n x 2n, leading
-// dim ld), spread over workgroups of 64 columns each.  colin holds column j
-// as left by step j - 1; every workgroup finds the same pivot in it (largest
-// modulus over rows >= j, ties to the smaller row), the rows j and p are
-// swapped, row j is divided by the pivot and column j is eliminated from
-// every other row (8 columns per workgroup, so that a 1024-pivot inverse
-// spreads over 256 workgroups).  The workgroup that owns column j + 1 writes that column,
-// as this step leaves it, to colout for the next step.  Columns left of j
-// are unit vectors already and are skipped.
-constexpr int kGjCols = 8;    // columns per workgroup (256 threads: 32 row groups)
-__global__ __launch_bounds__(256) void gj_step_kernel(SocElimBatch B, long ld, int n, int j) {
-  double2 *E = B.E[blockIdx.y];   // one grid row per walker
-  const double2 *colin = B.col[blockIdx.y] + (size_t)(j & 1) * n;
-  double2 *colout = B.col[blockIdx.y] + (size_t)((j + 1) & 1) * n;
-  unsigned long long *stats = B.stats[blockIdx.y];
-  __shared__ double2 col[1024];
-  __shared__ double wbest[4];
-  __shared__ int wbi[4];
-  __shared__ int piv;
-  __shared__ double2 rjv[kGjCols], vpv[kGjCols];
-  const int c0 = blockIdx.x * kGjCols;
-  if (c0 + kGjCols <= j) return;
+// left half <- (right half)^H, 16 x 16 tiles through LDS
+__global__ __launch_bounds__(256) void ch_adjoint_kernel(SocElimBatch B, long ld, int n) {
+  double2 *E = B.E[blockIdx.z];
+  __shared__ double2 tile[16][17];
+  const int t = threadIdx.x, i = t >> 4, j = t & 15;
+  const int r0 = blockIdx.y * 16, c0 = blockIdx.x * 16;
+  // read G[r0 + i][c0 + j] (right half), write conj into left [c0 + i][r0 + j]
+  if (r0 + i < n && c0 + j < n) tile[i][j] = E[(long)(r0 + i) * ld + n + c0 + j];
+  __syncthreads();
+  if (c0 + i < n && r0 + j < n) E[(long)(c0 + i) * ld + r0 + j] = cconj(tile[j][i]);
+}
+
+// ------------------------------------------------ blocked Gauss-Jordan
+// E = [M | I] (n x 2n, leading dim ld) is inverted in panels of kGjNb pivot
+// columns kb .. kb + nbp - 1, three launches per panel for the whole batch:
+//   gj_panel_kernel  one workgroup per matrix holds the panel's columns of
+//                    every row in registers and takes the panel's pivots by
+//                    partial pivoting on the Schur complement among the rows
+//                    not used yet (no rows are moved), then inverts the pivot
+//                    block D = E[R, panel] (rows R in pivot order): Z = D^{-1};
+//   gj_rows_kernel   the new block rows B = Z E[R, c] for the live columns
+//                    c >= kb + nbp;
+//   cgemm            E[:, c] -= E[:, panel] B[:, c] for every row (MFMA).
+// The pivot rows must become B itself: the panel kernel subtracts 1 from
+// their pivot entries E[R_a, kb + a] (the panel's columns are not read
+// again), so that the same rank-nbp product leaves E[R_a] - (D - I)_a B = B_a.
+// After the last panel row prow[c] holds (e_c | row c of M^{-1}), and
+// gj_gather_kernel writes M^{-1} into the left half.  Row r counts as used
+// once piv[n + r] = c < kb with piv[c] = r, so the scratch needs no clearing
+// between inversions (a stale entry fails the test).
+constexpr int kGjThreads = 512;   // panel kernel: rows t and t + 512 (n <= 1024)
+
+__device__ __forceinline__ unsigned long long shfl_xor_u64(unsigned long long v, int m) {
+  const int lo = __shfl_xor((int)(unsigned)v, m, 64);
+  const int hi = __shfl_xor((int)(unsigned)(v >> 32), m, 64);
+  return ((unsigned long long)(unsigned)hi << 32) | (unsigned long long)(unsigned)lo;
+}
+
+__global__ __launch_bounds__(kGjThreads) void gj_panel_kernel(SocElimBatch B, long ld, int n,
+                                                              int kb) {
+  const int w = blockIdx.x;
+  double2 *E = B.E[w];
+  int *prow = B.piv[w], *slot = B.piv[w] + n;
+  double2 *Z = B.B[w] + (size_t)kGjNb * 2 * n;
+  const int nbp = min(kGjNb, n - kb);
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  for (int r = t; r < n; r += 256) col[r] = colin[r];
-  __syncthreads();
-  double bv = -1.0;
-  int bi = n;
-  for (int r = j + t; r < n; r += 256) {
-    const double a = hypot(col[r].x, col[r].y);
-    if (a > bv) { bv = a; bi = r; }
+  constexpr int kWaves = kGjThreads / 64;
+  __shared__ unsigned long long wkey[2][kWaves];
+  __shared__ double2 wrow[2][kWaves][kGjNb];
+  __shared__ double2 D[kGjNb][2 * kGjNb];
+  __shared__ int rows[kGjNb];
+
+  // the panel's entries of rows t and t + 512 (clamped addresses, all loads
+  // in flight together), and whether each row is still unused
+  double2 a[2][kGjNb];
+  int r[2], sl[2];
+  bool live[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    r[i] = t + kGjThreads * i;
+    const int rc = min(r[i], n - 1);
+#pragma unroll
+    for (int j = 0; j < kGjNb; ++j) a[i][j] = E[(long)rc * ld + kb + min(j, nbp - 1)];
+    sl[i] = slot[rc];
   }
-  for (int off = 32; off > 0; off >>= 1) {
-    const double ov = __shfl_down(bv, off, 64);
-    const int oi = __shfl_down(bi, off, 64);
-    if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const bool cand = sl[i] >= 0 && sl[i] < kb;
+    const int pr = prow[cand ? sl[i] : 0];
+    live[i] = r[i] < n && !(cand && pr == r[i]);
   }
-  if (lane == 0) { wbest[wave] = bv; wbi[wave] = bi; }
-  __syncthreads();
-  if (t == 0) {
-    double b = -1.0;
-    int p = n;
-    for (int w = 0; w < 4; ++w)
-      if (wbest[w] > b || (wbest[w] == b && wbi[w] < p)) { b = wbest[w]; p = wbi[w]; }
-    piv = (b > 0.0 && isfinite(b)) ? p : -1;
-    if (piv < 0 && blockIdx.x == 0) stats[kStError] |= kErrSingular;
+
+  // per column: the largest |entry|^2 among unused rows wins; the key packs
+  // its IEEE bits (a non-negative double orders like its bit pattern) with
+  // 2047 - row in the low 11 bits, so ties go to the smaller row and the
+  // reduction is an integer max.  Each wave's winner puts its key and its
+  // panel row in LDS (double-buffered by column parity: one barrier a column).
+  // The register rows are shifted one column left after each column, so the
+  // current column is always a[i][0] and no register is indexed by j.
+  bool singular = false;
+  for (int j = 0; j < nbp; ++j) {
+    const int bf = j & 1;
+    unsigned long long best = 0;
+    int bi = 0;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const double m = a[i][0].x * a[i][0].x + a[i][0].y * a[i][0].y;
+      const unsigned long long key = ((unsigned long long)__double_as_longlong(m) & ~0x7FFull) |
+                                     (unsigned long long)(2047 - r[i]);
+      if (live[i] && key > best) {
+        best = key;
+        bi = i;
+      }
+    }
+    unsigned long long wb = best;
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) {
+      const unsigned long long o = shfl_xor_u64(wb, m);
+      wb = o > wb ? o : wb;
+    }
+    // (two stores with constant register indices: a select between the rows
+    // would index the register array at run time and move it to scratch)
+    if (wb != 0 && best == wb) {
+      wkey[bf][wave] = wb;
+      if (bi == 0) {
+#pragma unroll
+        for (int c = 0; c < kGjNb; ++c) wrow[bf][wave][c] = a[0][c];
+      } else {
+#pragma unroll
+        for (int c = 0; c < kGjNb; ++c) wrow[bf][wave][c] = a[1][c];
+      }
+    }
+    if (wb == 0 && lane == 0) wkey[bf][wave] = 0;
+    __syncthreads();
+    unsigned long long kmax = 0;
+    int wv = 0;
+#pragma unroll
+    for (int v = 0; v < kWaves; ++v) {
+      const unsigned long long k = wkey[bf][v];
+      if (k > kmax) {
+        kmax = k;
+        wv = v;
+      }
+    }
+    // an unused row always exists, so kmax >= 1024 names one (the clamp
+    // only keeps the indices in range should that ever fail)
+    const int p = min(2047 - (int)(kmax & 0x7FF), n - 1);
+    const double2 d = wrow[bf][wv][0];
+    const double dm = d.x * d.x + d.y * d.y;
+    singular = singular || kmax < 1024 || !(dm > 0.0) || !isfinite(dm);
+    const double2 inv = make_double2(d.x / dm, -d.y / dm);
+    if (t == 0) {
+      prow[kb + j] = p;
+      slot[p] = kb + j;
+      rows[j] = p;
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      if (r[i] == p) live[i] = false;
+      if (live[i]) {
+        const double2 f = cmul(a[i][0], inv);
+#pragma unroll
+        for (int c = 1; c < kGjNb; ++c) a[i][c] = csub(a[i][c], cmul(f, wrow[bf][wv][c]));
+      }
+#pragma unroll
+      for (int c = 0; c + 1 < kGjNb; ++c) a[i][c] = a[i][c + 1];
+      a[i][kGjNb - 1] = make_double2(0.0, 0.0);
+    }
   }
   __syncthreads();
-  const int p = piv;
-  if (p < 0) return;
-  const double2 d = col[p];
-  const int cl = t & (kGjCols - 1), rg = t / kGjCols;
-  constexpr int kRowGroups = 256 / kGjCols;
-  const int c = c0 + cl;
-  const bool live = c < 2 * n && (c >= j || c >= n);
-  if (rg == 0 && live) {
-    const double2 vj = E[(long)p * ld + c], vp = E[(long)j * ld + c];
-    const double2 rj = cdiv(vj, d);
-    rjv[cl] = rj;
-    vpv[cl] = vp;
-    E[(long)j * ld + c] = rj;
-    if (c == j + 1) colout[j] = rj;
+  // [D | I] in LDS, D extended by the identity to kGjNb x kGjNb; its
+  // elimination needs no pivoting (D's rows are in the order of the pivots
+  // just taken), one thread per entry of the 16 x 32 block
+  const int ra = t >> 5, cb = t & 31;
+  {
+    double2 v;
+    if (cb < kGjNb && ra < nbp && cb < nbp)
+      v = E[(long)rows[ra] * ld + kb + cb];
+    else
+      v = make_double2((cb & (kGjNb - 1)) == ra ? 1.0 : 0.0, 0.0);
+    D[ra][cb] = v;
   }
   __syncthreads();
-  if (!live) return;
-  const double2 rj = rjv[cl];
-  for (int r = rg; r < n; r += kRowGroups) {
-    if (r == j) continue;
-    const double2 f = (r == p) ? col[j] : col[r];
-    const double2 v = (r == p) ? vpv[cl] : E[(long)r * ld + c];
-    const double2 x = csub(v, cmul(f, rj));
-    E[(long)r * ld + c] = x;
-    if (c == j + 1) colout[r] = x;
+  for (int s = 0; s < nbp; ++s) {
+    const double2 x = D[ra][cb], das = D[ra][s], dsb = D[s][cb], ps = D[s][s];
+    __syncthreads();
+    const double pm = ps.x * ps.x + ps.y * ps.y;
+    const double2 rowv = cmul(dsb, make_double2(ps.x / pm, -ps.y / pm));
+    D[ra][cb] = ra == s ? rowv : csub(x, cmul(das, rowv));
+    __syncthreads();
+  }
+  if (cb >= kGjNb)
+    Z[ra * kGjNb + cb - kGjNb] =
+        (ra < nbp && cb - kGjNb < nbp) ? D[ra][cb] : make_double2(0.0, 0.0);
+  if (t < nbp) E[(long)rows[t] * ld + kb + t].x -= 1.0;
+  if (singular && t == 0) B.stats[w][kStError] |= kErrSingular;
+}
+
+// B[a][c] = sum_b Z[a][b] E[R_b][c] for a < nbp and the live columns
+// c >= kb + nbp; 64 columns a workgroup, four rows of B a thread.
+__global__ __launch_bounds__(256) void gj_rows_kernel(SocElimBatch B, long ld, int n, int kb) {
+  const int w = blockIdx.y;
+  const double2 *E = B.E[w];
+  const int *prow = B.piv[w];
+  const double2 *Z = B.B[w] + (size_t)kGjNb * 2 * n;
+  double2 *Bk = B.B[w];
+  const int nbp = min(kGjNb, n - kb), c0 = kb + nbp, n2 = 2 * n;
+  const int t = threadIdx.x, g = t >> 6;
+  const int col = c0 + (int)blockIdx.x * 64 + (t & 63);
+  __shared__ double2 Zs[kGjNb][kGjNb];
+  static_assert(kGjNb * kGjNb == 256, "one Z entry a thread");
+  Zs[t >> 4][t & 15] = Z[t];
+  __syncthreads();
+  const int cc = min(col, n2 - 1);
+  double2 x[kGjNb];
+#pragma unroll
+  for (int b = 0; b < kGjNb; ++b) x[b] = E[(long)prow[kb + min(b, nbp - 1)] * ld + cc];
+#pragma unroll
+  for (int q = 0; q < kGjNb / 4; ++q) {
+    const int ar = g + 4 * q;
+    double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int b = 0; b < kGjNb; ++b) cfma(acc, Zs[ar][b], x[b]);
+    if (ar < nbp && col < n2) Bk[(long)ar * n2 + col] = acc;
   }
 }
 
-// colout[r] = E[r][0]
-__global__ __launch_bounds__(256) void col0_kernel(SocElimBatch B, long ld, int n) {
-  const double2 *E = B.E[blockIdx.y];
-  double2 *colout = B.col[blockIdx.y];
-  const int r = blockIdx.x * 256 + threadIdx.x;
-  if (r < n) colout[r] = E[(long)r * ld];
+// left half row c <- right half of row prow[c] (= row c of M^{-1})
+__global__ __launch_bounds__(256) void gj_gather_kernel(SocElimBatch B, long ld, int n) {
+  double2 *E = B.E[blockIdx.y];
+  const int c = blockIdx.x;
+  const double2 *src = E + (long)B.piv[blockIdx.y][c] * ld + n;
+  double2 *dst = E + (long)c * ld;
+  for (int j = threadIdx.x; j < n; j += 256) dst[j] = src[j];
 }
 
 // --------------------------------------------------------------- decisions
@@ -1087,23 +1281,52 @@ hipError_t set_identity(double2 *E, long ld, int n, int off, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t cholesky(const SocElimBatch &b, long ld, int n, hipStream_t st) {
-  if (n < 1 || b.n < 1) return hipSuccess;
-  if (b.n > kSocMaxBatch) return hipErrorInvalidValue;
-  for (int j = 0; j + 1 < n; ++j) {
-    const int rows = n - j - 1;
-    hipLaunchKernelGGL(chol_step_kernel, dim3((rows + 3) / 4, b.n), dim3(256), 0, st, b, ld, n, j);
+hipError_t chol_inverse(const SocElimBatch &b, long ld, int n, hipStream_t st) {
+  if (n < 1 || n > 1024 || b.n < 1 || b.n > kSocMaxBatch) return hipErrorInvalidValue;
+  for (int kb = 0; kb < n; kb += kGjNb) {
+    const int nbp = min(kGjNb, n - kb), c0 = kb + nbp;
+    hipLaunchKernelGGL(ch_panel_kernel, dim3(b.n), dim3(256), 0, st, b, ld, n, kb);
+    hipLaunchKernelGGL(ch_rows_kernel, dim3((n + 63) / 64, b.n), dim3(256), 0, st, b, ld, n, kb);
+    if (c0 >= n) continue;
+    CgemmBatch g{};
+    for (int w = 0; w < b.n; ++w) {
+      CgemmDesc d = cdesc(b.E[w] + (long)c0 * ld + kb, ld, b.B[w] + c0, 2L * n,
+                          b.E[w] + (long)c0 * ld + c0, ld, n - c0, n, nbp);
+      d.Cin = d.C;
+      d.ldcin = ld;
+      d.alpha = make_double2(-1.0, 0.0);
+      d.beta = make_double2(1.0, 0.0);
+      g.d[g.count++] = d;
+    }
+    const hipError_t e = cgemm(g, kOpN, kOpN, st);
+    if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(chol_final_kernel, dim3((n + 3) / 4, b.n), dim3(256), 0, st, b, ld, n);
+  const int nt = (n + 15) / 16;
+  hipLaunchKernelGGL(ch_adjoint_kernel, dim3(nt, nt, b.n), dim3(256), 0, st, b, ld, n);
   return hipGetLastError();
 }
 
 hipError_t gj_inverse(const SocElimBatch &b, long ld, int n, hipStream_t st) {
   if (n < 1 || n > 1024 || b.n < 1 || b.n > kSocMaxBatch) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(col0_kernel, dim3((n + 255) / 256, b.n), dim3(256), 0, st, b, ld, n);
-  const dim3 grid((2 * n + kGjCols - 1) / kGjCols, b.n);
-  for (int j = 0; j < n; ++j)
-    hipLaunchKernelGGL(gj_step_kernel, grid, dim3(256), 0, st, b, ld, n, j);
+  for (int kb = 0; kb < n; kb += kGjNb) {
+    const int nbp = min(kGjNb, n - kb), c0 = kb + nbp;
+    hipLaunchKernelGGL(gj_panel_kernel, dim3(b.n), dim3(kGjThreads), 0, st, b, ld, n, kb);
+    hipLaunchKernelGGL(gj_rows_kernel, dim3((2 * n - c0 + 63) / 64, b.n), dim3(256), 0, st, b, ld,
+                       n, kb);
+    CgemmBatch g{};
+    for (int w = 0; w < b.n; ++w) {
+      CgemmDesc d = cdesc(b.E[w] + kb, ld, b.B[w] + c0, 2L * n, b.E[w] + c0, ld, n, 2 * n - c0,
+                          nbp);
+      d.Cin = b.E[w] + c0;
+      d.ldcin = ld;
+      d.alpha = make_double2(-1.0, 0.0);
+      d.beta = make_double2(1.0, 0.0);
+      g.d[g.count++] = d;
+    }
+    const hipError_t e = cgemm(g, kOpN, kOpN, st);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(gj_gather_kernel, dim3(n, b.n), dim3(256), 0, st, b, ld, n);
   return hipGetLastError();
 }
 

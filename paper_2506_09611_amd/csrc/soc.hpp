@@ -58,20 +58,32 @@ hipError_t conj_copy(const double2 *X, double2 *Y, long n, hipStream_t st);
 hipError_t set_identity(double2 *E, long ld, int n, int off, hipStream_t st);
 // Walkers of one SOC batch: all share n2, n_e, M, k_tau, the scheme and k.
 constexpr int kSocMaxBatch = 8;
+// Pivots per panel of the blocked Gauss-Jordan inverse.
+constexpr int kGjNb = 16;
+// complex128 scratch of one walker's blocked eliminations of order n (block
+// rows kGjNb x 2n, then two kGjNb x kGjNb blocks), and the int scratch of
+// the Gauss-Jordan inverse (pivot row of each column, pivot column of each row)
+inline size_t gj_scratch_complex(size_t n) { return kGjNb * 2 * n + 2 * kGjNb * kGjNb; }
+inline size_t gj_scratch_int(size_t n) { return 2 * n; }
 // The matrices of a batched elimination, one per walker: E (n x 2n or
-// n x n, leading dim ld), its pivot-column scratch (2n) and error flags.
+// n x n, leading dim ld), the Gauss-Jordan scratch and error flags.
 struct SocElimBatch {
   double2 *E[kSocMaxBatch];
-  double2 *col[kSocMaxBatch];
+  double2 *B[kSocMaxBatch];   // gj_scratch_complex(n)
+  int *piv[kSocMaxBatch];     // gj_scratch_int(n)
   unsigned long long *stats[kSocMaxBatch];
   int n;
 };
-// upper triangle of each S = E[w] (n x n, leading dim ld, Hermitian positive
-// definite) <- R with S = R^H R; strict lower triangle <- 0
-hipError_t cholesky(const SocElimBatch &b, long ld, int n, hipStream_t st);
-// each E[w] = [M | I] (n x 2n, leading dim ld) -> [I | M^{-1}] by Gauss-Jordan
-// with partial pivoting, one launch per pivot column for the whole batch;
-// col[w]: 2n scratch; n <= 1024
+// each E[w] = [S | I] (n x 2n, leading dim ld), S Hermitian positive
+// definite: the left half <- R^{-1} with S = R^H R, R upper triangular with
+// a positive diagonal, by blocked Cholesky-normalised forward elimination
+// (kGjNb columns a panel, three launches per panel for the whole batch; the
+// right half ends as R^{-H}); n <= 1024
+hipError_t chol_inverse(const SocElimBatch &b, long ld, int n, hipStream_t st);
+// each E[w] = [M | I] (n x 2n, leading dim ld): the left half <- M^{-1} by
+// blocked Gauss-Jordan elimination with partial pivoting (kGjNb pivots per
+// panel, three launches per panel for the whole batch; the right half is
+// left overwritten); n <= 1024
 hipError_t gj_inverse(const SocElimBatch &b, long ld, int n, hipStream_t st);
 
 constexpr int kSocMaxK = 32;   // group size of the decision kernel (2k x 2k in LDS)

@@ -33,9 +33,10 @@ struct pqmc_soc_ctx {
   double2 *Rw[2] = {nullptr, nullptr}, *Lw[2] = {nullptr, nullptr}, *Xtmp = nullptr;
   double2 *UR = nullptr, *ULt = nullptr;            // current (a slot or a work buffer)
   double2 *E = nullptr;                             // ne x 2ne: [U_L U_R | I] -> [I | T]
-  double2 *T = nullptr;                             // = E + ne, leading dim 2 ne
+  double2 *T = nullptr;                             // = E (left half), leading dim 2 ne
   long ldT = 0;
-  double2 *colbuf = nullptr;                        // 2 ne: Gauss-Jordan pivot columns
+  double2 *gjB = nullptr;                           // Gauss-Jordan block rows and Z
+  int *gjP = nullptr;                               // Gauss-Jordan pivot order
   double2 *P2 = nullptr, *P1 = nullptr, *W0 = nullptr, *D = nullptr, *Q = nullptr;
   double2 *P2part = nullptr, *P1part = nullptr, *W0part = nullptr;   // split-K slices
   int ksplit = 0;                                   // depth per slice (0: no split)
@@ -153,9 +154,10 @@ void layout(pqmc_soc_ctx &c, char *base, size_t *bytes) {
   }
   c.Xtmp = cv.take<double2>(n2 * ne);
   c.E = cv.take<double2>(ne * 2 * ne);
-  c.T = c.E ? c.E + ne : nullptr;
+  c.T = c.E;
   c.ldT = 2L * (long)ne;
-  c.colbuf = cv.take<double2>(2 * ne);
+  c.gjB = cv.take<double2>(gj_scratch_complex(ne));
+  c.gjP = cv.take<int>(gj_scratch_int(ne));
   c.P2 = cv.take<double2>(kn * ne);
   c.P1 = cv.take<double2>(ne * kn);
   c.W0 = cv.take<double2>(kn * kn);
@@ -266,7 +268,8 @@ SocElimBatch elim_batch(const SocWalkers &b) {
   SocElimBatch e{};
   for (int i = 0; i < b.n; ++i) {
     e.E[i] = b[i].E;
-    e.col[i] = b[i].colbuf;
+    e.B[i] = b[i].gjB;
+    e.piv[i] = b[i].gjP;
     e.stats[i] = b[i].stats;
   }
   e.n = b.n;
@@ -274,7 +277,7 @@ SocElimBatch elim_batch(const SocWalkers &b) {
 }
 
 // dst[i] = A[i] R^{-1} with A^H A = R^H R (A: n2 x ne): columns orthonormalised.
-// E serves as scratch: [A^H A | I] -> [R | I] -> [I | R^{-1}].
+// E serves as scratch: [A^H A | I] -> R^{-1} in the left half.
 int orthonormalize(const SocWalkers &b, const double2 *const *A, double2 *const *dst) {
   pqmc_soc_ctx &L = b.lead();
   const int n2 = L.n2, ne = L.ne;
@@ -286,19 +289,17 @@ int orthonormalize(const SocWalkers &b, const double2 *const *A, double2 *const 
   }
   int rc = gram.flush();
   if (rc) return rc;
-  const SocElimBatch eb = elim_batch(b);
-  PQ_HIP_CHECK(cholesky(eb, ld, ne, L.st));
   for (int i = 0; i < b.n; ++i) PQ_HIP_CHECK(set_identity(b[i].E, ld, ne, ne, L.st));
-  PQ_HIP_CHECK(gj_inverse(eb, ld, ne, L.st));
+  PQ_HIP_CHECK(chol_inverse(elim_batch(b), ld, ne, L.st));
   CgemmQueue out{L.st, kOpN, kOpN};
   for (int i = 0; i < b.n; ++i) {
-    rc = out.add(cdesc(A[i], ne, b[i].E + ne, ld, dst[i], ne, n2, ne, ne));
+    rc = out.add(cdesc(A[i], ne, b[i].E, ld, dst[i], ne, n2, ne, ne));
     if (rc) return rc;
   }
   return out.flush();
 }
 
-// T = (U_L U_R)^{-1} = (ULt^T UR)^{-1}, in the right half of E
+// T = (U_L U_R)^{-1} = (ULt^T UR)^{-1}, in the left half of E
 int refresh_T(const SocWalkers &b) {
   pqmc_soc_ctx &L = b.lead();
   const int n2 = L.n2, ne = L.ne;

@@ -155,6 +155,33 @@ def test_soc_24x24_full_sweep(scheme, k):
     ch.close()
 
 
+@pytest.mark.timeout(600)
+def test_soc_32x32_largest_inverse():
+    """L = 32 at n = 1 (2N = 2048, N_e = 1024): the largest order of the
+    blocked Gauss-Jordan inverse (64 panels of 16 pivots).  The initial G and,
+    after a 10-slice delayed window across two stabilisations, the decisions,
+    fields and G against the oracle; and G is still the projector
+    1 - U_R (U_L U_R)^{-1} U_L: G^2 = G, tr G = 2N - N_e."""
+    p = synth.make_soc_problem(32, 1024, -4.0, lam=0.5, dtau=0.05, n_slices=10, stab_every=5,
+                               perturb=1e-3, seed=synth.SEED_BASE + 105)
+    ch = _chain(p, "delayed", 32)
+    w = _walker(p, "delayed", 32)
+    G, Gr = ch.green(), w.green()
+    err = np.max(np.abs(G - Gr)) / max(1.0, np.max(np.abs(Gr)))
+    print(f"32x32 soc initial G rel err {err:.2e}", flush=True)
+    assert err < 1e-10
+    ch.forward_window(10)
+    w.forward_window(10)
+    _check(ch, w, 0, p.n_slices, "32x32 soc delayed k=32 window")
+    G = ch.green()
+    idem = np.max(np.abs(G @ G - G)) / max(1.0, np.max(np.abs(G)))
+    tr = np.trace(G)
+    print(f"32x32 soc: |G^2 - G| {idem:.2e}, tr G {tr.real:.12f}{tr.imag:+.2e}i", flush=True)
+    assert idem < 1e-9
+    assert abs(tr - (2048 - 1024)) < 1e-8
+    ch.close()
+
+
 def test_soc_full_filling_and_single_site():
     """N_e = 2N (U_R square): every ratio is det A(-2x) = 1, so every flip is
     accepted and G = 0; and the single-site lattice (2 orbitals, both filled:
