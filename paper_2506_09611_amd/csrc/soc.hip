@@ -556,29 +556,39 @@ __global__ __launch_bounds__(256) void gj_gather_kernel(SocElimBatch B, long ld,
 // Out: D (n x n) = delta_bd Mc, Mc = (1 + W0_AA)^{-1} spread to n x n (zero
 // outside the accepted set A), so that T = T0 - (T0 U_L[:, g]) D (W_g T0);
 // *nflush = n if A is not empty, else 0; accepted sites' fields flipped and
-// their rows of U_R rotated by A(-2x) = 1 + delta.
+// accx[j] = their old field (rotate_accepted then turns their U_R rows).
+//
+// The decisions sweep pivots out of E = 1 + W0 (W0 = W0p with each site's
+// flip block on its column pair).  Once the 2 x 2 pivot blocks of the
+// accepted sites are swept (principal pivot transform), every unswept pivot
+// block E_JJ, J = (j, kk + j), is its Schur complement given A: the current
+// 1 + W_j T V_j, whose determinant is site j's ratio (Eqs. (A7)-(A9)); and
+// the swept block E_AA is -(1 + W0_AA)^{-1}.  Accepting site j sweeps J with
+// S = E_JJ:
+//   E_rc -= E_rJ S^{-1} E_Jc,  E_rJ <- E_rJ S^{-1},  E_Jc <- S^{-1} E_Jc,
+//   E_JJ <- -S^{-1}            (r, c outside J).
+// All four cases are one formula, E_rc -= e_r g_c, with e_r = E_rJ - [r in J]
+// (the unit row of r's place in J), g_c = S^{-1} E_Jc for c outside J and
+// g_c = u_c - S^{-1} u_c for c in J, and -2 on the two diagonal entries of
+// J.  E lives in registers (thread t: column t % 64, rows t / 64 + 4 i); per
+// site the owners of J's two rows and two columns publish them in LDS
+// (double-buffered by site parity: one barrier a site), every thread reads
+// the pivot block and takes the same decision, and a rejected site changes
+// nothing.
 constexpr int kDecThreads = 256;
 
 __global__ __launch_bounds__(kDecThreads) void soc_decide_kernel(SocDecideBatch B) {
   const SocDecideArgs &a = B.a[blockIdx.x];   // one workgroup per walker
-  extern __shared__ double2 lds[];
+  extern __shared__ double2 Ms[];      // n x (n + 1): Mc at the end
   const int kk = a.kk, n = 2 * kk;
-  // rows padded by one element: lanes walking down a column hit distinct banks
   const int ld = n + 1;
-  double2 *W0 = lds;                 // n x n, leading dim ld
-  double2 *Mc = W0 + n * ld;         // n x n, leading dim ld
-  double2 *u = Mc + n * ld;          // n x 2: Mc W0[:, jc]
-  double2 *w = u + 2 * n;            // 2 x n: W0[jr, :] Mc
-  __shared__ double2 Sinv[4];
-  __shared__ double2 Sm[4];
-  __shared__ double2 Gm[2 * 64];
-  __shared__ int accs;
   __shared__ double xs[64];
-  __shared__ double us[64];       // the group's Metropolis uniforms (independent of decisions)
+  __shared__ double us[64];            // the group's Metropolis uniforms (independent of decisions)
   __shared__ int accm[64];
-  __shared__ int n_acc;
-  const int t = threadIdx.x;
-  int n_low = 0, n_neg = 0;       // thread 0's counters
+  __shared__ double2 colJ[2][2][64];   // [site parity][J place][row]
+  __shared__ double2 rowJ[2][2][64];   // [site parity][J place][column]
+  const int t = threadIdx.x, c = t & 63, rq = t >> 6;
+  int n_low = 0, n_neg = 0, n_acc = 0;   // thread 0's counters (n_acc: every thread's)
   bool nonfinite = false;
   int8_t *xrow = a.fields + (long)a.li * a.N + a.g0;
   for (int j = t; j < kk; j += kDecThreads) {
@@ -586,64 +596,58 @@ __global__ __launch_bounds__(kDecThreads) void soc_decide_kernel(SocDecideBatch 
     us[j] = philox_uniform(a.key0, a.key1, a.sweep, a.slice_code, (uint64_t)(a.g0 + j),
                            kPurposeMH);
   }
-  if (t == 0) n_acc = 0;
   __syncthreads();
-  // W0 with the flip blocks applied to the column pairs (j, kk + j):
-  // delta = [[dd, -x do], [x do, dd]], dd = cos 2gamma - 1, do = sin 2gamma
-  for (int e = t; e < n * kk; e += kDecThreads) {
-    const int r = e / kk, j = e % kk;
-    const double x = xs[j];
-    const double2 w0 = a.W0p[(long)r * n + j], w1 = a.W0p[(long)r * n + kk + j];
-    const double d00 = a.dd, d01 = -x * a.doff, d10 = x * a.doff, d11 = a.dd;
-    W0[r * ld + j] = make_double2(w0.x * d00 + w1.x * d10, w0.y * d00 + w1.y * d10);
-    W0[r * ld + kk + j] = make_double2(w0.x * d01 + w1.x * d11, w0.y * d01 + w1.y * d11);
+  // this thread's entries of E = 1 + W0: the flip block delta = [[dd, -x do],
+  // [x do, dd]] (dd = cos 2gamma - 1, do = sin 2gamma) of site cs on the
+  // column pair (cs, kk + cs); zero outside n x n
+  const bool cv = c < n;
+  const int cs = cv ? (c < kk ? c : c - kk) : 0;
+  const bool up = c < kk;
+  double2 e[16];
+  {
+    const double x = xs[cs];
+    const double da = up ? a.dd : -x * a.doff, db = up ? x * a.doff : a.dd;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int r = rq + 4 * i;
+      const int rr = min(r, n - 1);
+      const double2 w0 = a.W0p[(long)rr * n + cs], w1 = a.W0p[(long)rr * n + kk + cs];
+      double2 v = make_double2(w0.x * da + w1.x * db, w0.y * da + w1.y * db);
+      if (r == c) v.x += 1.0;
+      e[i] = (r < n && cv) ? v : make_double2(0.0, 0.0);
+    }
   }
-  for (int e = t; e < n * ld; e += kDecThreads) Mc[e] = make_double2(0.0, 0.0);
-  __syncthreads();
   for (int j = 0; j < kk; ++j) {
-    const int c0 = j, c1 = kk + j;
-    // u = Mc W0[:, (c0, c1)],  w = W0[(c0, c1), :] Mc
-    if (t < 2 * n) {
-      const int q = t >= n ? 1 : 0, r = t - q * n;
-      const int col = q ? c1 : c0;
-      double2 s = make_double2(0.0, 0.0);
-      for (int b = 0; b < n; ++b) cfma(s, Mc[r * ld + b], W0[b * ld + col]);
-      u[r * 2 + q] = s;
-    } else if (t < 4 * n) {
-      const int e = t - 2 * n, q = e >= n ? 1 : 0, c = e - q * n;
-      const int row = q ? c1 : c0;
-      double2 s = make_double2(0.0, 0.0);
-      for (int b = 0; b < n; ++b) cfma(s, W0[row * ld + b], Mc[b * ld + c]);
-      w[q * n + c] = s;
+    const int p = j & 1, c0 = j, c1 = kk + j;
+    // publish J's columns (their owners) and rows (selected from the registers)
+    if (c == c0 || c == c1) {
+      const int q = c == c1 ? 1 : 0;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) colJ[p][q][rq + 4 * i] = e[i];
     }
-    __syncthreads();
-    // S = 1 + W0[jr, jc] - W0[jr, :] u  (the current 1 + W_j T V_j): wave q
-    // forms entry (q / 2, q % 2), one product per lane, then a shuffle sum
     {
-      const int q = t >> 6, lane = t & 63;
-      const int p = q >> 1, qq = q & 1;
-      const int row = p ? c1 : c0;
-      double2 prod = make_double2(0.0, 0.0);
-      if (lane < n) prod = cmul(W0[row * ld + lane], u[lane * 2 + qq]);
-      for (int off = 32; off > 0; off >>= 1) {
-        prod.x += __shfl_down(prod.x, off, 64);
-        prod.y += __shfl_down(prod.y, off, 64);
+      double v0x = 0.0, v0y = 0.0, v1x = 0.0, v1y = 0.0;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int r = rq + 4 * i;
+        v0x = r == c0 ? e[i].x : v0x;
+        v0y = r == c0 ? e[i].y : v0y;
+        v1x = r == c1 ? e[i].x : v1x;
+        v1y = r == c1 ? e[i].y : v1y;
       }
-      if (lane == 0) {
-        double2 v = csub(W0[row * ld + (qq ? c1 : c0)], prod);
-        if (p == qq) v.x += 1.0;
-        Sm[q] = v;
-      }
+      if (rq == (c0 & 3)) rowJ[p][0][c] = make_double2(v0x, v0y);
+      if (rq == (c1 & 3)) rowJ[p][1][c] = make_double2(v1x, v1y);
     }
     __syncthreads();
+    const double2 S00 = rowJ[p][0][c0], S01 = rowJ[p][0][c1];
+    const double2 S10 = rowJ[p][1][c0], S11 = rowJ[p][1][c1];
+    const double2 R = csub(cmul(S00, S11), cmul(S01, S10));
+    const double absR = hypot(R.x, R.y);
+    const double uu = us[j];
+    const bool finite = !isnan(absR);
+    const bool acc = __builtin_amdgcn_readfirstlane((finite && uu < absR) ? 1 : 0) != 0;
     if (t == 0) {
-      double2 S[2][2] = {{Sm[0], Sm[1]}, {Sm[2], Sm[3]}};
-      const double2 R = csub(cmul(S[0][0], S[1][1]), cmul(S[0][1], S[1][0]));
-      const double absR = hypot(R.x, R.y);
       const int site = a.g0 + j;
-      const double uu = us[j];
-      const bool finite = !isnan(absR);
-      const bool acc = finite && uu < absR;
       const double margin = absR - uu;
       // counters kept in registers, added to memory once per group
       if (fabs(margin) < 1e-12) ++n_low;
@@ -656,66 +660,56 @@ __global__ __launch_bounds__(kDecThreads) void soc_decide_kernel(SocDecideBatch 
         a.log_meta[3 * idx + 2] = acc ? 1 : 0;
         a.log_margin[idx] = margin;
       }
-      if (acc) {
-        const double2 iR = cdiv(make_double2(1.0, 0.0), R);
-        Sinv[0] = cmul(S[1][1], iR);
-        Sinv[1] = cmul(make_double2(-S[0][1].x, -S[0][1].y), iR);
-        Sinv[2] = cmul(make_double2(-S[1][0].x, -S[1][0].y), iR);
-        Sinv[3] = cmul(S[0][0], iR);
-        xrow[j] = (int8_t)(xs[j] > 0.0 ? -1 : 1);
-        n_acc += 1;
-      }
-      accs = acc ? 1 : 0;
-      accm[j] = accs;
+      if (acc) xrow[j] = (int8_t)(xs[j] > 0.0 ? -1 : 1);
+      accm[j] = acc ? 1 : 0;
     }
-    __syncthreads();
-    if (accs) {
-      // Mc += (e_jc - u) G with G = Sinv (e_jr - w) (2 x n, formed first)
-      if (t < 2 * n) {
-        const int q = t >= n ? 1 : 0, c = t - q * n;
-        const double2 r0 = make_double2((c == c0 ? 1.0 : 0.0) - w[c].x, -w[c].y);
-        const double2 r1 = make_double2((c == c1 ? 1.0 : 0.0) - w[n + c].x, -w[n + c].y);
-        double2 g = cmul(Sinv[2 * q], r0);
-        cfma(g, Sinv[2 * q + 1], r1);
-        Gm[q * 64 + c] = g;
-      }
-      __syncthreads();
-      const int c = t & 63;
-      if (c < n) {
-        const double2 g0 = Gm[c], g1 = Gm[64 + c];
-        for (int r = t >> 6; r < n; r += kDecThreads / 64) {
-          const double2 l0 = make_double2((r == c0 ? 1.0 : 0.0) - u[r * 2].x, -u[r * 2].y);
-          const double2 l1 = make_double2((r == c1 ? 1.0 : 0.0) - u[r * 2 + 1].x, -u[r * 2 + 1].y);
-          double2 v = Mc[r * ld + c];
-          cfma(v, l0, g0);
-          cfma(v, l1, g1);
-          Mc[r * ld + c] = v;
-        }
-      }
-    }
-    __syncthreads();
-  }
-  // rows (site, N + site) of U_R <- (1 + delta) rows for the accepted sites
-  // (no later decision of the group reads them)
-  for (int j = 0; j < kk; ++j) {
-    if (!accm[j]) continue;
-    const double x = xs[j];
-    const double d00 = 1.0 + a.dd, d01 = -x * a.doff, d10 = x * a.doff, d11 = 1.0 + a.dd;
-    double2 *p0 = a.UR + (long)(a.g0 + j) * a.ne, *p1 = a.UR + (long)(a.N + a.g0 + j) * a.ne;
-    for (int c = t; c < a.ne; c += kDecThreads) {
-      const double2 r0 = p0[c], r1 = p1[c];
-      p0[c] = make_double2(d00 * r0.x + d01 * r1.x, d00 * r0.y + d01 * r1.y);
-      p1[c] = make_double2(d10 * r0.x + d11 * r1.x, d10 * r0.y + d11 * r1.y);
+    if (!acc) continue;
+    ++n_acc;
+    const double2 iR = cdiv(make_double2(1.0, 0.0), R);
+    const double2 I00 = cmul(S11, iR), I01 = cmul(make_double2(-S01.x, -S01.y), iR);
+    const double2 I10 = cmul(make_double2(-S10.x, -S10.y), iR), I11 = cmul(S00, iR);
+    // g for this column
+    const double2 ej0 = rowJ[p][0][c], ej1 = rowJ[p][1][c];
+    double2 g0 = cmul(I00, ej0), g1 = cmul(I10, ej0);
+    cfma(g0, I01, ej1);
+    cfma(g1, I11, ej1);
+    const bool k0 = c == c0, k1 = c == c1;
+    g0.x = k0 ? 1.0 - I00.x : (k1 ? -I01.x : g0.x);
+    g0.y = k0 ? -I00.y : (k1 ? -I01.y : g0.y);
+    g1.x = k0 ? -I10.x : (k1 ? 1.0 - I11.x : g1.x);
+    g1.y = k0 ? -I10.y : (k1 ? -I11.y : g1.y);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int r = rq + 4 * i;
+      double2 e0 = colJ[p][0][r], e1 = colJ[p][1][r];
+      e0.x -= r == c0 ? 1.0 : 0.0;
+      e1.x -= r == c1 ? 1.0 : 0.0;
+      double2 v = csub(e[i], cmul(e0, g0));
+      v = csub(v, cmul(e1, g1));
+      v.x -= (r == c && (k0 || k1)) ? 2.0 : 0.0;
+      e[i] = v;
     }
   }
+  // Mc = -E on A x A, zero elsewhere, to LDS; the accepted sites' old fields
+  __syncthreads();   // accm visible
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int r = rq + 4 * i;
+    if (r < n && cv) {
+      const bool in = accm[r < kk ? r : r - kk] && accm[cs];
+      Ms[r * ld + c] = in ? make_double2(-e[i].x, -e[i].y) : make_double2(0.0, 0.0);
+    }
+  }
+  for (int j = t; j < kk; j += kDecThreads) a.accx[j] = accm[j] ? (int)xs[j] : 0;
+  __syncthreads();
   // D = delta_bd Mc (rows (j, kk + j) of Mc mixed by the pre-flip delta_j)
-  for (int e = t; e < kk * n; e += kDecThreads) {
-    const int j = e / n, c = e % n;
+  for (int e2 = t; e2 < kk * n; e2 += kDecThreads) {
+    const int j = e2 / n, q = e2 % n;
     const double x = xs[j];
     const double d00 = a.dd, d01 = -x * a.doff, d10 = x * a.doff, d11 = a.dd;
-    const double2 m0 = Mc[j * ld + c], m1 = Mc[(kk + j) * ld + c];
-    a.D[(long)j * n + c] = make_double2(d00 * m0.x + d01 * m1.x, d00 * m0.y + d01 * m1.y);
-    a.D[(long)(kk + j) * n + c] =
+    const double2 m0 = Ms[j * ld + q], m1 = Ms[(kk + j) * ld + q];
+    a.D[(long)j * n + q] = make_double2(d00 * m0.x + d01 * m1.x, d00 * m0.y + d01 * m1.y);
+    a.D[(long)(kk + j) * n + q] =
         make_double2(d10 * m0.x + d11 * m1.x, d10 * m0.y + d11 * m1.y);
   }
   if (t == 0) {
@@ -728,6 +722,29 @@ __global__ __launch_bounds__(kDecThreads) void soc_decide_kernel(SocDecideBatch 
     if (n_neg) a.stats[kStNegative] += n_neg;
     if (nonfinite) a.stats[kStError] |= kErrNonFinite;
   }
+}
+
+// U_R rows of the sites accepted by decide / decide1 <- (1 + delta) rows:
+// w = 2, rows (site, N + site) by the 2 x 2 block of the old field; w = 1,
+// row site by the phase factor.  Grid (256-column slices, kk, walkers).
+__global__ __launch_bounds__(256) void rotate_accepted_kernel(SocDecideBatch B, int w) {
+  const SocDecideArgs &a = B.a[blockIdx.z];
+  const int j = blockIdx.y;
+  if (j >= a.kk) return;
+  const int xo = a.accx[j];
+  const int q = (int)blockIdx.x * 256 + (int)threadIdx.x;
+  if (xo == 0 || q >= a.ne) return;
+  const double x = (double)xo;
+  double2 *p0 = a.UR + (long)(a.g0 + j) * a.ne + q;
+  if (w == 1) {
+    *p0 = cmul(make_double2(1.0 + a.dd, -x * a.doff), *p0);
+    return;
+  }
+  double2 *p1 = a.UR + (long)(a.N + a.g0 + j) * a.ne + q;
+  const double d00 = 1.0 + a.dd, d01 = -x * a.doff, d10 = x * a.doff, d11 = 1.0 + a.dd;
+  const double2 r0 = *p0, r1 = *p1;
+  *p0 = make_double2(d00 * r0.x + d01 * r1.x, d00 * r0.y + d01 * r1.y);
+  *p1 = make_double2(d10 * r0.x + d11 * r1.x, d10 * r0.y + d11 * r1.y);
 }
 
 // Gauss-Jordan elimination with partial pivoting of the n x n left part of
@@ -980,24 +997,23 @@ __device__ __forceinline__ double2 flip_delta(const SocDecideArgs &a, double x) 
 // W0 = W0p diag(delta) and Mc = (1 + W0_AA)^{-1} spread to kk x kk (zero
 // outside the accepted set A), site j's ratio is the Schur complement
 // r = 1 + W0_jj - W0_j,: Mc W0_:,j (the recursion of Eq. (28)) and the test
-// is u < |r|^2; accepting j borders Mc by one row and column.  Out: D =
-// diag(delta) Mc, so that T = T0 - (T0 U_L[:, g]) D (U_g T0) (Eq. (30)).
+// is u < |r|^2.  As in the rank-two kernel, E = 1 + W0 is swept, in
+// registers: the unswept diagonal entry E_jj is r; accepting j sweeps pivot j
+//   E_rc -= E_rj E_jc / r,  E_rj <- E_rj / r,  E_jc <- E_jc / r,  E_jj <- -1 / r,
+// as one formula E_rc -= e_r g_c with e_r = E_rj - [r = j], g_c = E_jc / r
+// (c != j), g_j = 1 - 1 / r, and -2 on E_jj; the swept block ends as
+// E_AA = -Mc.  Out: D = diag(delta) Mc, so that T = T0 - (T0 U_L[:, g]) D
+// (U_g T0) (Eq. (30)); accx as the rank-two kernel.
 __global__ __launch_bounds__(kDecThreads) void cplx_decide_kernel(SocDecideBatch B) {
   const SocDecideArgs &a = B.a[blockIdx.x];   // one workgroup per walker
-  extern __shared__ double2 lds[];
+  extern __shared__ double2 Ms[];      // n x (n + 1): Mc at the end
   const int n = a.kk;
   const int ld = n + 1;
-  double2 *W0 = lds;                 // n x n, leading dim ld
-  double2 *Mc = W0 + n * ld;         // n x n, leading dim ld
-  double2 *u = Mc + n * ld;          // Mc W0[:, j]
-  double2 *w = u + n;                // W0[j, :] Mc
-  __shared__ double2 Sinv;
-  __shared__ int accs;
   __shared__ double xs[64], us[64];
   __shared__ int accm[64];
-  __shared__ int n_acc;
-  const int t = threadIdx.x, lane = t & 63;
-  int n_low = 0;
+  __shared__ double2 colJ[2][64], rowJ[2][64];   // [site parity][row / column]
+  const int t = threadIdx.x, c = t & 63, rq = t >> 6;
+  int n_low = 0, n_acc = 0;
   bool nonfinite = false;
   int8_t *xrow = a.fields + (long)a.li * a.N + a.g0;
   for (int j = t; j < n; j += kDecThreads) {
@@ -1006,82 +1022,87 @@ __global__ __launch_bounds__(kDecThreads) void cplx_decide_kernel(SocDecideBatch
                     : philox_uniform(a.key0, a.key1, a.sweep, a.slice_code,
                                      (uint64_t)(a.g0 + j), kPurposeMH);
   }
-  if (t == 0) n_acc = 0;
   __syncthreads();
-  for (int e = t; e < n * n; e += kDecThreads) {
-    const int r = e / n, j = e - r * n;
-    W0[r * ld + j] = cmul(a.W0p[(long)r * n + j], flip_delta(a, xs[j]));
+  const bool cv = c < n;
+  double2 e[16];
+  {
+    const double2 dl = flip_delta(a, xs[cv ? c : 0]);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int r = rq + 4 * i;
+      double2 v = cmul(a.W0p[(long)min(r, n - 1) * n + (cv ? c : 0)], dl);
+      if (r == c) v.x += 1.0;
+      e[i] = (r < n && cv) ? v : make_double2(0.0, 0.0);
+    }
   }
-  for (int e = t; e < n * ld; e += kDecThreads) Mc[e] = make_double2(0.0, 0.0);
+  for (int j = 0; j < n; ++j) {
+    const int p = j & 1;
+    if (c == j) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) colJ[p][rq + 4 * i] = e[i];
+    }
+    {
+      double vx = 0.0, vy = 0.0;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        vx = rq + 4 * i == j ? e[i].x : vx;
+        vy = rq + 4 * i == j ? e[i].y : vy;
+      }
+      if (rq == (j & 3)) rowJ[p][c] = make_double2(vx, vy);
+    }
+    __syncthreads();
+    const double2 r = rowJ[p][j];
+    const double R = r.x * r.x + r.y * r.y;   // r_up r_dn with r_dn = conj(r_up)
+    const double uu = us[j];
+    const bool finite = !isnan(R);
+    const bool acc = __builtin_amdgcn_readfirstlane((finite && uu < R) ? 1 : 0) != 0;
+    if (t == 0) {
+      const double margin = R - uu;
+      if (fabs(margin) < 1e-12) ++n_low;
+      if (!finite) nonfinite = true;
+      const int site = a.g0 + j;
+      const long long idx = a.log_base + site;
+      if (a.log_meta && idx < a.log_cap) {
+        a.log_meta[3 * idx + 0] = (int32_t)a.slice_code;
+        a.log_meta[3 * idx + 1] = site;
+        a.log_meta[3 * idx + 2] = acc ? 1 : 0;
+        a.log_margin[idx] = margin;
+      }
+      if (acc) xrow[j] = (int8_t)(xs[j] > 0.0 ? -1 : 1);
+      accm[j] = acc ? 1 : 0;
+    }
+    if (!acc) continue;
+    ++n_acc;
+    const double2 ir = cdiv(make_double2(1.0, 0.0), r);
+    double2 g = cmul(rowJ[p][c], ir);
+    const bool kj = c == j;
+    g.x = kj ? 1.0 - ir.x : g.x;
+    g.y = kj ? -ir.y : g.y;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int rw = rq + 4 * i;
+      double2 er = colJ[p][rw];
+      er.x -= rw == j ? 1.0 : 0.0;
+      double2 v = csub(e[i], cmul(er, g));
+      v.x -= (rw == c && kj) ? 2.0 : 0.0;
+      e[i] = v;
+    }
+  }
+  __syncthreads();   // accm visible
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int r = rq + 4 * i;
+    if (r < n && cv) {
+      const bool in = accm[r] && accm[c];
+      Ms[r * ld + c] = in ? make_double2(-e[i].x, -e[i].y) : make_double2(0.0, 0.0);
+    }
+  }
+  for (int j = t; j < n; j += kDecThreads) a.accx[j] = accm[j] ? (int)xs[j] : 0;
   __syncthreads();
-  for (int j = 0; j < n; ++j) {
-    if (t < n) {
-      double2 s = make_double2(0.0, 0.0);
-      for (int b = 0; b < n; ++b) cfma(s, Mc[t * ld + b], W0[b * ld + j]);
-      u[t] = s;
-    } else if (t >= 64 && t < 64 + n) {
-      const int c = t - 64;
-      double2 s = make_double2(0.0, 0.0);
-      for (int b = 0; b < n; ++b) cfma(s, W0[j * ld + b], Mc[b * ld + c]);
-      w[c] = s;
-    }
-    __syncthreads();
-    if (t < 64) {
-      double2 prod = lane < n ? cmul(W0[j * ld + lane], u[lane]) : make_double2(0.0, 0.0);
-      for (int off = 32; off > 0; off >>= 1) {
-        prod.x += __shfl_down(prod.x, off, 64);
-        prod.y += __shfl_down(prod.y, off, 64);
-      }
-      if (lane == 0) {
-        double2 r = csub(W0[j * ld + j], prod);
-        r.x += 1.0;
-        const double R = r.x * r.x + r.y * r.y;   // r_up r_dn with r_dn = conj(r_up)
-        const double uu = us[j];
-        const bool finite = !isnan(R);
-        const bool acc = finite && uu < R;
-        const double margin = R - uu;
-        if (fabs(margin) < 1e-12) ++n_low;
-        if (!finite) nonfinite = true;
-        const int site = a.g0 + j;
-        const long long idx = a.log_base + site;
-        if (a.log_meta && idx < a.log_cap) {
-          a.log_meta[3 * idx + 0] = (int32_t)a.slice_code;
-          a.log_meta[3 * idx + 1] = site;
-          a.log_meta[3 * idx + 2] = acc ? 1 : 0;
-          a.log_margin[idx] = margin;
-        }
-        if (acc) {
-          Sinv = cdiv(make_double2(1.0, 0.0), r);
-          xrow[j] = (int8_t)(xs[j] > 0.0 ? -1 : 1);
-          n_acc += 1;
-        }
-        accs = acc ? 1 : 0;
-        accm[j] = accs;
-      }
-    }
-    __syncthreads();
-    if (accs) {
-      // Mc += (e_j - u) Sinv (e_j - w)^T
-      const double2 si = Sinv;
-      for (int e = t; e < n * n; e += kDecThreads) {
-        const int r = e / n, c = e - r * n;
-        const double2 l = make_double2((r == j ? 1.0 : 0.0) - u[r].x, -u[r].y);
-        const double2 g = cmul(si, make_double2((c == j ? 1.0 : 0.0) - w[c].x, -w[c].y));
-        cfma(Mc[r * ld + c], l, g);
-      }
-    }
-    __syncthreads();
-  }
-  // rows of U_R of the accepted sites <- (1 + delta) rows
-  for (int j = 0; j < n; ++j) {
-    if (!accm[j]) continue;
-    const double2 f = make_double2(1.0 + a.dd, -xs[j] * a.doff);
-    double2 *p0 = a.UR + (long)(a.g0 + j) * a.ne;
-    for (int c = t; c < a.ne; c += kDecThreads) p0[c] = cmul(f, p0[c]);
-  }
-  for (int e = t; e < n * n; e += kDecThreads) {
-    const int j = e / n, c = e - j * n;
-    a.D[(long)j * n + c] = cmul(flip_delta(a, xs[j]), Mc[j * ld + c]);
+  // D = diag(delta) Mc
+  for (int e2 = t; e2 < n * n; e2 += kDecThreads) {
+    const int j = e2 / n, q = e2 - j * n;
+    a.D[(long)j * n + q] = cmul(flip_delta(a, xs[j]), Ms[j * ld + q]);
   }
   if (t == 0) {
     *a.nflush = n_acc > 0 ? n : 0;
@@ -1366,10 +1387,10 @@ hipError_t phase_rows(const double2 *X, long ldx, double2 *Y, long ldy, int ncol
 hipError_t decide1(const SocDecideArgs *a, int nb, hipStream_t st) {
   if (a[0].kk < 1 || a[0].kk > 2 * kSocMaxK) return hipErrorInvalidValue;
   const int n = a[0].kk;
-  const size_t lds = sizeof(double2) * (2 * (size_t)n * (n + 1) + 2 * (size_t)n);
+  const size_t lds = sizeof(double2) * (size_t)n * (n + 1);
   static const hipError_t attr = hipFuncSetAttribute(
       (const void *)cplx_decide_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-      (int)(sizeof(double2) * (2 * 64 * 65 + 2 * 64)));
+      (int)(sizeof(double2) * 64 * 65));
   return launch_decide(cplx_decide_kernel, a, nb, lds, st, attr);
 }
 
@@ -1383,13 +1404,22 @@ hipError_t block_decide1(const SocDecideArgs *a, int nb, hipStream_t st) {
   return launch_decide(cplx_block_decide_kernel, a, nb, lds, st, attr);
 }
 
+hipError_t rotate_accepted(const SocDecideArgs *a, int nb, int w, hipStream_t st) {
+  if (nb < 1 || nb > kSocMaxBatch || a[0].kk < 1 || a[0].kk > 2 * kSocMaxK) return hipErrorInvalidValue;
+  SocDecideBatch B{};
+  for (int i = 0; i < nb; ++i) B.a[i] = a[i];
+  hipLaunchKernelGGL(rotate_accepted_kernel, dim3((a[0].ne + 255) / 256, a[0].kk, nb), dim3(256),
+                     0, st, B, w);
+  return hipGetLastError();
+}
+
 hipError_t decide(const SocDecideArgs *a, int nb, hipStream_t st) {
   if (a[0].kk < 1 || a[0].kk > kSocMaxK) return hipErrorInvalidValue;
   const int n = 2 * a[0].kk;
-  const size_t lds = sizeof(double2) * (2 * (size_t)n * (n + 1) + 4 * (size_t)n);
+  const size_t lds = sizeof(double2) * (size_t)n * (n + 1);
   static const hipError_t attr = hipFuncSetAttribute(
       (const void *)soc_decide_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-      (int)(sizeof(double2) * (2 * 64 * 65 + 4 * 64)));
+      (int)(sizeof(double2) * 64 * 65));
   return launch_decide(soc_decide_kernel, a, nb, lds, st, attr);
 }
 

@@ -92,6 +92,8 @@ struct SocDecideArgs {
   double2 *D;              // 2kk x 2kk out
   double2 *UR;             // 2N x ne
   int *nflush;             // out: 2kk or 0
+  int *accx;               // out (delayed and local): per site of the group, its field
+                           // before the flip if accepted, else 0 (2 kSocMaxK ints)
   int8_t *fields;          // M x N
   int li, N, ne, g0, kk;
   double dd, doff;         // delta = [[dd, -x doff], [x doff, dd]]
@@ -108,6 +110,10 @@ struct SocDecideBatch {
   SocDecideArgs a[kSocMaxBatch];
 };
 hipError_t decide(const SocDecideArgs *a, int nb, hipStream_t st);
+// after decide / decide1: the U_R rows of the accepted sites (accx) rotated
+// by 1 + delta (w = 2: the row pairs (site, N + site); w = 1: the phase of
+// row site), one workgroup per (256 columns, site, walker)
+hipError_t rotate_accepted(const SocDecideArgs *a, int nb, int w, hipStream_t st);
 // The one-sector model (U < 0 of Sec. II B, w = 1): rows scaled by the
 // phases e^{i sign gamma x_i}; decisions of kk <= 64 sites with a scalar
 // flip delta per site (delayed / local, and block force bias).

@@ -42,6 +42,7 @@ struct pqmc_soc_ctx {
   int ksplit = 0;                                   // depth per slice (0: no split)
   double2 *Tay0 = nullptr, *Tay1 = nullptr;         // n2 x n2 (set-up, then G)
   int *nflush = nullptr;
+  int *accx = nullptr;                              // accepted sites' old fields (decide)
   int8_t *fields = nullptr;
   int8_t *replay = nullptr;                         // 2 M x N forced outcomes (w = 1)
   bool replaying = false;
@@ -170,6 +171,7 @@ void layout(pqmc_soc_ctx &c, char *base, size_t *bytes) {
     c.W0part = cv.take<double2>(ns * kn * kn);
   }
   c.nflush = cv.take<int>(4);
+  c.accx = cv.take<int>(2 * kSocMaxK);
   c.fields = cv.take<int8_t>((size_t)c.M * c.N);
   if (c.w == 1) c.replay = cv.take<int8_t>((size_t)2 * c.M * c.N);
   c.stats = cv.take<unsigned long long>(16);
@@ -510,6 +512,7 @@ int update_slice(const SocWalkers &b, int l, int dir) {
       d.D = c.D;
       d.UR = c.UR;
       d.nflush = c.nflush;
+      d.accx = c.accx;
       d.fields = c.fields;
       d.li = li;
       d.N = N;
@@ -533,12 +536,12 @@ int update_slice(const SocWalkers &b, int l, int dir) {
       d.force = c.replaying ? c.replay + ((size_t)dir * c.M + li) * N : nullptr;
       da[i] = d;
     }
-    if (L.w == 1)
-      PQ_HIP_CHECK(L.block ? block_decide1(da, b.n, L.st) : decide1(da, b.n, L.st));
-    else if (L.block)
-      PQ_HIP_CHECK(block_decide(da, b.n, L.st));
-    else
-      PQ_HIP_CHECK(decide(da, b.n, L.st));
+    if (L.block) {
+      PQ_HIP_CHECK(L.w == 1 ? block_decide1(da, b.n, L.st) : block_decide(da, b.n, L.st));
+    } else {
+      PQ_HIP_CHECK(L.w == 1 ? decide1(da, b.n, L.st) : decide(da, b.n, L.st));
+      PQ_HIP_CHECK(rotate_accepted(da, b.n, L.w, L.st));
+    }
     CgemmQueue qq{L.st, kOpN, kOpN};
     for (int i = 0; i < b.n && !rc; ++i) {
       CgemmDesc q = cdesc(b[i].P1, n, b[i].D, n, b[i].Q, n, ne, n, n);
