@@ -905,7 +905,75 @@ __device__ double lds_gj_inverse(double *A, int ld, int n, double *colk, double 
   return det;
 }
 
-// Block force-bias decision for kk <= 64 sites (one workgroup of NT lanes):
+// Wave-level synchronisation: the LDS operations of one wave complete in
+// issue order, so a fence that keeps the compiler from moving memory
+// operations across it is all that one wave's lanes need between writing
+// and reading each other's LDS entries.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// lds_gj_inverse for one wave: the calling wave's 64 lanes invert the n x n
+// matrix A (n <= 64) in place with no workgroup barrier, so that two waves
+// can invert two matrices at once; returns det(A) in every lane.
+__device__ double wave_gj_inverse(double *A, int ld, int n, double *colk, double *rowk,
+                                  int *ipiv) {
+  const int lane = threadIdx.x & 63;
+  double det = 1.0;
+  for (int k = 0; k < n; ++k) {
+    const bool cand = lane >= k && lane < n;
+    double bv = cand ? fabs(A[lane * ld + k]) : -1.0;
+    int bi = cand ? lane : 0x7fffffff;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ov = __shfl_xor(bv, o, 64);
+      const int oi = __shfl_xor(bi, o, 64);
+      const bool take = (ov > bv) || (ov == bv && oi < bi);
+      bv = take ? ov : bv;
+      bi = take ? oi : bi;
+    }
+    const int p = __builtin_amdgcn_readfirstlane(bi < n ? bi : k);
+    if (lane == 0) ipiv[k] = p;
+    if (p != k)
+      for (int j = lane; j < n; j += 64) {
+        const double x = A[k * ld + j];
+        A[k * ld + j] = A[p * ld + j];
+        A[p * ld + j] = x;
+      }
+    wave_sync();
+    const double piv = A[k * ld + k];
+    det *= (p != k) ? -piv : piv;
+    const double ip = 1.0 / piv;
+    for (int i = lane; i < n; i += 64) {
+      colk[i] = A[i * ld + k];
+      rowk[i] = A[k * ld + i] * ip;
+    }
+    wave_sync();
+    for (int e = lane; e < n * n; e += 64) {
+      const int i = e / n, j = e % n;
+      double v;
+      if (i == k) v = (j == k) ? ip : rowk[j];
+      else v = (j == k) ? -colk[i] * ip : A[i * ld + j] - colk[i] * rowk[j];
+      A[i * ld + j] = v;
+    }
+    wave_sync();
+  }
+  for (int k = n - 1; k >= 0; --k) {
+    const int p = __builtin_amdgcn_readfirstlane(ipiv[k]);
+    if (p != k)
+      for (int i = lane; i < n; i += 64) {
+        const double x = A[i * ld + k];
+        A[i * ld + k] = A[i * ld + p];
+        A[i * ld + p] = x;
+      }
+    wave_sync();
+  }
+  return det;
+}
+
+// Block force-bias decision for kk <= 64 sites (one workgroup of NT lanes;
+// NT = 128 for kk <= 16: wave s inverts spin s's matrices, both at once):
 // force bias from B = 1 + diag(Delta_b) W0 (Eq. (35)), heat-bath proposal,
 // det[1 + W0_FF diag(Delta'_F)] per spin and the Metropolis test with the
 // prior ratio (Sec. III B).  Both small inversions use partial pivoting.
@@ -925,6 +993,8 @@ __global__ __launch_bounds__(NT) void block_decide_kernel(Batch<DecideArgs> B) {
   __shared__ double colk[64], rowk[64];
   __shared__ int ipiv[64];
   __shared__ int s_piv;
+  __shared__ double colk2[2][64], rowk2[2][64], rdet[2];   // the two-wave form
+  __shared__ int ipiv2[2][64];
   __shared__ double db[2][64], nbar[2][64], sval[64], dp[2][64], hbm[64];
   __shared__ int xold[64], xnew[64], flist[64], posF[64];
   __shared__ int s_nF;
@@ -941,22 +1011,40 @@ __global__ __launch_bounds__(NT) void block_decide_kernel(Batch<DecideArgs> B) {
     W0s[1][(e / kk) * LD + e % kk] = A.g.W0[1][(e / kk) * kmax + e % kk];
   }
   __syncthreads();
-  for (int s = 0; s < 2; ++s) {
-    // M1 = W0 (kept for the force-bias product), M0 = 1 + diag(Delta_b) W0
-    for (int e = t; e < kk * kk; e += NT) {
+  if constexpr (NT == 128) {
+    // wave s inverts spin s's 1 + diag(Delta_b) W0 (in M0 / M1), both at once
+    const int sw = t >> 6, ln = t & 63;
+    double *Mw = sw ? M1 : M0;
+    for (int e = ln; e < kk * kk; e += 64) {
       const int ia = e / kk, ib = e % kk;
-      const double w = W0s[s][ia * LD + ib];
-      M1[ia * LD + ib] = w;
-      M0[ia * LD + ib] = (ia == ib ? 1.0 : 0.0) + db[s][ia] * w;
+      Mw[ia * LD + ib] = (ia == ib ? 1.0 : 0.0) + db[sw][ia] * W0s[sw][ia * LD + ib];
     }
-    __syncthreads();
-    lds_gj_inverse<NT>(M0, LD, kk, colk, rowk, ipiv, &s_piv);
-    if (t < kk) {
+    wave_sync();
+    wave_gj_inverse(Mw, LD, kk, colk2[sw], rowk2[sw], ipiv2[sw]);
+    if (ln < kk) {
       double v = 0.0;
-      for (int m = 0; m < kk; ++m) v += M1[t * LD + m] * M0[m * LD + t];
-      nbar[s][t] = (1.0 + db[s][t]) * v;     // [UU_R (U_L UU_R)^{-1} U_L]_ii
+      for (int m = 0; m < kk; ++m) v += W0s[sw][ln * LD + m] * Mw[m * LD + ln];
+      nbar[sw][ln] = (1.0 + db[sw][ln]) * v;     // [UU_R (U_L UU_R)^{-1} U_L]_ii
     }
     __syncthreads();
+  } else {
+    for (int s = 0; s < 2; ++s) {
+      // M1 = W0 (kept for the force-bias product), M0 = 1 + diag(Delta_b) W0
+      for (int e = t; e < kk * kk; e += NT) {
+        const int ia = e / kk, ib = e % kk;
+        const double w = W0s[s][ia * LD + ib];
+        M1[ia * LD + ib] = w;
+        M0[ia * LD + ib] = (ia == ib ? 1.0 : 0.0) + db[s][ia] * w;
+      }
+      __syncthreads();
+      lds_gj_inverse<NT>(M0, LD, kk, colk, rowk, ipiv, &s_piv);
+      if (t < kk) {
+        double v = 0.0;
+        for (int m = 0; m < kk; ++m) v += M1[t * LD + m] * M0[m * LD + t];
+        nbar[s][t] = (1.0 + db[s][t]) * v;     // [UU_R (U_L UU_R)^{-1} U_L]_ii
+      }
+      __syncthreads();
+    }
   }
   // heat-bath proposal x'_i, P(+1) = 1 / (1 + e^{-2 s_i}), s_i = alpha (nbar_up - nbar_dn)
   if (t < kk) {
@@ -1023,8 +1111,19 @@ __global__ __launch_bounds__(NT) void block_decide_kernel(Batch<DecideArgs> B) {
     M1[ia * LD + ib] = (ia == ib ? 1.0 : 0.0) + W0s[1][fa * LD + fb] * dp[1][ib];
   }
   __syncthreads();
-  const double r0 = lds_gj_inverse<NT>(M0, LD, nF, colk, rowk, ipiv, &s_piv);
-  const double r1 = lds_gj_inverse<NT>(M1, LD, nF, colk, rowk, ipiv, &s_piv);
+  double r0, r1;
+  if constexpr (NT == 128) {
+    // wave s: spin s's flip-set determinant and inverse, both at once
+    const int sw = t >> 6;
+    const double r = wave_gj_inverse(sw ? M1 : M0, LD, nF, colk2[sw], rowk2[sw], ipiv2[sw]);
+    if ((t & 63) == 0) rdet[sw] = r;
+    __syncthreads();
+    r0 = rdet[0];
+    r1 = rdet[1];
+  } else {
+    r0 = lds_gj_inverse<NT>(M0, LD, nF, colk, rowk, ipiv, &s_piv);
+    r1 = lds_gj_inverse<NT>(M1, LD, nF, colk, rowk, ipiv, &s_piv);
+  }
   // prior ratio P(X'->X)/P(X->X') and the test, evaluated identically in every lane
   double lp = 0.0;
   for (int a = 0; a < nF; ++a) {
@@ -1620,14 +1719,15 @@ hipError_t block_decide(const GroupBufs *g, const SweepCtx *c, int nw, int g0, c
     hipError_t e = hipFuncSetAttribute((const void *)block_decide_kernel<256>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void *)block_decide_kernel<64>,
+    return hipFuncSetAttribute((const void *)block_decide_kernel<128>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   }();
   if (attr != hipSuccess) return attr;
   return decide_by_class(B, nw, kkw, 2, block_class,
                          [&](int k, const Batch<DecideArgs> &S, int n) {
     const dim3 grid(n, decide_rows(S, n, panels));
-    if (k == 0) hipLaunchKernelGGL((block_decide_kernel<64>), grid, dim3(64), lds, st, S);
+    // kk <= 16: one wave per spin sector, each inverting its own matrices
+    if (k == 0) hipLaunchKernelGGL((block_decide_kernel<128>), grid, dim3(128), lds, st, S);
     else hipLaunchKernelGGL((block_decide_kernel<256>), grid, dim3(256), lds, st, S);
   });
 }
