@@ -122,7 +122,8 @@ typedef enum { PQMC_LOCAL = 0, PQMC_DELAYED = 1, PQMC_BLOCK_FB = 2,
  * N <= 4096 and ||dtau H0||_1 <= 1 applies e^{-+dtau H0} as the Taylor series
  * of the sparse H0 (degree J with a dropped term below 2^-60; the same
  * operator to rounding), which costs 2 J nnz(H0) N_sigma flops per product
- * instead of 2 N^2 N_sigma. */
+ * instead of 2 N^2 N_sigma.  The same holds for the complex 2N x 2N H0 of
+ * pqmc_soc_create (and the U < 0 model), where this flag is also accepted. */
 #define PQMC_FLAG_DENSE_PROP 64u
 
 /* kernel classes of pqmc_get_kernel_times() */

@@ -355,7 +355,8 @@ class SocChain:
     """
 
     def __init__(self, hopping, trial, U, dtau, n_slices, stab_every, seed, walker_id=0,
-                 scheme=Scheme.DELAYED, k=16, log=False, timing=False, stream=None):
+                 scheme=Scheme.DELAYED, k=16, log=False, timing=False, stream=None,
+                 dense_prop=False):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device visible to torch")
@@ -368,7 +369,8 @@ class SocChain:
             ctypes.POINTER(ctypes.c_double)), self._P.view(np.float64).ctypes.data_as(
             ctypes.POINTER(ctypes.c_double)), float(U), float(dtau), int(n_slices),
             int(stab_every), int(seed) & (2**64 - 1), int(walker_id))
-        flags = (FLAG_LOG if log else 0) | (FLAG_TIMING if timing else 0)
+        flags = ((FLAG_LOG if log else 0) | (FLAG_TIMING if timing else 0)
+                 | (FLAG_DENSE_PROP if dense_prop else 0))
         self._opts = UpdateOpts(int(scheme), int(k), int(k), flags)
         nbytes = ctypes.c_size_t(0)
         _check(self._lib, self._lib.pqmc_soc_workspace_bytes(

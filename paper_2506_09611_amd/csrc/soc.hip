@@ -200,6 +200,99 @@ __global__ __launch_bounds__(256) void csum_kernel(CsumBatch b) {
   d.dst[(long)r * d.ldd + c] = s;
 }
 
+// ------------------------------------------------------- propagation
+// One workgroup of 512 threads owns one column of one product for all n2
+// rows: both Horner iterates in LDS (2 x n2 complex), the thread's R rows of
+// X and of a M (ELL, WD entries a row) in registers.  Each step reads the
+// neighbour rows from LDS and ends on a barrier; X is read once and Y
+// written once.  XCD-aware: consecutive workgroup ids go round-robin to the
+// 8 XCDs, so XCD x takes the contiguous range [x per, (x + 1) per) of
+// columns, and the eight columns of a cache line of X and Y share one L2.
+constexpr int kCexpThreads = 512;
+
+// The matrix values stay in registers when R <= 4 and R WD <= 32; above that (n2 > 2048
+// rows) they are read at every step (cached, shared by
+// every workgroup) so that the kernel does not spill.
+template <int R, int WD>
+__global__ __launch_bounds__(kCexpThreads) void cexpv_kernel(CexpvBatch B) {
+  constexpr bool kRegVal = R * WD <= 32 && R <= 4;
+  constexpr int RV = kRegVal ? R : 1;
+  const CexpvDesc &d = B.d[blockIdx.y];
+  const int per = (int)(gridDim.x >> 3);   // the grid is a multiple of 8
+  const int col = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+  if (col >= d.n) return;
+  extern __shared__ double2 czs[];
+  double2 *Za = czs, *Zb = czs + d.n2;
+  const int t = threadIdx.x, n2 = d.n2;
+  const double cs = d.conj ? -1.0 : 1.0;
+  // a M entry e of row r (zero past the row's w entries)
+  auto mval = [&](int r, int e) {
+    const int rr = min(r, n2 - 1), ec = min(e, d.w - 1);
+    const double2 v = d.val[(long)rr * d.w + ec];
+    const double m = (r < n2 && e < d.w) ? d.a : 0.0;
+    return make_double2(v.x * m, cs * v.y * m);
+  };
+  double2 x[R];
+  int idx[R][WD];
+  double2 val[RV][WD];
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const int r = t + kCexpThreads * i;
+    const int rr = min(r, n2 - 1);
+#pragma unroll
+    for (int e = 0; e < WD; ++e) {
+      idx[i][e] = d.idx[(long)rr * d.w + min(e, d.w - 1)];
+      if constexpr (kRegVal) val[i][e] = mval(r, e);
+    }
+    x[i] = d.X[(long)rr * d.ldx + col];
+    if (r < n2) Za[r] = x[i];
+  }
+  __syncthreads();
+  for (int j = d.J; j >= 1; --j) {
+    const double inv = 1.0 / (double)j;
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const int r = t + kCexpThreads * i;
+      if (r < n2) {
+        double2 s = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int e = 0; e < WD; ++e) {
+          if constexpr (kRegVal) cfma(s, val[i][e], Za[idx[i][e]]);
+          else cfma(s, mval(r, e), Za[idx[i][e]]);
+        }
+        Zb[r] = make_double2(fma(s.x, inv, x[i].x), fma(s.y, inv, x[i].y));
+      }
+    }
+    __syncthreads();
+    double2 *tmp = Za;
+    Za = Zb;
+    Zb = tmp;
+  }
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const int r = t + kCexpThreads * i;
+    if (r < n2) d.Y[(long)r * d.ldy + col] = Za[r];
+  }
+}
+
+template <int R, int WD>
+hipError_t launch_cexpv(const CexpvBatch &b, int nmax, int n2max, hipStream_t st) {
+  const size_t lds = sizeof(double2) * 2 * (size_t)n2max;
+  static const hipError_t attr = hipFuncSetAttribute(
+      (const void *)cexpv_kernel<R, WD>, hipFuncAttributeMaxDynamicSharedMemorySize,
+      (int)(sizeof(double2) * 2 * kCexpMaxN));
+  if (attr != hipSuccess) return attr;
+  hipLaunchKernelGGL((cexpv_kernel<R, WD>), dim3((nmax + 7) / 8 * 8, b.count), dim3(kCexpThreads),
+                     lds, st, b);
+  return hipGetLastError();
+}
+
+template <int R>
+hipError_t launch_cexpv_w(const CexpvBatch &b, int nmax, int n2max, int wmax, hipStream_t st) {
+  if (wmax <= 4) return launch_cexpv<R, 4>(b, nmax, n2max, st);
+  return launch_cexpv<R, 8>(b, nmax, n2max, st);
+}
+
 // ------------------------------------------------------------- rotations
 // rows (i, N+i) of Y <- A(sign x_i) rows (i, N+i) of X (n2 x ncols, leading
 // dims ldx, ldy; X == Y allowed), A(y) = [[cos gamma y, sin gamma y],
@@ -1277,6 +1370,25 @@ CgemmDesc cdesc(const double2 *A, long lda, const double2 *B, long ldb, double2 
   d.alpha = make_double2(1.0, 0.0);
   d.beta = make_double2(0.0, 0.0);
   return d;
+}
+
+hipError_t cexpv(const CexpvBatch &b, hipStream_t st) {
+  if (b.count < 1 || b.count > kCexpvMaxBatch) return hipErrorInvalidValue;
+  int nmax = 0, n2max = 0, wmax = 1;
+  for (int i = 0; i < b.count; ++i) {
+    const CexpvDesc &d = b.d[i];
+    if (d.n2 < 1 || d.n2 > kCexpMaxN || d.w < 1 || d.w > kCexpMaxW || d.n < 1 || d.J < 0 ||
+        d.X == d.Y)
+      return hipErrorInvalidValue;
+    nmax = max(nmax, d.n);
+    n2max = max(n2max, d.n2);
+    wmax = max(wmax, d.w);
+  }
+  const int R = (n2max + kCexpThreads - 1) / kCexpThreads;
+  if (R <= 1) return launch_cexpv_w<1>(b, nmax, n2max, wmax, st);
+  if (R <= 2) return launch_cexpv_w<2>(b, nmax, n2max, wmax, st);
+  if (R <= 4) return launch_cexpv_w<4>(b, nmax, n2max, wmax, st);
+  return launch_cexpv_w<8>(b, nmax, n2max, wmax, st);
 }
 
 hipError_t rotate_rows(const double2 *X, long ldx, double2 *Y, long ldy, int ncols, int N,

@@ -47,6 +47,30 @@ CgemmDesc cdesc(const double2 *A, long lda, const double2 *B, long ldb, double2 
 // op pairs supported: (N, N), (N, T), (T, N), (H, N)
 hipError_t cgemm(const CgemmBatch &b, int opA, int opB, hipStream_t st);
 
+// Y = e^{a M} X for a sparse complex M (M = H0, or H0^T = conj(H0) when conj
+// is set: H0 is Hermitian, so both share H0's pattern), X and Y n2 x n
+// row-major (leading dims ldx, ldy; X != Y): the Taylor series of degree J
+// in Horner form, Z <- X + (a M Z) / j for j = J .. 1.  M in ELL form: row r
+// has w entries idx[r w + e], val[r w + e] (padded with zero values).
+constexpr int kCexpMaxN = 4096, kCexpMaxW = 8, kCexpvMaxBatch = 16;
+struct CexpvDesc {
+  const double2 *X;
+  long ldx;
+  double2 *Y;
+  long ldy;
+  int n2, n;
+  const int *idx;
+  const double2 *val;
+  int w, J;
+  double a;
+  int conj;
+};
+struct CexpvBatch {
+  CexpvDesc d[kCexpvMaxBatch];
+  int count;
+};
+hipError_t cexpv(const CexpvBatch &b, hipStream_t st);
+
 // rows (i, N+i) of Y <- A(sign x_i) rows (i, N+i) of X (X == Y allowed),
 // A(y) = [[cos gamma y, sin gamma y], [-sin gamma y, cos gamma y]];
 // c = cos gamma, s = sin gamma.

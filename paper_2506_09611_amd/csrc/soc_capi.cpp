@@ -41,6 +41,12 @@ struct pqmc_soc_ctx {
   double2 *P2part = nullptr, *P1part = nullptr, *W0part = nullptr;   // split-K slices
   int ksplit = 0;                                   // depth per slice (0: no split)
   double2 *Tay0 = nullptr, *Tay1 = nullptr;         // n2 x n2 (set-up, then G)
+  // H0 in ELL form (n2 x kCexpMaxW) for the Taylor propagation, its degree J;
+  // sparse_prop when H0 qualifies (at most kCexpMaxW entries a row, dtau ||H0|| <= 1)
+  int *ell_idx = nullptr;
+  double2 *ell_val = nullptr;
+  int ell_w = 0, taylor_J = 0;
+  bool sparse_prop = false;
   int *nflush = nullptr;
   int *accx = nullptr;                              // accepted sites' old fields (decide)
   int8_t *fields = nullptr;
@@ -60,7 +66,7 @@ struct pqmc_soc_ctx {
 
 namespace {
 
-constexpr unsigned kSocFlags = PQMC_FLAG_LOG | PQMC_FLAG_TIMING;
+constexpr unsigned kSocFlags = PQMC_FLAG_LOG | PQMC_FLAG_TIMING | PQMC_FLAG_DENSE_PROP;
 
 double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
@@ -86,7 +92,7 @@ pqmc_status validate(const pqmc_soc_problem *p, const pqmc_update_opts *o) {
     return err(PQMC_EINVAL, "delay_k in [1, 32] for the SOC path");
   if (o->scheme == PQMC_BLOCK_FB && (o->block_b < 1 || o->block_b > kSocMaxK))
     return err(PQMC_EINVAL, "block_b in [1, 32] for the SOC path");
-  if (o->flags & ~kSocFlags) return err(PQMC_EINVAL, "flags: only LOG and TIMING");
+  if (o->flags & ~kSocFlags) return err(PQMC_EINVAL, "flags: only LOG, TIMING and DENSE_PROP");
   const long n2 = 2L * p->n_sites;
   double asym = 0.0, amax = 0.0;
   for (long i = 0; i < n2; ++i)
@@ -146,6 +152,8 @@ void layout(pqmc_soc_ctx &c, char *base, size_t *bytes) {
   c.Kinv = cv.take<double2>(n2 * n2);
   c.Tay0 = cv.take<double2>(n2 * n2);
   c.Tay1 = cv.take<double2>(n2 * n2);
+  c.ell_idx = cv.take<int>(n2 * kCexpMaxW);
+  c.ell_val = cv.take<double2>(n2 * kCexpMaxW);
   c.P = cv.take<double2>(n2 * ne);
   c.Lstack = cv.take<double2>((c.nst + 1) * n2 * ne);
   c.Rstack = cv.take<double2>((c.nst + 1) * n2 * ne);
@@ -250,6 +258,33 @@ struct CgemmQueue {
   }
 };
 
+struct CexpvQueue {
+  hipStream_t st;
+  CexpvBatch cur{};
+  int add(const CexpvDesc &d) {
+    cur.d[cur.count++] = d;
+    return cur.count == kCexpvMaxBatch ? flush() : PQMC_OK;
+  }
+  int flush() {
+    if (cur.count == 0) return PQMC_OK;
+    hipError_t e = cexpv(cur, st);
+    cur.count = 0;
+    if (e != hipSuccess) return fail_device(e, "cexpv", __FILE__, __LINE__);
+    return PQMC_OK;
+  }
+};
+
+// the Taylor propagation applies (H0 qualified and the dense form not asked for)
+bool sparse(const pqmc_soc_ctx &c) {
+  return c.sparse_prop && !(c.opts.flags & PQMC_FLAG_DENSE_PROP);
+}
+
+// Y = e^{a M} X for M = H0 (conj = 0) or H0^T = conj(H0) (conj = 1)
+CexpvDesc cexpv_desc(const pqmc_soc_ctx &c, const double2 *X, double2 *Y, double a, int conj) {
+  return CexpvDesc{X, c.ne, Y, c.ne, c.n2, c.ne, c.ell_idx, c.ell_val, c.ell_w, c.taylor_J, a,
+                   conj};
+}
+
 struct CsumQueue {
   hipStream_t st;
   CsumBatch cur{};
@@ -323,14 +358,22 @@ int prop_forward(const SocWalkers &b, int l) {
   pqmc_soc_ctx &L = b.lead();
   const int n2 = L.n2, ne = L.ne;
   CgemmQueue qr{L.st, kOpN, kOpN}, ql{L.st, kOpT, kOpN};
+  CexpvQueue qx{L.st};
   for (int i = 0; i < b.n; ++i) {
     pqmc_soc_ctx &c = b[i];
-    int rc = qr.add(cdesc(c.K, n2, c.UR, ne, other(c.UR, c.Rw), ne, n2, ne, n2));
-    if (!rc) rc = ql.add(cdesc(c.Kinv, n2, c.ULt, ne, other(c.ULt, c.Lw), ne, n2, ne, n2));
+    int rc;
+    if (sparse(c)) {   // K = e^{-dtau H0}; K^{-T} = e^{dtau H0^T}
+      rc = qx.add(cexpv_desc(c, c.UR, other(c.UR, c.Rw), -c.dtau, 0));
+      if (!rc) rc = qx.add(cexpv_desc(c, c.ULt, other(c.ULt, c.Lw), c.dtau, 1));
+    } else {
+      rc = qr.add(cdesc(c.K, n2, c.UR, ne, other(c.UR, c.Rw), ne, n2, ne, n2));
+      if (!rc) rc = ql.add(cdesc(c.Kinv, n2, c.ULt, ne, other(c.ULt, c.Lw), ne, n2, ne, n2));
+    }
     if (rc) return rc;
   }
   int rc = qr.flush();
   if (!rc) rc = ql.flush();
+  if (!rc) rc = qx.flush();
   if (rc) return rc;
   for (int i = 0; i < b.n; ++i) {
     pqmc_soc_ctx &c = b[i];
@@ -358,6 +401,7 @@ int prop_backward(const SocWalkers &b, int l, bool with_R) {
   const int n2 = L.n2, ne = L.ne;
   // ULt <- K^T diag(e^{i gamma x}) ULt; U_R <- K^{-1} diag(e^{-i gamma x}) U_R (w = 1)
   CgemmQueue ql{L.st, kOpT, kOpN};
+  CexpvQueue qx{L.st};
   for (int i = 0; i < b.n; ++i) {
     pqmc_soc_ctx &c = b[i];
     const int8_t *x = c.fields + (size_t)(l - 1) * c.N;
@@ -365,14 +409,18 @@ int prop_backward(const SocWalkers &b, int l, bool with_R) {
       PQ_HIP_CHECK(phase_rows(c.ULt, ne, c.Xtmp, ne, ne, c.N, x, c.c1, c.s1, 1.0, c.st));
     else
       PQ_HIP_CHECK(rotate_rows(c.ULt, ne, c.Xtmp, ne, ne, c.N, x, c.c1, c.s1, -1.0, c.st));
-    int rc = ql.add(cdesc(c.K, n2, c.Xtmp, ne, other(c.ULt, c.Lw), ne, n2, ne, n2));
+    const int rc = sparse(c)   // K^T = e^{-dtau H0^T}
+                       ? qx.add(cexpv_desc(c, c.Xtmp, other(c.ULt, c.Lw), -c.dtau, 1))
+                       : ql.add(cdesc(c.K, n2, c.Xtmp, ne, other(c.ULt, c.Lw), ne, n2, ne, n2));
     if (rc) return rc;
   }
   int rc = ql.flush();
+  if (!rc) rc = qx.flush();
   if (rc) return rc;
   for (int i = 0; i < b.n; ++i) b[i].ULt = other(b[i].ULt, b[i].Lw);
   if (!with_R) return PQMC_OK;
   CgemmQueue qr{L.st, kOpN, kOpN};
+  CexpvQueue qy{L.st};
   for (int i = 0; i < b.n; ++i) {
     pqmc_soc_ctx &c = b[i];
     const int8_t *x = c.fields + (size_t)(l - 1) * c.N;
@@ -380,10 +428,13 @@ int prop_backward(const SocWalkers &b, int l, bool with_R) {
       PQ_HIP_CHECK(phase_rows(c.UR, ne, c.Xtmp, ne, ne, c.N, x, c.c1, c.s1, -1.0, c.st));
     else
       PQ_HIP_CHECK(rotate_rows(c.UR, ne, c.Xtmp, ne, ne, c.N, x, c.c1, c.s1, -1.0, c.st));
-    rc = qr.add(cdesc(c.Kinv, n2, c.Xtmp, ne, other(c.UR, c.Rw), ne, n2, ne, n2));
+    rc = sparse(c)   // K^{-1} = e^{dtau H0}
+             ? qy.add(cexpv_desc(c, c.Xtmp, other(c.UR, c.Rw), c.dtau, 0))
+             : qr.add(cdesc(c.Kinv, n2, c.Xtmp, ne, other(c.UR, c.Rw), ne, n2, ne, n2));
     if (rc) return rc;
   }
   rc = qr.flush();
+  if (!rc) rc = qy.flush();
   if (rc) return rc;
   for (int i = 0; i < b.n; ++i) b[i].UR = other(b[i].UR, b[i].Rw);
   return PQMC_OK;
@@ -711,6 +762,54 @@ static pqmc_status create_common(pqmc_soc_ctx *c, const double *hopping, const d
   if (e == hipSuccess) e = hipStreamSynchronize(c->st);
   if (e != hipSuccess) return fail(fail_device(e, "upload", __FILE__, __LINE__));
   const double x = c->dtau * norm;
+  // H0 in ELL form for the Taylor propagation when it is sparse enough; the
+  // degree J is the smallest whose first dropped term x^{J+1} / (J+1)! is at
+  // most 2^-60 (x = dtau ||H0|| <= 1, ||H0|| the largest absolute row sum)
+  {
+    int w = 0;
+    for (size_t i = 0; i < n2; ++i) {
+      int nz = 0;
+      for (size_t j = 0; j < n2; ++j)
+        nz += (hopping[2 * (i * n2 + j)] != 0.0 || hopping[2 * (i * n2 + j) + 1] != 0.0);
+      w = std::max(w, nz);
+    }
+    if (w <= kCexpMaxW && (int)n2 <= kCexpMaxN && x <= 1.0) {
+      w = std::max(w, 1);
+      std::vector<int> idx(n2 * w);
+      std::vector<double2> val(n2 * w);
+      for (size_t i = 0; i < n2; ++i) {
+        int m = 0;
+        for (size_t j = 0; j < n2; ++j) {
+          const double re = hopping[2 * (i * n2 + j)], im = hopping[2 * (i * n2 + j) + 1];
+          if (re != 0.0 || im != 0.0) {
+            idx[i * w + m] = (int)j;
+            val[i * w + m] = make_double2(re, im);
+            ++m;
+          }
+        }
+        for (; m < w; ++m) {
+          idx[i * w + m] = (int)i;
+          val[i * w + m] = make_double2(0.0, 0.0);
+        }
+      }
+      int J = 0;
+      double term = 1.0;   // x^J / J!
+      while (x > 0.0 && term * x / (J + 1) > std::ldexp(1.0, -60)) {
+        ++J;
+        term *= x / J;
+      }
+      hipError_t ee = hipMemcpyAsync(c->ell_idx, idx.data(), sizeof(int) * idx.size(),
+                                     hipMemcpyHostToDevice, c->st);
+      if (ee == hipSuccess)
+        ee = hipMemcpyAsync(c->ell_val, val.data(), sizeof(double2) * val.size(),
+                            hipMemcpyHostToDevice, c->st);
+      if (ee == hipSuccess) ee = hipStreamSynchronize(c->st);   // the host vectors go away
+      if (ee != hipSuccess) return fail(fail_device(ee, "upload H0 rows", __FILE__, __LINE__));
+      c->ell_w = w;
+      c->taylor_J = J;
+      c->sparse_prop = true;
+    }
+  }
   const int sq = x > 0.5 ? (int)std::ceil(std::log2(x / 0.5)) : 0;
   const double scale = c->dtau / std::ldexp(1.0, sq);
   int rc = expm(*c, -scale, sq, c->K);
@@ -903,7 +1002,7 @@ namespace pq {
 namespace soc {
 
 namespace {
-constexpr unsigned kOneFlags = PQMC_FLAG_LOG | PQMC_FLAG_TIMING;
+constexpr unsigned kOneFlags = PQMC_FLAG_LOG | PQMC_FLAG_TIMING | PQMC_FLAG_DENSE_PROP;
 
 pqmc_status one_check_opts(const pqmc_update_opts *o) {
   if (o->scheme != PQMC_LOCAL && o->scheme != PQMC_DELAYED && o->scheme != PQMC_BLOCK_FB)
@@ -912,7 +1011,8 @@ pqmc_status one_check_opts(const pqmc_update_opts *o) {
     return err(PQMC_EINVAL, "delay_k in [1, 64] for U < 0");
   if (o->scheme == PQMC_BLOCK_FB && (o->block_b < 1 || o->block_b > 2 * kSocMaxK))
     return err(PQMC_EINVAL, "block_b in [1, 64] for U < 0");
-  if (o->flags & ~kOneFlags) return err(PQMC_EINVAL, "flags for U < 0: only LOG and TIMING");
+  if (o->flags & ~kOneFlags)
+    return err(PQMC_EINVAL, "flags for U < 0: only LOG, TIMING and DENSE_PROP");
   return PQMC_OK;
 }
 

@@ -120,3 +120,57 @@ def test_triangular_hopping_eight_wide_rows():
     q = dataclasses.replace(p, hopping=H, trial_up=np.ascontiguousarray(V[:, :13]),
                             trial_dn=np.ascontiguousarray(V[:, :13]))
     _both(q, "delayed", sweeps=1, k=6)
+
+
+def _soc_both(p, scheme, k, sweeps=1):
+    """SOC walkers with the Taylor propagation of the sparse complex H0 and with
+    the dense K: the oracle's decisions and G for both, the two G equal to
+    1e-12 and not bitwise equal."""
+    from oracle.soc import SocWalker
+    from paper_2506_09611_amd import SocChain, Scheme
+    sc = {"local": Scheme.LOCAL, "delayed": Scheme.DELAYED, "block": Scheme.BLOCK_FB}[scheme]
+    chains = [SocChain(p.hopping, p.trial, p.U, p.dtau, p.n_slices, p.stab_every, p.seed,
+                       p.walker_id, scheme=sc, k=k, log=True, dense_prop=d)
+              for d in (False, True)]
+    w = SocWalker(p, scheme, k=k, b=k)
+    for sw in range(sweeps):
+        w.sweep()
+        for ch in chains:
+            ch.sweep(1)
+            meta, margin = ch.decisions()
+            compare_decisions(meta, margin, w.log, sw, p.n_slices)
+            assert np.array_equal(ch.fields(), w.fields)
+            G, Gr = ch.green(), w.green()
+            assert np.max(np.abs(G - Gr)) / max(1.0, np.max(np.abs(Gr))) < 1e-10
+        Gs, Gd = chains[0].green(), chains[1].green()
+        d = np.max(np.abs(Gs - Gd)) / max(1.0, np.max(np.abs(Gd)))
+        print(f"soc {scheme} L={p.L} sweep {sw}: sparse vs dense G {d:.2e}", flush=True)
+        assert d < 1e-12
+    assert not np.array_equal(chains[0].green(), chains[1].green())
+    for ch in chains:
+        ch.close()
+
+
+@pytest.mark.parametrize("scheme,k", [("local", 1), ("delayed", 8), ("block", 4)])
+def test_soc_sparse_and_dense_propagation_4x4(scheme, k):
+    """Rashba hopping (eight nonzeros per row of the 2N x 2N H0: four same-spin
+    and four spin-flip neighbours) on 4x4, two sweeps."""
+    p = synth.make_soc_problem(4, 14, -4.0, lam=0.5, dtau=0.05, n_slices=20, stab_every=5,
+                               perturb=1e-3, seed=synth.SEED_BASE + 106)
+    _soc_both(p, scheme, k, sweeps=2)
+
+
+@pytest.mark.timeout(300)
+def test_soc_sparse_and_dense_propagation_16x16():
+    """2N = 512, N_e = 256 (R = 1 row a thread, eight entries): one sweep."""
+    p = synth.make_soc_problem(16, 256, -4.0, lam=0.5, dtau=0.05, n_slices=10, stab_every=5,
+                               perturb=1e-3, seed=synth.SEED_BASE + 107)
+    _soc_both(p, "delayed", 32)
+
+
+def test_negative_u_sparse_and_dense_propagation():
+    """The U < 0 one-sector model (real H0 embedded in complex) through the
+    spin-decoupled calls, both propagation forms against the oracle."""
+    p = synth.make_problem(6, 13, 13, -4.0, n_slices=20, stab_every=5, perturb=1e-3,
+                           seed=synth.SEED_BASE + 108)
+    _both(p, "delayed", sweeps=2, k=4)
