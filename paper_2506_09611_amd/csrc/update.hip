@@ -883,12 +883,16 @@ __device__ double lds_gj_inverse(double *A, int ld, int n, double *colk, double 
       rowk[i] = A[k * ld + i] * ip;
     }
     __syncthreads();
-    for (int e = t; e < n * n; e += NT) {
-      const int i = e / n, j = e % n;
-      double v;
-      if (i == k) v = (j == k) ? ip : rowk[j];
-      else v = (j == k) ? -colk[i] * ip : A[i * ld + j] - colk[i] * rowk[j];
-      A[i * ld + j] = v;
+    // rows t / 64 + (NT / 64) q, columns t % 64 (n <= 64; no integer division)
+    for (int i = t >> 6; i < n; i += NT / 64) {
+      const int j = t & 63;
+      if (j < n) {
+        const double ci = colk[i];
+        double v;
+        if (i == k) v = (j == k) ? ip : rowk[j];
+        else v = (j == k) ? -ci * ip : A[i * ld + j] - ci * rowk[j];
+        A[i * ld + j] = v;
+      }
     }
     __syncthreads();
   }
@@ -914,59 +918,74 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
-// lds_gj_inverse for one wave: the calling wave's 64 lanes invert the n x n
-// matrix A (n <= 64) in place with no workgroup barrier, so that two waves
-// can invert two matrices at once; returns det(A) in every lane.
-__device__ double wave_gj_inverse(double *A, int ld, int n, double *colk, double *rowk,
-                                  int *ipiv) {
-  const int lane = threadIdx.x & 63;
+// In-place inverse of the n x n matrix A (n <= 16, LDS, row-major, stride ld)
+// by Gauss-Jordan elimination with partial pivoting, by the 64 lanes of the
+// calling wave alone (no workgroup barrier, so that two waves can invert two
+// matrices at once); returns det(A) in every lane.  Lane (i, q) = (lane / 4,
+// lane % 4) owns row i, columns q + 4 p.  Per column: the pivot (the largest
+// |A_rk|, r >= k, by an integer max over keys that pack the magnitude's bits
+// with 63 - r, so ties go to the smaller row), the row swap, then every
+// entry's new value from loads issued before any store (a wave's LDS
+// operations complete in order), so one LDS round trip a column.
+__device__ __forceinline__ unsigned long long shfl_xor_key(unsigned long long v, int m) {
+  const int lo = __shfl_xor((int)(unsigned)v, m, 64);
+  const int hi = __shfl_xor((int)(unsigned)(v >> 32), m, 64);
+  return ((unsigned long long)(unsigned)hi << 32) | (unsigned long long)(unsigned)lo;
+}
+
+__device__ double wave_gj_inverse16(double *A, int ld, int n, int *ipiv) {
+  const int lane = threadIdx.x & 63, i = lane >> 2, jq = lane & 3;
+  const int ic = min(i, n - 1);
   double det = 1.0;
   for (int k = 0; k < n; ++k) {
-    const bool cand = lane >= k && lane < n;
-    double bv = cand ? fabs(A[lane * ld + k]) : -1.0;
-    int bi = cand ? lane : 0x7fffffff;
+    const double av = A[ic * ld + k];
+    unsigned long long key =
+        (i >= k && i < n)
+            ? (((unsigned long long)__double_as_longlong(fabs(av)) & ~0x3Full) |
+               (unsigned long long)(63 - i))
+            : 0ull;
+    // the four lanes of a row hold the same key: reduce over the rows only
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      const double ov = __shfl_xor(bv, o, 64);
-      const int oi = __shfl_xor(bi, o, 64);
-      const bool take = (ov > bv) || (ov == bv && oi < bi);
-      bv = take ? ov : bv;
-      bi = take ? oi : bi;
+    for (int m = 4; m < 64; m <<= 1) {
+      const unsigned long long o = shfl_xor_key(key, m);
+      key = o > key ? o : key;
     }
-    const int p = __builtin_amdgcn_readfirstlane(bi < n ? bi : k);
+    const int p = __builtin_amdgcn_readfirstlane(min(63 - (int)(key & 0x3F), n - 1));
     if (lane == 0) ipiv[k] = p;
-    if (p != k)
-      for (int j = lane; j < n; j += 64) {
-        const double x = A[k * ld + j];
-        A[k * ld + j] = A[p * ld + j];
-        A[p * ld + j] = x;
-      }
+    if (p != k && lane < n) {
+      const double x = A[k * ld + lane];
+      A[k * ld + lane] = A[p * ld + lane];
+      A[p * ld + lane] = x;
+    }
     wave_sync();
     const double piv = A[k * ld + k];
-    det *= (p != k) ? -piv : piv;
-    const double ip = 1.0 / piv;
-    for (int i = lane; i < n; i += 64) {
-      colk[i] = A[i * ld + k];
-      rowk[i] = A[k * ld + i] * ip;
+    const double aik = A[ic * ld + k];
+    double akj[4], aij[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int jc = min(jq + 4 * q, n - 1);
+      akj[q] = A[k * ld + jc];
+      aij[q] = A[ic * ld + jc];
     }
-    wave_sync();
-    for (int e = lane; e < n * n; e += 64) {
-      const int i = e / n, j = e % n;
-      double v;
-      if (i == k) v = (j == k) ? ip : rowk[j];
-      else v = (j == k) ? -colk[i] * ip : A[i * ld + j] - colk[i] * rowk[j];
-      A[i * ld + j] = v;
+    const double ip = 1.0 / piv;
+    det *= (p != k) ? -piv : piv;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int j = jq + 4 * q;
+      if (i < n && j < n) {
+        const double rk = akj[q] * ip;
+        A[i * ld + j] = (i == k) ? ((j == k) ? ip : rk) : ((j == k) ? -aik * ip : aij[q] - aik * rk);
+      }
     }
     wave_sync();
   }
   for (int k = n - 1; k >= 0; --k) {
     const int p = __builtin_amdgcn_readfirstlane(ipiv[k]);
-    if (p != k)
-      for (int i = lane; i < n; i += 64) {
-        const double x = A[i * ld + k];
-        A[i * ld + k] = A[i * ld + p];
-        A[i * ld + p] = x;
-      }
+    if (p != k && lane < n) {
+      const double x = A[lane * ld + k];
+      A[lane * ld + k] = A[lane * ld + p];
+      A[lane * ld + p] = x;
+    }
     wave_sync();
   }
   return det;
@@ -993,7 +1012,7 @@ __global__ __launch_bounds__(NT) void block_decide_kernel(Batch<DecideArgs> B) {
   __shared__ double colk[64], rowk[64];
   __shared__ int ipiv[64];
   __shared__ int s_piv;
-  __shared__ double colk2[2][64], rowk2[2][64], rdet[2];   // the two-wave form
+  __shared__ double rdet[2];   // the two-wave form
   __shared__ int ipiv2[2][64];
   __shared__ double db[2][64], nbar[2][64], sval[64], dp[2][64], hbm[64];
   __shared__ int xold[64], xnew[64], flist[64], posF[64];
@@ -1020,7 +1039,7 @@ __global__ __launch_bounds__(NT) void block_decide_kernel(Batch<DecideArgs> B) {
       Mw[ia * LD + ib] = (ia == ib ? 1.0 : 0.0) + db[sw][ia] * W0s[sw][ia * LD + ib];
     }
     wave_sync();
-    wave_gj_inverse(Mw, LD, kk, colk2[sw], rowk2[sw], ipiv2[sw]);
+    wave_gj_inverse16(Mw, LD, kk, ipiv2[sw]);
     if (ln < kk) {
       double v = 0.0;
       for (int m = 0; m < kk; ++m) v += W0s[sw][ln * LD + m] * Mw[m * LD + ln];
@@ -1115,7 +1134,7 @@ __global__ __launch_bounds__(NT) void block_decide_kernel(Batch<DecideArgs> B) {
   if constexpr (NT == 128) {
     // wave s: spin s's flip-set determinant and inverse, both at once
     const int sw = t >> 6;
-    const double r = wave_gj_inverse(sw ? M1 : M0, LD, nF, colk2[sw], rowk2[sw], ipiv2[sw]);
+    const double r = wave_gj_inverse16(sw ? M1 : M0, LD, nF, ipiv2[sw]);
     if ((t & 63) == 0) rdet[sw] = r;
     __syncthreads();
     r0 = rdet[0];
