@@ -188,6 +188,7 @@ void layout(pqmc_ctx &c, char *base, size_t *bytes) {
   c.lb.delta[0] = cv.take<double>(2);
   c.lb.delta[1] = cv.take<double>(2);
   c.gb.nA = cv.take<int>(2);
+  c.gb.alist = cv.take<int>(kmax);
   c.gb.uni = cv.take<double>(kmax + 1);
   c.gb.kmax = kmax;
   c.gb.chunks = c.opts.tile_chunks > 0 ? c.opts.tile_chunks : 2;

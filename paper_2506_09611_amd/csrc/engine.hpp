@@ -165,6 +165,7 @@ struct GroupBufs {
   double *sc[2];                   // kmax
   double *Q[2];                    // Ns x kmax: P1 Mc (flush without the tile kernel)
   int *nA;                         // 2: |A|, and the flush rank (kk, or 0 when A is empty)
+  int *alist;                      // kmax: the sites of A in increasing order (|A| of them)
   int kmax;
   int Ns[2];                       // particles per spin
   int chunks;                      // tile kernel: column chunks asked per row strip

@@ -527,6 +527,11 @@ __global__ __launch_bounds__(kDecThreads) void delayed_decide_kernel(Batch<Decid
     A.g.sc[0][t] = mine ? 1.0 + dl[0][t] : 1.0;
     A.g.sc[1][t] = mine ? 1.0 + dl[1][t] : 1.0;
     if (mine) C.fields[(long)C.li * C.N + A.g0 + t] = (int8_t)(-C.fields[(long)C.li * C.N + A.g0 + t]);
+    if (mine) {   // the accepted sites in order
+      int pos = 0;
+      for (int m = 0; m < t; ++m) pos += acc_s[m];
+      A.g.alist[pos] = t;
+    }
   }
   if (t == 0) {
     A.g.nA[0] = (int)n_acc;
@@ -692,6 +697,7 @@ __global__ __launch_bounds__(64) void delayed_decide_wave_kernel(Batch<DecideArg
     A.g.sc[0][lane] = mine ? 1.0 + C.dflip[0][xl > 0 ? 0 : 1] : 1.0;
     A.g.sc[1][lane] = mine ? 1.0 + C.dflip[1][xl > 0 ? 0 : 1] : 1.0;
     if (mine) C.fields[(long)C.li * C.N + A.g0 + lane] = (int8_t)(-xl);
+    if (mine) A.g.alist[__popcll(amask & ((1ull << lane) - 1))] = lane;   // A in order
   }
   // Mc = diag(Delta_A) (E_AA)^{-1} = -diag(Delta_A) (swept E)_AA, zero elsewhere
 #pragma unroll
@@ -823,7 +829,10 @@ __global__ __launch_bounds__(128) void delayed_decide_spin_kernel(Batch<DecideAr
   if (lane < kk) {
     const bool mine = (amask >> lane) & 1;
     A.g.sc[sp][lane] = mine ? 1.0 + C.dflip[sp][xl > 0 ? 0 : 1] : 1.0;
-    if (sp == 0 && mine) C.fields[(long)C.li * C.N + A.g0 + lane] = (int8_t)(-xl);
+    if (sp == 0 && mine) {
+      C.fields[(long)C.li * C.N + A.g0 + lane] = (int8_t)(-xl);
+      A.g.alist[__popcll(amask & ((1ull << lane) - 1))] = lane;   // A in order
+    }
   }
   // Mc_s = diag(Delta_A) (E_AA)^{-1} = -diag(Delta_A) (swept E)_AA, zero elsewhere
   double *Mc = A.g.Mc[sp];
@@ -1168,6 +1177,7 @@ __global__ __launch_bounds__(NT) void block_decide_kernel(Batch<DecideArgs> B) {
   }
   if (acc_b) {
     // Mc = diag(Delta'_F) (E'_FF)^{-1} spread to kk x kk, row scales, new fields
+    if (t < nF) A.g.alist[t] = flist[t];   // F in site order
     if (t < kk) {
       const int pf = posF[t];
       A.g.sc[0][t] = pf >= 0 ? 1.0 + dp[0][pf] : 1.0;
@@ -1310,14 +1320,23 @@ __global__ __launch_bounds__(kTileThreads, KP <= 32 ? 4 : 1) void group_tile_ker
   const int row0 = rb * 64;
   const int kmax = a.g.kmax;
   const int kk = a.kk, kkp = a.kk_prev;
-  const int kp = (kkp + 3) & ~3;            // flush rank rounded to the MFMA depth
-  R *T = tile_matrix<R>(a.m, s);
   extern __shared__ double lds_raw[];
+  const bool fl = a.flush && a.g.nA[0] > 0;
+  // The flush has rank |A|: P1 Mc P2 only involves the accepted sites'
+  // columns of P1 and rows of P2 (Mc is zero outside A x A), so they are
+  // gathered by the pending group's site list and the flush runs at |A|
+  // rounded to the MFMA depth instead of the group size.
+  const int na = fl ? a.g.nA[0] : 0;
+  const int kp = (na + 3) & ~3;
+  __shared__ int al_s[KP];
+  for (int e = t; e < KP; e += NT)
+    al_s[e] = (e < na) ? a.g.alist[e] : (na > 0 ? a.g.alist[na - 1] : 0);
+  __syncthreads();
+  R *T = tile_matrix<R>(a.m, s);
   R *lds = reinterpret_cast<R *>(lds_raw);
   R *Y = lds;                      // KP x kLdt: U_g over the strip's rows (whole walk)
   R *X = Y + KP * kLdt;            // 64 x kLdt: the current tile of T
   R *Zb = X + 64 * kLdt;           // KP x kLdt: the tile's P2 columns, then its L_g columns
-  const bool fl = a.flush && a.g.nA[0] > 0;
 
   // accepted rows of U_R over the chunk's columns, by the first strip
   if (fl && rb == 0) {
@@ -1349,13 +1368,16 @@ __global__ __launch_bounds__(kTileThreads, KP <= 32 ? 4 : 1) void group_tile_ker
     for (int i = 0; i < kPre; ++i) {
       const int e = t + NT * i;
       const int r = e / kpad, m = e % kpad;
-      A1[r * ld1 + m] = (m < kkp && row0 + r < Ns) ? (R)P1[(long)(row0 + r) * kmax + m] : (R)0.0;
+      A1[r * ld1 + m] =
+          (m < na && row0 + r < Ns) ? (R)P1[(long)(row0 + r) * kmax + al_s[m]] : (R)0.0;
     }
 #pragma unroll
     for (int i = 0; i < kPreM; ++i) {
       const int e = t + NT * i;
       const int ma = e / kpad, mb = e % kpad;
-      if (e < kpad * kpad) M1[ma * ld1 + mb] = (ma < kkp && mb < kkp) ? (R)Mc[ma * kmax + mb] : (R)0.0;
+      if (e < kpad * kpad)
+        M1[ma * ld1 + mb] =
+            (ma < na && mb < na) ? (R)Mc[al_s[ma] * kmax + al_s[mb]] : (R)0.0;
     }
     __syncthreads();
     {
@@ -1453,7 +1475,7 @@ __global__ __launch_bounds__(kTileThreads, KP <= 32 ? 4 : 1) void group_tile_ker
       for (int i = 0; i < kPre; ++i) {
         const int e = t + NT * i;
         const int m = e >> 6, c = cb * 64 + (e & 63);
-        pv[i] = P2[(long)min(m, kkp - 1) * Ns + min(c, Ns - 1)];
+        pv[i] = P2[(long)al_s[min(m, KP - 1)] * Ns + min(c, Ns - 1)];
       }
     };
     load_tile(cb0, acc, lg);
