@@ -783,18 +783,16 @@ def main():
             cs = [c1]
             if name == "local" and args.local_window > 0:
                 # the per-site-launch form (the one batches of walkers use)
+                # (per-launch HIP events on: the per-site kernel against the
+                # HBM roofline at the window's own acceptance)
                 sl = make_walkers(p, name, args.k, args.b, W, streams[:1])
                 for x in sl:
-                    x.set_opts(x.scheme, x.k, x.b, site_launches=True)
+                    x.set_opts(x.scheme, x.k, x.b, site_launches=True, ktime=True)
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
-                batch_forward_window(sl, args.local_window)
+                kst = batch_forward_window(sl, args.local_window)
                 torch.cuda.synchronize()
                 w = time.perf_counter() - t0
-                # the per-site kernel against the HBM roofline: one more slice
-                # visit with per-launch events, at that visit's acceptance
-                sl[0].set_opts(sl[0].scheme, sl[0].k, sl[0].b, ktime=True)
-                kst = batch_forward_window(sl, 1)
                 acc_l = sum(x["accepted"] for x in kst) / max(1, sum(x["proposed"] for x in kst))
                 roof_l = roofline(p, "local", args.k, args.b, acc_l, sl[0].kernel_times(),
                                   "local", walkers=W)
@@ -805,7 +803,7 @@ def main():
                 schemes["local_site_launches"] = {
                     "window_slice_visits": args.local_window, "s_window": w,
                     "field_updates_per_s": W * args.local_window * N / w, "walkers": W,
-                    "note": "one launch per site, one batch, forward window",
+                    "note": "one launch per site, one batch, forward window, per-launch events",
                     "roofline": roof_l}
                 cs += sl
         else:
