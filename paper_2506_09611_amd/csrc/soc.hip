@@ -902,10 +902,35 @@ __device__ void gj_lds(double2 *A, int n, int ncols, int ld, double2 *det, int *
       *det = dt;
     }
     __syncthreads();
-    for (int e = t; e < n * ncols; e += kDecThreads) {
-      const int r = e / ncols, c = e - r * ncols;
-      if (r == j || c < j) continue;
-      A[r * ld + c] = csub(A[r * ld + c], cmul(fcol[r], A[j * ld + c]));
+    // rows wave + 4 q, columns lane and lane + 64 (n <= 64, ncols <= 128):
+    // the entries and multipliers of four rows a wave loaded before any of
+    // their stores, one LDS round trip per four rows (no integer division)
+    {
+      const int wv = t >> 6;
+      double2 ajc[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) ajc[h] = A[j * ld + min(lane + 64 * h, ncols - 1)];
+      // four rows a wave at a time, their loads issued together
+      auto upd = [&](int r, double2 f, double2 v0, double2 v1) {
+        if (r < n && r != j) {
+          if (lane < ncols && lane >= j) A[r * ld + lane] = csub(v0, cmul(f, ajc[0]));
+          if (lane + 64 < ncols && lane + 64 >= j) A[r * ld + lane + 64] = csub(v1, cmul(f, ajc[1]));
+        }
+      };
+      const int c0 = min(lane, ncols - 1), c1 = min(lane + 64, ncols - 1);
+      for (int r0 = wv; r0 < n; r0 += 16) {
+        const int ra = r0, rb = r0 + 4, rc = r0 + 8, rd = r0 + 12;
+        const int pa = min(ra, n - 1), pb = min(rb, n - 1), pc = min(rc, n - 1), pd = min(rd, n - 1);
+        const double2 fa = fcol[pa], fb = fcol[pb], fc = fcol[pc], fd = fcol[pd];
+        const double2 a0 = A[pa * ld + c0], a1 = A[pa * ld + c1];
+        const double2 b0 = A[pb * ld + c0], b1 = A[pb * ld + c1];
+        const double2 d0 = A[pc * ld + c0], d1 = A[pc * ld + c1];
+        const double2 e0 = A[pd * ld + c0], e1 = A[pd * ld + c1];
+        upd(ra, fa, a0, a1);
+        upd(rb, fb, b0, b1);
+        upd(rc, fc, d0, d1);
+        upd(rd, fd, e0, e1);
+      }
     }
     __syncthreads();
   }
@@ -1029,6 +1054,8 @@ __global__ __launch_bounds__(kDecThreads) void soc_block_decide_kernel(SocDecide
   __syncthreads();
   // D = delta_F S_F^{-1} spread to the block's n x n (zero elsewhere)
   for (int e = t; e < n * n; e += kDecThreads) a.D[e] = make_double2(0.0, 0.0);
+  if (!acc_s)
+    for (int j = t; j < kk; j += kDecThreads) a.accx[j] = 0;   // no rows to turn
   __syncthreads();
   if (!acc_s) return;
   for (int e = t; e < m * m; e += kDecThreads) {
@@ -1044,18 +1071,11 @@ __global__ __launch_bounds__(kDecThreads) void soc_block_decide_kernel(SocDecide
     const int ar = r < nf ? j : kk + j, ac = c < nf ? jc : kk + jc;
     a.D[(long)ar * n + ac] = make_double2(e0 * m0.x + e1 * m1.x, e0 * m0.y + e1 * m1.y);
   }
-  // fields and U_R row pairs of the flip set
-  for (int q = 0; q < nf; ++q) {
-    const int j = fidx[q];
-    const double x = xs[j];
-    const double d00 = 1.0 + a.dd, d01 = -x * a.doff, d10 = x * a.doff, d11 = 1.0 + a.dd;
-    double2 *p0 = a.UR + (long)(a.g0 + j) * a.ne, *p1 = a.UR + (long)(a.N + a.g0 + j) * a.ne;
-    for (int c = t; c < a.ne; c += kDecThreads) {
-      const double2 r0 = p0[c], r1 = p1[c];
-      p0[c] = make_double2(d00 * r0.x + d01 * r1.x, d00 * r0.y + d01 * r1.y);
-      p1[c] = make_double2(d10 * r0.x + d11 * r1.x, d10 * r0.y + d11 * r1.y);
-    }
-    if (t == 0) xrow[j] = (int8_t)(x > 0.0 ? -1 : 1);
+  // fields of the flip set, and its old fields for rotate_accepted (which
+  // turns the U_R row pairs)
+  for (int j = t; j < kk; j += kDecThreads) {
+    if (flip[j]) xrow[j] = (int8_t)(xs[j] > 0.0 ? -1 : 1);
+    a.accx[j] = flip[j] ? (int)xs[j] : 0;
   }
 }
 

@@ -587,10 +587,11 @@ int update_slice(const SocWalkers &b, int l, int dir) {
       d.force = c.replaying ? c.replay + ((size_t)dir * c.M + li) * N : nullptr;
       da[i] = d;
     }
-    if (L.block) {
-      PQ_HIP_CHECK(L.w == 1 ? block_decide1(da, b.n, L.st) : block_decide(da, b.n, L.st));
+    if (L.block && L.w == 1) {
+      PQ_HIP_CHECK(block_decide1(da, b.n, L.st));
     } else {
-      PQ_HIP_CHECK(L.w == 1 ? decide1(da, b.n, L.st) : decide(da, b.n, L.st));
+      PQ_HIP_CHECK(L.block ? block_decide(da, b.n, L.st)
+                           : (L.w == 1 ? decide1(da, b.n, L.st) : decide(da, b.n, L.st)));
       PQ_HIP_CHECK(rotate_accepted(da, b.n, L.w, L.st));
     }
     CgemmQueue qq{L.st, kOpN, kOpN};
