@@ -118,7 +118,7 @@ TRAFFIC_FILES = {
 }
 
 
-def measured_traffic(cls, scheme, k, walkers, workload):
+def measured_traffic(cls, scheme, k, walkers, workload, tile_chunks=None):
     """HBM bytes per launch of the tile kernel or the per-site local kernel
     from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE runs (scaled by the
     same counters on a plain copy of known size), or None when they do not
@@ -136,7 +136,9 @@ def measured_traffic(cls, scheme, k, walkers, workload):
     digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
     if (rec.get("source_sha256") != digest or rec.get("scheme") != scheme
             or ("k" in rec and int(rec["k"]) != k) or int(rec.get("walkers", -1)) != walkers
-            or rec.get("workload") != workload):
+            or rec.get("workload") != workload
+            or ("tile_chunks" in rec and tile_chunks is not None
+                and int(rec["tile_chunks"]) != tile_chunks)):
         return None
     return float(rec["traffic_bytes_per_launch"])
 
@@ -600,9 +602,10 @@ def main():
     ap.add_argument("--serve-slices", type=int, default=20, help="M of the serving jobs")
     ap.add_argument("--serve-budget-gb", type=float, default=64.0,
                     help="HBM budget of the admitted walkers (0 = 90%% of free memory)")
-    ap.add_argument("--tile-chunks", type=int, default=0,
+    ap.add_argument("--tile-chunks", type=int, default=1,
                     help="column chunks per row strip of the flush kernel for the batched "
-                         "walkers (0: the library default)")
+                         "walkers (1: one per strip, the pipelined strip kernel for groups of "
+                         "17-32 sites; 0: the library default of two)")
     ap.add_argument("--ktime-window", type=int, default=10,
                     help="forward slice visits instrumented per kernel after the timed sweeps")
     args = ap.parse_args()
@@ -677,7 +680,8 @@ def main():
     roof_flush = roofline(p, args.scheme, args.k, args.b, acc, ktimes, "tile", walkers=W)
     for r in (roof, roof_flush):
         if r is not None:
-            r["traffic"] = measured_traffic(r["kernel"], args.scheme, args.k, W, args.workload)
+            r["traffic"] = measured_traffic(r["kernel"], args.scheme, args.k, W, args.workload,
+                                            args.tile_chunks)
     if args.steps > 0:
         log(f"{args.scheme}: {dt / args.steps:.3f} s/sweep, {value:.4g} fu/s, "
             f"update-only {upd:.4g}")
@@ -701,6 +705,7 @@ def main():
                         if args.workload == "c3" else args.workload,
             "scheme": args.scheme, "delay_k": args.k, "block_b": args.b, "walkers": S * W,
             "batches": f"{S} x {W} walkers, one HIP stream each, run concurrently",
+            "tile_chunks": args.tile_chunks,
         },
         "update_only_field_updates_per_s": upd,
         "acceptance": acc,

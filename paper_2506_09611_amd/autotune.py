@@ -26,7 +26,8 @@ import os
 from typing import Dict, Optional, Sequence
 
 DEFAULT_CANDIDATES = (8, 16, 32, 64, 128)
-DEFAULT_CHUNKS = (2, 4, 64)   # tile_chunks: two per strip, four, one tile per workgroup
+DEFAULT_CHUNKS = (1, 2, 4, 64)   # tile_chunks: one per strip (the pipelined strip kernel
+                                 # for groups of 17-32 sites), two, four, one tile per workgroup
 
 
 @dataclasses.dataclass

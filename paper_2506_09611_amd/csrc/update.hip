@@ -1592,6 +1592,350 @@ __global__ __launch_bounds__(kTileThreads, KP <= 32 ? 4 : 1) void group_tile_ker
   }
 }
 
+// ------------------------------------------------------------------------
+// Strip form of the fused tile kernel, for batches whose walkers ask for one
+// column chunk per row strip: one workgroup of 16 waves per (matrix, row
+// strip of 64 rows) walks all tiles of its strip as a two-stage pipeline.
+// Waves 0-7 (flush waves) apply the pending flush to tile t of T (each wave a
+// 16 x 32 block in registers), store it and copy it to LDS; in the same step
+// waves 8-15 (panel waves) form the P2 partial and the P1 share of tile t - 1
+// from the copy made one step earlier.  Tile copies, the flush's P2 columns
+// and the L_g rows are double-buffered in LDS (150 KB at KP = 32), so a step
+// ends on one barrier and the halves' MFMA and memory work overlap.  Every
+// product has the operands and the order of accumulation of the one-chunk
+// tile kernel above, so the two give the same bits.
+// ------------------------------------------------------------------------
+constexpr int kStripThreads = 1024;
+
+template <int KP, class R>
+__global__ __launch_bounds__(kStripThreads) void group_strip_kernel(Batch<TileArgs> B) {
+  typedef Mma<R> MM;
+  typedef typename MM::acc Acc2[2];
+  constexpr int NTR = kStripThreads / 2;             // threads per role
+  constexpr int NW = NTR / 64;                       // waves per role
+  constexpr int kPre = 64 * KP / NTR;                // per lane: a KP x 64 operand
+  constexpr int kpad = KP;
+  constexpr int QS = KP / 4;                         // depth steps of the flush
+  const int per = gridDim.x >> 3;   // the grid is a multiple of 8
+  const int flat = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  const int spm = B.w[0].tpm;       // row strips per matrix (the largest walker's)
+  const int mat = flat / spm;
+  if (mat >= B.w[0].nmat) return;
+  const TileArgs &a = B.w[mat >> 1];
+  const int s = mat & 1;
+  const int Ns = a.m.Ns[s];
+  const int nt = (Ns + 63) / 64;
+  const int rb = flat % spm;
+  if (rb >= nt) return;
+  const int t = threadIdx.x, lane = t & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
+  const bool fwave = wv < NW;
+  const int tr = fwave ? t : t - NTR;                // thread index within the role
+  const int li = lane & 15, lk = lane >> 4;
+  const int wm = (wv >> 1) & 3, wn = wv & 1;         // flush waves' 16 x 32 block
+  const int row0 = rb * 64;
+  const int kmax = a.g.kmax;
+  const int kk = a.kk, kkp = a.kk_prev;
+  const int n = nt;                                  // tiles of the strip
+  R *T = tile_matrix<R>(a.m, s);
+  const double *P2 = a.g.P2[s];
+  const double *ULt = a.m.ULt[s];
+  extern __shared__ double lds_raw[];
+  R *lds = reinterpret_cast<R *>(lds_raw);
+  R *Y = lds;                      // KP x kLdt: U_g over the strip's rows
+  R *Xb = Y + KP * kLdt;           // 2 x 64 x kLdt: tile copies
+  R *Pb = Xb + 2 * 64 * kLdt;      // 2 x KP x kLdt: the flush's P2 columns
+  R *Lb = Pb + 2 * KP * kLdt;      // 2 x KP x kLdt: L_g columns
+
+  Acc2 accA, accB;                 // flush waves: two tiles' blocks of T
+  // flush waves: P2 columns of the next tile; panel waves: L_g rows of the
+  // next tile
+  double ra[kPre];
+  auto load_t = [&](int cb, Acc2 &acc) {
+#pragma unroll
+    for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int r = row0 + wm * 16 + MM::row(lane, j), c = cb * 64 + wn * 32 + ni * 16 + li;
+        acc[ni][j] = T[(long)min(r, Ns - 1) * Ns + min(c, Ns - 1)];
+      }
+  };
+  auto load_l = [&](int cb) {
+#pragma unroll
+    for (int i = 0; i < kPre; ++i) {
+      const int e = tr + NTR * i;
+      const int m = e >> 6, c = cb * 64 + (e & 63);
+      ra[i] = ULt[(long)(a.g0 + min(m, kk - 1)) * Ns + min(c, Ns - 1)];
+    }
+  };
+  // the panel waves' first L_g rows go out before the set-up
+  const bool fl = a.flush && a.g.nA[0] > 0;
+  if (!fwave && kk > 0) load_l(0);
+  const int na = fl ? a.g.nA[0] : 0;
+  const int kp = (na + 3) & ~3;
+  __shared__ int al_s[KP];
+  for (int e = t; e < KP; e += kStripThreads)
+    al_s[e] = (e < na) ? a.g.alist[e] : (na > 0 ? a.g.alist[na - 1] : 0);
+  __syncthreads();
+  auto load_p = [&](int cb, double (&pv)[kPre]) {
+#pragma unroll
+    for (int i = 0; i < kPre; ++i) {
+      const int e = tr + NTR * i;
+      const int m = e >> 6, c = cb * 64 + (e & 63);
+      pv[i] = P2[(long)al_s[min(m, KP - 1)] * Ns + min(c, Ns - 1)];
+    }
+  };
+  if (fwave && fl) load_p(0, ra);   // the first tile's P2 columns, before the set-up
+
+  // accepted rows of U_R, by the first strip
+  if (fl && rb == 0) {
+    const double *sc = a.g.sc[s];
+    double *UR = a.m.UR[s];
+    for (int e = t; e < kkp * Ns; e += kStripThreads) {
+      const int m = e / Ns, c = e % Ns;
+      UR[(long)(a.g0_prev + m) * Ns + c] *= sc[m];
+    }
+  }
+  // U_g over the strip's rows (the next group's panels)
+  if (kk > 0) {
+    const double *UR = a.m.UR[s];
+    for (int e = t; e < KP * 64; e += kStripThreads) {
+      const int m = e >> 6, c = e & 63;
+      Y[m * kLdt + c] = (m < kk && row0 + c < Ns) ? UR[(long)(a.g0 + m) * Ns + row0 + c] : 0.0;
+    }
+  }
+  // -(P1 Mc) rows of the strip, into the flush waves' registers in the A
+  // layout of the flush: qa[q] = Q[wm 16 + li][4 q + lk]
+  R qa[QS];
+  if (fl) {
+    const int ld1 = kpad + 1;
+    R *A1 = Xb;                      // 64 x ld1 (aliases the tile copies before the walk)
+    R *M1 = A1 + 64 * ld1;           // kpad x ld1
+    const double *P1 = a.g.P1[s], *Mc = a.g.Mc[s];
+    for (int e = t; e < 64 * kpad; e += kStripThreads) {
+      const int r = e / kpad, m = e % kpad;
+      A1[r * ld1 + m] =
+          (m < na && row0 + r < Ns) ? (R)P1[(long)(row0 + r) * kmax + al_s[m]] : (R)0.0;
+    }
+    for (int e = t; e < kpad * kpad; e += kStripThreads) {
+      const int ma = e / kpad, mb = e % kpad;
+      M1[ma * ld1 + mb] = (ma < na && mb < na) ? (R)Mc[al_s[ma] * kmax + al_s[mb]] : (R)0.0;
+    }
+    __syncthreads();
+    constexpr int QT = KP / 16, QV = (QT + 1) / 2;
+    const int rq = wv & 3, uh = (wv >> 2) & 1;
+    typename MM::acc q[QV];
+    if (fwave) {
+#pragma unroll
+      for (int v = 0; v < QV; ++v) q[v] = MM::zero();
+      for (int k0 = 0; k0 < kp; k0 += 4) {
+        const R av = A1[(16 * rq + li) * ld1 + k0 + lk];
+#pragma unroll
+        for (int v = 0; v < QV; ++v) {
+          const int u = uh + 2 * v;
+          if (u < QT) q[v] = MM::op(av, M1[(k0 + lk) * ld1 + u * 16 + li], q[v]);
+        }
+      }
+    }
+    __syncthreads();
+    if (fwave) {
+#pragma unroll
+      for (int v = 0; v < QV; ++v) {
+        const int u = uh + 2 * v;
+        if (u < QT)
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            A1[(16 * rq + MM::row(lane, j)) * ld1 + u * 16 + li] = -q[v][j];
+      }
+    }
+    __syncthreads();
+    if (fwave) {
+#pragma unroll
+      for (int q2 = 0; q2 < QS; ++q2) qa[q2] = A1[(wm * 16 + li) * ld1 + 4 * q2 + lk];
+    }
+  }
+  __syncthreads();   // Y staged; A1 / M1 free
+  const int mtk = (kk + 15) >> 4;
+
+  // flush waves: one pipeline step flushes tile st (in `cur`), stores it and
+  // copies it to LDS.  The loads of the step before are waited for by the
+  // first use of their registers, and only then are this step's issued, so
+  // that they have a whole step to arrive.
+  auto fwalk = [&](auto flc, auto nxc) {
+    constexpr bool FL = decltype(flc)::value, NX = decltype(nxc)::value;
+    auto put_p = [&](int cb) {
+      R *P = Pb + (cb & 1) * KP * kLdt;
+#pragma unroll
+      for (int i = 0; i < kPre; ++i) {
+        const int e = tr + NTR * i;
+        P[(e >> 6) * kLdt + (e & 63)] = (R)ra[i];
+      }
+    };
+    auto fstep = [&](int st, Acc2 &cur, Acc2 &nxt) {
+      if (st < n) {
+        const int cb = st, col0 = cb * 64;
+        if (FL) {
+          if (st + 1 < n) put_p(cb + 1);
+#pragma unroll
+          for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) asm volatile("" ::"v"(cur[ni][j]));
+          if (st + 2 < n) load_p(cb + 2, ra);
+          if (st + 1 < n) load_t(cb + 1, nxt);
+          const R *P = Pb + (cb & 1) * KP * kLdt;
+#pragma unroll
+          for (int q = 0; q < QS; ++q) {
+            if (4 * q < kp) {
+              const R b0 = P[(4 * q + lk) * kLdt + wn * 32 + li];
+              const R b1 = P[(4 * q + lk) * kLdt + wn * 32 + 16 + li];
+              cur[0] = MM::op(qa[q], b0, cur[0]);
+              cur[1] = MM::op(qa[q], b1, cur[1]);
+            }
+          }
+#pragma unroll
+          for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              const int r = row0 + wm * 16 + MM::row(lane, j), c = col0 + wn * 32 + ni * 16 + li;
+              if (r < Ns && c < Ns) T[(long)r * Ns + c] = cur[ni][j];
+            }
+        }
+        if (NX) {
+          R *X = Xb + (cb & 1) * 64 * kLdt;
+#pragma unroll
+          for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+              X[(wm * 16 + MM::row(lane, j)) * kLdt + wn * 32 + ni * 16 + li] = cur[ni][j];
+        }
+        if (!FL && st + 1 < n) load_t(cb + 1, nxt);
+      }
+      __syncthreads();
+    };
+    load_t(0, accA);
+    if (FL) {
+      put_p(0);
+      if (n > 1) load_p(1, ra);
+    }
+    __syncthreads();
+    for (int st = 0; st <= n; st += 2) {
+      fstep(st, accA, accB);
+      if (st + 1 <= n) fstep(st + 1, accB, accA);
+    }
+    __syncthreads();   // the panel waves' epilogue
+  };
+
+  // panel waves: one pipeline step forms the P2 partial and the P1 share of
+  // tile st - 1 from its copy in LDS; the L_g rows of the next tile arrive in
+  // registers
+  auto gwalk = [&](auto nxc) {
+    constexpr bool NX = decltype(nxc)::value;
+    const int gw = wv - NW;
+    constexpr int U1 = (4 * (KP / 16) + NW - 1) / NW;
+    constexpr int U2 = (4 * (KP / 16) + NW - 1) / NW;
+    typename MM::acc p1acc[U1];
+    int rt1[U1], mt1[U1];
+#pragma unroll
+    for (int u = 0; u < U1; ++u) {
+      const int tt = gw + NW * u;
+      const bool v = tt < 4 * mtk;
+      rt1[u] = v ? tt / mtk : 0;
+      mt1[u] = v ? tt % mtk : 0;
+      p1acc[u] = MM::zero();
+    }
+    double *o2 = a.g.P2part[s] + (long)rb * kmax * Ns;
+    auto put_l = [&](int cb) {
+      R *L = Lb + (cb & 1) * KP * kLdt;
+#pragma unroll
+      for (int i = 0; i < kPre; ++i) {
+        const int e = tr + NTR * i;
+        const int m = e >> 6, c = cb * 64 + (e & 63);
+        L[m * kLdt + (e & 63)] = (R)(ra[i] * ((m < kk && c < Ns) ? 1.0 : 0.0));
+      }
+    };
+    __syncthreads();
+    for (int st = 0; st <= n; ++st) {
+      if (NX) {
+        if (st < n) put_l(st);
+        if (st + 1 < n) load_l(st + 1);
+        if (st >= 1) {
+          const int cb = st - 1, col0 = cb * 64;
+          const R *X = Xb + (cb & 1) * 64 * kLdt;
+          const R *L = Lb + (cb & 1) * KP * kLdt;
+          // P2 partial of the tile: U_g[:, strip rows] T_tile (kk x 64)
+#pragma unroll
+          for (int u = 0; u < U2; ++u) {
+            const int tt = gw + NW * u;
+            if (tt >= 4 * mtk) continue;
+            const int mt2 = tt >> 2, ct2 = tt & 3;
+            typename MM::acc p2t = MM::zero();
+            for (int k0 = 0; k0 < 64; k0 += 4)
+              p2t = MM::op(Y[(mt2 * 16 + li) * kLdt + k0 + lk],
+                           X[(k0 + lk) * kLdt + ct2 * 16 + li], p2t);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              const int m = mt2 * 16 + MM::row(lane, j), c = col0 + ct2 * 16 + li;
+              if (m < kk && c < Ns) o2[(long)m * Ns + c] = p2t[j];
+            }
+          }
+          // P1 rows of the strip += T_tile L_g[tile columns, :]
+#pragma unroll
+          for (int u = 0; u < U1; ++u) {
+            if (gw + NW * u >= 4 * mtk) continue;
+            for (int k0 = 0; k0 < 64; k0 += 4)
+              p1acc[u] = MM::op(X[(rt1[u] * 16 + li) * kLdt + k0 + lk],
+                                L[(mt1[u] * 16 + li) * kLdt + k0 + lk], p1acc[u]);
+          }
+        }
+      }
+      __syncthreads();
+    }
+    if (!NX) {
+      __syncthreads();
+      return;
+    }
+    // P1 partial of the strip (one column chunk), then its W0 partial U_g P1
+    double *o1 = a.g.P1part[s];
+    R *X = Xb;
+#pragma unroll
+    for (int u = 0; u < U1; ++u) {
+      if (gw + NW * u >= 4 * mtk) continue;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int r = row0 + rt1[u] * 16 + MM::row(lane, j), m1 = mt1[u] * 16 + li;
+        if (r < Ns && m1 < kk) o1[(long)r * kmax + m1] = p1acc[u][j];
+        X[(rt1[u] * 16 + MM::row(lane, j)) * kLdt + mt1[u] * 16 + li] = p1acc[u][j];
+      }
+    }
+    __syncthreads();   // (the flush waves' last barrier)
+    constexpr int UW = (KP / 16 * KP / 16 + NW - 1) / NW;
+    double *ow = a.g.W0part[s] + (long)rb * kmax * kmax;
+#pragma unroll
+    for (int u = 0; u < UW; ++u) {
+      const int tt = gw + NW * u;
+      if (tt >= mtk * mtk) continue;
+      const int mw = tt / mtk, nw2 = tt % mtk;
+      typename MM::acc w0 = MM::zero();
+      for (int k0 = 0; k0 < 64; k0 += 4)
+        w0 = MM::op(Y[(mw * 16 + li) * kLdt + k0 + lk], X[(k0 + lk) * kLdt + nw2 * 16 + li], w0);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int m = mw * 16 + MM::row(lane, j), n2 = nw2 * 16 + li;
+        if (m < kk && n2 < kk) ow[m * kmax + n2] = w0[j];
+      }
+    }
+  };
+
+  if (fwave) {
+    if (fl && kk > 0) fwalk(std::true_type{}, std::true_type{});
+    else if (kk > 0) fwalk(std::false_type{}, std::true_type{});
+    else if (fl) fwalk(std::true_type{}, std::false_type{});
+  } else {
+    if (kk > 0) gwalk(std::true_type{});
+    else if (fl) gwalk(std::false_type{});
+  }
+}
+
 }  // namespace
 
 // kernel arguments are passed by value: keep every batch within 4 KB
@@ -1787,6 +2131,20 @@ hipError_t launch_tile(const Batch<TileArgs> &B, int nw, hipStream_t st) {
   return hipGetLastError();
 }
 
+template <int KP, class R>
+hipError_t launch_strip(const Batch<TileArgs> &B, int nw, hipStream_t st) {
+  // Y, two tile copies, two P2-column and two L_g buffers: 150 KB (KP = 32,
+  // double), one workgroup per CU
+  const size_t lds = sizeof(R) * ((size_t)5 * KP + 128) * kLdt;
+  static const hipError_t attr = hipFuncSetAttribute(
+      (const void *)group_strip_kernel<KP, R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (attr != hipSuccess) return attr;
+  const int total = 2 * nw * B.w[0].tpm;
+  hipLaunchKernelGGL((group_strip_kernel<KP, R>), dim3((total + 7) / 8 * 8), dim3(kStripThreads),
+                     lds, st, B);
+  return hipGetLastError();
+}
+
 hipError_t group_tile(const SpinMats *m, const GroupBufs *g, int nw, int g0_prev,
                       const int *kk_prev, int g0, const int *kk, bool fp32, hipStream_t st) {
   if (nw < 1 || nw > kMaxBatch) return hipErrorInvalidValue;
@@ -1812,6 +2170,9 @@ hipError_t group_tile(const SpinMats *m, const GroupBufs *g, int nw, int g0_prev
     B.w[w].chm = chm;
     B.w[w].tpm = nt * chm;
   }
+  // one chunk per strip for every walker, groups of 17-32 sites, float64:
+  // the pipelined strip kernel (the same bits as the one-chunk tile kernel)
+  if (chm == 1 && !fp32 && kmax > 16 && kmax <= 32) return launch_strip<32, double>(B, nw, st);
   if (fp32) {
     if (kmax <= 16) return launch_tile<16, float>(B, nw, st);
     if (kmax <= 32) return launch_tile<32, float>(B, nw, st);

@@ -60,7 +60,7 @@ def test_tune_on_device(tmp_path):
     assert set(r.update_s_per_slice) == {8, 16, 32, 100}
     assert all(t > 0 for t in r.update_s_per_slice.values())
     if r.k <= 64:   # the chunk stage (fused path) at the chosen k
-        assert set(r.chunk_s_per_slice) == {2, 4, 64} and r.tile_chunks in (2, 4, 64)
+        assert set(r.chunk_s_per_slice) == {1, 2, 4, 64} and r.tile_chunks in (1, 2, 4, 64)
         assert all(t > 0 for t in r.chunk_s_per_slice.values())
     again = tune_delay(p.hopping, p.trial_up, p.trial_dn, p.U, p.dtau, p.stab_every,
                        candidates=(8, 16, 32, 128), walkers=2, cache=path)

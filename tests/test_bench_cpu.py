@@ -77,3 +77,7 @@ def test_traffic_record_matches_only_its_launch():
     assert bench.measured_traffic("tile", "block", 32, 8, "c3") is None
     assert bench.measured_traffic("local", "delayed", 32, 8, "c3") is None
     assert bench.measured_traffic("decide", "delayed", 32, 8, "c3") is None
+    rec = _record("tile")
+    if rec is not None and "tile_chunks" in rec:
+        c = int(rec["tile_chunks"])
+        assert bench.measured_traffic("tile", "delayed", 32, 8, "c3", c + 1) is None

@@ -124,6 +124,63 @@ def test_tile_chunks_mixed_in_one_batch():
         ch.close()
 
 
+def test_strip_kernel_one_chunk_batch_c3():
+    """40x40: two walkers asking for one column chunk per row strip (the
+    pipelined strip kernel for groups of 17-32 sites) in one batch, over a
+    10-slice window: each takes its oracle's decisions and G, and walker 1
+    equals its single run with the same option bitwise."""
+    from paper_2506_09611_amd import batch_forward_window
+    p = synth.workload("c3", n_slices=20, stab_every=10)
+    probs = _walkers(p, 2)
+    chains = [make_chain(q, "delayed", k=32, tile_chunks=1) for q in probs]
+    batch_forward_window(chains, 10)
+    for q, ch in zip(probs, chains):
+        w = Walker(q, "delayed", k=32)
+        w.forward_window(10)
+        meta, margin = ch.decisions()
+        n, low = compare_decisions(meta, margin, w.log, 0, p.n_slices)
+        print(f"strip kernel walker {q.walker_id}: {n} decisions equal, low {low}", flush=True)
+        assert np.array_equal(ch.fields(), w.fields)
+        assert green_rel_err(ch, w) < 1e-10
+    single = make_chain(probs[1], "delayed", k=32, tile_chunks=1)
+    single.forward_window(10)
+    for s in range(2):
+        assert np.array_equal(chains[1].green(s), single.green(s))
+    for ch in chains + [single]:
+        ch.close()
+
+
+def test_strip_kernel_mixed_sizes_whole_sweeps():
+    """6x6, 8x8 and 12x12 walkers (one and two row strips of 64) with one
+    column chunk per strip and k = 32 in one batch, two whole sweeps: each
+    against its oracle and bitwise against its single run."""
+    from paper_2506_09611_amd import batch_sweep
+    probs = []
+    for i, (L, n) in enumerate([(6, 13), (8, 25), (12, 61)]):
+        q = synth.make_problem(L, n, n, 4.0, n_slices=20, stab_every=5, perturb=1e-3,
+                               seed=synth.SEED_BASE + 47 + i)
+        probs.append(dataclasses.replace(q, walker_id=i))
+    chains = [make_chain(q, "delayed", k=32, tile_chunks=1) for q in probs]
+    refs = [Walker(q, "delayed", k=32) for q in probs]
+    for sw in range(2):
+        batch_sweep(chains, 1)
+        for q, ch, w in zip(probs, chains, refs):
+            w.sweep()
+            meta, margin = ch.decisions()
+            compare_decisions(meta, margin, w.log, sw, q.n_slices)
+            assert np.array_equal(ch.fields(), w.fields)
+            assert green_rel_err(ch, w) < 1e-10
+        print(f"strip kernel mixed batch sweep {sw}: oracle decisions and G equal", flush=True)
+    for q, ch in zip(probs, chains):
+        single = make_chain(q, "delayed", k=32, tile_chunks=1)
+        single.sweep(2)
+        for s in range(2):
+            assert np.array_equal(ch.green(s), single.green(s)), q.walker_id
+        single.close()
+    for ch in chains:
+        ch.close()
+
+
 def test_tile_chunks_precision_form_equals_single_runs():
     """The float32 form with walkers asking for 2, 3 and 64 column chunks in
     one batch: each walker equals its single run with the same option
